@@ -1,0 +1,308 @@
+/*
+ * oracle.c -- plain C statement of the preconditioner and hull (arXiv
+ * 1505.00914).  TEST INFRASTRUCTURE ONLY: see oracle.h for who may use it.
+ *
+ * Written for a reader checking it against the paper by eye: no blocking,
+ * no fusion, no reordering beyond what the definitions state.  Single thread.
+ */
+#include "oracle.h"
+
+#include <stdlib.h>
+#include <string.h>
+
+/* Largest admissible p: p+1 (the empty-column sentinel) must fit in int32. */
+#define OR_PMAX 2147483646
+
+/* ---------------------------------------------------------------------------
+ * Algorithm 1 (Proposed heuristic, "Reduction of Points").
+ *
+ * L holds one (ly, hy) pair per column and starts as (p+1, -1) in every
+ * column.  Each point (x, y) of P, taken in the order given, replaces the
+ * pair of its column by (min(y, ly), max(y, hy)).  Coordinates are assumed
+ * to lie in 1..p (the square of side p in the same section); anything else
+ * is reported instead of being folded in.
+ * ------------------------------------------------------------------------- */
+int or_reduce(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *hi)
+{
+    if (p < 1 || p > OR_PMAX || n < 0) return OR_EINVAL;
+    if (n > 0 && pts == NULL) return OR_EINVAL;
+    if (lo == NULL || hi == NULL) return OR_EINVAL;
+
+    for (int64_t j = 0; j < n; ++j) {
+        int32_t x = pts[2 * j], y = pts[2 * j + 1];
+        if (x < 1 || x > p || y < 1 || y > p) return OR_ERANGE;
+    }
+
+    /* L = [(p+1, -1), ..., (p+1, -1)] */
+    for (int32_t i = 0; i < p; ++i) {
+        lo[i] = p + 1;
+        hi[i] = -1;
+    }
+
+    /* foreach point in P */
+    for (int64_t j = 0; j < n; ++j) {
+        int32_t xi = pts[2 * j], yi = pts[2 * j + 1];
+        int32_t yv = lo[xi - 1], yu = hi[xi - 1];      /* (yv, yu) = L[xi]   */
+        int32_t ly = yi < yv ? yi : yv;                /* ly = min(yi, yv)   */
+        int32_t hy = yi > yu ? yi : yu;                /* hy = max(yi, yu)   */
+        lo[xi - 1] = ly;                               /* L[xi] = (ly, hy)   */
+        hi[xi - 1] = hy;
+    }
+    return OR_OK;
+}
+
+/* An entry of L is valid when it differs from the sentinel (p+1, -1).  After
+ * Algorithm 1 a column is either untouched (exactly the sentinel) or holds
+ * 1 <= ly <= hy <= p, so "differs from the sentinel" is the test written
+ * here, literally. */
+static int or_valid(int32_t lo, int32_t hi, int32_t p)
+{
+    return !(lo == p + 1 && hi == -1);
+}
+
+/* ---------------------------------------------------------------------------
+ * Bit array M (Discussion, "Extraction using an array of bits").  M[i] = 1
+ * exactly for the valid columns i; with w-bit words, column i is bit
+ * (i-1) & (w-1) of word (i-1) >> log2(w).  Here w = 64.
+ * ------------------------------------------------------------------------- */
+int64_t or_mask(const int32_t *lo, const int32_t *hi, int32_t p, uint64_t *M)
+{
+    if (p < 1 || p > OR_PMAX || lo == NULL || hi == NULL || M == NULL) return OR_EINVAL;
+    int64_t words = ((int64_t)p + 63) / 64;
+    memset(M, 0, (size_t)words * sizeof(uint64_t));
+    int64_t set = 0;
+    for (int64_t i = 1; i <= p; ++i) {
+        if (or_valid(lo[i - 1], hi[i - 1], p)) {
+            int64_t b = (i - 1) >> 6;          /* block word   */
+            int64_t pb = (i - 1) & 63;         /* bit in block */
+            M[b] |= (uint64_t)1 << pb;
+            ++set;
+        }
+    }
+    return set;
+}
+
+/* Count of trailing zero bits of a non-zero word, by plain shifting (the
+ * hardware instruction the paper relies on is only a faster way to get the
+ * same number). */
+static int32_t or_ctz64(uint64_t x)
+{
+    int32_t c = 0;
+    while ((x & 1u) == 0) {
+        x >>= 1;
+        ++c;
+    }
+    return c;
+}
+
+/* Table I: while the word is non-zero, report pos = ctz(word) and clear that
+ * bit with word ^= 1 << pos.  Positions come out in ascending order. */
+int32_t or_ctz_positions(uint64_t word, int32_t *pos)
+{
+    int32_t c = 0;
+    while (word != 0) {
+        int32_t q = or_ctz64(word);
+        pos[c++] = q;
+        word ^= (uint64_t)1 << q;
+    }
+    return c;
+}
+
+/* Extraction over all words of M: column i = b*w + pb + 1. */
+int32_t or_extract(const uint64_t *M, int32_t p, int32_t *cols)
+{
+    if (p < 1 || p > OR_PMAX || M == NULL || cols == NULL) return OR_EINVAL;
+    int64_t words = ((int64_t)p + 63) / 64;
+    int32_t k = 0;
+    int32_t pos[64];
+    for (int64_t b = 0; b < words; ++b) {
+        int32_t c = or_ctz_positions(M[b], pos);
+        for (int32_t t = 0; t < c; ++t) cols[k++] = (int32_t)(b * 64 + pos[t] + 1);
+    }
+    return k;
+}
+
+/* ---------------------------------------------------------------------------
+ * Lemma 1 (Building a polyline): scanning L along x and skipping the
+ * entries that still hold the sentinel gives the valid columns in ascending
+ * x.  The chain is stored as (x, lo, hi) per valid column.
+ * ------------------------------------------------------------------------- */
+int32_t or_chain(const int32_t *lo, const int32_t *hi, int32_t p,
+                 int32_t *x, int32_t *clo, int32_t *chi)
+{
+    if (p < 1 || p > OR_PMAX || lo == NULL || hi == NULL) return OR_EINVAL;
+    int32_t k = 0;
+    for (int32_t i = 1; i <= p; ++i) {
+        if (or_valid(lo[i - 1], hi[i - 1], p)) {
+            x[k] = i;
+            clo[k] = lo[i - 1];
+            chi[k] = hi[i - 1];
+            ++k;
+        }
+    }
+    return k;
+}
+
+/* The points the chain joins, in the order Lemma 1 walks them: within a
+ * column from (x, ly) up to (x, hy), then on to the next valid column.  A
+ * column with ly = hy contributes its single point once. */
+int64_t or_reduced(const int32_t *x, const int32_t *clo, const int32_t *chi,
+                   int32_t k, int32_t *rx, int32_t *ry)
+{
+    int64_t s = 0;
+    for (int32_t t = 0; t < k; ++t) {
+        rx[s] = x[t];
+        ry[s] = clo[t];
+        ++s;
+        if (chi[t] > clo[t]) {
+            rx[s] = x[t];
+            ry[s] = chi[t];
+            ++s;
+        }
+    }
+    return s;
+}
+
+/* ---------------------------------------------------------------------------
+ * Andrew's monotone chain over a lexicographically sorted sequence of
+ * distinct points.
+ *
+ * cross(o, a, b) = (a - o) x (b - o), evaluated in int64.  Every coordinate
+ * difference is below 2^31 in magnitude, so each product is below 2^62 and
+ * the difference of two products below 2^63: exact.
+ *
+ * lower: walk the points left to right; before pushing q, pop while the last
+ *        two stacked points and q fail to make a strict left turn
+ *        (cross <= 0, which also removes collinear points);
+ * upper: the same walk right to left;
+ * hull : lower without its last point, then upper without its last point.
+ * A sequence of 0 or 1 points is its own hull.
+ * ------------------------------------------------------------------------- */
+static int64_t or_cross(int64_t ox, int64_t oy, int64_t ax, int64_t ay,
+                        int64_t bx, int64_t by)
+{
+    return (ax - ox) * (by - oy) - (ay - oy) * (bx - ox);
+}
+
+static int64_t or_andrew(const int32_t *px, const int32_t *py, int64_t m,
+                         int32_t *vx, int32_t *vy)
+{
+    if (m <= 1) {
+        for (int64_t i = 0; i < m; ++i) {
+            vx[i] = px[i];
+            vy[i] = py[i];
+        }
+        return m;
+    }
+    /* The stack for one chain holds at most m points. */
+    int32_t *sx = (int32_t *)malloc((size_t)m * sizeof(int32_t));
+    int32_t *sy = (int32_t *)malloc((size_t)m * sizeof(int32_t));
+    if (sx == NULL || sy == NULL) {
+        free(sx);
+        free(sy);
+        return OR_EINVAL;
+    }
+    int64_t h = 0;
+
+    /* lower chain */
+    int64_t t = 0;
+    for (int64_t i = 0; i < m; ++i) {
+        while (t >= 2 && or_cross(sx[t - 2], sy[t - 2], sx[t - 1], sy[t - 1], px[i], py[i]) <= 0) --t;
+        sx[t] = px[i];
+        sy[t] = py[i];
+        ++t;
+    }
+    for (int64_t i = 0; i + 1 < t; ++i) {
+        vx[h] = sx[i];
+        vy[h] = sy[i];
+        ++h;
+    }
+
+    /* upper chain */
+    t = 0;
+    for (int64_t i = m - 1; i >= 0; --i) {
+        while (t >= 2 && or_cross(sx[t - 2], sy[t - 2], sx[t - 1], sy[t - 1], px[i], py[i]) <= 0) --t;
+        sx[t] = px[i];
+        sy[t] = py[i];
+        ++t;
+    }
+    for (int64_t i = 0; i + 1 < t; ++i) {
+        vx[h] = sx[i];
+        vy[h] = sy[i];
+        ++h;
+    }
+
+    free(sx);
+    free(sy);
+    return h;
+}
+
+int32_t or_hull_chain(const int32_t *x, const int32_t *clo, const int32_t *chi,
+                      int32_t k, int32_t *vx, int32_t *vy)
+{
+    if (k < 0) return OR_EINVAL;
+    for (int32_t t = 0; t + 1 < k; ++t)
+        if (!(x[t] < x[t + 1])) return OR_EORDER;
+    for (int32_t t = 0; t < k; ++t)
+        if (chi[t] < clo[t]) return OR_EORDER;
+    if (k == 0) return 0;
+
+    int32_t *rx = (int32_t *)malloc((size_t)2 * (size_t)k * sizeof(int32_t));
+    int32_t *ry = (int32_t *)malloc((size_t)2 * (size_t)k * sizeof(int32_t));
+    if (rx == NULL || ry == NULL) {
+        free(rx);
+        free(ry);
+        return OR_EINVAL;
+    }
+    /* R is strictly increasing in (x, y) order: x grows from column to column
+     * and lo < hi inside a column, so Andrew's scan needs no sort here. */
+    int64_t s = or_reduced(x, clo, chi, k, rx, ry);
+    int64_t h = or_andrew(rx, ry, s, vx, vy);
+    free(rx);
+    free(ry);
+    return (int32_t)h;
+}
+
+static int or_lex_cmp(const void *a, const void *b)
+{
+    const int32_t *u = (const int32_t *)a, *v = (const int32_t *)b;
+    if (u[0] != v[0]) return u[0] < v[0] ? -1 : 1;
+    if (u[1] != v[1]) return u[1] < v[1] ? -1 : 1;
+    return 0;
+}
+
+int64_t or_hull_full(const int32_t *pts, int64_t n, int32_t *vx, int32_t *vy)
+{
+    if (n < 0) return OR_EINVAL;
+    if (n == 0) return 0;
+    int32_t *q = (int32_t *)malloc((size_t)n * 2 * sizeof(int32_t));
+    if (q == NULL) return OR_EINVAL;
+    memcpy(q, pts, (size_t)n * 2 * sizeof(int32_t));
+    qsort(q, (size_t)n, 2 * sizeof(int32_t), or_lex_cmp);
+
+    /* keep one copy of each distinct point */
+    int64_t m = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (m > 0 && q[2 * (m - 1)] == q[2 * i] && q[2 * (m - 1) + 1] == q[2 * i + 1]) continue;
+        q[2 * m] = q[2 * i];
+        q[2 * m + 1] = q[2 * i + 1];
+        ++m;
+    }
+    int32_t *px = (int32_t *)malloc((size_t)m * sizeof(int32_t));
+    int32_t *py = (int32_t *)malloc((size_t)m * sizeof(int32_t));
+    if (px == NULL || py == NULL) {
+        free(q);
+        free(px);
+        free(py);
+        return OR_EINVAL;
+    }
+    for (int64_t i = 0; i < m; ++i) {
+        px[i] = q[2 * i];
+        py[i] = q[2 * i + 1];
+    }
+    int64_t h = or_andrew(px, py, m, vx, vy);
+    free(q);
+    free(px);
+    free(py);
+    return h;
+}

@@ -1,0 +1,89 @@
+/*
+ * oracle.h -- CPU oracle for the integer convex-hull preconditioner of
+ * Cadenas & Megson, "An Empirical Evaluation of Preconditioning Data for
+ * Accelerating Convex Hull Computations" (arXiv 1505.00914).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the plain, slow, obviously
+ * correct statement of what the GPU path computes.  Only the test suite, the
+ * smoke check and the CPU-baseline leg of the benchmark may load it.  It
+ * shares no code, header, table or helper with the GPU library, and the GPU
+ * library never calls it.
+ *
+ * Everything here is exact integer arithmetic: the method never rounds.
+ *
+ * Conventions (readings of the paper, all written out in the design notes):
+ *   - points are interleaved int32 pairs (x, y), 1 <= x, y <= p;
+ *   - L is held as two int32 arrays lo[p], hi[p]; column x lives at index x-1;
+ *   - an empty column holds the sentinel (p+1, -1) (Algorithm 1 initialisation);
+ *   - the bit array M uses 64-bit words: column i is bit (i-1)&63 of word
+ *     (i-1)>>6 (Discussion, "Extraction using an array of bits", with w = 64);
+ *   - the hull is listed counter-clockwise starting at the lexicographic
+ *     minimum (smallest x, then smallest y), without repeating the first
+ *     vertex, keeping strictly convex vertices only (collinear points are
+ *     dropped, as the Appendix argues they cannot be hull vertices).
+ *
+ * Pins: every function below is checked by the CPU test-suite against the
+ * paper's worked example, its gap example and Table I, closed forms,
+ * brute force on tiny inputs, exhaustive enumeration for p <= 3 and an
+ * independent library hull (Qhull).  No function is "parity unpinned".
+ */
+#ifndef PAPER_1505_00914_ORACLE_H
+#define PAPER_1505_00914_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OR_OK      0
+#define OR_EINVAL (-1)   /* bad argument (p out of [1, 2^31-2], n < 0, NULL) */
+#define OR_ERANGE (-2)   /* a coordinate lies outside [1, p]                 */
+#define OR_EORDER (-3)   /* hull_chain input is not strictly x-increasing    */
+
+/* Algorithm 1 (Proposed heuristic): lo/hi receive p entries each.  Every
+ * point is checked for 1 <= x, y <= p first; on failure nothing is written
+ * and OR_ERANGE is returned.  Then L starts at (p+1, -1) everywhere and the
+ * points are folded in, in input order, by per-column min/max. */
+int or_reduce(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *hi);
+
+/* Bit array M (Discussion, "Extraction using an array of bits"): word
+ * (i-1)>>6, bit (i-1)&63 is set iff column i holds a valid entry.  M must
+ * have ceil(p/64) words.  Returns the number of set bits. */
+int64_t or_mask(const int32_t *lo, const int32_t *hi, int32_t p, uint64_t *M);
+
+/* Table I: set-bit positions of one word by the count-trailing-zeros loop,
+ * ascending.  Returns the count written to pos (at most 64). */
+int32_t or_ctz_positions(uint64_t word, int32_t *pos);
+
+/* Extraction of the valid columns from M, word by word with the Table I
+ * loop, ascending.  cols receives 1-based column numbers; returns count. */
+int32_t or_extract(const uint64_t *M, int32_t p, int32_t *cols);
+
+/* Lemma 1 chain as a structure of arrays: the valid columns of L in
+ * ascending x.  x, clo, chi need room for p entries.  Returns k. */
+int32_t or_chain(const int32_t *lo, const int32_t *hi, int32_t p,
+                 int32_t *x, int32_t *clo, int32_t *chi);
+
+/* The reduced point sequence R walked along the Lemma 1 chain: for each
+ * chain column (x, lo), then (x, hi) when hi > lo.  rx, ry need 2k entries.
+ * Returns s = |R|. */
+int64_t or_reduced(const int32_t *x, const int32_t *clo, const int32_t *chi,
+                   int32_t k, int32_t *rx, int32_t *ry);
+
+/* Convex hull of the chain (Andrew's monotone chain over R, which is already
+ * in lexicographic order, so no sort).  vx, vy need 2k entries.  Returns the
+ * vertex count h >= 0, or OR_EORDER if x is not strictly increasing. */
+int32_t or_hull_chain(const int32_t *x, const int32_t *clo, const int32_t *chi,
+                      int32_t k, int32_t *vx, int32_t *vy);
+
+/* Convex hull of all n input points (Andrew's monotone chain after sorting
+ * and de-duplicating a copy), the independent side of the Appendix claim
+ * hull(reduced) == hull(input).  vx, vy need n entries.  Returns h, or
+ * OR_EINVAL on allocation failure. */
+int64_t or_hull_full(const int32_t *pts, int64_t n, int32_t *vx, int32_t *vy);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

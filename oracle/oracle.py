@@ -1,0 +1,191 @@
+"""ctypes binding of the plain-C oracle (oracle.c).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).  Each function mirrors
+one C function and cites, through it, the passage of the paper it follows.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+OR_OK, OR_EINVAL, OR_ERANGE, OR_EORDER = 0, -1, -2, -3
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_HDR = os.path.join(_HERE, "oracle.h")
+
+
+def lib_path() -> str:
+    return os.path.join(_HERE, "liboracle.so")
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def build(force: bool = True, extra_flags: tuple[str, ...] = (), out: str | None = None) -> str:
+    """Compile oracle.c with gcc into a shared library (single thread, -O2).
+
+    ``extra_flags`` exists so that tests can build planted-mistake variants
+    of the oracle (``-DOR_MUTANT=<n>``) into a separate file ``out``.
+    """
+    out = out or lib_path()
+    if not force and os.path.exists(out) and os.path.getmtime(out) >= max(
+        os.path.getmtime(_SRC), os.path.getmtime(_HDR)
+    ):
+        return out
+    tmp = out + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-fPIC", "-shared",
+           *extra_flags, "-o", tmp, _SRC]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
+    return out
+
+
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+
+
+def _load(path: str) -> ctypes.CDLL:
+    lib = ctypes.CDLL(path)
+    lib.or_reduce.argtypes = [_i32p, ctypes.c_int64, ctypes.c_int32, _i32p, _i32p]
+    lib.or_reduce.restype = ctypes.c_int
+    lib.or_mask.argtypes = [_i32p, _i32p, ctypes.c_int32, _u64p]
+    lib.or_mask.restype = ctypes.c_int64
+    lib.or_ctz_positions.argtypes = [ctypes.c_uint64, _i32p]
+    lib.or_ctz_positions.restype = ctypes.c_int32
+    lib.or_extract.argtypes = [_u64p, ctypes.c_int32, _i32p]
+    lib.or_extract.restype = ctypes.c_int32
+    lib.or_chain.argtypes = [_i32p, _i32p, ctypes.c_int32, _i32p, _i32p, _i32p]
+    lib.or_chain.restype = ctypes.c_int32
+    lib.or_reduced.argtypes = [_i32p, _i32p, _i32p, ctypes.c_int32, _i32p, _i32p]
+    lib.or_reduced.restype = ctypes.c_int64
+    lib.or_hull_chain.argtypes = [_i32p, _i32p, _i32p, ctypes.c_int32, _i32p, _i32p]
+    lib.or_hull_chain.restype = ctypes.c_int32
+    lib.or_hull_full.argtypes = [_i32p, ctypes.c_int64, _i32p, _i32p]
+    lib.or_hull_full.restype = ctypes.c_int64
+    return lib
+
+
+_LIBS: dict[str, ctypes.CDLL] = {}
+
+
+def _lib(path: str | None = None) -> ctypes.CDLL:
+    path = path or lib_path()
+    if path not in _LIBS:
+        if path == lib_path():
+            build(force=False)
+        _LIBS[path] = _load(path)
+    return _LIBS[path]
+
+
+def _ptr(a: np.ndarray, ctype=_i32p):
+    return a.ctypes.data_as(ctype)
+
+
+def _points(pts) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(pts, dtype=np.int32).reshape(-1, 2))
+    return a
+
+
+def reduce(pts, p: int, lib: str | None = None) -> tuple[np.ndarray, np.ndarray]:
+    """Algorithm 1: returns (lo, hi), each of length p (column x at x-1)."""
+    a = _points(pts)
+    lo = np.empty(p, np.int32)
+    hi = np.empty(p, np.int32)
+    rc = _lib(lib).or_reduce(_ptr(a), a.shape[0], p, _ptr(lo), _ptr(hi))
+    if rc != OR_OK:
+        raise OracleError(f"or_reduce failed: {rc}")
+    return lo, hi
+
+
+def mask(lo: np.ndarray, hi: np.ndarray, p: int, lib: str | None = None) -> np.ndarray:
+    """Bit array M in 64-bit words (column i -> word (i-1)>>6, bit (i-1)&63)."""
+    lo = np.ascontiguousarray(lo, np.int32)
+    hi = np.ascontiguousarray(hi, np.int32)
+    M = np.empty((p + 63) // 64, np.uint64)
+    rc = _lib(lib).or_mask(_ptr(lo), _ptr(hi), p, _ptr(M, _u64p))
+    if rc < 0:
+        raise OracleError(f"or_mask failed: {rc}")
+    return M
+
+
+def ctz_positions(word: int, lib: str | None = None) -> list[int]:
+    """Table I: ascending set-bit positions of one 64-bit word."""
+    pos = np.empty(64, np.int32)
+    c = _lib(lib).or_ctz_positions(ctypes.c_uint64(word), _ptr(pos))
+    return [int(v) for v in pos[:c]]
+
+
+def extract(M: np.ndarray, p: int, lib: str | None = None) -> np.ndarray:
+    """Valid columns (1-based, ascending) from M via the Table I loop."""
+    M = np.ascontiguousarray(M, np.uint64)
+    cols = np.empty(p, np.int32)
+    k = _lib(lib).or_extract(_ptr(M, _u64p), p, _ptr(cols))
+    if k < 0:
+        raise OracleError(f"or_extract failed: {k}")
+    return cols[:k].copy()
+
+
+def chain(lo: np.ndarray, hi: np.ndarray, p: int, lib: str | None = None):
+    """Lemma 1 chain as (x, lo, hi) arrays over the valid columns."""
+    lo = np.ascontiguousarray(lo, np.int32)
+    hi = np.ascontiguousarray(hi, np.int32)
+    x = np.empty(p, np.int32)
+    cl = np.empty(p, np.int32)
+    ch = np.empty(p, np.int32)
+    k = _lib(lib).or_chain(_ptr(lo), _ptr(hi), p, _ptr(x), _ptr(cl), _ptr(ch))
+    if k < 0:
+        raise OracleError(f"or_chain failed: {k}")
+    return x[:k].copy(), cl[:k].copy(), ch[:k].copy()
+
+
+def reduced(x, clo, chi, lib: str | None = None) -> np.ndarray:
+    """The reduced point sequence R along the chain, shape (s, 2)."""
+    x = np.ascontiguousarray(x, np.int32)
+    clo = np.ascontiguousarray(clo, np.int32)
+    chi = np.ascontiguousarray(chi, np.int32)
+    k = x.shape[0]
+    rx = np.empty(max(2 * k, 1), np.int32)
+    ry = np.empty(max(2 * k, 1), np.int32)
+    s = _lib(lib).or_reduced(_ptr(x), _ptr(clo), _ptr(chi), k, _ptr(rx), _ptr(ry))
+    return np.stack([rx[:s], ry[:s]], axis=1)
+
+
+def hull_chain(x, clo, chi, lib: str | None = None) -> np.ndarray:
+    """Hull of the chain: (h, 2) int32, CCW from the lexicographic minimum."""
+    x = np.ascontiguousarray(x, np.int32)
+    clo = np.ascontiguousarray(clo, np.int32)
+    chi = np.ascontiguousarray(chi, np.int32)
+    k = x.shape[0]
+    vx = np.empty(max(2 * k, 1), np.int32)
+    vy = np.empty(max(2 * k, 1), np.int32)
+    h = _lib(lib).or_hull_chain(_ptr(x), _ptr(clo), _ptr(chi), k, _ptr(vx), _ptr(vy))
+    if h < 0:
+        raise OracleError(f"or_hull_chain failed: {h}")
+    return np.stack([vx[:h], vy[:h]], axis=1)
+
+
+def hull_full(pts, lib: str | None = None) -> np.ndarray:
+    """Hull of all input points (sort + de-duplicate + Andrew)."""
+    a = _points(pts)
+    n = a.shape[0]
+    vx = np.empty(max(n, 1), np.int32)
+    vy = np.empty(max(n, 1), np.int32)
+    h = _lib(lib).or_hull_full(_ptr(a), n, _ptr(vx), _ptr(vy))
+    if h < 0:
+        raise OracleError(f"or_hull_full failed: {h}")
+    return np.stack([vx[:h], vy[:h]], axis=1)
+
+
+def precondition_and_hull(pts, p: int, lib: str | None = None) -> dict:
+    """The whole path on one cloud: L, M, chain, reduced set and hull."""
+    lo, hi = reduce(pts, p, lib)
+    M = mask(lo, hi, p, lib)
+    x, cl, ch = chain(lo, hi, p, lib)
+    hull = hull_chain(x, cl, ch, lib)
+    return {"lo": lo, "hi": hi, "mask": M, "x": x, "clo": cl, "chi": ch,
+            "k": int(x.shape[0]), "hull": hull}

@@ -1,0 +1,331 @@
+"""Pins of the CPU oracle: what the paper and plain mathematics fix.
+
+Each ``pin_*`` function runs one family of checks against an oracle build
+(``lib`` = path of a compiled oracle, ``None`` for the real one) and returns
+a list of failure messages (empty = pinned).  The same functions are run
+against planted-mistake builds of the oracle to show they would catch them.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+from tests import brute
+from tests.golden import fixtures
+
+
+def _safe(fn):
+    def wrapped(lib=None):
+        try:
+            return fn(lib)
+        except Exception as e:  # an oracle failing loudly is also a catch
+            return [f"{fn.__name__} raised {type(e).__name__}: {e}"]
+    wrapped.__name__ = fn.__name__
+    return wrapped
+
+
+def _run_path(pts, p, lib):
+    r = oracle.precondition_and_hull(pts, p, lib=lib)
+    return r
+
+
+@_safe
+def pin_worked_example(lib=None):
+    """Algorithm 1 worked example (p = 5) and its pentagon hull."""
+    f = fixtures.read("worked_example_p5.txt")
+    p = int(f["p"][0])
+    pts = fixtures.pairs(f["points"])
+    want = fixtures.pairs(f["L"])
+    errs = []
+    r = _run_path(pts, p, lib)
+    got = list(zip(r["lo"].tolist(), r["hi"].tolist()))
+    if got != want:
+        errs.append(f"L {got} != paper {want}")
+    if r["hull"].shape[0] != int(f["hull_vertices"][0]):
+        errs.append(f"hull has {r['hull'].shape[0]} vertices, paper: pentagon")
+    # the vertex list follows from the paper's L by hand: the lower side runs
+    # (1,1) -> (5,2), the right side (5,2) -> (5,3), the upper side
+    # (5,3) -> (3,5) -> (1,4); every other reduced point lies strictly inside.
+    if [tuple(v) for v in r["hull"].tolist()] != [(1, 1), (5, 2), (5, 3), (3, 5), (1, 4)]:
+        errs.append(f"hull {r['hull'].tolist()}")
+    errs += brute.check_canonical_hull(r["hull"].tolist(), pts)
+    return errs
+
+
+@_safe
+def pin_gap_example(lib=None):
+    """Sentinel (p+1, -1) in empty columns and the valid-entry word 10101."""
+    f = fixtures.read("gap_example_p5.txt")
+    p = int(f["p"][0])
+    pts = fixtures.pairs(f["points"])
+    want = fixtures.pairs(f["L"])
+    errs = []
+    r = _run_path(pts, p, lib)
+    got = list(zip(r["lo"].tolist(), r["hi"].tolist()))
+    if got != want:
+        errs.append(f"L {got} != paper {want}")
+    word = int(f["mask_bits"][0], 2)
+    if r["mask"].tolist() != [word]:
+        errs.append(f"mask {r['mask'].tolist()} != {word}")
+    cols = oracle.extract(r["mask"], p, lib=lib).tolist()
+    if cols != [1, 3, 5]:
+        errs.append(f"extracted columns {cols}")
+    if r["x"].tolist() != [1, 3, 5]:
+        errs.append(f"chain x {r['x'].tolist()}")
+    return errs
+
+
+@_safe
+def pin_table1(lib=None):
+    f = fixtures.read("table1_ctz.txt")
+    word = int(f["word"][0], 0)
+    want = [int(v) for v in f["positions"]]
+    got = oracle.ctz_positions(word, lib=lib)
+    errs = [] if got == want else [f"ctz positions {got} != {want}"]
+    # every single bit of a 64-bit word, and the all-ones word
+    for b in range(64):
+        if oracle.ctz_positions(1 << b, lib=lib) != [b]:
+            errs.append(f"single bit {b}")
+            break
+    if oracle.ctz_positions((1 << 64) - 1, lib=lib) != list(range(64)):
+        errs.append("all-ones word")
+    return errs
+
+
+@_safe
+def pin_block_index(lib=None):
+    f = fixtures.read("block_index.txt")
+    i = int(f["i"][0])
+    b32, pb32 = (int(v) for v in f["w32"])
+    b64, pb64 = (int(v) for v in f["w64"])
+    errs = []
+    if b32 * 32 + pb32 + 1 != i or b64 * 64 + pb64 + 1 != i:
+        errs.append("fixture inconsistent")
+    p = i + 100
+    r = _run_path([(i, 7)], p, lib)
+    M = r["mask"]
+    nz = np.nonzero(M)[0].tolist()
+    if nz != [b64] or int(M[b64]) != (1 << pb64):
+        errs.append(f"mask non-zero words {nz}")
+    if oracle.extract(M, p, lib=lib).tolist() != [i]:
+        errs.append("extract")
+    return errs
+
+
+@_safe
+def pin_closed_forms(lib=None):
+    errs = []
+    for p in range(1, 8):
+        grid = [(x, y) for x in range(1, p + 1) for y in range(1, p + 1)]
+        r = _run_path(grid, p, lib)
+        if r["lo"].tolist() != [1] * p or r["hi"].tolist() != [p] * p:
+            errs.append(f"full grid p={p}: L")
+        want = [(1, 1)] if p == 1 else [(1, 1), (p, 1), (p, p), (1, p)]
+        if [tuple(v) for v in r["hull"].tolist()] != want:
+            errs.append(f"full grid p={p}: hull {r['hull'].tolist()}")
+    p = 6
+    cases = {
+        "diagonal": ([(i, i) for i in range(1, 7)], [(1, 1), (6, 6)]),
+        "antidiagonal": ([(i, 7 - i) for i in range(1, 7)], [(1, 6), (6, 1)]),
+        "row": ([(i, 4) for i in range(1, 7)], [(1, 4), (6, 4)]),
+        "column": ([(3, y) for y in (5, 2, 4, 3)], [(3, 2), (3, 5)]),
+        "point": ([(2, 5)], [(2, 5)]),
+        "duplicates": ([(4, 4)] * 5, [(4, 4)]),
+        "two-points": ([(5, 1), (2, 3)], [(2, 3), (5, 1)]),
+        "triangle+collinear": ([(1, 1), (3, 1), (5, 1), (3, 3), (2, 2), (4, 2)],
+                               [(1, 1), (5, 1), (3, 3)]),
+    }
+    for name, (pts, want) in cases.items():
+        r = _run_path(pts, p, lib)
+        got = [tuple(v) for v in r["hull"].tolist()]
+        if got != want:
+            errs.append(f"{name}: hull {got} != {want}")
+    r = _run_path(np.zeros((0, 2), np.int32), 9, lib)
+    if r["k"] != 0 or r["hull"].shape[0] != 0:
+        errs.append("empty input")
+    if r["lo"].tolist() != [10] * 9 or r["hi"].tolist() != [-1] * 9:
+        errs.append("empty input: L not all sentinel")
+    return errs
+
+
+def _check_small(pts, p, lib) -> list[str]:
+    errs = []
+    r = _run_path(pts, p, lib)
+    lo, hi = brute.column_extremes(pts, p)
+    if r["lo"].tolist() != lo or r["hi"].tolist() != hi:
+        errs.append(f"L mismatch for {pts}")
+    e = brute.check_canonical_hull(r["hull"].tolist(), pts)
+    if e:
+        errs.append(f"hull_chain {pts} p={p}: {e[0]}")
+    full = oracle.hull_full(pts, lib=lib)
+    if full.tolist() != r["hull"].tolist():
+        errs.append(f"hull_full != hull_chain for {pts}")
+    R = oracle.reduced(r["x"], r["clo"], r["chi"], lib=lib)
+    if not brute.polyline_is_simple(R.tolist()):
+        errs.append(f"chain not simple for {pts}")
+    return errs
+
+
+@_safe
+def pin_brute_random(lib=None):
+    rng = np.random.default_rng(20150504)
+    errs = []
+    for _ in range(250):
+        p = int(rng.integers(1, 9))
+        n = int(rng.integers(1, 15))
+        pts = [tuple(v) for v in rng.integers(1, p + 1, size=(n, 2)).tolist()]
+        errs += _check_small(pts, p, lib)
+        if len(errs) > 3:
+            break
+    return errs
+
+
+@_safe
+def pin_exhaustive_p3(lib=None):
+    cells = [(x, y) for x in range(1, 4) for y in range(1, 4)]
+    errs = []
+    for bits in range(1, 1 << 9):
+        pts = [c for j, c in enumerate(cells) if bits >> j & 1]
+        errs += _check_small(pts, 3, lib)
+        if len(errs) > 3:
+            break
+    return errs
+
+
+@_safe
+def pin_qhull(lib=None):
+    from scipy.spatial import ConvexHull
+
+    from paper_1505_00914_amd import synth
+
+    errs = []
+    for kind, n, p, seed in [("uniform", 3000, 200, 1), ("ellipsoids", 5000, 256, 2),
+                             ("gaussian", 5000, 256, 3), ("disc", 5000, 300, 4)]:
+        pts = synth.cloud(kind, n, p, seed).numpy()
+        r = _run_path(pts, p, lib)
+        q = ConvexHull(pts.astype(np.float64))
+        want = set(map(tuple, pts[q.vertices].tolist()))
+        got = set(map(tuple, r["hull"].tolist()))
+        if got != want:
+            errs.append(f"{kind}: oracle hull != Qhull vertices")
+    return errs
+
+
+@_safe
+def pin_appendix(lib=None):
+    """hull(reduced set) == hull(all points), exactly, on larger clouds."""
+    from paper_1505_00914_amd import synth
+
+    errs = []
+    for kind, n, p, seed in [("uniform", 100_000, 1024, 0), ("ellipsoids", 100_000, 4096, 2),
+                             ("gaussian", 50_000, 512, 7), ("disc", 50_000, 2048, 9),
+                             ("uniform", 300, 100_000, 5)]:
+        pts = synth.cloud(kind, n, p, seed).numpy()
+        r = _run_path(pts, p, lib)
+        full = oracle.hull_full(pts, lib=lib)
+        if full.tolist() != r["hull"].tolist():
+            errs.append(f"{kind}: hull(reduced) != hull(full)")
+    return errs
+
+
+@_safe
+def pin_invariants(lib=None):
+    from paper_1505_00914_amd import synth
+
+    errs = []
+    for kind, n, p, seed in [("uniform", 20_000, 512, 11), ("ellipsoids", 30_000, 1024, 12),
+                             ("uniform", 50, 1000, 13)]:
+        pts = synth.cloud(kind, n, p, seed).numpy()
+        r = _run_path(pts, p, lib)
+        R = oracle.reduced(r["x"], r["clo"], r["chi"], lib=lib)
+        s, k = R.shape[0], r["k"]
+        if not (s <= 2 * p and s <= n and k <= min(n, p) and k <= s):
+            errs.append(f"{kind}: size bounds s={s} k={k}")
+        keys = R[:, 0].astype(np.int64) * (p + 2) + R[:, 1]
+        if not np.all(np.diff(keys) > 0):
+            errs.append(f"{kind}: R not strictly lexicographic")
+        want = set()
+        for x, lo, hi in zip(r["x"].tolist(), r["clo"].tolist(), r["chi"].tolist()):
+            want.add((x, lo))
+            want.add((x, hi))
+        if set(map(tuple, R.tolist())) != want:
+            errs.append(f"{kind}: R is not the set of column extremes")
+        if oracle.extract(r["mask"], p, lib=lib).tolist() != r["x"].tolist():
+            errs.append(f"{kind}: extract(M) != chain x")
+        if int(sum(bin(int(w)).count("1") for w in r["mask"])) != k:
+            errs.append(f"{kind}: popcount(M) != k")
+    pts = synth.cloud("uniform", 40, 30, 3).numpy()
+    r = _run_path(pts, 30, lib)
+    if not brute.polyline_is_simple(oracle.reduced(r["x"], r["clo"], r["chi"], lib=lib).tolist()):
+        errs.append("chain not simple")
+    return errs
+
+
+@_safe
+def pin_metamorphic(lib=None):
+    from paper_1505_00914_amd import synth
+
+    errs = []
+    p = 300
+    pts = synth.cloud("ellipsoids", 20_000, p, 21).numpy()
+    base = _run_path(pts, p, lib)
+    rng = np.random.default_rng(3)
+    perm = pts[rng.permutation(pts.shape[0])]
+    r = _run_path(perm, p, lib)
+    if r["lo"].tolist() != base["lo"].tolist() or r["hi"].tolist() != base["hi"].tolist():
+        errs.append("not permutation invariant")
+    dup = np.concatenate([pts, pts[: 5000]], 0)
+    r = _run_path(dup, p, lib)
+    if r["lo"].tolist() != base["lo"].tolist() or r["hull"].tolist() != base["hull"].tolist():
+        errs.append("not duplication invariant")
+    mx = pts.copy()
+    mx[:, 0] = p + 1 - mx[:, 0]
+    r = _run_path(mx, p, lib)
+    if r["lo"].tolist() != base["lo"][::-1].tolist() or r["hi"].tolist() != base["hi"][::-1].tolist():
+        errs.append("x reflection does not reverse L")
+    mapped = {(p + 1 - x, y) for x, y in base["hull"].tolist()}
+    if set(map(tuple, r["hull"].tolist())) != mapped:
+        errs.append("x reflection does not map the hull")
+    my = pts.copy()
+    my[:, 1] = p + 1 - my[:, 1]
+    r = _run_path(my, p, lib)
+    valid = base["hi"] >= 0
+    if not (np.array_equal(r["lo"][valid], p + 1 - base["hi"][valid])
+            and np.array_equal(r["hi"][valid], p + 1 - base["lo"][valid])):
+        errs.append("y reflection does not swap and mirror lo/hi")
+    mapped = {(x, p + 1 - y) for x, y in base["hull"].tolist()}
+    if set(map(tuple, r["hull"].tolist())) != mapped:
+        errs.append("y reflection does not map the hull")
+    t = pts[:, ::-1].copy()
+    r = _run_path(t, p, lib)
+    if set(map(tuple, r["hull"].tolist())) != {(y, x) for x, y in base["hull"].tolist()}:
+        errs.append("transpose does not map the hull")
+    return errs
+
+
+@_safe
+def pin_errors(lib=None):
+    errs = []
+    for pts, p in [([(0, 1)], 4), ([(1, 5)], 4), ([(5, 1)], 4), ([(2, -1)], 4)]:
+        try:
+            oracle.reduce(pts, p, lib=lib)
+            errs.append(f"no error for {pts} with p={p}")
+        except oracle.OracleError as e:
+            if str(oracle.OR_ERANGE) not in str(e):
+                errs.append(f"wrong error {e}")
+    try:
+        oracle.reduce([(1, 1)], 0, lib=lib)
+        errs.append("p = 0 accepted")
+    except oracle.OracleError:
+        pass
+    return errs
+
+
+ALL_PINS = [pin_worked_example, pin_gap_example, pin_table1, pin_block_index,
+            pin_closed_forms, pin_brute_random, pin_exhaustive_p3, pin_qhull,
+            pin_appendix, pin_invariants, pin_metamorphic, pin_errors]
+
+# the cheap pins, run first against planted mistakes
+FAST_PINS = [pin_worked_example, pin_gap_example, pin_table1, pin_block_index,
+             pin_closed_forms, pin_errors, pin_brute_random]
+

@@ -1,0 +1,67 @@
+"""Planted mistakes in copies of the oracle must each fail at least one pin.
+
+Every mutant is a one-token change of the kind a careless edit makes: a
+flipped comparison, a swapped operand, a dropped term, an off-by-one.  The
+real ``oracle.c`` is never modified; each mutant is compiled from a patched
+copy into a temporary directory, on the CPU.
+"""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+from tests import oracle_pins
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+MUTANTS = {
+    "collinear-kept": ("<= 0) --t;", "< 0) --t;"),
+    "min-as-max": ("int32_t ly = yi < yv ? yi : yv;", "int32_t ly = yi > yv ? yi : yv;"),
+    "max-as-min": ("int32_t hy = yi > yu ? yi : yu;", "int32_t hy = yi < yu ? yi : yu;"),
+    "sentinel-lo": ("lo[i] = p + 1;", "lo[i] = p;"),
+    "sentinel-hi": ("hi[i] = -1;", "hi[i] = 0;"),
+    "x-y-swapped": ("int32_t xi = pts[2 * j], yi = pts[2 * j + 1];",
+                    "int32_t yi = pts[2 * j], xi = pts[2 * j + 1];"),
+    "store-lo-into-hi": ("hi[xi - 1] = hy;", "hi[xi - 1] = ly;"),
+    "cross-sign": ("return (ax - ox) * (by - oy) - (ay - oy) * (bx - ox);",
+                   "return (ay - oy) * (bx - ox) - (ax - ox) * (by - oy);"),
+    "cross-dropped-term": ("return (ax - ox) * (by - oy) - (ay - oy) * (bx - ox);",
+                           "return (ax - ox) * (by - oy);"),
+    "cross-transposed": ("return (ax - ox) * (by - oy) - (ay - oy) * (bx - ox);",
+                         "return (ax - ox) * (by - oy) - (ay - oy) * (bx - oy);"),
+    "keep-last-of-lower": ("    for (int64_t i = 0; i + 1 < t; ++i) {\n        vx[h] = sx[i];",
+                           "    for (int64_t i = 0; i < t; ++i) {\n        vx[h] = sx[i];"),
+    "mask-bit-off-by-one": ("int64_t pb = (i - 1) & 63;", "int64_t pb = i & 63;"),
+    "ctz-pos-off-by-one": ("pos[c++] = q;", "pos[c++] = q + 1;"),
+    "valid-inverted": ("return !(lo == p + 1 && hi == -1);", "return (lo == p + 1 && hi == -1);"),
+    "reduced-repeats-single": ("if (chi[t] > clo[t]) {", "if (chi[t] >= clo[t]) {"),
+    "range-check-off": ("if (x < 1 || x > p || y < 1 || y > p) return OR_ERANGE;",
+                        "if (x < 1 || x > p || y < 1) return OR_ERANGE;"),
+    "chain-skips-last": ("for (int32_t i = 1; i <= p; ++i) {\n        if (or_valid(lo[i - 1], hi[i - 1], p)) {\n            x[k] = i;",
+                         "for (int32_t i = 1; i < p; ++i) {\n        if (or_valid(lo[i - 1], hi[i - 1], p)) {\n            x[k] = i;"),
+}
+
+
+def _build_mutant(tmp_path, name, old, new):
+    src = open(os.path.join(ROOT, "oracle", "oracle.c")).read()
+    assert src.count(old) >= 1, f"mutant {name}: pattern not found"
+    src = src.replace(old, new)
+    d = tmp_path / name
+    d.mkdir()
+    shutil.copy(os.path.join(ROOT, "oracle", "oracle.h"), d / "oracle.h")
+    (d / "oracle.c").write_text(src)
+    out = d / "liboracle_mutant.so"
+    subprocess.run(["gcc", "-O1", "-std=c99", "-fPIC", "-shared", "-o", str(out), str(d / "oracle.c")],
+                   check=True)
+    return str(out)
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(tmp_path, name):
+    old, new = MUTANTS[name]
+    lib = _build_mutant(tmp_path, name, old, new)
+    for pin in oracle_pins.FAST_PINS + [p for p in oracle_pins.ALL_PINS if p not in oracle_pins.FAST_PINS]:
+        if pin(lib):
+            return
+    pytest.fail(f"no pin catches mutant {name}")
