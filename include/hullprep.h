@@ -1,0 +1,199 @@
+/*
+ * hullprep.h -- C ABI of libhullprep.so, an MI355X (gfx950) implementation of
+ * the sort-free convex-hull preconditioner of Cadenas & Megson, "An Empirical
+ * Evaluation of Preconditioning Data for Accelerating Convex Hull
+ * Computations" (arXiv 1505.00914), followed by an exact hull of the reduced
+ * chain.
+ *
+ * The path, per point cloud:
+ *   1. L init    -- every column of L starts as the empty sentinel (p+1, -1)
+ *                   (Algorithm 1, initialisation of L);
+ *   2. reduce    -- each point (x, y) lowers L[x].lo to y and raises L[x].hi
+ *                   to y (Algorithm 1, the loop over P);
+ *   3. compact   -- the columns that are not the sentinel, in ascending x,
+ *                   become the chain (Lemma 1 and the "Building a polyline"
+ *                   paragraph; extraction order of Table I);
+ *   4. hull      -- the convex hull of the chain's points, listed CCW from the
+ *                   lexicographic minimum, strictly convex vertices only (the
+ *                   Appendix: collinear points are not hull vertices).
+ *
+ * Conventions shared by every entry point
+ * ----------------------------------------
+ * - Points are interleaved int32 pairs (x, y) in DEVICE memory, 1 <= x, y <= p
+ *   (the square of side p of the "Proposed heuristic" section).  Points
+ *   outside that square are skipped and reported through the device status
+ *   word (HP_ERANGE); the other outputs of that cloud are then unspecified.
+ * - 1 <= p <= HP_P_MAX so that the sentinel p+1 fits in int32.  n >= 0 is a
+ *   64-bit count.
+ * - L is two int32 arrays lo[p], hi[p]; column x lives at index x-1.
+ * - The bit array M uses 64-bit words: column i is bit (i-1)&63 of word
+ *   (i-1)>>6 (Discussion, "Extraction using an array of bits", w = 64).
+ * - A chain is three int32 arrays x[], lo[], hi[] over the valid columns in
+ *   ascending x.  Its reduced point sequence is, per column, (x, lo) then
+ *   (x, hi) when hi > lo (Lemma 1).
+ * - A hull is two int32 arrays hx[], hy[]: counter-clockwise, starting at the
+ *   lexicographically smallest vertex, no repeated closing vertex, collinear
+ *   boundary points dropped.  0, 1 or 2 vertices for degenerate inputs.
+ * - "info" is a DEVICE int32[4] per cloud: [HP_INFO_STATUS] = HP_OK or a
+ *   negative data error, [HP_INFO_K] = valid columns k, [HP_INFO_S] = reduced
+ *   points s, [HP_INFO_H] = hull vertices h.  It is written asynchronously;
+ *   read it after synchronising the stream.
+ * - Every data buffer is caller-owned device memory.  The library allocates
+ *   nothing during hp_precondition / hp_hull / hp_run / hp_batched_run; the
+ *   caller passes a workspace of at least the size the matching *_bytes /
+ *   plan query returns.  The workspace needs no initialisation and must not
+ *   be shared by calls that may overlap.
+ * - All calls are asynchronous on `stream` (a hipStream_t, or NULL for the
+ *   null stream).  A return value < 0 is a synchronous argument or launch
+ *   error and nothing was enqueued; hp_last_error() then describes it (per
+ *   thread).  Data errors never abort: they land in info[HP_INFO_STATUS].
+ * - Calls on different streams with different workspaces may run
+ *   concurrently.
+ */
+#ifndef HULLPREP_H
+#define HULLPREP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HP_ABI_VERSION 1
+
+#define HP_OK         0
+#define HP_EINVAL    (-1)  /* bad argument: NULL pointer, p or n out of range  */
+#define HP_ERANGE    (-2)  /* (device status) a coordinate outside [1, p]       */
+#define HP_ECAPACITY (-3)  /* an output or workspace is smaller than required   */
+#define HP_EDEVICE   (-4)  /* a HIP call failed                                  */
+#define HP_ENOMEM    (-5)  /* host or device allocation failed (plans only)      */
+
+#define HP_P_MAX 2147483646
+
+#define HP_INFO_STATUS 0
+#define HP_INFO_K      1
+#define HP_INFO_S      2
+#define HP_INFO_H      3
+#define HP_INFO_WORDS  4
+
+/* Reduction strategies for Algorithm 1 (all give identical results). */
+#define HP_STRATEGY_AUTO    0  /* tuned choice per (n, p) regime                */
+#define HP_STRATEGY_LDS     1  /* workgroup-private L in LDS, merged afterwards */
+#define HP_STRATEGY_GLOBAL  2  /* one L in device memory, filtered atomics      */
+
+/* Human-readable name of a status code (static string). */
+const char *hp_status_string(int code);
+
+/* Description of the last synchronous error on this host thread. */
+const char *hp_last_error(void);
+
+/* HP_ABI_VERSION of the loaded library. */
+int hp_abi_version(void);
+
+/* Largest p that the LDS strategy accepts on the current device. */
+int32_t hp_lds_max_p(void);
+
+/* Force a strategy for later calls on this process (HP_STRATEGY_*), e.g. for
+ * tests; HP_STRATEGY_AUTO restores the tuned choice.  Also settable with the
+ * environment variable HP_FORCE_STRATEGY=lds|global. */
+int hp_set_strategy(int strategy);
+
+/* Launch-shape override for later calls in this process (used by the tuner):
+ * strategy (HP_STRATEGY_*), reduce block size (256, 512 or 1024), 16-byte
+ * vectors per lane per step (2, 4 or 8) and grid size; 0 leaves a field to
+ * the tuning table.  hp_tune_set(0, 0, 0, 0) clears every override. */
+int hp_tune_set(int32_t strategy, int32_t block, int32_t vpt, int32_t grid);
+
+/* Load a tuning table written by the tuner: one line per regime
+ * "log2n log2p strategy block vpt grid"; '#' starts a comment line. */
+int hp_tune_load(const char *path);
+
+/* ------------------------------------------------------------------------
+ * Single cloud
+ * ---------------------------------------------------------------------- */
+
+/* Workspace size (bytes) for hp_precondition and hp_run on n points with
+ * side p.  Returns HP_OK and writes *bytes, or HP_EINVAL. */
+int hp_workspace_bytes(int64_t n, int32_t p, size_t *bytes);
+
+/* Steps 1-3 (L init, Algorithm 1, compaction into the Lemma 1 chain).
+ *   pts        device, 2n int32, interleaved (x, y); may be NULL when n == 0
+ *   lo, hi     device, p int32 each, or both NULL: receive L
+ *   mask       device, ceil(p/64) uint64, or NULL: receives M
+ *   cx, clo, chi  device, chain_cap int32 each: receive the chain
+ *   chain_cap  must be >= min(n, p) (HP_ECAPACITY otherwise)
+ *   info       device int32[4]: status, k, s (h is left as 0)
+ *   ws         device workspace of ws_bytes >= hp_workspace_bytes(n, p)
+ */
+int hp_precondition(const int32_t *pts, int64_t n, int32_t p,
+                    int32_t *lo, int32_t *hi, uint64_t *mask,
+                    int32_t *cx, int32_t *clo, int32_t *chi, int32_t chain_cap,
+                    int32_t *info, void *ws, size_t ws_bytes, void *stream);
+
+/* Workspace size (bytes) for hp_hull on a chain of capacity chain_cap. */
+int hp_hull_workspace_bytes(int32_t chain_cap, size_t *bytes);
+
+/* Step 4 alone: the hull of a chain produced by hp_precondition (or any
+ * chain with strictly increasing x and lo <= hi).  The chain length k is
+ * read on the device from info[HP_INFO_K]; info[HP_INFO_H] receives h.
+ *   hx, hy     device, hull_cap int32 each; hull_cap >= 2 * chain_cap
+ */
+int hp_hull(const int32_t *cx, const int32_t *clo, const int32_t *chi, int32_t chain_cap,
+            int32_t *hx, int32_t *hy, int32_t hull_cap,
+            int32_t *info, void *ws, size_t ws_bytes, void *stream);
+
+/* Steps 1-4 fused: the chain and its hull in one call (the hull is built
+ * from L directly, in parallel with the chain write).  Arguments as above;
+ * hull_cap >= 2 * min(n, p).  Uses the hp_workspace_bytes(n, p) workspace. */
+int hp_run(const int32_t *pts, int64_t n, int32_t p,
+           int32_t *lo, int32_t *hi, uint64_t *mask,
+           int32_t *cx, int32_t *clo, int32_t *chi, int32_t chain_cap,
+           int32_t *hx, int32_t *hy, int32_t hull_cap,
+           int32_t *info, void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Batches of ragged clouds (one persistent launch, replayed from a HIP graph)
+ * ---------------------------------------------------------------------- */
+
+typedef struct hp_plan hp_plan;
+
+/* Build a plan for B clouds.  offsets: HOST int64[B+1], non-decreasing, cloud
+ * b owns points [offsets[b], offsets[b+1]) of the concatenated array;
+ * p: HOST int32[B].  The plan copies both, picks a strategy and a work split
+ * per cloud, and owns small device descriptor tables (allocated here, freed by
+ * hp_plan_destroy).  Returns HP_OK and *plan, or an error. */
+int hp_plan_create(const int64_t *offsets, const int32_t *p, int32_t B, hp_plan **plan);
+
+/* Output and workspace sizes of a plan.  Cloud b's chain occupies
+ * [chain_off[b], chain_off[b+1]) of the chain arrays (capacity min(n_b, p_b))
+ * and its hull [hull_off[b], hull_off[b+1]) of the hull arrays (capacity
+ * 2 min(n_b, p_b)).  Any pointer may be NULL; chain_off / hull_off are HOST
+ * int64[B+1]. */
+int hp_plan_query(const hp_plan *plan, int64_t *chain_total, int64_t *hull_total,
+                  size_t *ws_bytes, int64_t *chain_off, int64_t *hull_off);
+
+/* Run a plan: every cloud's chain, hull and info (device int32[B][4]).
+ * The first call on a given (stream, buffers) captures a HIP graph of the
+ * launch sequence; later calls with the same buffers replay it. */
+int hp_batched_run(hp_plan *plan, const int32_t *pts,
+                   int32_t *cx, int32_t *clo, int32_t *chi,
+                   int32_t *hx, int32_t *hy, int32_t *info,
+                   void *ws, size_t ws_bytes, void *stream);
+
+/* Baseline of the batched form: the same outputs computed by one plain
+ * hp_run-style launch sequence per cloud, cloud after cloud, on `stream`.
+ * Uses the same workspace size as hp_batched_run. */
+int hp_batched_run_percloud(hp_plan *plan, const int32_t *pts,
+                            int32_t *cx, int32_t *clo, int32_t *chi,
+                            int32_t *hx, int32_t *hy, int32_t *info,
+                            void *ws, size_t ws_bytes, void *stream);
+
+/* Free a plan (NULL is accepted).  The caller must have synchronised every
+ * stream the plan ran on. */
+void hp_plan_destroy(hp_plan *plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HULLPREP_H */

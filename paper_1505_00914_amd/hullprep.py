@@ -1,0 +1,155 @@
+"""Python binding of libhullprep with torch tensors for device memory.
+
+Names follow the C ABI (``hp_precondition``, ``hp_hull``, ``hp_run``, plans
+for batches); torch only provides device buffers and the current stream.
+Inputs must already be int32 CUDA (HIP) tensors; nothing is converted or
+computed here.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+from ._lib import (HP_INFO_H, HP_INFO_K, HP_INFO_S, HP_INFO_STATUS,  # noqa: F401
+                   HP_STRATEGY_AUTO, HP_STRATEGY_GLOBAL, HP_STRATEGY_LDS, HullprepError)
+
+
+def _ptr(t: torch.Tensor | None) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _check_points(points: torch.Tensor) -> int:
+    if not points.is_cuda:
+        raise ValueError("points must be a device tensor")
+    if points.dtype != torch.int32 or points.dim() != 2 or points.shape[1] != 2:
+        raise ValueError("points must be an (n, 2) int32 tensor")
+    if not points.is_contiguous():
+        raise ValueError("points must be contiguous")
+    return points.shape[0]
+
+
+def workspace_bytes(n: int, p: int) -> int:
+    v = ctypes.c_size_t()
+    _lib.call("hp_workspace_bytes", n, p, ctypes.byref(v))
+    return v.value
+
+
+def hull_workspace_bytes(chain_cap: int) -> int:
+    v = ctypes.c_size_t()
+    _lib.call("hp_hull_workspace_bytes", chain_cap, ctypes.byref(v))
+    return v.value
+
+
+def set_strategy(strategy: int) -> None:
+    _lib.call("hp_set_strategy", strategy)
+
+
+def tune_set(strategy: int = 0, block: int = 0, vpt: int = 0, grid: int = 0) -> None:
+    _lib.call("hp_tune_set", strategy, block, vpt, grid)
+
+
+def tune_load(path: str) -> None:
+    _lib.call("hp_tune_load", path.encode())
+
+
+def lds_max_p() -> int:
+    return int(_lib.load().hp_lds_max_p())
+
+
+@dataclass
+class Buffers:
+    """Caller-owned device buffers of one single-cloud call."""
+    n: int
+    p: int
+    lo: torch.Tensor
+    hi: torch.Tensor
+    mask: torch.Tensor
+    cx: torch.Tensor
+    clo: torch.Tensor
+    chi: torch.Tensor
+    hx: torch.Tensor
+    hy: torch.Tensor
+    info: torch.Tensor
+    ws: torch.Tensor
+
+    @staticmethod
+    def allocate(n: int, p: int, device, export_L: bool = True) -> "Buffers":
+        cap = max(1, min(n, p))
+        i32 = dict(dtype=torch.int32, device=device)
+        lo = torch.empty(p, **i32) if export_L else None
+        hi = torch.empty(p, **i32) if export_L else None
+        mask = torch.empty((p + 63) // 64, dtype=torch.int64, device=device) if export_L else None
+        return Buffers(n, p, lo, hi, mask,
+                       torch.empty(cap, **i32), torch.empty(cap, **i32), torch.empty(cap, **i32),
+                       torch.empty(2 * cap, **i32), torch.empty(2 * cap, **i32),
+                       torch.zeros(4, **i32),
+                       torch.empty(workspace_bytes(n, p), dtype=torch.uint8, device=device))
+
+
+def hp_precondition(points: torch.Tensor, p: int, buf: Buffers, stream=None) -> None:
+    """Enqueue L init, Algorithm 1 and the chain compaction (no sync)."""
+    n = _check_points(points)
+    _lib.call("hp_precondition", _ptr(points), n, p, _ptr(buf.lo), _ptr(buf.hi), _ptr(buf.mask),
+              _ptr(buf.cx), _ptr(buf.clo), _ptr(buf.chi), buf.cx.numel(), _ptr(buf.info),
+              _ptr(buf.ws), buf.ws.numel(), _stream(stream))
+
+
+def hp_hull(buf: Buffers, stream=None, ws: torch.Tensor | None = None) -> None:
+    """Enqueue the hull of the chain held in ``buf`` (k read on device)."""
+    cap = buf.cx.numel()
+    if ws is None:
+        need = hull_workspace_bytes(cap)
+        ws = buf.ws if buf.ws.numel() >= need else torch.empty(need, dtype=torch.uint8,
+                                                                device=buf.ws.device)
+    _lib.call("hp_hull", _ptr(buf.cx), _ptr(buf.clo), _ptr(buf.chi), cap, _ptr(buf.hx),
+              _ptr(buf.hy), buf.hx.numel(), _ptr(buf.info), _ptr(ws), ws.numel(),
+              _stream(stream))
+
+
+def hp_run(points: torch.Tensor, p: int, buf: Buffers, stream=None) -> None:
+    """Enqueue the fused path: chain and hull (no sync)."""
+    n = _check_points(points)
+    _lib.call("hp_run", _ptr(points), n, p, _ptr(buf.lo), _ptr(buf.hi), _ptr(buf.mask),
+              _ptr(buf.cx), _ptr(buf.clo), _ptr(buf.chi), buf.cx.numel(), _ptr(buf.hx),
+              _ptr(buf.hy), buf.hx.numel(), _ptr(buf.info), _ptr(buf.ws), buf.ws.numel(),
+              _stream(stream))
+
+
+def collect(buf: Buffers) -> dict:
+    """Synchronise and return host copies of every output (trimmed)."""
+    torch.cuda.synchronize(buf.info.device)
+    info = buf.info.cpu().tolist()
+    k, h = info[HP_INFO_K], info[HP_INFO_H]
+    out = {"status": info[HP_INFO_STATUS], "k": k, "s": info[HP_INFO_S], "h": h,
+           "x": buf.cx[:k].cpu().numpy(), "clo": buf.clo[:k].cpu().numpy(),
+           "chi": buf.chi[:k].cpu().numpy(),
+           "hull": torch.stack([buf.hx[:h], buf.hy[:h]], 1).cpu().numpy()}
+    if buf.lo is not None:
+        out["lo"] = buf.lo.cpu().numpy()
+        out["hi"] = buf.hi.cpu().numpy()
+        out["mask"] = buf.mask.cpu().numpy().view("uint64")
+    return out
+
+
+def run(points: torch.Tensor, p: int, export_L: bool = True) -> dict:
+    """One cloud end to end (allocates its buffers; for tests and examples)."""
+    buf = Buffers.allocate(points.shape[0], p, points.device, export_L)
+    hp_run(points, p, buf)
+    return collect(buf)
+
+
+def precondition_then_hull(points: torch.Tensor, p: int) -> dict:
+    """hp_precondition followed by hp_hull on its chain."""
+    buf = Buffers.allocate(points.shape[0], p, points.device, True)
+    hp_precondition(points, p, buf)
+    hp_hull(buf)
+    return collect(buf)

@@ -1,0 +1,93 @@
+"""The C ABI library loads, exports what the header declares, and rejects
+bad arguments before touching a device (no compute call on the CPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1505_00914_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "hullprep.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hp_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_path():
+    names = _declared()
+    for need in ("hp_precondition", "hp_hull", "hp_run", "hp_plan_create", "hp_batched_run",
+                 "hp_plan_destroy", "hp_workspace_bytes", "hp_status_string"):
+        assert need in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert missing == []
+
+
+def test_binding_covers_every_declared_symbol():
+    assert sorted(_lib.SIGNATURES) == _declared()
+
+
+def test_status_strings():
+    lib = _lib.load()
+    for code in (0, -1, -2, -3, -4, -5):
+        assert lib.hp_status_string(code)
+    assert lib.hp_abi_version() == 1
+
+
+@pytest.mark.parametrize("n,p", [(10, 0), (10, -5), (-1, 10), (10, 2147483647)])
+def test_bad_sizes_rejected(n, p):
+    lib = _lib.load()
+    info = (ctypes.c_int32 * 4)()
+    dummy = ctypes.c_void_p(0x10000)
+    rc = lib.hp_run(dummy, n, p, None, None, None, dummy, dummy, dummy, 10, dummy, dummy, 20,
+                    ctypes.cast(info, ctypes.c_void_p), dummy, 1 << 20, None)
+    assert rc == _lib.HP_EINVAL
+    assert lib.hp_last_error()
+
+
+def test_null_and_capacity_rejected():
+    lib = _lib.load()
+    d = ctypes.c_void_p(0x10000)
+    # NULL points with n > 0
+    assert lib.hp_precondition(None, 5, 8, None, None, None, d, d, d, 5, d, d, 1 << 20, None) == _lib.HP_EINVAL
+    # misaligned points
+    assert lib.hp_precondition(ctypes.c_void_p(0x10004), 5, 8, None, None, None, d, d, d, 5, d, d,
+                               1 << 20, None) == _lib.HP_EINVAL
+    # lo without hi
+    assert lib.hp_precondition(d, 5, 8, d, None, None, d, d, d, 5, d, d, 1 << 20, None) == _lib.HP_EINVAL
+    # chain capacity below min(n, p)
+    assert lib.hp_precondition(d, 50, 8, None, None, None, d, d, d, 7, d, d, 1 << 20, None) == _lib.HP_ECAPACITY
+    # hull capacity below 2 min(n, p)
+    assert lib.hp_run(d, 50, 8, None, None, None, d, d, d, 8, d, d, 15, d, d, 1 << 20, None) == _lib.HP_ECAPACITY
+    # workspace too small
+    assert lib.hp_run(d, 50, 8, None, None, None, d, d, d, 8, d, d, 16, d, d, 16, None) == _lib.HP_ECAPACITY
+    # hull-only entry point
+    assert lib.hp_hull(d, d, d, 10, d, d, 19, d, d, 1 << 20, None) == _lib.HP_ECAPACITY
+    assert lib.hp_hull(d, d, d, -1, d, d, 19, d, d, 1 << 20, None) == _lib.HP_EINVAL
+
+
+def test_workspace_queries():
+    lib = _lib.load()
+    v = ctypes.c_size_t()
+    assert lib.hp_workspace_bytes(10_000_000, 4096, ctypes.byref(v)) == 0 and v.value > 0
+    small = v.value
+    assert lib.hp_workspace_bytes(10_000_000, 1 << 20, ctypes.byref(v)) == 0 and v.value > 0
+    assert lib.hp_hull_workspace_bytes(4096, ctypes.byref(v)) == 0 and v.value > 0
+    assert small > 0
+
+
+def test_strategy_and_tuning_setters():
+    lib = _lib.load()
+    assert lib.hp_set_strategy(7) == _lib.HP_EINVAL
+    assert lib.hp_set_strategy(0) == 0
+    assert lib.hp_tune_set(1, 300, 4, 10) == _lib.HP_EINVAL
+    assert lib.hp_tune_set(1, 256, 4, 10) == 0
+    assert lib.hp_tune_set(0, 0, 0, 0) == 0
+    assert lib.hp_tune_load(b"/nonexistent/table") == _lib.HP_EINVAL

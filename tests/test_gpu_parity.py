@@ -1,0 +1,173 @@
+"""GPU path (through the C ABI) against the CPU oracle, bit for bit.
+
+Every case runs the HIP library on seeded inputs and compares L, the M
+words, the chain (x, lo, hi), k, s and the hull vertex list exactly with the
+oracle computed on the same points.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1505_00914_amd import synth
+from tests.golden import fixtures
+
+pytestmark = pytest.mark.gpu
+
+HP_ERANGE = -2
+
+
+@pytest.fixture(scope="module")
+def hp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1505_00914_amd import hullprep
+    yield hullprep
+    hullprep.set_strategy(0)
+    hullprep.tune_set(0, 0, 0, 0)
+
+
+def _oracle(pts_np, p):
+    r = oracle.precondition_and_hull(pts_np, p)
+    R = oracle.reduced(r["x"], r["clo"], r["chi"])
+    r["s"] = int(R.shape[0])
+    return r
+
+
+def _compare(got, want, label, check_L=True):
+    assert got["status"] == 0, f"{label}: status {got['status']}"
+    assert got["k"] == want["k"], f"{label}: k {got['k']} != {want['k']}"
+    assert got["s"] == want["s"], f"{label}: s {got['s']} != {want['s']}"
+    if check_L:
+        assert np.array_equal(got["lo"], want["lo"]), f"{label}: lo differs"
+        assert np.array_equal(got["hi"], want["hi"]), f"{label}: hi differs"
+        assert np.array_equal(got["mask"], want["mask"]), f"{label}: M differs"
+    assert np.array_equal(got["x"], want["x"]), f"{label}: chain x differs"
+    assert np.array_equal(got["clo"], want["clo"]), f"{label}: chain lo differs"
+    assert np.array_equal(got["chi"], want["chi"]), f"{label}: chain hi differs"
+    assert got["h"] == want["hull"].shape[0], f"{label}: h {got['h']} != {want['hull'].shape[0]}"
+    assert np.array_equal(got["hull"], want["hull"]), f"{label}: hull differs"
+
+
+def _run_both(hp, pts_cpu: torch.Tensor, p: int, label: str, strategies=(1, 2), split=True):
+    print(f"[case] {label} n={pts_cpu.shape[0]} p={p}", flush=True)
+    want = _oracle(pts_cpu.numpy(), p)
+    dev = pts_cpu.cuda()
+    for s in strategies:
+        hp.set_strategy(s)
+        got = hp.run(dev, p)
+        _compare(got, want, f"{label}/strategy{s}/run")
+        if split:
+            got = hp.precondition_then_hull(dev, p)
+            _compare(got, want, f"{label}/strategy{s}/precondition+hull")
+    hp.set_strategy(0)
+    return want
+
+
+def test_worked_example(hp):
+    f = fixtures.read("worked_example_p5.txt")
+    pts = torch.tensor(fixtures.pairs(f["points"]), dtype=torch.int32)
+    want = _run_both(hp, pts, int(f["p"][0]), "worked-example")
+    assert list(zip(want["lo"].tolist(), want["hi"].tolist())) == fixtures.pairs(f["L"])
+
+
+def test_gap_example(hp):
+    f = fixtures.read("gap_example_p5.txt")
+    pts = torch.tensor(fixtures.pairs(f["points"]), dtype=torch.int32)
+    _run_both(hp, pts, int(f["p"][0]), "gap-example")
+
+
+@pytest.mark.parametrize("kind,n,p,seed", [
+    ("uniform", 100_000, 1024, 0),          # the small uniform workload, full size
+    ("uniform", 100_003, 1000, 5),          # ragged n and p
+    ("ellipsoids", 200_001, 4096, 2),
+    ("ellipsoids", 50_000, 4097, 3),
+    ("gaussian", 300_000, 4096, 4),
+    ("disc", 200_000, 65_536, 6),           # p beyond LDS: global strategy only
+    ("uniform", 1_000, 20_000, 7),          # sparse: p > n
+    ("uniform", 64, 64, 8),
+    ("ellipsoids", 1_000_000, 16_384, 9),
+])
+def test_configs(hp, kind, n, p, seed):
+    pts = synth.cloud(kind, n, p, seed)
+    strategies = (1, 2) if p <= hp.lds_max_p() else (2,)
+    _run_both(hp, pts, p, f"{kind}-{n}-{p}", strategies)
+
+
+def _edge_cases():
+    cases = {}
+    cases["empty"] = (np.zeros((0, 2), np.int32), 7)
+    cases["one-point"] = (np.array([[3, 4]], np.int32), 7)
+    cases["p1"] = (np.ones((10, 2), np.int32), 1)
+    cases["one-column"] = (np.stack([np.full(500, 9), np.arange(1, 501) % 37 + 1], 1).astype(np.int32), 40)
+    cases["one-row"] = (np.stack([np.arange(1, 301), np.full(300, 5)], 1).astype(np.int32), 300)
+    cases["diagonal"] = (np.stack([np.arange(1, 2001), np.arange(1, 2001)], 1).astype(np.int32), 2000)
+    rng = np.random.default_rng(1)
+    xs = rng.choice([1, 1000], size=5000)
+    cases["x-edges"] = (np.stack([xs, rng.integers(1, 1001, 5000)], 1).astype(np.int32), 1000)
+    cases["corners"] = (np.array([[1, 1], [1, 2048], [2048, 1], [2048, 2048]] * 50, np.int32), 2048)
+    cases["duplicates"] = (np.tile(np.array([[17, 3], [17, 3], [2, 9]], np.int32), (1000, 1)), 20)
+    cases["sparse-2p20"] = (rng.integers(1, (1 << 20) + 1, size=(3000, 2)).astype(np.int32), 1 << 20)
+    cases["two-columns"] = (np.array([[5, 1], [5, 9], [6, 4]], np.int32), 9)
+    return cases
+
+
+@pytest.mark.parametrize("name", sorted(_edge_cases()))
+def test_edge_cases(hp, name):
+    pts, p = _edge_cases()[name]
+    strategies = (1, 2) if p <= hp.lds_max_p() else (2,)
+    _run_both(hp, torch.from_numpy(pts), p, name, strategies)
+
+
+def test_unaligned_start(hp):
+    """A points view that starts 8 bytes past a 16-byte boundary."""
+    base = synth.cloud("uniform", 40_001, 777, 11)
+    view_cpu = base[1:]
+    want = _oracle(view_cpu.contiguous().numpy(), 777)
+    dev = base.cuda()[1:]
+    assert dev.data_ptr() % 16 == 8
+    for s in (1, 2):
+        hp.set_strategy(s)
+        _compare(hp.run(dev, 777), want, f"unaligned/strategy{s}")
+    hp.set_strategy(0)
+
+
+def test_out_of_range_reports(hp):
+    pts = synth.cloud("uniform", 10_000, 100, 12)
+    pts[5000] = torch.tensor([101, 3], dtype=torch.int32)
+    pts[17] = torch.tensor([4, 0], dtype=torch.int32)
+    for s in (1, 2):
+        hp.set_strategy(s)
+        got = hp.run(pts.cuda(), 100)
+        assert got["status"] == HP_ERANGE
+    hp.set_strategy(0)
+
+
+def test_launch_shapes(hp):
+    """Every block size / vector depth / grid size gives the same result."""
+    pts = synth.cloud("ellipsoids", 300_000, 2048, 13)
+    want = _oracle(pts.numpy(), 2048)
+    dev = pts.cuda()
+    for strategy in (1, 2):
+        for block in (256, 512, 1024):
+            for vpt in (2, 4, 8):
+                for grid in (1, 7, 300):
+                    hp.tune_set(strategy, block, vpt, grid)
+                    _compare(hp.run(dev, 2048), want, f"shape {strategy}/{block}/{vpt}/{grid}")
+    hp.tune_set(0, 0, 0, 0)
+
+
+def test_repeat_is_stable(hp):
+    """Repeated runs on reused buffers give identical results (the
+    workspace carries nothing over)."""
+    pts = synth.cloud("gaussian", 500_000, 3000, 14).cuda()
+    buf = hp.Buffers.allocate(pts.shape[0], 3000, pts.device)
+    first = None
+    for _ in range(5):
+        hp.hp_run(pts, 3000, buf)
+        got = hp.collect(buf)
+        if first is None:
+            first = got
+        else:
+            for key in ("lo", "hi", "x", "clo", "chi", "hull"):
+                assert np.array_equal(got[key], first[key])
