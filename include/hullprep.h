@@ -78,9 +78,12 @@ extern "C" {
 #define HP_INFO_WORDS  4
 
 /* Reduction strategies for Algorithm 1 (all give identical results). */
-#define HP_STRATEGY_AUTO    0  /* tuned choice per (n, p) regime                */
-#define HP_STRATEGY_LDS     1  /* workgroup-private L in LDS, merged afterwards */
-#define HP_STRATEGY_GLOBAL  2  /* one L in device memory, filtered atomics      */
+#define HP_STRATEGY_AUTO         0  /* tuned choice per (n, p) regime             */
+#define HP_STRATEGY_LDS          1  /* workgroup-private L in LDS, merged into the
+                                       device L with filtered atomics            */
+#define HP_STRATEGY_GLOBAL       2  /* one L in device memory, filtered atomics   */
+#define HP_STRATEGY_LDS_PARTIAL  3  /* workgroup-private L in LDS, written out as
+                                       partial arrays merged by the finish step  */
 
 /* Human-readable name of a status code (static string). */
 const char *hp_status_string(int code);
@@ -96,7 +99,7 @@ int32_t hp_lds_max_p(void);
 
 /* Force a strategy for later calls on this process (HP_STRATEGY_*), e.g. for
  * tests; HP_STRATEGY_AUTO restores the tuned choice.  Also settable with the
- * environment variable HP_FORCE_STRATEGY=lds|global. */
+ * environment variable HP_FORCE_STRATEGY=lds|global|lds_partial. */
 int hp_set_strategy(int strategy);
 
 /* Launch-shape override for later calls in this process (used by the tuner):
@@ -108,6 +111,15 @@ int hp_tune_set(int32_t strategy, int32_t block, int32_t vpt, int32_t grid);
 /* Load a tuning table written by the tuner: one line per regime
  * "log2n log2p strategy block vpt grid"; '#' starts a comment line. */
 int hp_tune_load(const char *path);
+
+/* Measurement hook.  While enabled, every reduce-kernel launch (the
+ * n-proportional step, Algorithm 1) of hp_precondition / hp_run is bracketed
+ * by a pair of HIP events recorded on the launch stream (up to 4096 pairs).
+ * hp_timing_read synchronises those events, returns the number of timed
+ * launches and their total / minimum / maximum duration in milliseconds, and
+ * starts a new tally.  Off by default; enabling allocates the event pool. */
+int hp_timing_enable(int on);
+int hp_timing_read(int32_t *count, double *total_ms, double *min_ms, double *max_ms);
 
 /* ------------------------------------------------------------------------
  * Single cloud

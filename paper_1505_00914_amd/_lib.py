@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_PKG, "libhullprep.so")
 HP_OK, HP_EINVAL, HP_ERANGE, HP_ECAPACITY, HP_EDEVICE, HP_ENOMEM = 0, -1, -2, -3, -4, -5
 HP_P_MAX = 2147483646
 HP_INFO_STATUS, HP_INFO_K, HP_INFO_S, HP_INFO_H, HP_INFO_WORDS = 0, 1, 2, 3, 4
-HP_STRATEGY_AUTO, HP_STRATEGY_LDS, HP_STRATEGY_GLOBAL = 0, 1, 2
+HP_STRATEGY_AUTO, HP_STRATEGY_LDS, HP_STRATEGY_GLOBAL, HP_STRATEGY_LDS_PARTIAL = 0, 1, 2, 3
 
 # every entry point the header declares, with (restype, argtypes)
 _vp = ctypes.c_void_p
@@ -34,6 +34,10 @@ SIGNATURES = {
     "hp_set_strategy": (ctypes.c_int, [ctypes.c_int]),
     "hp_tune_set": (ctypes.c_int, [_i32, _i32, _i32, _i32]),
     "hp_tune_load": (ctypes.c_int, [ctypes.c_char_p]),
+    "hp_timing_enable": (ctypes.c_int, [ctypes.c_int]),
+    "hp_timing_read": (ctypes.c_int, [_i32p, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_double)]),
     "hp_workspace_bytes": (ctypes.c_int, [_i64, _i32, _szp]),
     "hp_precondition": (ctypes.c_int, [_vp, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _i32,
                                        _vp, _vp, _sz, _vp]),

@@ -36,7 +36,7 @@ const DeviceInfo &device_info() {
     D.cus = (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, d) == hipSuccess && v > 0) ? v : 256;
     D.lds_bytes = (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, d) == hipSuccess && v > 0) ? v : 65536;
     D.max_threads_cu = (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxThreadsPerMultiProcessor, d) == hipSuccess && v > 0) ? v : 2048;
-    D.lds_max_p = D.lds_bytes / 8;
+    D.lds_max_p = D.lds_bytes / 8 - 1;  // p pairs plus one flag word
     g_dev[d] = D;
     g_dev_ok[d] = true;
   }
@@ -53,6 +53,7 @@ int forced_strategy() {
     if (e) {
       if (!strcmp(e, "lds")) g_forced = HP_STRATEGY_LDS;
       else if (!strcmp(e, "global")) g_forced = HP_STRATEGY_GLOBAL;
+      else if (!strcmp(e, "lds_partial")) g_forced = HP_STRATEGY_LDS_PARTIAL;
     }
   }
   return g_forced;
@@ -91,7 +92,7 @@ int tuned_strategy(int64_t n, int32_t p) {
   // workgroup sees several points per column
   const DeviceInfo *D = nullptr;
   (void)D;
-  return ((int64_t)n >= 4 * (int64_t)p) ? HP_STRATEGY_LDS : HP_STRATEGY_GLOBAL;
+  return ((int64_t)n >= 4 * (int64_t)p) ? HP_STRATEGY_LDS_PARTIAL : HP_STRATEGY_GLOBAL;
 }
 
 void tune_override(int64_t n, int32_t p, int *block, int *vpt, int *G) {
@@ -132,9 +133,67 @@ int tune_load(const char *path) {
   return HP_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Reduce-kernel timing (events on the launch stream)
+// ---------------------------------------------------------------------------
+constexpr int kTimingSlots = 4096;
+static bool g_timing_on = false;
+static bool g_timing_pool = false;
+static hipEvent_t g_ev0[kTimingSlots], g_ev1[kTimingSlots];
+static int g_timing_used = 0;
+
+bool timing_slot(hipEvent_t *e0, hipEvent_t *e1) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!g_timing_on || g_timing_used >= kTimingSlots) return false;
+  const int slot = g_timing_used++;
+  *e0 = g_ev0[slot];
+  *e1 = g_ev1[slot];
+  return true;
+}
+
+int timing_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (on && !g_timing_pool) {
+    for (int i = 0; i < kTimingSlots; ++i) {
+      if (hipEventCreate(&g_ev0[i]) != hipSuccess || hipEventCreate(&g_ev1[i]) != hipSuccess)
+        return set_error(HP_EDEVICE, "hipEventCreate failed");
+    }
+    g_timing_pool = true;
+  }
+  g_timing_on = on != 0;
+  g_timing_used = 0;
+  return HP_OK;
+}
+
+int timing_read(int32_t *count, double *total, double *mn, double *mx) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  double t = 0, lo = 0, hi = 0;
+  for (int i = 0; i < g_timing_used; ++i) {
+    if (hipEventSynchronize(g_ev1[i]) != hipSuccess) return set_error(HP_EDEVICE, "hipEventSynchronize failed");
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, g_ev0[i], g_ev1[i]) != hipSuccess)
+      return set_error(HP_EDEVICE, "hipEventElapsedTime failed");
+    t += ms;
+    lo = i == 0 ? ms : std::min(lo, (double)ms);
+    hi = i == 0 ? ms : std::max(hi, (double)ms);
+  }
+  if (count) *count = g_timing_used;
+  if (total) *total = t;
+  if (mn) *mn = lo;
+  if (mx) *mx = hi;
+  g_timing_used = 0;
+  return HP_OK;
+}
+
 }  // namespace hp
 
 using namespace hp;
+
+extern "C" int hp_timing_enable(int on) { return timing_enable(on); }
+
+extern "C" int hp_timing_read(int32_t *count, double *total_ms, double *min_ms, double *max_ms) {
+  return timing_read(count, total_ms, min_ms, max_ms);
+}
 
 extern "C" const char *hp_status_string(int code) {
   switch (code) {
@@ -155,7 +214,7 @@ extern "C" int hp_abi_version(void) { return HP_ABI_VERSION; }
 extern "C" int32_t hp_lds_max_p(void) { return (int32_t)device_info().lds_max_p; }
 
 extern "C" int hp_set_strategy(int strategy) {
-  if (strategy != HP_STRATEGY_AUTO && strategy != HP_STRATEGY_LDS && strategy != HP_STRATEGY_GLOBAL)
+  if (strategy < HP_STRATEGY_AUTO || strategy > HP_STRATEGY_LDS_PARTIAL)
     return set_error(HP_EINVAL, "unknown strategy %d", strategy);
   forced_strategy();
   std::lock_guard<std::mutex> lk(g_mu);
@@ -164,7 +223,8 @@ extern "C" int hp_set_strategy(int strategy) {
 }
 
 extern "C" int hp_tune_set(int32_t strategy, int32_t block, int32_t vpt, int32_t grid) {
-  if (strategy < 0 || strategy > 2) return set_error(HP_EINVAL, "unknown strategy %d", strategy);
+  if (strategy < 0 || strategy > HP_STRATEGY_LDS_PARTIAL)
+    return set_error(HP_EINVAL, "unknown strategy %d", strategy);
   const bool ok_shape = (block == 0 && vpt == 0) ||
                         ((block == 256 || block == 512 || block == 1024) && (vpt == 2 || vpt == 4 || vpt == 8));
   if (!ok_shape) return set_error(HP_EINVAL, "unsupported block %d / vpt %d", block, vpt);

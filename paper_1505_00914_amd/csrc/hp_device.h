@@ -15,7 +15,7 @@ namespace hp {
 constexpr int kWave = 64;        // CDNA wavefront width
 constexpr int kSlab = 64;        // columns per slab = one M word = one wave
 constexpr int kTile = 16;        // level-0 hull tile (singleton candidates)
-constexpr int kFanIn = 16;       // children per hull-tree node above a slab
+constexpr int kFanIn = 64;       // children per hull-tree node above a slab
 constexpr int kMaxLevels = 12;   // hull-tree levels (slab level is 1)
 
 // Control words at the head of every workspace.
@@ -37,34 +37,64 @@ struct TreeShape {
   int32_t nodes;                  // total nodes
 };
 
-__device__ __forceinline__ long long cross3(int2 o, int2 a, int2 b) {
-  return ((long long)a.x - o.x) * ((long long)b.y - o.y) -
-         ((long long)a.y - o.y) * ((long long)b.x - o.x);
+// Exact geometry.  SMALL: every coordinate magnitude is below 2^15, so each
+// difference fits in 16 bits, each product of two differences in 30 bits
+// (full-rate 24-bit multiplies) and a cross product in int32.  Otherwise the
+// products are formed in int64.
+template <bool SMALL>
+__device__ __forceinline__ long long mulc(int a, int b) {
+  if (SMALL) return (long long)__mul24(a, b);
+  return (long long)a * (long long)b;
+}
+
+template <bool SMALL>
+__device__ __forceinline__ bool cross_pos(int2 o, int2 a, int2 b) {  // cross(o, a, b) > 0
+  if (SMALL) return __mul24(a.x - o.x, b.y - o.y) > __mul24(a.y - o.y, b.x - o.x);
+  return mulc<false>(a.x - o.x, b.y - o.y) > mulc<false>(a.y - o.y, b.x - o.x);
+}
+
+template <bool SMALL>
+__device__ __forceinline__ bool cross_neg(int2 o, int2 a, int2 b) {  // cross(o, a, b) < 0
+  if (SMALL) return __mul24(a.x - o.x, b.y - o.y) < __mul24(a.y - o.y, b.x - o.x);
+  return mulc<false>(a.x - o.x, b.y - o.y) < mulc<false>(a.y - o.y, b.x - o.x);
+}
+
+// The int64 forms take differences in 64 bits: with coordinates up to
+// 2^31 - 2 (or their negation) a difference needs 32 bits plus sign.
+template <>
+__device__ __forceinline__ bool cross_pos<false>(int2 o, int2 a, int2 b) {
+  return ((long long)a.x - o.x) * ((long long)b.y - o.y) > ((long long)a.y - o.y) * ((long long)b.x - o.x);
+}
+
+template <>
+__device__ __forceinline__ bool cross_neg<false>(int2 o, int2 a, int2 b) {
+  return ((long long)a.x - o.x) * ((long long)b.y - o.y) < ((long long)a.y - o.y) * ((long long)b.x - o.x);
 }
 
 // slope(u1, v) > slope(u2, v) for u1, u2 strictly left of v.
+template <bool SMALL>
 __device__ __forceinline__ bool steeper_left(int2 u1, int2 u2, int2 v) {
-  long long l = ((long long)v.y - u1.y) * ((long long)v.x - u2.x);
-  long long r = ((long long)v.y - u2.y) * ((long long)v.x - u1.x);
-  return l > r;
+  if (SMALL) return __mul24(v.y - u1.y, v.x - u2.x) > __mul24(v.y - u2.y, v.x - u1.x);
+  return ((long long)v.y - u1.y) * ((long long)v.x - u2.x) > ((long long)v.y - u2.y) * ((long long)v.x - u1.x);
 }
 
 // slope(v, w1) < slope(v, w2) for w1, w2 strictly right of v.
+template <bool SMALL>
 __device__ __forceinline__ bool flatter_right(int2 w1, int2 w2, int2 v) {
-  long long l = ((long long)w1.y - v.y) * ((long long)w2.x - v.x);
-  long long r = ((long long)w2.y - v.y) * ((long long)w1.x - v.x);
-  return l < r;
+  if (SMALL) return __mul24(w1.y - v.y, w2.x - v.x) < __mul24(w2.y - v.y, w1.x - v.x);
+  return ((long long)w1.y - v.y) * ((long long)w2.x - v.x) < ((long long)w2.y - v.y) * ((long long)w1.x - v.x);
 }
 
 // Lower convex chain a[0..m) entirely left of v: index of the vertex that
 // maximises slope(a[t], v) (the lower tangent from v).  Along the chain that
 // slope rises while v lies strictly left of the directed edge a[t]->a[t+1]
 // and falls afterwards, so a binary search on that predicate finds it.
+template <bool SMALL>
 __device__ __forceinline__ int tangent_left(const int2 *a, int m, int2 v) {
   int lo = 0, hi = m - 1;
   while (lo < hi) {
     int mid = (lo + hi) >> 1;
-    if (cross3(a[mid], a[mid + 1], v) > 0) lo = mid + 1;
+    if (cross_pos<SMALL>(a[mid], a[mid + 1], v)) lo = mid + 1;
     else hi = mid;
   }
   return lo;
@@ -72,45 +102,15 @@ __device__ __forceinline__ int tangent_left(const int2 *a, int m, int2 v) {
 
 // Lower convex chain b[0..m) entirely right of v: index minimising
 // slope(v, b[t]) (mirror image of tangent_left).
+template <bool SMALL>
 __device__ __forceinline__ int tangent_right(const int2 *b, int m, int2 v) {
   int lo = 0, hi = m - 1;
   while (lo < hi) {
     int mid = (lo + hi) >> 1;
-    if (cross3(v, b[mid], b[mid + 1]) < 0) lo = mid + 1;
+    if (cross_neg<SMALL>(v, b[mid], b[mid + 1])) lo = mid + 1;
     else hi = mid;
   }
   return lo;
-}
-
-// Lower-hull membership of candidate r of child j, given that every child is
-// the lower hull of an x-separated group of points listed left to right.  v
-// is a strict vertex of the lower hull of the union iff the steepest slope
-// into v from any point on its left is smaller than the flattest slope out of
-// v to any point on its right; both extremes are attained on the children's
-// hulls (own neighbours, tangents to the other children).
-__device__ inline bool lower_survives(const int2 *data, const int *cs, const int *cc,
-                                      int nchild, int j, int r) {
-  const int2 v = data[cs[j] + r];
-  bool hasL = false, hasR = false;
-  int2 uL = v, wR = v;
-  if (r > 0) { uL = data[cs[j] + r - 1]; hasL = true; }
-  for (int t = 0; t < j; ++t) {
-    const int m = cc[t];
-    if (m == 0) continue;
-    const int2 *a = data + cs[t];
-    const int2 u = a[tangent_left(a, m, v)];
-    if (!hasL || steeper_left(u, uL, v)) { uL = u; hasL = true; }
-  }
-  if (r + 1 < cc[j]) { wR = data[cs[j] + r + 1]; hasR = true; }
-  for (int t = j + 1; t < nchild; ++t) {
-    const int m = cc[t];
-    if (m == 0) continue;
-    const int2 *b = data + cs[t];
-    const int2 w = b[tangent_right(b, m, v)];
-    if (!hasR || flatter_right(w, wR, v)) { wR = w; hasR = true; }
-  }
-  if (!hasL || !hasR) return true;
-  return cross3(uL, v, wR) > 0;
 }
 
 // Wave-wide exclusive prefix count of `flag` and the wave total.
@@ -120,51 +120,6 @@ __device__ __forceinline__ int wave_rank(bool flag, int *total) {
   const unsigned lane = threadIdx.x & (kWave - 1);
   const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
   return __popcll(m & below);
-}
-
-// Merge `nchild` x-ordered lower hulls into the lower hull of their union,
-// by the whole workgroup.  data/cs/cc describe the children (cs, cc in LDS);
-// survivors are written in order to out[0..), and the count is returned to
-// every thread.  s_tmp: LDS scratch of BLOCK/kWave + 1 ints.
-template <int BLOCK>
-__device__ int merge_lower(const int2 *data, const int *cs, const int *cc, int nchild,
-                           int2 *out, int *s_tmp) {
-  __shared__ int s_pref[kFanIn + 1];
-  const int tid = threadIdx.x;
-  if (tid == 0) {
-    int acc = 0;
-    for (int t = 0; t < nchild; ++t) { s_pref[t] = acc; acc += cc[t]; }
-    s_pref[nchild] = acc;
-  }
-  __syncthreads();
-  const int total = s_pref[nchild];
-  int written = 0;
-  for (int base = 0; base < total; base += BLOCK) {
-    const int q = base + tid;
-    bool keep = false;
-    int2 v = make_int2(0, 0);
-    if (q < total) {
-      int j = 0;
-      while (j + 1 < nchild && s_pref[j + 1] <= q) ++j;
-      const int r = q - s_pref[j];
-      v = data[cs[j] + r];
-      keep = lower_survives(data, cs, cc, nchild, j, r);
-    }
-    int wt;
-    const int wr = wave_rank(keep, &wt);
-    const int w = tid / kWave;
-    if ((tid & (kWave - 1)) == 0) s_tmp[w] = wt;
-    __syncthreads();
-    int off = 0, all = 0;
-    for (int i = 0; i < BLOCK / kWave; ++i) {
-      if (i < w) off += s_tmp[i];
-      all += s_tmp[i];
-    }
-    if (keep) out[written + off + wr] = v;
-    written += all;
-    __syncthreads();
-  }
-  return written;
 }
 
 }  // namespace hp

@@ -41,6 +41,11 @@ int tuned_strategy(int64_t n, int32_t p);
 // arguments unchanged when nothing applies).
 void tune_override(int64_t n, int32_t p, int *block, int *vpt, int *G);
 
+// Reduce-kernel timing hook: when enabled (and not full) hands out the next
+// pair of events, which the launch passes to hipExtLaunchKernelGGL so that
+// they carry the dispatch's own start and end timestamps.
+bool timing_slot(hipEvent_t *e0, hipEvent_t *e1);
+
 // Single-cloud sequence (defined in hp_single.hip).
 int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *hi, uint64_t *mask,
                int32_t *cx, int32_t *clo, int32_t *chi, int32_t chain_cap, int32_t *hx, int32_t *hy,

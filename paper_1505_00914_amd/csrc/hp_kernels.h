@@ -23,23 +23,84 @@ namespace hp {
 // missed one.
 __device__ __forceinline__ void fold_point_lds(int2 *L, int p, int x, int y, bool &bad) {
   const unsigned xi = (unsigned)(x - 1), yi = (unsigned)(y - 1);
-  if (xi < (unsigned)p && yi < (unsigned)p) {
-    const int2 cur = L[xi];
-    if (y < cur.x) atomicMin(&L[xi].x, y);
-    if (y > cur.y) atomicMax(&L[xi].y, y);
-  } else {
-    bad = true;
-  }
+  const bool ok = (xi < (unsigned)p) & (yi < (unsigned)p);
+  bad |= !ok;
+  const unsigned c = ok ? xi : 0u;
+  const int2 cur = L[c];
+  if (ok && y < cur.x) atomicMin(&L[c].x, y);
+  if (ok && y > cur.y) atomicMax(&L[c].y, y);
+}
+
+// A coherent 8-byte read of an (lo, hi) pair that other workgroups update
+// with device-scope atomics (a plain load could keep hitting a stale cache
+// line, which would defeat the filter without breaking correctness).
+__device__ __forceinline__ int2 load_coherent(const int2 *a) {
+  const unsigned long long v = __hip_atomic_load(reinterpret_cast<const unsigned long long *>(a),
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return make_int2((int)(unsigned)(v & 0xffffffffull), (int)(unsigned)(v >> 32));
 }
 
 __device__ __forceinline__ void fold_point_global(int2 *L, int p, int x, int y, bool &bad) {
   const unsigned xi = (unsigned)(x - 1), yi = (unsigned)(y - 1);
-  if (xi < (unsigned)p && yi < (unsigned)p) {
-    const int2 cur = L[xi];
+  const bool ok = (xi < (unsigned)p) & (yi < (unsigned)p);
+  bad |= !ok;
+  if (ok) {
+    const int2 cur = load_coherent(&L[xi]);
     if (y < cur.x) __hip_atomic_fetch_min(&L[xi].x, y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (y > cur.y) __hip_atomic_fetch_max(&L[xi].y, y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  } else {
-    bad = true;
+  }
+}
+
+// Folding 2*VPT points held as VPT int4 vectors is split in two phases so
+// that the stream loop can put its next loads between them: gather reads the
+// current (lo, hi) pair of every point's column, all issued before any is
+// used; apply compares and issues the atomics.  A point that shares a column
+// with an earlier point of the batch may see a value that the earlier point
+// is about to improve, which only costs an extra atomic.
+template <int VPT>
+struct Batch {
+  int y[2 * VPT];
+  unsigned c[2 * VPT];
+  bool ok[2 * VPT];
+  int2 cur[2 * VPT];
+};
+
+template <int VPT, bool LDS>
+__device__ __forceinline__ void gather(const int2 *L, int p, const int4 (&q)[VPT], Batch<VPT> &b,
+                                       bool &bad) {
+#pragma unroll
+  for (int u = 0; u < VPT; ++u) {
+    const int xs[2] = {q[u].x, q[u].z};
+    const int ys[2] = {q[u].y, q[u].w};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int j = 2 * u + h;
+      const unsigned xi = (unsigned)(xs[h] - 1), yi = (unsigned)(ys[h] - 1);
+      b.ok[j] = (xi < (unsigned)p) & (yi < (unsigned)p);
+      bad |= !b.ok[j];
+      b.c[j] = b.ok[j] ? xi : 0u;
+      b.y[j] = ys[h];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 2 * VPT; ++j) b.cur[j] = LDS ? L[b.c[j]] : load_coherent(&L[b.c[j]]);
+}
+
+template <int VPT, bool LDS>
+__device__ __forceinline__ void apply(int2 *L, const Batch<VPT> &b) {
+#pragma unroll
+  for (int j = 0; j < 2 * VPT; ++j) {
+    const unsigned c = b.c[j];
+    const int y = b.y[j];
+    if (LDS) {
+      if (b.ok[j] && y < b.cur[j].x) atomicMin(&L[c].x, y);
+      if (b.ok[j] && y > b.cur[j].y) atomicMax(&L[c].y, y);
+    } else {
+      if (b.ok[j] && y < b.cur[j].x)
+        __hip_atomic_fetch_min(&L[c].x, y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (b.ok[j] && y > b.cur[j].y)
+        __hip_atomic_fetch_max(&L[c].y, y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
   }
 }
 
@@ -66,6 +127,14 @@ struct FinishArgs {
   // control
   int32_t *ctl;
   int32_t *info;
+  const int32_t *wg_err;  // per-workgroup range-error words of the reduce
+  int32_t n_wg_err;
+  // chain: scanned by the last slab (scan_root), then written by it
+  // (chain_inline) or by k_chain; otherwise written by the first hull level
+  int32_t scan_root;
+  int32_t chain_inline;
+  int32_t *cx_out, *clo_out, *chi_out;
+  int32_t chain_cap;
 };
 
 }  // namespace hp

@@ -2,6 +2,8 @@
 #include <climits>
 #include <cstring>
 
+#include <hip/hip_ext.h>
+
 #include "hp_host.h"
 #include "hp_kernels.h"
 
@@ -55,79 +57,131 @@ __device__ __forceinline__ void stream_points(const int32_t *__restrict__ pts, i
   }
   const int4 *v = reinterpret_cast<const int4 *>(pts + 2 * head);
   constexpr int64_t chunk = (int64_t)BLOCK * VPT;
-  for (int64_t t0 = wg * chunk; t0 < nv; t0 += nwg * chunk) {
-    if (t0 + chunk <= nv) {
-      int4 q[VPT];
+  const int64_t step = nwg * chunk;
+  int64_t t0 = wg * chunk;
+  // Full chunks, software-pipelined: the next chunk's loads are issued
+  // (unconditionally, from a valid address) before the current chunk is
+  // folded into L, so VPT 16-byte loads per lane stay in flight.
+  int4 q[VPT];
+  bool have = t0 + chunk <= nv;
+  if (have) {
 #pragma unroll
-      for (int u = 0; u < VPT; ++u) q[u] = v[t0 + u * BLOCK + threadIdx.x];
+    for (int u = 0; u < VPT; ++u) q[u] = v[t0 + u * BLOCK + threadIdx.x];
+  }
+  while (have) {
+    const int64_t t1 = t0 + step;
+    const bool have_next = t1 + chunk <= nv;
+    const int64_t tl = have_next ? t1 : t0;
+    Batch<VPT> b;
+    gather<VPT, LDS>(L, p, q, b, bad);
+    int4 qn[VPT];
 #pragma unroll
-      for (int u = 0; u < VPT; ++u) {
+    for (int u = 0; u < VPT; ++u) qn[u] = v[tl + u * BLOCK + threadIdx.x];
+    apply<VPT, LDS>(L, b);
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) q[u] = qn[u];
+    t0 = t1;
+    have = have_next;
+  }
+  // at most one partial chunk remains for this workgroup
+  if (t0 < nv) {
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+      const int64_t idx = t0 + u * BLOCK + threadIdx.x;
+      if (idx < nv) {
+        const int4 r = v[idx];
         if (LDS) {
-          fold_point_lds(L, p, q[u].x, q[u].y, bad);
-          fold_point_lds(L, p, q[u].z, q[u].w, bad);
+          fold_point_lds(L, p, r.x, r.y, bad);
+          fold_point_lds(L, p, r.z, r.w, bad);
         } else {
-          fold_point_global(L, p, q[u].x, q[u].y, bad);
-          fold_point_global(L, p, q[u].z, q[u].w, bad);
-        }
-      }
-    } else {
-#pragma unroll
-      for (int u = 0; u < VPT; ++u) {
-        const int64_t idx = t0 + u * BLOCK + threadIdx.x;
-        if (idx < nv) {
-          const int4 q = v[idx];
-          if (LDS) {
-            fold_point_lds(L, p, q.x, q.y, bad);
-            fold_point_lds(L, p, q.z, q.w, bad);
-          } else {
-            fold_point_global(L, p, q.x, q.y, bad);
-            fold_point_global(L, p, q.z, q.w, bad);
-          }
+          fold_point_global(L, p, r.x, r.y, bad);
+          fold_point_global(L, p, r.z, r.w, bad);
         }
       }
     }
   }
 }
 
-// Workgroup-private L in LDS; written out as one partial L per workgroup.
-template <int BLOCK, int VPT>
+// Control words the finish step relies on.  When no init kernel runs (the
+// partial-L strategy), workgroup 0 of the reduce kernel clears them: the
+// finish kernel only starts after the reduce kernel has completed.
+struct ResetArgs {
+  int32_t *ctl;
+  int32_t *tree_ctr;
+  int32_t nodes;
+  int32_t *info;
+};
+
+__device__ __forceinline__ void reset_controls(const ResetArgs &R) {
+  if (blockIdx.x != 0 || R.ctl == nullptr) return;
+  for (int j = threadIdx.x; j < kCtlWords; j += blockDim.x) R.ctl[j] = 0;
+  for (int j = threadIdx.x; j < R.nodes; j += blockDim.x) R.tree_ctr[j] = 0;
+  if (threadIdx.x < HP_INFO_WORDS) R.info[threadIdx.x] = 0;
+}
+
+// Workgroup-private L in LDS.  MERGE_ATOMIC: folded into the device L with
+// filtered device-scope atomics (only touched columns that improve on the
+// value read first); otherwise written out as one partial L per workgroup
+// and merged by k_finish.  Every workgroup writes its own range-error word.
+template <int BLOCK, int VPT, bool MERGE_ATOMIC>
 __global__ __launch_bounds__(BLOCK) void k_reduce_lds(const int32_t *__restrict__ pts, int64_t n,
-                                                      int32_t p, int2 *__restrict__ part,
-                                                      int32_t *__restrict__ ctl) {
-  extern __shared__ int2 sL[];
+                                                      int32_t p, int2 *__restrict__ out_L,
+                                                      int32_t *__restrict__ wg_err, ResetArgs R) {
+  extern __shared__ int2 sL[];           // p pairs, then one flag word
+  int &s_bad = reinterpret_cast<int &>(sL[p]);
+  reset_controls(R);
+  if (threadIdx.x == 0) s_bad = 0;
   for (int c = threadIdx.x; c < p; c += BLOCK) sL[c] = make_int2(p + 1, -1);
   __syncthreads();
   bool bad = false;
   stream_points<BLOCK, VPT, true>(pts, n, p, sL, blockIdx.x, gridDim.x, bad);
+  if (bad) s_bad = 1;
   __syncthreads();
-  int2 *out = part + (size_t)blockIdx.x * (size_t)p;
-  for (int c = threadIdx.x; c < p; c += BLOCK) out[c] = sL[c];
-  if (bad) atomicOr(&ctl[kCtlErr], kErrRange);
+  if (MERGE_ATOMIC) {
+    for (int c = threadIdx.x; c < p; c += BLOCK) {
+      const int2 mine = sL[c];
+      if (mine.x > mine.y) continue;  // column untouched by this workgroup
+      const int2 cur = load_coherent(&out_L[c]);
+      if (mine.x < cur.x)
+        __hip_atomic_fetch_min(&out_L[c].x, mine.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (mine.y > cur.y)
+        __hip_atomic_fetch_max(&out_L[c].y, mine.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  } else {
+    int2 *out = out_L + (size_t)blockIdx.x * (size_t)p;
+    for (int c = threadIdx.x; c < p; c += BLOCK) out[c] = sL[c];
+  }
+  if (threadIdx.x == 0) wg_err[blockIdx.x] = s_bad ? kErrRange : 0;
 }
 
 // One L in device memory, updated with filtered device-scope atomics.
 template <int BLOCK, int VPT>
 __global__ __launch_bounds__(BLOCK) void k_reduce_global(const int32_t *__restrict__ pts, int64_t n,
                                                          int32_t p, int2 *L,
-                                                         int32_t *__restrict__ ctl) {
+                                                         int32_t *__restrict__ wg_err, ResetArgs R) {
+  __shared__ int s_bad;
+  reset_controls(R);
+  if (threadIdx.x == 0) s_bad = 0;
+  __syncthreads();
   bool bad = false;
   stream_points<BLOCK, VPT, false>(pts, n, p, L, blockIdx.x, gridDim.x, bad);
-  if (bad) atomicOr(&ctl[kCtlErr], kErrRange);
+  if (bad) s_bad = 1;
+  __syncthreads();
+  if (threadIdx.x == 0) wg_err[blockIdx.x] = s_bad ? kErrRange : 0;
 }
 
 // ---------------------------------------------------------------------------
-// Finish: one workgroup of 256 threads per slab of 64 positions.
+// Finish: one workgroup of 1024 threads per slab of 64 positions.
 // ---------------------------------------------------------------------------
-constexpr int kFinBlock = 256;
-constexpr int kStage = 4096;  // candidates per side staged in LDS for a merge
+constexpr int kFinBlock = 1024;
+constexpr int kFinGroups = kFinBlock / kSlab;  // partial-merge thread groups
 
 struct FinishShared {
-  int2 red[4][kSlab];          // partial-merge scratch
+  int2 red[kFinGroups][kSlab]; // partial-merge scratch
   int2 pt[2][kSlab];           // slab points: side 0 (x, lo), side 1 (x, -hi)
-  int2 lvl0[2][kSlab];         // tile hulls
-  int2 stage[kStage];          // children of a tree node
-  int cs[kFanIn], cc[kFanIn];
-  int l1cs[2][4], l1cc[2][4];
+  int2 stage[2 * kSlab];       // slab hulls per side
+  unsigned char keep8[kFinBlock / kWave];  // slab-hull keep bits, 8 candidates per wave
+  unsigned long long valid;    // valid positions of the slab
   int tmp[kFinBlock / kWave + 1];
   int slab_cnt[2];
   int flag;
@@ -199,77 +253,50 @@ __device__ int assemble_hull(const int2 *low, int nl, const int2 *upn, int nu, i
 
 // Merge the children of tree node (lev, j) for both sides; writes the node's
 // hulls into cand buffer lev&1 (or, for the root, assembles the hull).
-__device__ void tree_merge_node(const FinishArgs &A, FinishShared &S, int lev, int j) {
-  const TreeShape &T = A.tree;
-  const int c0 = j * kFanIn;
-  const int nch = min(kFanIn, T.size[lev - 1] - c0);
-  const int64_t P = A.positions;
-  const bool root = (lev == T.nlev);
-  int nkeep[2];
-  for (int side = 0; side < 2; ++side) {
-    const int2 *src = A.cand + ((size_t)((lev - 1) & 1) * 2 + side) * (size_t)P;
-    int2 *dst = A.cand + ((size_t)(lev & 1) * 2 + side) * (size_t)P;
-    if (threadIdx.x == 0) {
-      int acc = 0;
-      for (int t = 0; t < nch; ++t) {
-        const int child = c0 + t;
-        S.cc[t] = A.ccount[side * T.nodes + T.base[lev - 1] + child];
-        S.cs[t] = acc;
-        acc += S.cc[t];
-      }
-      S.flag = acc;
-    }
-    __syncthreads();
-    const int total = S.flag;
-    const int2 *data;
-    if (total <= kStage) {
-      // stage the children contiguously in LDS
-      for (int t = 0; t < nch; ++t) {
-        const int2 *cp = src + (size_t)(c0 + t) * (size_t)T.span[lev - 1];
-        for (int r = threadIdx.x; r < S.cc[t]; r += kFinBlock) S.stage[S.cs[t] + r] = cp[r];
-      }
-      data = S.stage;
-    } else {
-      // too many to stage: point the children at device memory
-      __syncthreads();
-      if (threadIdx.x == 0)
-        for (int t = 0; t < nch; ++t) S.cs[t] = (int)((size_t)(c0 + t) * (size_t)T.span[lev - 1]);
-      data = src;
-    }
-    __syncthreads();
-    int2 *out = dst + (size_t)j * (size_t)T.span[lev];
-    nkeep[side] = merge_lower<kFinBlock>(data, S.cs, S.cc, nch, out, S.tmp);
-    if (threadIdx.x == 0) A.ccount[side * T.nodes + T.base[lev] + j] = nkeep[side];
-    __syncthreads();
-  }
-  if (root) {
-    __threadfence_block();
-    __syncthreads();
-    const int2 *low = A.cand + ((size_t)(lev & 1) * 2 + 0) * (size_t)P;
-    const int2 *upn = A.cand + ((size_t)(lev & 1) * 2 + 1) * (size_t)P;
-    bool overflow = false;
-    const int h = assemble_hull(low, nkeep[0], upn, nkeep[1], A.hx, A.hy, A.hull_cap, overflow);
-    if (threadIdx.x == 0) {
-      A.info[HP_INFO_H] = overflow ? 0 : h;
-      if (overflow) atomicMin(&A.info[HP_INFO_STATUS], HP_ECAPACITY);
-    }
-  }
-}
-
-__device__ bool last_arrival(int32_t *ctr, int expected, FinishShared &S) {
-  __threadfence();
+// Last-arriver test: the barrier completes every thread's stores, then one
+// acquire-release increment publishes them (and, for the last arriver,
+// makes every earlier arriver's stores visible to the whole workgroup).
+// s_flag is an LDS word.
+__device__ bool last_arrival_flag(int32_t *ctr, int expected, int *s_flag) {
   __syncthreads();
   if (threadIdx.x == 0) {
     const int old = __hip_atomic_fetch_add(ctr, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    S.flag = (old == expected - 1) ? 1 : 0;
+    *s_flag = (old == expected - 1) ? 1 : 0;
   }
   __syncthreads();
-  const bool last = S.flag != 0;
-  if (last) __threadfence();
-  return last;
+  return *s_flag != 0;
 }
 
-template <int FROM_CHAIN>
+__device__ bool last_arrival(int32_t *ctr, int expected, FinishShared &S) {
+  return last_arrival_flag(ctr, expected, &S.flag);
+}
+
+// Chain write of slabs [s0, s1) with the slab offsets already scanned: one
+// wave per slab, ballot rank inside the slab (Lemma 1 order).
+__device__ void write_chain_slab(const int2 *Lm, int32_t p, const int32_t *slab_off, int slab,
+                                 int32_t *cx, int32_t *clo, int32_t *chi, int32_t cap,
+                                 int32_t *info) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t pos = (int64_t)slab * kSlab + lane;
+  int2 L = make_int2(1, 0);
+  const bool inside = pos < p;
+  if (inside) L = Lm[pos];
+  const bool valid = inside && L.x <= L.y;
+  int tot;
+  const int r = wave_rank(valid, &tot);
+  const int off = slab_off[slab] + r;
+  if (valid) {
+    if (off < cap) {
+      cx[off] = (int)pos + 1;
+      clo[off] = L.x;
+      chi[off] = L.y;
+    } else {
+      atomicMin(&info[HP_INFO_STATUS], HP_ECAPACITY);
+    }
+  }
+}
+
+template <int FROM_CHAIN, bool SMALL>
 __global__ __launch_bounds__(kFinBlock) void k_finish(FinishArgs A) {
   __shared__ FinishShared S;
   const int tid = threadIdx.x;
@@ -288,13 +315,18 @@ __global__ __launch_bounds__(kFinBlock) void k_finish(FinishArgs A) {
       const int2 *src = A.part + pos;
       const int G = A.G;
       int g = grp;
-      for (; g + 12 < G; g += 16) {
-        const int2 a = src[(size_t)g * A.p], b = src[(size_t)(g + 4) * A.p];
-        const int2 c = src[(size_t)(g + 8) * A.p], d = src[(size_t)(g + 12) * A.p];
-        mlo = min(mlo, min(min(a.x, b.x), min(c.x, d.x)));
-        mhi = max(mhi, max(max(a.y, b.y), max(c.y, d.y)));
+      // kFinGroups threads per column, 16 independent loads in flight each
+      for (; g + 15 * kFinGroups < G; g += 16 * kFinGroups) {
+        int2 a[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) a[u] = src[(size_t)(g + kFinGroups * u) * A.p];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          mlo = min(mlo, a[u].x);
+          mhi = max(mhi, a[u].y);
+        }
       }
-      for (; g < G; g += 4) {
+      for (; g < G; g += kFinGroups) {
         const int2 a = src[(size_t)g * A.p];
         mlo = min(mlo, a.x);
         mhi = max(mhi, a.y);
@@ -303,7 +335,7 @@ __global__ __launch_bounds__(kFinBlock) void k_finish(FinishArgs A) {
     S.red[grp][lane] = make_int2(mlo, mhi);
     __syncthreads();
     if (grp == 0) {
-      for (int k = 1; k < 4; ++k) {
+      for (int k = 1; k < kFinGroups; ++k) {
         mlo = min(mlo, S.red[k][lane].x);
         mhi = max(mhi, S.red[k][lane].y);
       }
@@ -340,65 +372,83 @@ __global__ __launch_bounds__(kFinBlock) void k_finish(FinishArgs A) {
     if (A.do_hull) {
       S.pt[0][lane] = make_int2(x, lo);
       S.pt[1][lane] = make_int2(x, -hi);
+      if (lane == 0) S.valid = vm;
     }
   }
   __syncthreads();
 
-  // ---- hull level 0 (tiles of 16) and level 1 (the slab), wave 0 -----------
+  // ---- slab hull: every valid point against the 63 others of its slab.
+  // 128 candidates (64 positions x 2 sides), 8 lanes each; lane g of a
+  // candidate's group checks positions g, g+8, ..., g+56, keeping the
+  // steepest slope into v from the left and the flattest slope out of v to
+  // the right; the group combines them and v is kept iff they make a strict
+  // left turn (collinear points dropped, Appendix).  Branch-free selects.
   if (A.do_hull) {
-    if (grp == 0) {
-      const unsigned long long vm = __ballot(valid);
-      const int t0 = lane & ~(kTile - 1);
-      for (int side = 0; side < 2; ++side) {
-        const int2 v = S.pt[side][lane];
-        bool keep = false;
-        if (valid) {
-          bool hasL = false, hasR = false;
-          int2 uL = v, wR = v;
-          for (int jj = t0; jj < lane; ++jj) {
-            if (!((vm >> jj) & 1ull)) continue;
-            const int2 u = S.pt[side][jj];
-            if (!hasL || steeper_left(u, uL, v)) { uL = u; hasL = true; }
-          }
-          for (int jj = lane + 1; jj < t0 + kTile; ++jj) {
-            if (!((vm >> jj) & 1ull)) continue;
-            const int2 w = S.pt[side][jj];
-            if (!hasR || flatter_right(w, wR, v)) { wR = w; hasR = true; }
-          }
-          keep = !hasL || !hasR || cross3(uL, v, wR) > 0;
-        }
-        const unsigned long long km = __ballot(keep);
-        const unsigned tb = (unsigned)((km >> t0) & 0xFFFFull);
-        const int r = __popc(tb & ((1u << (lane - t0)) - 1u));
-        if (keep) S.lvl0[side][t0 + r] = v;
-        if (lane == t0) {
-          S.l1cs[side][lane / kTile] = t0;
-          S.l1cc[side][lane / kTile] = __popc(tb);
-        }
+    {
+      constexpr int kG = kFinBlock / (2 * kSlab);   // lanes per candidate
+      const unsigned long long vm = S.valid;
+      const int cand = tid / kG, g = tid % kG;
+      const int side = cand / kSlab, i = cand % kSlab;
+      const int2 v = S.pt[side][i];
+      int2 uL = v, wR = v;
+      bool hasL = false, hasR = false;
+#pragma unroll
+      for (int k = 0; k < kSlab / kG; ++k) {
+        const int jj = g + k * kG;
+        const int2 u = S.pt[side][jj];
+        const bool ok = ((vm >> jj) & 1ull) != 0;
+        const bool isL = ok & (jj < i), isR = ok & (jj > i);
+        const bool tL = isL & (!hasL | steeper_left<SMALL>(u, uL, v));
+        const bool tR = isR & (!hasR | flatter_right<SMALL>(u, wR, v));
+        uL = tL ? u : uL;
+        hasL |= tL;
+        wR = tR ? u : wR;
+        hasR |= tR;
+      }
+#pragma unroll
+      for (int d = kG / 2; d > 0; d >>= 1) {
+        const int2 ou = make_int2(__shfl_xor(uL.x, d, kWave), __shfl_xor(uL.y, d, kWave));
+        const int2 ow = make_int2(__shfl_xor(wR.x, d, kWave), __shfl_xor(wR.y, d, kWave));
+        const bool ohL = __shfl_xor((int)hasL, d, kWave) != 0;
+        const bool ohR = __shfl_xor((int)hasR, d, kWave) != 0;
+        const bool tL = ohL & (!hasL | steeper_left<SMALL>(ou, uL, v));
+        const bool tR = ohR & (!hasR | flatter_right<SMALL>(ow, wR, v));
+        uL = tL ? ou : uL;
+        hasL |= tL;
+        wR = tR ? ow : wR;
+        hasR |= tR;
+      }
+      const bool keep = ((vm >> i) & 1ull) && (!hasL | !hasR | cross_pos<SMALL>(uL, v, wR));
+      // ballot over the wave: its 8 candidates' keep bits at lanes 0, 8, ...
+      const unsigned long long kb = __ballot(keep && g == 0);
+      if (lane == 0) {
+        unsigned bits = 0;
+#pragma unroll
+        for (int q = 0; q < kWave / kG; ++q) bits |= (unsigned)((kb >> (q * kG)) & 1ull) << q;
+        S.keep8[grp] = (unsigned char)bits;
       }
     }
     __syncthreads();
-    if (grp == 0) {
-      for (int side = 0; side < 2; ++side) {
-        const int T = lane / kTile, r = lane % kTile;
-        bool keep = false;
-        int2 v = make_int2(0, 0);
-        if (r < S.l1cc[side][T]) {
-          v = S.lvl0[side][lane];
-          keep = lower_survives(S.lvl0[side], S.l1cs[side], S.l1cc[side], 4, T, r);
-        }
-        int tot;
-        const int rk = wave_rank(keep, &tot);
-        if (A.tree.nlev == 1) {
-          if (keep) S.stage[side * kSlab + rk] = v;   // single slab: keep in LDS
-        } else {
-          int2 *dst = A.cand + ((size_t)1 * 2 + side) * (size_t)A.positions + (size_t)slab * kSlab;
-          if (keep) dst[rk] = v;
-        }
-        if (lane == 0) {
-          A.ccount[side * A.tree.nodes + slab] = tot;
-          S.slab_cnt[side] = tot;
-        }
+    if (grp < 2) {
+      // wave `side` compacts its side: position lane kept iff bit set
+      const int side = grp;
+      const int bitpos = side * kSlab + lane;   // candidate index
+      constexpr int kG = kFinBlock / (2 * kSlab);
+      constexpr int kPerWave = kWave / kG;      // candidates per wave
+      const bool keep = (S.keep8[bitpos / kPerWave] >> (bitpos % kPerWave)) & 1;
+      int tot;
+      const int rk = wave_rank(keep, &tot);
+      if (keep) S.stage[side * kSlab + rk] = S.pt[side][lane];
+      if (lane == 0) S.slab_cnt[side] = tot;
+    }
+    __syncthreads();
+    if (grp < 2) {
+      const int side = grp;
+      const int tot = S.slab_cnt[side];
+      if (A.tree.nlev > 1) {
+        int2 *dst = A.cand + (size_t)side * (size_t)A.positions + (size_t)slab * kSlab;
+        if (lane < tot) dst[lane] = S.stage[side * kSlab + lane];
+        if (lane == 0) A.ccount[side * A.tree.nodes + slab] = tot;
       }
     }
     __syncthreads();
@@ -413,71 +463,495 @@ __global__ __launch_bounds__(kFinBlock) void k_finish(FinishArgs A) {
     }
   }
 
-  // ---- last slab: scan the slab counts (preconditioner only) ---------------
-  if (!FROM_CHAIN) {
+  // ---- last slab: scan the slab counts (when the chain is not written by
+  // the first hull level) ------------------------------------------------------
+  if (!FROM_CHAIN && A.scan_root) {
     if (last_arrival(&A.ctl[kCtlSlabsDone], gridDim.x, S)) {
       const int nslab = gridDim.x;
-      // slab_off = exclusive scan of slab_k; k and s totals
-      for (int i = tid; i < nslab; i += kFinBlock) A.slab_off[i] = A.slab_k[i];
+      __syncthreads();
+      if (tid == 0) S.flag = 0;
+      // slab_off = exclusive scan of slab_k; k and s totals.  The counts,
+      // the s parts and the error words are all loaded before any is used.
+      int s_part = 0, err = 0;
+      for (int i = tid; i < nslab || i < A.n_wg_err; i += kFinBlock) {
+        const int kk = i < nslab ? A.slab_k[i] : 0;
+        const int ss = i < nslab ? A.slab_s[i] : 0;
+        const int ee = i < A.n_wg_err ? A.wg_err[i] : 0;
+        if (i < nslab) A.slab_off[i] = kk;
+        s_part += ss;
+        err |= ee;
+      }
       __syncthreads();
       const int k = block_exclusive_scan(A.slab_off, nslab, S.tmp, &S.scan_carry);
-      int s_part = 0;
-      for (int i = tid; i < nslab; i += kFinBlock) s_part += A.slab_s[i];
       // block sum of s
       for (int d = kWave / 2; d > 0; d >>= 1) s_part += __shfl_down(s_part, d, kWave);
       __syncthreads();
       if (lane == 0) S.tmp[grp] = s_part;
+      __syncthreads();
+      if (err) atomicOr(&S.flag, err);
       __syncthreads();
       if (tid == 0) {
         int s = 0;
         for (int w = 0; w < kFinBlock / kWave; ++w) s += S.tmp[w];
         A.info[HP_INFO_K] = k;
         A.info[HP_INFO_S] = s;
-        const int err = __hip_atomic_load(&A.ctl[kCtlErr], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (err & kErrRange) atomicMin(&A.info[HP_INFO_STATUS], HP_ERANGE);
+        if (S.flag & kErrRange) atomicMin(&A.info[HP_INFO_STATUS], HP_ERANGE);
+      }
+      if (A.chain_inline) {
+        // every wave writes the chain of up to 4 slabs per round, all loads first
+        constexpr int kW = kFinBlock / kWave;
+        for (int sl0 = grp; sl0 < nslab; sl0 += 4 * kW) {
+          int2 Lv[4];
+          int offv[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int sl = sl0 + u * kW;
+            const int64_t pos = (int64_t)sl * kSlab + lane;
+            Lv[u] = (sl < nslab && pos < A.p) ? A.Lm[pos] : make_int2(1, 0);
+            offv[u] = sl < nslab ? A.slab_off[sl] : 0;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int sl = sl0 + u * kW;
+            const bool valid = sl < nslab && Lv[u].x <= Lv[u].y;
+            int tot;
+            const int r = wave_rank(valid, &tot);
+            const int off = offv[u] + r;
+            if (valid) {
+              if (off < A.chain_cap) {
+                A.cx_out[off] = sl * kSlab + lane + 1;
+                A.clo_out[off] = Lv[u].x;
+                A.chi_out[off] = Lv[u].y;
+              } else {
+                atomicMin(&A.info[HP_INFO_STATUS], HP_ECAPACITY);
+              }
+            }
+          }
+        }
       }
     }
   }
 
-  // ---- hull tree above the slabs: the last child merges its parent ---------
-  if (A.do_hull && A.tree.nlev > 1) {
-    int lev = 1, j = slab;
-    while (lev < A.tree.nlev) {
-      const int parent = j / kFanIn;
-      const int nch = min(kFanIn, A.tree.size[lev] - parent * kFanIn);
-      if (!last_arrival(&A.tree_ctr[A.tree.base[lev + 1] + parent], nch, S)) break;
-      ++lev;
-      j = parent;
-      tree_merge_node(A, S, lev, j);
+}
+
+// ---------------------------------------------------------------------------
+// Hull levels above the slabs.  Level l has one node per kFanIn nodes of
+// level l-1; a node's hull is the lower hull (per side) of its children's
+// hulls.  kSplit workgroups per child test the child's vertices, one
+// wavefront per vertex: lane t finds the tangent point on sibling t (binary
+// search), lane j (the vertex's own child) contributes its neighbours, and a
+// shuffle reduction yields the steepest slope in and the flattest slope out;
+// the vertex survives iff they make a strict left turn.  The survivors of all
+// siblings, in order, are exactly the parent's hull; the last workgroup of
+// the parent to finish writes it (or, at the root, the final vertex list).
+// Hulls of level-l nodes live in buffer (l-1)&1, compacted at the node's
+// first position, lower side then upper side (y negated).
+// ---------------------------------------------------------------------------
+constexpr int kHullBlock = 1024;
+constexpr int kSplit = 4;                       // workgroups per child
+constexpr int kWaves = kHullBlock / kWave;      // candidates per round
+constexpr int kStage = 4096;                    // sibling vertices per side in LDS
+
+// Copy `total` pairs laid out as nseg segments (segment t: cnt[t] pairs at
+// src + seg_pos(t)) into dst[0..total), where cs[t] is the prefix of cnt.
+// Each thread resolves all of its (at most kBatch) elements and issues every
+// load before storing: one memory latency instead of one per element.
+template <int BLOCK, int kBatch, typename SegPos>
+__device__ __forceinline__ void gather_segments(int2 *dst, const int2 *src, const int *cs, int nseg,
+                                                int total, SegPos seg_pos) {
+  for (int base = 0; base < total; base += BLOCK * kBatch) {
+    int2 v[kBatch];
+    int q[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      q[u] = base + u * BLOCK + (int)threadIdx.x;
+      if (q[u] < total) {
+        int lo = 0, hi = nseg - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (cs[mid] <= q[u]) lo = mid;
+          else hi = mid - 1;
+        }
+        v[u] = src[seg_pos(lo) + (size_t)(q[u] - cs[lo])];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u)
+      if (q[u] < total) dst[q[u]] = v[u];
+  }
+}
+
+struct HullArgs {
+  int2 *buf[2];             // [2 sides][positions] each
+  uint8_t *keep;            // [2 * positions] survival flags of the current level
+  int32_t *ccount;          // [2][nodes] hull sizes of nodes
+  TreeShape tree;
+  int32_t positions;
+  int32_t *hx, *hy;
+  int32_t hull_cap;
+  int32_t *info;
+  // chain written by the root compaction (two-level tree, small p)
+  int32_t chain_fused;
+  const int2 *Lm;
+  int32_t p;
+  const int32_t *slab_k, *slab_s;
+  const int32_t *wg_err;
+  int32_t n_wg_err;
+  int32_t *cx, *clo, *chi;
+  int32_t chain_cap;
+};
+
+struct HullShared {
+  int2 stage[2][kStage];
+  uint32_t keepw[kStage / 2];      // keep bytes of 64 slots of 64 positions
+  int cs[2][kFanIn], cc[2][kFanIn];
+  int total[2];
+  int wsum[kWaves];
+  int sum[3];
+  int carry;
+};
+
+// Wave-wide combine of each lane's steepest-left / flattest-right extreme
+// for the wave's candidate v; true iff v is a strict lower-hull vertex.
+template <bool SMALL>
+__device__ __forceinline__ bool wave_extremes_keep(int2 v, int2 uL, bool hasL, int2 wR, bool hasR) {
+#pragma unroll 1
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    const int2 ou = make_int2(__shfl_xor(uL.x, d, kWave), __shfl_xor(uL.y, d, kWave));
+    const int2 ow = make_int2(__shfl_xor(wR.x, d, kWave), __shfl_xor(wR.y, d, kWave));
+    const bool ohL = __shfl_xor((int)hasL, d, kWave) != 0;
+    const bool ohR = __shfl_xor((int)hasR, d, kWave) != 0;
+    if (ohL && (!hasL || steeper_left<SMALL>(ou, uL, v))) { uL = ou; hasL = true; }
+    if (ohR && (!hasR || flatter_right<SMALL>(ow, wR, v))) { wR = ow; hasR = true; }
+  }
+  return !hasL || !hasR || cross_pos<SMALL>(uL, v, wR);
+}
+
+// Sizes and prefixes of the children of `parent` at level lev-1, both sides
+// (waves 0 and 1).
+__device__ __forceinline__ void load_children(const HullArgs &H, HullShared &S, int lev, int sib0,
+                                              int nsib) {
+  const TreeShape &T = H.tree;
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  if (wave < 2) {
+    const int side = wave;
+    const int m = lane < nsib ? H.ccount[side * T.nodes + T.base[lev - 1] + sib0 + lane] : 0;
+    int incl = m;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const int o = __shfl_up(incl, d, kWave);
+      if (lane >= d) incl += o;
+    }
+    if (lane < nsib) { S.cc[side][lane] = m; S.cs[side][lane] = incl - m; }
+    if (lane == kWave - 1) S.total[side] = incl;
+  }
+}
+
+// The whole chain, written by the single root-compaction workgroup when the
+// hull tree has two levels and the slab count is at most kRootChainSlabs:
+// slab offsets by a scan of the slab counts, then one wave per slab writes
+// its valid columns at its offset (Lemma 1 order).  Also writes k, s and the
+// range status.  All loads of a round are issued before any is used.
+constexpr int kRootChainSlabs = kHullBlock / 4;  // p <= 16384
+
+__device__ void root_chain(const HullArgs &H, HullShared &S) {
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  const int nslab = H.tree.size[1];
+  // slab counts (one per thread), s parts and error words
+  const int kk = tid < nslab ? H.slab_k[tid] : 0;
+  int ss = tid < nslab ? H.slab_s[tid] : 0;
+  int err = 0;
+  for (int i = tid; i < H.n_wg_err; i += kHullBlock) err |= H.wg_err[i];
+  // inclusive scan of kk over the first nslab threads (4 waves at most)
+  int incl = kk;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int o = __shfl_up(incl, d, kWave);
+    if (lane >= d) incl += o;
+  }
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    ss += __shfl_xor(ss, d, kWave);
+    err |= __shfl_xor(err, d, kWave);
+  }
+  if (lane == kWave - 1) S.wsum[wave] = incl;
+  if (tid < 3) S.sum[tid] = 0;
+  __syncthreads();
+  if (lane == 0) {
+    atomicAdd(&S.sum[0], ss);
+    if (err) atomicOr(&S.sum[1], err);
+  }
+  int carry = 0;
+  for (int w = 0; w < wave; ++w) carry += S.wsum[w];
+  __syncthreads();
+  // slab offsets into the stage area (reused: stage is not yet in use)
+  int *off = reinterpret_cast<int *>(S.stage[1]);
+  if (tid < nslab) off[tid] = carry + incl - kk;
+  int ktot = 0;
+  for (int w = 0; w < kWaves; ++w) ktot += S.wsum[w];
+  __syncthreads();
+  // one wave per slab; 16 slabs per round
+  for (int sl0 = 0; sl0 < nslab; sl0 += kWaves) {
+    const int sl = sl0 + wave;
+    const int64_t pos = (int64_t)sl * kSlab + lane;
+    const int2 L = (sl < nslab && pos < H.p) ? H.Lm[pos] : make_int2(1, 0);
+    const bool valid = L.x <= L.y;
+    int tot;
+    const int r = wave_rank(valid, &tot);
+    if (valid) {
+      const int o = off[sl] + r;
+      if (o < H.chain_cap) {
+        H.cx[o] = (int)pos + 1;
+        H.clo[o] = L.x;
+        H.chi[o] = L.y;
+      } else {
+        atomicMin(&H.info[HP_INFO_STATUS], HP_ECAPACITY);
+      }
+    }
+  }
+  if (tid == 0) {
+    H.info[HP_INFO_K] = ktot;
+    H.info[HP_INFO_S] = S.sum[0];
+    if (S.sum[1] & kErrRange) atomicMin(&H.info[HP_INFO_STATUS], HP_ERANGE);
+  }
+  __syncthreads();
+}
+
+// Copy the nsib child slots (span positions each, both sides) into LDS as
+// they lie in device memory: all loads first, then the stores.
+__device__ __forceinline__ void stage_whole(HullShared &S, const int2 *in, int64_t P, int sib0,
+                                            int nsib, int span) {
+  constexpr int kPer = 2 * kStage / kHullBlock;
+  int2 v[kPer];
+  const int n = nsib * span;
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int idx = (int)threadIdx.x + u * kHullBlock;
+    const int side = idx / kStage, rem = idx % kStage;
+    if (rem < n && (int64_t)sib0 * span + rem < P) v[u] = in[(size_t)side * P + (size_t)sib0 * span + rem];
+  }
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int idx = (int)threadIdx.x + u * kHullBlock;
+    const int side = idx / kStage, rem = idx % kStage;
+    if (rem < n && (int64_t)sib0 * span + rem < P) S.stage[side][rem] = v[u];
+  }
+}
+
+// Level test: kSplit workgroups per child node of level lev-1 decide, for
+// each of the child's hull vertices, whether it survives among its siblings.
+template <bool SMALL>
+__global__ __launch_bounds__(kHullBlock) void k_hull_test(HullArgs H, int lev) {
+  __shared__ HullShared S;
+  const TreeShape &T = H.tree;
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wave = tid / kWave;
+  const int c = blockIdx.x / kSplit;        // child node at level lev-1
+  const int part = blockIdx.x % kSplit;
+  const int parent = c / kFanIn;
+  const int sib0 = parent * kFanIn;
+  const int nsib = min(kFanIn, T.size[lev - 1] - sib0);
+  const int j = c - sib0;
+  const int64_t P = H.positions;
+  const size_t span_c = (size_t)T.span[lev - 1];
+  const int2 *in = H.buf[(lev - 2) & 1];
+
+  // Siblings' vertices in LDS.  When all of their slots fit (first level:
+  // 64-position children), the slots are copied whole, position-indexed, in
+  // the same round of loads as the counts; otherwise the counts come first
+  // and the vertices are packed, or read in place when even that overflows.
+  const bool whole = (size_t)nsib * span_c <= (size_t)kStage;
+  if (whole) stage_whole(S, in, P, sib0, nsib, (int)span_c);
+  load_children(H, S, lev, sib0, nsib);
+  __syncthreads();
+  bool staged = whole;
+  if (!whole) {
+    staged = S.total[0] <= kStage && S.total[1] <= kStage;
+    if (staged)
+      for (int side = 0; side < 2; ++side)
+        gather_segments<kHullBlock, kStage / kHullBlock>(
+            S.stage[side], in + (size_t)side * P, S.cs[side], nsib, S.total[side],
+            [&](int t) { return (size_t)(sib0 + t) * span_c; });
+    __syncthreads();
+  }
+  auto child_ptr = [&](int side, int t) -> const int2 * {
+    if (whole) return S.stage[side] + (size_t)t * span_c;
+    return staged ? S.stage[side] + S.cs[side][t] : in + (size_t)side * P + (size_t)(sib0 + t) * span_c;
+  };
+
+  // this workgroup's share of the child's vertices: index q runs over the
+  // lower side then the upper side; one wavefront per vertex
+  const int n0 = S.cc[0][j], n1 = S.cc[1][j];
+  const int nq = n0 + n1;
+  uint8_t *keep = H.keep + (size_t)c * span_c * 2;
+  for (int q = part * kWaves + wave; q < nq; q += kSplit * kWaves) {
+    const int side = q < n0 ? 0 : 1;
+    const int r = side ? q - n0 : q;
+    const int *cc = S.cc[side];
+    const int2 *own = child_ptr(side, j);
+    const int2 v = own[r];
+    int2 uL = v, wR = v;
+    bool hasL = false, hasR = false;
+    const int t = lane;
+    if (t == j) {
+      if (r > 0) { uL = own[r - 1]; hasL = true; }
+      if (r + 1 < cc[j]) { wR = own[r + 1]; hasR = true; }
+    } else if (t < nsib && cc[t] > 0) {
+      const int2 *a = child_ptr(side, t);
+      if (t < j) { uL = a[tangent_left<SMALL>(a, cc[t], v)]; hasL = true; }
+      else { wR = a[tangent_right<SMALL>(a, cc[t], v)]; hasR = true; }
+    }
+    const bool k = wave_extremes_keep<SMALL>(v, uL, hasL, wR, hasR);
+    if (lane == 0) keep[q] = k ? 1 : 0;
+  }
+}
+
+// Level compaction: one workgroup per parent concatenates its children's
+// surviving vertices in order (the parent's hull); the root assembles the
+// final vertex list.  Survivors never move to a higher index, so the root
+// compacts in place in LDS.
+template <bool SMALL>
+__global__ __launch_bounds__(kHullBlock) void k_hull_compact(HullArgs H, int lev) {
+  __shared__ HullShared S;
+  const TreeShape &T = H.tree;
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wave = tid / kWave;
+  const int parent = blockIdx.x;
+  const int sib0 = parent * kFanIn;
+  const int nsib = min(kFanIn, T.size[lev - 1] - sib0);
+  const int64_t P = H.positions;
+  const size_t span_c = (size_t)T.span[lev - 1];
+  const size_t span_p = (size_t)T.span[lev];
+  const int2 *in = H.buf[(lev - 2) & 1];
+  int2 *out = H.buf[(lev - 1) & 1];
+  const bool root = lev == T.nlev;
+
+  if (H.chain_fused && lev == 2) root_chain(H, S);
+
+  const bool whole = (size_t)nsib * span_c <= (size_t)kStage && span_c <= 64;
+  if (whole) {
+    // child slots and their keep bytes, one round of loads
+    stage_whole(S, in, P, sib0, nsib, (int)span_c);
+    const uint32_t *kw = reinterpret_cast<const uint32_t *>(H.keep + (size_t)sib0 * span_c * 2);
+    const int64_t first = (int64_t)sib0 * (int64_t)span_c * 2;
+    const int nw = (int)((std::min<int64_t>(first + (int64_t)nsib * span_c * 2, 2 * P) - first + 3) / 4);
+    for (int i = tid; i < nw; i += kHullBlock) S.keepw[i] = kw[i];
+  }
+  load_children(H, S, lev, sib0, nsib);
+  __syncthreads();
+  const bool in_lds = root && (whole || (S.total[0] <= kStage && S.total[1] <= kStage));
+  int nkeep[2];
+  if (whole) {
+    // in-LDS ordered compaction: thread i owns child i/16's positions
+    // 4*(i%16) .. +3 (64-position slots), per side
+    const unsigned char *kb = reinterpret_cast<const unsigned char *>(S.keepw);
+    for (int side = 0; side < 2; ++side) {
+      const int t = tid / 16, r0 = (tid % 16) * 4;
+      int2 vv[4];
+      bool kf[4];
+      int cnt = 0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int r = r0 + u;
+        kf[u] = false;
+        if (t < nsib && r < S.cc[side][t]) {
+          kf[u] = kb[t * span_c * 2 + (side ? S.cc[0][t] : 0) + r] != 0;
+          vv[u] = S.stage[side][t * span_c + r];
+        }
+        cnt += kf[u] ? 1 : 0;
+      }
+      // block exclusive scan of cnt (thread order = (child, position) order)
+      int incl = cnt;
+#pragma unroll
+      for (int d = 1; d < kWave; d <<= 1) {
+        const int o = __shfl_up(incl, d, kWave);
+        if (lane >= d) incl += o;
+      }
+      if (lane == kWave - 1) S.wsum[wave] = incl;
+      __syncthreads();
+      int off = 0, all = 0;
+      for (int w = 0; w < kWaves; ++w) {
+        if (w < wave) off += S.wsum[w];
+        all += S.wsum[w];
+      }
+      off += incl - cnt;
+      __syncthreads();  // every survivor read before any is written back
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (!kf[u]) continue;
+        if (in_lds) S.stage[side][off] = vv[u];
+        else out[(size_t)side * P + (size_t)parent * span_p + off] = vv[u];
+        ++off;
+      }
+      nkeep[side] = all;
+      if (tid == 0) H.ccount[side * T.nodes + T.base[lev] + parent] = all;
+      __syncthreads();
+    }
+  } else {
+  for (int side = 0; side < 2; ++side) {
+    const int total = S.total[side];
+    if (tid == 0) S.carry = 0;
+    __syncthreads();
+    for (int base = 0; base < total; base += kHullBlock) {
+      const int q = base + tid;
+      bool kf = false;
+      int2 v = make_int2(0, 0);
+      if (q < total) {
+        int lo = 0, hi = nsib - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (S.cs[side][mid] <= q) lo = mid;
+          else hi = mid - 1;
+        }
+        const int r = q - S.cs[side][lo];
+        const size_t cpos = (size_t)(sib0 + lo) * span_c;
+        kf = H.keep[cpos * 2 + (side ? S.cc[0][lo] : 0) + r] != 0;
+        v = in[(size_t)side * P + cpos + r];
+      }
+      int wt;
+      const int wr = wave_rank(kf, &wt);
+      if (lane == 0) S.wsum[wave] = wt;
+      __syncthreads();
+      int off = S.carry, all = 0;
+      for (int w = 0; w < kWaves; ++w) {
+        if (w < wave) off += S.wsum[w];
+        all += S.wsum[w];
+      }
+      if (kf) {
+        if (in_lds) S.stage[side][off + wr] = v;
+        else out[(size_t)side * P + (size_t)parent * span_p + off + wr] = v;
+      }
+      __syncthreads();
+      if (tid == 0) S.carry += all;
+      __syncthreads();
+    }
+    nkeep[side] = S.carry;
+    if (tid == 0) H.ccount[side * T.nodes + T.base[lev] + parent] = S.carry;
+    __syncthreads();
+  }
+  }
+  if (root) {
+    bool overflow = false;
+    const int2 *low = in_lds ? S.stage[0] : out;
+    const int2 *upn = in_lds ? S.stage[1] : out + P;
+    const int h = assemble_hull(low, nkeep[0], upn, nkeep[1], H.hx, H.hy, H.hull_cap, overflow);
+    if (tid == 0) {
+      H.info[HP_INFO_H] = overflow ? 0 : h;
+      if (overflow) atomicMin(&H.info[HP_INFO_STATUS], HP_ECAPACITY);
     }
   }
 }
 
-// Chain write: one wave per slab, at the scanned offset (Lemma 1 order).
+// Chain write for large p: one wave per slab, at the scanned offset.
 __global__ __launch_bounds__(256) void k_chain(const int2 *__restrict__ Lm, int32_t p,
                                                const int32_t *__restrict__ slab_off, int32_t nslab,
                                                int32_t *cx, int32_t *clo, int32_t *chi,
                                                int32_t cap, int32_t *info) {
-  const int lane = threadIdx.x & (kWave - 1);
   const int slab = blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
   if (slab >= nslab) return;
-  const int64_t pos = (int64_t)slab * kSlab + lane;
-  int2 L = make_int2(1, 0);
-  const bool inside = pos < p;
-  if (inside) L = Lm[pos];
-  const bool valid = inside && L.x <= L.y;
-  int tot;
-  const int r = wave_rank(valid, &tot);
-  const int off = slab_off[slab] + r;
-  if (valid) {
-    if (off < cap) {
-      cx[off] = (int)pos + 1;
-      clo[off] = L.x;
-      chi[off] = L.y;
-    } else {
-      atomicMin(&info[HP_INFO_STATUS], HP_ECAPACITY);
-    }
-  }
+  write_chain_slab(Lm, p, slab_off, slab, cx, clo, chi, cap, info);
 }
 
 // ---------------------------------------------------------------------------
@@ -504,22 +978,29 @@ static TreeShape make_tree(int64_t positions) {
 }
 
 struct Layout {
-  size_t ctl, tree, slab_k, slab_s, slab_off, Lm, part, cand, ccount, total;
+  size_t ctl, tree, wg_err, slab_k, slab_s, slab_off, Lm, part, cand, keep, ccount, total;
 };
 
 static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Largest reduce grid any strategy or tuned override may use.
+constexpr int kMaxGrid = 4096;
+// Largest p whose chain the scan root writes itself (no k_chain launch).
+constexpr int32_t kChainInline = 32768;
 
 static Layout make_layout(int64_t positions, int32_t p, int64_t part_pairs, const TreeShape &T) {
   Layout Y;
   size_t o = 0;
   Y.ctl = o;      o = align_up(o + sizeof(int32_t) * kCtlWords);
   Y.tree = o;     o = align_up(o + sizeof(int32_t) * (size_t)T.nodes);
+  Y.wg_err = o;   o = align_up(o + sizeof(int32_t) * (size_t)kMaxGrid);
   Y.slab_k = o;   o = align_up(o + sizeof(int32_t) * (size_t)T.size[1]);
   Y.slab_s = o;   o = align_up(o + sizeof(int32_t) * (size_t)T.size[1]);
   Y.slab_off = o; o = align_up(o + sizeof(int32_t) * (size_t)T.size[1]);
   Y.Lm = o;       o = align_up(o + sizeof(int2) * (size_t)(p > 0 ? p : 0));
   Y.part = o;     o = align_up(o + sizeof(int2) * (size_t)part_pairs);
   Y.cand = o;     o = align_up(o + sizeof(int2) * 4 * (size_t)positions);
+  Y.keep = o;     o = align_up(o + 2 * (size_t)positions);
   Y.ccount = o;   o = align_up(o + sizeof(int32_t) * 2 * (size_t)T.nodes);
   Y.total = o;
   return Y;
@@ -532,23 +1013,24 @@ struct Plan1 {
   int block, vpt, G;
 };
 
+static bool is_lds(int s) { return s == HP_STRATEGY_LDS || s == HP_STRATEGY_LDS_PARTIAL; }
+
 static Plan1 choose(int64_t n, int32_t p) {
   const DeviceInfo &D = device_info();
   Plan1 P;
   int s = forced_strategy();
   if (s == HP_STRATEGY_AUTO) s = tuned_strategy(n, p);
-  if (s == HP_STRATEGY_LDS && (int64_t)p > D.lds_max_p) s = HP_STRATEGY_GLOBAL;
+  if (is_lds(s) && (int64_t)p > D.lds_max_p) s = HP_STRATEGY_GLOBAL;
   P.strategy = s;
   P.block = 1024;
   P.vpt = 4;
-  if (s == HP_STRATEGY_LDS) {
-    // enough points per workgroup that the partial L (8p bytes) stays small
-    // next to the points it summarises, but never fewer groups than needed
-    // to keep every CU streaming when n is large
-    const int64_t per_wg_min = 8 * (int64_t)p;
+  if (is_lds(s)) {
+    // one workgroup per CU (or fewer when the cloud is small: every
+    // workgroup should see several points per column, since its private L
+    // costs 8p bytes of LDS initialisation and of merge traffic)
+    const int64_t per_wg_min = 4 * (int64_t)p;
     int64_t G = per_wg_min > 0 ? n / per_wg_min : 1;
-    const int64_t gmax = (int64_t)D.cus * D.lds_groups_per_cu(p);
-    if (G > gmax) G = gmax;
+    if (G > D.cus) G = D.cus;
     if (G < 1) G = 1;
     P.G = (int)G;
   } else {
@@ -560,16 +1042,19 @@ static Plan1 choose(int64_t n, int32_t p) {
     P.G = (int)G;
   }
   tune_override(n, p, &P.block, &P.vpt, &P.G);
-  if (P.strategy == HP_STRATEGY_LDS && P.G > lds_grid_max()) P.G = (int)lds_grid_max();
+  if (is_lds(P.strategy) && P.G > lds_grid_max()) P.G = (int)lds_grid_max();
+  if (P.G > kMaxGrid) P.G = kMaxGrid;
   if (P.G < 1) P.G = 1;
   return P;
 }
 
+// Pairs of the reduce output region: G partial L arrays for the partial
+// variant, otherwise nothing (the device L is the merged-L region).
 static int64_t part_pairs_for(const Plan1 &P, int32_t p) {
-  return P.strategy == HP_STRATEGY_LDS ? (int64_t)P.G * p : (int64_t)p;
+  return P.strategy == HP_STRATEGY_LDS_PARTIAL ? (int64_t)P.G * p : 0;
 }
 
-// Largest grid the LDS strategy may use (also bounds tuned overrides).
+// Largest grid the LDS strategies may use (also bounds tuned overrides).
 static int64_t lds_grid_max() { return (int64_t)device_info().cus * 4; }
 
 static size_t ws_bytes_for(int64_t n, int32_t p) {
@@ -577,35 +1062,53 @@ static size_t ws_bytes_for(int64_t n, int32_t p) {
   // so that a later strategy change still fits the same workspace
   (void)n;
   const TreeShape T = make_tree(p);
-  const int64_t part = (int64_t)p <= device_info().lds_max_p ? lds_grid_max() * p : (int64_t)p;
+  const int64_t part = (int64_t)p <= device_info().lds_max_p ? lds_grid_max() * p : 0;
   return make_layout(p, p, part, T).total;
 }
 
-template <int BLOCK, int VPT>
-static hipError_t launch_reduce(const Plan1 &P, const int32_t *pts, int64_t n, int32_t p, int2 *part,
-                                int32_t *ctl, hipStream_t s) {
-  if (P.strategy == HP_STRATEGY_LDS) {
-    const size_t lds = sizeof(int2) * (size_t)p;
-    static bool attr_set = false;
-    if (!attr_set) {
-      const hipError_t e = hipFuncSetAttribute((const void *)k_reduce_lds<BLOCK, VPT>,
-                                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                                               device_info().lds_bytes);
-      if (e != hipSuccess) return e;
-      attr_set = true;
-    }
-    hipLaunchKernelGGL((k_reduce_lds<BLOCK, VPT>), dim3(P.G), dim3(BLOCK), lds, s, pts, n, p, part, ctl);
-  } else {
-    hipLaunchKernelGGL((k_reduce_global<BLOCK, VPT>), dim3(P.G), dim3(BLOCK), 0, s, pts, n, p, part,
-                       ctl);
-  }
+template <typename K, typename... Args>
+static hipError_t launch(K kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s, hipEvent_t e0,
+                         hipEvent_t e1, Args... args) {
+  if (e0)
+    hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)lds, s, e0, e1, 0, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
   return hipGetLastError();
 }
 
-static hipError_t dispatch_reduce(const Plan1 &P, const int32_t *pts, int64_t n, int32_t p, int2 *part,
-                                  int32_t *ctl, hipStream_t s) {
+template <int BLOCK, int VPT, bool ATOMIC>
+static hipError_t launch_lds(const Plan1 &P, const int32_t *pts, int64_t n, int32_t p, int2 *out,
+                             int32_t *wg_err, ResetArgs R, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    const hipError_t e = hipFuncSetAttribute((const void *)k_reduce_lds<BLOCK, VPT, ATOMIC>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             device_info().lds_bytes);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  return launch(k_reduce_lds<BLOCK, VPT, ATOMIC>, dim3(P.G), dim3(BLOCK), sizeof(int2) * ((size_t)p + 1), s,
+                e0, e1, pts, n, p, out, wg_err, R);
+}
+
+template <int BLOCK, int VPT>
+static hipError_t launch_reduce(const Plan1 &P, const int32_t *pts, int64_t n, int32_t p, int2 *Lm,
+                                int2 *part, int32_t *wg_err, ResetArgs R, hipStream_t s, hipEvent_t e0,
+                                hipEvent_t e1) {
+  if (P.strategy == HP_STRATEGY_LDS)
+    return launch_lds<BLOCK, VPT, true>(P, pts, n, p, Lm, wg_err, R, s, e0, e1);
+  if (P.strategy == HP_STRATEGY_LDS_PARTIAL)
+    return launch_lds<BLOCK, VPT, false>(P, pts, n, p, part, wg_err, R, s, e0, e1);
+  return launch(k_reduce_global<BLOCK, VPT>, dim3(P.G), dim3(BLOCK), 0, s, e0, e1, pts, n, p, Lm,
+                wg_err, R);
+}
+
+static hipError_t dispatch_reduce(const Plan1 &P, const int32_t *pts, int64_t n, int32_t p, int2 *Lm,
+                                  int2 *part, int32_t *wg_err, ResetArgs R, hipStream_t s,
+                                  hipEvent_t e0, hipEvent_t e1) {
 #define HP_CASE(B, V) \
-  if (P.block == B && P.vpt == V) return launch_reduce<B, V>(P, pts, n, p, part, ctl, s);
+  if (P.block == B && P.vpt == V)   \
+    return launch_reduce<B, V>(P, pts, n, p, Lm, part, wg_err, R, s, e0, e1);
   HP_CASE(1024, 4)
   HP_CASE(1024, 2)
   HP_CASE(1024, 8)
@@ -617,6 +1120,32 @@ static hipError_t dispatch_reduce(const Plan1 &P, const int32_t *pts, int64_t n,
   HP_CASE(256, 8)
 #undef HP_CASE
   return hipErrorInvalidValue;
+}
+
+// Hull levels 2..nlev: a test launch and a compaction launch per level (the
+// slab level ran in k_finish).  H must have its chain fields filled.
+static hipError_t launch_hull_levels(const TreeShape &T, int64_t positions, char *w, const Layout &Y,
+                                     HullArgs H, bool small, hipStream_t s) {
+  if (T.nlev < 2) return hipSuccess;
+  H.buf[0] = reinterpret_cast<int2 *>(w + Y.cand);
+  H.buf[1] = H.buf[0] + 2 * (size_t)positions;
+  H.keep = reinterpret_cast<uint8_t *>(w + Y.keep);
+  H.ccount = reinterpret_cast<int32_t *>(w + Y.ccount);
+  H.tree = T;
+  H.positions = (int32_t)positions;
+  for (int lev = 2; lev <= T.nlev; ++lev) {
+    const dim3 gt(T.size[lev - 1] * kSplit), gc(T.size[lev]);
+    if (small) {
+      hipLaunchKernelGGL((k_hull_test<true>), gt, dim3(kHullBlock), 0, s, H, lev);
+      hipLaunchKernelGGL((k_hull_compact<true>), gc, dim3(kHullBlock), 0, s, H, lev);
+    } else {
+      hipLaunchKernelGGL((k_hull_test<false>), gt, dim3(kHullBlock), 0, s, H, lev);
+      hipLaunchKernelGGL((k_hull_compact<false>), gc, dim3(kHullBlock), 0, s, H, lev);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // Enqueue the whole single-cloud sequence.  Shared by hp_precondition,
@@ -633,22 +1162,39 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
   int32_t *ctl = reinterpret_cast<int32_t *>(w + Y.ctl);
   int32_t *tree = reinterpret_cast<int32_t *>(w + Y.tree);
   int2 *part = reinterpret_cast<int2 *>(w + Y.part);
+  int2 *Lm = reinterpret_cast<int2 *>(w + Y.Lm);
+  const bool partial = P.strategy == HP_STRATEGY_LDS_PARTIAL;
+  int32_t *wg_err = reinterpret_cast<int32_t *>(w + Y.wg_err);
 
-  const int ninit = (int)std::min<int64_t>(1024, std::max<int64_t>(1, ((int64_t)std::max<int64_t>(p, T.nodes) + 255) / 256));
-  hipLaunchKernelGGL(k_init, dim3(ninit), dim3(256), 0, s, ctl, tree, T.nodes, info, 0,
-                     P.strategy == HP_STRATEGY_GLOBAL ? part : nullptr, p);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return set_error(HP_EDEVICE, "k_init launch: %s", hipGetErrorString(e));
-  e = dispatch_reduce(P, pts, n, p, part, ctl, s);
+  // The partial strategy writes every merged column itself, so only the
+  // control words need clearing, which reduce workgroup 0 does; the atomic
+  // strategies need the device L at the sentinel first.
+  ResetArgs R;
+  R.ctl = nullptr;
+  R.tree_ctr = tree;
+  R.nodes = T.nodes;
+  R.info = info;
+  hipError_t e;
+  if (partial) {
+    R.ctl = ctl;
+  } else {
+    const int ninit = (int)std::min<int64_t>(1024, std::max<int64_t>(1, ((int64_t)std::max<int64_t>(p, T.nodes) + 255) / 256));
+    hipLaunchKernelGGL(k_init, dim3(ninit), dim3(256), 0, s, ctl, tree, T.nodes, info, 0, Lm, p);
+    e = hipGetLastError();
+    if (e != hipSuccess) return set_error(HP_EDEVICE, "k_init launch: %s", hipGetErrorString(e));
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  timing_slot(&e0, &e1);
+  e = dispatch_reduce(P, pts, n, p, Lm, part, wg_err, R, s, e0, e1);
   if (e != hipSuccess) return set_error(HP_EDEVICE, "reduce launch: %s", hipGetErrorString(e));
 
   FinishArgs A;
   memset(&A, 0, sizeof(A));
-  A.part = part;
-  A.G = P.strategy == HP_STRATEGY_LDS ? P.G : 1;
+  A.part = partial ? part : Lm;
+  A.G = partial ? P.G : 1;
   A.positions = p;
   A.p = p;
-  A.Lm = reinterpret_cast<int2 *>(w + Y.Lm);
+  A.Lm = Lm;
   A.lo = lo;
   A.hi = hi;
   A.mask = mask;
@@ -665,14 +1211,53 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
   A.hull_cap = hull_cap;
   A.ctl = ctl;
   A.info = info;
-  hipLaunchKernelGGL(k_finish<0>, dim3(T.size[1]), dim3(kFinBlock), 0, s, A);
+  A.wg_err = wg_err;
+  A.n_wg_err = P.G;
+  // with a two-level hull tree and few slabs the root compaction writes
+  // the chain; otherwise the last slab scans and writes it
+  const bool fused = do_hull && T.nlev == 2 && T.size[1] <= kRootChainSlabs;
+  A.scan_root = fused ? 0 : 1;
+  A.chain_inline = p <= kChainInline ? 1 : 0;
+  A.cx_out = cx;
+  A.clo_out = clo;
+  A.chi_out = chi;
+  A.chain_cap = chain_cap;
+  // coordinates of L are at most p: below 2^15 the hull runs on 24-bit products
+  const bool small = p < (1 << 15);
+  if (small)
+    hipLaunchKernelGGL((k_finish<0, true>), dim3(T.size[1]), dim3(kFinBlock), 0, s, A);
+  else
+    hipLaunchKernelGGL((k_finish<0, false>), dim3(T.size[1]), dim3(kFinBlock), 0, s, A);
   e = hipGetLastError();
   if (e != hipSuccess) return set_error(HP_EDEVICE, "k_finish launch: %s", hipGetErrorString(e));
-  const int nslab = T.size[1];
-  hipLaunchKernelGGL(k_chain, dim3((nslab + 3) / 4), dim3(256), 0, s, A.Lm, p, A.slab_off, nslab, cx,
-                     clo, chi, chain_cap, info);
-  e = hipGetLastError();
-  if (e != hipSuccess) return set_error(HP_EDEVICE, "k_chain launch: %s", hipGetErrorString(e));
+  if (!fused && !A.chain_inline) {
+    const int nslab = T.size[1];
+    hipLaunchKernelGGL(k_chain, dim3((nslab + 3) / 4), dim3(256), 0, s, Lm, p, A.slab_off, nslab, cx,
+                       clo, chi, chain_cap, info);
+    e = hipGetLastError();
+    if (e != hipSuccess) return set_error(HP_EDEVICE, "k_chain launch: %s", hipGetErrorString(e));
+  }
+  if (do_hull) {
+    HullArgs H;
+    memset(&H, 0, sizeof(H));
+    H.hx = hx;
+    H.hy = hy;
+    H.hull_cap = hull_cap;
+    H.info = info;
+    H.chain_fused = fused ? 1 : 0;
+    H.Lm = Lm;
+    H.p = p;
+    H.slab_k = A.slab_k;
+    H.slab_s = A.slab_s;
+    H.wg_err = wg_err;
+    H.n_wg_err = P.G;
+    H.cx = cx;
+    H.clo = clo;
+    H.chi = chi;
+    H.chain_cap = chain_cap;
+    e = launch_hull_levels(T, p, w, Y, H, small, s);
+    if (e != hipSuccess) return set_error(HP_EDEVICE, "hull level launch: %s", hipGetErrorString(e));
+  }
   return HP_OK;
 }
 
@@ -773,8 +1358,16 @@ extern "C" int hp_hull(const int32_t *cx, const int32_t *clo, const int32_t *chi
   A.hull_cap = hull_cap;
   A.ctl = ctl;
   A.info = info;
-  hipLaunchKernelGGL(k_finish<1>, dim3(T.size[1]), dim3(kFinBlock), 0, s, A);
+  hipLaunchKernelGGL((k_finish<1, false>), dim3(T.size[1]), dim3(kFinBlock), 0, s, A);
   e = hipGetLastError();
   if (e != hipSuccess) return set_error(HP_EDEVICE, "k_finish launch: %s", hipGetErrorString(e));
+  HullArgs H;
+  memset(&H, 0, sizeof(H));
+  H.hx = hx;
+  H.hy = hy;
+  H.hull_cap = hull_cap;
+  H.info = info;
+  e = launch_hull_levels(T, chain_cap, w, Y, H, false, s);
+  if (e != hipSuccess) return set_error(HP_EDEVICE, "hull level launch: %s", hipGetErrorString(e));
   return HP_OK;
 }

@@ -61,6 +61,18 @@ def tune_load(path: str) -> None:
     _lib.call("hp_tune_load", path.encode())
 
 
+def timing_enable(on: bool = True) -> None:
+    _lib.call("hp_timing_enable", 1 if on else 0)
+
+
+def timing_read() -> dict:
+    """Reduce-kernel launches timed since the last read (HIP events)."""
+    c = ctypes.c_int32()
+    t, lo, hi = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _lib.call("hp_timing_read", ctypes.byref(c), ctypes.byref(t), ctypes.byref(lo), ctypes.byref(hi))
+    return {"count": c.value, "total_ms": t.value, "min_ms": lo.value, "max_ms": hi.value}
+
+
 def lds_max_p() -> int:
     return int(_lib.load().hp_lds_max_p())
 
