@@ -12,8 +12,8 @@ Prints ONE JSON line: whole-path Gpoints/s, the reduce kernel's achieved HBM
 bandwidth against the 8 TB/s peak (HIP events around every reduce launch on
 its own stream), the HBM traffic from committed rocprofv3 counters when they
 match the current kernel source, and the CPU oracle timed on a bounded
-sample.  Optional sections: the batched form against the per-cloud launch
-sequence (--batched) and the served form (--serve).
+sample, plus the batched form (4096 ragged clouds) against the per-cloud
+launch sequence, and optionally the served form (--serve).
 """
 from __future__ import annotations
 
@@ -157,6 +157,65 @@ def bench_single(args, torch, hp, synth):
     return out, host, p
 
 
+def bench_batched(args, torch, hp, synth) -> dict:
+    """4096 ragged clouds (n log-uniform in [1e3, 1e6], p log-uniform in
+    [256, 16384], uniform or ellipsoid-surface points) through one plan: the
+    recorded batched launch sequence against the plain per-cloud launch
+    sequence on the same buffers, outputs compared cloud by cloud, and a
+    sample of clouds checked against the oracle."""
+    import numpy as np
+
+    import oracle
+
+    spec = synth.batch_spec(args.batch_clouds, seed=5)
+    pts, offsets, ps = synth.batch(spec, device="cuda:0", ellipsoid_count=4)
+    total = int(offsets[-1])
+    plan = hp.Plan(offsets.numpy(), ps.numpy())
+    buf = plan.allocate("cuda:0")
+    ref = plan.allocate("cuda:0")
+    stream = torch.cuda.current_stream()
+    for _ in range(2):
+        plan.run(pts, buf, stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.batch_steps):
+        plan.run(pts, buf, stream)
+    torch.cuda.synchronize()
+    t_b = (time.perf_counter() - t0) / args.batch_steps
+    plan.run_percloud(pts, ref, stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.percloud_steps):
+        plan.run_percloud(pts, ref, stream)
+    torch.cuda.synchronize()
+    t_p = (time.perf_counter() - t0) / args.percloud_steps
+
+    got, base = plan.collect(buf), plan.collect(ref)
+    same = all(g["status"] == r["status"] == 0 and g["k"] == r["k"] and g["s"] == r["s"]
+               and np.array_equal(g["x"], r["x"]) and np.array_equal(g["clo"], r["clo"])
+               and np.array_equal(g["chi"], r["chi"]) and np.array_equal(g["hull"], r["hull"])
+               for g, r in zip(got, base))
+    rng = np.random.default_rng(0)
+    sample = rng.choice(len(spec), size=min(32, len(spec)), replace=False)
+    host = pts.cpu().numpy()
+    offs = offsets.numpy()
+    ok = 0
+    for b in sample:
+        want = oracle.precondition_and_hull(host[offs[b]:offs[b + 1]], int(ps[b]))
+        g = got[b]
+        ok += int(g["k"] == want["k"] and np.array_equal(g["x"], want["x"])
+                  and np.array_equal(g["clo"], want["clo"]) and np.array_equal(g["chi"], want["chi"])
+                  and np.array_equal(g["hull"], want["hull"]))
+    plan.close()
+    return {"clouds": len(spec), "points": total, "bytes": 8 * total,
+            "ms_per_batch": round(t_b * 1e3, 4), "gpoints_per_s": round(total / t_b / 1e9, 3),
+            "hbm_gbs": round(8 * total / t_b / 1e9, 1),
+            "percloud_ms_per_batch": round(t_p * 1e3, 4),
+            "speedup_vs_percloud": round(t_p / t_b, 2),
+            "identical_to_percloud": bool(same),
+            "oracle_sample_ok": f"{ok}/{len(sample)}"}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -166,7 +225,10 @@ def main(argv=None):
     ap.add_argument("--copies", type=int, default=6)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--batched", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batch-clouds", type=int, default=4096)
+    ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--percloud-steps", type=int, default=2)
     ap.add_argument("--serve", action="store_true")
     ap.add_argument("--strategy", type=int, default=0)
     args = ap.parse_args(argv)
@@ -187,9 +249,8 @@ def main(argv=None):
     if args.strategy:
         hp.set_strategy(args.strategy)
     out, host, p = bench_single(args, torch, hp, synth)
-    if args.batched:
-        from paper_1505_00914_amd import batch_bench
-        out["batched"] = batch_bench.run(torch)
+    if not args.no_batched:
+        out["batched"] = bench_batched(args, torch, hp, synth)
     if args.serve:
         from paper_1505_00914_amd import serve
         out["serving"] = serve.bench(torch)

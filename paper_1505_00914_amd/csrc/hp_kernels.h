@@ -137,4 +137,34 @@ struct FinishArgs {
   int32_t chain_cap;
 };
 
+// Arguments of the hull levels above the slabs for one cloud.
+struct HullArgs {
+  int2 *buf[2];             // [2 sides][positions] each
+  uint8_t *keep;            // [2 * positions] survival flags of the current level
+  int32_t *ccount;          // [2][nodes] hull sizes of nodes
+  TreeShape tree;
+  int32_t positions;
+  int32_t *hx, *hy;
+  int32_t hull_cap;
+  int32_t *info;
+  // chain written by the root compaction (two-level tree, small p)
+  int32_t chain_fused;
+  const int2 *Lm;
+  int32_t p;
+  const int32_t *slab_k, *slab_s;
+  const int32_t *wg_err;
+  int32_t n_wg_err;
+  int32_t *cx, *clo, *chi;
+  int32_t chain_cap;
+};
+
+// One chunk of a batched reduce.
+struct BatchItem {
+  int32_t cloud;
+  int32_t mode;     // 0: whole cloud in LDS, 1: LDS + atomic merge, 2: global atomics
+  int64_t start;    // first point (index into the concatenated points)
+  int64_t count;
+  int64_t pad;
+};
+
 }  // namespace hp

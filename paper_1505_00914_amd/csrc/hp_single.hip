@@ -296,13 +296,14 @@ __device__ void write_chain_slab(const int2 *Lm, int32_t p, const int32_t *slab_
   }
 }
 
+// Per-slab work of the finish step, for slab `slab` of the cloud described
+// by A (the single-cloud kernel passes its block index, the batched kernel
+// the slab of its work item).
 template <int FROM_CHAIN, bool SMALL>
-__global__ __launch_bounds__(kFinBlock) void k_finish(FinishArgs A) {
-  __shared__ FinishShared S;
+__device__ __forceinline__ void finish_body(const FinishArgs &A, FinishShared &S, const int slab) {
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int grp = tid / kWave;
-  const int slab = blockIdx.x;
   const int64_t pos = (int64_t)slab * kSlab + lane;
   const bool inside = pos < A.positions;
 
@@ -466,8 +467,8 @@ __global__ __launch_bounds__(kFinBlock) void k_finish(FinishArgs A) {
   // ---- last slab: scan the slab counts (when the chain is not written by
   // the first hull level) ------------------------------------------------------
   if (!FROM_CHAIN && A.scan_root) {
-    if (last_arrival(&A.ctl[kCtlSlabsDone], gridDim.x, S)) {
-      const int nslab = gridDim.x;
+    if (last_arrival(&A.ctl[kCtlSlabsDone], A.tree.size[1], S)) {
+      const int nslab = A.tree.size[1];
       __syncthreads();
       if (tid == 0) S.flag = 0;
       // slab_off = exclusive scan of slab_k; k and s totals.  The counts,
@@ -534,6 +535,12 @@ __global__ __launch_bounds__(kFinBlock) void k_finish(FinishArgs A) {
 
 }
 
+template <int FROM_CHAIN, bool SMALL>
+__global__ __launch_bounds__(kFinBlock) void k_finish(FinishArgs A) {
+  __shared__ FinishShared S;
+  finish_body<FROM_CHAIN, SMALL>(A, S, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // Hull levels above the slabs.  Level l has one node per kFanIn nodes of
 // level l-1; a node's hull is the lower hull (per side) of its children's
@@ -548,7 +555,6 @@ __global__ __launch_bounds__(kFinBlock) void k_finish(FinishArgs A) {
 // first position, lower side then upper side (y negated).
 // ---------------------------------------------------------------------------
 constexpr int kHullBlock = 1024;
-constexpr int kSplit = 4;                       // workgroups per child
 constexpr int kWaves = kHullBlock / kWave;      // candidates per round
 constexpr int kStage = 4096;                    // sibling vertices per side in LDS
 
@@ -580,26 +586,6 @@ __device__ __forceinline__ void gather_segments(int2 *dst, const int2 *src, cons
       if (q[u] < total) dst[q[u]] = v[u];
   }
 }
-
-struct HullArgs {
-  int2 *buf[2];             // [2 sides][positions] each
-  uint8_t *keep;            // [2 * positions] survival flags of the current level
-  int32_t *ccount;          // [2][nodes] hull sizes of nodes
-  TreeShape tree;
-  int32_t positions;
-  int32_t *hx, *hy;
-  int32_t hull_cap;
-  int32_t *info;
-  // chain written by the root compaction (two-level tree, small p)
-  int32_t chain_fused;
-  const int2 *Lm;
-  int32_t p;
-  const int32_t *slab_k, *slab_s;
-  const int32_t *wg_err;
-  int32_t n_wg_err;
-  int32_t *cx, *clo, *chi;
-  int32_t chain_cap;
-};
 
 struct HullShared {
   int2 stage[2][kStage];
@@ -647,50 +633,55 @@ __device__ __forceinline__ void load_children(const HullArgs &H, HullShared &S, 
   }
 }
 
-// The whole chain, written by the single root-compaction workgroup when the
-// hull tree has two levels and the slab count is at most kRootChainSlabs:
-// slab offsets by a scan of the slab counts, then one wave per slab writes
-// its valid columns at its offset (Lemma 1 order).  Also writes k, s and the
-// range status.  All loads of a round are issued before any is used.
-constexpr int kRootChainSlabs = kHullBlock / 4;  // p <= 16384
+// The whole chain, written by the single root-compaction workgroup (used
+// when the slab count is small enough): slab offsets by a scan of the slab
+// counts (kept in LDS), then one wave per slab writes its valid columns at
+// its offset (Lemma 1 order).  Also writes k, s and the range status.
+constexpr int kRootChainSlabs = 2 * kStage;  // offsets fit in the stage area
 
 __device__ void root_chain(const HullArgs &H, HullShared &S) {
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const int nslab = H.tree.size[1];
-  // slab counts (one per thread), s parts and error words
-  const int kk = tid < nslab ? H.slab_k[tid] : 0;
-  int ss = tid < nslab ? H.slab_s[tid] : 0;
-  int err = 0;
+  int *off = reinterpret_cast<int *>(&S.stage[0][0]);
+  if (tid < 3) S.sum[tid] = 0;
+  if (tid == 0) S.carry = 0;
+  __syncthreads();
+  int ss = 0, err = 0;
   for (int i = tid; i < H.n_wg_err; i += kHullBlock) err |= H.wg_err[i];
-  // inclusive scan of kk over the first nslab threads (4 waves at most)
-  int incl = kk;
+  for (int base = 0; base < nslab; base += kHullBlock) {
+    const int i = base + tid;
+    const int kk = i < nslab ? H.slab_k[i] : 0;
+    ss += i < nslab ? H.slab_s[i] : 0;
+    int incl = kk;
 #pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const int o = __shfl_up(incl, d, kWave);
-    if (lane >= d) incl += o;
+    for (int d = 1; d < kWave; d <<= 1) {
+      const int o = __shfl_up(incl, d, kWave);
+      if (lane >= d) incl += o;
+    }
+    if (lane == kWave - 1) S.wsum[wave] = incl;
+    __syncthreads();
+    int before = S.carry, all = 0;
+    for (int w = 0; w < kWaves; ++w) {
+      if (w < wave) before += S.wsum[w];
+      all += S.wsum[w];
+    }
+    if (i < nslab) off[i] = before + incl - kk;
+    __syncthreads();
+    if (tid == 0) S.carry += all;
+    __syncthreads();
   }
 #pragma unroll
   for (int d = kWave / 2; d > 0; d >>= 1) {
     ss += __shfl_xor(ss, d, kWave);
     err |= __shfl_xor(err, d, kWave);
   }
-  if (lane == kWave - 1) S.wsum[wave] = incl;
-  if (tid < 3) S.sum[tid] = 0;
-  __syncthreads();
   if (lane == 0) {
     atomicAdd(&S.sum[0], ss);
     if (err) atomicOr(&S.sum[1], err);
   }
-  int carry = 0;
-  for (int w = 0; w < wave; ++w) carry += S.wsum[w];
   __syncthreads();
-  // slab offsets into the stage area (reused: stage is not yet in use)
-  int *off = reinterpret_cast<int *>(S.stage[1]);
-  if (tid < nslab) off[tid] = carry + incl - kk;
-  int ktot = 0;
-  for (int w = 0; w < kWaves; ++w) ktot += S.wsum[w];
-  __syncthreads();
-  // one wave per slab; 16 slabs per round
+  const int ktot = S.carry;
+  // one wave per slab, kWaves slabs per round
   for (int sl0 = 0; sl0 < nslab; sl0 += kWaves) {
     const int sl = sl0 + wave;
     const int64_t pos = (int64_t)sl * kSlab + lane;
@@ -741,14 +732,14 @@ __device__ __forceinline__ void stage_whole(HullShared &S, const int2 *in, int64
 // Level test: kSplit workgroups per child node of level lev-1 decide, for
 // each of the child's hull vertices, whether it survives among its siblings.
 template <bool SMALL>
-__global__ __launch_bounds__(kHullBlock) void k_hull_test(HullArgs H, int lev) {
-  __shared__ HullShared S;
+__device__ __forceinline__ void hull_test_body(const HullArgs &H, HullShared &S, const int lev,
+                                               const int item) {
   const TreeShape &T = H.tree;
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wave = tid / kWave;
-  const int c = blockIdx.x / kSplit;        // child node at level lev-1
-  const int part = blockIdx.x % kSplit;
+  const int c = item / kSplit;              // child node at level lev-1
+  const int part = item % kSplit;
   const int parent = c / kFanIn;
   const int sib0 = parent * kFanIn;
   const int nsib = min(kFanIn, T.size[lev - 1] - sib0);
@@ -812,13 +803,18 @@ __global__ __launch_bounds__(kHullBlock) void k_hull_test(HullArgs H, int lev) {
 // final vertex list.  Survivors never move to a higher index, so the root
 // compacts in place in LDS.
 template <bool SMALL>
-__global__ __launch_bounds__(kHullBlock) void k_hull_compact(HullArgs H, int lev) {
+__global__ __launch_bounds__(kHullBlock) void k_hull_test(HullArgs H, int lev) {
   __shared__ HullShared S;
+  hull_test_body<SMALL>(H, S, lev, blockIdx.x);
+}
+
+template <bool SMALL>
+__device__ __forceinline__ void hull_compact_body(const HullArgs &H, HullShared &S, const int lev,
+                                                  const int parent) {
   const TreeShape &T = H.tree;
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wave = tid / kWave;
-  const int parent = blockIdx.x;
   const int sib0 = parent * kFanIn;
   const int nsib = min(kFanIn, T.size[lev - 1] - sib0);
   const int64_t P = H.positions;
@@ -828,7 +824,7 @@ __global__ __launch_bounds__(kHullBlock) void k_hull_compact(HullArgs H, int lev
   int2 *out = H.buf[(lev - 1) & 1];
   const bool root = lev == T.nlev;
 
-  if (H.chain_fused && lev == 2) root_chain(H, S);
+  if (H.chain_fused && root) root_chain(H, S);
 
   const bool whole = (size_t)nsib * span_c <= (size_t)kStage && span_c <= 64;
   if (whole) {
@@ -944,6 +940,12 @@ __global__ __launch_bounds__(kHullBlock) void k_hull_compact(HullArgs H, int lev
   }
 }
 
+template <bool SMALL>
+__global__ __launch_bounds__(kHullBlock) void k_hull_compact(HullArgs H, int lev) {
+  __shared__ HullShared S;
+  hull_compact_body<SMALL>(H, S, lev, blockIdx.x);
+}
+
 // Chain write for large p: one wave per slab, at the scanned offset.
 __global__ __launch_bounds__(256) void k_chain(const int2 *__restrict__ Lm, int32_t p,
                                                const int32_t *__restrict__ slab_off, int32_t nslab,
@@ -952,6 +954,260 @@ __global__ __launch_bounds__(256) void k_chain(const int2 *__restrict__ Lm, int3
   const int slab = blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
   if (slab >= nslab) return;
   write_chain_slab(Lm, p, slab_off, slab, cx, clo, chi, cap, info);
+}
+
+// ---------------------------------------------------------------------------
+// Batched form.  Every cloud has its own FinishArgs / HullArgs (device
+// arrays written by the plan); work tables map each workgroup to a
+// (cloud, local index) pair, so one launch per step covers all clouds.
+// ---------------------------------------------------------------------------
+
+// Zero each cloud's info and control words; set the L of clouds that are
+// reduced with atomics to the sentinel; reset the reduce work counter.
+__global__ __launch_bounds__(256) void k_b_fill(const FinishArgs *fa, const uint8_t *needs_fill,
+                                                int32_t *counter) {
+  const int b = blockIdx.x;
+  const FinishArgs &A = fa[b];
+  if (b == 0 && threadIdx.x == 0) *counter = 0;
+  if (threadIdx.x < HP_INFO_WORDS) A.info[threadIdx.x] = 0;
+  for (int j = threadIdx.x; j < kCtlWords; j += 256) A.ctl[j] = 0;
+  if (needs_fill[b])
+    for (int c = threadIdx.x; c < A.p; c += 256) A.Lm[c] = make_int2(A.p + 1, -1);
+}
+
+// Persistent reduce: workgroups take chunks from a shared counter until the
+// list is exhausted (every wave leaves the loop once the counter passes the
+// end).  Modes: 0 = the chunk is the whole cloud, LDS L stored as is;
+// 1 = LDS L merged into the cloud's L by filtered atomics; 2 = filtered
+// atomics straight into the cloud's L (sparse clouds).
+template <int BLOCK, int VPT>
+__global__ __launch_bounds__(BLOCK) void k_b_reduce(const int32_t *__restrict__ pts,
+                                                    const BatchItem *__restrict__ items,
+                                                    int32_t nitems, int32_t *counter,
+                                                    const FinishArgs *fa) {
+  extern __shared__ int2 sL[];
+  __shared__ int s_item, s_bad;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      s_item = atomicAdd(counter, 1);
+      s_bad = 0;
+    }
+    __syncthreads();
+    const int it = s_item;
+    if (it >= nitems) break;
+    const BatchItem I = items[it];
+    const FinishArgs &A = fa[I.cloud];
+    const int p = A.p;
+    int2 *L = A.Lm;
+    const int32_t *src = pts + 2 * I.start;
+    bool bad = false;
+    if (I.mode == 2) {
+      stream_points<BLOCK, VPT, false>(src, I.count, p, L, 0, 1, bad);
+    } else {
+      for (int c = threadIdx.x; c < p; c += BLOCK) sL[c] = make_int2(p + 1, -1);
+      __syncthreads();
+      stream_points<BLOCK, VPT, true>(src, I.count, p, sL, 0, 1, bad);
+      __syncthreads();
+      if (I.mode == 0) {
+        for (int c = threadIdx.x; c < p; c += BLOCK) L[c] = sL[c];
+      } else {
+        for (int c = threadIdx.x; c < p; c += BLOCK) {
+          const int2 mine = sL[c];
+          if (mine.x > mine.y) continue;
+          const int2 cur = load_coherent(&L[c]);
+          if (mine.x < cur.x)
+            __hip_atomic_fetch_min(&L[c].x, mine.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (mine.y > cur.y)
+            __hip_atomic_fetch_max(&L[c].y, mine.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+    }
+    if (bad) s_bad = 1;
+    __syncthreads();
+    if (threadIdx.x == 0 && s_bad) atomicMin(&A.info[HP_INFO_STATUS], HP_ERANGE);
+  }
+}
+
+template <bool SMALL>
+__global__ __launch_bounds__(kFinBlock) void k_b_finish(const int2 *__restrict__ work, const FinishArgs *fa) {
+  __shared__ FinishShared S;
+  const int2 w = work[blockIdx.x];
+  finish_body<0, SMALL>(fa[w.x], S, w.y);
+}
+
+template <bool SMALL>
+__global__ __launch_bounds__(kHullBlock) void k_b_hull_test(const int2 *__restrict__ work,
+                                                            const HullArgs *ha, int lev) {
+  __shared__ HullShared S;
+  const int2 w = work[blockIdx.x];
+  hull_test_body<SMALL>(ha[w.x], S, lev, w.y);
+}
+
+template <bool SMALL>
+__global__ __launch_bounds__(kHullBlock) void k_b_hull_compact(const int2 *__restrict__ work,
+                                                               const HullArgs *ha, int lev) {
+  __shared__ HullShared S;
+  const int2 w = work[blockIdx.x];
+  hull_compact_body<SMALL>(ha[w.x], S, lev, w.y);
+}
+
+// ---------------------------------------------------------------------------
+// Batched finish, shaped for throughput across many clouds: every lane runs
+// the monotone chain (Andrew) over its own x-sorted input, so each step does
+// O(points) work with no cross-lane traffic.
+//   k_b_slabs      per 64-column slab and side: the slab's hull, its M word,
+//                  its counts (a lane per slab-side, 64 slabs per workgroup)
+//   k_b_nodes      per tree node and side: the chain over its children's
+//                  hulls in order (a lane per node-side), for each level
+//   k_b_root       per cloud: slab offsets (scan), k, s, the final vertex
+//                  list from the root's two sides
+//   k_b_chain      per slab: the chain at the scanned offset (Lemma 1 order)
+// ---------------------------------------------------------------------------
+constexpr int kTileSlabs = 64;                   // slabs per k_b_slabs workgroup
+constexpr int kTileCols = kTileSlabs * kSlab;    // 4096 columns
+
+// Andrew's lower chain over get(0..m), pushed into out[] (which serves as the
+// stack); pops while the last two and the new point fail a strict left turn.
+template <bool SMALL, typename Get>
+__device__ __forceinline__ int mono_chain(Get get, int m, int2 *out) {
+  int top = 0;
+  int2 a = make_int2(0, 0), b = make_int2(0, 0);
+  for (int i = 0; i < m; ++i) {
+    const int2 v = get(i);
+    while (top >= 2 && !cross_pos<SMALL>(a, b, v)) {
+      --top;
+      b = a;
+      if (top >= 2) a = out[top - 2];
+    }
+    out[top] = v;
+    ++top;
+    a = b;
+    b = v;
+  }
+  return top;
+}
+
+template <bool SMALL>
+__global__ __launch_bounds__(2 * kTileSlabs) void k_b_slabs(const int2 *__restrict__ work,
+                                                             const FinishArgs *fa) {
+  __shared__ int2 sL[kTileCols];
+  const int2 w = work[blockIdx.x];
+  const FinishArgs &A = fa[w.x];
+  const int p = A.p;
+  const int64_t c0 = (int64_t)w.y * kTileCols;
+  const int ncol = (int)min<int64_t>(kTileCols, p - c0);
+  for (int i = threadIdx.x; i < kTileCols; i += 2 * kTileSlabs)
+    sL[i] = i < ncol ? A.Lm[c0 + i] : make_int2(1, 0);
+  __syncthreads();
+  const int nslab_tile = (ncol + kSlab - 1) / kSlab;
+  // M words and slab counts: each wave ballots its slabs
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  for (int sl = wave; sl < nslab_tile; sl += (2 * kTileSlabs) / kWave) {
+    const int2 L = sL[sl * kSlab + lane];
+    const bool valid = L.x <= L.y;
+    const unsigned long long vm = __ballot(valid);
+    const unsigned long long sm = __ballot(valid && L.x < L.y);
+    if (lane == 0) {
+      const int gs = w.y * kTileSlabs + sl;
+      if (A.mask) A.mask[gs] = vm;
+      A.slab_k[gs] = __popcll(vm);
+      A.slab_s[gs] = __popcll(vm) + __popcll(sm);
+    }
+  }
+  // one lane per (slab, side)
+  const int sl = threadIdx.x >> 1, side = threadIdx.x & 1;
+  if (sl < nslab_tile) {
+    const int gs = w.y * kTileSlabs + sl;
+    const int base = sl * kSlab;
+    int2 *out = A.cand + (size_t)side * (size_t)p + (size_t)gs * kSlab;
+    // valid columns of the slab in order, as (x, lo) or (x, -hi)
+    unsigned long long vm = 0;
+    for (int i = 0; i < kSlab; ++i) vm |= (unsigned long long)(sL[base + i].x <= sL[base + i].y) << i;
+    const int m = __popcll(vm);
+    unsigned long long it = vm;
+    auto get = [&](int) -> int2 {
+      const int i = __ffsll((long long)it) - 1;
+      it &= it - 1;
+      const int2 L = sL[base + i];
+      return make_int2((int)(c0 + base + i + 1), side ? -L.y : L.x);
+    };
+    const int cnt = mono_chain<SMALL>(get, m, out);
+    A.ccount[side * A.tree.nodes + gs] = cnt;
+  }
+}
+
+// One lane per (node at level lev, side): the chain over the children's
+// hulls (level lev-1, buffer (lev-2)&1) into the node's slot of buffer
+// (lev-1)&1.
+template <bool SMALL>
+__global__ __launch_bounds__(64) void k_b_nodes(const int4 *__restrict__ work, int nwork,
+                                                const HullArgs *ha, int lev) {
+  const int t = blockIdx.x * 64 + threadIdx.x;
+  if (t >= nwork) return;
+  const int4 w = work[t];                 // (cloud, node, side, -)
+  const HullArgs &H = ha[w.x];
+  const TreeShape &T = H.tree;
+  const int node = w.y, side = w.z;
+  const int64_t P = H.positions;
+  const int2 *in = H.buf[(lev - 2) & 1] + (size_t)side * P;
+  int2 *out = H.buf[(lev - 1) & 1] + (size_t)side * P + (size_t)node * T.span[lev];
+  const int c0 = node * kFanIn, nc = min(kFanIn, T.size[lev - 1] - c0);
+  const int32_t *cnt = H.ccount + side * T.nodes + T.base[lev - 1];
+  int child = 0, r = 0, m = 0;
+  for (int c = 0; c < nc; ++c) m += cnt[c0 + c];
+  auto get = [&](int) -> int2 {
+    while (r >= cnt[c0 + child]) { ++child; r = 0; }
+    return in[(size_t)(c0 + child) * T.span[lev - 1] + r++];
+  };
+  const int k = mono_chain<SMALL>(get, m, out);
+  H.ccount[side * T.nodes + T.base[lev] + node] = k;
+}
+
+// Per cloud (one wave): slab offsets and totals, then the final hull from
+// the root's two sides (lower left to right, then upper back).
+__global__ __launch_bounds__(64) void k_b_root(const FinishArgs *fa, const HullArgs *ha) {
+  const FinishArgs &A = fa[blockIdx.x];
+  const HullArgs &H = ha[blockIdx.x];
+  const TreeShape &T = A.tree;
+  const int lane = threadIdx.x;
+  const int nslab = T.size[1];
+  int carry = 0, stot = 0;
+  for (int base = 0; base < nslab; base += kWave) {
+    const int i = base + lane;
+    const int kk = i < nslab ? A.slab_k[i] : 0;
+    stot += i < nslab ? A.slab_s[i] : 0;
+    int incl = kk;
+    for (int d = 1; d < kWave; d <<= 1) {
+      const int o = __shfl_up(incl, d, kWave);
+      if (lane >= d) incl += o;
+    }
+    if (i < nslab) A.slab_off[i] = carry + incl - kk;
+    carry += __shfl(incl, kWave - 1, kWave);
+  }
+  for (int d = kWave / 2; d > 0; d >>= 1) stot += __shfl_xor(stot, d, kWave);
+  const int64_t P = H.positions;
+  const int2 *root = H.buf[(T.nlev - 1) & 1];
+  const int nl = H.ccount[0 * T.nodes + T.base[T.nlev]];
+  const int nu = H.ccount[1 * T.nodes + T.base[T.nlev]];
+  bool overflow = false;
+  const int h = assemble_hull(root, nl, root + P, nu, H.hx, H.hy, H.hull_cap, overflow);
+  if (lane == 0) {
+    A.info[HP_INFO_K] = carry;
+    A.info[HP_INFO_S] = stot;
+    A.info[HP_INFO_H] = overflow ? 0 : h;
+    if (overflow) atomicMin(&A.info[HP_INFO_STATUS], HP_ECAPACITY);
+  }
+}
+
+// Per slab (one wave): its valid columns at the scanned offset.
+__global__ __launch_bounds__(256) void k_b_chain(const int2 *__restrict__ work, int nwork,
+                                                 const FinishArgs *fa) {
+  const int t = blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
+  if (t >= nwork) return;
+  const int2 w = work[t];
+  const FinishArgs &A = fa[w.x];
+  write_chain_slab(A.Lm, A.p, A.slab_off, w.y, A.cx_out, A.clo_out, A.chi_out, A.chain_cap, A.info);
 }
 
 // ---------------------------------------------------------------------------
@@ -987,6 +1243,8 @@ static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 constexpr int kMaxGrid = 4096;
 // Largest p whose chain the scan root writes itself (no k_chain launch).
 constexpr int32_t kChainInline = 32768;
+// Single cloud: largest slab count whose chain the root compaction writes.
+constexpr int32_t kSingleRootChainSlabs = 256;
 
 static Layout make_layout(int64_t positions, int32_t p, int64_t part_pairs, const TreeShape &T) {
   Layout Y;
@@ -1215,7 +1473,7 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
   A.n_wg_err = P.G;
   // with a two-level hull tree and few slabs the root compaction writes
   // the chain; otherwise the last slab scans and writes it
-  const bool fused = do_hull && T.nlev == 2 && T.size[1] <= kRootChainSlabs;
+  const bool fused = do_hull && T.nlev == 2 && T.size[1] <= kSingleRootChainSlabs;
   A.scan_root = fused ? 0 : 1;
   A.chain_inline = p <= kChainInline ? 1 : 0;
   A.cx_out = cx;
@@ -1259,6 +1517,78 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
     if (e != hipSuccess) return set_error(HP_EDEVICE, "hull level launch: %s", hipGetErrorString(e));
   }
   return HP_OK;
+}
+
+void tree_shape(int64_t positions, TreeShape *out) { *out = make_tree(positions); }
+
+hipError_t launch_b_fill(int B, const FinishArgs *fa, const uint8_t *needs_fill, int32_t *counter,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_b_fill, dim3(B), dim3(256), 0, s, fa, needs_fill, counter);
+  return hipGetLastError();
+}
+
+hipError_t prepare_b_reduce() {
+  return hipFuncSetAttribute((const void *)k_b_reduce<1024, 4>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             device_info().lds_bytes - 64);
+}
+
+hipError_t launch_b_reduce(int grid, size_t lds_bytes, const int32_t *pts, const BatchItem *items,
+                           int32_t nitems, int32_t *counter, const FinishArgs *fa, hipStream_t s) {
+  hipLaunchKernelGGL((k_b_reduce<1024, 4>), dim3(grid), dim3(1024), lds_bytes, s, pts, items, nitems,
+                     counter, fa);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_finish(bool small, int nwork, const int2 *work, const FinishArgs *fa, hipStream_t s) {
+  if (nwork <= 0) return hipSuccess;
+  if (small) hipLaunchKernelGGL((k_b_finish<true>), dim3(nwork), dim3(kFinBlock), 0, s, work, fa);
+  else hipLaunchKernelGGL((k_b_finish<false>), dim3(nwork), dim3(kFinBlock), 0, s, work, fa);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_hull(bool small, int lev, int ntest, const int2 *test, int ncompact,
+                         const int2 *compact, const HullArgs *ha, hipStream_t s) {
+  if (ntest > 0) {
+    if (small) hipLaunchKernelGGL((k_b_hull_test<true>), dim3(ntest), dim3(kHullBlock), 0, s, test, ha, lev);
+    else hipLaunchKernelGGL((k_b_hull_test<false>), dim3(ntest), dim3(kHullBlock), 0, s, test, ha, lev);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (ncompact > 0) {
+    if (small)
+      hipLaunchKernelGGL((k_b_hull_compact<true>), dim3(ncompact), dim3(kHullBlock), 0, s, compact, ha, lev);
+    else
+      hipLaunchKernelGGL((k_b_hull_compact<false>), dim3(ncompact), dim3(kHullBlock), 0, s, compact, ha, lev);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_b_slabs(bool small, int ntiles, const int2 *tiles, const FinishArgs *fa,
+                          hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  if (small) hipLaunchKernelGGL((k_b_slabs<true>), dim3(ntiles), dim3(2 * kTileSlabs), 0, s, tiles, fa);
+  else hipLaunchKernelGGL((k_b_slabs<false>), dim3(ntiles), dim3(2 * kTileSlabs), 0, s, tiles, fa);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_nodes(bool small, int lev, int nwork, const int4 *work, const HullArgs *ha,
+                          hipStream_t s) {
+  if (nwork <= 0) return hipSuccess;
+  const dim3 g((nwork + 63) / 64);
+  if (small) hipLaunchKernelGGL((k_b_nodes<true>), g, dim3(64), 0, s, work, nwork, ha, lev);
+  else hipLaunchKernelGGL((k_b_nodes<false>), g, dim3(64), 0, s, work, nwork, ha, lev);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_root(int B, const FinishArgs *fa, const HullArgs *ha, hipStream_t s) {
+  hipLaunchKernelGGL(k_b_root, dim3(B), dim3(64), 0, s, fa, ha);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_chain(int nwork, const int2 *work, const FinishArgs *fa, hipStream_t s) {
+  if (nwork <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_b_chain, dim3((nwork + 3) / 4), dim3(256), 0, s, work, nwork, fa);
+  return hipGetLastError();
 }
 
 size_t single_ws_bytes(int64_t n, int32_t p) { return ws_bytes_for(n, p); }

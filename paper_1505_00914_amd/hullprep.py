@@ -165,3 +165,97 @@ def precondition_then_hull(points: torch.Tensor, p: int) -> dict:
     hp_precondition(points, p, buf)
     hp_hull(buf)
     return collect(buf)
+
+
+# ---------------------------------------------------------------------------
+# Batches
+# ---------------------------------------------------------------------------
+@dataclass
+class BatchBuffers:
+    """Caller-owned device buffers of one batched run."""
+    cx: torch.Tensor
+    clo: torch.Tensor
+    chi: torch.Tensor
+    hx: torch.Tensor
+    hy: torch.Tensor
+    info: torch.Tensor
+    ws: torch.Tensor
+
+
+class Plan:
+    """A batch of ragged clouds: offsets (B+1, int64) into the concatenated
+    points and one p per cloud.  Wraps hp_plan_create / hp_plan_query /
+    hp_batched_run / hp_batched_run_percloud / hp_plan_destroy."""
+
+    def __init__(self, offsets, p):
+        import numpy as np
+
+        self.offsets = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        self.p = np.ascontiguousarray(np.asarray(p, dtype=np.int32))
+        self.B = int(self.p.shape[0])
+        if self.offsets.shape[0] != self.B + 1:
+            raise ValueError("offsets must have B+1 entries")
+        h = ctypes.c_void_p()
+        _lib.call("hp_plan_create", self.offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                  self.p.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), self.B, ctypes.byref(h))
+        self._h = h
+        ct, ht = ctypes.c_int64(), ctypes.c_int64()
+        wb = ctypes.c_size_t()
+        self.chain_off = np.zeros(self.B + 1, np.int64)
+        self.hull_off = np.zeros(self.B + 1, np.int64)
+        _lib.call("hp_plan_query", self._h, ctypes.byref(ct), ctypes.byref(ht), ctypes.byref(wb),
+                  self.chain_off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                  self.hull_off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+        self.chain_total, self.hull_total, self.ws_bytes = ct.value, ht.value, wb.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().hp_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def allocate(self, device) -> BatchBuffers:
+        i32 = dict(dtype=torch.int32, device=device)
+        c = max(1, self.chain_total)
+        h = max(1, self.hull_total)
+        return BatchBuffers(torch.empty(c, **i32), torch.empty(c, **i32), torch.empty(c, **i32),
+                            torch.empty(h, **i32), torch.empty(h, **i32),
+                            torch.zeros(max(1, 4 * self.B), **i32),
+                            torch.empty(max(1, self.ws_bytes), dtype=torch.uint8, device=device))
+
+    def _args(self, points, buf):
+        _check_points(points)
+        return (_ptr(points), _ptr(buf.cx), _ptr(buf.clo), _ptr(buf.chi), _ptr(buf.hx), _ptr(buf.hy),
+                _ptr(buf.info), _ptr(buf.ws), buf.ws.numel())
+
+    def run(self, points: torch.Tensor, buf: BatchBuffers, stream=None) -> None:
+        """hp_batched_run: one recorded launch sequence (HIP graph) for all clouds."""
+        _lib.call("hp_batched_run", self._h, *self._args(points, buf), _stream(stream))
+
+    def run_percloud(self, points: torch.Tensor, buf: BatchBuffers, stream=None) -> None:
+        """hp_batched_run_percloud: the plain per-cloud launch sequence (baseline)."""
+        _lib.call("hp_batched_run_percloud", self._h, *self._args(points, buf), _stream(stream))
+
+    def collect(self, buf: BatchBuffers) -> list[dict]:
+        """Synchronise and split the outputs per cloud (host copies)."""
+        torch.cuda.synchronize(buf.info.device)
+        if self.B == 0:
+            return []
+        info = buf.info.cpu().numpy().reshape(-1, 4)[: self.B]
+        cx, clo, chi = buf.cx.cpu().numpy(), buf.clo.cpu().numpy(), buf.chi.cpu().numpy()
+        hx, hy = buf.hx.cpu().numpy(), buf.hy.cpu().numpy()
+        out = []
+        import numpy as np
+
+        for b in range(self.B):
+            st, k, s, h = (int(v) for v in info[b])
+            c0, h0 = int(self.chain_off[b]), int(self.hull_off[b])
+            out.append({"status": st, "k": k, "s": s, "h": h,
+                        "x": cx[c0:c0 + k], "clo": clo[c0:c0 + k], "chi": chi[c0:c0 + k],
+                        "hull": np.stack([hx[h0:h0 + h], hy[h0:h0 + h]], 1)})
+        return out
