@@ -4,7 +4,8 @@
 // cloud's reduce mode and chunks, its hull-tree shape, its workspace slots
 // and its output offsets, plus the work tables of every launch.  A run is a
 // fixed sequence of wide launches over all clouds (fill, one persistent
-// reduce, slab finish, hull test and compaction per level), recorded once
+// reduce, slab tiles with their level-2 hulls, upper hull levels, per-cloud
+// root, chain write), recorded once
 // into a HIP graph and replayed; the graph is re-recorded only when the
 // caller's buffers change.
 #include <algorithm>
@@ -19,7 +20,11 @@ namespace hp {
 
 namespace {
 
-constexpr int64_t kChunk = 1 << 16;      // points per reduce work item
+// Points per reduce work item: at least 64 per column of the cloud, so the
+// LDS init and the merge of a chunk's L stay small against its stream, and
+// within [2^16, 2^20] so the persistent grid still balances.
+constexpr int64_t kChunkMin = 1 << 16, kChunkMax = 1 << 20;
+int64_t chunk_for(int32_t p) { return std::min(kChunkMax, std::max(kChunkMin, 64 * (int64_t)p)); }
 constexpr int32_t kBatchPMax = 65536;    // largest p a batched cloud may have
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -41,9 +46,10 @@ struct hp_plan {
   std::vector<int64_t> chain_off, hull_off;  // B+1
   std::vector<uint8_t> needs_fill;
   std::vector<hp::BatchItem> items;
-  std::vector<int2> fin[2];        // [small?] (cloud, slab)
   int maxlev = 1;
-  std::vector<int2> test[2][hp::kMaxLevels + 1], comp[2][hp::kMaxLevels + 1];
+  std::vector<int2> tiles;         // (cloud, tile of 64 slabs)
+  std::vector<int4> nodes[2][hp::kMaxLevels + 1];  // [small?][level >= 3] (cloud, node, side, 0)
+  std::vector<int2> chain_work;    // (cloud, slab)
   size_t ws_batched = 0, ws_single = 0;
   size_t lds_bytes = 0;
   int reduce_grid = 1;
@@ -54,9 +60,9 @@ struct hp_plan {
   int32_t *d_counter = nullptr;
   hp::FinishArgs *d_fa = nullptr;
   hp::HullArgs *d_ha = nullptr;
-  int2 *d_fin[2] = {nullptr, nullptr};
-  int2 *d_test[2][hp::kMaxLevels + 1] = {};
-  int2 *d_comp[2][hp::kMaxLevels + 1] = {};
+  int2 *d_tiles = nullptr;
+  int4 *d_nodes[2][hp::kMaxLevels + 1] = {};
+  int2 *d_chain = nullptr;
   // graph state
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
@@ -145,17 +151,16 @@ hipError_t enqueue_batched(const hp_plan *P, const int32_t *pts, hipStream_t s) 
                         P->d_counter, P->d_fa, s);
     if (e != hipSuccess) return e;
   }
-  for (int sm = 0; sm < 2; ++sm) {
-    e = launch_b_finish(sm == 1, (int)P->fin[sm].size(), P->d_fin[sm], P->d_fa, s);
-    if (e != hipSuccess) return e;
-  }
-  for (int lev = 2; lev <= P->maxlev; ++lev)
+  e = launch_b_tiles((int)P->tiles.size(), P->d_tiles, P->d_fa, s);
+  if (e != hipSuccess) return e;
+  for (int lev = 3; lev <= P->maxlev; ++lev)
     for (int sm = 0; sm < 2; ++sm) {
-      e = launch_b_hull(sm == 1, lev, (int)P->test[sm][lev].size(), P->d_test[sm][lev],
-                        (int)P->comp[sm][lev].size(), P->d_comp[sm][lev], P->d_ha, s);
+      e = launch_b_nodes(sm == 1, lev, (int)P->nodes[sm][lev].size(), P->d_nodes[sm][lev], P->d_ha, s);
       if (e != hipSuccess) return e;
     }
-  return hipSuccess;
+  e = launch_b_root(P->B, P->d_fa, P->d_ha, s);
+  if (e != hipSuccess) return e;
+  return launch_b_chain((int)P->chain_work.size(), P->d_chain, P->d_fa, s);
 }
 
 }  // namespace
@@ -224,22 +229,23 @@ extern "C" int hp_plan_create(const int64_t *offsets, const int32_t *p, int32_t 
     // reduce mode and chunks
     const bool dense = (int64_t)pb <= lds_p_max && n >= 4 * (int64_t)pb;
     if (n > 0) {
-      if (dense && n <= kChunk) {
+      const int64_t chunk = chunk_for(pb);
+      if (dense && n <= chunk) {
         P->items.push_back(BatchItem{b, 0, offsets[b], n, 0});
         P->needs_fill[b] = 0;
       } else {
-        for (int64_t s0 = 0; s0 < n; s0 += kChunk)
-          P->items.push_back(BatchItem{b, dense ? 1 : 2, offsets[b] + s0, std::min(kChunk, n - s0), 0});
+        for (int64_t s0 = 0; s0 < n; s0 += chunk)
+          P->items.push_back(BatchItem{b, dense ? 1 : 2, offsets[b] + s0, std::min(chunk, n - s0), 0});
       }
       if (dense) pmax_lds = std::max(pmax_lds, pb);
     }
     // work tables
     const int sm = pb < (1 << 15) ? 1 : 0;
-    for (int j = 0; j < T.size[1]; ++j) P->fin[sm].push_back(make_int2(b, j));
-    for (int lev = 2; lev <= T.nlev; ++lev) {
-      for (int q = 0; q < T.size[lev - 1] * kSplit; ++q) P->test[sm][lev].push_back(make_int2(b, q));
-      for (int q = 0; q < T.size[lev]; ++q) P->comp[sm][lev].push_back(make_int2(b, q));
-    }
+    for (int j = 0; j < T.size[1]; ++j) P->chain_work.push_back(make_int2(b, j));
+    for (int j = 0; j * kFanIn < T.size[1]; ++j) P->tiles.push_back(make_int2(b, j));
+    for (int lev = 3; lev <= T.nlev; ++lev)
+      for (int q = 0; q < T.size[lev]; ++q)
+        for (int side = 0; side < 2; ++side) P->nodes[sm][lev].push_back(make_int4(b, q, side, 0));
   }
   P->ws_batched = o;
   P->ws_single = single_max;
@@ -258,14 +264,11 @@ extern "C" int hp_plan_create(const int64_t *offsets, const int32_t *p, int32_t 
   const size_t o_counter = reserve(sizeof(int32_t));
   const size_t o_fa = reserve(sizeof(FinishArgs) * (size_t)std::max(1, B));
   const size_t o_ha = reserve(sizeof(HullArgs) * (size_t)std::max(1, B));
-  size_t o_fin[2], o_test[2][kMaxLevels + 1], o_comp[2][kMaxLevels + 1];
-  for (int sm = 0; sm < 2; ++sm) {
-    o_fin[sm] = reserve(sizeof(int2) * P->fin[sm].size());
-    for (int lev = 0; lev <= kMaxLevels; ++lev) {
-      o_test[sm][lev] = reserve(sizeof(int2) * P->test[sm][lev].size());
-      o_comp[sm][lev] = reserve(sizeof(int2) * P->comp[sm][lev].size());
-    }
-  }
+  size_t o_nodes[2][kMaxLevels + 1];
+  const size_t o_chain = reserve(sizeof(int2) * P->chain_work.size());
+  const size_t o_tiles = reserve(sizeof(int2) * P->tiles.size());
+  for (int sm = 0; sm < 2; ++sm)
+    for (int lev = 0; lev <= kMaxLevels; ++lev) o_nodes[sm][lev] = reserve(sizeof(int4) * P->nodes[sm][lev].size());
   if (hipMalloc(&P->dmem, dsz) != hipSuccess) return fail_plan(P, set_error(HP_ENOMEM, "device allocation of %zu bytes failed", dsz));
   char *dm = static_cast<char *>(P->dmem);
   P->d_items = reinterpret_cast<BatchItem *>(dm + o_items);
@@ -277,17 +280,16 @@ extern "C" int hp_plan_create(const int64_t *offsets, const int32_t *p, int32_t 
     return bytes == 0 || hipMemcpy(dm + at, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
   };
   bool ok = up(o_items, P->items.data(), sizeof(BatchItem) * P->items.size()) &&
-            up(o_fill, P->needs_fill.data(), P->needs_fill.size());
-  for (int sm = 0; sm < 2 && ok; ++sm) {
-    P->d_fin[sm] = reinterpret_cast<int2 *>(dm + o_fin[sm]);
-    ok = up(o_fin[sm], P->fin[sm].data(), sizeof(int2) * P->fin[sm].size());
+            up(o_fill, P->needs_fill.data(), P->needs_fill.size()) &&
+            up(o_chain, P->chain_work.data(), sizeof(int2) * P->chain_work.size()) &&
+            up(o_tiles, P->tiles.data(), sizeof(int2) * P->tiles.size());
+  P->d_chain = reinterpret_cast<int2 *>(dm + o_chain);
+  P->d_tiles = reinterpret_cast<int2 *>(dm + o_tiles);
+  for (int sm = 0; sm < 2 && ok; ++sm)
     for (int lev = 0; lev <= kMaxLevels && ok; ++lev) {
-      P->d_test[sm][lev] = reinterpret_cast<int2 *>(dm + o_test[sm][lev]);
-      P->d_comp[sm][lev] = reinterpret_cast<int2 *>(dm + o_comp[sm][lev]);
-      ok = up(o_test[sm][lev], P->test[sm][lev].data(), sizeof(int2) * P->test[sm][lev].size()) &&
-           up(o_comp[sm][lev], P->comp[sm][lev].data(), sizeof(int2) * P->comp[sm][lev].size());
+      P->d_nodes[sm][lev] = reinterpret_cast<int4 *>(dm + o_nodes[sm][lev]);
+      ok = up(o_nodes[sm][lev], P->nodes[sm][lev].data(), sizeof(int4) * P->nodes[sm][lev].size());
     }
-  }
   if (!ok) return fail_plan(P, set_error(HP_EDEVICE, "uploading plan tables failed"));
   if (prepare_b_reduce() != hipSuccess) return fail_plan(P, set_error(HP_EDEVICE, "reduce kernel setup failed"));
   if (hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking) != hipSuccess)

@@ -66,13 +66,9 @@ hipError_t launch_b_fill(int B, const FinishArgs *fa, const uint8_t *needs_fill,
 hipError_t prepare_b_reduce();  // raise the dynamic LDS limit (before capture)
 hipError_t launch_b_reduce(int grid, size_t lds_bytes, const int32_t *pts, const BatchItem *items,
                            int32_t nitems, int32_t *counter, const FinishArgs *fa, hipStream_t s);
-hipError_t launch_b_finish(bool small, int nwork, const int2 *work, const FinishArgs *fa, hipStream_t s);
-hipError_t launch_b_slabs(bool small, int ntiles, const int2 *tiles, const FinishArgs *fa, hipStream_t s);
+hipError_t launch_b_tiles(int ntiles, const int2 *tiles, const FinishArgs *fa, hipStream_t s);
 hipError_t launch_b_nodes(bool small, int lev, int nwork, const int4 *work, const HullArgs *ha,
                           hipStream_t s);
 hipError_t launch_b_root(int B, const FinishArgs *fa, const HullArgs *ha, hipStream_t s);
 hipError_t launch_b_chain(int nwork, const int2 *work, const FinishArgs *fa, hipStream_t s);
-hipError_t launch_b_hull(bool small, int lev, int ntest, const int2 *test, int ncompact,
-                         const int2 *compact, const HullArgs *ha, hipStream_t s);
-
 }  // namespace hp

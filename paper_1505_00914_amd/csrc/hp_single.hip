@@ -637,7 +637,6 @@ __device__ __forceinline__ void load_children(const HullArgs &H, HullShared &S, 
 // when the slab count is small enough): slab offsets by a scan of the slab
 // counts (kept in LDS), then one wave per slab writes its valid columns at
 // its offset (Lemma 1 order).  Also writes k, s and the range status.
-constexpr int kRootChainSlabs = 2 * kStage;  // offsets fit in the stage area
 
 __device__ void root_chain(const HullArgs &H, HullShared &S) {
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
@@ -1029,139 +1028,247 @@ __global__ __launch_bounds__(BLOCK) void k_b_reduce(const int32_t *__restrict__ 
   }
 }
 
-template <bool SMALL>
-__global__ __launch_bounds__(kFinBlock) void k_b_finish(const int2 *__restrict__ work, const FinishArgs *fa) {
-  __shared__ FinishShared S;
-  const int2 w = work[blockIdx.x];
-  finish_body<0, SMALL>(fa[w.x], S, w.y);
-}
-
-template <bool SMALL>
-__global__ __launch_bounds__(kHullBlock) void k_b_hull_test(const int2 *__restrict__ work,
-                                                            const HullArgs *ha, int lev) {
-  __shared__ HullShared S;
-  const int2 w = work[blockIdx.x];
-  hull_test_body<SMALL>(ha[w.x], S, lev, w.y);
-}
-
-template <bool SMALL>
-__global__ __launch_bounds__(kHullBlock) void k_b_hull_compact(const int2 *__restrict__ work,
-                                                               const HullArgs *ha, int lev) {
-  __shared__ HullShared S;
-  const int2 w = work[blockIdx.x];
-  hull_compact_body<SMALL>(ha[w.x], S, lev, w.y);
-}
-
 // ---------------------------------------------------------------------------
-// Batched finish, shaped for throughput across many clouds: every lane runs
-// the monotone chain (Andrew) over its own x-sorted input, so each step does
-// O(points) work with no cross-lane traffic.
-//   k_b_slabs      per 64-column slab and side: the slab's hull, its M word,
-//                  its counts (a lane per slab-side, 64 slabs per workgroup)
-//   k_b_nodes      per tree node and side: the chain over its children's
-//                  hulls in order (a lane per node-side), for each level
-//   k_b_root       per cloud: slab offsets (scan), k, s, the final vertex
-//                  list from the root's two sides
-//   k_b_chain      per slab: the chain at the scanned offset (Lemma 1 order)
+// Batched finish, shaped for throughput across many clouds: each lower hull
+// is built by Andrew's monotone chain run by one lane over x-sorted input
+// held in LDS, so a step costs one LDS read and there is no cross-lane
+// traffic.
+//   k_b_tiles   per tile of 64 slabs (= one level-2 node): each slab's M
+//               word and counts, each slab's two hulls (a lane per slab and
+//               side), then the node's two hulls from the slab hulls (a lane
+//               per side)
+//   k_b_nodes   per node above level 2 and side: the chain over its
+//               children's hulls staged in LDS
+//   k_b_root    per cloud: slab offsets (scan), k, s, the final vertex list
+//   k_b_chain   per slab: the chain at the scanned offset (Lemma 1 order)
 // ---------------------------------------------------------------------------
-constexpr int kTileSlabs = 64;                   // slabs per k_b_slabs workgroup
+constexpr int kTileSlabs = kFanIn;               // slabs per tile
 constexpr int kTileCols = kTileSlabs * kSlab;    // 4096 columns
+constexpr int kRow = kSlab + 2;                  // LDS row stride (entries)
+constexpr int kSideWords = kTileSlabs * kRow + 1;
+constexpr int kNodeCap = 4096;                   // points a k_b_nodes wave stages
 
-// Andrew's lower chain over get(0..m), pushed into out[] (which serves as the
-// stack); pops while the last two and the new point fail a strict left turn.
-template <bool SMALL, typename Get>
-__device__ __forceinline__ int mono_chain(Get get, int m, int2 *out) {
-  int top = 0;
+// A tile entry packs one point in tile-local coordinates: column in the
+// tile (12 bits) above a 16-bit height, lo - 1 for the lower side and p - hi
+// for the upper side.  Both are translations of (x, lo) and (x, -hi), so the
+// turn tests are unchanged; every difference fits in 17 signed bits and the
+// 24-bit products are exact.
+struct TilePt {
+  __device__ __forceinline__ int2 operator()(uint32_t e) const {
+    return make_int2((int)(e >> 16), (int)(e & 0xFFFFu));
+  }
+};
+struct PlainPt {
+  __device__ __forceinline__ int2 operator()(int2 e) const { return e; }
+};
+
+// Lower chain of the points of E[0..nL) followed by those of R[0..nR), both
+// already lower chains (strict left turns) and R entirely right of E; the
+// result is left in E[0..), count returned.  The left chain stays the
+// bottom of Andrew's stack, so only the right chain is scanned, and once an
+// entry R[j] (j >= 1) is pushed without a pop the stack ends in R[j-1],
+// R[j], and the rest of R extends it with left turns: it is copied without
+// tests.  R may lie in the same array at or after E + nL: every write goes
+// at or before the entry just read.
+template <bool SMALL, typename T, typename Pt>
+__device__ __forceinline__ int merge_right(T *E, int nL, const T *R, int nR, Pt pt) {
+  int top = nL;
   int2 a = make_int2(0, 0), b = make_int2(0, 0);
-  for (int i = 0; i < m; ++i) {
-    const int2 v = get(i);
+  if (top >= 2) a = pt(E[top - 2]);
+  if (top >= 1) b = pt(E[top - 1]);
+  int j = 0;
+  while (j < nR) {
+    const T e = R[j];
+    const int2 v = pt(e);
+    bool popped = false;
     while (top >= 2 && !cross_pos<SMALL>(a, b, v)) {
       --top;
       b = a;
-      if (top >= 2) a = out[top - 2];
+      if (top >= 2) a = pt(E[top - 2]);
+      popped = true;
     }
-    out[top] = v;
-    ++top;
+    E[top++] = e;
     a = b;
     b = v;
+    ++j;
+    if (j >= 2 && !popped) break;
   }
+  for (; j + 4 <= nR; j += 4) {
+    const T e0 = R[j], e1 = R[j + 1], e2 = R[j + 2], e3 = R[j + 3];
+    E[top] = e0;
+    E[top + 1] = e1;
+    E[top + 2] = e2;
+    E[top + 3] = e3;
+    top += 4;
+  }
+  for (; j < nR; ++j) E[top++] = R[j];
   return top;
 }
 
-template <bool SMALL>
-__global__ __launch_bounds__(2 * kTileSlabs) void k_b_slabs(const int2 *__restrict__ work,
+__global__ __launch_bounds__(2 * kTileSlabs) void k_b_tiles(const int2 *__restrict__ work,
                                                              const FinishArgs *fa) {
-  __shared__ int2 sL[kTileCols];
+  __shared__ uint32_t sE[2 * kSideWords];       // per side, per slab: a row of entries
+  __shared__ unsigned long long sVm[kTileSlabs], sSm[kTileSlabs];
+  __shared__ int sTop[2][kTileSlabs];
   const int2 w = work[blockIdx.x];
   const FinishArgs &A = fa[w.x];
   const int p = A.p;
+  const int2 *const Lm = A.Lm;
+  uint64_t *const mask = A.mask;
+  int32_t *const slab_k = A.slab_k;
+  int32_t *const slab_s = A.slab_s;
   const int64_t c0 = (int64_t)w.y * kTileCols;
   const int ncol = (int)min<int64_t>(kTileCols, p - c0);
-  for (int i = threadIdx.x; i < kTileCols; i += 2 * kTileSlabs)
-    sL[i] = i < ncol ? A.Lm[c0 + i] : make_int2(1, 0);
-  __syncthreads();
-  const int nslab_tile = (ncol + kSlab - 1) / kSlab;
-  // M words and slab counts: each wave ballots its slabs
-  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  for (int sl = wave; sl < nslab_tile; sl += (2 * kTileSlabs) / kWave) {
-    const int2 L = sL[sl * kSlab + lane];
+  const int nslab = (ncol + kSlab - 1) / kSlab;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  constexpr int kIter = kTileSlabs / 2;
+  // columns -> entries and ballots (wave w takes slabs w, w + 2, ...)
+  int2 Lr[kIter];
+#pragma unroll
+  for (int k = 0; k < kIter; ++k) {
+    const int col = (2 * k + wave) * kSlab + lane;
+    Lr[k] = col < ncol ? Lm[c0 + col] : make_int2(1, 0);
+  }
+#pragma unroll
+  for (int k = 0; k < kIter; ++k) {
+    const int sl = 2 * k + wave;
+    const int col = sl * kSlab + lane;
+    const int2 L = Lr[k];
     const bool valid = L.x <= L.y;
     const unsigned long long vm = __ballot(valid);
     const unsigned long long sm = __ballot(valid && L.x < L.y);
+    sE[sl * kRow + lane] = ((uint32_t)col << 16) | (uint32_t)(L.x - 1);
+    sE[kSideWords + sl * kRow + lane] = ((uint32_t)col << 16) | (uint32_t)(p - L.y);
     if (lane == 0) {
-      const int gs = w.y * kTileSlabs + sl;
-      if (A.mask) A.mask[gs] = vm;
-      A.slab_k[gs] = __popcll(vm);
-      A.slab_s[gs] = __popcll(vm) + __popcll(sm);
+      sVm[sl] = vm;
+      sSm[sl] = sm;
     }
   }
-  // one lane per (slab, side)
-  const int sl = threadIdx.x >> 1, side = threadIdx.x & 1;
-  if (sl < nslab_tile) {
-    const int gs = w.y * kTileSlabs + sl;
-    const int base = sl * kSlab;
-    int2 *out = A.cand + (size_t)side * (size_t)p + (size_t)gs * kSlab;
-    // valid columns of the slab in order, as (x, lo) or (x, -hi)
-    unsigned long long vm = 0;
-    for (int i = 0; i < kSlab; ++i) vm |= (unsigned long long)(sL[base + i].x <= sL[base + i].y) << i;
-    const int m = __popcll(vm);
-    unsigned long long it = vm;
-    auto get = [&](int) -> int2 {
-      const int i = __ffsll((long long)it) - 1;
-      it &= it - 1;
-      const int2 L = sL[base + i];
-      return make_int2((int)(c0 + base + i + 1), side ? -L.y : L.x);
-    };
-    const int cnt = mono_chain<SMALL>(get, m, out);
-    A.ccount[side * A.tree.nodes + gs] = cnt;
+  __syncthreads();
+  if (tid < nslab) {
+    const int gs = w.y * kTileSlabs + tid;
+    const unsigned long long vm = sVm[tid];
+    if (mask) mask[gs] = vm;
+    slab_k[gs] = __popcll(vm);
+    slab_s[gs] = __popcll(vm) + __popcll(sSm[tid]);
+  }
+  // a lane per (slab, side): the slab's hull, in place over its row
+  {
+    const int sl = tid >> 1, side = tid & 1;
+    uint32_t *row = sE + side * kSideWords + sl * kRow;
+    unsigned long long vm = sVm[sl];
+    int top = 0;
+    int2 a = make_int2(0, 0), b = make_int2(0, 0);
+    while (vm) {
+      const int i = __ffsll((long long)vm) - 1;
+      vm &= vm - 1;
+      const uint32_t e = row[i];
+      const int2 v = TilePt()(e);
+      while (top >= 2 && !cross_pos<true>(a, b, v)) {
+        --top;
+        b = a;
+        if (top >= 2) a = TilePt()(row[top - 2]);
+      }
+      row[top++] = e;
+      a = b;
+      b = v;
+    }
+    sTop[side][sl] = top;
+  }
+  // binary merge tree over the slab hulls: at step h, the lane of (group g,
+  // side) joins the hulls of slabs g*2h and g*2h + h, leaving the result at
+  // the first one's row
+  for (int h = 1; h < kTileSlabs; h <<= 1) {
+    __syncthreads();
+    const int g = tid >> 1, side = tid & 1;
+    const int s0 = g * 2 * h, s1 = s0 + h;
+    if (s1 < nslab) {
+      uint32_t *E = sE + side * kSideWords + s0 * kRow;
+      sTop[side][s0] = merge_right<true>(E, sTop[side][s0], E + h * kRow, sTop[side][s1], TilePt());
+    }
+  }
+  __syncthreads();
+  // write the node's hulls (level 2, or level 1 when the cloud is one slab)
+  const TreeShape &T = A.tree;
+  const int lev = T.nlev >= 2 ? 2 : 1;
+  const int64_t x0 = c0 + 1;
+  int2 *const cand = A.cand;
+  const int span = T.span[lev];
+  for (int side = 0; side < 2; ++side) {
+    const int cnt = sTop[side][0];
+    const uint32_t *E = sE + side * kSideWords;
+    int2 *out = cand + (size_t)((lev - 1) & 1) * 2 * (size_t)p + (size_t)side * p + (size_t)w.y * span;
+    for (int j = tid; j < cnt; j += 2 * kTileSlabs) {
+      const uint32_t e = E[j];
+      const int y = (int)(e & 0xFFFFu);
+      out[j] = make_int2((int)(x0 + (e >> 16)), side ? y - p : y + 1);
+    }
+    if (tid == 0) A.ccount[side * T.nodes + T.base[lev] + w.y] = cnt;
   }
 }
 
-// One lane per (node at level lev, side): the chain over the children's
-// hulls (level lev-1, buffer (lev-2)&1) into the node's slot of buffer
-// (lev-1)&1.
+// A wave per (node at level lev >= 3, side): the children's hulls (level
+// lev-1, buffer (lev-2)&1) staged in LDS in order and joined child by child
+// by lane 0, the result copied to the node's slot of buffer (lev-1)&1.  A
+// node whose children hold more than kNodeCap points is joined the same way
+// in global memory.
 template <bool SMALL>
-__global__ __launch_bounds__(64) void k_b_nodes(const int4 *__restrict__ work, int nwork,
-                                                const HullArgs *ha, int lev) {
-  const int t = blockIdx.x * 64 + threadIdx.x;
-  if (t >= nwork) return;
-  const int4 w = work[t];                 // (cloud, node, side, -)
+__global__ __launch_bounds__(kWave) void k_b_nodes(const int4 *__restrict__ work, const HullArgs *ha,
+                                                   int lev) {
+  __shared__ int2 sP[kNodeCap];
+  __shared__ int sOff[kFanIn + 1];
+  __shared__ int sTop;
+  const int4 w = work[blockIdx.x];        // (cloud, node, side, -)
   const HullArgs &H = ha[w.x];
   const TreeShape &T = H.tree;
   const int node = w.y, side = w.z;
+  const int lane = threadIdx.x;
   const int64_t P = H.positions;
   const int2 *in = H.buf[(lev - 2) & 1] + (size_t)side * P;
   int2 *out = H.buf[(lev - 1) & 1] + (size_t)side * P + (size_t)node * T.span[lev];
   const int c0 = node * kFanIn, nc = min(kFanIn, T.size[lev - 1] - c0);
   const int32_t *cnt = H.ccount + side * T.nodes + T.base[lev - 1];
-  int child = 0, r = 0, m = 0;
-  for (int c = 0; c < nc; ++c) m += cnt[c0 + c];
-  auto get = [&](int) -> int2 {
-    while (r >= cnt[c0 + child]) { ++child; r = 0; }
-    return in[(size_t)(c0 + child) * T.span[lev - 1] + r++];
-  };
-  const int k = mono_chain<SMALL>(get, m, out);
-  H.ccount[side * T.nodes + T.base[lev] + node] = k;
+  int32_t *const ccount_out = H.ccount + side * T.nodes + T.base[lev] + node;
+  const size_t span = (size_t)T.span[lev - 1];
+  // child offsets (wave scan)
+  const int mine = lane < nc ? cnt[c0 + lane] : 0;
+  int incl = mine;
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int o = __shfl_up(incl, d, kWave);
+    if (lane >= d) incl += o;
+  }
+  const int m = __shfl(incl, kWave - 1, kWave);
+  sOff[lane] = incl - mine;
+  if (lane == 0) sOff[kFanIn] = m;
+  __syncthreads();
+  if (m <= kNodeCap) {
+    for (int j = lane; j < m; j += kWave) {
+      int lo = 0, hi = nc - 1;            // last child with sOff[c] <= j
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (sOff[mid] <= j) lo = mid;
+        else hi = mid - 1;
+      }
+      sP[j] = in[(size_t)(c0 + lo) * span + (j - sOff[lo])];
+    }
+    __syncthreads();
+    if (lane == 0) {
+      int top = sOff[1] - sOff[0];
+      for (int c = 1; c < nc; ++c)
+        top = merge_right<SMALL>(sP, top, sP + sOff[c], sOff[c + 1] - sOff[c], PlainPt());
+      sTop = top;
+    }
+    __syncthreads();
+    const int top = sTop;
+    for (int j = lane; j < top; j += kWave) out[j] = sP[j];
+    if (lane == 0) *ccount_out = top;
+    return;
+  }
+  if (lane != 0) return;
+  int top = 0;
+  for (int c = 0; c < nc; ++c)
+    top = merge_right<SMALL>(out, top, in + (size_t)(c0 + c) * span, cnt[c0 + c], PlainPt());
+  *ccount_out = top;
 }
 
 // Per cloud (one wave): slab offsets and totals, then the final hull from
@@ -1539,44 +1646,17 @@ hipError_t launch_b_reduce(int grid, size_t lds_bytes, const int32_t *pts, const
   return hipGetLastError();
 }
 
-hipError_t launch_b_finish(bool small, int nwork, const int2 *work, const FinishArgs *fa, hipStream_t s) {
-  if (nwork <= 0) return hipSuccess;
-  if (small) hipLaunchKernelGGL((k_b_finish<true>), dim3(nwork), dim3(kFinBlock), 0, s, work, fa);
-  else hipLaunchKernelGGL((k_b_finish<false>), dim3(nwork), dim3(kFinBlock), 0, s, work, fa);
-  return hipGetLastError();
-}
-
-hipError_t launch_b_hull(bool small, int lev, int ntest, const int2 *test, int ncompact,
-                         const int2 *compact, const HullArgs *ha, hipStream_t s) {
-  if (ntest > 0) {
-    if (small) hipLaunchKernelGGL((k_b_hull_test<true>), dim3(ntest), dim3(kHullBlock), 0, s, test, ha, lev);
-    else hipLaunchKernelGGL((k_b_hull_test<false>), dim3(ntest), dim3(kHullBlock), 0, s, test, ha, lev);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  if (ncompact > 0) {
-    if (small)
-      hipLaunchKernelGGL((k_b_hull_compact<true>), dim3(ncompact), dim3(kHullBlock), 0, s, compact, ha, lev);
-    else
-      hipLaunchKernelGGL((k_b_hull_compact<false>), dim3(ncompact), dim3(kHullBlock), 0, s, compact, ha, lev);
-  }
-  return hipGetLastError();
-}
-
-hipError_t launch_b_slabs(bool small, int ntiles, const int2 *tiles, const FinishArgs *fa,
-                          hipStream_t s) {
+hipError_t launch_b_tiles(int ntiles, const int2 *tiles, const FinishArgs *fa, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  if (small) hipLaunchKernelGGL((k_b_slabs<true>), dim3(ntiles), dim3(2 * kTileSlabs), 0, s, tiles, fa);
-  else hipLaunchKernelGGL((k_b_slabs<false>), dim3(ntiles), dim3(2 * kTileSlabs), 0, s, tiles, fa);
+  hipLaunchKernelGGL(k_b_tiles, dim3(ntiles), dim3(2 * kTileSlabs), 0, s, tiles, fa);
   return hipGetLastError();
 }
 
 hipError_t launch_b_nodes(bool small, int lev, int nwork, const int4 *work, const HullArgs *ha,
                           hipStream_t s) {
   if (nwork <= 0) return hipSuccess;
-  const dim3 g((nwork + 63) / 64);
-  if (small) hipLaunchKernelGGL((k_b_nodes<true>), g, dim3(64), 0, s, work, nwork, ha, lev);
-  else hipLaunchKernelGGL((k_b_nodes<false>), g, dim3(64), 0, s, work, nwork, ha, lev);
+  if (small) hipLaunchKernelGGL((k_b_nodes<true>), dim3(nwork), dim3(kWave), 0, s, work, ha, lev);
+  else hipLaunchKernelGGL((k_b_nodes<false>), dim3(nwork), dim3(kWave), 0, s, work, ha, lev);
   return hipGetLastError();
 }
 

@@ -104,3 +104,33 @@ def test_empty_batch(hp):
     plan.run(torch.zeros((0, 2), dtype=torch.int32, device="cuda"), buf)
     assert plan.collect(buf) == []
     plan.close()
+
+
+def _parabolas(p, period, scale):
+    """One point (x, lo) and one (x, hi) per column, lo a parabola repeated
+    every `period` columns and hi its mirror image: lower hulls with hundreds
+    of vertices per period on both sides."""
+    x = np.arange(1, p + 1, dtype=np.int64)
+    t = (x - 1) % period
+    lo = 1 + np.ceil((t - period / 2) ** 2 / scale).astype(np.int64)
+    hi = p + 1 - lo
+    pts = np.concatenate([np.stack([x, lo], 1), np.stack([x, hi], 1)])
+    assert pts.min() >= 1 and pts.max() <= p
+    return pts.astype(np.int32)
+
+
+def test_batched_large_hulls(hp):
+    """Clouds whose upper tree levels hold many hull vertices: more than one
+    node merge can stage in LDS (p = 65536) and fewer (p = 8192, 20000)."""
+    clouds = [_parabolas(65_536, 4096, 65.0), _parabolas(8_192, 4096, 520.0),
+              _parabolas(20_000, 1000, 16.0), _parabolas(1_000, 1000, 1000.0)]
+    ps = np.array([65_536, 8_192, 20_000, 1_000], np.int32)
+    offsets = np.zeros(len(clouds) + 1, np.int64)
+    offsets[1:] = np.cumsum([c.shape[0] for c in clouds])
+    pts = np.concatenate(clouds)
+    print(f"[case] parabola batch, p = {ps.tolist()}", flush=True)
+    plan = hp.Plan(offsets, ps)
+    buf = plan.allocate("cuda")
+    plan.run(torch.from_numpy(pts).cuda(), buf)
+    _check(plan.collect(buf), pts, offsets, ps, "parabolas")
+    plan.close()

@@ -109,6 +109,11 @@ def _edge_cases():
     cases["duplicates"] = (np.tile(np.array([[17, 3], [17, 3], [2, 9]], np.int32), (1000, 1)), 20)
     cases["sparse-2p20"] = (rng.integers(1, (1 << 20) + 1, size=(3000, 2)).astype(np.int32), 1 << 20)
     cases["two-columns"] = (np.array([[5, 1], [5, 9], [6, 4]], np.int32), 9)
+    # a parabola per 4096 columns and its mirror image: thousands of hull
+    # vertices below the root
+    x = np.arange(1, 65_537, dtype=np.int64)
+    lo = 1 + np.ceil(((x - 1) % 4096 - 2048.0) ** 2 / 65).astype(np.int64)
+    cases["parabolas-2p16"] = (np.concatenate([np.stack([x, lo], 1), np.stack([x, 65_537 - lo], 1)]).astype(np.int32), 65_536)
     return cases
 
 
