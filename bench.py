@@ -216,6 +216,181 @@ def bench_batched(args, torch, hp, synth) -> dict:
             "oracle_sample_ok": f"{ok}/{len(sample)}"}
 
 
+def _serve_pool(torch, synth, count: int, seed: int, device_copy: bool):
+    """Pre-generated requests: n log-uniform in [1e4, 1e7], p log-uniform in
+    [1024, 65536], kind uniform / Gaussian / ellipsoids with equal odds;
+    points in page-locked host memory (and a device copy when asked)."""
+    spec = synth.batch_spec(count, seed=seed, n_range=(10_000, 10_000_000), p_range=(1024, 65_536),
+                            kinds=("uniform", "gaussian", "ellipsoids"))
+    host, dev = [], []
+    for kind, n, p, s in spec:
+        c = synth.cloud(kind, n, p, s, device="cuda:0")
+        host.append(c.cpu().pin_memory())
+        dev.append(c if device_copy else None)
+    torch.cuda.synchronize()
+    return spec, host, dev
+
+
+def _percentiles(lat_ms):
+    import numpy as np
+
+    a = np.asarray(lat_ms)
+    return {"p50_ms": round(float(np.percentile(a, 50)), 4), "p99_ms": round(float(np.percentile(a, 99)), 4),
+            "max_ms": round(float(a.max()), 4), "mean_ms": round(float(a.mean()), 4)}
+
+
+def _wait_until(hp, due_ns: int) -> None:
+    """Sleep (releasing the interpreter lock) until shortly before due_ns,
+    then spin on the library clock."""
+    while True:
+        left = due_ns - hp.clock_ns()
+        if left <= 0:
+            return
+        if left > 300_000:
+            time.sleep((left - 200_000) / 1e9)
+
+
+def bench_serve(args, torch, hp, synth) -> dict:
+    """Open-loop Poisson arrivals (rate args.serve_rate per second for
+    args.serve_seconds) drawn from a pool of pre-generated requests, served
+    (a) by the library's server (continuous batching, memory admission) from
+    page-locked host memory, (b) by the same server with the points already in
+    device memory, and (c) as a baseline, first-in first-out, one request at a
+    time with the plain single-cloud launch sequence.  Latency = the time the
+    result is in host memory minus the scheduled arrival time."""
+    import threading
+
+    import numpy as np
+
+    sys.setswitchinterval(0.0005)
+    spec, host, dev = _serve_pool(torch, synth, args.serve_pool, 6, True)
+    rng = np.random.default_rng(7)
+    gaps = rng.exponential(1.0 / args.serve_rate, size=int(args.serve_rate * args.serve_seconds * 1.2) + 16)
+    arrivals = np.cumsum(gaps)
+    arrivals = arrivals[arrivals < args.serve_seconds]
+    picks = rng.integers(0, len(spec), size=arrivals.shape[0])
+
+    # reference result of every pool entry: each request alone
+    ref = []
+    srv = hp.Server(args.serve_budget << 30, max_batch=1)
+    for (kind, n, p, _), c in zip(spec, host):
+        r = srv.submit(c, p)
+        srv.wait(r)
+        ref.append(r.result())
+    srv.close()
+
+    def same(a, b):
+        return (a["status"] == b["status"] == 0 and a["k"] == b["k"] and a["s"] == b["s"]
+                and a["h"] == b["h"] and np.array_equal(a["x"], b["x"]) and np.array_equal(a["clo"], b["clo"])
+                and np.array_equal(a["chi"], b["chi"]) and np.array_equal(a["hull"], b["hull"]))
+
+    def run_server(on_device: bool) -> dict:
+        srv = hp.Server(args.serve_budget << 30, max_batch=args.serve_max_batch)
+        for i in range(min(8, len(spec))):       # warm the pinned allocator and the kernels
+            r = srv.submit(dev[i] if on_device else host[i], spec[i][2])
+            srv.wait(r)
+        reqs = [None] * len(arrivals)
+        done = threading.Event()
+        lat = [0.0] * len(arrivals)
+        bad = [0]
+        first_bad = []
+
+        def waiter():
+            for i in range(len(arrivals)):
+                while reqs[i] is None:
+                    time.sleep(0.0001)
+                srv.wait(reqs[i])
+                lat[i] = (reqs[i].done_ns - t0 - int(arrivals[i] * 1e9)) / 1e6
+                got = reqs[i].result()
+                if not same(got, ref[picks[i]]):
+                    bad[0] += 1
+                    if len(first_bad) < 4:
+                        w = ref[picks[i]]
+                        first_bad.append({"i": i, "pool": int(picks[i]), "n": spec[picks[i]][1],
+                                          "p": spec[picks[i]][2],
+                                          "got": [got["status"], got["k"], got["s"], got["h"]],
+                                          "want": [w["status"], w["k"], w["s"], w["h"]],
+                                          "differ": [key for key in ("x", "clo", "chi", "hull")
+                                                     if not np.array_equal(got[key], w[key])]})
+                reqs[i] = True          # drop the buffers
+            done.set()
+
+        th = threading.Thread(target=waiter, daemon=True)
+        t0 = hp.clock_ns()
+        th.start()
+        for i, at in enumerate(arrivals):
+            _wait_until(hp, t0 + int(at * 1e9))
+            j = int(picks[i])
+            reqs[i] = srv.submit(dev[j] if on_device else host[j], spec[j][2])
+        done.wait()
+        t_end = hp.clock_ns()
+        st = srv.stats()
+        srv.close()
+        pts = int(sum(spec[int(j)][1] for j in picks))
+        out = _percentiles(lat)
+        out.update({"requests": len(arrivals), "req_per_s": round(len(arrivals) / ((t_end - t0) / 1e9), 1),
+                    "gpoints_per_s": round(pts / ((t_end - t0) / 1e9) / 1e9, 3),
+                    "mean_batch": round(st["batched_requests"] / max(1, st["batches"]), 2),
+                    "peak_arena_gib": round(st["peak_bytes"] / 2**30, 3),
+                    "identical_to_alone": bad[0] == 0})
+        if bad[0]:
+            out["mismatches"] = bad[0]
+            out["first_mismatches"] = first_bad
+        return out
+
+    def run_fifo() -> dict:
+        """One request at a time, plain single-cloud launches, FIFO."""
+        dev_pts = torch.empty((max(s[1] for s in spec), 2), dtype=torch.int32, device="cuda:0")
+        maxp = max(s[2] for s in spec)
+        buf = hp.Buffers.allocate(max(s[1] for s in spec), maxp, torch.device("cuda:0"), export_L=False)
+        buf.ws = torch.empty(max(hp.workspace_bytes(s[1], s[2]) for s in spec), dtype=torch.uint8,
+                             device="cuda:0")
+        stream = torch.cuda.current_stream()
+        lat = []
+        pin_out = torch.empty(4, dtype=torch.int32, pin_memory=True)
+        t0 = hp.clock_ns()
+        for i, at in enumerate(arrivals):
+            due = t0 + int(at * 1e9)
+            _wait_until(hp, due)
+            j = int(picks[i])
+            n, p = spec[j][1], spec[j][2]
+            dev_pts[:n].copy_(host[j], non_blocking=True)
+            cap = min(n, p)
+            hp.hp_run(dev_pts[:n], p, buf, stream)
+            cx = buf.cx[:cap].to("cpu", non_blocking=True)
+            hx = buf.hx[:2 * cap].to("cpu", non_blocking=True)
+            pin_out.copy_(buf.info, non_blocking=True)
+            stream.synchronize()
+            lat.append((hp.clock_ns() - due) / 1e6)
+            del cx, hx
+        t_end = hp.clock_ns()
+        out = _percentiles(lat)
+        out.update({"requests": len(arrivals), "req_per_s": round(len(arrivals) / ((t_end - t0) / 1e9), 1)})
+        return out
+
+    # host-to-device copy rate of page-locked memory, for context
+    big = max(range(len(spec)), key=lambda j: spec[j][1])
+    dst = torch.empty_like(host[big], device="cuda:0")
+    dst.copy_(host[big], non_blocking=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        dst.copy_(host[big], non_blocking=True)
+    torch.cuda.synchronize()
+    h2d = 5 * host[big].numel() * 4 / (time.perf_counter() - t0) / 1e9
+    offered = args.serve_rate * float(np.mean([8 * spec[j][1] for j in picks])) / 1e9
+    del dst
+
+    res = {"h2d_pinned_gbs": round(h2d, 1), "offered_h2d_gbs": round(offered, 1),
+           "trace": f"Poisson {args.serve_rate}/s for {args.serve_seconds} s, pool of {len(spec)} requests "
+                    f"(n log-uniform 1e4..1e7, p log-uniform 1024..65536, uniform/gaussian/ellipsoids)",
+           "budget_gib": args.serve_budget, "max_batch": args.serve_max_batch}
+    res["server_host_points"] = run_server(False)
+    res["server_device_points"] = run_server(True)
+    res["fifo_percloud_host_points"] = run_fifo()
+    return res
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -230,6 +405,11 @@ def main(argv=None):
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--percloud-steps", type=int, default=2)
     ap.add_argument("--serve", action="store_true")
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--serve-pool", type=int, default=32)
+    ap.add_argument("--serve-budget", type=int, default=8, help="device arena, GiB")
+    ap.add_argument("--serve-max-batch", type=int, default=64)
     ap.add_argument("--strategy", type=int, default=0)
     args = ap.parse_args(argv)
 
@@ -252,8 +432,7 @@ def main(argv=None):
     if not args.no_batched:
         out["batched"] = bench_batched(args, torch, hp, synth)
     if args.serve:
-        from paper_1505_00914_amd import serve
-        out["serving"] = serve.bench(torch)
+        out["serving"] = bench_serve(args, torch, hp, synth)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(host, p, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -67,7 +67,8 @@ extern "C" {
 #define HP_ERANGE    (-2)  /* (device status) a coordinate outside [1, p]       */
 #define HP_ECAPACITY (-3)  /* an output or workspace is smaller than required   */
 #define HP_EDEVICE   (-4)  /* a HIP call failed                                  */
-#define HP_ENOMEM    (-5)  /* host or device allocation failed (plans only)      */
+#define HP_ENOMEM    (-5)  /* host or device allocation failed (plans, servers)  */
+#define HP_ETIMEOUT  (-6)  /* hp_server_wait: the request has not completed yet */
 
 #define HP_P_MAX 2147483646
 
@@ -204,6 +205,60 @@ int hp_batched_run_percloud(hp_plan *plan, const int32_t *pts,
 /* Free a plan (NULL is accepted).  The caller must have synchronised every
  * stream the plan ran on. */
 void hp_plan_destroy(hp_plan *plan);
+
+/* ------------------------------------------------------------------------
+ * Served form: independent requests joined into batches by the library's
+ * scheduler thread (continuous batching)
+ * ---------------------------------------------------------------------- */
+
+typedef struct hp_server hp_server;
+
+/* Start a server on the current device.  device_budget_bytes is allocated
+ * once, here, as the arena from which every request in flight takes one
+ * block (its points when they come from host memory, its workspace, its
+ * device outputs): a request is admitted, in arrival order, only when its
+ * block fits.  max_batch bounds the requests joined into one launch
+ * sequence.  Up to two batches are in flight; the points of the next batch
+ * are copied while the current one computes. */
+int hp_server_create(size_t device_budget_bytes, int32_t max_batch, hp_server **server);
+
+/* Device bytes of the arena block a request of n points with side p needs
+ * (on_device: the points are already in device memory and are not copied). */
+int hp_server_request_bytes(int64_t n, int32_t p, int32_t on_device, size_t *bytes);
+
+/* Queue one request (one cloud, 1 <= p <= 65536).
+ *   pts        n interleaved (x, y) int32: HOST memory, copied by the server
+ *              (page-locked memory keeps the copy asynchronous), or DEVICE
+ *              memory when on_device != 0; either way it must stay valid
+ *              until the request completes
+ *   cx, clo, chi  HOST int32[chain_cap] each: the chain (Lemma 1 order)
+ *   hx, hy     HOST int32[2 * chain_cap] each: the hull
+ *   chain_cap  >= min(n, p)
+ *   info       HOST int32[HP_INFO_WORDS]: status, k, s, h
+ * Outputs are written before the request completes (page-locked memory
+ * keeps those copies asynchronous too).  Returns HP_OK and *ticket;
+ * HP_ECAPACITY when the request alone exceeds the budget; HP_EINVAL for bad
+ * arguments.  Data errors (a point outside [1, p]) go to info[0]. */
+int hp_server_submit(hp_server *server, const int32_t *pts, int64_t n, int32_t p, int32_t on_device,
+                     int32_t *cx, int32_t *clo, int32_t *chi, int32_t chain_cap,
+                     int32_t *hx, int32_t *hy, int32_t *info, int64_t *ticket);
+
+/* Wait for a request to complete (timeout_us < 0: without limit).  On
+ * HP_OK the outputs are in place, *done_ns (may be NULL) holds the time the
+ * server saw it complete (hp_clock_ns clock) and the ticket is retired;
+ * HP_ETIMEOUT leaves it pending. */
+int hp_server_wait(hp_server *server, int64_t ticket, int64_t timeout_us, int64_t *done_ns);
+
+/* Counters: stats[0] batches issued, [1] requests completed, [2] requests
+ * issued in batches, [3] peak arena bytes in use, [4] requests waiting,
+ * [5] arena bytes. */
+int hp_server_stats(hp_server *server, int64_t *stats);
+
+/* Drain every queued request, stop the scheduler and free the server. */
+int hp_server_destroy(hp_server *server);
+
+/* Monotonic clock of the completion times, in nanoseconds. */
+int64_t hp_clock_ns(void);
 
 #ifdef __cplusplus
 }

@@ -12,7 +12,7 @@ import os
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libhullprep.so")
 
-HP_OK, HP_EINVAL, HP_ERANGE, HP_ECAPACITY, HP_EDEVICE, HP_ENOMEM = 0, -1, -2, -3, -4, -5
+HP_OK, HP_EINVAL, HP_ERANGE, HP_ECAPACITY, HP_EDEVICE, HP_ENOMEM, HP_ETIMEOUT = 0, -1, -2, -3, -4, -5, -6
 HP_P_MAX = 2147483646
 HP_INFO_STATUS, HP_INFO_K, HP_INFO_S, HP_INFO_H, HP_INFO_WORDS = 0, 1, 2, 3, 4
 HP_STRATEGY_AUTO, HP_STRATEGY_LDS, HP_STRATEGY_GLOBAL, HP_STRATEGY_LDS_PARTIAL = 0, 1, 2, 3
@@ -51,6 +51,14 @@ SIGNATURES = {
     "hp_batched_run_percloud": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz,
                                                _vp]),
     "hp_plan_destroy": (None, [_vp]),
+    "hp_server_create": (ctypes.c_int, [_sz, _i32, ctypes.POINTER(_vp)]),
+    "hp_server_request_bytes": (ctypes.c_int, [_i64, _i32, _i32, _szp]),
+    "hp_server_submit": (ctypes.c_int, [_vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp, _i32, _vp, _vp, _vp,
+                                        _i64p]),
+    "hp_server_wait": (ctypes.c_int, [_vp, _i64, _i64, _i64p]),
+    "hp_server_stats": (ctypes.c_int, [_vp, _i64p]),
+    "hp_server_destroy": (ctypes.c_int, [_vp]),
+    "hp_clock_ns": (_i64, []),
 }
 
 

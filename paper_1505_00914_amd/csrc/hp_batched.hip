@@ -1,20 +1,19 @@
-// hp_batched.hip -- plans and runs for batches of ragged point clouds.
+// hp_batched.hip -- batches of ragged point clouds: the shared work tables
+// (hp_batch.h) and the recorded plan (hp_plan_*).
 //
 // A plan fixes, once, everything that depends only on the cloud sizes: each
 // cloud's reduce mode and chunks, its hull-tree shape, its workspace slots
-// and its output offsets, plus the work tables of every launch.  A run is a
+// and its output offsets, plus the work lists of every launch.  A run is a
 // fixed sequence of wide launches over all clouds (fill, one persistent
-// reduce, slab tiles with their level-2 hulls, upper hull levels, per-cloud
-// root, chain write), recorded once
-// into a HIP graph and replayed; the graph is re-recorded only when the
-// caller's buffers change.
+// reduce, slab tiles with their level-2 hulls, upper node levels, per-cloud
+// root, chain write), recorded once into a HIP graph and replayed; the
+// graph is re-recorded only when the caller's buffers change.
 #include <algorithm>
 #include <cstring>
 #include <new>
 #include <vector>
 
-#include "hp_host.h"
-#include "hp_kernels.h"
+#include "hp_batch.h"
 
 namespace hp {
 
@@ -25,147 +24,204 @@ namespace {
 // within [2^16, 2^20] so the persistent grid still balances.
 constexpr int64_t kChunkMin = 1 << 16, kChunkMax = 1 << 20;
 int64_t chunk_for(int32_t p) { return std::min(kChunkMax, std::max(kChunkMin, 64 * (int64_t)p)); }
-constexpr int32_t kBatchPMax = 65536;    // largest p a batched cloud may have
-
-size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
-
-struct CloudSlots {
-  size_t ctl, slab_k, slab_s, slab_off, Lm, cand, keep, ccount;
-};
 
 }  // namespace
+
+CloudSlots cloud_slots(int32_t p, const TreeShape &T) {
+  CloudSlots S;
+  size_t o = 0;
+  S.slab_k = o;   o = align256(o + sizeof(int32_t) * (size_t)T.size[1]);
+  S.slab_s = o;   o = align256(o + sizeof(int32_t) * (size_t)T.size[1]);
+  S.slab_off = o; o = align256(o + sizeof(int32_t) * (size_t)T.size[1]);
+  S.Lm = o;       o = align256(o + sizeof(int2) * (size_t)p);
+  S.cand = o;     o = align256(o + sizeof(int2) * 4 * (size_t)p);
+  S.ccount = o;   o = align256(o + sizeof(int32_t) * 2 * (size_t)T.nodes);
+  S.total = o;
+  return S;
+}
+
+BCloud make_bcloud(int32_t p, const TreeShape &T, char *base, const CloudSlots &S, const CloudOut &o) {
+  BCloud c;
+  memset(&c, 0, sizeof(c));
+  c.p = p;
+  c.tree = T;
+  c.Lm = reinterpret_cast<int2 *>(base + S.Lm);
+  c.mask = o.mask;
+  c.slab_k = reinterpret_cast<int32_t *>(base + S.slab_k);
+  c.slab_s = reinterpret_cast<int32_t *>(base + S.slab_s);
+  c.slab_off = reinterpret_cast<int32_t *>(base + S.slab_off);
+  c.cand = reinterpret_cast<int2 *>(base + S.cand);
+  c.ccount = reinterpret_cast<int32_t *>(base + S.ccount);
+  c.cx = o.cx;
+  c.clo = o.clo;
+  c.chi = o.chi;
+  c.chain_cap = o.chain_cap;
+  c.hx = o.hx;
+  c.hy = o.hy;
+  c.hull_cap = o.hull_cap;
+  c.info = o.info;
+  return c;
+}
+
+void BatchTables::clear() {
+  B = 0;
+  maxlev = 1;
+  pmax_lds = 1;
+  items.clear();
+  needs_fill.clear();
+  tiles.clear();
+  chain.clear();
+  for (auto &v : nodes)
+    for (auto &w : v) w.clear();
+}
+
+void BatchTables::add_cloud(int64_t n, int32_t p, const TreeShape &T, int64_t lds_p_max) {
+  const int32_t b = B++;
+  maxlev = std::max(maxlev, T.nlev);
+  // reduce: a dense cloud (n >= 4p, L fits in LDS) goes through LDS, whole
+  // when it fits one item, else in chunks merged by atomics; a sparse cloud
+  // folds straight into its L in device memory
+  const bool dense = (int64_t)p <= lds_p_max && n >= 4 * (int64_t)p;
+  uint8_t fill = 1;
+  if (n > 0) {
+    const int64_t chunk = chunk_for(p);
+    if (dense && n <= chunk) {
+      items.push_back(HostItem{b, 0, 0, n});
+      fill = 0;
+    } else {
+      for (int64_t s0 = 0; s0 < n; s0 += chunk)
+        items.push_back(HostItem{b, dense ? 1 : 2, s0, std::min(chunk, n - s0)});
+    }
+    if (dense) pmax_lds = std::max(pmax_lds, p);
+  }
+  needs_fill.push_back(fill);
+  const int sm = p < (1 << 15) ? 1 : 0;
+  for (int j = 0; j < T.size[1]; ++j) chain.push_back(make_int2(b, j));
+  for (int j = 0; j * kFanIn < T.size[1]; ++j) tiles.push_back(make_int2(b, j));
+  for (int lev = 3; lev <= T.nlev; ++lev)
+    for (int q = 0; q < T.size[lev]; ++q)
+      for (int side = 0; side < 2; ++side) nodes[sm][lev].push_back(make_int4(b, q, side, 0));
+}
+
+size_t BatchTables::cloud_image_bound(int64_t n, int32_t p, const TreeShape &T) {
+  const int64_t nitems = n / chunk_for(p) + 2;
+  int64_t nnodes = 0;
+  for (int lev = 3; lev <= T.nlev; ++lev) nnodes += 2 * (int64_t)T.size[lev];
+  return sizeof(BCloud) + 1 + sizeof(BatchItem) * (size_t)nitems + sizeof(int2) * (size_t)T.size[1] * 2 +
+         sizeof(int4) * (size_t)nnodes;
+}
+
+void BatchTables::sort_items() {
+  std::stable_sort(items.begin(), items.end(),
+                   [](const HostItem &a, const HostItem &c) { return a.count > c.count; });
+}
+
+namespace {
+
+struct ImageLayout {
+  size_t clouds, fill, counter, items, tiles, chain, nodes[2][kMaxLevels + 1], total;
+};
+
+ImageLayout image_layout(const BatchTables &t) {
+  ImageLayout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { const size_t at = o; o = align256(o + std::max<size_t>(bytes, 1)); return at; };
+  L.clouds = take(sizeof(BCloud) * (size_t)t.B);
+  L.fill = take(t.needs_fill.size());
+  L.counter = take(sizeof(int32_t));
+  L.items = take(sizeof(BatchItem) * t.items.size());
+  L.tiles = take(sizeof(int2) * t.tiles.size());
+  L.chain = take(sizeof(int2) * t.chain.size());
+  for (int sm = 0; sm < 2; ++sm)
+    for (int lev = 0; lev <= kMaxLevels; ++lev) L.nodes[sm][lev] = take(sizeof(int4) * t.nodes[sm][lev].size());
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+size_t batch_image_bytes(const BatchTables &t) { return image_layout(t).total; }
+
+void batch_image(const BatchTables &t, const std::vector<BCloud> &clouds,
+                 const std::vector<const int32_t *> &cloud_pts, char *host, char *dev, DeviceBatch &D) {
+  const ImageLayout L = image_layout(t);
+  memset(host, 0, L.total);
+  memcpy(host + L.clouds, clouds.data(), sizeof(BCloud) * (size_t)t.B);
+  memcpy(host + L.fill, t.needs_fill.data(), t.needs_fill.size());
+  BatchItem *it = reinterpret_cast<BatchItem *>(host + L.items);
+  for (size_t i = 0; i < t.items.size(); ++i) {
+    const HostItem &h = t.items[i];
+    it[i].pts = cloud_pts[h.cloud] + 2 * h.offset;
+    it[i].count = h.count;
+    it[i].cloud = h.cloud;
+    it[i].mode = h.mode;
+  }
+  memcpy(host + L.tiles, t.tiles.data(), sizeof(int2) * t.tiles.size());
+  memcpy(host + L.chain, t.chain.data(), sizeof(int2) * t.chain.size());
+  D.B = t.B;
+  D.clouds = reinterpret_cast<BCloud *>(dev + L.clouds);
+  D.needs_fill = reinterpret_cast<uint8_t *>(dev + L.fill);
+  D.counter = reinterpret_cast<int32_t *>(dev + L.counter);
+  D.items = reinterpret_cast<BatchItem *>(dev + L.items);
+  D.nitems = (int32_t)t.items.size();
+  D.tiles = reinterpret_cast<int2 *>(dev + L.tiles);
+  D.ntiles = (int32_t)t.tiles.size();
+  D.chain = reinterpret_cast<int2 *>(dev + L.chain);
+  D.nchain = (int32_t)t.chain.size();
+  for (int sm = 0; sm < 2; ++sm)
+    for (int lev = 0; lev <= kMaxLevels; ++lev) {
+      memcpy(host + L.nodes[sm][lev], t.nodes[sm][lev].data(), sizeof(int4) * t.nodes[sm][lev].size());
+      D.nodes[sm][lev] = reinterpret_cast<int4 *>(dev + L.nodes[sm][lev]);
+      D.nnodes[sm][lev] = (int32_t)t.nodes[sm][lev].size();
+    }
+  D.maxlev = t.maxlev;
+  const DeviceInfo &I = device_info();
+  D.lds_bytes = sizeof(int2) * ((size_t)t.pmax_lds + 1);
+  const int per_cu = std::max<int>(1, std::min<int>(2, (int)((size_t)(I.lds_bytes - 64) / D.lds_bytes)));
+  D.reduce_grid = I.cus * per_cu;
+}
+
+hipError_t enqueue_batch(const DeviceBatch &D, hipStream_t s) {
+  if (D.B == 0) return hipSuccess;
+  hipError_t e = launch_b_fill(D.B, D.clouds, D.needs_fill, D.counter, s);
+  if (e != hipSuccess) return e;
+  e = launch_b_reduce(D.reduce_grid, D.lds_bytes, D.items, D.nitems, D.counter, D.clouds, s);
+  if (e != hipSuccess) return e;
+  e = launch_b_tiles(D.ntiles, D.tiles, D.clouds, s);
+  if (e != hipSuccess) return e;
+  for (int lev = 3; lev <= D.maxlev; ++lev)
+    for (int sm = 0; sm < 2; ++sm) {
+      e = launch_b_nodes(sm == 1, lev, D.nnodes[sm][lev], D.nodes[sm][lev], D.clouds, s);
+      if (e != hipSuccess) return e;
+    }
+  e = launch_b_root(D.B, D.clouds, s);
+  if (e != hipSuccess) return e;
+  return launch_b_chain(D.nchain, D.chain, D.clouds, s);
+}
 
 }  // namespace hp
 
 struct hp_plan {
   int32_t B = 0;
-  std::vector<int64_t> off;        // B+1
-  std::vector<int32_t> p;          // B
-  std::vector<hp::TreeShape> tree; // B
-  std::vector<hp::CloudSlots> slot;
+  std::vector<int64_t> off;          // B+1
+  std::vector<int32_t> p;            // B
+  std::vector<hp::TreeShape> tree;   // B
+  std::vector<hp::CloudSlots> slot;  // B
+  std::vector<size_t> slot_base;     // B: byte offset of each cloud's slots in the workspace
   std::vector<int64_t> chain_off, hull_off;  // B+1
-  std::vector<uint8_t> needs_fill;
-  std::vector<hp::BatchItem> items;
-  int maxlev = 1;
-  std::vector<int2> tiles;         // (cloud, tile of 64 slabs)
-  std::vector<int4> nodes[2][hp::kMaxLevels + 1];  // [small?][level >= 3] (cloud, node, side, 0)
-  std::vector<int2> chain_work;    // (cloud, slab)
+  hp::BatchTables tables;
   size_t ws_batched = 0, ws_single = 0;
-  size_t lds_bytes = 0;
-  int reduce_grid = 1;
-  // device copies
-  void *dmem = nullptr;
-  hp::BatchItem *d_items = nullptr;
-  uint8_t *d_needs_fill = nullptr;
-  int32_t *d_counter = nullptr;
-  hp::FinishArgs *d_fa = nullptr;
-  hp::HullArgs *d_ha = nullptr;
-  int2 *d_tiles = nullptr;
-  int4 *d_nodes[2][hp::kMaxLevels + 1] = {};
-  int2 *d_chain = nullptr;
+  // device image of the tables (rewritten when the buffers change)
+  size_t image_bytes = 0;
+  void *dimage = nullptr;
+  std::vector<char> himage;
+  hp::DeviceBatch dev;
   // graph state
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   const void *bound[8] = {};
 };
-
-namespace hp {
-
-namespace {
-
-int fail_plan(hp_plan *P, int code) {
-  hp_plan_destroy(P);
-  return code;
-}
-
-// Fill the per-cloud argument blocks for the given buffers.
-void build_args(const hp_plan *P, const int32_t *pts, int32_t *cx, int32_t *clo, int32_t *chi,
-                int32_t *hx, int32_t *hy, int32_t *info, char *ws, std::vector<FinishArgs> &fa,
-                std::vector<HullArgs> &ha) {
-  (void)pts;
-  fa.assign(P->B, FinishArgs());
-  ha.assign(P->B, HullArgs());
-  for (int b = 0; b < P->B; ++b) {
-    const CloudSlots &S = P->slot[b];
-    const int32_t p = P->p[b];
-    const TreeShape &T = P->tree[b];
-    FinishArgs A;
-    memset(&A, 0, sizeof(A));
-    int2 *Lm = reinterpret_cast<int2 *>(ws + S.Lm);
-    A.part = Lm;
-    A.G = 1;
-    A.positions = p;
-    A.p = p;
-    A.Lm = Lm;
-    A.slab_k = reinterpret_cast<int32_t *>(ws + S.slab_k);
-    A.slab_s = reinterpret_cast<int32_t *>(ws + S.slab_s);
-    A.slab_off = reinterpret_cast<int32_t *>(ws + S.slab_off);
-    A.do_hull = 1;
-    A.cand = reinterpret_cast<int2 *>(ws + S.cand);
-    A.ccount = reinterpret_cast<int32_t *>(ws + S.ccount);
-    A.tree = T;
-    A.hx = hx + P->hull_off[b];
-    A.hy = hy + P->hull_off[b];
-    A.hull_cap = (int32_t)(P->hull_off[b + 1] - P->hull_off[b]);
-    A.ctl = reinterpret_cast<int32_t *>(ws + S.ctl);
-    A.info = info + (size_t)HP_INFO_WORDS * b;
-    A.scan_root = T.nlev == 1 ? 1 : 0;
-    A.chain_inline = 1;
-    A.cx_out = cx + P->chain_off[b];
-    A.clo_out = clo + P->chain_off[b];
-    A.chi_out = chi + P->chain_off[b];
-    A.chain_cap = (int32_t)(P->chain_off[b + 1] - P->chain_off[b]);
-    fa[b] = A;
-
-    HullArgs H;
-    memset(&H, 0, sizeof(H));
-    H.buf[0] = A.cand;
-    H.buf[1] = A.cand + 2 * (size_t)p;
-    H.keep = reinterpret_cast<uint8_t *>(ws + S.keep);
-    H.ccount = A.ccount;
-    H.tree = T;
-    H.positions = p;
-    H.hx = A.hx;
-    H.hy = A.hy;
-    H.hull_cap = A.hull_cap;
-    H.info = A.info;
-    H.chain_fused = T.nlev >= 2 ? 1 : 0;
-    H.Lm = Lm;
-    H.p = p;
-    H.slab_k = A.slab_k;
-    H.slab_s = A.slab_s;
-    H.cx = A.cx_out;
-    H.clo = A.clo_out;
-    H.chi = A.chi_out;
-    H.chain_cap = A.chain_cap;
-    ha[b] = H;
-  }
-}
-
-hipError_t enqueue_batched(const hp_plan *P, const int32_t *pts, hipStream_t s) {
-  hipError_t e = launch_b_fill(P->B, P->d_fa, P->d_needs_fill, P->d_counter, s);
-  if (e != hipSuccess) return e;
-  if (!P->items.empty()) {
-    e = launch_b_reduce(P->reduce_grid, P->lds_bytes, pts, P->d_items, (int32_t)P->items.size(),
-                        P->d_counter, P->d_fa, s);
-    if (e != hipSuccess) return e;
-  }
-  e = launch_b_tiles((int)P->tiles.size(), P->d_tiles, P->d_fa, s);
-  if (e != hipSuccess) return e;
-  for (int lev = 3; lev <= P->maxlev; ++lev)
-    for (int sm = 0; sm < 2; ++sm) {
-      e = launch_b_nodes(sm == 1, lev, (int)P->nodes[sm][lev].size(), P->d_nodes[sm][lev], P->d_ha, s);
-      if (e != hipSuccess) return e;
-    }
-  e = launch_b_root(P->B, P->d_fa, P->d_ha, s);
-  if (e != hipSuccess) return e;
-  return launch_b_chain((int)P->chain_work.size(), P->d_chain, P->d_fa, s);
-}
-
-}  // namespace
-
-}  // namespace hp
 
 using namespace hp;
 
@@ -174,8 +230,13 @@ extern "C" void hp_plan_destroy(hp_plan *P) {
   if (P->exec) (void)hipGraphExecDestroy(P->exec);
   if (P->graph) (void)hipGraphDestroy(P->graph);
   if (P->cap) (void)hipStreamDestroy(P->cap);
-  if (P->dmem) (void)hipFree(P->dmem);
+  if (P->dimage) (void)hipFree(P->dimage);
   delete P;
+}
+
+static int fail_plan(hp_plan *P, int code) {
+  hp_plan_destroy(P);
+  return code;
 }
 
 extern "C" int hp_plan_create(const int64_t *offsets, const int32_t *p, int32_t B, hp_plan **out) {
@@ -197,100 +258,32 @@ extern "C" int hp_plan_create(const int64_t *offsets, const int32_t *p, int32_t 
   P->p.assign(p, p + B);
   P->tree.resize(B);
   P->slot.resize(B);
+  P->slot_base.resize(B);
   P->chain_off.assign(B + 1, 0);
   P->hull_off.assign(B + 1, 0);
-  P->needs_fill.assign(B, 1);
 
   const DeviceInfo &D = device_info();
   const int64_t lds_p_max = D.lds_max_p - 8;  // room for the reduce's own words
-  int32_t pmax_lds = 1;
-  size_t o = 0;
-  size_t single_max = 0;
+  size_t o = 0, single_max = 0;
   for (int b = 0; b < B; ++b) {
     const int64_t n = offsets[b + 1] - offsets[b];
-    const int32_t pb = p[b];
-    tree_shape(pb, &P->tree[b]);
-    const TreeShape &T = P->tree[b];
-    P->maxlev = std::max(P->maxlev, T.nlev);
-    CloudSlots &S = P->slot[b];
-    S.ctl = o;      o = align256(o + sizeof(int32_t) * kCtlWords);
-    S.slab_k = o;   o = align256(o + sizeof(int32_t) * (size_t)T.size[1]);
-    S.slab_s = o;   o = align256(o + sizeof(int32_t) * (size_t)T.size[1]);
-    S.slab_off = o; o = align256(o + sizeof(int32_t) * (size_t)T.size[1]);
-    S.Lm = o;       o = align256(o + sizeof(int2) * (size_t)pb);
-    S.cand = o;     o = align256(o + sizeof(int2) * 4 * (size_t)pb);
-    S.keep = o;     o = align256(o + 2 * (size_t)pb);
-    S.ccount = o;   o = align256(o + sizeof(int32_t) * 2 * (size_t)T.nodes);
-    const int64_t cap = std::min<int64_t>(n, pb);
+    tree_shape(p[b], &P->tree[b]);
+    P->slot[b] = cloud_slots(p[b], P->tree[b]);
+    P->slot_base[b] = o;
+    o += P->slot[b].total;
+    const int64_t cap = chain_cap_for(n, p[b]);
     P->chain_off[b + 1] = P->chain_off[b] + cap;
     P->hull_off[b + 1] = P->hull_off[b] + 2 * cap;
-    single_max = std::max(single_max, single_ws_bytes(n, pb));
-
-    // reduce mode and chunks
-    const bool dense = (int64_t)pb <= lds_p_max && n >= 4 * (int64_t)pb;
-    if (n > 0) {
-      const int64_t chunk = chunk_for(pb);
-      if (dense && n <= chunk) {
-        P->items.push_back(BatchItem{b, 0, offsets[b], n, 0});
-        P->needs_fill[b] = 0;
-      } else {
-        for (int64_t s0 = 0; s0 < n; s0 += chunk)
-          P->items.push_back(BatchItem{b, dense ? 1 : 2, offsets[b] + s0, std::min(chunk, n - s0), 0});
-      }
-      if (dense) pmax_lds = std::max(pmax_lds, pb);
-    }
-    // work tables
-    const int sm = pb < (1 << 15) ? 1 : 0;
-    for (int j = 0; j < T.size[1]; ++j) P->chain_work.push_back(make_int2(b, j));
-    for (int j = 0; j * kFanIn < T.size[1]; ++j) P->tiles.push_back(make_int2(b, j));
-    for (int lev = 3; lev <= T.nlev; ++lev)
-      for (int q = 0; q < T.size[lev]; ++q)
-        for (int side = 0; side < 2; ++side) P->nodes[sm][lev].push_back(make_int4(b, q, side, 0));
+    single_max = std::max(single_max, single_ws_bytes(n, p[b]));
+    P->tables.add_cloud(n, p[b], P->tree[b], lds_p_max);
   }
+  P->tables.sort_items();
   P->ws_batched = o;
   P->ws_single = single_max;
-  // longest chunks first, so the persistent reduce ends evenly
-  std::stable_sort(P->items.begin(), P->items.end(),
-                   [](const BatchItem &a, const BatchItem &c) { return a.count > c.count; });
-  P->lds_bytes = sizeof(int2) * ((size_t)pmax_lds + 1);
-  const int per_cu = std::max<int>(1, std::min<int>(2, (int)((size_t)(D.lds_bytes - 64) / P->lds_bytes)));
-  P->reduce_grid = D.cus * per_cu;
-
-  // device tables: one allocation
-  size_t dsz = 0;
-  auto reserve = [&](size_t bytes) { size_t at = dsz; dsz = align256(dsz + std::max<size_t>(bytes, 1)); return at; };
-  const size_t o_items = reserve(sizeof(BatchItem) * P->items.size());
-  const size_t o_fill = reserve(P->needs_fill.size());
-  const size_t o_counter = reserve(sizeof(int32_t));
-  const size_t o_fa = reserve(sizeof(FinishArgs) * (size_t)std::max(1, B));
-  const size_t o_ha = reserve(sizeof(HullArgs) * (size_t)std::max(1, B));
-  size_t o_nodes[2][kMaxLevels + 1];
-  const size_t o_chain = reserve(sizeof(int2) * P->chain_work.size());
-  const size_t o_tiles = reserve(sizeof(int2) * P->tiles.size());
-  for (int sm = 0; sm < 2; ++sm)
-    for (int lev = 0; lev <= kMaxLevels; ++lev) o_nodes[sm][lev] = reserve(sizeof(int4) * P->nodes[sm][lev].size());
-  if (hipMalloc(&P->dmem, dsz) != hipSuccess) return fail_plan(P, set_error(HP_ENOMEM, "device allocation of %zu bytes failed", dsz));
-  char *dm = static_cast<char *>(P->dmem);
-  P->d_items = reinterpret_cast<BatchItem *>(dm + o_items);
-  P->d_needs_fill = reinterpret_cast<uint8_t *>(dm + o_fill);
-  P->d_counter = reinterpret_cast<int32_t *>(dm + o_counter);
-  P->d_fa = reinterpret_cast<FinishArgs *>(dm + o_fa);
-  P->d_ha = reinterpret_cast<HullArgs *>(dm + o_ha);
-  auto up = [&](size_t at, const void *src, size_t bytes) {
-    return bytes == 0 || hipMemcpy(dm + at, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
-  };
-  bool ok = up(o_items, P->items.data(), sizeof(BatchItem) * P->items.size()) &&
-            up(o_fill, P->needs_fill.data(), P->needs_fill.size()) &&
-            up(o_chain, P->chain_work.data(), sizeof(int2) * P->chain_work.size()) &&
-            up(o_tiles, P->tiles.data(), sizeof(int2) * P->tiles.size());
-  P->d_chain = reinterpret_cast<int2 *>(dm + o_chain);
-  P->d_tiles = reinterpret_cast<int2 *>(dm + o_tiles);
-  for (int sm = 0; sm < 2 && ok; ++sm)
-    for (int lev = 0; lev <= kMaxLevels && ok; ++lev) {
-      P->d_nodes[sm][lev] = reinterpret_cast<int4 *>(dm + o_nodes[sm][lev]);
-      ok = up(o_nodes[sm][lev], P->nodes[sm][lev].data(), sizeof(int4) * P->nodes[sm][lev].size());
-    }
-  if (!ok) return fail_plan(P, set_error(HP_EDEVICE, "uploading plan tables failed"));
+  P->image_bytes = batch_image_bytes(P->tables);
+  P->himage.resize(P->image_bytes);
+  if (hipMalloc(&P->dimage, P->image_bytes) != hipSuccess)
+    return fail_plan(P, set_error(HP_ENOMEM, "device allocation of %zu bytes failed", P->image_bytes));
   if (prepare_b_reduce() != hipSuccess) return fail_plan(P, set_error(HP_EDEVICE, "reduce kernel setup failed"));
   if (hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking) != hipSuccess)
     return fail_plan(P, set_error(HP_EDEVICE, "stream creation failed"));
@@ -329,20 +322,34 @@ extern "C" int hp_batched_run(hp_plan *P, const int32_t *pts, int32_t *cx, int32
   hipStream_t s = (hipStream_t)stream;
   const void *now[8] = {pts, cx, clo, chi, hx, hy, info, ws};
   if (!P->exec || memcmp(now, P->bound, sizeof(now)) != 0) {
-    // new buffers: rewrite the argument blocks and re-record the graph (the
-    // caller's earlier runs on this plan must finish reading the old ones)
+    // new buffers: rewrite the device image and re-record the graph (the
+    // caller's earlier runs on this plan must finish reading the old image)
     if (hipStreamSynchronize(s) != hipSuccess) return set_error(HP_EDEVICE, "stream synchronisation failed");
-    std::vector<FinishArgs> fa;
-    std::vector<HullArgs> ha;
-    build_args(P, pts, cx, clo, chi, hx, hy, info, static_cast<char *>(ws), fa, ha);
-    if (hipMemcpy(P->d_fa, fa.data(), sizeof(FinishArgs) * fa.size(), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(P->d_ha, ha.data(), sizeof(HullArgs) * ha.size(), hipMemcpyHostToDevice) != hipSuccess)
-      return set_error(HP_EDEVICE, "uploading argument blocks failed");
+    std::vector<BCloud> clouds(P->B);
+    std::vector<const int32_t *> cpts(P->B);
+    char *wsb = static_cast<char *>(ws);
+    for (int b = 0; b < P->B; ++b) {
+      CloudOut o;
+      o.cx = cx + P->chain_off[b];
+      o.clo = clo + P->chain_off[b];
+      o.chi = chi + P->chain_off[b];
+      o.chain_cap = (int32_t)(P->chain_off[b + 1] - P->chain_off[b]);
+      o.hx = hx + P->hull_off[b];
+      o.hy = hy + P->hull_off[b];
+      o.hull_cap = (int32_t)(P->hull_off[b + 1] - P->hull_off[b]);
+      o.info = info + (size_t)HP_INFO_WORDS * b;
+      o.mask = nullptr;
+      clouds[b] = make_bcloud(P->p[b], P->tree[b], wsb + P->slot_base[b], P->slot[b], o);
+      cpts[b] = pts ? pts + 2 * P->off[b] : nullptr;
+    }
+    batch_image(P->tables, clouds, cpts, P->himage.data(), static_cast<char *>(P->dimage), P->dev);
+    if (hipMemcpy(P->dimage, P->himage.data(), P->image_bytes, hipMemcpyHostToDevice) != hipSuccess)
+      return set_error(HP_EDEVICE, "uploading the batch tables failed");
     if (P->exec) { (void)hipGraphExecDestroy(P->exec); P->exec = nullptr; }
     if (P->graph) { (void)hipGraphDestroy(P->graph); P->graph = nullptr; }
     if (hipStreamBeginCapture(P->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
       return set_error(HP_EDEVICE, "graph capture could not start");
-    const hipError_t e = enqueue_batched(P, pts, P->cap);
+    const hipError_t e = enqueue_batch(P->dev, P->cap);
     hipGraph_t g = nullptr;
     const hipError_t e2 = hipStreamEndCapture(P->cap, &g);
     if (e != hipSuccess || e2 != hipSuccess || !g) {

@@ -203,6 +203,7 @@ extern "C" const char *hp_status_string(int code) {
     case HP_ECAPACITY: return "HP_ECAPACITY: output or workspace too small";
     case HP_EDEVICE: return "HP_EDEVICE: HIP call failed";
     case HP_ENOMEM: return "HP_ENOMEM: allocation failed";
+    case HP_ETIMEOUT: return "HP_ETIMEOUT: not completed yet";
     default: return "unknown status";
   }
 }

@@ -58,17 +58,16 @@ struct TreeShape;
 void tree_shape(int64_t positions, TreeShape *out);
 
 // Batched launch steps (defined in hp_single.hip).
-struct FinishArgs;
-struct HullArgs;
 struct BatchItem;
-hipError_t launch_b_fill(int B, const FinishArgs *fa, const uint8_t *needs_fill, int32_t *counter,
+struct BCloud;
+hipError_t launch_b_fill(int B, const BCloud *cl, const uint8_t *needs_fill, int32_t *counter,
                          hipStream_t s);
-hipError_t prepare_b_reduce();  // raise the dynamic LDS limit (before capture)
-hipError_t launch_b_reduce(int grid, size_t lds_bytes, const int32_t *pts, const BatchItem *items,
-                           int32_t nitems, int32_t *counter, const FinishArgs *fa, hipStream_t s);
-hipError_t launch_b_tiles(int ntiles, const int2 *tiles, const FinishArgs *fa, hipStream_t s);
-hipError_t launch_b_nodes(bool small, int lev, int nwork, const int4 *work, const HullArgs *ha,
+hipError_t prepare_b_reduce();
+hipError_t launch_b_reduce(int grid, size_t lds_bytes, const BatchItem *items, int32_t nitems,
+                           int32_t *counter, const BCloud *cl, hipStream_t s);
+hipError_t launch_b_tiles(int ntiles, const int2 *tiles, const BCloud *cl, hipStream_t s);
+hipError_t launch_b_nodes(bool small, int lev, int nwork, const int4 *work, const BCloud *cl,
                           hipStream_t s);
-hipError_t launch_b_root(int B, const FinishArgs *fa, const HullArgs *ha, hipStream_t s);
-hipError_t launch_b_chain(int nwork, const int2 *work, const FinishArgs *fa, hipStream_t s);
+hipError_t launch_b_root(int B, const BCloud *cl, hipStream_t s);
+hipError_t launch_b_chain(int nwork, const int2 *work, const BCloud *cl, hipStream_t s);
 }  // namespace hp

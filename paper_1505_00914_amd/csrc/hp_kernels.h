@@ -159,12 +159,29 @@ struct HullArgs {
 };
 
 // One chunk of a batched reduce.
+// Batched form: one work item of the persistent reduce.
 struct BatchItem {
-  int32_t cloud;
-  int32_t mode;     // 0: whole cloud in LDS, 1: LDS + atomic merge, 2: global atomics
-  int64_t start;    // first point (index into the concatenated points)
-  int64_t count;
-  int64_t pad;
+  const int32_t *pts;  // first point of the item (device)
+  int64_t count;       // points in the item
+  int32_t cloud;       // index into the cloud table
+  int32_t mode;        // 0: whole cloud in LDS, 1: LDS + atomic merge, 2: global atomics
+};
+
+// Batched form: everything the kernels need about one cloud.  All pointers
+// are device memory; cand holds [2 levels][2 sides][p] candidate points.
+struct BCloud {
+  int32_t p;
+  TreeShape tree;
+  int2 *Lm;                       // p pairs
+  uint64_t *mask;                 // optional M export
+  int32_t *slab_k, *slab_s, *slab_off;
+  int2 *cand;
+  int32_t *ccount;                // [2 sides][tree nodes]
+  int32_t *cx, *clo, *chi;        // chain
+  int32_t chain_cap;
+  int32_t *hx, *hy;               // hull
+  int32_t hull_cap;
+  int32_t *info;                  // HP_INFO_WORDS words
 };
 
 }  // namespace hp

@@ -1,0 +1,514 @@
+// hp_serve.hip -- the served form: independent requests (one cloud each)
+// joined into batches by a scheduler thread (continuous batching).
+//
+// Admission: every request needs one block of the server's device arena
+// (its points when they come from the host, its workspace slots, its device
+// outputs and info words).  The arena is allocated once, at creation, with
+// the caller's budget; a request waits in FIFO order until its block fits.
+//
+// Scheduling: up to kSlots batches are in flight.  Whenever a slot is free
+// and requests are waiting, the thread admits as many as fit (at most
+// max_batch), copies their points and the batch's work tables to the device
+// on the copy stream and, once those copies are done, runs on the compute
+// stream one batched launch sequence for the small requests and the
+// single-cloud sequence for each request of at least kServeSingleN points
+// (which fills the device by itself); every request's outputs are then
+// copied back into the caller's host buffers behind them.  A batch completes when its last copy
+// has landed; its requests are then marked done with the completion time
+// and their blocks return to the arena.  Copies of the next batch overlap
+// the kernels of the current one.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "hp_arena.h"
+#include "hp_batch.h"
+
+namespace hp {
+
+namespace {
+
+constexpr int kSlots = 4;                   // batches in flight
+constexpr size_t kTableBytes = 8u << 20;    // work-table image capacity of one batch
+// Requests with at least this many points run the single-cloud launch
+// sequence, which spreads one cloud over the whole device; smaller ones
+// share one batched launch sequence.
+constexpr int64_t kServeSingleN = 1 << 18;
+
+int64_t now_ns() {
+  return std::chrono::duration_cast<std::chrono::nanoseconds>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+struct Request {
+  int64_t id = 0;
+  int64_t n = 0;
+  int32_t p = 1;
+  const int32_t *pts = nullptr;
+  bool on_device = false;
+  int32_t *cx = nullptr, *clo = nullptr, *chi = nullptr, *hx = nullptr, *hy = nullptr, *info = nullptr;
+  int32_t cap = 0;               // chain capacity min(n, p); the hull has 2 cap
+  bool single = false;           // runs the single-cloud launch sequence
+  TreeShape tree;
+  CloudSlots slots;              // batched workspace (single: one workspace of ws_bytes)
+  size_t ws_bytes = 0;
+  size_t o_pts = 0, o_slots = 0, o_chain = 0, o_hull = 0, o_info = 0, bytes = 0;
+  size_t table_bound = 0;
+  size_t block = Arena::kFail;
+  hipEvent_t ev = nullptr;       // recorded after the request's last output copy
+  bool done = false;
+  int64_t done_ns = 0;
+};
+
+using RequestPtr = std::shared_ptr<Request>;
+
+struct Slot {
+  bool busy = false;
+  std::vector<RequestPtr> reqs;  // in the order their events are recorded
+  size_t head = 0;               // reqs[0, head) have completed and are not touched again
+  std::vector<hipEvent_t> events;  // taken from the pool for this batch
+  char *himg = nullptr;          // pinned host image of the work tables
+  void *dimg = nullptr;          // its device copy
+};
+
+}  // namespace
+
+}  // namespace hp
+
+struct hp_server {
+  int device = 0;
+  size_t budget = 0;
+  int32_t max_batch = 1;
+  int64_t lds_p_max = 1;
+  hp::Arena arena;
+  char *dmem = nullptr;
+  hipStream_t copy = nullptr, comp = nullptr;
+  hp::Slot slot[hp::kSlots];
+  std::vector<hipEvent_t> ev_pool;   // used by the scheduler thread only
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<hp::RequestPtr> pending;
+  std::unordered_map<int64_t, hp::RequestPtr> live;   // submitted and not yet waited for
+  int64_t next_id = 0;
+  bool stop = false;
+  std::thread thread;
+  // statistics
+  int64_t batches = 0, served = 0, peak_in_use = 0, batched_requests = 0;
+};
+
+namespace hp {
+
+namespace {
+
+void layout_request(Request &r) {
+  tree_shape(r.p, &r.tree);
+  r.single = r.n >= kServeSingleN;
+  r.slots = cloud_slots(r.p, r.tree);
+  r.ws_bytes = r.single ? align256(single_ws_bytes(r.n, r.p)) : r.slots.total;
+  r.cap = (int32_t)chain_cap_for(r.n, r.p);
+  size_t o = 0;
+  r.o_pts = o;
+  if (!r.on_device) o = align256(o + 8 * (size_t)r.n);
+  r.o_slots = o;
+  o += r.ws_bytes;
+  r.o_chain = o;
+  o = align256(o + 3 * sizeof(int32_t) * (size_t)r.cap);
+  r.o_hull = o;
+  o = align256(o + 4 * sizeof(int32_t) * (size_t)r.cap);
+  r.o_info = o;
+  o = align256(o + sizeof(int32_t) * HP_INFO_WORDS);
+  r.bytes = o;
+  r.table_bound = r.single ? 0 : BatchTables::cloud_image_bound(r.n, r.p, r.tree);
+}
+
+// Mark one request done and return its block.  Called with the lock held.
+void finish(hp_server *S, Request *r, int status, int64_t t) {
+  if (status != HP_OK) r->info[HP_INFO_STATUS] = status;
+  r->done = true;
+  r->done_ns = t;
+  S->arena.release(r->block);
+  r->block = Arena::kFail;
+  ++S->served;
+}
+
+// Free a slot whose requests are all done: its events go back to the pool.
+void release_slot(hp_server *S, Slot &sl) {
+  for (hipEvent_t e : sl.events) S->ev_pool.push_back(e);
+  sl.events.clear();
+  sl.reqs.clear();
+  sl.head = 0;
+  sl.busy = false;
+}
+
+// Complete the requests of a slot whose events have fired (in recording
+// order).  Called with the lock held; returns true if any completed.
+bool poll_slot(hp_server *S, Slot &sl, bool &busy) {
+  bool any = false;
+  const int64_t t = now_ns();
+  while (sl.head < sl.reqs.size()) {
+    Request *r = sl.reqs[sl.head].get();
+    const hipError_t q = hipEventQuery(r->ev);
+    if (q == hipErrorNotReady) break;
+    finish(S, r, q == hipSuccess ? HP_OK : HP_EDEVICE, t);
+    ++sl.head;
+    any = true;
+  }
+  if (any) S->cv_done.notify_all();
+  if (sl.head == sl.reqs.size()) release_slot(S, sl);
+  else busy = true;
+  return any;
+}
+
+hipEvent_t pool_event(hp_server *S, Slot &sl) {
+  hipEvent_t e = nullptr;
+  if (!S->ev_pool.empty()) {
+    e = S->ev_pool.back();
+    S->ev_pool.pop_back();
+  } else if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+    return nullptr;
+  }
+  sl.events.push_back(e);
+  return e;
+}
+
+// Copies and launches for the requests in `take` (blocks already
+// allocated).  Runs without the lock, on the scheduler thread.  The small
+// requests' points and the work tables are copied first and computed in one
+// batched launch sequence; each large request then waits only for its own
+// points and runs the single-cloud sequence.  Every request's outputs are
+// copied back right behind its own kernels, and its event recorded, so it
+// completes independently of the rest of the batch.  Reorders `take` into
+// event order.
+hipError_t issue(hp_server *S, Slot &sl, std::vector<RequestPtr> &take) {
+  std::stable_partition(take.begin(), take.end(), [](const RequestPtr &r) { return !r->single; });
+  BatchTables t;
+  std::vector<BCloud> clouds;
+  std::vector<const int32_t *> cpts;
+  std::vector<const int32_t *> dpts(take.size());
+  hipError_t e = hipSuccess;
+  auto outputs = [&](Request &r) {
+    char *base = S->dmem + r.block;
+    CloudOut o;
+    int32_t *chain = reinterpret_cast<int32_t *>(base + r.o_chain);
+    int32_t *hull = reinterpret_cast<int32_t *>(base + r.o_hull);
+    o.cx = chain;
+    o.clo = chain + r.cap;
+    o.chi = chain + 2 * (size_t)r.cap;
+    o.chain_cap = r.cap;
+    o.hx = hull;
+    o.hy = hull + 2 * (size_t)r.cap;
+    o.hull_cap = 2 * r.cap;
+    o.info = reinterpret_cast<int32_t *>(base + r.o_info);
+    o.mask = nullptr;
+    return o;
+  };
+  auto copy_in = [&](size_t b) -> hipError_t {
+    Request &r = *take[b];
+    if (r.on_device) {
+      dpts[b] = r.pts;
+      return hipSuccess;
+    }
+    int32_t *dst = reinterpret_cast<int32_t *>(S->dmem + r.block + r.o_pts);
+    dpts[b] = dst;
+    if (r.n == 0) return hipSuccess;
+    return hipMemcpyAsync(dst, r.pts, 8 * (size_t)r.n, hipMemcpyHostToDevice, S->copy);
+  };
+  auto copy_out = [&](Request &r) -> hipError_t {
+    const char *base = S->dmem + r.block;
+    const int32_t *chain = reinterpret_cast<const int32_t *>(base + r.o_chain);
+    const int32_t *hull = reinterpret_cast<const int32_t *>(base + r.o_hull);
+    const size_t c = sizeof(int32_t) * (size_t)r.cap;
+    hipError_t x = hipSuccess;
+    if (r.cap > 0) {
+      if ((x = hipMemcpyAsync(r.cx, chain, c, hipMemcpyDeviceToHost, S->comp)) != hipSuccess) return x;
+      if ((x = hipMemcpyAsync(r.clo, chain + r.cap, c, hipMemcpyDeviceToHost, S->comp)) != hipSuccess) return x;
+      if ((x = hipMemcpyAsync(r.chi, chain + 2 * (size_t)r.cap, c, hipMemcpyDeviceToHost, S->comp)) != hipSuccess) return x;
+      if ((x = hipMemcpyAsync(r.hx, hull, 2 * c, hipMemcpyDeviceToHost, S->comp)) != hipSuccess) return x;
+      if ((x = hipMemcpyAsync(r.hy, hull + 2 * (size_t)r.cap, 2 * c, hipMemcpyDeviceToHost, S->comp)) != hipSuccess) return x;
+    }
+    return hipMemcpyAsync(r.info, base + r.o_info, sizeof(int32_t) * HP_INFO_WORDS, hipMemcpyDeviceToHost, S->comp);
+  };
+  // small requests: points, tables, one batched launch, outputs, one event
+  size_t nsmall = 0;
+  while (nsmall < take.size() && !take[nsmall]->single) {
+    Request &r = *take[nsmall];
+    if ((e = copy_in(nsmall)) != hipSuccess) return e;
+    t.add_cloud(r.n, r.p, r.tree, S->lds_p_max);
+    clouds.push_back(make_bcloud(r.p, r.tree, S->dmem + r.block + r.o_slots, r.slots, outputs(r)));
+    cpts.push_back(dpts[nsmall]);
+    ++nsmall;
+  }
+  if (nsmall > 0) {
+    t.sort_items();
+    const size_t img = batch_image_bytes(t);
+    if (img > kTableBytes) return hipErrorInvalidValue;   // excluded by admission
+    DeviceBatch D;
+    batch_image(t, clouds, cpts, sl.himg, static_cast<char *>(sl.dimg), D);
+    if ((e = hipMemcpyAsync(sl.dimg, sl.himg, img, hipMemcpyHostToDevice, S->copy)) != hipSuccess) return e;
+    hipEvent_t copied = pool_event(S, sl), done = pool_event(S, sl);
+    if (!copied || !done) return hipErrorOutOfMemory;
+    if ((e = hipEventRecord(copied, S->copy)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(S->comp, copied, 0)) != hipSuccess) return e;
+    if ((e = enqueue_batch(D, S->comp)) != hipSuccess) return e;
+    for (size_t b = 0; b < nsmall; ++b)
+      if ((e = copy_out(*take[b])) != hipSuccess) return e;
+    if ((e = hipEventRecord(done, S->comp)) != hipSuccess) return e;
+    for (size_t b = 0; b < nsmall; ++b) take[b]->ev = done;
+  }
+  // large requests, each behind its own copy
+  for (size_t b = nsmall; b < take.size(); ++b) {
+    Request &r = *take[b];
+    if ((e = copy_in(b)) != hipSuccess) return e;
+    hipEvent_t copied = pool_event(S, sl), done = pool_event(S, sl);
+    if (!copied || !done) return hipErrorOutOfMemory;
+    if ((e = hipEventRecord(copied, S->copy)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(S->comp, copied, 0)) != hipSuccess) return e;
+    const CloudOut o = outputs(r);
+    if (run_single(dpts[b], r.n, r.p, nullptr, nullptr, nullptr, o.cx, o.clo, o.chi, o.chain_cap, o.hx, o.hy,
+                   o.hull_cap, o.info, S->dmem + r.block + r.o_slots, r.ws_bytes, S->comp, true) != HP_OK)
+      return hipErrorLaunchFailure;
+    if ((e = copy_out(r)) != hipSuccess) return e;
+    if ((e = hipEventRecord(done, S->comp)) != hipSuccess) return e;
+    r.ev = done;
+  }
+  return hipSuccess;
+}
+
+// Admit the waiting requests that fit (FIFO, stop at the first that does
+// not) into a free slot and issue them.  Called with the lock held; drops
+// it around the device calls.  Returns true if a batch was issued.
+bool launch(hp_server *S, Slot &sl, std::unique_lock<std::mutex> &lk) {
+  std::vector<RequestPtr> take;
+  size_t table = BatchTables::kImageSlack;
+  while (!S->pending.empty() && (int32_t)take.size() < S->max_batch) {
+    const RequestPtr &r = S->pending.front();
+    if (table + r->table_bound > kTableBytes) break;
+    const size_t at = S->arena.alloc(r->bytes);
+    if (at == Arena::kFail) break;
+    r->block = at;
+    table += r->table_bound;
+    take.push_back(r);
+    S->pending.pop_front();
+  }
+  if (take.empty()) return false;
+  S->peak_in_use = std::max<int64_t>(S->peak_in_use, (int64_t)S->arena.in_use());
+  sl.busy = true;
+  ++S->batches;
+  S->batched_requests += (int64_t)take.size();
+  lk.unlock();
+  const hipError_t e = issue(S, sl, take);
+  if (e != hipSuccess) {
+    // nothing of this batch may still touch its blocks when they are freed
+    (void)hipStreamSynchronize(S->copy);
+    (void)hipStreamSynchronize(S->comp);
+  }
+  lk.lock();
+  sl.reqs = take;
+  sl.head = 0;
+  if (e != hipSuccess) {
+    const int64_t t = now_ns();
+    for (const RequestPtr &r : take) finish(S, r.get(), HP_EDEVICE, t);
+    S->cv_done.notify_all();
+    release_slot(S, sl);
+  }
+  return true;
+}
+
+void serve_loop(hp_server *S) {
+  (void)hipSetDevice(S->device);
+  std::unique_lock<std::mutex> lk(S->mu);
+  for (;;) {
+    bool progressed = false, busy = false;
+    for (Slot &sl : S->slot)
+      if (sl.busy && poll_slot(S, sl, busy)) progressed = true;
+    for (Slot &sl : S->slot) {
+      if (sl.busy || S->pending.empty()) continue;
+      if (launch(S, sl, lk)) {
+        progressed = true;
+        busy = true;
+      }
+    }
+    if (progressed) continue;
+    if (S->stop && S->pending.empty() && !busy) break;
+    if (busy) {
+      lk.unlock();
+      std::this_thread::yield();
+      lk.lock();
+    } else {
+      S->cv_work.wait(lk, [&] { return S->stop || !S->pending.empty(); });
+    }
+  }
+}
+
+}  // namespace
+
+}  // namespace hp
+
+using namespace hp;
+
+extern "C" int hp_server_destroy(hp_server *S) {
+  if (!S) return HP_OK;
+  if (S->thread.joinable()) {
+    {
+      std::lock_guard<std::mutex> g(S->mu);
+      S->stop = true;
+    }
+    S->cv_work.notify_all();
+    S->thread.join();
+  }
+  S->live.clear();
+  for (Slot &sl : S->slot) {
+    for (hipEvent_t e : sl.events) (void)hipEventDestroy(e);
+    if (sl.himg) (void)hipHostFree(sl.himg);
+    if (sl.dimg) (void)hipFree(sl.dimg);
+  }
+  for (hipEvent_t e : S->ev_pool) (void)hipEventDestroy(e);
+  if (S->copy) (void)hipStreamDestroy(S->copy);
+  if (S->comp) (void)hipStreamDestroy(S->comp);
+  if (S->dmem) (void)hipFree(S->dmem);
+  delete S;
+  return HP_OK;
+}
+
+extern "C" int hp_server_create(size_t device_budget_bytes, int32_t max_batch, hp_server **out) {
+  if (!out) return set_error(HP_EINVAL, "server pointer is NULL");
+  *out = nullptr;
+  if (max_batch < 1) return set_error(HP_EINVAL, "max_batch = %d < 1", max_batch);
+  if (device_budget_bytes < Arena::kAlign) return set_error(HP_EINVAL, "device budget of %zu bytes is too small", device_budget_bytes);
+  hp_server *S = new (std::nothrow) hp_server;
+  if (!S) return set_error(HP_ENOMEM, "host allocation failed");
+  if (hipGetDevice(&S->device) != hipSuccess) {
+    hp_server_destroy(S);
+    return set_error(HP_EDEVICE, "no current device");
+  }
+  const DeviceInfo &D = device_info();
+  S->lds_p_max = D.lds_max_p - 8;
+  S->budget = device_budget_bytes / Arena::kAlign * Arena::kAlign;
+  S->max_batch = max_batch;
+  int rc = HP_OK;
+  if (hipMalloc(reinterpret_cast<void **>(&S->dmem), S->budget) != hipSuccess)
+    rc = set_error(HP_ENOMEM, "device arena of %zu bytes could not be allocated", S->budget);
+  if (rc == HP_OK && (hipStreamCreateWithFlags(&S->copy, hipStreamNonBlocking) != hipSuccess ||
+                      hipStreamCreateWithFlags(&S->comp, hipStreamNonBlocking) != hipSuccess))
+    rc = set_error(HP_EDEVICE, "stream creation failed");
+  for (Slot &sl : S->slot) {
+    if (rc != HP_OK) break;
+    if (hipHostMalloc(reinterpret_cast<void **>(&sl.himg), kTableBytes, hipHostMallocDefault) != hipSuccess ||
+        hipMalloc(&sl.dimg, kTableBytes) != hipSuccess)
+      rc = set_error(HP_ENOMEM, "server slot resources could not be allocated");
+  }
+  if (rc == HP_OK && prepare_b_reduce() != hipSuccess) rc = set_error(HP_EDEVICE, "reduce kernel setup failed");
+  if (rc != HP_OK) {
+    hp_server_destroy(S);
+    return rc;
+  }
+  S->arena.reset(S->budget);
+  try {
+    S->thread = std::thread(serve_loop, S);
+  } catch (...) {
+    hp_server_destroy(S);
+    return set_error(HP_EDEVICE, "scheduler thread could not start");
+  }
+  *out = S;
+  return HP_OK;
+}
+
+extern "C" int hp_server_request_bytes(int64_t n, int32_t p, int32_t on_device, size_t *bytes) {
+  if (!bytes) return set_error(HP_EINVAL, "bytes is NULL");
+  if (n < 0) return set_error(HP_EINVAL, "n = %lld < 0", (long long)n);
+  if (p < 1 || p > kBatchPMax) return set_error(HP_EINVAL, "p = %d outside [1, %d]", p, kBatchPMax);
+  Request r;
+  r.n = n;
+  r.p = p;
+  r.on_device = on_device != 0;
+  layout_request(r);
+  *bytes = r.bytes;
+  return HP_OK;
+}
+
+extern "C" int hp_server_submit(hp_server *S, const int32_t *pts, int64_t n, int32_t p, int32_t on_device,
+                                int32_t *cx, int32_t *clo, int32_t *chi, int32_t chain_cap, int32_t *hx,
+                                int32_t *hy, int32_t *info, int64_t *ticket) {
+  if (!S) return set_error(HP_EINVAL, "server is NULL");
+  if (!ticket) return set_error(HP_EINVAL, "ticket is NULL");
+  if (n < 0) return set_error(HP_EINVAL, "n = %lld < 0", (long long)n);
+  if (p < 1 || p > kBatchPMax) return set_error(HP_EINVAL, "p = %d outside [1, %d]", p, kBatchPMax);
+  if (n > 0 && !pts) return set_error(HP_EINVAL, "pts is NULL");
+  if (pts && ((uintptr_t)pts & 7)) return set_error(HP_EINVAL, "pts is not 8-byte aligned");
+  if (!info) return set_error(HP_EINVAL, "info is NULL");
+  const int64_t cap = chain_cap_for(n, p);
+  if (chain_cap < cap) return set_error(HP_ECAPACITY, "chain_cap %d < min(n, p) = %lld", chain_cap, (long long)cap);
+  if (cap > 0 && (!cx || !clo || !chi || !hx || !hy)) return set_error(HP_EINVAL, "NULL output buffer");
+  RequestPtr r;
+  try {
+    r = std::make_shared<Request>();
+  } catch (...) {
+    return set_error(HP_ENOMEM, "host allocation failed");
+  }
+  r->n = n;
+  r->p = p;
+  r->pts = pts;
+  r->on_device = on_device != 0;
+  r->cx = cx;
+  r->clo = clo;
+  r->chi = chi;
+  r->hx = hx;
+  r->hy = hy;
+  r->info = info;
+  layout_request(*r);
+  if (r->bytes > S->arena.size() || r->table_bound + BatchTables::kImageSlack > kTableBytes) {
+    const size_t need = r->bytes;
+    return set_error(HP_ECAPACITY, "request needs %zu device bytes, the server budget is %zu", need, S->budget);
+  }
+  {
+    std::lock_guard<std::mutex> g(S->mu);
+    r->id = S->next_id++;
+    S->live[r->id] = r;
+    S->pending.push_back(r);
+    *ticket = r->id;
+  }
+  S->cv_work.notify_one();
+  return HP_OK;
+}
+
+extern "C" int hp_server_wait(hp_server *S, int64_t ticket, int64_t timeout_us, int64_t *done_ns) {
+  if (!S) return set_error(HP_EINVAL, "server is NULL");
+  std::unique_lock<std::mutex> lk(S->mu);
+  auto it = S->live.find(ticket);
+  if (it == S->live.end()) return set_error(HP_EINVAL, "unknown ticket %lld", (long long)ticket);
+  const RequestPtr r = it->second;
+  auto ready = [&] { return r->done; };
+  if (timeout_us < 0) {
+    S->cv_done.wait(lk, ready);
+  } else if (!S->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready)) {
+    return HP_ETIMEOUT;
+  }
+  if (done_ns) *done_ns = r->done_ns;
+  S->live.erase(ticket);
+  return HP_OK;
+}
+
+extern "C" int hp_server_stats(hp_server *S, int64_t *stats) {
+  if (!S || !stats) return set_error(HP_EINVAL, "server or stats is NULL");
+  std::lock_guard<std::mutex> g(S->mu);
+  stats[0] = S->batches;
+  stats[1] = S->served;
+  stats[2] = S->batched_requests;
+  stats[3] = S->peak_in_use;
+  stats[4] = (int64_t)S->pending.size();
+  stats[5] = (int64_t)S->arena.size();
+  return HP_OK;
+}
+
+extern "C" int64_t hp_clock_ns(void) { return now_ns(); }

@@ -961,15 +961,14 @@ __global__ __launch_bounds__(256) void k_chain(const int2 *__restrict__ Lm, int3
 // (cloud, local index) pair, so one launch per step covers all clouds.
 // ---------------------------------------------------------------------------
 
-// Zero each cloud's info and control words; set the L of clouds that are
-// reduced with atomics to the sentinel; reset the reduce work counter.
-__global__ __launch_bounds__(256) void k_b_fill(const FinishArgs *fa, const uint8_t *needs_fill,
+// Zero each cloud's info words; set the L of clouds that are reduced with
+// atomics to the sentinel; reset the reduce work counter.
+__global__ __launch_bounds__(256) void k_b_fill(const BCloud *cl, const uint8_t *needs_fill,
                                                 int32_t *counter) {
   const int b = blockIdx.x;
-  const FinishArgs &A = fa[b];
+  const BCloud &A = cl[b];
   if (b == 0 && threadIdx.x == 0) *counter = 0;
   if (threadIdx.x < HP_INFO_WORDS) A.info[threadIdx.x] = 0;
-  for (int j = threadIdx.x; j < kCtlWords; j += 256) A.ctl[j] = 0;
   if (needs_fill[b])
     for (int c = threadIdx.x; c < A.p; c += 256) A.Lm[c] = make_int2(A.p + 1, -1);
 }
@@ -980,10 +979,9 @@ __global__ __launch_bounds__(256) void k_b_fill(const FinishArgs *fa, const uint
 // 1 = LDS L merged into the cloud's L by filtered atomics; 2 = filtered
 // atomics straight into the cloud's L (sparse clouds).
 template <int BLOCK, int VPT>
-__global__ __launch_bounds__(BLOCK) void k_b_reduce(const int32_t *__restrict__ pts,
-                                                    const BatchItem *__restrict__ items,
+__global__ __launch_bounds__(BLOCK) void k_b_reduce(const BatchItem *__restrict__ items,
                                                     int32_t nitems, int32_t *counter,
-                                                    const FinishArgs *fa) {
+                                                    const BCloud *cl) {
   extern __shared__ int2 sL[];
   __shared__ int s_item, s_bad;
   for (;;) {
@@ -996,10 +994,10 @@ __global__ __launch_bounds__(BLOCK) void k_b_reduce(const int32_t *__restrict__ 
     const int it = s_item;
     if (it >= nitems) break;
     const BatchItem I = items[it];
-    const FinishArgs &A = fa[I.cloud];
+    const BCloud &A = cl[I.cloud];
     const int p = A.p;
     int2 *L = A.Lm;
-    const int32_t *src = pts + 2 * I.start;
+    const int32_t *src = I.pts;
     bool bad = false;
     if (I.mode == 2) {
       stream_points<BLOCK, VPT, false>(src, I.count, p, L, 0, 1, bad);
@@ -1106,12 +1104,12 @@ __device__ __forceinline__ int merge_right(T *E, int nL, const T *R, int nR, Pt 
 }
 
 __global__ __launch_bounds__(2 * kTileSlabs) void k_b_tiles(const int2 *__restrict__ work,
-                                                             const FinishArgs *fa) {
+                                                             const BCloud *cl) {
   __shared__ uint32_t sE[2 * kSideWords];       // per side, per slab: a row of entries
   __shared__ unsigned long long sVm[kTileSlabs], sSm[kTileSlabs];
   __shared__ int sTop[2][kTileSlabs];
   const int2 w = work[blockIdx.x];
-  const FinishArgs &A = fa[w.x];
+  const BCloud &A = cl[w.x];
   const int p = A.p;
   const int2 *const Lm = A.Lm;
   uint64_t *const mask = A.mask;
@@ -1213,19 +1211,19 @@ __global__ __launch_bounds__(2 * kTileSlabs) void k_b_tiles(const int2 *__restri
 // node whose children hold more than kNodeCap points is joined the same way
 // in global memory.
 template <bool SMALL>
-__global__ __launch_bounds__(kWave) void k_b_nodes(const int4 *__restrict__ work, const HullArgs *ha,
+__global__ __launch_bounds__(kWave) void k_b_nodes(const int4 *__restrict__ work, const BCloud *cl,
                                                    int lev) {
   __shared__ int2 sP[kNodeCap];
   __shared__ int sOff[kFanIn + 1];
   __shared__ int sTop;
   const int4 w = work[blockIdx.x];        // (cloud, node, side, -)
-  const HullArgs &H = ha[w.x];
+  const BCloud &H = cl[w.x];
   const TreeShape &T = H.tree;
   const int node = w.y, side = w.z;
   const int lane = threadIdx.x;
-  const int64_t P = H.positions;
-  const int2 *in = H.buf[(lev - 2) & 1] + (size_t)side * P;
-  int2 *out = H.buf[(lev - 1) & 1] + (size_t)side * P + (size_t)node * T.span[lev];
+  const int64_t P = H.p;
+  const int2 *in = H.cand + (size_t)((lev - 2) & 1) * 2 * P + (size_t)side * P;
+  int2 *out = H.cand + (size_t)((lev - 1) & 1) * 2 * P + (size_t)side * P + (size_t)node * T.span[lev];
   const int c0 = node * kFanIn, nc = min(kFanIn, T.size[lev - 1] - c0);
   const int32_t *cnt = H.ccount + side * T.nodes + T.base[lev - 1];
   int32_t *const ccount_out = H.ccount + side * T.nodes + T.base[lev] + node;
@@ -1273,9 +1271,8 @@ __global__ __launch_bounds__(kWave) void k_b_nodes(const int4 *__restrict__ work
 
 // Per cloud (one wave): slab offsets and totals, then the final hull from
 // the root's two sides (lower left to right, then upper back).
-__global__ __launch_bounds__(64) void k_b_root(const FinishArgs *fa, const HullArgs *ha) {
-  const FinishArgs &A = fa[blockIdx.x];
-  const HullArgs &H = ha[blockIdx.x];
+__global__ __launch_bounds__(64) void k_b_root(const BCloud *cl) {
+  const BCloud &A = cl[blockIdx.x];
   const TreeShape &T = A.tree;
   const int lane = threadIdx.x;
   const int nslab = T.size[1];
@@ -1293,12 +1290,12 @@ __global__ __launch_bounds__(64) void k_b_root(const FinishArgs *fa, const HullA
     carry += __shfl(incl, kWave - 1, kWave);
   }
   for (int d = kWave / 2; d > 0; d >>= 1) stot += __shfl_xor(stot, d, kWave);
-  const int64_t P = H.positions;
-  const int2 *root = H.buf[(T.nlev - 1) & 1];
-  const int nl = H.ccount[0 * T.nodes + T.base[T.nlev]];
-  const int nu = H.ccount[1 * T.nodes + T.base[T.nlev]];
+  const int64_t P = A.p;
+  const int2 *root = A.cand + (size_t)((T.nlev - 1) & 1) * 2 * P;
+  const int nl = A.ccount[0 * T.nodes + T.base[T.nlev]];
+  const int nu = A.ccount[1 * T.nodes + T.base[T.nlev]];
   bool overflow = false;
-  const int h = assemble_hull(root, nl, root + P, nu, H.hx, H.hy, H.hull_cap, overflow);
+  const int h = assemble_hull(root, nl, root + P, nu, A.hx, A.hy, A.hull_cap, overflow);
   if (lane == 0) {
     A.info[HP_INFO_K] = carry;
     A.info[HP_INFO_S] = stot;
@@ -1309,12 +1306,12 @@ __global__ __launch_bounds__(64) void k_b_root(const FinishArgs *fa, const HullA
 
 // Per slab (one wave): its valid columns at the scanned offset.
 __global__ __launch_bounds__(256) void k_b_chain(const int2 *__restrict__ work, int nwork,
-                                                 const FinishArgs *fa) {
+                                                 const BCloud *cl) {
   const int t = blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
   if (t >= nwork) return;
   const int2 w = work[t];
-  const FinishArgs &A = fa[w.x];
-  write_chain_slab(A.Lm, A.p, A.slab_off, w.y, A.cx_out, A.clo_out, A.chi_out, A.chain_cap, A.info);
+  const BCloud &A = cl[w.x];
+  write_chain_slab(A.Lm, A.p, A.slab_off, w.y, A.cx, A.clo, A.chi, A.chain_cap, A.info);
 }
 
 // ---------------------------------------------------------------------------
@@ -1628,9 +1625,9 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
 
 void tree_shape(int64_t positions, TreeShape *out) { *out = make_tree(positions); }
 
-hipError_t launch_b_fill(int B, const FinishArgs *fa, const uint8_t *needs_fill, int32_t *counter,
+hipError_t launch_b_fill(int B, const BCloud *cl, const uint8_t *needs_fill, int32_t *counter,
                          hipStream_t s) {
-  hipLaunchKernelGGL(k_b_fill, dim3(B), dim3(256), 0, s, fa, needs_fill, counter);
+  hipLaunchKernelGGL(k_b_fill, dim3(B), dim3(256), 0, s, cl, needs_fill, counter);
   return hipGetLastError();
 }
 
@@ -1639,35 +1636,36 @@ hipError_t prepare_b_reduce() {
                              device_info().lds_bytes - 64);
 }
 
-hipError_t launch_b_reduce(int grid, size_t lds_bytes, const int32_t *pts, const BatchItem *items,
-                           int32_t nitems, int32_t *counter, const FinishArgs *fa, hipStream_t s) {
-  hipLaunchKernelGGL((k_b_reduce<1024, 4>), dim3(grid), dim3(1024), lds_bytes, s, pts, items, nitems,
-                     counter, fa);
+hipError_t launch_b_reduce(int grid, size_t lds_bytes, const BatchItem *items, int32_t nitems,
+                           int32_t *counter, const BCloud *cl, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_b_reduce<1024, 4>), dim3(grid), dim3(1024), lds_bytes, s, items, nitems, counter, cl);
   return hipGetLastError();
 }
 
-hipError_t launch_b_tiles(int ntiles, const int2 *tiles, const FinishArgs *fa, hipStream_t s) {
+hipError_t launch_b_tiles(int ntiles, const int2 *tiles, const BCloud *cl, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_b_tiles, dim3(ntiles), dim3(2 * kTileSlabs), 0, s, tiles, fa);
+  hipLaunchKernelGGL(k_b_tiles, dim3(ntiles), dim3(2 * kTileSlabs), 0, s, tiles, cl);
   return hipGetLastError();
 }
 
-hipError_t launch_b_nodes(bool small, int lev, int nwork, const int4 *work, const HullArgs *ha,
+hipError_t launch_b_nodes(bool small, int lev, int nwork, const int4 *work, const BCloud *cl,
                           hipStream_t s) {
   if (nwork <= 0) return hipSuccess;
-  if (small) hipLaunchKernelGGL((k_b_nodes<true>), dim3(nwork), dim3(kWave), 0, s, work, ha, lev);
-  else hipLaunchKernelGGL((k_b_nodes<false>), dim3(nwork), dim3(kWave), 0, s, work, ha, lev);
+  if (small) hipLaunchKernelGGL((k_b_nodes<true>), dim3(nwork), dim3(kWave), 0, s, work, cl, lev);
+  else hipLaunchKernelGGL((k_b_nodes<false>), dim3(nwork), dim3(kWave), 0, s, work, cl, lev);
   return hipGetLastError();
 }
 
-hipError_t launch_b_root(int B, const FinishArgs *fa, const HullArgs *ha, hipStream_t s) {
-  hipLaunchKernelGGL(k_b_root, dim3(B), dim3(64), 0, s, fa, ha);
+hipError_t launch_b_root(int B, const BCloud *cl, hipStream_t s) {
+  if (B <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_b_root, dim3(B), dim3(64), 0, s, cl);
   return hipGetLastError();
 }
 
-hipError_t launch_b_chain(int nwork, const int2 *work, const FinishArgs *fa, hipStream_t s) {
+hipError_t launch_b_chain(int nwork, const int2 *work, const BCloud *cl, hipStream_t s) {
   if (nwork <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_b_chain, dim3((nwork + 3) / 4), dim3(256), 0, s, work, nwork, fa);
+  hipLaunchKernelGGL(k_b_chain, dim3((nwork + 3) / 4), dim3(256), 0, s, work, nwork, cl);
   return hipGetLastError();
 }
 

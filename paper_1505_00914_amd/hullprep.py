@@ -259,3 +259,95 @@ class Plan:
                         "x": cx[c0:c0 + k], "clo": clo[c0:c0 + k], "chi": chi[c0:c0 + k],
                         "hull": np.stack([hx[h0:h0 + h], hy[h0:h0 + h]], 1)})
         return out
+
+
+def clock_ns() -> int:
+    """The clock of the server's completion times (monotonic, ns)."""
+    return int(_lib.load().hp_clock_ns())
+
+
+def server_request_bytes(n: int, p: int, on_device: bool = False) -> int:
+    b = ctypes.c_size_t()
+    _lib.call("hp_server_request_bytes", n, p, 1 if on_device else 0, ctypes.byref(b))
+    return b.value
+
+
+class Request:
+    """Host output buffers (page-locked) of one served request, filled by the
+    server before the request completes."""
+
+    def __init__(self, n: int, p: int, points: torch.Tensor):
+        cap = max(1, min(n, p))
+        pin = dict(dtype=torch.int32, pin_memory=True)
+        self.n, self.p, self.points = n, p, points
+        self.cap = cap
+        self.chain = torch.empty((3, cap), **pin)
+        self.hull = torch.empty((2, 2 * cap), **pin)
+        self.info = torch.zeros(4, **pin)
+        self.ticket = -1
+        self.done_ns = 0
+
+    def result(self) -> dict:
+        import numpy as np
+
+        st, k, s, h = (int(v) for v in self.info.tolist())
+        ch = self.chain.numpy()
+        hu = self.hull.numpy()
+        return {"status": st, "k": k, "s": s, "h": h, "x": ch[0, :k].copy(), "clo": ch[1, :k].copy(),
+                "chi": ch[2, :k].copy(), "hull": np.stack([hu[0, :h], hu[1, :h]], 1)}
+
+
+class Server:
+    """The served form: hp_server_create / submit / wait / stats / destroy.
+
+    ``budget_bytes`` of device memory is taken once as the admission arena;
+    ``max_batch`` bounds the requests joined into one launch sequence."""
+
+    def __init__(self, budget_bytes: int, max_batch: int = 64):
+        h = ctypes.c_void_p()
+        _lib.call("hp_server_create", int(budget_bytes), int(max_batch), ctypes.byref(h))
+        self._h = h
+
+    def submit(self, points: torch.Tensor, p: int, req: Request | None = None) -> Request:
+        """Queue one cloud: ``points`` is an (n, 2) int32 tensor in page-locked
+        host memory (copied by the server) or in device memory (read in
+        place); it must stay alive until the request completes."""
+        if points.dtype != torch.int32 or points.dim() != 2 or points.shape[1] != 2 or not points.is_contiguous():
+            raise ValueError("points must be a contiguous (n, 2) int32 tensor")
+        n = points.shape[0]
+        if req is None:
+            req = Request(n, p, points)
+        t = ctypes.c_int64()
+        _lib.call("hp_server_submit", self._h, points.data_ptr() if n else None, n, p,
+                  1 if points.is_cuda else 0, req.chain[0].data_ptr(), req.chain[1].data_ptr(),
+                  req.chain[2].data_ptr(), req.cap, req.hull[0].data_ptr(), req.hull[1].data_ptr(),
+                  req.info.data_ptr(), ctypes.byref(t))
+        req.ticket = t.value
+        return req
+
+    def wait(self, req: Request, timeout_us: int = -1) -> bool:
+        """Block until ``req`` completes (True) or the timeout passes (False)."""
+        d = ctypes.c_int64()
+        rc = _lib.load().hp_server_wait(self._h, req.ticket, int(timeout_us), ctypes.byref(d))
+        if rc == _lib.HP_ETIMEOUT:
+            return False
+        _lib.check(rc, "hp_server_wait")
+        req.done_ns = d.value
+        return True
+
+    def stats(self) -> dict:
+        s = (ctypes.c_int64 * 6)()
+        _lib.call("hp_server_stats", self._h, s)
+        return {"batches": s[0], "completed": s[1], "batched_requests": s[2], "peak_bytes": s[3],
+                "waiting": s[4], "arena_bytes": s[5]}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().hp_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

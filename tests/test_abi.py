@@ -36,7 +36,7 @@ def test_binding_covers_every_declared_symbol():
 
 def test_status_strings():
     lib = _lib.load()
-    for code in (0, -1, -2, -3, -4, -5):
+    for code in (0, -1, -2, -3, -4, -5, -6):
         assert lib.hp_status_string(code)
     assert lib.hp_abi_version() == 1
 
@@ -91,3 +91,43 @@ def test_strategy_and_tuning_setters():
     assert lib.hp_tune_set(1, 256, 4, 10) == 0
     assert lib.hp_tune_set(0, 0, 0, 0) == 0
     assert lib.hp_tune_load(b"/nonexistent/table") == _lib.HP_EINVAL
+
+
+def test_server_arguments_rejected_before_any_device_call():
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    assert lib.hp_server_create(0, 8, ctypes.byref(h)) == _lib.HP_EINVAL
+    assert lib.hp_server_create(1 << 20, 0, ctypes.byref(h)) == _lib.HP_EINVAL
+    assert lib.hp_server_create(1 << 20, 8, None) == _lib.HP_EINVAL
+    t = ctypes.c_int64()
+    d = ctypes.c_void_p(0x10000)
+    assert lib.hp_server_submit(None, d, 10, 10, 0, d, d, d, 10, d, d, d, ctypes.byref(t)) == _lib.HP_EINVAL
+    assert lib.hp_server_wait(None, 0, 0, None) == _lib.HP_EINVAL
+    assert lib.hp_server_stats(None, None) == _lib.HP_EINVAL
+    assert lib.hp_server_destroy(None) == _lib.HP_OK
+
+
+def test_server_request_bytes():
+    """Arena block of a request: host points are staged (8 B each), device
+    points are not; the rest (workspace slots, outputs) is the same."""
+    lib = _lib.load()
+    b = ctypes.c_size_t()
+    for n, p in ((0, 1), (1000, 256), (100_000, 4096), (10_000_000, 65_536)):
+        assert lib.hp_server_request_bytes(n, p, 0, ctypes.byref(b)) == _lib.HP_OK
+        host = b.value
+        assert lib.hp_server_request_bytes(n, p, 1, ctypes.byref(b)) == _lib.HP_OK
+        dev = b.value
+        assert host % 256 == 0 and dev % 256 == 0
+        assert 8 * n <= host - dev < 8 * n + 256
+        cap = min(n, p)
+        assert dev >= 8 * p + 32 * p + 28 * cap   # L, candidates, chain + hull
+    assert lib.hp_server_request_bytes(10, 0, 0, ctypes.byref(b)) == _lib.HP_EINVAL
+    assert lib.hp_server_request_bytes(10, 65_537, 0, ctypes.byref(b)) == _lib.HP_EINVAL
+    assert lib.hp_server_request_bytes(-1, 5, 0, ctypes.byref(b)) == _lib.HP_EINVAL
+
+
+def test_clock_is_monotonic():
+    lib = _lib.load()
+    a = lib.hp_clock_ns()
+    b = lib.hp_clock_ns()
+    assert 0 < a <= b
