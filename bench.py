@@ -29,7 +29,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-REDUCE_SOURCES = ["paper_1505_00914_amd/csrc/hp_single.hip", "paper_1505_00914_amd/csrc/hp_kernels.h",
+# sources of the single-cloud reduce kernel (the counter summary names their hash)
+REDUCE_SOURCES = ["paper_1505_00914_amd/csrc/hp_reduce.h", "paper_1505_00914_amd/csrc/hp_kernels.h",
                   "paper_1505_00914_amd/csrc/hp_device.h"]
 
 
@@ -391,6 +392,41 @@ def bench_serve(args, torch, hp, synth) -> dict:
     return res
 
 
+def summarize_trace(directory: str, command: str, title: str) -> str:
+    """Short text summary of a rocprofv3 --kernel-trace --stats output
+    directory: per-kernel calls and average / min / max duration of the
+    library's kernels, plus their launch shapes."""
+    import csv
+    import glob
+
+    stats_f = glob.glob(os.path.join(directory, "**", "*kernel_stats.csv"), recursive=True)
+    trace_f = glob.glob(os.path.join(directory, "**", "*kernel_trace.csv"), recursive=True)
+    if not stats_f:
+        raise SystemExit(f"no kernel_stats.csv under {directory}")
+    lines = [f"# {title}", "", "Command (from the repository root, on one MI355X):", "", "    " + command, "",
+             "rocprofv3 kernel statistics of the library's kernels (microseconds):", "",
+             f"{'kernel':58s} {'calls':>6s} {'avg_us':>9s} {'min_us':>9s} {'max_us':>9s} {'total_%':>8s}"]
+    rows = list(csv.DictReader(open(stats_f[0])))
+    for r in rows:
+        name = r["Name"]
+        if "hp::" not in name:
+            continue
+        short = name.replace("void ", "").split("(")[0]
+        lines.append(f"{short:58s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:9.2f} "
+                     f"{float(r['MinNs']) / 1e3:9.2f} {float(r['MaxNs']) / 1e3:9.2f} {float(r['Percentage']):8.2f}")
+    if trace_f:
+        seen = set()
+        lines += ["", "Launch shapes (grid threads, workgroup, VGPRs, LDS bytes):", ""]
+        for r in csv.DictReader(open(trace_f[0])):
+            short = r["Kernel_Name"].replace("void ", "").split("(")[0]
+            if "hp::" not in short or short in seen:
+                continue
+            seen.add(short)
+            lines.append(f"{short:58s} grid={r['Grid_Size_X']} wg={r['Workgroup_Size_X']} "
+                         f"vgpr={r.get('VGPR_Count', '?')} lds={r.get('LDS_Block_Size', '?')}")
+    return "\n".join(lines) + "\n"
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -411,7 +447,14 @@ def main(argv=None):
     ap.add_argument("--serve-budget", type=int, default=8, help="device arena, GiB")
     ap.add_argument("--serve-max-batch", type=int, default=64)
     ap.add_argument("--strategy", type=int, default=0)
+    ap.add_argument("--summarize-trace", metavar="DIR", help="summarise a rocprofv3 kernel-trace directory and exit")
+    ap.add_argument("--summary-command", default="", help="command line recorded in the summary")
+    ap.add_argument("--summary-title", default="kernel trace")
     args = ap.parse_args(argv)
+
+    if args.summarize_trace:
+        print(summarize_trace(args.summarize_trace, args.summary_command, args.summary_title), end="")
+        return 0
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "

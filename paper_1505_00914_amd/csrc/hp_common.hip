@@ -5,7 +5,10 @@
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <string>
 #include <vector>
+
+#include <dlfcn.h>
 
 #include "hp_host.h"
 
@@ -77,6 +80,33 @@ static int ilog2(int64_t v) {
   return l;
 }
 
+int tune_load(const char *path);
+
+// The table shipped beside the library (tuning_gfx950.txt in the directory
+// of libhullprep.so) is loaded on first use; HP_TUNING_FILE names another
+// file, or disables it when empty.  A missing file leaves the defaults.
+static void load_default_table() {
+  static std::once_flag once;
+  std::call_once(once, [] {
+    std::string path;
+    if (const char *env = getenv("HP_TUNING_FILE")) {
+      path = env;
+    } else {
+      Dl_info di;
+      if (dladdr(reinterpret_cast<void *>(&load_default_table), &di) && di.dli_fname) {
+        path = di.dli_fname;
+        const size_t slash = path.rfind('/');
+        path = (slash == std::string::npos ? std::string(".") : path.substr(0, slash)) + "/tuning_gfx950.txt";
+      }
+    }
+    if (path.empty()) return;
+    if (FILE *f = fopen(path.c_str(), "r")) {
+      fclose(f);
+      (void)tune_load(path.c_str());
+    }
+  });
+}
+
 static const TuneEntry *lookup(int64_t n, int32_t p) {
   const int ln = ilog2(n < 1 ? 1 : n), lp = ilog2(p);
   for (const TuneEntry &t : g_table)
@@ -85,6 +115,7 @@ static const TuneEntry *lookup(int64_t n, int32_t p) {
 }
 
 int tuned_strategy(int64_t n, int32_t p) {
+  load_default_table();
   std::lock_guard<std::mutex> lk(g_mu);
   if (g_set_strategy) return g_set_strategy;
   if (const TuneEntry *t = lookup(n, p)) return t->strategy;
@@ -96,6 +127,7 @@ int tuned_strategy(int64_t n, int32_t p) {
 }
 
 void tune_override(int64_t n, int32_t p, int *block, int *vpt, int *G) {
+  load_default_table();
   std::lock_guard<std::mutex> lk(g_mu);
   if (const TuneEntry *t = lookup(n, p)) {
     if (t->block) *block = t->block;

@@ -17,7 +17,8 @@ constexpr int kSlab = 64;        // columns per slab = one M word = one wave
 constexpr int kTile = 16;        // level-0 hull tile (singleton candidates)
 constexpr int kFanIn = 64;       // children per hull-tree node above a slab
 constexpr int kMaxLevels = 12;   // hull-tree levels (slab level is 1)
-constexpr int kSplit = 4;        // hull-test workgroups per child node
+constexpr int kSplit = 4;        // hull-test workgroups per child node above the slabs
+constexpr int kSplitSlab = 4;    // hull-test workgroups per slab
 
 // Control words at the head of every workspace.
 constexpr int kCtlErr = 0;       // bitmask of data errors seen by kernels

@@ -144,6 +144,7 @@ struct HullArgs {
   int32_t *ccount;          // [2][nodes] hull sizes of nodes
   TreeShape tree;
   int32_t positions;
+  int32_t split;            // test workgroups per child node
   int32_t *hx, *hy;
   int32_t hull_cap;
   int32_t *info;
@@ -158,7 +159,6 @@ struct HullArgs {
   int32_t chain_cap;
 };
 
-// One chunk of a batched reduce.
 // Batched form: one work item of the persistent reduce.
 struct BatchItem {
   const int32_t *pts;  // first point of the item (device)

@@ -1,0 +1,149 @@
+// hp_reduce.h -- Algorithm 1 on the device: the point stream and the
+// single-cloud reduce kernels (workgroup-private L in LDS, written out as a
+// partial or merged by atomics; or one L in device memory).  The batched
+// reduce streams its work items with the same stream_points.
+#pragma once
+
+#include "hp_kernels.h"
+
+namespace hp {
+
+// ---------------------------------------------------------------------------
+// Algorithm 1.  Points are read once, 16 bytes (two points) per lane per
+// load, VPT loads in flight per lane; consecutive lanes read consecutive
+// vectors and consecutive workgroups consecutive chunks.
+// ---------------------------------------------------------------------------
+template <int BLOCK, int VPT, bool LDS>
+__device__ __forceinline__ void stream_points(const int32_t *__restrict__ pts, int64_t n, int p,
+                                              int2 *L, int64_t wg, int64_t nwg, bool &bad) {
+  // pts is 8-byte aligned (checked on the host); peel one point if the
+  // vector body would otherwise start on an 8-byte boundary.
+  const int64_t head = (n > 0 && ((uintptr_t)pts & 15) != 0) ? 1 : 0;
+  const int64_t nv = (n - head) >> 1;
+  const int64_t tail = head + 2 * nv;  // index of the odd last point, if any
+  if (wg == 0 && threadIdx.x == 0) {
+    if (head) {
+      if (LDS) fold_point_lds(L, p, pts[0], pts[1], bad);
+      else fold_point_global(L, p, pts[0], pts[1], bad);
+    }
+    if (tail < n) {
+      if (LDS) fold_point_lds(L, p, pts[2 * tail], pts[2 * tail + 1], bad);
+      else fold_point_global(L, p, pts[2 * tail], pts[2 * tail + 1], bad);
+    }
+  }
+  const int4 *v = reinterpret_cast<const int4 *>(pts + 2 * head);
+  constexpr int64_t chunk = (int64_t)BLOCK * VPT;
+  const int64_t step = nwg * chunk;
+  int64_t t0 = wg * chunk;
+  // Full chunks, software-pipelined: the next chunk's loads are issued
+  // (unconditionally, from a valid address) before the current chunk is
+  // folded into L, so VPT 16-byte loads per lane stay in flight.
+  int4 q[VPT];
+  bool have = t0 + chunk <= nv;
+  if (have) {
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) q[u] = v[t0 + u * BLOCK + threadIdx.x];
+  }
+  while (have) {
+    const int64_t t1 = t0 + step;
+    const bool have_next = t1 + chunk <= nv;
+    const int64_t tl = have_next ? t1 : t0;
+    Batch<VPT> b;
+    gather<VPT, LDS>(L, p, q, b, bad);
+    int4 qn[VPT];
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) qn[u] = v[tl + u * BLOCK + threadIdx.x];
+    apply<VPT, LDS>(L, b);
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) q[u] = qn[u];
+    t0 = t1;
+    have = have_next;
+  }
+  // at most one partial chunk remains for this workgroup
+  if (t0 < nv) {
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+      const int64_t idx = t0 + u * BLOCK + threadIdx.x;
+      if (idx < nv) {
+        const int4 r = v[idx];
+        if (LDS) {
+          fold_point_lds(L, p, r.x, r.y, bad);
+          fold_point_lds(L, p, r.z, r.w, bad);
+        } else {
+          fold_point_global(L, p, r.x, r.y, bad);
+          fold_point_global(L, p, r.z, r.w, bad);
+        }
+      }
+    }
+  }
+}
+
+// Control words the finish step relies on.  When no init kernel runs (the
+// partial-L strategy), workgroup 0 of the reduce kernel clears them: the
+// finish kernel only starts after the reduce kernel has completed.
+struct ResetArgs {
+  int32_t *ctl;
+  int32_t *tree_ctr;
+  int32_t nodes;
+  int32_t *info;
+};
+
+__device__ __forceinline__ void reset_controls(const ResetArgs &R) {
+  if (blockIdx.x != 0 || R.ctl == nullptr) return;
+  for (int j = threadIdx.x; j < kCtlWords; j += blockDim.x) R.ctl[j] = 0;
+  for (int j = threadIdx.x; j < R.nodes; j += blockDim.x) R.tree_ctr[j] = 0;
+  if (threadIdx.x < HP_INFO_WORDS) R.info[threadIdx.x] = 0;
+}
+
+// Workgroup-private L in LDS.  MERGE_ATOMIC: folded into the device L with
+// filtered device-scope atomics (only touched columns that improve on the
+// value read first); otherwise written out as one partial L per workgroup
+// and merged by k_finish.  Every workgroup writes its own range-error word.
+template <int BLOCK, int VPT, bool MERGE_ATOMIC>
+__global__ __launch_bounds__(BLOCK) void k_reduce_lds(const int32_t *__restrict__ pts, int64_t n,
+                                                      int32_t p, int2 *__restrict__ out_L,
+                                                      int32_t *__restrict__ wg_err, ResetArgs R) {
+  extern __shared__ int2 sL[];           // p pairs, then one flag word
+  int &s_bad = reinterpret_cast<int &>(sL[p]);
+  reset_controls(R);
+  if (threadIdx.x == 0) s_bad = 0;
+  for (int c = threadIdx.x; c < p; c += BLOCK) sL[c] = make_int2(p + 1, -1);
+  __syncthreads();
+  bool bad = false;
+  stream_points<BLOCK, VPT, true>(pts, n, p, sL, blockIdx.x, gridDim.x, bad);
+  if (bad) s_bad = 1;
+  __syncthreads();
+  if (MERGE_ATOMIC) {
+    for (int c = threadIdx.x; c < p; c += BLOCK) {
+      const int2 mine = sL[c];
+      if (mine.x > mine.y) continue;  // column untouched by this workgroup
+      const int2 cur = load_coherent(&out_L[c]);
+      if (mine.x < cur.x)
+        __hip_atomic_fetch_min(&out_L[c].x, mine.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (mine.y > cur.y)
+        __hip_atomic_fetch_max(&out_L[c].y, mine.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  } else {
+    int2 *out = out_L + (size_t)blockIdx.x * (size_t)p;
+    for (int c = threadIdx.x; c < p; c += BLOCK) out[c] = sL[c];
+  }
+  if (threadIdx.x == 0) wg_err[blockIdx.x] = s_bad ? kErrRange : 0;
+}
+
+// One L in device memory, updated with filtered device-scope atomics.
+template <int BLOCK, int VPT>
+__global__ __launch_bounds__(BLOCK) void k_reduce_global(const int32_t *__restrict__ pts, int64_t n,
+                                                         int32_t p, int2 *L,
+                                                         int32_t *__restrict__ wg_err, ResetArgs R) {
+  __shared__ int s_bad;
+  reset_controls(R);
+  if (threadIdx.x == 0) s_bad = 0;
+  __syncthreads();
+  bool bad = false;
+  stream_points<BLOCK, VPT, false>(pts, n, p, L, blockIdx.x, gridDim.x, bad);
+  if (bad) s_bad = 1;
+  __syncthreads();
+  if (threadIdx.x == 0) wg_err[blockIdx.x] = s_bad ? kErrRange : 0;
+}
+
+}  // namespace hp

@@ -6,6 +6,8 @@
 
 #include "hp_host.h"
 #include "hp_kernels.h"
+#include "hp_output.h"
+#include "hp_reduce.h"
 
 namespace hp {
 
@@ -30,144 +32,6 @@ __global__ void k_init(int32_t *ctl, int32_t *tree_ctr, int32_t nodes, int32_t *
   }
   if (L)
     for (int64_t c = i; c < p; c += stride) L[c] = make_int2(p + 1, -1);
-}
-
-// ---------------------------------------------------------------------------
-// Algorithm 1.  Points are read once, 16 bytes (two points) per lane per
-// load, VPT loads in flight per lane; consecutive lanes read consecutive
-// vectors and consecutive workgroups consecutive chunks.
-// ---------------------------------------------------------------------------
-template <int BLOCK, int VPT, bool LDS>
-__device__ __forceinline__ void stream_points(const int32_t *__restrict__ pts, int64_t n, int p,
-                                              int2 *L, int64_t wg, int64_t nwg, bool &bad) {
-  // pts is 8-byte aligned (checked on the host); peel one point if the
-  // vector body would otherwise start on an 8-byte boundary.
-  const int64_t head = (n > 0 && ((uintptr_t)pts & 15) != 0) ? 1 : 0;
-  const int64_t nv = (n - head) >> 1;
-  const int64_t tail = head + 2 * nv;  // index of the odd last point, if any
-  if (wg == 0 && threadIdx.x == 0) {
-    if (head) {
-      if (LDS) fold_point_lds(L, p, pts[0], pts[1], bad);
-      else fold_point_global(L, p, pts[0], pts[1], bad);
-    }
-    if (tail < n) {
-      if (LDS) fold_point_lds(L, p, pts[2 * tail], pts[2 * tail + 1], bad);
-      else fold_point_global(L, p, pts[2 * tail], pts[2 * tail + 1], bad);
-    }
-  }
-  const int4 *v = reinterpret_cast<const int4 *>(pts + 2 * head);
-  constexpr int64_t chunk = (int64_t)BLOCK * VPT;
-  const int64_t step = nwg * chunk;
-  int64_t t0 = wg * chunk;
-  // Full chunks, software-pipelined: the next chunk's loads are issued
-  // (unconditionally, from a valid address) before the current chunk is
-  // folded into L, so VPT 16-byte loads per lane stay in flight.
-  int4 q[VPT];
-  bool have = t0 + chunk <= nv;
-  if (have) {
-#pragma unroll
-    for (int u = 0; u < VPT; ++u) q[u] = v[t0 + u * BLOCK + threadIdx.x];
-  }
-  while (have) {
-    const int64_t t1 = t0 + step;
-    const bool have_next = t1 + chunk <= nv;
-    const int64_t tl = have_next ? t1 : t0;
-    Batch<VPT> b;
-    gather<VPT, LDS>(L, p, q, b, bad);
-    int4 qn[VPT];
-#pragma unroll
-    for (int u = 0; u < VPT; ++u) qn[u] = v[tl + u * BLOCK + threadIdx.x];
-    apply<VPT, LDS>(L, b);
-#pragma unroll
-    for (int u = 0; u < VPT; ++u) q[u] = qn[u];
-    t0 = t1;
-    have = have_next;
-  }
-  // at most one partial chunk remains for this workgroup
-  if (t0 < nv) {
-#pragma unroll
-    for (int u = 0; u < VPT; ++u) {
-      const int64_t idx = t0 + u * BLOCK + threadIdx.x;
-      if (idx < nv) {
-        const int4 r = v[idx];
-        if (LDS) {
-          fold_point_lds(L, p, r.x, r.y, bad);
-          fold_point_lds(L, p, r.z, r.w, bad);
-        } else {
-          fold_point_global(L, p, r.x, r.y, bad);
-          fold_point_global(L, p, r.z, r.w, bad);
-        }
-      }
-    }
-  }
-}
-
-// Control words the finish step relies on.  When no init kernel runs (the
-// partial-L strategy), workgroup 0 of the reduce kernel clears them: the
-// finish kernel only starts after the reduce kernel has completed.
-struct ResetArgs {
-  int32_t *ctl;
-  int32_t *tree_ctr;
-  int32_t nodes;
-  int32_t *info;
-};
-
-__device__ __forceinline__ void reset_controls(const ResetArgs &R) {
-  if (blockIdx.x != 0 || R.ctl == nullptr) return;
-  for (int j = threadIdx.x; j < kCtlWords; j += blockDim.x) R.ctl[j] = 0;
-  for (int j = threadIdx.x; j < R.nodes; j += blockDim.x) R.tree_ctr[j] = 0;
-  if (threadIdx.x < HP_INFO_WORDS) R.info[threadIdx.x] = 0;
-}
-
-// Workgroup-private L in LDS.  MERGE_ATOMIC: folded into the device L with
-// filtered device-scope atomics (only touched columns that improve on the
-// value read first); otherwise written out as one partial L per workgroup
-// and merged by k_finish.  Every workgroup writes its own range-error word.
-template <int BLOCK, int VPT, bool MERGE_ATOMIC>
-__global__ __launch_bounds__(BLOCK) void k_reduce_lds(const int32_t *__restrict__ pts, int64_t n,
-                                                      int32_t p, int2 *__restrict__ out_L,
-                                                      int32_t *__restrict__ wg_err, ResetArgs R) {
-  extern __shared__ int2 sL[];           // p pairs, then one flag word
-  int &s_bad = reinterpret_cast<int &>(sL[p]);
-  reset_controls(R);
-  if (threadIdx.x == 0) s_bad = 0;
-  for (int c = threadIdx.x; c < p; c += BLOCK) sL[c] = make_int2(p + 1, -1);
-  __syncthreads();
-  bool bad = false;
-  stream_points<BLOCK, VPT, true>(pts, n, p, sL, blockIdx.x, gridDim.x, bad);
-  if (bad) s_bad = 1;
-  __syncthreads();
-  if (MERGE_ATOMIC) {
-    for (int c = threadIdx.x; c < p; c += BLOCK) {
-      const int2 mine = sL[c];
-      if (mine.x > mine.y) continue;  // column untouched by this workgroup
-      const int2 cur = load_coherent(&out_L[c]);
-      if (mine.x < cur.x)
-        __hip_atomic_fetch_min(&out_L[c].x, mine.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (mine.y > cur.y)
-        __hip_atomic_fetch_max(&out_L[c].y, mine.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  } else {
-    int2 *out = out_L + (size_t)blockIdx.x * (size_t)p;
-    for (int c = threadIdx.x; c < p; c += BLOCK) out[c] = sL[c];
-  }
-  if (threadIdx.x == 0) wg_err[blockIdx.x] = s_bad ? kErrRange : 0;
-}
-
-// One L in device memory, updated with filtered device-scope atomics.
-template <int BLOCK, int VPT>
-__global__ __launch_bounds__(BLOCK) void k_reduce_global(const int32_t *__restrict__ pts, int64_t n,
-                                                         int32_t p, int2 *L,
-                                                         int32_t *__restrict__ wg_err, ResetArgs R) {
-  __shared__ int s_bad;
-  reset_controls(R);
-  if (threadIdx.x == 0) s_bad = 0;
-  __syncthreads();
-  bool bad = false;
-  stream_points<BLOCK, VPT, false>(pts, n, p, L, blockIdx.x, gridDim.x, bad);
-  if (bad) s_bad = 1;
-  __syncthreads();
-  if (threadIdx.x == 0) wg_err[blockIdx.x] = s_bad ? kErrRange : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -220,37 +84,6 @@ __device__ int block_exclusive_scan(int32_t *a, int32_t n, int *s_tmp, int *s_ca
   return *s_carry;
 }
 
-// The final hull from the lower hull of (x, lo) and the lower hull of
-// (x, -hi) (both left to right): lower chain, then the upper chain walked
-// back, without the shared end points.  Returns h.
-__device__ int assemble_hull(const int2 *low, int nl, const int2 *upn, int nu, int32_t *hx,
-                             int32_t *hy, int32_t cap, bool &overflow) {
-  if (nl == 0 || nu == 0) return 0;
-  const int2 l0 = low[0], la = low[nl - 1];
-  const int2 u0 = make_int2(upn[0].x, -upn[0].y), ub = make_int2(upn[nu - 1].x, -upn[nu - 1].y);
-  const bool dropL = (la.x == ub.x && la.y == ub.y);
-  const bool dropU = (u0.x == l0.x && u0.y == l0.y);
-  const bool single = (nl == 1 && nu == 1 && dropL);
-  const int cntL = nl - (dropL ? 1 : 0);
-  const int cntU = nu - (dropU ? 1 : 0);
-  const int h = single ? 1 : cntL + cntU;
-  if (h > cap) {
-    overflow = true;
-    return h;
-  }
-  if (single) {
-    if (threadIdx.x == 0) { hx[0] = l0.x; hy[0] = l0.y; }
-    return 1;
-  }
-  for (int i = threadIdx.x; i < cntL; i += blockDim.x) { hx[i] = low[i].x; hy[i] = low[i].y; }
-  for (int j = threadIdx.x; j < cntU; j += blockDim.x) {
-    const int2 u = upn[nu - 1 - j];
-    hx[cntL + j] = u.x;
-    hy[cntL + j] = -u.y;
-  }
-  return h;
-}
-
 // Merge the children of tree node (lev, j) for both sides; writes the node's
 // hulls into cand buffer lev&1 (or, for the root, assembles the hull).
 // Last-arriver test: the barrier completes every thread's stores, then one
@@ -269,31 +102,6 @@ __device__ bool last_arrival_flag(int32_t *ctr, int expected, int *s_flag) {
 
 __device__ bool last_arrival(int32_t *ctr, int expected, FinishShared &S) {
   return last_arrival_flag(ctr, expected, &S.flag);
-}
-
-// Chain write of slabs [s0, s1) with the slab offsets already scanned: one
-// wave per slab, ballot rank inside the slab (Lemma 1 order).
-__device__ void write_chain_slab(const int2 *Lm, int32_t p, const int32_t *slab_off, int slab,
-                                 int32_t *cx, int32_t *clo, int32_t *chi, int32_t cap,
-                                 int32_t *info) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int64_t pos = (int64_t)slab * kSlab + lane;
-  int2 L = make_int2(1, 0);
-  const bool inside = pos < p;
-  if (inside) L = Lm[pos];
-  const bool valid = inside && L.x <= L.y;
-  int tot;
-  const int r = wave_rank(valid, &tot);
-  const int off = slab_off[slab] + r;
-  if (valid) {
-    if (off < cap) {
-      cx[off] = (int)pos + 1;
-      clo[off] = L.x;
-      chi[off] = L.y;
-    } else {
-      atomicMin(&info[HP_INFO_STATUS], HP_ECAPACITY);
-    }
-  }
 }
 
 // Per-slab work of the finish step, for slab `slab` of the cloud described
@@ -680,22 +488,33 @@ __device__ void root_chain(const HullArgs &H, HullShared &S) {
   }
   __syncthreads();
   const int ktot = S.carry;
-  // one wave per slab, kWaves slabs per round
-  for (int sl0 = 0; sl0 < nslab; sl0 += kWaves) {
-    const int sl = sl0 + wave;
-    const int64_t pos = (int64_t)sl * kSlab + lane;
-    const int2 L = (sl < nslab && pos < H.p) ? H.Lm[pos] : make_int2(1, 0);
-    const bool valid = L.x <= L.y;
-    int tot;
-    const int r = wave_rank(valid, &tot);
-    if (valid) {
-      const int o = off[sl] + r;
-      if (o < H.chain_cap) {
-        H.cx[o] = (int)pos + 1;
-        H.clo[o] = L.x;
-        H.chi[o] = L.y;
-      } else {
-        atomicMin(&H.info[HP_INFO_STATUS], HP_ECAPACITY);
+  // one wave per slab; each wave loads kRootSlabs slabs before writing any,
+  // so a pass costs one memory latency
+  constexpr int kRootSlabs = 4;
+  for (int sl0 = 0; sl0 < nslab; sl0 += kWaves * kRootSlabs) {
+    int2 L[kRootSlabs];
+#pragma unroll
+    for (int u = 0; u < kRootSlabs; ++u) {
+      const int sl = sl0 + u * kWaves + wave;
+      const int64_t pos = (int64_t)sl * kSlab + lane;
+      L[u] = (sl < nslab && pos < H.p) ? H.Lm[pos] : make_int2(1, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < kRootSlabs; ++u) {
+      const int sl = sl0 + u * kWaves + wave;
+      const int64_t pos = (int64_t)sl * kSlab + lane;
+      const bool valid = L[u].x <= L[u].y;
+      int tot;
+      const int r = wave_rank(valid, &tot);
+      if (valid) {
+        const int o = off[sl] + r;
+        if (o < H.chain_cap) {
+          H.cx[o] = (int)pos + 1;
+          H.clo[o] = L[u].x;
+          H.chi[o] = L[u].y;
+        } else {
+          atomicMin(&H.info[HP_INFO_STATUS], HP_ECAPACITY);
+        }
       }
     }
   }
@@ -737,8 +556,8 @@ __device__ __forceinline__ void hull_test_body(const HullArgs &H, HullShared &S,
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wave = tid / kWave;
-  const int c = item / kSplit;              // child node at level lev-1
-  const int part = item % kSplit;
+  const int c = item / H.split;             // child node at level lev-1
+  const int part = item % H.split;
   const int parent = c / kFanIn;
   const int sib0 = parent * kFanIn;
   const int nsib = min(kFanIn, T.size[lev - 1] - sib0);
@@ -775,7 +594,7 @@ __device__ __forceinline__ void hull_test_body(const HullArgs &H, HullShared &S,
   const int n0 = S.cc[0][j], n1 = S.cc[1][j];
   const int nq = n0 + n1;
   uint8_t *keep = H.keep + (size_t)c * span_c * 2;
-  for (int q = part * kWaves + wave; q < nq; q += kSplit * kWaves) {
+  for (int q = part * kWaves + wave; q < nq; q += H.split * kWaves) {
     const int side = q < n0 ? 0 : 1;
     const int r = side ? q - n0 : q;
     const int *cc = S.cc[side];
@@ -953,365 +772,6 @@ __global__ __launch_bounds__(256) void k_chain(const int2 *__restrict__ Lm, int3
   const int slab = blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
   if (slab >= nslab) return;
   write_chain_slab(Lm, p, slab_off, slab, cx, clo, chi, cap, info);
-}
-
-// ---------------------------------------------------------------------------
-// Batched form.  Every cloud has its own FinishArgs / HullArgs (device
-// arrays written by the plan); work tables map each workgroup to a
-// (cloud, local index) pair, so one launch per step covers all clouds.
-// ---------------------------------------------------------------------------
-
-// Zero each cloud's info words; set the L of clouds that are reduced with
-// atomics to the sentinel; reset the reduce work counter.
-__global__ __launch_bounds__(256) void k_b_fill(const BCloud *cl, const uint8_t *needs_fill,
-                                                int32_t *counter) {
-  const int b = blockIdx.x;
-  const BCloud &A = cl[b];
-  if (b == 0 && threadIdx.x == 0) *counter = 0;
-  if (threadIdx.x < HP_INFO_WORDS) A.info[threadIdx.x] = 0;
-  if (needs_fill[b])
-    for (int c = threadIdx.x; c < A.p; c += 256) A.Lm[c] = make_int2(A.p + 1, -1);
-}
-
-// Persistent reduce: workgroups take chunks from a shared counter until the
-// list is exhausted (every wave leaves the loop once the counter passes the
-// end).  Modes: 0 = the chunk is the whole cloud, LDS L stored as is;
-// 1 = LDS L merged into the cloud's L by filtered atomics; 2 = filtered
-// atomics straight into the cloud's L (sparse clouds).
-template <int BLOCK, int VPT>
-__global__ __launch_bounds__(BLOCK) void k_b_reduce(const BatchItem *__restrict__ items,
-                                                    int32_t nitems, int32_t *counter,
-                                                    const BCloud *cl) {
-  extern __shared__ int2 sL[];
-  __shared__ int s_item, s_bad;
-  for (;;) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      s_item = atomicAdd(counter, 1);
-      s_bad = 0;
-    }
-    __syncthreads();
-    const int it = s_item;
-    if (it >= nitems) break;
-    const BatchItem I = items[it];
-    const BCloud &A = cl[I.cloud];
-    const int p = A.p;
-    int2 *L = A.Lm;
-    const int32_t *src = I.pts;
-    bool bad = false;
-    if (I.mode == 2) {
-      stream_points<BLOCK, VPT, false>(src, I.count, p, L, 0, 1, bad);
-    } else {
-      for (int c = threadIdx.x; c < p; c += BLOCK) sL[c] = make_int2(p + 1, -1);
-      __syncthreads();
-      stream_points<BLOCK, VPT, true>(src, I.count, p, sL, 0, 1, bad);
-      __syncthreads();
-      if (I.mode == 0) {
-        for (int c = threadIdx.x; c < p; c += BLOCK) L[c] = sL[c];
-      } else {
-        for (int c = threadIdx.x; c < p; c += BLOCK) {
-          const int2 mine = sL[c];
-          if (mine.x > mine.y) continue;
-          const int2 cur = load_coherent(&L[c]);
-          if (mine.x < cur.x)
-            __hip_atomic_fetch_min(&L[c].x, mine.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          if (mine.y > cur.y)
-            __hip_atomic_fetch_max(&L[c].y, mine.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-      }
-    }
-    if (bad) s_bad = 1;
-    __syncthreads();
-    if (threadIdx.x == 0 && s_bad) atomicMin(&A.info[HP_INFO_STATUS], HP_ERANGE);
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Batched finish, shaped for throughput across many clouds: each lower hull
-// is built by Andrew's monotone chain run by one lane over x-sorted input
-// held in LDS, so a step costs one LDS read and there is no cross-lane
-// traffic.
-//   k_b_tiles   per tile of 64 slabs (= one level-2 node): each slab's M
-//               word and counts, each slab's two hulls (a lane per slab and
-//               side), then the node's two hulls from the slab hulls (a lane
-//               per side)
-//   k_b_nodes   per node above level 2 and side: the chain over its
-//               children's hulls staged in LDS
-//   k_b_root    per cloud: slab offsets (scan), k, s, the final vertex list
-//   k_b_chain   per slab: the chain at the scanned offset (Lemma 1 order)
-// ---------------------------------------------------------------------------
-constexpr int kTileSlabs = kFanIn;               // slabs per tile
-constexpr int kTileCols = kTileSlabs * kSlab;    // 4096 columns
-constexpr int kRow = kSlab + 2;                  // LDS row stride (entries)
-constexpr int kSideWords = kTileSlabs * kRow + 1;
-constexpr int kNodeCap = 4096;                   // points a k_b_nodes wave stages
-
-// A tile entry packs one point in tile-local coordinates: column in the
-// tile (12 bits) above a 16-bit height, lo - 1 for the lower side and p - hi
-// for the upper side.  Both are translations of (x, lo) and (x, -hi), so the
-// turn tests are unchanged; every difference fits in 17 signed bits and the
-// 24-bit products are exact.
-struct TilePt {
-  __device__ __forceinline__ int2 operator()(uint32_t e) const {
-    return make_int2((int)(e >> 16), (int)(e & 0xFFFFu));
-  }
-};
-struct PlainPt {
-  __device__ __forceinline__ int2 operator()(int2 e) const { return e; }
-};
-
-// Lower chain of the points of E[0..nL) followed by those of R[0..nR), both
-// already lower chains (strict left turns) and R entirely right of E; the
-// result is left in E[0..), count returned.  The left chain stays the
-// bottom of Andrew's stack, so only the right chain is scanned, and once an
-// entry R[j] (j >= 1) is pushed without a pop the stack ends in R[j-1],
-// R[j], and the rest of R extends it with left turns: it is copied without
-// tests.  R may lie in the same array at or after E + nL: every write goes
-// at or before the entry just read.
-template <bool SMALL, typename T, typename Pt>
-__device__ __forceinline__ int merge_right(T *E, int nL, const T *R, int nR, Pt pt) {
-  int top = nL;
-  int2 a = make_int2(0, 0), b = make_int2(0, 0);
-  if (top >= 2) a = pt(E[top - 2]);
-  if (top >= 1) b = pt(E[top - 1]);
-  int j = 0;
-  while (j < nR) {
-    const T e = R[j];
-    const int2 v = pt(e);
-    bool popped = false;
-    while (top >= 2 && !cross_pos<SMALL>(a, b, v)) {
-      --top;
-      b = a;
-      if (top >= 2) a = pt(E[top - 2]);
-      popped = true;
-    }
-    E[top++] = e;
-    a = b;
-    b = v;
-    ++j;
-    if (j >= 2 && !popped) break;
-  }
-  for (; j + 4 <= nR; j += 4) {
-    const T e0 = R[j], e1 = R[j + 1], e2 = R[j + 2], e3 = R[j + 3];
-    E[top] = e0;
-    E[top + 1] = e1;
-    E[top + 2] = e2;
-    E[top + 3] = e3;
-    top += 4;
-  }
-  for (; j < nR; ++j) E[top++] = R[j];
-  return top;
-}
-
-__global__ __launch_bounds__(2 * kTileSlabs) void k_b_tiles(const int2 *__restrict__ work,
-                                                             const BCloud *cl) {
-  __shared__ uint32_t sE[2 * kSideWords];       // per side, per slab: a row of entries
-  __shared__ unsigned long long sVm[kTileSlabs], sSm[kTileSlabs];
-  __shared__ int sTop[2][kTileSlabs];
-  const int2 w = work[blockIdx.x];
-  const BCloud &A = cl[w.x];
-  const int p = A.p;
-  const int2 *const Lm = A.Lm;
-  uint64_t *const mask = A.mask;
-  int32_t *const slab_k = A.slab_k;
-  int32_t *const slab_s = A.slab_s;
-  const int64_t c0 = (int64_t)w.y * kTileCols;
-  const int ncol = (int)min<int64_t>(kTileCols, p - c0);
-  const int nslab = (ncol + kSlab - 1) / kSlab;
-  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-  constexpr int kIter = kTileSlabs / 2;
-  // columns -> entries and ballots (wave w takes slabs w, w + 2, ...)
-  int2 Lr[kIter];
-#pragma unroll
-  for (int k = 0; k < kIter; ++k) {
-    const int col = (2 * k + wave) * kSlab + lane;
-    Lr[k] = col < ncol ? Lm[c0 + col] : make_int2(1, 0);
-  }
-#pragma unroll
-  for (int k = 0; k < kIter; ++k) {
-    const int sl = 2 * k + wave;
-    const int col = sl * kSlab + lane;
-    const int2 L = Lr[k];
-    const bool valid = L.x <= L.y;
-    const unsigned long long vm = __ballot(valid);
-    const unsigned long long sm = __ballot(valid && L.x < L.y);
-    sE[sl * kRow + lane] = ((uint32_t)col << 16) | (uint32_t)(L.x - 1);
-    sE[kSideWords + sl * kRow + lane] = ((uint32_t)col << 16) | (uint32_t)(p - L.y);
-    if (lane == 0) {
-      sVm[sl] = vm;
-      sSm[sl] = sm;
-    }
-  }
-  __syncthreads();
-  if (tid < nslab) {
-    const int gs = w.y * kTileSlabs + tid;
-    const unsigned long long vm = sVm[tid];
-    if (mask) mask[gs] = vm;
-    slab_k[gs] = __popcll(vm);
-    slab_s[gs] = __popcll(vm) + __popcll(sSm[tid]);
-  }
-  // a lane per (slab, side): the slab's hull, in place over its row
-  {
-    const int sl = tid >> 1, side = tid & 1;
-    uint32_t *row = sE + side * kSideWords + sl * kRow;
-    unsigned long long vm = sVm[sl];
-    int top = 0;
-    int2 a = make_int2(0, 0), b = make_int2(0, 0);
-    while (vm) {
-      const int i = __ffsll((long long)vm) - 1;
-      vm &= vm - 1;
-      const uint32_t e = row[i];
-      const int2 v = TilePt()(e);
-      while (top >= 2 && !cross_pos<true>(a, b, v)) {
-        --top;
-        b = a;
-        if (top >= 2) a = TilePt()(row[top - 2]);
-      }
-      row[top++] = e;
-      a = b;
-      b = v;
-    }
-    sTop[side][sl] = top;
-  }
-  // binary merge tree over the slab hulls: at step h, the lane of (group g,
-  // side) joins the hulls of slabs g*2h and g*2h + h, leaving the result at
-  // the first one's row
-  for (int h = 1; h < kTileSlabs; h <<= 1) {
-    __syncthreads();
-    const int g = tid >> 1, side = tid & 1;
-    const int s0 = g * 2 * h, s1 = s0 + h;
-    if (s1 < nslab) {
-      uint32_t *E = sE + side * kSideWords + s0 * kRow;
-      sTop[side][s0] = merge_right<true>(E, sTop[side][s0], E + h * kRow, sTop[side][s1], TilePt());
-    }
-  }
-  __syncthreads();
-  // write the node's hulls (level 2, or level 1 when the cloud is one slab)
-  const TreeShape &T = A.tree;
-  const int lev = T.nlev >= 2 ? 2 : 1;
-  const int64_t x0 = c0 + 1;
-  int2 *const cand = A.cand;
-  const int span = T.span[lev];
-  for (int side = 0; side < 2; ++side) {
-    const int cnt = sTop[side][0];
-    const uint32_t *E = sE + side * kSideWords;
-    int2 *out = cand + (size_t)((lev - 1) & 1) * 2 * (size_t)p + (size_t)side * p + (size_t)w.y * span;
-    for (int j = tid; j < cnt; j += 2 * kTileSlabs) {
-      const uint32_t e = E[j];
-      const int y = (int)(e & 0xFFFFu);
-      out[j] = make_int2((int)(x0 + (e >> 16)), side ? y - p : y + 1);
-    }
-    if (tid == 0) A.ccount[side * T.nodes + T.base[lev] + w.y] = cnt;
-  }
-}
-
-// A wave per (node at level lev >= 3, side): the children's hulls (level
-// lev-1, buffer (lev-2)&1) staged in LDS in order and joined child by child
-// by lane 0, the result copied to the node's slot of buffer (lev-1)&1.  A
-// node whose children hold more than kNodeCap points is joined the same way
-// in global memory.
-template <bool SMALL>
-__global__ __launch_bounds__(kWave) void k_b_nodes(const int4 *__restrict__ work, const BCloud *cl,
-                                                   int lev) {
-  __shared__ int2 sP[kNodeCap];
-  __shared__ int sOff[kFanIn + 1];
-  __shared__ int sTop;
-  const int4 w = work[blockIdx.x];        // (cloud, node, side, -)
-  const BCloud &H = cl[w.x];
-  const TreeShape &T = H.tree;
-  const int node = w.y, side = w.z;
-  const int lane = threadIdx.x;
-  const int64_t P = H.p;
-  const int2 *in = H.cand + (size_t)((lev - 2) & 1) * 2 * P + (size_t)side * P;
-  int2 *out = H.cand + (size_t)((lev - 1) & 1) * 2 * P + (size_t)side * P + (size_t)node * T.span[lev];
-  const int c0 = node * kFanIn, nc = min(kFanIn, T.size[lev - 1] - c0);
-  const int32_t *cnt = H.ccount + side * T.nodes + T.base[lev - 1];
-  int32_t *const ccount_out = H.ccount + side * T.nodes + T.base[lev] + node;
-  const size_t span = (size_t)T.span[lev - 1];
-  // child offsets (wave scan)
-  const int mine = lane < nc ? cnt[c0 + lane] : 0;
-  int incl = mine;
-  for (int d = 1; d < kWave; d <<= 1) {
-    const int o = __shfl_up(incl, d, kWave);
-    if (lane >= d) incl += o;
-  }
-  const int m = __shfl(incl, kWave - 1, kWave);
-  sOff[lane] = incl - mine;
-  if (lane == 0) sOff[kFanIn] = m;
-  __syncthreads();
-  if (m <= kNodeCap) {
-    for (int j = lane; j < m; j += kWave) {
-      int lo = 0, hi = nc - 1;            // last child with sOff[c] <= j
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (sOff[mid] <= j) lo = mid;
-        else hi = mid - 1;
-      }
-      sP[j] = in[(size_t)(c0 + lo) * span + (j - sOff[lo])];
-    }
-    __syncthreads();
-    if (lane == 0) {
-      int top = sOff[1] - sOff[0];
-      for (int c = 1; c < nc; ++c)
-        top = merge_right<SMALL>(sP, top, sP + sOff[c], sOff[c + 1] - sOff[c], PlainPt());
-      sTop = top;
-    }
-    __syncthreads();
-    const int top = sTop;
-    for (int j = lane; j < top; j += kWave) out[j] = sP[j];
-    if (lane == 0) *ccount_out = top;
-    return;
-  }
-  if (lane != 0) return;
-  int top = 0;
-  for (int c = 0; c < nc; ++c)
-    top = merge_right<SMALL>(out, top, in + (size_t)(c0 + c) * span, cnt[c0 + c], PlainPt());
-  *ccount_out = top;
-}
-
-// Per cloud (one wave): slab offsets and totals, then the final hull from
-// the root's two sides (lower left to right, then upper back).
-__global__ __launch_bounds__(64) void k_b_root(const BCloud *cl) {
-  const BCloud &A = cl[blockIdx.x];
-  const TreeShape &T = A.tree;
-  const int lane = threadIdx.x;
-  const int nslab = T.size[1];
-  int carry = 0, stot = 0;
-  for (int base = 0; base < nslab; base += kWave) {
-    const int i = base + lane;
-    const int kk = i < nslab ? A.slab_k[i] : 0;
-    stot += i < nslab ? A.slab_s[i] : 0;
-    int incl = kk;
-    for (int d = 1; d < kWave; d <<= 1) {
-      const int o = __shfl_up(incl, d, kWave);
-      if (lane >= d) incl += o;
-    }
-    if (i < nslab) A.slab_off[i] = carry + incl - kk;
-    carry += __shfl(incl, kWave - 1, kWave);
-  }
-  for (int d = kWave / 2; d > 0; d >>= 1) stot += __shfl_xor(stot, d, kWave);
-  const int64_t P = A.p;
-  const int2 *root = A.cand + (size_t)((T.nlev - 1) & 1) * 2 * P;
-  const int nl = A.ccount[0 * T.nodes + T.base[T.nlev]];
-  const int nu = A.ccount[1 * T.nodes + T.base[T.nlev]];
-  bool overflow = false;
-  const int h = assemble_hull(root, nl, root + P, nu, A.hx, A.hy, A.hull_cap, overflow);
-  if (lane == 0) {
-    A.info[HP_INFO_K] = carry;
-    A.info[HP_INFO_S] = stot;
-    A.info[HP_INFO_H] = overflow ? 0 : h;
-    if (overflow) atomicMin(&A.info[HP_INFO_STATUS], HP_ECAPACITY);
-  }
-}
-
-// Per slab (one wave): its valid columns at the scanned offset.
-__global__ __launch_bounds__(256) void k_b_chain(const int2 *__restrict__ work, int nwork,
-                                                 const BCloud *cl) {
-  const int t = blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
-  if (t >= nwork) return;
-  const int2 w = work[t];
-  const BCloud &A = cl[w.x];
-  write_chain_slab(A.Lm, A.p, A.slab_off, w.y, A.cx, A.clo, A.chi, A.chain_cap, A.info);
 }
 
 // ---------------------------------------------------------------------------
@@ -1496,7 +956,10 @@ static hipError_t launch_hull_levels(const TreeShape &T, int64_t positions, char
   H.tree = T;
   H.positions = (int32_t)positions;
   for (int lev = 2; lev <= T.nlev; ++lev) {
-    const dim3 gt(T.size[lev - 1] * kSplit), gc(T.size[lev]);
+    // slabs hold few vertices: one test workgroup each; nodes above
+    // hold more and get kSplit
+    H.split = lev == 2 ? kSplitSlab : kSplit;
+    const dim3 gt(T.size[lev - 1] * H.split), gc(T.size[lev]);
     if (small) {
       hipLaunchKernelGGL((k_hull_test<true>), gt, dim3(kHullBlock), 0, s, H, lev);
       hipLaunchKernelGGL((k_hull_compact<true>), gc, dim3(kHullBlock), 0, s, H, lev);
@@ -1624,50 +1087,6 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
 }
 
 void tree_shape(int64_t positions, TreeShape *out) { *out = make_tree(positions); }
-
-hipError_t launch_b_fill(int B, const BCloud *cl, const uint8_t *needs_fill, int32_t *counter,
-                         hipStream_t s) {
-  hipLaunchKernelGGL(k_b_fill, dim3(B), dim3(256), 0, s, cl, needs_fill, counter);
-  return hipGetLastError();
-}
-
-hipError_t prepare_b_reduce() {
-  return hipFuncSetAttribute((const void *)k_b_reduce<1024, 4>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             device_info().lds_bytes - 64);
-}
-
-hipError_t launch_b_reduce(int grid, size_t lds_bytes, const BatchItem *items, int32_t nitems,
-                           int32_t *counter, const BCloud *cl, hipStream_t s) {
-  if (nitems <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_b_reduce<1024, 4>), dim3(grid), dim3(1024), lds_bytes, s, items, nitems, counter, cl);
-  return hipGetLastError();
-}
-
-hipError_t launch_b_tiles(int ntiles, const int2 *tiles, const BCloud *cl, hipStream_t s) {
-  if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_b_tiles, dim3(ntiles), dim3(2 * kTileSlabs), 0, s, tiles, cl);
-  return hipGetLastError();
-}
-
-hipError_t launch_b_nodes(bool small, int lev, int nwork, const int4 *work, const BCloud *cl,
-                          hipStream_t s) {
-  if (nwork <= 0) return hipSuccess;
-  if (small) hipLaunchKernelGGL((k_b_nodes<true>), dim3(nwork), dim3(kWave), 0, s, work, cl, lev);
-  else hipLaunchKernelGGL((k_b_nodes<false>), dim3(nwork), dim3(kWave), 0, s, work, cl, lev);
-  return hipGetLastError();
-}
-
-hipError_t launch_b_root(int B, const BCloud *cl, hipStream_t s) {
-  if (B <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_b_root, dim3(B), dim3(64), 0, s, cl);
-  return hipGetLastError();
-}
-
-hipError_t launch_b_chain(int nwork, const int2 *work, const BCloud *cl, hipStream_t s) {
-  if (nwork <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_b_chain, dim3((nwork + 3) / 4), dim3(256), 0, s, work, nwork, cl);
-  return hipGetLastError();
-}
 
 size_t single_ws_bytes(int64_t n, int32_t p) { return ws_bytes_for(n, p); }
 
