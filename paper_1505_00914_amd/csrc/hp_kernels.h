@@ -140,7 +140,9 @@ struct FinishArgs {
 // Arguments of the hull levels above the slabs for one cloud.
 struct HullArgs {
   int2 *buf[2];             // [2 sides][positions] each
-  uint8_t *keep;            // [2 * positions] survival flags of the current level
+  uint8_t *keep;            // [2][keep_side] survival flags of the current level
+  int64_t keep_side;        // bytes per side of keep (positions rounded up to 4096)
+  int32_t *l2cnt;           // [level-2 nodes][test shares][2] survivor counts
   int32_t *ccount;          // [2][nodes] hull sizes of nodes
   TreeShape tree;
   int32_t positions;

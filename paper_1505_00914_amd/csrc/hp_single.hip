@@ -775,6 +775,284 @@ __global__ __launch_bounds__(256) void k_chain(const int2 *__restrict__ Lm, int3
 }
 
 // ---------------------------------------------------------------------------
+// Level 2 of clouds with at most kL2MaxSlabs slabs.  A level-2 node's
+// slab-hull vertices (at most 64 x 64 per side) are staged compacted, in x
+// order, in LDS.  Every vertex v is then tested against all the node's other
+// vertices of its side at once: with uL the one left of v that maximises
+// slope(uL, v) and wR the one right of v that minimises slope(v, wR), v is a
+// strict lower-hull vertex iff (uL, v, wR) turns strictly left (or one of
+// them does not exist).  Exact integer comparisons throughout.  The test
+// launch also writes the chain; the compaction launch keeps the survivors
+// in order (the node's hulls), assembles the final hull at the root and
+// writes k, s and the range status.
+// ---------------------------------------------------------------------------
+constexpr int kL2MaxSlabs = 1024;            // the path serves p <= 65536
+constexpr int kNodeVerts = kFanIn * kSlab;   // 4096 positions per level-2 node
+constexpr int kL2Waves = kHullBlock / kWave; // one tested vertex per wave
+
+struct L2Shared {
+  int2 P[2][kNodeVerts];     // the node's vertices per side, compacted in x order
+  int cnt[2][kFanIn];        // per slab: hull size
+  int off[2][kFanIn + 1];    // per slab: first compacted index (off[.][64] = count)
+  uint32_t keepw[2][kNodeVerts / 4];
+  int tmp[kL2Waves];
+  int sum[3];
+};
+
+// The node's slots (every position of its slabs, both sides) and the slab
+// hull sizes in one round of loads (and, with KEEP, the survival bytes of
+// the compacted vertices), then the vertices compacted in place in x order.
+template <bool KEEP>
+__device__ __forceinline__ void l2_stage(const HullArgs &H, L2Shared &S, int node) {
+  constexpr int kPer = 2 * kNodeVerts / kHullBlock;   // 8 slots per thread
+  const TreeShape &T = H.tree;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  const int sib0 = node * kFanIn, nsib = min(kFanIn, T.size[1] - sib0);
+  const int64_t P = H.positions;
+  const int64_t first = (int64_t)sib0 * kSlab;
+  const int2 *in = H.buf[0];
+  int2 v[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int idx = tid + u * kHullBlock;
+    const int side = idx / kNodeVerts, pos = idx % kNodeVerts;
+    if (first + pos < P) v[u] = in[(size_t)side * P + first + pos];
+  }
+  int m = 0;
+  if (wave < 2 && lane < nsib) m = H.ccount[wave * T.nodes + T.base[1] + sib0 + lane];
+  // survival bytes: kNodeVerts per side, as words, two per thread
+  uint32_t kw[2] = {0, 0};
+  if (KEEP) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int idx = tid + u * kHullBlock;
+      const int side = idx / (kNodeVerts / 4), w = idx % (kNodeVerts / 4);
+      kw[u] = reinterpret_cast<const uint32_t *>(H.keep + (size_t)side * H.keep_side + (size_t)node * kNodeVerts)[w];
+    }
+  }
+  if (wave < 2) {
+    int incl = m;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const int o = __shfl_up(incl, d, kWave);
+      if (lane >= d) incl += o;
+    }
+    S.cnt[wave][lane] = m;
+    S.off[wave][lane] = incl - m;
+    if (lane == kWave - 1) S.off[wave][kFanIn] = incl;
+  }
+  if (KEEP) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int idx = tid + u * kHullBlock;
+      S.keepw[idx / (kNodeVerts / 4)][idx % (kNodeVerts / 4)] = kw[u];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int idx = tid + u * kHullBlock;
+    const int side = idx / kNodeVerts, pos = idx % kNodeVerts;
+    const int t = pos / kSlab, r = pos % kSlab;
+    if (t < nsib && r < S.cnt[side][t]) S.P[side][S.off[side][t] + r] = v[u];
+  }
+  __syncthreads();
+}
+
+// Chain of slab `sl` by one wave, without barriers: its offset is the sum
+// of the counts of every earlier slab (at most kL2MaxSlabs).
+__device__ __forceinline__ void l2_chain_slab(const HullArgs &H, int sl) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t pos = (int64_t)sl * kSlab + lane;
+  const int2 L = pos < H.p ? H.Lm[pos] : make_int2(1, 0);
+  int base = 0;
+  for (int j = lane; j < sl; j += kWave) base += H.slab_k[j];
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) base += __shfl_xor(base, d, kWave);
+  const bool valid = L.x <= L.y;
+  int tot;
+  const int r = wave_rank(valid, &tot);
+  if (valid) {
+    const int o = base + r;
+    if (o < H.chain_cap) {
+      H.cx[o] = (int)pos + 1;
+      H.clo[o] = L.x;
+      H.chi[o] = L.y;
+    } else {
+      atomicMin(&H.info[HP_INFO_STATUS], HP_ECAPACITY);
+    }
+  }
+}
+
+// k, s and the range status of the whole cloud (one workgroup).
+__device__ __forceinline__ void l2_totals(const HullArgs &H, L2Shared &S) {
+  const int tid = threadIdx.x, lane = tid & (kWave - 1);
+  if (tid < 3) S.sum[tid] = 0;
+  __syncthreads();
+  int kk = 0, ss = 0, err = 0;
+  for (int j = tid; j < H.tree.size[1]; j += kHullBlock) {
+    kk += H.slab_k[j];
+    ss += H.slab_s[j];
+  }
+  for (int j = tid; j < H.n_wg_err; j += kHullBlock) err |= H.wg_err[j];
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    kk += __shfl_xor(kk, d, kWave);
+    ss += __shfl_xor(ss, d, kWave);
+    err |= __shfl_xor(err, d, kWave);
+  }
+  if (lane == 0) {
+    atomicAdd(&S.sum[0], kk);
+    atomicAdd(&S.sum[1], ss);
+    if (err) atomicOr(&S.sum[2], err);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    H.info[HP_INFO_K] = S.sum[0];
+    H.info[HP_INFO_S] = S.sum[1];
+    if (S.sum[2] & kErrRange) atomicMin(&H.info[HP_INFO_STATUS], HP_ERANGE);
+  }
+}
+
+// H.split workgroups per level-2 node.  Each tests its share of the node's
+// vertices (one wave per vertex), writes its survivors in order to the
+// node's slot of buffer 1 at its share's first index, with their count per
+// side in l2cnt, and writes the chain of its share of the node's slabs.
+template <bool SMALL>
+__global__ __launch_bounds__(kHullBlock) void k_l2_test(HullArgs H) {
+  __shared__ L2Shared S;
+  const int parts = H.split;
+  const int node = blockIdx.x / parts, part = blockIdx.x % parts;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  const TreeShape &T = H.tree;
+  if (blockIdx.x == 0) l2_totals(H, S);
+  l2_stage<false>(H, S, node);
+  const int C0 = S.off[0][kFanIn], C1 = S.off[1][kFanIn], total = C0 + C1;
+  const int per = (total + parts - 1) / parts;
+  const int q0 = min(total, part * per), q1 = min(total, q0 + per);
+  uint8_t *flag = reinterpret_cast<uint8_t *>(S.keepw);   // this share's verdicts
+  for (int q = q0 + wave; q < q1; q += kL2Waves) {
+    const int side = q < C0 ? 0 : 1;
+    const int i = side ? q - C0 : q;
+    const int cs = side ? C1 : C0;
+    const int2 *Pp = S.P[side];
+    const int2 v = Pp[i];
+    // lanes scan the vertices left of v and right of v; an empty extreme
+    // stays at v itself (same x), which the merge below never prefers
+    int2 uL = v, wR = v;
+    for (int k = lane; k < i; k += kWave) {
+      const int2 u = Pp[k];
+      if (uL.x == v.x || steeper_left<SMALL>(u, uL, v)) uL = u;
+    }
+    for (int k = i + 1 + lane; k < cs; k += kWave) {
+      const int2 w = Pp[k];
+      if (wR.x == v.x || flatter_right<SMALL>(w, wR, v)) wR = w;
+    }
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+      const int2 ou = make_int2(__shfl_xor(uL.x, d, kWave), __shfl_xor(uL.y, d, kWave));
+      const int2 ow = make_int2(__shfl_xor(wR.x, d, kWave), __shfl_xor(wR.y, d, kWave));
+      if (ou.x != v.x && (uL.x == v.x || steeper_left<SMALL>(ou, uL, v))) uL = ou;
+      if (ow.x != v.x && (wR.x == v.x || flatter_right<SMALL>(ow, wR, v))) wR = ow;
+    }
+    if (lane == 0) flag[q - q0] = (uL.x == v.x || wR.x == v.x || cross_pos<SMALL>(uL, v, wR)) ? 1 : 0;
+  }
+  __syncthreads();
+  // survivors of each side of the share, in order (waves 0 and 1; a share
+  // is at most a few hundred vertices)
+  if (wave < 2) {
+    const int side = wave;
+    const int a = side ? max(q0, C0) : q0, b = side ? q1 : min(q1, C0);   // share in q space
+    const int first = side ? a - C0 : a;                                    // in side index space
+    int2 *out = H.buf[1] + (size_t)side * H.positions + (size_t)node * T.span[2] + first;
+    int n = 0;
+    for (int q = a; q < b; q += kWave) {
+      const bool keep = q + lane < b && flag[q + lane - q0] != 0;
+      int tot;
+      const int r = wave_rank(keep, &tot);
+      if (keep) out[n + r] = S.P[side][(side ? q - C0 : q) + lane];
+      n += tot;
+    }
+    if (lane == 0) H.l2cnt[((size_t)node * parts + part) * 2 + side] = n;
+  }
+  // chain of this workgroup's slabs, one wave each
+  const int per_slabs = (kFanIn + parts - 1) / parts;
+  const int sl = node * kFanIn + part * per_slabs + wave;
+  if (wave < per_slabs && part * per_slabs + wave < kFanIn && sl < T.size[1]) l2_chain_slab(H, sl);
+}
+
+// One workgroup per level-2 node: the shares' survivors joined in order
+// (the node's hulls in buffer 1), or, at the root, the final vertex list.
+template <bool SMALL>
+__global__ __launch_bounds__(kHullBlock) void k_l2_compact(HullArgs H) {
+  __shared__ L2Shared S;
+  const int node = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  const TreeShape &T = H.tree;
+  const int parts = H.split;
+  const int64_t P = H.positions;
+  // per side: the shares' counts and their prefix; the shares' first
+  // indices follow from the staged counts of the test (per = ceil(C/parts))
+  if (wave < 2) {
+    const int side = wave;
+    const int m = lane < parts ? H.l2cnt[((size_t)node * parts + lane) * 2 + side] : 0;
+    int incl = m;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const int o = __shfl_up(incl, d, kWave);
+      if (lane >= d) incl += o;
+    }
+    S.cnt[side][lane] = m;
+    S.off[side][lane] = incl - m;
+    if (lane == kWave - 1) S.off[side][kFanIn] = incl;
+  }
+  // the test's share boundaries need C0 and C1: the node's slab-hull sizes
+  if (wave == 2 || wave == 3) {
+    const int side = wave - 2;
+    const int sib0 = node * kFanIn, nsib = min(kFanIn, T.size[1] - sib0);
+    int m = lane < nsib ? H.ccount[side * T.nodes + T.base[1] + sib0 + lane] : 0;
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) m += __shfl_xor(m, d, kWave);
+    if (lane == 0) S.sum[side] = m;
+  }
+  __syncthreads();
+  const int C0 = S.sum[0], C1 = S.sum[1], total = C0 + C1;
+  const int per = (total + parts - 1) / parts;
+  // gather every survivor: thread t takes survivors t, t + 1024, ...
+  int nk[2];
+  int2 *node_out = H.buf[1] + (size_t)node * T.span[2];
+  for (int side = 0; side < 2; ++side) {
+    const int all = S.off[side][kFanIn];
+    nk[side] = all;
+    for (int j = tid; j < all; j += kHullBlock) {
+      int lo = 0, hi = parts - 1;          // last share with off <= j
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (S.off[side][mid] <= j) lo = mid;
+        else hi = mid - 1;
+      }
+      const int q0 = min(total, lo * per);
+      const int first = side ? max(q0, C0) - C0 : q0;
+      S.P[side][j] = node_out[(size_t)side * P + first + (j - S.off[side][lo])];
+    }
+  }
+  __syncthreads();
+  const bool root = T.nlev == 2;
+  if (!root) {
+    for (int side = 0; side < 2; ++side)
+      for (int j = tid; j < nk[side]; j += kHullBlock) node_out[(size_t)side * P + j] = S.P[side][j];
+    if (tid < 2) H.ccount[tid * T.nodes + T.base[2] + node] = nk[tid];
+    return;
+  }
+  bool overflow = false;
+  const int h = assemble_hull(S.P[0], nk[0], S.P[1], nk[1], H.hx, H.hy, H.hull_cap, overflow);
+  if (tid == 0) {
+    H.info[HP_INFO_H] = overflow ? 0 : h;
+    if (overflow) atomicMin(&H.info[HP_INFO_STATUS], HP_ECAPACITY);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
 static TreeShape make_tree(int64_t positions) {
@@ -798,7 +1076,7 @@ static TreeShape make_tree(int64_t positions) {
 }
 
 struct Layout {
-  size_t ctl, tree, wg_err, slab_k, slab_s, slab_off, Lm, part, cand, keep, ccount, total;
+  size_t ctl, tree, wg_err, slab_k, slab_s, slab_off, Lm, part, cand, keep, l2cnt, ccount, total;
 };
 
 static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -809,6 +1087,13 @@ constexpr int kMaxGrid = 4096;
 constexpr int32_t kChainInline = 32768;
 // Single cloud: largest slab count whose chain the root compaction writes.
 constexpr int32_t kSingleRootChainSlabs = 256;
+
+// Survival bytes per side: positions rounded up to whole level-2 nodes, so
+// the level-2 test's flags (node * 4096 + vertex) stay in range and aligned.
+static size_t keep_side_bytes(int64_t positions) {
+  const int64_t P = positions < 1 ? 1 : positions;
+  return (size_t)((P + kNodeVerts - 1) / kNodeVerts) * kNodeVerts;
+}
 
 static Layout make_layout(int64_t positions, int32_t p, int64_t part_pairs, const TreeShape &T) {
   Layout Y;
@@ -822,7 +1107,8 @@ static Layout make_layout(int64_t positions, int32_t p, int64_t part_pairs, cons
   Y.Lm = o;       o = align_up(o + sizeof(int2) * (size_t)(p > 0 ? p : 0));
   Y.part = o;     o = align_up(o + sizeof(int2) * (size_t)part_pairs);
   Y.cand = o;     o = align_up(o + sizeof(int2) * 4 * (size_t)positions);
-  Y.keep = o;     o = align_up(o + 2 * (size_t)positions);
+  Y.keep = o;     o = align_up(o + 2 * keep_side_bytes(positions));
+  Y.l2cnt = o;    o = align_up(o + sizeof(int32_t) * 2 * kFanIn * (size_t)(T.nlev >= 2 ? T.size[2] : 1));
   Y.ccount = o;   o = align_up(o + sizeof(int32_t) * 2 * (size_t)T.nodes);
   Y.total = o;
   return Y;
@@ -947,17 +1233,36 @@ static hipError_t dispatch_reduce(const Plan1 &P, const int32_t *pts, int64_t n,
 // Hull levels 2..nlev: a test launch and a compaction launch per level (the
 // slab level ran in k_finish).  H must have its chain fields filled.
 static hipError_t launch_hull_levels(const TreeShape &T, int64_t positions, char *w, const Layout &Y,
-                                     HullArgs H, bool small, hipStream_t s) {
+                                     HullArgs H, bool small, hipStream_t s, bool l2path = false) {
   if (T.nlev < 2) return hipSuccess;
   H.buf[0] = reinterpret_cast<int2 *>(w + Y.cand);
   H.buf[1] = H.buf[0] + 2 * (size_t)positions;
   H.keep = reinterpret_cast<uint8_t *>(w + Y.keep);
+  H.keep_side = (int64_t)keep_side_bytes(positions);
+  H.l2cnt = reinterpret_cast<int32_t *>(w + Y.l2cnt);
   H.ccount = reinterpret_cast<int32_t *>(w + Y.ccount);
   H.tree = T;
   H.positions = (int32_t)positions;
-  for (int lev = 2; lev <= T.nlev; ++lev) {
-    // slabs hold few vertices: one test workgroup each; nodes above
-    // hold more and get kSplit
+  int first = 2;
+  if (l2path) {
+    // level 2 by the all-vertex test, which also writes the chain and the
+    // totals (H carries the chain fields and the slab counts)
+    // test workgroups per node: about 512 in all, 4 to 64 per node
+    H.split = std::max(4, std::min(64, 512 / T.size[2]));
+    const dim3 gt(T.size[2] * H.split), gc(T.size[2]);
+    if (small) {
+      hipLaunchKernelGGL((k_l2_test<true>), gt, dim3(kHullBlock), 0, s, H);
+      hipLaunchKernelGGL((k_l2_compact<true>), gc, dim3(kHullBlock), 0, s, H);
+    } else {
+      hipLaunchKernelGGL((k_l2_test<false>), gt, dim3(kHullBlock), 0, s, H);
+      hipLaunchKernelGGL((k_l2_compact<false>), gc, dim3(kHullBlock), 0, s, H);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    first = 3;
+  }
+  for (int lev = first; lev <= T.nlev; ++lev) {
+    // slab children get kSplitSlab test workgroups each, node children kSplit
     H.split = lev == 2 ? kSplitSlab : kSplit;
     const dim3 gt(T.size[lev - 1] * H.split), gc(T.size[lev]);
     if (small) {
@@ -1038,10 +1343,13 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
   A.info = info;
   A.wg_err = wg_err;
   A.n_wg_err = P.G;
-  // with a two-level hull tree and few slabs the root compaction writes
-  // the chain; otherwise the last slab scans and writes it
-  const bool fused = do_hull && T.nlev == 2 && T.size[1] <= kSingleRootChainSlabs;
-  A.scan_root = fused ? 0 : 1;
+  // With the hull and at most kL2MaxSlabs slabs, level 2 is the
+  // all-vertex test, which writes the chain and the totals.  Otherwise, with
+  // a two-level tree and few slabs the root compaction writes the chain, and
+  // in every other case the last slab scans and writes it.
+  const bool l2path = do_hull && T.nlev >= 2 && T.size[1] <= kL2MaxSlabs;
+  const bool fused = !l2path && do_hull && T.nlev == 2 && T.size[1] <= kSingleRootChainSlabs;
+  A.scan_root = (fused || l2path) ? 0 : 1;
   A.chain_inline = p <= kChainInline ? 1 : 0;
   A.cx_out = cx;
   A.clo_out = clo;
@@ -1055,7 +1363,7 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
     hipLaunchKernelGGL((k_finish<0, false>), dim3(T.size[1]), dim3(kFinBlock), 0, s, A);
   e = hipGetLastError();
   if (e != hipSuccess) return set_error(HP_EDEVICE, "k_finish launch: %s", hipGetErrorString(e));
-  if (!fused && !A.chain_inline) {
+  if (!fused && !l2path && !A.chain_inline) {
     const int nslab = T.size[1];
     hipLaunchKernelGGL(k_chain, dim3((nslab + 3) / 4), dim3(256), 0, s, Lm, p, A.slab_off, nslab, cx,
                        clo, chi, chain_cap, info);
@@ -1070,6 +1378,7 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
     H.hull_cap = hull_cap;
     H.info = info;
     H.chain_fused = fused ? 1 : 0;
+    H.split = kSplit;
     H.Lm = Lm;
     H.p = p;
     H.slab_k = A.slab_k;
@@ -1080,7 +1389,7 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
     H.clo = clo;
     H.chi = chi;
     H.chain_cap = chain_cap;
-    e = launch_hull_levels(T, p, w, Y, H, small, s);
+    e = launch_hull_levels(T, p, w, Y, H, small, s, l2path);
     if (e != hipSuccess) return set_error(HP_EDEVICE, "hull level launch: %s", hipGetErrorString(e));
   }
   return HP_OK;
