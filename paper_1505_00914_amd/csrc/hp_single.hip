@@ -790,10 +790,14 @@ constexpr int kL2MaxSlabs = 1024;            // the path serves p <= 65536
 constexpr int kNodeVerts = kFanIn * kSlab;   // 4096 positions per level-2 node
 constexpr int kL2Waves = kHullBlock / kWave; // one tested vertex per wave
 
+constexpr int kL2MaxParts = 128;             // test workgroups per node, at most
+constexpr int kL2TargetWgs = 512;            // test workgroups per launch, about
+
 struct L2Shared {
   int2 P[2][kNodeVerts];     // the node's vertices per side, compacted in x order
   int cnt[2][kFanIn];        // per slab: hull size
   int off[2][kFanIn + 1];    // per slab: first compacted index (off[.][64] = count)
+  int soff[2][kL2MaxParts + 1];  // per test share: first survivor index
   uint32_t keepw[2][kNodeVerts / 4];
   int tmp[kL2Waves];
   int sum[3];
@@ -914,6 +918,29 @@ __device__ __forceinline__ void l2_totals(const HullArgs &H, L2Shared &S) {
   }
 }
 
+// One step of a wave reduction: every lane receives the value of the lane
+// selected by the DPP control CTRL (rows outside ROWS keep their own).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int2 dpp_pair(int2 a) {
+  return make_int2(__builtin_amdgcn_update_dpp(a.x, a.x, CTRL, ROWS, 0xf, false),
+                   __builtin_amdgcn_update_dpp(a.y, a.y, CTRL, ROWS, 0xf, false));
+}
+
+// Wave-wide reduction of a point by an idempotent choice `pick` (quad
+// swaps, rotations by 4 and 8 within each row of 16, then the last lane of
+// each row carried to the next rows); the result, read from lane 63, is
+// uniform.
+template <typename Pick>
+__device__ __forceinline__ int2 wave_pick(int2 a, Pick pick) {
+  a = pick(a, dpp_pair<0xb1, 0xf>(a));    // quad_perm 1,0,3,2
+  a = pick(a, dpp_pair<0x4e, 0xf>(a));    // quad_perm 2,3,0,1
+  a = pick(a, dpp_pair<0x124, 0xf>(a));   // row_ror 4
+  a = pick(a, dpp_pair<0x128, 0xf>(a));   // row_ror 8
+  a = pick(a, dpp_pair<0x142, 0xa>(a));   // row_bcast 15 into rows 1 and 3
+  a = pick(a, dpp_pair<0x143, 0xc>(a));   // row_bcast 31 into rows 2 and 3
+  return make_int2(__builtin_amdgcn_readlane(a.x, 63), __builtin_amdgcn_readlane(a.y, 63));
+}
+
 // H.split workgroups per level-2 node.  Each tests its share of the node's
 // vertices (one wave per vertex), writes its survivors in order to the
 // node's slot of buffer 1 at its share's first index, with their count per
@@ -948,13 +975,12 @@ __global__ __launch_bounds__(kHullBlock) void k_l2_test(HullArgs H) {
       const int2 w = Pp[k];
       if (wR.x == v.x || flatter_right<SMALL>(w, wR, v)) wR = w;
     }
-#pragma unroll
-    for (int d = kWave / 2; d > 0; d >>= 1) {
-      const int2 ou = make_int2(__shfl_xor(uL.x, d, kWave), __shfl_xor(uL.y, d, kWave));
-      const int2 ow = make_int2(__shfl_xor(wR.x, d, kWave), __shfl_xor(wR.y, d, kWave));
-      if (ou.x != v.x && (uL.x == v.x || steeper_left<SMALL>(ou, uL, v))) uL = ou;
-      if (ow.x != v.x && (wR.x == v.x || flatter_right<SMALL>(ow, wR, v))) wR = ow;
-    }
+    uL = wave_pick(uL, [&](int2 a, int2 b) {
+      return b.x != v.x && (a.x == v.x || steeper_left<SMALL>(b, a, v)) ? b : a;
+    });
+    wR = wave_pick(wR, [&](int2 a, int2 b) {
+      return b.x != v.x && (a.x == v.x || flatter_right<SMALL>(b, a, v)) ? b : a;
+    });
     if (lane == 0) flag[q - q0] = (uL.x == v.x || wR.x == v.x || cross_pos<SMALL>(uL, v, wR)) ? 1 : 0;
   }
   __syncthreads();
@@ -995,16 +1021,20 @@ __global__ __launch_bounds__(kHullBlock) void k_l2_compact(HullArgs H) {
   // indices follow from the staged counts of the test (per = ceil(C/parts))
   if (wave < 2) {
     const int side = wave;
-    const int m = lane < parts ? H.l2cnt[((size_t)node * parts + lane) * 2 + side] : 0;
-    int incl = m;
+    int carry = 0;
+    for (int h = 0; h < kL2MaxParts; h += kWave) {
+      const int sh = h + lane;
+      const int m = sh < parts ? H.l2cnt[((size_t)node * parts + sh) * 2 + side] : 0;
+      int incl = m;
 #pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-      const int o = __shfl_up(incl, d, kWave);
-      if (lane >= d) incl += o;
+      for (int d = 1; d < kWave; d <<= 1) {
+        const int o = __shfl_up(incl, d, kWave);
+        if (lane >= d) incl += o;
+      }
+      S.soff[side][sh] = carry + incl - m;
+      carry += __shfl(incl, kWave - 1, kWave);
     }
-    S.cnt[side][lane] = m;
-    S.off[side][lane] = incl - m;
-    if (lane == kWave - 1) S.off[side][kFanIn] = incl;
+    if (lane == 0) S.soff[side][kL2MaxParts] = carry;
   }
   // the test's share boundaries need C0 and C1: the node's slab-hull sizes
   if (wave == 2 || wave == 3) {
@@ -1022,18 +1052,18 @@ __global__ __launch_bounds__(kHullBlock) void k_l2_compact(HullArgs H) {
   int nk[2];
   int2 *node_out = H.buf[1] + (size_t)node * T.span[2];
   for (int side = 0; side < 2; ++side) {
-    const int all = S.off[side][kFanIn];
+    const int all = S.soff[side][kL2MaxParts];
     nk[side] = all;
     for (int j = tid; j < all; j += kHullBlock) {
-      int lo = 0, hi = parts - 1;          // last share with off <= j
+      int lo = 0, hi = parts - 1;          // last share with soff <= j
       while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (S.off[side][mid] <= j) lo = mid;
+        if (S.soff[side][mid] <= j) lo = mid;
         else hi = mid - 1;
       }
       const int q0 = min(total, lo * per);
       const int first = side ? max(q0, C0) - C0 : q0;
-      S.P[side][j] = node_out[(size_t)side * P + first + (j - S.off[side][lo])];
+      S.P[side][j] = node_out[(size_t)side * P + first + (j - S.soff[side][lo])];
     }
   }
   __syncthreads();
@@ -1108,7 +1138,7 @@ static Layout make_layout(int64_t positions, int32_t p, int64_t part_pairs, cons
   Y.part = o;     o = align_up(o + sizeof(int2) * (size_t)part_pairs);
   Y.cand = o;     o = align_up(o + sizeof(int2) * 4 * (size_t)positions);
   Y.keep = o;     o = align_up(o + 2 * keep_side_bytes(positions));
-  Y.l2cnt = o;    o = align_up(o + sizeof(int32_t) * 2 * kFanIn * (size_t)(T.nlev >= 2 ? T.size[2] : 1));
+  Y.l2cnt = o;    o = align_up(o + sizeof(int32_t) * 2 * kL2MaxParts * (size_t)(T.nlev >= 2 ? T.size[2] : 1));
   Y.ccount = o;   o = align_up(o + sizeof(int32_t) * 2 * (size_t)T.nodes);
   Y.total = o;
   return Y;
@@ -1247,8 +1277,8 @@ static hipError_t launch_hull_levels(const TreeShape &T, int64_t positions, char
   if (l2path) {
     // level 2 by the all-vertex test, which also writes the chain and the
     // totals (H carries the chain fields and the slab counts)
-    // test workgroups per node: about 512 in all, 4 to 64 per node
-    H.split = std::max(4, std::min(64, 512 / T.size[2]));
+    // test workgroups per node: about kL2TargetWgs in all, 4 to kL2MaxParts per node
+    H.split = std::max(4, std::min(kL2MaxParts, kL2TargetWgs / T.size[2]));
     const dim3 gt(T.size[2] * H.split), gc(T.size[2]);
     if (small) {
       hipLaunchKernelGGL((k_l2_test<true>), gt, dim3(kHullBlock), 0, s, H);
