@@ -31,6 +31,15 @@ __device__ __forceinline__ void fold_point_lds(int2 *L, int p, int x, int y, boo
   if (ok && y > cur.y) atomicMax(&L[c].y, y);
 }
 
+// A partial L entry in 32 bits: lo - 1 in the low half, hi + 1 in the high
+// half (the sentinel (p+1, -1) becomes (p, 0)); valid for p < 65535.
+__device__ __forceinline__ uint32_t pack_partial(int2 L) {
+  return (uint32_t)(L.x - 1) | ((uint32_t)(L.y + 1) << 16);
+}
+__device__ __forceinline__ int2 unpack_partial(uint32_t w) {
+  return make_int2((int)(w & 0xFFFFu) + 1, (int)(w >> 16) - 1);
+}
+
 // A coherent 8-byte read of an (lo, hi) pair that other workgroups update
 // with device-scope atomics (a plain load could keep hitting a stale cache
 // line, which would defeat the filter without breaking correctness).
@@ -106,8 +115,9 @@ __device__ __forceinline__ void apply(int2 *L, const Batch<VPT> &b) {
 
 struct FinishArgs {
   // source: merged partial L (from_chain == 0) or a chain (from_chain == 1)
-  const int2 *part;       // G partial L arrays of p pairs each (or the global L)
+  const int2 *part;       // G partial L arrays of p packed words each (or the global L)
   int32_t G;
+  int32_t packed;         // part holds packed partial words (pack_partial)
   const int32_t *cx, *clo, *chi;  // chain source
   int32_t positions;      // p, or chain capacity
   int32_t p;

@@ -124,8 +124,10 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_lds(const int32_t *__restrict_
         __hip_atomic_fetch_max(&out_L[c].y, mine.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   } else {
-    int2 *out = out_L + (size_t)blockIdx.x * (size_t)p;
-    for (int c = threadIdx.x; c < p; c += BLOCK) out[c] = sL[c];
+    // the partial L packs (lo - 1, hi + 1) into 16 bits each (p is below
+    // the LDS limit, far below 2^16 - 1): half the bytes of the pairs
+    uint32_t *out = reinterpret_cast<uint32_t *>(out_L) + (size_t)blockIdx.x * (size_t)p;
+    for (int c = threadIdx.x; c < p; c += BLOCK) out[c] = pack_partial(sL[c]);
   }
   if (threadIdx.x == 0) wg_err[blockIdx.x] = s_bad ? kErrRange : 0;
 }

@@ -120,22 +120,30 @@ __device__ __forceinline__ void finish_body(const FinishArgs &A, FinishShared &S
   bool valid = false;
   if (!FROM_CHAIN) {
     int mlo = INT_MAX, mhi = INT_MIN;
-    if (inside) {
-      const int2 *src = A.part + pos;
+    if (inside && A.packed) {
+      const uint32_t *src = reinterpret_cast<const uint32_t *>(A.part) + pos;
       const int G = A.G;
       int g = grp;
       // kFinGroups threads per column, 16 independent loads in flight each
       for (; g + 15 * kFinGroups < G; g += 16 * kFinGroups) {
-        int2 a[16];
+        uint32_t a[16];
 #pragma unroll
         for (int u = 0; u < 16; ++u) a[u] = src[(size_t)(g + kFinGroups * u) * A.p];
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
-          mlo = min(mlo, a[u].x);
-          mhi = max(mhi, a[u].y);
+          const int2 e = unpack_partial(a[u]);
+          mlo = min(mlo, e.x);
+          mhi = max(mhi, e.y);
         }
       }
       for (; g < G; g += kFinGroups) {
+        const int2 e = unpack_partial(src[(size_t)g * A.p]);
+        mlo = min(mlo, e.x);
+        mhi = max(mhi, e.y);
+      }
+    } else if (inside) {
+      const int2 *src = A.part + pos;
+      for (int g = grp; g < A.G; g += kFinGroups) {
         const int2 a = src[(size_t)g * A.p];
         mlo = min(mlo, a.x);
         mhi = max(mhi, a.y);
@@ -1352,6 +1360,7 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
   memset(&A, 0, sizeof(A));
   A.part = partial ? part : Lm;
   A.G = partial ? P.G : 1;
+  A.packed = partial ? 1 : 0;
   A.positions = p;
   A.p = p;
   A.Lm = Lm;
