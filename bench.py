@@ -427,6 +427,70 @@ def summarize_trace(directory: str, command: str, title: str) -> str:
     return "\n".join(lines) + "\n"
 
 
+def copy_calibration(torch, mbytes: int) -> None:
+    """A plain copy kernel of known size (read mbytes, write mbytes), run a
+    few times so counter runs can scale the memory counters."""
+    n = mbytes * 1_000_000 // 4
+    a = torch.randint(0, 1 << 30, (n,), dtype=torch.int32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(5):          # the calibration kernel: torch's bitwise_not, one read and one write
+        torch.bitwise_not(a, out=b)
+    torch.cuda.synchronize()
+
+
+def summarize_counters(fetch_dir: str, write_dir: str, copy_bytes: float, command: str, workload: str) -> str:
+    """HBM bytes per reduce launch from two rocprofv3 --pmc runs (FETCH_SIZE,
+    then WRITE_SIZE, in KiB per dispatch), each scaled by what the counter
+    reads for the copy kernel of known size in the same run."""
+    import csv
+    import glob
+
+    def per_kernel(directory, counter):
+        files = glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True)
+        if not files:
+            raise SystemExit(f"no counter_collection.csv under {directory}")
+        acc = {}
+        for r in csv.DictReader(open(files[0])):
+            if r.get("Counter_Name") != counter:
+                continue
+            name = r["Kernel_Name"]
+            acc.setdefault(name, []).append(float(r["Counter_Value"]))
+        return acc
+
+    out = []
+    factors = {}
+    values = {}
+    for counter, directory in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        acc = per_kernel(directory, counter)
+        copy = [v for k, vs in acc.items() if "bitwise_not" in k for v in vs]
+        red = [v for k, vs in acc.items() if "k_reduce" in k for v in vs]
+        if not copy or not red:
+            raise SystemExit(f"{counter}: copy or reduce dispatches missing")
+        # medians: a dispatch whose counters were not collected reads 0
+        c_kib = sorted(copy)[len(copy) // 2]
+        r_kib = sorted(red)[len(red) // 2]
+        factors[counter] = copy_bytes / (c_kib * 1024.0)
+        values[counter] = (r_kib, len(red), c_kib, len(copy))
+    f_r, nf, f_c, ncf = values["FETCH_SIZE"]
+    w_r, nw, w_c, ncw = values["WRITE_SIZE"]
+    hbm = f_r * 1024.0 * factors["FETCH_SIZE"] + w_r * 1024.0 * factors["WRITE_SIZE"]
+    out += [f"# HBM traffic of the reduce kernel on {workload}", "",
+            "Commands (from the repository root, on one MI355X), one counter per run:", ""]
+    for c in ("FETCH_SIZE", "WRITE_SIZE"):
+        out.append("    " + command.replace("COUNTER", c))
+    out += ["",
+            f"copy kernel of known size: {copy_bytes:.0f} bytes read and written per dispatch",
+            f"  FETCH_SIZE {f_c:.1f} KiB per dispatch (median of {ncf}) -> scale {factors['FETCH_SIZE']:.4f}",
+            f"  WRITE_SIZE {w_c:.1f} KiB per dispatch (median of {ncw}) -> scale {factors['WRITE_SIZE']:.4f}",
+            f"reduce kernel (k_reduce_*), median per dispatch:",
+            f"  FETCH_SIZE {f_r:.1f} KiB ({nf} dispatches) -> {f_r * 1024 * factors['FETCH_SIZE']:.0f} bytes",
+            f"  WRITE_SIZE {w_r:.1f} KiB ({nw} dispatches) -> {w_r * 1024 * factors['WRITE_SIZE']:.0f} bytes",
+            "",
+            f"kernel_source_sha: {kernel_source_sha()}",
+            f"hbm_bytes_per_launch: {hbm:.0f}"]
+    return "\n".join(out) + "\n"
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -447,11 +511,19 @@ def main(argv=None):
     ap.add_argument("--serve-budget", type=int, default=8, help="device arena, GiB")
     ap.add_argument("--serve-max-batch", type=int, default=64)
     ap.add_argument("--strategy", type=int, default=0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
+                    help="run a plain copy kernel of this many MB first (for counter runs)")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="summarise two rocprofv3 --pmc directories (FETCH_SIZE, WRITE_SIZE) and exit")
     ap.add_argument("--summarize-trace", metavar="DIR", help="summarise a rocprofv3 kernel-trace directory and exit")
     ap.add_argument("--summary-command", default="", help="command line recorded in the summary")
     ap.add_argument("--summary-title", default="kernel trace")
     args = ap.parse_args(argv)
 
+    if args.summarize_counters:
+        print(summarize_counters(args.summarize_counters[0], args.summarize_counters[1],
+                                 args.copy_calibration * 1e6, args.summary_command, args.workload), end="")
+        return 0
     if args.summarize_trace:
         print(summarize_trace(args.summarize_trace, args.summary_command, args.summary_title), end="")
         return 0
@@ -471,6 +543,8 @@ def main(argv=None):
         return 1
     if args.strategy:
         hp.set_strategy(args.strategy)
+    if args.copy_calibration:
+        copy_calibration(torch, args.copy_calibration)
     out, host, p = bench_single(args, torch, hp, synth)
     if not args.no_batched:
         out["batched"] = bench_batched(args, torch, hp, synth)
