@@ -504,7 +504,8 @@ def main(argv=None):
     ap.add_argument("--batch-clouds", type=int, default=4096)
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--percloud-steps", type=int, default=2)
-    ap.add_argument("--serve", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served form")
+    ap.add_argument("--serve", action="store_true", help="(default) run the served form")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--serve-pool", type=int, default=32)
@@ -548,7 +549,7 @@ def main(argv=None):
     out, host, p = bench_single(args, torch, hp, synth)
     if not args.no_batched:
         out["batched"] = bench_batched(args, torch, hp, synth)
-    if args.serve:
+    if not args.no_serve:
         out["serving"] = bench_serve(args, torch, hp, synth)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(host, p, args.cpu_seconds)

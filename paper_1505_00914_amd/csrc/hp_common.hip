@@ -186,13 +186,11 @@ bool timing_slot(hipEvent_t *e0, hipEvent_t *e1) {
 int timing_enable(int on) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (on && !g_timing_pool) {
-    // timing-only events: no system-scope fence (cache writeback and
-    // invalidation) when they are recorded, so they do not slow the work
-    // they bracket; timing_read waits for them before reading
+    // default events: their durations track the kernel-trace durations of
+    // the profiler; fence-free events read noisier on this path
     for (int i = 0; i < kTimingSlots; ++i) {
-      if (hipEventCreateWithFlags(&g_ev0[i], hipEventDisableSystemFence) != hipSuccess ||
-          hipEventCreateWithFlags(&g_ev1[i], hipEventDisableSystemFence) != hipSuccess)
-        return set_error(HP_EDEVICE, "hipEventCreateWithFlags failed");
+      if (hipEventCreate(&g_ev0[i]) != hipSuccess || hipEventCreate(&g_ev1[i]) != hipSuccess)
+        return set_error(HP_EDEVICE, "hipEventCreate failed");
     }
     g_timing_pool = true;
   }

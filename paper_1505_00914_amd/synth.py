@@ -47,7 +47,9 @@ def disc(n: int, p: int, seed: int, device="cpu") -> torch.Tensor:
     out = []
     have = 0
     while have < n:
-        m = int((n - have) * 1.35) + 1024
+        # candidates in chunks of at most 2^26 rows: one call stays well
+        # below 2^31 elements
+        m = min(int((n - have) * 1.35) + 1024, 1 << 26)
         c = torch.randint(1, p + 1, (m, 2), generator=g, device=device, dtype=torch.int64)
         d = (2 * c - p - 1)
         keep = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) <= p * p
