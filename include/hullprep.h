@@ -85,6 +85,11 @@ extern "C" {
 #define HP_STRATEGY_GLOBAL       2  /* one L in device memory, filtered atomics   */
 #define HP_STRATEGY_LDS_PARTIAL  3  /* workgroup-private L in LDS, written out as
                                        partial arrays merged by the finish step  */
+#define HP_STRATEGY_WINDOW       4  /* L split into column windows that fit LDS:
+                                       the workgroups of one chunk of points, one
+                                       per window, each fold the points of their
+                                       window and write a partial array (for p
+                                       above the LDS limit, up to 8 windows)     */
 
 /* Human-readable name of a status code (static string). */
 const char *hp_status_string(int code);

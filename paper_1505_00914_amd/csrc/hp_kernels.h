@@ -21,11 +21,16 @@ namespace hp {
 // are issued only when the point improves it: lo only ever falls and hi only
 // ever rises, so a stale read can only cause an unnecessary atomic, never a
 // missed one.
-__device__ __forceinline__ void fold_point_lds(int2 *L, int p, int x, int y, bool &bad) {
+// With a column window (wc > 0) L holds columns c0 .. c0 + wc - 1 only and
+// points of other columns are skipped (after their range check).
+__device__ __forceinline__ void fold_point_lds(int2 *L, int p, int x, int y, bool &bad, unsigned c0 = 0,
+                                               unsigned wc = 0) {
   const unsigned xi = (unsigned)(x - 1), yi = (unsigned)(y - 1);
-  const bool ok = (xi < (unsigned)p) & (yi < (unsigned)p);
+  bool ok = (xi < (unsigned)p) & (yi < (unsigned)p);
   bad |= !ok;
-  const unsigned c = ok ? xi : 0u;
+  const unsigned xr = xi - c0;
+  if (wc) ok = ok & (xr < wc);
+  const unsigned c = ok ? xr : 0u;
   const int2 cur = L[c];
   if (ok && y < cur.x) atomicMin(&L[c].x, y);
   if (ok && y > cur.y) atomicMax(&L[c].y, y);
@@ -33,6 +38,7 @@ __device__ __forceinline__ void fold_point_lds(int2 *L, int p, int x, int y, boo
 
 // A partial L entry in 32 bits: lo - 1 in the low half, hi + 1 in the high
 // half (the sentinel (p+1, -1) becomes (p, 0)); valid for p < 65535.
+__host__ __device__ __forceinline__ bool partial_packs(int64_t p) { return p < 65535; }
 __device__ __forceinline__ uint32_t pack_partial(int2 L) {
   return (uint32_t)(L.x - 1) | ((uint32_t)(L.y + 1) << 16);
 }
@@ -74,9 +80,9 @@ struct Batch {
   int2 cur[2 * VPT];
 };
 
-template <int VPT, bool LDS>
+template <int VPT, bool LDS, bool WIN = false>
 __device__ __forceinline__ void gather(const int2 *L, int p, const int4 (&q)[VPT], Batch<VPT> &b,
-                                       bool &bad) {
+                                       bool &bad, unsigned c0 = 0, unsigned wc = 0) {
 #pragma unroll
   for (int u = 0; u < VPT; ++u) {
     const int xs[2] = {q[u].x, q[u].z};
@@ -87,7 +93,13 @@ __device__ __forceinline__ void gather(const int2 *L, int p, const int4 (&q)[VPT
       const unsigned xi = (unsigned)(xs[h] - 1), yi = (unsigned)(ys[h] - 1);
       b.ok[j] = (xi < (unsigned)p) & (yi < (unsigned)p);
       bad |= !b.ok[j];
-      b.c[j] = b.ok[j] ? xi : 0u;
+      if (WIN) {
+        const unsigned xr = xi - c0;
+        b.ok[j] = b.ok[j] & (xr < wc);
+        b.c[j] = b.ok[j] ? xr : 0u;
+      } else {
+        b.c[j] = b.ok[j] ? xi : 0u;
+      }
       b.y[j] = ys[h];
     }
   }

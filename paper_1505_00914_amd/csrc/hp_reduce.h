@@ -13,9 +13,10 @@ namespace hp {
 // load, VPT loads in flight per lane; consecutive lanes read consecutive
 // vectors and consecutive workgroups consecutive chunks.
 // ---------------------------------------------------------------------------
-template <int BLOCK, int VPT, bool LDS>
+template <int BLOCK, int VPT, bool LDS, bool WIN = false>
 __device__ __forceinline__ void stream_points(const int32_t *__restrict__ pts, int64_t n, int p,
-                                              int2 *L, int64_t wg, int64_t nwg, bool &bad) {
+                                              int2 *L, int64_t wg, int64_t nwg, bool &bad,
+                                              unsigned c0 = 0, unsigned wc = 0) {
   // pts is 8-byte aligned (checked on the host); peel one point if the
   // vector body would otherwise start on an 8-byte boundary.
   const int64_t head = (n > 0 && ((uintptr_t)pts & 15) != 0) ? 1 : 0;
@@ -23,11 +24,11 @@ __device__ __forceinline__ void stream_points(const int32_t *__restrict__ pts, i
   const int64_t tail = head + 2 * nv;  // index of the odd last point, if any
   if (wg == 0 && threadIdx.x == 0) {
     if (head) {
-      if (LDS) fold_point_lds(L, p, pts[0], pts[1], bad);
+      if (LDS) fold_point_lds(L, p, pts[0], pts[1], bad, c0, wc);
       else fold_point_global(L, p, pts[0], pts[1], bad);
     }
     if (tail < n) {
-      if (LDS) fold_point_lds(L, p, pts[2 * tail], pts[2 * tail + 1], bad);
+      if (LDS) fold_point_lds(L, p, pts[2 * tail], pts[2 * tail + 1], bad, c0, wc);
       else fold_point_global(L, p, pts[2 * tail], pts[2 * tail + 1], bad);
     }
   }
@@ -49,7 +50,7 @@ __device__ __forceinline__ void stream_points(const int32_t *__restrict__ pts, i
     const bool have_next = t1 + chunk <= nv;
     const int64_t tl = have_next ? t1 : t0;
     Batch<VPT> b;
-    gather<VPT, LDS>(L, p, q, b, bad);
+    gather<VPT, LDS, WIN>(L, p, q, b, bad, c0, wc);
     int4 qn[VPT];
 #pragma unroll
     for (int u = 0; u < VPT; ++u) qn[u] = v[tl + u * BLOCK + threadIdx.x];
@@ -67,8 +68,8 @@ __device__ __forceinline__ void stream_points(const int32_t *__restrict__ pts, i
       if (idx < nv) {
         const int4 r = v[idx];
         if (LDS) {
-          fold_point_lds(L, p, r.x, r.y, bad);
-          fold_point_lds(L, p, r.z, r.w, bad);
+          fold_point_lds(L, p, r.x, r.y, bad, c0, wc);
+          fold_point_lds(L, p, r.z, r.w, bad, c0, wc);
         } else {
           fold_point_global(L, p, r.x, r.y, bad);
           fold_point_global(L, p, r.z, r.w, bad);
@@ -130,6 +131,44 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_lds(const int32_t *__restrict_
     for (int c = threadIdx.x; c < p; c += BLOCK) out[c] = pack_partial(sL[c]);
   }
   if (threadIdx.x == 0) wg_err[blockIdx.x] = s_bad ? kErrRange : 0;
+}
+
+// Column windows of L in LDS (p above the LDS limit).  The grid is Gc
+// chunk groups times W windows, Gc a multiple of 8; workgroup b runs window
+// (b / 8) % W of chunk group (b / 8 / W) * 8 + b % 8, so the W workgroups
+// that read one chunk group have consecutive dispatch slots on the same XCD
+// (workgroups are dealt to the 8 XCDs in turn) and the repeated reads of its
+// points hit that XCD's L2.  Each writes its window of the chunk group's
+// partial array (packed words when p allows, else pairs); the finish step
+// folds the Gc partials.
+template <int BLOCK, int VPT>
+__global__ __launch_bounds__(BLOCK) void k_reduce_window(const int32_t *__restrict__ pts, int64_t n,
+                                                         int32_t p, int32_t W, int32_t wc,
+                                                         uint32_t *__restrict__ out_part,
+                                                         int32_t *__restrict__ wg_err, ResetArgs R) {
+  extern __shared__ int2 sL[];           // wc pairs, then one flag word
+  int &s_bad = reinterpret_cast<int &>(sL[wc]);
+  const int b = blockIdx.x, k = b >> 3;
+  const int w = k % W, cg = (k / W) * 8 + (b & 7);
+  const int Gc = (int)(gridDim.x / W);
+  const unsigned c0 = (unsigned)w * (unsigned)wc;
+  reset_controls(R);
+  if (threadIdx.x == 0) s_bad = 0;
+  for (int c = threadIdx.x; c < wc; c += BLOCK) sL[c] = make_int2(p + 1, -1);
+  __syncthreads();
+  bool bad = false;
+  stream_points<BLOCK, VPT, true, true>(pts, n, p, sL, cg, Gc, bad, c0, (unsigned)wc);
+  if (bad) s_bad = 1;
+  __syncthreads();
+  const int ncol = min(wc, p - (int)c0);
+  if (partial_packs(p)) {
+    uint32_t *out = out_part + (size_t)cg * (size_t)p + c0;
+    for (int c = threadIdx.x; c < ncol; c += BLOCK) out[c] = pack_partial(sL[c]);
+  } else {
+    int2 *out = reinterpret_cast<int2 *>(out_part) + (size_t)cg * (size_t)p + c0;
+    for (int c = threadIdx.x; c < ncol; c += BLOCK) out[c] = sL[c];
+  }
+  if (threadIdx.x == 0) wg_err[b] = s_bad ? kErrRange : 0;
 }
 
 // One L in device memory, updated with filtered device-scope atomics.

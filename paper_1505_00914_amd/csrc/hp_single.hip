@@ -1156,8 +1156,21 @@ static int64_t lds_grid_max();
 
 struct Plan1 {
   int strategy;
-  int block, vpt, G;
+  int block, vpt, G;   // G: workgroups of the reduce
+  int W, wc;           // column windows (HP_STRATEGY_WINDOW): count and columns each
 };
+
+// Column windows: at most kWinMax windows, at most kWinMaxGroups chunk
+// groups (a multiple of 8: one per XCD slot).
+constexpr int kWinMax = 8;
+constexpr int kWinMaxGroups = 64;
+
+// Partial arrays the reduce writes (each p packed words), or 0.
+static int partial_count(const Plan1 &P) {
+  if (P.strategy == HP_STRATEGY_LDS_PARTIAL) return P.G;
+  if (P.strategy == HP_STRATEGY_WINDOW) return P.G / P.W;
+  return 0;
+}
 
 static bool is_lds(int s) { return s == HP_STRATEGY_LDS || s == HP_STRATEGY_LDS_PARTIAL; }
 
@@ -1166,7 +1179,19 @@ static Plan1 choose(int64_t n, int32_t p) {
   Plan1 P;
   int s = forced_strategy();
   if (s == HP_STRATEGY_AUTO) s = tuned_strategy(n, p);
-  if (is_lds(s) && (int64_t)p > D.lds_max_p) s = HP_STRATEGY_GLOBAL;
+  P.W = 1;
+  P.wc = p;
+  if ((is_lds(s) && (int64_t)p > D.lds_max_p) || s == HP_STRATEGY_WINDOW) {
+    // column windows when the L does not fit LDS (or when asked for)
+    const int64_t W = ((int64_t)p + D.lds_max_p - 1) / D.lds_max_p;
+    if (W <= kWinMax && (s == HP_STRATEGY_WINDOW || n >= 4 * (int64_t)p)) {
+      s = HP_STRATEGY_WINDOW;
+      P.W = (int)W;
+      P.wc = (int)(((int64_t)p + W - 1) / W);
+    } else {
+      s = HP_STRATEGY_GLOBAL;
+    }
+  }
   P.strategy = s;
   P.block = 1024;
   P.vpt = 4;
@@ -1179,6 +1204,8 @@ static Plan1 choose(int64_t n, int32_t p) {
     if (G > D.cus) G = D.cus;
     if (G < 1) G = 1;
     P.G = (int)G;
+  } else if (s == HP_STRATEGY_WINDOW) {
+    P.G = D.cus;   // chunk groups x windows, fixed below
   } else {
     const int64_t vecs = (n + 1) / 2;
     int64_t G = (vecs + (int64_t)P.block * P.vpt - 1) / ((int64_t)P.block * P.vpt);
@@ -1188,6 +1215,11 @@ static Plan1 choose(int64_t n, int32_t p) {
     P.G = (int)G;
   }
   tune_override(n, p, &P.block, &P.vpt, &P.G);
+  if (s == HP_STRATEGY_WINDOW) {
+    int groups = (P.G / P.W) / 8 * 8;
+    groups = std::max(8, std::min(kWinMaxGroups, groups));
+    P.G = groups * P.W;
+  }
   if (is_lds(P.strategy) && P.G > lds_grid_max()) P.G = (int)lds_grid_max();
   if (P.G > kMaxGrid) P.G = kMaxGrid;
   if (P.G < 1) P.G = 1;
@@ -1197,7 +1229,9 @@ static Plan1 choose(int64_t n, int32_t p) {
 // Pairs of the reduce output region: G partial L arrays for the partial
 // variant, otherwise nothing (the device L is the merged-L region).
 static int64_t part_pairs_for(const Plan1 &P, int32_t p) {
-  return P.strategy == HP_STRATEGY_LDS_PARTIAL ? (int64_t)P.G * p : 0;
+  // packed partial words take half a pair slot each
+  const int64_t entries = (int64_t)partial_count(P) * p;
+  return partial_packs(p) ? (entries + 1) / 2 : entries;
 }
 
 // Largest grid the LDS strategies may use (also bounds tuned overrides).
@@ -1208,7 +1242,13 @@ static size_t ws_bytes_for(int64_t n, int32_t p) {
   // so that a later strategy change still fits the same workspace
   (void)n;
   const TreeShape T = make_tree(p);
-  const int64_t part = (int64_t)p <= device_info().lds_max_p ? lds_grid_max() * p : 0;
+  const int64_t lds_max = device_info().lds_max_p;
+  int64_t part = 0;
+  if ((int64_t)p <= lds_max) part = (lds_grid_max() * p + 1) / 2;
+  if ((int64_t)p <= kWinMax * lds_max) {
+    const int64_t entries = (int64_t)kWinMaxGroups * p;
+    part = std::max<int64_t>(part, partial_packs(p) ? (entries + 1) / 2 : entries);
+  }
   return make_layout(p, p, part, T).total;
 }
 
@@ -1245,6 +1285,18 @@ static hipError_t launch_reduce(const Plan1 &P, const int32_t *pts, int64_t n, i
     return launch_lds<BLOCK, VPT, true>(P, pts, n, p, Lm, wg_err, R, s, e0, e1);
   if (P.strategy == HP_STRATEGY_LDS_PARTIAL)
     return launch_lds<BLOCK, VPT, false>(P, pts, n, p, part, wg_err, R, s, e0, e1);
+  if (P.strategy == HP_STRATEGY_WINDOW) {
+    static bool attr_set = false;
+    if (!attr_set) {
+      const hipError_t e = hipFuncSetAttribute((const void *)k_reduce_window<BLOCK, VPT>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               device_info().lds_bytes);
+      if (e != hipSuccess) return e;
+      attr_set = true;
+    }
+    return launch(k_reduce_window<BLOCK, VPT>, dim3(P.G), dim3(BLOCK), sizeof(int2) * ((size_t)P.wc + 1), s,
+                  e0, e1, pts, n, p, P.W, P.wc, reinterpret_cast<uint32_t *>(part), wg_err, R);
+  }
   return launch(k_reduce_global<BLOCK, VPT>, dim3(P.G), dim3(BLOCK), 0, s, e0, e1, pts, n, p, Lm,
                 wg_err, R);
 }
@@ -1331,7 +1383,7 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
   int32_t *tree = reinterpret_cast<int32_t *>(w + Y.tree);
   int2 *part = reinterpret_cast<int2 *>(w + Y.part);
   int2 *Lm = reinterpret_cast<int2 *>(w + Y.Lm);
-  const bool partial = P.strategy == HP_STRATEGY_LDS_PARTIAL;
+  const bool partial = partial_count(P) > 0;
   int32_t *wg_err = reinterpret_cast<int32_t *>(w + Y.wg_err);
 
   // The partial strategy writes every merged column itself, so only the
@@ -1359,8 +1411,8 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
   FinishArgs A;
   memset(&A, 0, sizeof(A));
   A.part = partial ? part : Lm;
-  A.G = partial ? P.G : 1;
-  A.packed = partial ? 1 : 0;
+  A.G = partial ? partial_count(P) : 1;
+  A.packed = partial && partial_packs(p) ? 1 : 0;
   A.positions = p;
   A.p = p;
   A.Lm = Lm;

@@ -37,11 +37,16 @@ QUICK = [(23, 12, "ellipsoids")]
 
 def _candidates(n: int, p: int, cus: int, lds_max_p: int):
     strategies = [hp.HP_STRATEGY_GLOBAL]
+    windows = -(-p // lds_max_p)
     if p <= lds_max_p and n >= 2 * p:
         strategies = [hp.HP_STRATEGY_LDS_PARTIAL, hp.HP_STRATEGY_LDS, hp.HP_STRATEGY_GLOBAL]
+    elif windows <= 8 and n >= 2 * p:
+        strategies = [hp.HP_STRATEGY_WINDOW, hp.HP_STRATEGY_GLOBAL]
     for s in strategies:
         if s == hp.HP_STRATEGY_GLOBAL:
             grids = sorted({max(1, int(cus * f)) for f in (1, 2, 4, 8)})
+        elif s == hp.HP_STRATEGY_WINDOW:
+            grids = [g * windows for g in (8, 16, 32, 64)]
         else:
             gmax = max(1, n // (2 * p))
             grids = sorted({min(gmax, max(1, int(cus * f))) for f in (0.5, 1, 1.5, 2, 3, 4)})

@@ -49,7 +49,7 @@ def _compare(got, want, label, check_L=True):
     assert np.array_equal(got["hull"], want["hull"]), f"{label}: hull differs"
 
 
-def _run_both(hp, pts_cpu: torch.Tensor, p: int, label: str, strategies=(1, 2, 3), split=True):
+def _run_both(hp, pts_cpu: torch.Tensor, p: int, label: str, strategies=(1, 2, 3, 4), split=True):
     print(f"[case] {label} n={pts_cpu.shape[0]} p={p}", flush=True)
     want = _oracle(pts_cpu.numpy(), p)
     dev = pts_cpu.cuda()
@@ -90,7 +90,7 @@ def test_gap_example(hp):
 ])
 def test_configs(hp, kind, n, p, seed):
     pts = synth.cloud(kind, n, p, seed)
-    strategies = (1, 2, 3) if p <= hp.lds_max_p() else (2,)
+    strategies = (1, 2, 3, 4) if p <= hp.lds_max_p() else (2, 4)
     _run_both(hp, pts, p, f"{kind}-{n}-{p}", strategies)
 
 
@@ -120,7 +120,7 @@ def _edge_cases():
 @pytest.mark.parametrize("name", sorted(_edge_cases()))
 def test_edge_cases(hp, name):
     pts, p = _edge_cases()[name]
-    strategies = (1, 2, 3) if p <= hp.lds_max_p() else (2,)
+    strategies = (1, 2, 3, 4) if p <= hp.lds_max_p() else (2, 4)
     _run_both(hp, torch.from_numpy(pts), p, name, strategies)
 
 
@@ -131,7 +131,7 @@ def test_unaligned_start(hp):
     want = _oracle(view_cpu.contiguous().numpy(), 777)
     dev = base.cuda()[1:]
     assert dev.data_ptr() % 16 == 8
-    for s in (1, 2, 3):
+    for s in (1, 2, 3, 4):
         hp.set_strategy(s)
         _compare(hp.run(dev, 777), want, f"unaligned/strategy{s}")
     hp.set_strategy(0)
@@ -141,7 +141,7 @@ def test_out_of_range_reports(hp):
     pts = synth.cloud("uniform", 10_000, 100, 12)
     pts[5000] = torch.tensor([101, 3], dtype=torch.int32)
     pts[17] = torch.tensor([4, 0], dtype=torch.int32)
-    for s in (1, 2, 3):
+    for s in (1, 2, 3, 4):
         hp.set_strategy(s)
         got = hp.run(pts.cuda(), 100)
         assert got["status"] == HP_ERANGE
@@ -153,7 +153,7 @@ def test_launch_shapes(hp):
     pts = synth.cloud("ellipsoids", 300_000, 2048, 13)
     want = _oracle(pts.numpy(), 2048)
     dev = pts.cuda()
-    for strategy in (1, 2, 3):
+    for strategy in (1, 2, 3, 4):
         for block in (256, 512, 1024):
             for vpt in (2, 4, 8):
                 for grid in (1, 7, 300):
@@ -176,3 +176,17 @@ def test_repeat_is_stable(hp):
         else:
             for key in ("lo", "hi", "x", "clo", "chi", "hull"):
                 assert np.array_equal(got[key], first[key])
+
+
+@pytest.mark.parametrize("kind,n,p,seed", [
+    ("uniform", 400_000, 65_536, 21),       # 4 windows
+    ("gaussian", 300_000, 40_000, 22),      # 2 windows, uneven last window
+    ("uniform", 700_000, 163_000, 23),      # 8 windows
+    ("disc", 100_000, 20_481, 24),          # just above the LDS limit
+    ("uniform", 300_000, 65_534, 25),       # largest p whose partials pack in 16 bits
+    ("uniform", 300_000, 65_535, 26),       # smallest p whose partials do not
+])
+def test_column_windows(hp, kind, n, p, seed):
+    """p above the LDS limit: the column-window reduce against the oracle."""
+    pts = synth.cloud(kind, n, p, seed)
+    _run_both(hp, pts, p, f"window-{kind}-{n}-{p}", strategies=(4, 2))
