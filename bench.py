@@ -158,6 +158,58 @@ def bench_single(args, torch, hp, synth):
     return out, host, p
 
 
+def bench_regimes(args, torch, hp, synth) -> list:
+    """The other single-cloud workloads at full size, timed like the main
+    one (plain region for Gpoints/s, event region for the reduce kernel),
+    each checked against the oracle on the last step's outputs."""
+    import numpy as np
+
+    import oracle
+
+    res = []
+    for name in args.regimes.split(","):
+        if not name or name == args.workload:
+            continue
+        w = synth.WORKLOADS[name]
+        p = w["p"]
+        pts = synth.cloud(w["kind"], w["n"], p, w["seed"], device="cuda:0")
+        n = pts.shape[0]
+        copies = [pts] + [pts.clone() for _ in range(max(0, min(5, int(600e6 // (8 * n)))))]
+        buf = hp.Buffers.allocate(n, p, pts.device, export_L=False)
+        stream = torch.cuda.current_stream()
+        steps = max(10, min(args.steps, int(2e9 // (8 * n))))
+        for i in range(3):
+            hp.hp_run(copies[i % len(copies)], p, buf, stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            hp.hp_run(copies[i % len(copies)], p, buf, stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        hp.timing_enable(True)
+        hp.timing_read()
+        for i in range(steps):
+            hp.hp_run(copies[i % len(copies)], p, buf, stream)
+        torch.cuda.synchronize()
+        tm = hp.timing_read()
+        hp.timing_enable(False)
+        got = hp.collect(buf)
+        want = oracle.precondition_and_hull(pts.cpu().numpy(), p)
+        ok = (got["status"] == 0 and got["k"] == want["k"] and np.array_equal(got["x"], want["x"])
+              and np.array_equal(got["clo"], want["clo"]) and np.array_equal(got["chi"], want["chi"])
+              and np.array_equal(got["hull"], want["hull"]))
+        red_ms = tm["total_ms"] / max(1, tm["count"])
+        gbs = 8.0 * n / (red_ms * 1e-3) / 1e9
+        res.append({"workload": name, "n": n, "p": p, "steps": steps,
+                    "gpoints_per_s": round(n * steps / (t1 - t0) / 1e9, 3),
+                    "ms_per_step": round((t1 - t0) * 1e3 / steps, 5),
+                    "reduce_ms_avg": round(red_ms, 5), "reduce_gbs": round(gbs, 1),
+                    "reduce_frac": round(gbs / HBM_PEAK_GBS, 4), "parity_vs_oracle": bool(ok)})
+        del copies, pts, buf
+        torch.cuda.empty_cache()
+    return res
+
+
 def bench_batched(args, torch, hp, synth) -> dict:
     """4096 ragged clouds (n log-uniform in [1e3, 1e6], p log-uniform in
     [256, 16384], uniform or ellipsoid-surface points) through one plan: the
@@ -287,22 +339,29 @@ def bench_serve(args, torch, hp, synth) -> dict:
 
     def run_server(on_device: bool) -> dict:
         srv = hp.Server(args.serve_budget << 30, max_batch=args.serve_max_batch)
-        for i in range(min(8, len(spec))):       # warm the pinned allocator and the kernels
-            r = srv.submit(dev[i] if on_device else host[i], spec[i][2])
+        max_n = max(sp[1] for sp in spec)
+        max_p = max(sp[2] for sp in spec)
+        # a ring of page-locked output buffers, reused once the waiter has
+        # checked the request that last used them (no allocation per request)
+        ring = [hp.Request(max_n, max_p, None) for _ in range(args.serve_ring)]
+        for i in range(min(8, len(spec))):       # warm the kernels
+            r = srv.submit(dev[i] if on_device else host[i], spec[i][2], ring[i])
             srv.wait(r)
-        reqs = [None] * len(arrivals)
+        checked = [0]
         done = threading.Event()
         lat = [0.0] * len(arrivals)
         bad = [0]
         first_bad = []
+        issued = [None] * len(arrivals)
 
         def waiter():
             for i in range(len(arrivals)):
-                while reqs[i] is None:
+                while issued[i] is None:
                     time.sleep(0.0001)
-                srv.wait(reqs[i])
-                lat[i] = (reqs[i].done_ns - t0 - int(arrivals[i] * 1e9)) / 1e6
-                got = reqs[i].result()
+                r = issued[i]
+                srv.wait(r)
+                lat[i] = (r.done_ns - t0 - int(arrivals[i] * 1e9)) / 1e6
+                got = r.result()
                 if not same(got, ref[picks[i]]):
                     bad[0] += 1
                     if len(first_bad) < 4:
@@ -310,10 +369,9 @@ def bench_serve(args, torch, hp, synth) -> dict:
                         first_bad.append({"i": i, "pool": int(picks[i]), "n": spec[picks[i]][1],
                                           "p": spec[picks[i]][2],
                                           "got": [got["status"], got["k"], got["s"], got["h"]],
-                                          "want": [w["status"], w["k"], w["s"], w["h"]],
-                                          "differ": [key for key in ("x", "clo", "chi", "hull")
-                                                     if not np.array_equal(got[key], w[key])]})
-                reqs[i] = True          # drop the buffers
+                                          "want": [w["status"], w["k"], w["s"], w["h"]]})
+                issued[i] = True
+                checked[0] = i + 1
             done.set()
 
         th = threading.Thread(target=waiter, daemon=True)
@@ -321,8 +379,10 @@ def bench_serve(args, torch, hp, synth) -> dict:
         th.start()
         for i, at in enumerate(arrivals):
             _wait_until(hp, t0 + int(at * 1e9))
+            while checked[0] <= i - len(ring):   # its ring slot is still in use
+                time.sleep(0.00005)
             j = int(picks[i])
-            reqs[i] = srv.submit(dev[j] if on_device else host[j], spec[j][2])
+            issued[i] = srv.submit(dev[j] if on_device else host[j], spec[j][2], ring[i % len(ring)])
         done.wait()
         t_end = hp.clock_ns()
         st = srv.stats()
@@ -339,7 +399,7 @@ def bench_serve(args, torch, hp, synth) -> dict:
             out["first_mismatches"] = first_bad
         return out
 
-    def run_fifo() -> dict:
+    def run_fifo(on_device: bool = False) -> dict:
         """One request at a time, plain single-cloud launches, FIFO."""
         dev_pts = torch.empty((max(s[1] for s in spec), 2), dtype=torch.int32, device="cuda:0")
         maxp = max(s[2] for s in spec)
@@ -349,21 +409,30 @@ def bench_serve(args, torch, hp, synth) -> dict:
         stream = torch.cuda.current_stream()
         lat = []
         pin_out = torch.empty(4, dtype=torch.int32, pin_memory=True)
+        cap_max = min(max(sp[1] for sp in spec), maxp)
+        out_chain = torch.empty((3, cap_max), dtype=torch.int32, pin_memory=True)
+        out_hull = torch.empty((2, 2 * cap_max), dtype=torch.int32, pin_memory=True)
         t0 = hp.clock_ns()
         for i, at in enumerate(arrivals):
             due = t0 + int(at * 1e9)
             _wait_until(hp, due)
             j = int(picks[i])
             n, p = spec[j][1], spec[j][2]
-            dev_pts[:n].copy_(host[j], non_blocking=True)
+            if on_device:
+                src = dev[j]
+            else:
+                dev_pts[:n].copy_(host[j], non_blocking=True)
+                src = dev_pts[:n]
             cap = min(n, p)
-            hp.hp_run(dev_pts[:n], p, buf, stream)
-            cx = buf.cx[:cap].to("cpu", non_blocking=True)
-            hx = buf.hx[:2 * cap].to("cpu", non_blocking=True)
+            hp.hp_run(src, p, buf, stream)
+            # the same outputs the server returns: chain, hull, info
+            for t_dev, t_host in ((buf.cx, out_chain[0]), (buf.clo, out_chain[1]), (buf.chi, out_chain[2])):
+                t_host[:cap].copy_(t_dev[:cap], non_blocking=True)
+            out_hull[0][:2 * cap].copy_(buf.hx[:2 * cap], non_blocking=True)
+            out_hull[1][:2 * cap].copy_(buf.hy[:2 * cap], non_blocking=True)
             pin_out.copy_(buf.info, non_blocking=True)
             stream.synchronize()
             lat.append((hp.clock_ns() - due) / 1e6)
-            del cx, hx
         t_end = hp.clock_ns()
         out = _percentiles(lat)
         out.update({"requests": len(arrivals), "req_per_s": round(len(arrivals) / ((t_end - t0) / 1e9), 1)})
@@ -388,7 +457,18 @@ def bench_serve(args, torch, hp, synth) -> dict:
            "budget_gib": args.serve_budget, "max_batch": args.serve_max_batch}
     res["server_host_points"] = run_server(False)
     res["server_device_points"] = run_server(True)
-    res["fifo_percloud_host_points"] = run_fifo()
+    res["fifo_percloud_host_points"] = run_fifo(False)
+    res["fifo_percloud_device_points"] = run_fifo(True)
+    # the same comparison at a higher arrival rate, points in device memory
+    if args.serve_stress_rate > 0:
+        gaps = rng.exponential(1.0 / args.serve_stress_rate,
+                               size=int(args.serve_stress_rate * args.serve_seconds * 1.2) + 16)
+        a2 = np.cumsum(gaps)
+        arrivals = a2[a2 < args.serve_seconds]
+        picks = rng.integers(0, len(spec), size=arrivals.shape[0])
+        res["stress_rate"] = args.serve_stress_rate
+        res["stress_server_device_points"] = run_server(True)
+        res["stress_fifo_percloud_device_points"] = run_fifo(True)
     return res
 
 
@@ -501,6 +581,8 @@ def main(argv=None):
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--regimes", default="uniform_100k_p1024,disc_2p28_p2p20,gaussian_2p28_p4096",
+                    help="other single-cloud workloads timed beside the main one ('' for none)")
     ap.add_argument("--batch-clouds", type=int, default=4096)
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--percloud-steps", type=int, default=2)
@@ -511,6 +593,9 @@ def main(argv=None):
     ap.add_argument("--serve-pool", type=int, default=32)
     ap.add_argument("--serve-budget", type=int, default=8, help="device arena, GiB")
     ap.add_argument("--serve-max-batch", type=int, default=64)
+    ap.add_argument("--serve-ring", type=int, default=128, help="page-locked output buffers reused by the trace")
+    ap.add_argument("--serve-stress-rate", type=float, default=8000.0,
+                    help="second arrival rate (device-resident points) for server vs FIFO; 0 skips it")
     ap.add_argument("--strategy", type=int, default=0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="run a plain copy kernel of this many MB first (for counter runs)")
@@ -547,6 +632,8 @@ def main(argv=None):
     if args.copy_calibration:
         copy_calibration(torch, args.copy_calibration)
     out, host, p = bench_single(args, torch, hp, synth)
+    if args.regimes:
+        out["regimes"] = bench_regimes(args, torch, hp, synth)
     if not args.no_batched:
         out["batched"] = bench_batched(args, torch, hp, synth)
     if not args.no_serve:

@@ -44,6 +44,10 @@ constexpr size_t kTableBytes = 8u << 20;    // work-table image capacity of one 
 // sequence, which spreads one cloud over the whole device; smaller ones
 // share one batched launch sequence.
 constexpr int64_t kServeSingleN = 1 << 18;
+// Smaller requests share a batched launch sequence only when at least this
+// many are issued together; fewer run the single-cloud sequence each, which
+// has the lower latency for one cloud.
+constexpr size_t kServeMinBatch = 8;
 
 int64_t now_ns() {
   return std::chrono::duration_cast<std::chrono::nanoseconds>(
@@ -59,7 +63,7 @@ struct Request {
   bool on_device = false;
   int32_t *cx = nullptr, *clo = nullptr, *chi = nullptr, *hx = nullptr, *hy = nullptr, *info = nullptr;
   int32_t cap = 0;               // chain capacity min(n, p); the hull has 2 cap
-  bool single = false;           // runs the single-cloud launch sequence
+  bool single = false;           // always runs the single-cloud launch sequence
   TreeShape tree;
   CloudSlots slots;              // batched workspace (single: one workspace of ws_bytes)
   size_t ws_bytes = 0;
@@ -93,7 +97,7 @@ struct hp_server {
   int64_t lds_p_max = 1;
   hp::Arena arena;
   char *dmem = nullptr;
-  hipStream_t copy = nullptr, comp = nullptr;
+  hipStream_t copy = nullptr, comp = nullptr, out = nullptr;   // copies in, kernels, copies out
   hp::Slot slot[hp::kSlots];
   std::vector<hipEvent_t> ev_pool;   // used by the scheduler thread only
   std::mutex mu;
@@ -115,7 +119,9 @@ void layout_request(Request &r) {
   tree_shape(r.p, &r.tree);
   r.single = r.n >= kServeSingleN;
   r.slots = cloud_slots(r.p, r.tree);
-  r.ws_bytes = r.single ? align256(single_ws_bytes(r.n, r.p)) : r.slots.total;
+  // every request can run the single-cloud sequence; small ones can also
+  // join a batched sequence (their slots fit the same space)
+  r.ws_bytes = std::max(align256(single_ws_bytes(r.n, r.p)), r.slots.total);
   r.cap = (int32_t)chain_cap_for(r.n, r.p);
   size_t o = 0;
   r.o_pts = o;
@@ -192,6 +198,9 @@ hipEvent_t pool_event(hp_server *S, Slot &sl) {
 // event order.
 hipError_t issue(hp_server *S, Slot &sl, std::vector<RequestPtr> &take) {
   std::stable_partition(take.begin(), take.end(), [](const RequestPtr &r) { return !r->single; });
+  size_t small = 0;
+  while (small < take.size() && !take[small]->single) ++small;
+  const size_t nbatched = small >= kServeMinBatch ? small : 0;   // the rest run one by one
   BatchTables t;
   std::vector<BCloud> clouds;
   std::vector<const int32_t *> cpts;
@@ -231,17 +240,17 @@ hipError_t issue(hp_server *S, Slot &sl, std::vector<RequestPtr> &take) {
     const size_t c = sizeof(int32_t) * (size_t)r.cap;
     hipError_t x = hipSuccess;
     if (r.cap > 0) {
-      if ((x = hipMemcpyAsync(r.cx, chain, c, hipMemcpyDeviceToHost, S->comp)) != hipSuccess) return x;
-      if ((x = hipMemcpyAsync(r.clo, chain + r.cap, c, hipMemcpyDeviceToHost, S->comp)) != hipSuccess) return x;
-      if ((x = hipMemcpyAsync(r.chi, chain + 2 * (size_t)r.cap, c, hipMemcpyDeviceToHost, S->comp)) != hipSuccess) return x;
-      if ((x = hipMemcpyAsync(r.hx, hull, 2 * c, hipMemcpyDeviceToHost, S->comp)) != hipSuccess) return x;
-      if ((x = hipMemcpyAsync(r.hy, hull + 2 * (size_t)r.cap, 2 * c, hipMemcpyDeviceToHost, S->comp)) != hipSuccess) return x;
+      if ((x = hipMemcpyAsync(r.cx, chain, c, hipMemcpyDeviceToHost, S->out)) != hipSuccess) return x;
+      if ((x = hipMemcpyAsync(r.clo, chain + r.cap, c, hipMemcpyDeviceToHost, S->out)) != hipSuccess) return x;
+      if ((x = hipMemcpyAsync(r.chi, chain + 2 * (size_t)r.cap, c, hipMemcpyDeviceToHost, S->out)) != hipSuccess) return x;
+      if ((x = hipMemcpyAsync(r.hx, hull, 2 * c, hipMemcpyDeviceToHost, S->out)) != hipSuccess) return x;
+      if ((x = hipMemcpyAsync(r.hy, hull + 2 * (size_t)r.cap, 2 * c, hipMemcpyDeviceToHost, S->out)) != hipSuccess) return x;
     }
-    return hipMemcpyAsync(r.info, base + r.o_info, sizeof(int32_t) * HP_INFO_WORDS, hipMemcpyDeviceToHost, S->comp);
+    return hipMemcpyAsync(r.info, base + r.o_info, sizeof(int32_t) * HP_INFO_WORDS, hipMemcpyDeviceToHost, S->out);
   };
   // small requests: points, tables, one batched launch, outputs, one event
   size_t nsmall = 0;
-  while (nsmall < take.size() && !take[nsmall]->single) {
+  while (nsmall < nbatched) {
     Request &r = *take[nsmall];
     if ((e = copy_in(nsmall)) != hipSuccess) return e;
     t.add_cloud(r.n, r.p, r.tree, S->lds_p_max);
@@ -256,30 +265,34 @@ hipError_t issue(hp_server *S, Slot &sl, std::vector<RequestPtr> &take) {
     DeviceBatch D;
     batch_image(t, clouds, cpts, sl.himg, static_cast<char *>(sl.dimg), D);
     if ((e = hipMemcpyAsync(sl.dimg, sl.himg, img, hipMemcpyHostToDevice, S->copy)) != hipSuccess) return e;
-    hipEvent_t copied = pool_event(S, sl), done = pool_event(S, sl);
-    if (!copied || !done) return hipErrorOutOfMemory;
+    hipEvent_t copied = pool_event(S, sl), computed = pool_event(S, sl), done = pool_event(S, sl);
+    if (!copied || !computed || !done) return hipErrorOutOfMemory;
     if ((e = hipEventRecord(copied, S->copy)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(S->comp, copied, 0)) != hipSuccess) return e;
     if ((e = enqueue_batch(D, S->comp)) != hipSuccess) return e;
+    if ((e = hipEventRecord(computed, S->comp)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(S->out, computed, 0)) != hipSuccess) return e;
     for (size_t b = 0; b < nsmall; ++b)
       if ((e = copy_out(*take[b])) != hipSuccess) return e;
-    if ((e = hipEventRecord(done, S->comp)) != hipSuccess) return e;
+    if ((e = hipEventRecord(done, S->out)) != hipSuccess) return e;
     for (size_t b = 0; b < nsmall; ++b) take[b]->ev = done;
   }
   // large requests, each behind its own copy
   for (size_t b = nsmall; b < take.size(); ++b) {
     Request &r = *take[b];
     if ((e = copy_in(b)) != hipSuccess) return e;
-    hipEvent_t copied = pool_event(S, sl), done = pool_event(S, sl);
-    if (!copied || !done) return hipErrorOutOfMemory;
+    hipEvent_t copied = pool_event(S, sl), computed = pool_event(S, sl), done = pool_event(S, sl);
+    if (!copied || !computed || !done) return hipErrorOutOfMemory;
     if ((e = hipEventRecord(copied, S->copy)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(S->comp, copied, 0)) != hipSuccess) return e;
     const CloudOut o = outputs(r);
     if (run_single(dpts[b], r.n, r.p, nullptr, nullptr, nullptr, o.cx, o.clo, o.chi, o.chain_cap, o.hx, o.hy,
                    o.hull_cap, o.info, S->dmem + r.block + r.o_slots, r.ws_bytes, S->comp, true) != HP_OK)
       return hipErrorLaunchFailure;
+    if ((e = hipEventRecord(computed, S->comp)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(S->out, computed, 0)) != hipSuccess) return e;
     if ((e = copy_out(r)) != hipSuccess) return e;
-    if ((e = hipEventRecord(done, S->comp)) != hipSuccess) return e;
+    if ((e = hipEventRecord(done, S->out)) != hipSuccess) return e;
     r.ev = done;
   }
   return hipSuccess;
@@ -312,6 +325,7 @@ bool launch(hp_server *S, Slot &sl, std::unique_lock<std::mutex> &lk) {
     // nothing of this batch may still touch its blocks when they are freed
     (void)hipStreamSynchronize(S->copy);
     (void)hipStreamSynchronize(S->comp);
+    (void)hipStreamSynchronize(S->out);
   }
   lk.lock();
   sl.reqs = take;
@@ -375,6 +389,7 @@ extern "C" int hp_server_destroy(hp_server *S) {
   }
   for (hipEvent_t e : S->ev_pool) (void)hipEventDestroy(e);
   if (S->copy) (void)hipStreamDestroy(S->copy);
+  if (S->out) (void)hipStreamDestroy(S->out);
   if (S->comp) (void)hipStreamDestroy(S->comp);
   if (S->dmem) (void)hipFree(S->dmem);
   delete S;
@@ -400,7 +415,8 @@ extern "C" int hp_server_create(size_t device_budget_bytes, int32_t max_batch, h
   if (hipMalloc(reinterpret_cast<void **>(&S->dmem), S->budget) != hipSuccess)
     rc = set_error(HP_ENOMEM, "device arena of %zu bytes could not be allocated", S->budget);
   if (rc == HP_OK && (hipStreamCreateWithFlags(&S->copy, hipStreamNonBlocking) != hipSuccess ||
-                      hipStreamCreateWithFlags(&S->comp, hipStreamNonBlocking) != hipSuccess))
+                      hipStreamCreateWithFlags(&S->comp, hipStreamNonBlocking) != hipSuccess ||
+                      hipStreamCreateWithFlags(&S->out, hipStreamNonBlocking) != hipSuccess))
     rc = set_error(HP_EDEVICE, "stream creation failed");
   for (Slot &sl : S->slot) {
     if (rc != HP_OK) break;

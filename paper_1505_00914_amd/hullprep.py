@@ -277,7 +277,8 @@ class Request:
     """Host output buffers (page-locked) of one served request, filled by the
     server before the request completes."""
 
-    def __init__(self, n: int, p: int, points: torch.Tensor):
+    def __init__(self, n: int, p: int, points: torch.Tensor | None = None):
+        """Buffers for any request with min(n, p) up to min(n, p) here."""
         cap = max(1, min(n, p))
         pin = dict(dtype=torch.int32, pin_memory=True)
         self.n, self.p, self.points = n, p, points
@@ -318,6 +319,9 @@ class Server:
         n = points.shape[0]
         if req is None:
             req = Request(n, p, points)
+        elif req.cap < min(n, p):
+            raise ValueError("the request's buffers are too small for this cloud")
+        req.n, req.p, req.points = n, p, points
         t = ctypes.c_int64()
         _lib.call("hp_server_submit", self._h, points.data_ptr() if n else None, n, p,
                   1 if points.is_cuda else 0, req.chain[0].data_ptr(), req.chain[1].data_ptr(),
