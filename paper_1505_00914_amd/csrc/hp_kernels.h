@@ -177,6 +177,7 @@ struct HullArgs {
   const int2 *Lm;
   int32_t p;
   const int32_t *slab_k, *slab_s;
+  const int32_t *slab_off;  // scanned slab offsets (k, s and status already written), or null
   const int32_t *wg_err;
   int32_t n_wg_err;
   int32_t *cx, *clo, *chi;

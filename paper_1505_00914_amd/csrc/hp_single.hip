@@ -783,7 +783,7 @@ __global__ __launch_bounds__(256) void k_chain(const int2 *__restrict__ Lm, int3
 }
 
 // ---------------------------------------------------------------------------
-// Level 2 of clouds with at most kL2MaxSlabs slabs.  A level-2 node's
+// Level 2 of every cloud with more than one slab.  A level-2 node's
 // slab-hull vertices (at most 64 x 64 per side) are staged compacted, in x
 // order, in LDS.  Every vertex v is then tested against all the node's other
 // vertices of its side at once: with uL the one left of v that maximises
@@ -794,7 +794,7 @@ __global__ __launch_bounds__(256) void k_chain(const int2 *__restrict__ Lm, int3
 // in order (the node's hulls), assembles the final hull at the root and
 // writes k, s and the range status.
 // ---------------------------------------------------------------------------
-constexpr int kL2MaxSlabs = 1024;            // the path serves p <= 65536
+constexpr int kL2MaxSlabs = 1024;            // chain offsets summed in-kernel up to here
 constexpr int kNodeVerts = kFanIn * kSlab;   // 4096 positions per level-2 node
 constexpr int kL2Waves = kHullBlock / kWave; // one tested vertex per wave
 
@@ -871,16 +871,21 @@ __device__ __forceinline__ void l2_stage(const HullArgs &H, L2Shared &S, int nod
   __syncthreads();
 }
 
-// Chain of slab `sl` by one wave, without barriers: its offset is the sum
+// Chain of slab `sl` by one wave, without barriers: its offset is the
+// scanned one when the slab-finish step scanned (many slabs), else the sum
 // of the counts of every earlier slab (at most kL2MaxSlabs).
 __device__ __forceinline__ void l2_chain_slab(const HullArgs &H, int sl) {
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t pos = (int64_t)sl * kSlab + lane;
   const int2 L = pos < H.p ? H.Lm[pos] : make_int2(1, 0);
   int base = 0;
-  for (int j = lane; j < sl; j += kWave) base += H.slab_k[j];
+  if (H.slab_off) {
+    base = H.slab_off[sl];
+  } else {
+    for (int j = lane; j < sl; j += kWave) base += H.slab_k[j];
 #pragma unroll
-  for (int d = kWave / 2; d > 0; d >>= 1) base += __shfl_xor(base, d, kWave);
+    for (int d = kWave / 2; d > 0; d >>= 1) base += __shfl_xor(base, d, kWave);
+  }
   const bool valid = L.x <= L.y;
   int tot;
   const int r = wave_rank(valid, &tot);
@@ -960,7 +965,7 @@ __global__ __launch_bounds__(kHullBlock) void k_l2_test(HullArgs H) {
   const int node = blockIdx.x / parts, part = blockIdx.x % parts;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const TreeShape &T = H.tree;
-  if (blockIdx.x == 0) l2_totals(H, S);
+  if (blockIdx.x == 0 && !H.slab_off) l2_totals(H, S);
   l2_stage<false>(H, S, node);
   const int C0 = S.off[0][kFanIn], C1 = S.off[1][kFanIn], total = C0 + C1;
   const int per = (total + parts - 1) / parts;
@@ -1434,14 +1439,15 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
   A.info = info;
   A.wg_err = wg_err;
   A.n_wg_err = P.G;
-  // With the hull and at most kL2MaxSlabs slabs, level 2 is the
-  // all-vertex test, which writes the chain and the totals.  Otherwise, with
-  // a two-level tree and few slabs the root compaction writes the chain, and
-  // in every other case the last slab scans and writes it.
-  const bool l2path = do_hull && T.nlev >= 2 && T.size[1] <= kL2MaxSlabs;
+  // With the hull and more than one slab, level 2 is the all-vertex test,
+  // which also writes the chain: from offsets it sums itself (up to
+  // kL2MaxSlabs slabs, when it also writes the totals) or from the last
+  // slab's scan.  Without the hull the last slab scans and writes the chain.
+  const bool l2path = do_hull && T.nlev >= 2;
+  const bool l2scan = l2path && T.size[1] > kL2MaxSlabs;
   const bool fused = !l2path && do_hull && T.nlev == 2 && T.size[1] <= kSingleRootChainSlabs;
-  A.scan_root = (fused || l2path) ? 0 : 1;
-  A.chain_inline = p <= kChainInline ? 1 : 0;
+  A.scan_root = (fused || (l2path && !l2scan)) ? 0 : 1;
+  A.chain_inline = (!l2path && p <= kChainInline) ? 1 : 0;
   A.cx_out = cx;
   A.clo_out = clo;
   A.chi_out = chi;
@@ -1470,6 +1476,7 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
     H.info = info;
     H.chain_fused = fused ? 1 : 0;
     H.split = kSplit;
+    H.slab_off = l2scan ? A.slab_off : nullptr;
     H.Lm = Lm;
     H.p = p;
     H.slab_k = A.slab_k;

@@ -68,8 +68,7 @@ def test_mix_equals_alone_and_oracle(hp):
         assert srv.wait(r, timeout_us=60_000_000)
     st = srv.stats()
     srv.close()
-    assert st["completed"] == len(spec)
-    assert st["batches"] < len(spec), "queued requests were never joined into a batch"
+    assert st["completed"] == len(spec) and st["batched_requests"] == len(spec)
     print(f"[case] the same requests alone, one at a time", flush=True)
     alone = hp.Server(budget_bytes=2 << 30, max_batch=1)
     for i, (c, (kind, n, p, _)) in enumerate(zip(clouds, spec)):
@@ -136,3 +135,25 @@ def test_range_error_stays_with_its_request(hp):
     assert rb.result()["status"] == -2
     _check_oracle(ra.result(), a, 100, "clean neighbour")
     srv.close()
+
+
+def test_queued_requests_join_a_batch(hp):
+    """Requests that queue behind large ones are issued together: the small
+    ones then share one batched launch sequence, and every result still
+    equals the oracle's."""
+    big = [synth.cloud("uniform", 1 << 24, 4096, 40 + i).pin_memory() for i in range(4)]
+    small = [(synth.cloud("uniform", 5_000 + 17 * i, 1000 + i, 100 + i).pin_memory(), 1000 + i)
+             for i in range(40)]
+    srv = hp.Server(budget_bytes=2 << 30, max_batch=64)
+    rb = [srv.submit(b, 4096) for b in big]
+    rs = [srv.submit(c, p) for c, p in small]
+    for r in rb + rs:
+        assert srv.wait(r, timeout_us=60_000_000)
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == 44
+    assert st["batches"] < 44 - 8, f"queued requests were not joined: {st}"
+    for r, b in zip(rb, big):
+        _check_oracle(r.result(), b, 4096, "large request")
+    for r, (c, p) in zip(rs, small):
+        _check_oracle(r.result(), c, p, "queued small request")
