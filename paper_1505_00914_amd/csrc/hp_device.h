@@ -23,6 +23,7 @@ constexpr int kSplitSlab = 4;    // hull-test workgroups per slab
 // Control words at the head of every workspace.
 constexpr int kCtlErr = 0;       // bitmask of data errors seen by kernels
 constexpr int kCtlSlabsDone = 1; // slabs finished (last-arriver scan)
+constexpr int kCtlTestDone = 2;  // level-2 test workgroups done (single level-2 node)
 constexpr int kCtlWords = 64;
 
 constexpr int kErrRange = 1;     // a point outside [1, p]

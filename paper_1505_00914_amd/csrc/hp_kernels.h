@@ -172,6 +172,7 @@ struct HullArgs {
   int32_t *hx, *hy;
   int32_t hull_cap;
   int32_t *info;
+  int32_t *ctl;             // control words (single level-2 node: test arrivals)
   // chain written by the root compaction (two-level tree, small p)
   int32_t chain_fused;
   const int2 *Lm;

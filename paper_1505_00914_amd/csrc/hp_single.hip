@@ -954,31 +954,20 @@ __device__ __forceinline__ int2 wave_pick(int2 a, Pick pick) {
   return make_int2(__builtin_amdgcn_readlane(a.x, 63), __builtin_amdgcn_readlane(a.y, 63));
 }
 
-// H.split workgroups per level-2 node.  Each tests its share of the node's
-// vertices (one wave per vertex), writes its survivors in order to the
-// node's slot of buffer 1 at its share's first index, with their count per
-// side in l2cnt, and writes the chain of its share of the node's slabs.
+// Verdicts of the node's vertices q0 .. q1-1 (index q runs over the lower
+// side, then the upper side), one wave per vertex: lanes scan the vertices
+// left of v and right of v; an empty extreme stays at v itself (same x),
+// which the wave reduction never prefers.  flag[q - q0] = 1 iff v survives.
 template <bool SMALL>
-__global__ __launch_bounds__(kHullBlock) void k_l2_test(HullArgs H) {
-  __shared__ L2Shared S;
-  const int parts = H.split;
-  const int node = blockIdx.x / parts, part = blockIdx.x % parts;
-  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-  const TreeShape &T = H.tree;
-  if (blockIdx.x == 0 && !H.slab_off) l2_totals(H, S);
-  l2_stage<false>(H, S, node);
-  const int C0 = S.off[0][kFanIn], C1 = S.off[1][kFanIn], total = C0 + C1;
-  const int per = (total + parts - 1) / parts;
-  const int q0 = min(total, part * per), q1 = min(total, q0 + per);
-  uint8_t *flag = reinterpret_cast<uint8_t *>(S.keepw);   // this share's verdicts
+__device__ __forceinline__ void l2_test_share(const L2Shared &S, int q0, int q1, int C0, int C1,
+                                              uint8_t *flag) {
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   for (int q = q0 + wave; q < q1; q += kL2Waves) {
     const int side = q < C0 ? 0 : 1;
     const int i = side ? q - C0 : q;
     const int cs = side ? C1 : C0;
     const int2 *Pp = S.P[side];
     const int2 v = Pp[i];
-    // lanes scan the vertices left of v and right of v; an empty extreme
-    // stays at v itself (same x), which the merge below never prefers
     int2 uL = v, wR = v;
     for (int k = lane; k < i; k += kWave) {
       const int2 u = Pp[k];
@@ -996,8 +985,25 @@ __global__ __launch_bounds__(kHullBlock) void k_l2_test(HullArgs H) {
     });
     if (lane == 0) flag[q - q0] = (uL.x == v.x || wR.x == v.x || cross_pos<SMALL>(uL, v, wR)) ? 1 : 0;
   }
-  __syncthreads();
-  // survivors of each side of the share, in order (waves 0 and 1; a share
+}
+
+// H.split workgroups per level-2 node.  Each tests its share of the node's
+// vertices (one wave per vertex), writes its survivors in order to the
+// node's slot of buffer 1 at its share's first index, with their count per
+// side in l2cnt, and writes the chain of its share of the node's slabs.
+template <bool SMALL>
+__device__ __forceinline__ void l2_test_body(const HullArgs &H, L2Shared &S, const int node, const int part) {
+  const int parts = H.split;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  const TreeShape &T = H.tree;
+  if (node == 0 && part == 0 && !H.slab_off) l2_totals(H, S);
+  l2_stage<false>(H, S, node);
+  const int C0 = S.off[0][kFanIn], C1 = S.off[1][kFanIn], total = C0 + C1;
+  const int per = (total + parts - 1) / parts;
+  const int q0 = min(total, part * per), q1 = min(total, q0 + per);
+  uint8_t *flag = reinterpret_cast<uint8_t *>(S.keepw);   // this share's verdicts
+  l2_test_share<SMALL>(S, q0, q1, C0, C1, flag);
+  __syncthreads();  // survivors of each side of the share, in order (waves 0 and 1; a share
   // is at most a few hundred vertices)
   if (wave < 2) {
     const int side = wave;
@@ -1020,12 +1026,16 @@ __global__ __launch_bounds__(kHullBlock) void k_l2_test(HullArgs H) {
   if (wave < per_slabs && part * per_slabs + wave < kFanIn && sl < T.size[1]) l2_chain_slab(H, sl);
 }
 
+template <bool SMALL>
+__global__ __launch_bounds__(kHullBlock) void k_l2_test(HullArgs H) {
+  __shared__ L2Shared S;
+  l2_test_body<SMALL>(H, S, blockIdx.x / H.split, blockIdx.x % H.split);
+}
+
 // One workgroup per level-2 node: the shares' survivors joined in order
 // (the node's hulls in buffer 1), or, at the root, the final vertex list.
 template <bool SMALL>
-__global__ __launch_bounds__(kHullBlock) void k_l2_compact(HullArgs H) {
-  __shared__ L2Shared S;
-  const int node = blockIdx.x;
+__device__ __forceinline__ void l2_compact_body(const HullArgs &H, L2Shared &S, const int node) {
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const TreeShape &T = H.tree;
   const int parts = H.split;
@@ -1095,6 +1105,143 @@ __global__ __launch_bounds__(kHullBlock) void k_l2_compact(HullArgs H) {
   }
 }
 
+template <bool SMALL>
+__global__ __launch_bounds__(kHullBlock) void k_l2_compact(HullArgs H) {
+  __shared__ L2Shared S;
+  l2_compact_body<SMALL>(H, S, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// A cloud whose slabs form a single level-2 node (2 to 64 slabs): the test
+// workgroups also finish the cloud, with no compaction launch.  Each issues
+// every load it needs in one round (the node's slots and slab-hull sizes;
+// the L columns and earlier slab counts of its chain slab; for workgroup 0
+// the counts and error words of the totals), tests its share of the
+// vertices, and stores its verdict bytes, its chain slab and the totals.
+// The last workgroup to finish (acquire-release count) still holds every
+// vertex of the node in LDS: it loads all verdicts, compacts the survivors
+// of each side in x order and writes the hull.  Needs H.split >= slabs.
+// ---------------------------------------------------------------------------
+template <bool SMALL>
+__global__ __launch_bounds__(kHullBlock) void k_l2_root(HullArgs H) {
+  __shared__ L2Shared S;
+  __shared__ int s_flag;
+  const int parts = H.split, part = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  const int nslab = H.tree.size[1];
+  // chain slab `part` (last wave) and the totals (workgroup 0, wave before
+  // it): loads first, used after the test
+  const bool chain_w = wave == kL2Waves - 1 && part < nslab;
+  const bool tot_w = wave == kL2Waves - 2 && part == 0;
+  int2 cL = make_int2(1, 0);
+  int cbase = 0, tk = 0, ts = 0, te = 0;
+  if (chain_w) {
+    const int64_t pos = (int64_t)part * kSlab + lane;
+    if (pos < H.p) cL = H.Lm[pos];
+    if (lane < part) cbase = H.slab_k[lane];
+  }
+  if (tot_w) {
+    if (lane < nslab) {
+      tk = H.slab_k[lane];
+      ts = H.slab_s[lane];
+    }
+    for (int j = lane; j < H.n_wg_err; j += kWave) te |= H.wg_err[j];
+  }
+  l2_stage<false>(H, S, 0);
+  const int C0 = S.off[0][kFanIn], C1 = S.off[1][kFanIn], total = C0 + C1;
+  const int per = (total + parts - 1) / parts;
+  const int q0 = min(total, part * per), q1 = min(total, q0 + per);
+  uint8_t *flag = reinterpret_cast<uint8_t *>(S.keepw);
+  l2_test_share<SMALL>(S, q0, q1, C0, C1, flag);
+  __syncthreads();
+  for (int j = tid; j < q1 - q0; j += kHullBlock) H.keep[q0 + j] = flag[j];
+  if (chain_w) {
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) cbase += __shfl_xor(cbase, d, kWave);
+    const bool valid = cL.x <= cL.y;
+    int tot;
+    const int r = wave_rank(valid, &tot);
+    if (valid) {
+      const int o = cbase + r;
+      if (o < H.chain_cap) {
+        H.cx[o] = part * kSlab + lane + 1;
+        H.clo[o] = cL.x;
+        H.chi[o] = cL.y;
+      } else {
+        atomicMin(&H.info[HP_INFO_STATUS], HP_ECAPACITY);
+      }
+    }
+  }
+  if (tot_w) {
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+      tk += __shfl_xor(tk, d, kWave);
+      ts += __shfl_xor(ts, d, kWave);
+      te |= __shfl_xor(te, d, kWave);
+    }
+    if (lane == 0) {
+      H.info[HP_INFO_K] = tk;
+      H.info[HP_INFO_S] = ts;
+      if (te & kErrRange) atomicMin(&H.info[HP_INFO_STATUS], HP_ERANGE);
+    }
+  }
+  if (!last_arrival_flag(&H.ctl[kCtlTestDone], parts, &s_flag)) return;
+
+  // the root: every verdict (at most 2 x 4096 bytes, two words per thread)
+  const uint32_t *kw = reinterpret_cast<const uint32_t *>(H.keep);
+  const int nw = (total + 3) / 4;
+  uint32_t w2[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) w2[u] = tid + u * kHullBlock < nw ? kw[tid + u * kHullBlock] : 0u;
+  uint32_t *kl = &S.keepw[0][0];   // both rows, 2 x 1024 words
+#pragma unroll
+  for (int u = 0; u < 2; ++u) kl[tid + u * kHullBlock] = w2[u];
+  __syncthreads();
+  // survivors of each side in x order: slot idx = side * 4096 + i, eight
+  // per thread; a wave's 64 lanes cover one run of 64 slots (chunk)
+  constexpr int kPer = 2 * kNodeVerts / kHullBlock;
+  int2 v[kPer];
+  bool keep[kPer];
+  int rank[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int idx = tid + u * kHullBlock;
+    const int side = idx / kNodeVerts, i = idx % kNodeVerts;
+    const int C = side ? C1 : C0;
+    keep[u] = i < C && flag[side ? C0 + i : i] != 0;
+    v[u] = keep[u] ? S.P[side][i] : make_int2(0, 0);
+    int tot;
+    rank[u] = wave_rank(keep[u], &tot);
+    if (lane == 0) S.soff[side][(idx % kNodeVerts) / kWave] = tot;
+  }
+  __syncthreads();
+  if (wave < 2) {
+    // exclusive scan of the 64 chunk counts of side `wave`
+    const int m = S.soff[wave][lane];
+    int incl = m;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const int o = __shfl_up(incl, d, kWave);
+      if (lane >= d) incl += o;
+    }
+    S.soff[wave][lane] = incl - m;
+    if (lane == kWave - 1) S.sum[wave] = incl;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int idx = tid + u * kHullBlock;
+    const int side = idx / kNodeVerts, i = idx % kNodeVerts;
+    if (keep[u]) S.P[side][S.soff[side][i / kWave] + rank[u]] = v[u];
+  }
+  __syncthreads();
+  bool overflow = false;
+  const int h = assemble_hull(S.P[0], S.sum[0], S.P[1], S.sum[1], H.hx, H.hy, H.hull_cap, overflow);
+  if (tid == 0) {
+    H.info[HP_INFO_H] = overflow ? 0 : h;
+    if (overflow) atomicMin(&H.info[HP_INFO_STATUS], HP_ECAPACITY);
+  }
+}
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
@@ -1327,9 +1474,7 @@ static hipError_t dispatch_reduce(const Plan1 &P, const int32_t *pts, int64_t n,
 
 // Hull levels 2..nlev: a test launch and a compaction launch per level (the
 // slab level ran in k_finish).  H must have its chain fields filled.
-static hipError_t launch_hull_levels(const TreeShape &T, int64_t positions, char *w, const Layout &Y,
-                                     HullArgs H, bool small, hipStream_t s, bool l2path = false) {
-  if (T.nlev < 2) return hipSuccess;
+static void hull_buffers(HullArgs &H, const TreeShape &T, int64_t positions, char *w, const Layout &Y) {
   H.buf[0] = reinterpret_cast<int2 *>(w + Y.cand);
   H.buf[1] = H.buf[0] + 2 * (size_t)positions;
   H.keep = reinterpret_cast<uint8_t *>(w + Y.keep);
@@ -1338,7 +1483,21 @@ static hipError_t launch_hull_levels(const TreeShape &T, int64_t positions, char
   H.ccount = reinterpret_cast<int32_t *>(w + Y.ccount);
   H.tree = T;
   H.positions = (int32_t)positions;
+}
+
+static hipError_t launch_hull_levels(const TreeShape &T, int64_t positions, char *w, const Layout &Y,
+                                     HullArgs H, bool small, hipStream_t s, bool l2path = false) {
+  if (T.nlev < 2) return hipSuccess;
+  hull_buffers(H, T, positions, w, Y);
   int first = 2;
+  if (l2path && T.nlev == 2) {
+    // a single level-2 node: its test workgroups also write the hull (two
+    // per slab, at least one per slab for the chain)
+    H.split = std::min(kL2MaxParts, 2 * T.size[1]);
+    if (small) hipLaunchKernelGGL((k_l2_root<true>), dim3(H.split), dim3(kHullBlock), 0, s, H);
+    else hipLaunchKernelGGL((k_l2_root<false>), dim3(H.split), dim3(kHullBlock), 0, s, H);
+    return hipGetLastError();
+  }
   if (l2path) {
     // level 2 by the all-vertex test, which also writes the chain and the
     // totals (H carries the chain fields and the slab counts)
@@ -1454,6 +1613,25 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
   A.chain_cap = chain_cap;
   // coordinates of L are at most p: below 2^15 the hull runs on 24-bit products
   const bool small = p < (1 << 15);
+  HullArgs H;
+  memset(&H, 0, sizeof(H));
+  H.hx = hx;
+  H.hy = hy;
+  H.hull_cap = hull_cap;
+  H.info = info;
+  H.chain_fused = fused ? 1 : 0;
+  H.split = kSplit;
+  H.slab_off = l2scan ? A.slab_off : nullptr;
+  H.Lm = Lm;
+  H.p = p;
+  H.slab_k = A.slab_k;
+  H.slab_s = A.slab_s;
+  H.wg_err = wg_err;
+  H.n_wg_err = P.G;
+  H.cx = cx;
+  H.clo = clo;
+  H.chi = chi;
+  H.chain_cap = chain_cap;
   if (small)
     hipLaunchKernelGGL((k_finish<0, true>), dim3(T.size[1]), dim3(kFinBlock), 0, s, A);
   else
@@ -1468,25 +1646,7 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
     if (e != hipSuccess) return set_error(HP_EDEVICE, "k_chain launch: %s", hipGetErrorString(e));
   }
   if (do_hull) {
-    HullArgs H;
-    memset(&H, 0, sizeof(H));
-    H.hx = hx;
-    H.hy = hy;
-    H.hull_cap = hull_cap;
-    H.info = info;
-    H.chain_fused = fused ? 1 : 0;
-    H.split = kSplit;
-    H.slab_off = l2scan ? A.slab_off : nullptr;
-    H.Lm = Lm;
-    H.p = p;
-    H.slab_k = A.slab_k;
-    H.slab_s = A.slab_s;
-    H.wg_err = wg_err;
-    H.n_wg_err = P.G;
-    H.cx = cx;
-    H.clo = clo;
-    H.chi = chi;
-    H.chain_cap = chain_cap;
+    H.ctl = ctl;
     e = launch_hull_levels(T, p, w, Y, H, small, s, l2path);
     if (e != hipSuccess) return set_error(HP_EDEVICE, "hull level launch: %s", hipGetErrorString(e));
   }
