@@ -24,6 +24,9 @@ ARCH = os.environ.get("HP_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # keep single-lane atomics as issued: the wave-aggregated form reads the
+    # result at once, which would expose the reduce's chunk grabs
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
     "-Wall", "-Wno-unused-result", "-Wno-unused-function",
     f"-I{INCLUDE}", f"-I{CSRC}",
 ]

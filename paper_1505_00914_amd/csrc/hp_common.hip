@@ -39,7 +39,7 @@ const DeviceInfo &device_info() {
     D.cus = (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, d) == hipSuccess && v > 0) ? v : 256;
     D.lds_bytes = (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, d) == hipSuccess && v > 0) ? v : 65536;
     D.max_threads_cu = (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxThreadsPerMultiProcessor, d) == hipSuccess && v > 0) ? v : 2048;
-    D.lds_max_p = D.lds_bytes / 8 - 1;  // p pairs plus one flag word
+    D.lds_max_p = D.lds_bytes / 8 - 2;  // p pairs plus the reduce's flag and grab words
     g_dev[d] = D;
     g_dev_ok[d] = true;
   }

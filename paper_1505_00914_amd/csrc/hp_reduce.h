@@ -79,6 +79,148 @@ __device__ __forceinline__ void stream_points(const int32_t *__restrict__ pts, i
   }
 }
 
+// Work sharing of the single-cloud reduce.  The vector body is cut into
+// chunks of BLOCK * VPT vectors (the last one possibly partial).  Workgroup
+// wg first takes chunks wg, wg + nwg, ... below `nstat` (a fixed fraction of
+// its equal share); the chunks from nstat on are handed out in pairs by a
+// device-wide counter, so that workgroups that started late (whole XCDs are
+// dispatched microseconds apart) or stream slowly take fewer of them.
+// Thread 0 issues the grab of the next pair when it hands out the current
+// one, so the atomic's latency hides behind two chunks of streaming, and
+// passes the pair to the workgroup through LDS (the barrier waits on LDS
+// only, not on the loads in flight).  The counter is zero at the start of a
+// run and is cleared by the finish step; each workgroup records how many
+// chunks it folded so that the finish step can check that every chunk was
+// folded exactly once.
+struct DynArgs {
+  unsigned long long *ctr;  // grab counter, zero at the start of the run (null: static only)
+  int32_t *wg_cnt;          // per workgroup: chunks folded
+  int32_t static_frac8;     // static share, in eighths of the equal share
+};
+
+__host__ __device__ __forceinline__ int64_t dyn_chunks(int64_t n, uintptr_t pts, int64_t chunk) {
+  const int64_t head = (n > 0 && (pts & 15) != 0) ? 1 : 0;
+  const int64_t nv = (n - head) >> 1;
+  return (nv + chunk - 1) / chunk;
+}
+
+template <int BLOCK, int VPT, bool LDS>
+__device__ __forceinline__ void stream_points_dyn(const int32_t *__restrict__ pts, int64_t n, int p, int2 *L,
+                                                  int64_t wg, int64_t nwg, bool &bad, const DynArgs &D,
+                                                  int *s_slot) {
+  const int64_t head = (n > 0 && ((uintptr_t)pts & 15) != 0) ? 1 : 0;
+  const int64_t nv = (n - head) >> 1;
+  const int64_t tail = head + 2 * nv;
+  if (wg == 0 && threadIdx.x == 0) {
+    if (head) {
+      if (LDS) fold_point_lds(L, p, pts[0], pts[1], bad);
+      else fold_point_global(L, p, pts[0], pts[1], bad);
+    }
+    if (tail < n) {
+      if (LDS) fold_point_lds(L, p, pts[2 * tail], pts[2 * tail + 1], bad);
+      else fold_point_global(L, p, pts[2 * tail], pts[2 * tail + 1], bad);
+    }
+  }
+  const int4 *v = reinterpret_cast<const int4 *>(pts + 2 * head);
+  constexpr int64_t chunk = (int64_t)BLOCK * VPT;
+  const int64_t nfull = nv / chunk;
+  const int64_t ntot = (nv + chunk - 1) / chunk;   // nfull, plus a partial chunk
+  // static chunks per workgroup: none, or at least two (the first grab goes
+  // out two chunks before the static ones run out)
+  int64_t mine = (ntot / nwg) * D.static_frac8 / 8;
+  if (mine < 2) mine = 0;
+  const int64_t nstat = mine * nwg;
+  const bool dyn = ntot > nstat;
+  int64_t k = 0;                  // static chunks handed out
+  int pos = 0;                    // chunks of the current pair handed out (0: need a grab)
+  int64_t pair = 0;               // first chunk of the current pair
+  int slot = 0;                   // LDS slot of the next refill (two, used in turn)
+  unsigned long long g = 0;       // thread 0: the grab in flight
+  bool issued = false;            // thread 0: whether g is in flight
+  // the next chunk index of this workgroup, or -1; uniform over the workgroup
+  auto next = [&]() -> int64_t {
+    if (k < mine) {
+      const int64_t c = wg + k * nwg;
+      ++k;
+      if (dyn && threadIdx.x == 0 && k == mine - 2) {
+        g = __hip_atomic_fetch_add(D.ctr, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        issued = true;
+      }
+      return c;
+    }
+    if (!dyn) return -1;
+    if (pos == 1) {
+      pos = 0;
+      return pair + 1 < ntot ? pair + 1 : -1;
+    }
+    if (threadIdx.x == 0) {
+      if (!issued) g = __hip_atomic_fetch_add(D.ctr, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_slot[slot] = (int)(g < 0x7fffffffull ? g : 0x7fffffffull);   // pairs: far below 2^31
+      g = __hip_atomic_fetch_add(D.ctr, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      issued = true;
+    }
+    // one barrier per refill: a slot is written again only two refills
+    // later, after every wave has passed the barrier in between
+    __syncthreads();
+    pair = nstat + 2 * (int64_t)s_slot[slot];
+    slot ^= 1;
+    pos = 1;
+    return pair < ntot ? pair : -1;
+  };
+  // chunk indices run one ahead of the loads: the barrier of a refill is
+  // taken while the next chunk's loads are in flight
+  int folded = 0;
+  int64_t part = -1;              // the partial chunk, if this workgroup gets it
+  const bool has_part = ntot > nfull;
+  auto take = [&](int64_t c) -> int64_t {
+    if (has_part && c == nfull) {
+      part = c;
+      return -1;
+    }
+    return c;
+  };
+  int64_t cur = take(next());
+  int64_t nx = cur >= 0 ? take(next()) : -1;
+  int4 q[VPT];
+  if (cur >= 0) {
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) q[u] = v[cur * chunk + u * BLOCK + threadIdx.x];
+  }
+  while (cur >= 0) {
+    const int64_t tl = nx >= 0 ? nx : cur;
+    Batch<VPT> b;
+    gather<VPT, LDS>(L, p, q, b, bad);
+    int4 qn[VPT];
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) qn[u] = v[tl * chunk + u * BLOCK + threadIdx.x];
+    apply<VPT, LDS>(L, b);
+    ++folded;
+    const int64_t nn = nx >= 0 ? take(next()) : -1;
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) q[u] = qn[u];
+    cur = nx;
+    nx = nn;
+  }
+  if (part >= 0) {
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+      const int64_t idx = part * chunk + u * BLOCK + threadIdx.x;
+      if (idx < nv) {
+        const int4 r = v[idx];
+        if (LDS) {
+          fold_point_lds(L, p, r.x, r.y, bad);
+          fold_point_lds(L, p, r.z, r.w, bad);
+        } else {
+          fold_point_global(L, p, r.x, r.y, bad);
+          fold_point_global(L, p, r.z, r.w, bad);
+        }
+      }
+    }
+    ++folded;
+  }
+  if (threadIdx.x == 0) D.wg_cnt[wg] = folded;
+}
+
 // Control words the finish step relies on.  When no init kernel runs (the
 // partial-L strategy), workgroup 0 of the reduce kernel clears them: the
 // finish kernel only starts after the reduce kernel has completed.
@@ -103,15 +245,17 @@ __device__ __forceinline__ void reset_controls(const ResetArgs &R) {
 template <int BLOCK, int VPT, bool MERGE_ATOMIC>
 __global__ __launch_bounds__(BLOCK) void k_reduce_lds(const int32_t *__restrict__ pts, int64_t n,
                                                       int32_t p, int2 *__restrict__ out_L,
-                                                      int32_t *__restrict__ wg_err, ResetArgs R) {
-  extern __shared__ int2 sL[];           // p pairs, then one flag word
-  int &s_bad = reinterpret_cast<int &>(sL[p]);
+                                                      int32_t *__restrict__ wg_err, ResetArgs R, DynArgs D) {
+  extern __shared__ int2 sL[];           // p pairs, then the flag word and the two grab slots
+  int &s_bad = sL[p].x;
+  int *s_slot = &sL[p].y;                // sL[p].y and sL[p + 1].x
   reset_controls(R);
   if (threadIdx.x == 0) s_bad = 0;
   for (int c = threadIdx.x; c < p; c += BLOCK) sL[c] = make_int2(p + 1, -1);
   __syncthreads();
   bool bad = false;
-  stream_points<BLOCK, VPT, true>(pts, n, p, sL, blockIdx.x, gridDim.x, bad);
+  if (D.ctr) stream_points_dyn<BLOCK, VPT, true>(pts, n, p, sL, blockIdx.x, gridDim.x, bad, D, s_slot);
+  else stream_points<BLOCK, VPT, true>(pts, n, p, sL, blockIdx.x, gridDim.x, bad);
   if (bad) s_bad = 1;
   __syncthreads();
   if (MERGE_ATOMIC) {
@@ -175,13 +319,15 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_window(const int32_t *__restri
 template <int BLOCK, int VPT>
 __global__ __launch_bounds__(BLOCK) void k_reduce_global(const int32_t *__restrict__ pts, int64_t n,
                                                          int32_t p, int2 *L,
-                                                         int32_t *__restrict__ wg_err, ResetArgs R) {
+                                                         int32_t *__restrict__ wg_err, ResetArgs R, DynArgs D) {
   __shared__ int s_bad;
+  __shared__ int s_slot[2];
   reset_controls(R);
   if (threadIdx.x == 0) s_bad = 0;
   __syncthreads();
   bool bad = false;
-  stream_points<BLOCK, VPT, false>(pts, n, p, L, blockIdx.x, gridDim.x, bad);
+  if (D.ctr) stream_points_dyn<BLOCK, VPT, false>(pts, n, p, L, blockIdx.x, gridDim.x, bad, D, s_slot);
+  else stream_points<BLOCK, VPT, false>(pts, n, p, L, blockIdx.x, gridDim.x, bad);
   if (bad) s_bad = 1;
   __syncthreads();
   if (threadIdx.x == 0) wg_err[blockIdx.x] = s_bad ? kErrRange : 0;

@@ -1,5 +1,8 @@
 // hp_single.hip -- single-cloud kernels and entry points of libhullprep.
+#include <atomic>
 #include <climits>
+#include <cstdlib>
+#include <mutex>
 #include <cstring>
 
 #include <hip/hip_ext.h>
@@ -50,6 +53,7 @@ struct FinishShared {
   int slab_cnt[2];
   int flag;
   int scan_carry;
+  int folded;                  // chunks the reduce workgroups report (slab 0)
 };
 
 // Exclusive scan of n ints in place (by one workgroup); returns the total.
@@ -115,6 +119,14 @@ __device__ __forceinline__ void finish_body(const FinishArgs &A, FinishShared &S
   const int64_t pos = (int64_t)slab * kSlab + lane;
   const bool inside = pos < A.positions;
 
+  // ---- slab 0: the reduce's chunk accounting (loads issued with the fold's)
+  const bool check = !FROM_CHAIN && slab == 0 && A.dyn_ctr != nullptr;
+  int folded = 0;
+  if (check) {
+    if (tid == 0) S.folded = 0;
+    for (int j = tid; j < A.n_wg_err; j += kFinBlock) folded += A.wg_cnt[j];
+  }
+
   // ---- the slab's points --------------------------------------------------
   int x = 0, lo = 0, hi = -1;
   bool valid = false;
@@ -151,6 +163,11 @@ __device__ __forceinline__ void finish_body(const FinishArgs &A, FinishShared &S
     }
     S.red[grp][lane] = make_int2(mlo, mhi);
     __syncthreads();
+    if (check) {
+#pragma unroll
+      for (int d = kWave / 2; d > 0; d >>= 1) folded += __shfl_xor(folded, d, kWave);
+      if (lane == 0 && folded) atomicAdd(&S.folded, folded);
+    }
     if (grp == 0) {
       for (int k = 1; k < kFinGroups; ++k) {
         mlo = min(mlo, S.red[k][lane].x);
@@ -193,6 +210,12 @@ __device__ __forceinline__ void finish_body(const FinishArgs &A, FinishShared &S
     }
   }
   __syncthreads();
+  if (check && tid == 0) {
+    // every chunk folded exactly once; the counter is zero again for the
+    // next run that uses its slot
+    if ((int64_t)S.folded != A.dyn_expect) atomicMin(&A.info[HP_INFO_STATUS], HP_EDEVICE);
+    __hip_atomic_store(A.dyn_ctr, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 
   // ---- slab hull: every valid point against the 63 others of its slab.
   // 128 candidates (64 positions x 2 sides), 8 lanes each; lane g of a
@@ -1265,8 +1288,46 @@ static TreeShape make_tree(int64_t positions) {
   return T;
 }
 
+// Grab counters of the reduce's shared chunks: one slot per run, taken in
+// turn, zero-initialised with the module and cleared by the finish step of
+// the run that used it.  Runs in flight at the same time on one device take
+// different slots unless more than kGrabSlots of them overlap.
+constexpr int kGrabSlots = 4096;
+__device__ unsigned long long g_grab[kGrabSlots];
+
+static unsigned long long *grab_counter() {
+  static std::mutex mu;
+  static unsigned long long *base[64] = {};
+  static std::atomic<uint32_t> seq{0};
+  const int d = device_info().device;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    if (!base[d]) {
+      void *ptr = nullptr;
+      if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(g_grab)) != hipSuccess || !ptr) return nullptr;
+      base[d] = static_cast<unsigned long long *>(ptr);
+    }
+  }
+  return base[d] + (seq.fetch_add(1, std::memory_order_relaxed) % kGrabSlots);
+}
+
+// Chunks per reduce workgroup from which the chunks are shared.
+constexpr int64_t kDynMinChunks = 32;
+
+// Static share of the shared-chunk reduce in eighths (HP_DYN_STATIC8, 0..8;
+// HP_DYN_OFF=1 turns chunk sharing off).
+static int dyn_static8() {
+  static int v = -2;
+  if (v == -2) {
+    const char *off = getenv("HP_DYN_OFF");
+    const char *e = getenv("HP_DYN_STATIC8");
+    v = (off && atoi(off) == 1) ? -1 : (e ? std::max(0, std::min(8, atoi(e))) : 6);
+  }
+  return v;
+}
+
 struct Layout {
-  size_t ctl, tree, wg_err, slab_k, slab_s, slab_off, Lm, part, cand, keep, l2cnt, ccount, total;
+  size_t ctl, tree, wg_err, wg_cnt, slab_k, slab_s, slab_off, Lm, part, cand, keep, l2cnt, ccount, total;
 };
 
 static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -1291,6 +1352,7 @@ static Layout make_layout(int64_t positions, int32_t p, int64_t part_pairs, cons
   Y.ctl = o;      o = align_up(o + sizeof(int32_t) * kCtlWords);
   Y.tree = o;     o = align_up(o + sizeof(int32_t) * (size_t)T.nodes);
   Y.wg_err = o;   o = align_up(o + sizeof(int32_t) * (size_t)kMaxGrid);
+  Y.wg_cnt = o;   o = align_up(o + sizeof(int32_t) * (size_t)kMaxGrid);
   Y.slab_k = o;   o = align_up(o + sizeof(int32_t) * (size_t)T.size[1]);
   Y.slab_s = o;   o = align_up(o + sizeof(int32_t) * (size_t)T.size[1]);
   Y.slab_off = o; o = align_up(o + sizeof(int32_t) * (size_t)T.size[1]);
@@ -1416,7 +1478,8 @@ static hipError_t launch(K kernel, dim3 grid, dim3 block, size_t lds, hipStream_
 
 template <int BLOCK, int VPT, bool ATOMIC>
 static hipError_t launch_lds(const Plan1 &P, const int32_t *pts, int64_t n, int32_t p, int2 *out,
-                             int32_t *wg_err, ResetArgs R, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+                             int32_t *wg_err, ResetArgs R, DynArgs D, hipStream_t s, hipEvent_t e0,
+                             hipEvent_t e1) {
   static bool attr_set = false;
   if (!attr_set) {
     const hipError_t e = hipFuncSetAttribute((const void *)k_reduce_lds<BLOCK, VPT, ATOMIC>,
@@ -1425,18 +1488,18 @@ static hipError_t launch_lds(const Plan1 &P, const int32_t *pts, int64_t n, int3
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  return launch(k_reduce_lds<BLOCK, VPT, ATOMIC>, dim3(P.G), dim3(BLOCK), sizeof(int2) * ((size_t)p + 1), s,
-                e0, e1, pts, n, p, out, wg_err, R);
+  return launch(k_reduce_lds<BLOCK, VPT, ATOMIC>, dim3(P.G), dim3(BLOCK), sizeof(int2) * ((size_t)p + 2), s,
+                e0, e1, pts, n, p, out, wg_err, R, D);
 }
 
 template <int BLOCK, int VPT>
 static hipError_t launch_reduce(const Plan1 &P, const int32_t *pts, int64_t n, int32_t p, int2 *Lm,
-                                int2 *part, int32_t *wg_err, ResetArgs R, hipStream_t s, hipEvent_t e0,
-                                hipEvent_t e1) {
+                                int2 *part, int32_t *wg_err, ResetArgs R, DynArgs D, hipStream_t s,
+                                hipEvent_t e0, hipEvent_t e1) {
   if (P.strategy == HP_STRATEGY_LDS)
-    return launch_lds<BLOCK, VPT, true>(P, pts, n, p, Lm, wg_err, R, s, e0, e1);
+    return launch_lds<BLOCK, VPT, true>(P, pts, n, p, Lm, wg_err, R, D, s, e0, e1);
   if (P.strategy == HP_STRATEGY_LDS_PARTIAL)
-    return launch_lds<BLOCK, VPT, false>(P, pts, n, p, part, wg_err, R, s, e0, e1);
+    return launch_lds<BLOCK, VPT, false>(P, pts, n, p, part, wg_err, R, D, s, e0, e1);
   if (P.strategy == HP_STRATEGY_WINDOW) {
     static bool attr_set = false;
     if (!attr_set) {
@@ -1450,15 +1513,15 @@ static hipError_t launch_reduce(const Plan1 &P, const int32_t *pts, int64_t n, i
                   e0, e1, pts, n, p, P.W, P.wc, reinterpret_cast<uint32_t *>(part), wg_err, R);
   }
   return launch(k_reduce_global<BLOCK, VPT>, dim3(P.G), dim3(BLOCK), 0, s, e0, e1, pts, n, p, Lm,
-                wg_err, R);
+                wg_err, R, D);
 }
 
 static hipError_t dispatch_reduce(const Plan1 &P, const int32_t *pts, int64_t n, int32_t p, int2 *Lm,
-                                  int2 *part, int32_t *wg_err, ResetArgs R, hipStream_t s,
+                                  int2 *part, int32_t *wg_err, ResetArgs R, DynArgs D, hipStream_t s,
                                   hipEvent_t e0, hipEvent_t e1) {
 #define HP_CASE(B, V) \
   if (P.block == B && P.vpt == V)   \
-    return launch_reduce<B, V>(P, pts, n, p, Lm, part, wg_err, R, s, e0, e1);
+    return launch_reduce<B, V>(P, pts, n, p, Lm, part, wg_err, R, D, s, e0, e1);
   HP_CASE(1024, 4)
   HP_CASE(1024, 2)
   HP_CASE(1024, 8)
@@ -1567,9 +1630,19 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
     e = hipGetLastError();
     if (e != hipSuccess) return set_error(HP_EDEVICE, "k_init launch: %s", hipGetErrorString(e));
   }
+  // chunk sharing for the LDS and device-L strategies when every workgroup
+  // has many chunks to stream: one counter serves about one grab per 10 ns,
+  // which short runs would saturate
+  DynArgs D;
+  D.ctr = nullptr;
+  D.wg_cnt = reinterpret_cast<int32_t *>(w + Y.wg_cnt);
+  D.static_frac8 = dyn_static8();
+  const int64_t nchunks = dyn_chunks(n, (uintptr_t)pts, (int64_t)P.block * P.vpt);
+  if (D.static_frac8 >= 0 && P.strategy != HP_STRATEGY_WINDOW && nchunks >= kDynMinChunks * (int64_t)P.G)
+    D.ctr = grab_counter();
   hipEvent_t e0 = nullptr, e1 = nullptr;
   timing_slot(&e0, &e1);
-  e = dispatch_reduce(P, pts, n, p, Lm, part, wg_err, R, s, e0, e1);
+  e = dispatch_reduce(P, pts, n, p, Lm, part, wg_err, R, D, s, e0, e1);
   if (e != hipSuccess) return set_error(HP_EDEVICE, "reduce launch: %s", hipGetErrorString(e));
 
   FinishArgs A;
@@ -1598,6 +1671,9 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
   A.info = info;
   A.wg_err = wg_err;
   A.n_wg_err = P.G;
+  A.dyn_ctr = D.ctr;
+  A.wg_cnt = D.wg_cnt;
+  A.dyn_expect = nchunks;
   // With the hull and more than one slab, level 2 is the all-vertex test,
   // which also writes the chain: from offsets it sums itself (up to
   // kL2MaxSlabs slabs, when it also writes the totals) or from the last

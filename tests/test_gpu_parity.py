@@ -162,6 +162,28 @@ def test_launch_shapes(hp):
     hp.tune_set(0, 0, 0, 0)
 
 
+@pytest.mark.parametrize("n,offset", [
+    (262_144, 0),        # chunks divide the vectors evenly
+    (262_145, 0),        # odd count: a last single point
+    (250_001, 1),        # start 8 bytes past 16-byte alignment, odd count
+    (250_000, 1),        # misaligned start, partial last chunk
+])
+def test_shared_chunks(hp, n, offset):
+    """Small grids so that most chunks are handed out by the grab counter:
+    every strategy that shares chunks, two runs in a row on one workspace
+    (the counter is cleared between runs), against the oracle."""
+    base = synth.cloud("ellipsoids", n + offset, 1500, 31 + n % 7)
+    pts = base[offset:]
+    want = _oracle(pts.numpy(), 1500)
+    full = base.cuda()
+    dev = full[offset:]
+    for strategy, grid in ((3, 7), (1, 5), (2, 3), (3, 1)):
+        hp.tune_set(strategy, 256, 2, grid)
+        for rep in range(2):
+            _compare(hp.run(dev, 1500), want, f"shared chunks n={n} off={offset} s={strategy} g={grid} rep={rep}")
+    hp.tune_set(0, 0, 0, 0)
+
+
 def test_repeat_is_stable(hp):
     """Repeated runs on reused buffers give identical results (the
     workspace carries nothing over)."""
