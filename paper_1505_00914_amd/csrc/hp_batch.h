@@ -10,7 +10,7 @@
 #include <vector>
 
 #include "hp_host.h"
-#include "hp_kernels.h"
+#include "hp_args.h"
 
 namespace hp {
 

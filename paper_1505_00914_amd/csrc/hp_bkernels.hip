@@ -3,6 +3,7 @@
 // Every cloud of a batch is described by one BCloud in device memory; work
 // lists map each workgroup (or lane) to a (cloud, local index) pair, so one
 // launch per step covers all clouds of the batch.
+#include "hp_args.h"
 #include "hp_host.h"
 #include "hp_output.h"
 #include "hp_reduce.h"

@@ -8,7 +8,7 @@
 #include <hip/hip_ext.h>
 
 #include "hp_host.h"
-#include "hp_kernels.h"
+#include "hp_args.h"
 #include "hp_output.h"
 #include "hp_reduce.h"
 
