@@ -66,8 +66,7 @@ struct HullArgs {
   int32_t hull_cap;
   int32_t *info;
   int32_t *ctl;             // control words (single level-2 node: test arrivals)
-  // chain written by the root compaction (two-level tree, small p)
-  int32_t chain_fused;
+  // chain written by the level-2 test (and the totals, unless slab_off is set)
   const int2 *Lm;
   int32_t p;
   const int32_t *slab_k, *slab_s;

@@ -472,91 +472,6 @@ __device__ __forceinline__ void load_children(const HullArgs &H, HullShared &S, 
   }
 }
 
-// The whole chain, written by the single root-compaction workgroup (used
-// when the slab count is small enough): slab offsets by a scan of the slab
-// counts (kept in LDS), then one wave per slab writes its valid columns at
-// its offset (Lemma 1 order).  Also writes k, s and the range status.
-
-__device__ void root_chain(const HullArgs &H, HullShared &S) {
-  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-  const int nslab = H.tree.size[1];
-  int *off = reinterpret_cast<int *>(&S.stage[0][0]);
-  if (tid < 3) S.sum[tid] = 0;
-  if (tid == 0) S.carry = 0;
-  __syncthreads();
-  int ss = 0, err = 0;
-  for (int i = tid; i < H.n_wg_err; i += kHullBlock) err |= H.wg_err[i];
-  for (int base = 0; base < nslab; base += kHullBlock) {
-    const int i = base + tid;
-    const int kk = i < nslab ? H.slab_k[i] : 0;
-    ss += i < nslab ? H.slab_s[i] : 0;
-    int incl = kk;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-      const int o = __shfl_up(incl, d, kWave);
-      if (lane >= d) incl += o;
-    }
-    if (lane == kWave - 1) S.wsum[wave] = incl;
-    __syncthreads();
-    int before = S.carry, all = 0;
-    for (int w = 0; w < kWaves; ++w) {
-      if (w < wave) before += S.wsum[w];
-      all += S.wsum[w];
-    }
-    if (i < nslab) off[i] = before + incl - kk;
-    __syncthreads();
-    if (tid == 0) S.carry += all;
-    __syncthreads();
-  }
-#pragma unroll
-  for (int d = kWave / 2; d > 0; d >>= 1) {
-    ss += __shfl_xor(ss, d, kWave);
-    err |= __shfl_xor(err, d, kWave);
-  }
-  if (lane == 0) {
-    atomicAdd(&S.sum[0], ss);
-    if (err) atomicOr(&S.sum[1], err);
-  }
-  __syncthreads();
-  const int ktot = S.carry;
-  // one wave per slab; each wave loads kRootSlabs slabs before writing any,
-  // so a pass costs one memory latency
-  constexpr int kRootSlabs = 4;
-  for (int sl0 = 0; sl0 < nslab; sl0 += kWaves * kRootSlabs) {
-    int2 L[kRootSlabs];
-#pragma unroll
-    for (int u = 0; u < kRootSlabs; ++u) {
-      const int sl = sl0 + u * kWaves + wave;
-      const int64_t pos = (int64_t)sl * kSlab + lane;
-      L[u] = (sl < nslab && pos < H.p) ? H.Lm[pos] : make_int2(1, 0);
-    }
-#pragma unroll
-    for (int u = 0; u < kRootSlabs; ++u) {
-      const int sl = sl0 + u * kWaves + wave;
-      const int64_t pos = (int64_t)sl * kSlab + lane;
-      const bool valid = L[u].x <= L[u].y;
-      int tot;
-      const int r = wave_rank(valid, &tot);
-      if (valid) {
-        const int o = off[sl] + r;
-        if (o < H.chain_cap) {
-          H.cx[o] = (int)pos + 1;
-          H.clo[o] = L[u].x;
-          H.chi[o] = L[u].y;
-        } else {
-          atomicMin(&H.info[HP_INFO_STATUS], HP_ECAPACITY);
-        }
-      }
-    }
-  }
-  if (tid == 0) {
-    H.info[HP_INFO_K] = ktot;
-    H.info[HP_INFO_S] = S.sum[0];
-    if (S.sum[1] & kErrRange) atomicMin(&H.info[HP_INFO_STATUS], HP_ERANGE);
-  }
-  __syncthreads();
-}
-
 // Copy the nsib child slots (span positions each, both sides) into LDS as
 // they lie in device memory: all loads first, then the stores.
 __device__ __forceinline__ void stage_whole(HullShared &S, const int2 *in, int64_t P, int sib0,
@@ -672,8 +587,6 @@ __device__ __forceinline__ void hull_compact_body(const HullArgs &H, HullShared 
   const int2 *in = H.buf[(lev - 2) & 1];
   int2 *out = H.buf[(lev - 1) & 1];
   const bool root = lev == T.nlev;
-
-  if (H.chain_fused && root) root_chain(H, S);
 
   const bool whole = (size_t)nsib * span_c <= (size_t)kStage && span_c <= 64;
   if (whole) {
@@ -1336,8 +1249,6 @@ static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 constexpr int kMaxGrid = 4096;
 // Largest p whose chain the scan root writes itself (no k_chain launch).
 constexpr int32_t kChainInline = 32768;
-// Single cloud: largest slab count whose chain the root compaction writes.
-constexpr int32_t kSingleRootChainSlabs = 256;
 
 // Survival bytes per side: positions rounded up to whole level-2 nodes, so
 // the level-2 test's flags (node * 4096 + vertex) stay in range and aligned.
@@ -1680,8 +1591,7 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
   // slab's scan.  Without the hull the last slab scans and writes the chain.
   const bool l2path = do_hull && T.nlev >= 2;
   const bool l2scan = l2path && T.size[1] > kL2MaxSlabs;
-  const bool fused = !l2path && do_hull && T.nlev == 2 && T.size[1] <= kSingleRootChainSlabs;
-  A.scan_root = (fused || (l2path && !l2scan)) ? 0 : 1;
+  A.scan_root = (l2path && !l2scan) ? 0 : 1;
   A.chain_inline = (!l2path && p <= kChainInline) ? 1 : 0;
   A.cx_out = cx;
   A.clo_out = clo;
@@ -1695,7 +1605,6 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
   H.hy = hy;
   H.hull_cap = hull_cap;
   H.info = info;
-  H.chain_fused = fused ? 1 : 0;
   H.split = kSplit;
   H.slab_off = l2scan ? A.slab_off : nullptr;
   H.Lm = Lm;
@@ -1714,7 +1623,7 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
     hipLaunchKernelGGL((k_finish<0, false>), dim3(T.size[1]), dim3(kFinBlock), 0, s, A);
   e = hipGetLastError();
   if (e != hipSuccess) return set_error(HP_EDEVICE, "k_finish launch: %s", hipGetErrorString(e));
-  if (!fused && !l2path && !A.chain_inline) {
+  if (!l2path && !A.chain_inline) {
     const int nslab = T.size[1];
     hipLaunchKernelGGL(k_chain, dim3((nslab + 3) / 4), dim3(256), 0, s, Lm, p, A.slab_off, nslab, cx,
                        clo, chi, chain_cap, info);
