@@ -232,10 +232,13 @@ __device__ __forceinline__ void finish_body(const FinishArgs &A, FinishShared &S
       const int2 v = S.pt[side][i];
       int2 uL = v, wR = v;
       bool hasL = false, hasR = false;
+      int2 pk[kSlab / kG];
+#pragma unroll
+      for (int k = 0; k < kSlab / kG; ++k) pk[k] = S.pt[side][g + k * kG];
 #pragma unroll
       for (int k = 0; k < kSlab / kG; ++k) {
         const int jj = g + k * kG;
-        const int2 u = S.pt[side][jj];
+        const int2 u = pk[k];
         const bool ok = ((vm >> jj) & 1ull) != 0;
         const bool isL = ok & (jj < i), isR = ok & (jj > i);
         const bool tL = isL & (!hasL | steeper_left<SMALL>(u, uL, v));
@@ -797,12 +800,24 @@ __device__ __forceinline__ void l2_stage(const HullArgs &H, L2Shared &S, int nod
     }
   }
   __syncthreads();
+  // every slot's destination first, then the stores.  Slot u of this thread
+  // is position lane of slab wave + 16 (u % 4) on side u / 4: the slab is
+  // uniform over the wave, so each lane reads slab `lane`'s count and offset
+  // once and the wave picks its four with readlane
+  static_assert(kHullBlock == 16 * kWave && kPer == 8, "stage layout");
+  const int cl[2] = {S.cnt[0][lane], S.cnt[1][lane]};   // written for all 64 slabs
+  const int ol[2] = {S.off[0][lane], S.off[1][lane]};
+  int dst[kPer];
 #pragma unroll
   for (int u = 0; u < kPer; ++u) {
-    const int idx = tid + u * kHullBlock;
-    const int side = idx / kNodeVerts, pos = idx % kNodeVerts;
-    const int t = pos / kSlab, r = pos % kSlab;
-    if (t < nsib && r < S.cnt[side][t]) S.P[side][S.off[side][t] + r] = v[u];
+    const int side = u / 4, t = wave + 16 * (u % 4);
+    const int c = __builtin_amdgcn_readlane(cl[side], t), o = __builtin_amdgcn_readlane(ol[side], t);
+    dst[u] = (t < nsib && lane < c) ? o + lane : -1;
+  }
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int side = (tid + u * kHullBlock) / kNodeVerts;
+    if (dst[u] >= 0) S.P[side][dst[u]] = v[u];
   }
   __syncthreads();
 }
@@ -905,14 +920,31 @@ __device__ __forceinline__ void l2_test_share(const L2Shared &S, int q0, int q1,
     const int2 *Pp = S.P[side];
     const int2 v = Pp[i];
     int2 uL = v, wR = v;
-    for (int k = lane; k < i; k += kWave) {
-      const int2 u = Pp[k];
+    auto left = [&](int2 u) {
       if (uL.x == v.x || steeper_left<SMALL>(u, uL, v)) uL = u;
-    }
-    for (int k = i + 1 + lane; k < cs; k += kWave) {
-      const int2 w = Pp[k];
+    };
+    auto right = [&](int2 w) {
       if (wR.x == v.x || flatter_right<SMALL>(w, wR, v)) wR = w;
+    };
+    // four reads in flight per lane before their comparisons
+    int k = lane;
+    for (; k + 3 * kWave < i; k += 4 * kWave) {
+      const int2 u0 = Pp[k], u1 = Pp[k + kWave], u2 = Pp[k + 2 * kWave], u3 = Pp[k + 3 * kWave];
+      left(u0);
+      left(u1);
+      left(u2);
+      left(u3);
     }
+    for (; k < i; k += kWave) left(Pp[k]);
+    k = i + 1 + lane;
+    for (; k + 3 * kWave < cs; k += 4 * kWave) {
+      const int2 w0 = Pp[k], w1 = Pp[k + kWave], w2 = Pp[k + 2 * kWave], w3 = Pp[k + 3 * kWave];
+      right(w0);
+      right(w1);
+      right(w2);
+      right(w3);
+    }
+    for (; k < cs; k += kWave) right(Pp[k]);
     uL = wave_pick(uL, [&](int2 a, int2 b) {
       return b.x != v.x && (a.x == v.x || steeper_left<SMALL>(b, a, v)) ? b : a;
     });
@@ -1135,20 +1167,27 @@ __global__ __launch_bounds__(kHullBlock) void k_l2_root(HullArgs H) {
   __syncthreads();
   // survivors of each side in x order: slot idx = side * 4096 + i, eight
   // per thread; a wave's 64 lanes cover one run of 64 slots (chunk)
+  // (slot u of this thread is vertex i = tid + 1024 (u % 4) of side u / 4,
+  // in chunk wave + 16 (u % 4); every read below is unconditional and in
+  // range: i < 4096 and C0 + i < 8192)
   constexpr int kPer = 2 * kNodeVerts / kHullBlock;
   int2 v[kPer];
+  uint8_t fb[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int side = u / 4, i = tid + kHullBlock * (u % 4);
+    fb[u] = flag[side ? C0 + i : i];
+    v[u] = S.P[side][i];
+  }
   bool keep[kPer];
   int rank[kPer];
 #pragma unroll
   for (int u = 0; u < kPer; ++u) {
-    const int idx = tid + u * kHullBlock;
-    const int side = idx / kNodeVerts, i = idx % kNodeVerts;
-    const int C = side ? C1 : C0;
-    keep[u] = i < C && flag[side ? C0 + i : i] != 0;
-    v[u] = keep[u] ? S.P[side][i] : make_int2(0, 0);
+    const int side = u / 4, i = tid + kHullBlock * (u % 4);
+    keep[u] = i < (side ? C1 : C0) && fb[u] != 0;
     int tot;
     rank[u] = wave_rank(keep[u], &tot);
-    if (lane == 0) S.soff[side][(idx % kNodeVerts) / kWave] = tot;
+    if (lane == 0) S.soff[side][wave + 16 * (u % 4)] = tot;
   }
   __syncthreads();
   if (wave < 2) {
@@ -1164,11 +1203,12 @@ __global__ __launch_bounds__(kHullBlock) void k_l2_root(HullArgs H) {
     if (lane == kWave - 1) S.sum[wave] = incl;
   }
   __syncthreads();
+  const int sl[2] = {S.soff[0][lane], S.soff[1][lane]};
 #pragma unroll
   for (int u = 0; u < kPer; ++u) {
-    const int idx = tid + u * kHullBlock;
-    const int side = idx / kNodeVerts, i = idx % kNodeVerts;
-    if (keep[u]) S.P[side][S.soff[side][i / kWave] + rank[u]] = v[u];
+    const int side = u / 4;
+    const int base = __builtin_amdgcn_readlane(sl[side], wave + 16 * (u % 4));
+    if (keep[u]) S.P[side][base + rank[u]] = v[u];
   }
   __syncthreads();
   bool overflow = false;
