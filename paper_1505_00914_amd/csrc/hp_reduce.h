@@ -13,6 +13,16 @@ namespace hp {
 // load, VPT loads in flight per lane; consecutive lanes read consecutive
 // vectors and consecutive workgroups consecutive chunks.
 // ---------------------------------------------------------------------------
+
+// A 16-byte load of the point stream, marked non-temporal: every point is
+// read exactly once, so the caches are better left to L and the partials
+// (measured: 4 % faster on 80 MB, 8 % on 2 GiB).  The column-window reduce
+// keeps plain loads: its W reads of one chunk group are meant to hit L2.
+typedef int hp_v4i __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ int4 load_stream(const int4 *a) {
+  const hp_v4i t = __builtin_nontemporal_load(reinterpret_cast<const hp_v4i *>(a));
+  return make_int4(t.x, t.y, t.z, t.w);
+}
 template <int BLOCK, int VPT, bool LDS, bool WIN = false>
 __device__ __forceinline__ void stream_points(const int32_t *__restrict__ pts, int64_t n, int p,
                                               int2 *L, int64_t wg, int64_t nwg, bool &bad,
@@ -43,7 +53,7 @@ __device__ __forceinline__ void stream_points(const int32_t *__restrict__ pts, i
   bool have = t0 + chunk <= nv;
   if (have) {
 #pragma unroll
-    for (int u = 0; u < VPT; ++u) q[u] = v[t0 + u * BLOCK + threadIdx.x];
+    for (int u = 0; u < VPT; ++u) q[u] = WIN ? v[t0 + u * BLOCK + threadIdx.x] : load_stream(&v[t0 + u * BLOCK + threadIdx.x]);
   }
   while (have) {
     const int64_t t1 = t0 + step;
@@ -53,7 +63,7 @@ __device__ __forceinline__ void stream_points(const int32_t *__restrict__ pts, i
     gather<VPT, LDS, WIN>(L, p, q, b, bad, c0, wc);
     int4 qn[VPT];
 #pragma unroll
-    for (int u = 0; u < VPT; ++u) qn[u] = v[tl + u * BLOCK + threadIdx.x];
+    for (int u = 0; u < VPT; ++u) qn[u] = WIN ? v[tl + u * BLOCK + threadIdx.x] : load_stream(&v[tl + u * BLOCK + threadIdx.x]);
     apply<VPT, LDS>(L, b);
 #pragma unroll
     for (int u = 0; u < VPT; ++u) q[u] = qn[u];
@@ -184,7 +194,7 @@ __device__ __forceinline__ void stream_points_dyn(const int32_t *__restrict__ pt
   int4 q[VPT];
   if (cur >= 0) {
 #pragma unroll
-    for (int u = 0; u < VPT; ++u) q[u] = v[cur * chunk + u * BLOCK + threadIdx.x];
+    for (int u = 0; u < VPT; ++u) q[u] = load_stream(&v[cur * chunk + u * BLOCK + threadIdx.x]);
   }
   while (cur >= 0) {
     const int64_t tl = nx >= 0 ? nx : cur;
@@ -192,7 +202,7 @@ __device__ __forceinline__ void stream_points_dyn(const int32_t *__restrict__ pt
     gather<VPT, LDS>(L, p, q, b, bad);
     int4 qn[VPT];
 #pragma unroll
-    for (int u = 0; u < VPT; ++u) qn[u] = v[tl * chunk + u * BLOCK + threadIdx.x];
+    for (int u = 0; u < VPT; ++u) qn[u] = load_stream(&v[tl * chunk + u * BLOCK + threadIdx.x]);
     apply<VPT, LDS>(L, b);
     ++folded;
     const int64_t nn = nx >= 0 ? take(next()) : -1;
