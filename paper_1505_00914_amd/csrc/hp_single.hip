@@ -261,7 +261,7 @@ __device__ __forceinline__ void finish_body(const FinishArgs &A, FinishShared &S
         wR = tR ? ow : wR;
         hasR |= tR;
       }
-      const bool keep = ((vm >> i) & 1ull) && (!hasL | !hasR | cross_pos<SMALL>(uL, v, wR));
+      const bool keep = (((vm >> i) & 1ull) != 0) & (!hasL | !hasR | cross_pos<SMALL>(uL, v, wR));
       // ballot over the wave: its 8 candidates' keep bits at lanes 0, 8, ...
       const unsigned long long kb = __ballot(keep && g == 0);
       if (lane == 0) {
@@ -449,10 +449,15 @@ __device__ __forceinline__ bool wave_extremes_keep(int2 v, int2 uL, bool hasL, i
     const int2 ow = make_int2(__shfl_xor(wR.x, d, kWave), __shfl_xor(wR.y, d, kWave));
     const bool ohL = __shfl_xor((int)hasL, d, kWave) != 0;
     const bool ohR = __shfl_xor((int)hasR, d, kWave) != 0;
-    if (ohL && (!hasL || steeper_left<SMALL>(ou, uL, v))) { uL = ou; hasL = true; }
-    if (ohR && (!hasR || flatter_right<SMALL>(ow, wR, v))) { wR = ow; hasR = true; }
+    // branch-free: both tests are plain integer arithmetic
+    const bool tL = ohL & (!hasL | steeper_left<SMALL>(ou, uL, v));
+    const bool tR = ohR & (!hasR | flatter_right<SMALL>(ow, wR, v));
+    uL = make_int2(tL ? ou.x : uL.x, tL ? ou.y : uL.y);
+    wR = make_int2(tR ? ow.x : wR.x, tR ? ow.y : wR.y);
+    hasL |= tL;
+    hasR |= tR;
   }
-  return !hasL || !hasR || cross_pos<SMALL>(uL, v, wR);
+  return !hasL | !hasR | cross_pos<SMALL>(uL, v, wR);
 }
 
 // Sizes and prefixes of the children of `parent` at level lev-1, both sides
@@ -920,11 +925,17 @@ __device__ __forceinline__ void l2_test_share(const L2Shared &S, int q0, int q1,
     const int2 *Pp = S.P[side];
     const int2 v = Pp[i];
     int2 uL = v, wR = v;
+    // branch-free updates: both tests are plain integer arithmetic, so
+    // they are evaluated and combined without short-circuit branches
     auto left = [&](int2 u) {
-      if (uL.x == v.x || steeper_left<SMALL>(u, uL, v)) uL = u;
+      const bool t = (uL.x == v.x) | steeper_left<SMALL>(u, uL, v);
+      uL.x = t ? u.x : uL.x;
+      uL.y = t ? u.y : uL.y;
     };
     auto right = [&](int2 w) {
-      if (wR.x == v.x || flatter_right<SMALL>(w, wR, v)) wR = w;
+      const bool t = (wR.x == v.x) | flatter_right<SMALL>(w, wR, v);
+      wR.x = t ? w.x : wR.x;
+      wR.y = t ? w.y : wR.y;
     };
     // four reads in flight per lane before their comparisons
     int k = lane;
@@ -946,12 +957,15 @@ __device__ __forceinline__ void l2_test_share(const L2Shared &S, int q0, int q1,
     }
     for (; k < cs; k += kWave) right(Pp[k]);
     uL = wave_pick(uL, [&](int2 a, int2 b) {
-      return b.x != v.x && (a.x == v.x || steeper_left<SMALL>(b, a, v)) ? b : a;
+      const bool t = (b.x != v.x) & ((a.x == v.x) | steeper_left<SMALL>(b, a, v));
+      return make_int2(t ? b.x : a.x, t ? b.y : a.y);
     });
     wR = wave_pick(wR, [&](int2 a, int2 b) {
-      return b.x != v.x && (a.x == v.x || flatter_right<SMALL>(b, a, v)) ? b : a;
+      const bool t = (b.x != v.x) & ((a.x == v.x) | flatter_right<SMALL>(b, a, v));
+      return make_int2(t ? b.x : a.x, t ? b.y : a.y);
     });
-    if (lane == 0) flag[q - q0] = (uL.x == v.x || wR.x == v.x || cross_pos<SMALL>(uL, v, wR)) ? 1 : 0;
+    const bool keep = (uL.x == v.x) | (wR.x == v.x) | cross_pos<SMALL>(uL, v, wR);
+    if (lane == 0) flag[q - q0] = keep ? 1 : 0;
   }
 }
 
