@@ -90,6 +90,13 @@ extern "C" {
                                        per window, each fold the points of their
                                        window and write a partial array (for p
                                        above the LDS limit, up to 8 windows)     */
+#define HP_STRATEGY_SAMPLED      5  /* one L in device memory: a sample of the
+                                       points (a prefix, 1/8 of them) is folded
+                                       first; per group of columns the sampled
+                                       (max lo, min hi) then lets the passes over
+                                       the rest skip every point that cannot
+                                       change L, the filter being rebuilt once
+                                       half-way (for large p, n >= 16 p)         */
 
 /* Human-readable name of a status code (static string). */
 const char *hp_status_string(int code);
@@ -105,7 +112,7 @@ int32_t hp_lds_max_p(void);
 
 /* Force a strategy for later calls on this process (HP_STRATEGY_*), e.g. for
  * tests; HP_STRATEGY_AUTO restores the tuned choice.  Also settable with the
- * environment variable HP_FORCE_STRATEGY=lds|global|lds_partial. */
+ * environment variable HP_FORCE_STRATEGY=lds|global|lds_partial|window|sampled. */
 int hp_set_strategy(int strategy);
 
 /* Launch-shape override for later calls in this process (used by the tuner):

@@ -43,6 +43,7 @@ struct FinishArgs {
   int32_t n_wg_err;
   unsigned long long *dyn_ctr;  // the reduce's grab counter (cleared here), or null
   const int32_t *wg_cnt;        // per-workgroup chunks folded by the reduce
+  int32_t n_wg_cnt;             // workgroups of the pass that shared chunks
   int64_t dyn_expect;           // chunks of the run
   // chain: scanned by the last slab (scan_root), then written by it
   // (chain_inline) or by k_chain; otherwise written by the first hull level

@@ -58,6 +58,7 @@ int forced_strategy() {
       else if (!strcmp(e, "global")) g_forced = HP_STRATEGY_GLOBAL;
       else if (!strcmp(e, "lds_partial")) g_forced = HP_STRATEGY_LDS_PARTIAL;
       else if (!strcmp(e, "window")) g_forced = HP_STRATEGY_WINDOW;
+      else if (!strcmp(e, "sampled")) g_forced = HP_STRATEGY_SAMPLED;
     }
   }
   return g_forced;
@@ -250,7 +251,7 @@ extern "C" int hp_abi_version(void) { return HP_ABI_VERSION; }
 extern "C" int32_t hp_lds_max_p(void) { return (int32_t)device_info().lds_max_p; }
 
 extern "C" int hp_set_strategy(int strategy) {
-  if (strategy < HP_STRATEGY_AUTO || strategy > HP_STRATEGY_WINDOW)
+  if (strategy < HP_STRATEGY_AUTO || strategy > HP_STRATEGY_SAMPLED)
     return set_error(HP_EINVAL, "unknown strategy %d", strategy);
   forced_strategy();
   std::lock_guard<std::mutex> lk(g_mu);
@@ -259,7 +260,7 @@ extern "C" int hp_set_strategy(int strategy) {
 }
 
 extern "C" int hp_tune_set(int32_t strategy, int32_t block, int32_t vpt, int32_t grid) {
-  if (strategy < 0 || strategy > HP_STRATEGY_WINDOW)
+  if (strategy < 0 || strategy > HP_STRATEGY_SAMPLED)
     return set_error(HP_EINVAL, "unknown strategy %d", strategy);
   const bool ok_shape = (block == 0 && vpt == 0) ||
                         ((block == 256 || block == 512 || block == 1024) && (vpt == 2 || vpt == 4 || vpt == 8));

@@ -71,9 +71,14 @@ struct Batch {
   int2 cur[2 * VPT];
 };
 
-template <int VPT, bool LDS, bool WIN = false>
+// FILT (device L only): a point goes on to the read of its column only when
+// its y lies outside the range filt[column >> fshift]; inside it, y can
+// improve neither extreme (the range is bounded by a lower L, see
+// k_reduce_filtered).
+template <int VPT, bool LDS, bool WIN = false, bool FILT = false>
 __device__ __forceinline__ void gather(const int2 *L, int p, const int4 (&q)[VPT], Batch<VPT> &b,
-                                       bool &bad, unsigned c0 = 0, unsigned wc = 0) {
+                                       bool &bad, unsigned c0 = 0, unsigned wc = 0,
+                                       const int2 *filt = nullptr, int fshift = 0) {
 #pragma unroll
   for (int u = 0; u < VPT; ++u) {
     const int xs[2] = {q[u].x, q[u].z};
@@ -93,6 +98,16 @@ __device__ __forceinline__ void gather(const int2 *L, int p, const int4 (&q)[VPT
       }
       b.y[j] = ys[h];
     }
+  }
+  if (FILT) {
+#pragma unroll
+    for (int j = 0; j < 2 * VPT; ++j) {
+      const int2 f = filt[b.c[j] >> fshift];
+      b.ok[j] = b.ok[j] & ((b.y[j] < f.x) | (b.y[j] > f.y));
+    }
+#pragma unroll
+    for (int j = 0; j < 2 * VPT; ++j) b.cur[j] = b.ok[j] ? load_coherent(&L[b.c[j]]) : make_int2(0, 0);
+    return;
   }
 #pragma unroll
   for (int j = 0; j < 2 * VPT; ++j) b.cur[j] = LDS ? L[b.c[j]] : load_coherent(&L[b.c[j]]);

@@ -4,6 +4,8 @@
 // reduce streams its work items with the same stream_points.
 #pragma once
 
+#include <climits>
+
 #include "hp_kernels.h"
 
 namespace hp {
@@ -23,10 +25,11 @@ __device__ __forceinline__ int4 load_stream(const int4 *a) {
   const hp_v4i t = __builtin_nontemporal_load(reinterpret_cast<const hp_v4i *>(a));
   return make_int4(t.x, t.y, t.z, t.w);
 }
-template <int BLOCK, int VPT, bool LDS, bool WIN = false>
+template <int BLOCK, int VPT, bool LDS, bool WIN = false, bool FILT = false>
 __device__ __forceinline__ void stream_points(const int32_t *__restrict__ pts, int64_t n, int p,
                                               int2 *L, int64_t wg, int64_t nwg, bool &bad,
-                                              unsigned c0 = 0, unsigned wc = 0) {
+                                              unsigned c0 = 0, unsigned wc = 0,
+                                              const int2 *filt = nullptr, int fshift = 0) {
   // pts is 8-byte aligned (checked on the host); peel one point if the
   // vector body would otherwise start on an 8-byte boundary.
   const int64_t head = (n > 0 && ((uintptr_t)pts & 15) != 0) ? 1 : 0;
@@ -60,7 +63,7 @@ __device__ __forceinline__ void stream_points(const int32_t *__restrict__ pts, i
     const bool have_next = t1 + chunk <= nv;
     const int64_t tl = have_next ? t1 : t0;
     Batch<VPT> b;
-    gather<VPT, LDS, WIN>(L, p, q, b, bad, c0, wc);
+    gather<VPT, LDS, WIN, FILT>(L, p, q, b, bad, c0, wc, filt, fshift);
     int4 qn[VPT];
 #pragma unroll
     for (int u = 0; u < VPT; ++u) qn[u] = WIN ? v[tl + u * BLOCK + threadIdx.x] : load_stream(&v[tl + u * BLOCK + threadIdx.x]);
@@ -114,10 +117,10 @@ __host__ __device__ __forceinline__ int64_t dyn_chunks(int64_t n, uintptr_t pts,
   return (nv + chunk - 1) / chunk;
 }
 
-template <int BLOCK, int VPT, bool LDS>
+template <int BLOCK, int VPT, bool LDS, bool FILT = false>
 __device__ __forceinline__ void stream_points_dyn(const int32_t *__restrict__ pts, int64_t n, int p, int2 *L,
                                                   int64_t wg, int64_t nwg, bool &bad, const DynArgs &D,
-                                                  int *s_slot) {
+                                                  int *s_slot, const int2 *filt = nullptr, int fshift = 0) {
   const int64_t head = (n > 0 && ((uintptr_t)pts & 15) != 0) ? 1 : 0;
   const int64_t nv = (n - head) >> 1;
   const int64_t tail = head + 2 * nv;
@@ -199,7 +202,7 @@ __device__ __forceinline__ void stream_points_dyn(const int32_t *__restrict__ pt
   while (cur >= 0) {
     const int64_t tl = nx >= 0 ? nx : cur;
     Batch<VPT> b;
-    gather<VPT, LDS>(L, p, q, b, bad);
+    gather<VPT, LDS, false, FILT>(L, p, q, b, bad, 0, 0, filt, fshift);
     int4 qn[VPT];
 #pragma unroll
     for (int u = 0; u < VPT; ++u) qn[u] = load_stream(&v[tl * chunk + u * BLOCK + threadIdx.x]);
@@ -338,6 +341,38 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_global(const int32_t *__restri
   bool bad = false;
   if (D.ctr) stream_points_dyn<BLOCK, VPT, false>(pts, n, p, L, blockIdx.x, gridDim.x, bad, D, s_slot);
   else stream_points<BLOCK, VPT, false>(pts, n, p, L, blockIdx.x, gridDim.x, bad);
+  if (bad) s_bad = 1;
+  __syncthreads();
+  if (threadIdx.x == 0) wg_err[blockIdx.x] = s_bad ? kErrRange : 0;
+}
+
+// ---------------------------------------------------------------------------
+// Sampled filter for a device L (p above what LDS windows cover).  A first
+// pass folds a sample of the points into L exactly (k_reduce_global over a
+// prefix of the points).  k_filter_build then bounds, per group of 2^fshift
+// columns, the largest sampled lo and the smallest sampled hi: F[g] =
+// (max lo, min hi), or (p + 1, -1) -- filter nothing -- when a column of the
+// group has no sampled point.  The main pass (k_reduce_filtered) keeps F in
+// LDS and sends a point on to the read of its column in L only when y < F.x
+// or y > F.y.  A point it skips has lo_final <= lo_sample <= F.x <= y and,
+// likewise, y <= hi_final, so it cannot change L.  With k sampled points
+// per column about 1 / (k + 1) of the remaining points still read L.
+// (k_filter_build is in hp_single.hip.)
+// ---------------------------------------------------------------------------
+template <int BLOCK, int VPT>
+__global__ __launch_bounds__(BLOCK) void k_reduce_filtered(const int32_t *__restrict__ pts, int64_t n,
+                                                           int32_t p, int2 *L, const int2 *__restrict__ F,
+                                                           int32_t fshift, int32_t ngroups,
+                                                           int32_t *__restrict__ wg_err, DynArgs D) {
+  extern __shared__ int2 sF[];           // ngroups filter pairs, then the flag word and two grab slots
+  int &s_bad = sF[ngroups].x;
+  int *s_slot = &sF[ngroups].y;          // sF[ngroups].y and sF[ngroups + 1].x
+  for (int g = threadIdx.x; g < ngroups; g += BLOCK) sF[g] = F[g];
+  if (threadIdx.x == 0) s_bad = 0;
+  __syncthreads();
+  bool bad = false;
+  if (D.ctr) stream_points_dyn<BLOCK, VPT, false, true>(pts, n, p, L, blockIdx.x, gridDim.x, bad, D, s_slot, sF, fshift);
+  else stream_points<BLOCK, VPT, false, false, true>(pts, n, p, L, blockIdx.x, gridDim.x, bad, 0, 0, sF, fshift);
   if (bad) s_bad = 1;
   __syncthreads();
   if (threadIdx.x == 0) wg_err[blockIdx.x] = s_bad ? kErrRange : 0;

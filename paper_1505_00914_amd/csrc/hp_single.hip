@@ -37,6 +37,34 @@ __global__ void k_init(int32_t *ctl, int32_t *tree_ctr, int32_t nodes, int32_t *
     for (int64_t c = i; c < p; c += stride) L[c] = make_int2(p + 1, -1);
 }
 
+// The sampled filter of the device-L reduce: per group of 2^fshift columns,
+// (largest sampled lo, smallest sampled hi), or (p + 1, -1) when a column of
+// the group has no sampled point (see k_reduce_filtered).
+__global__ __launch_bounds__(256) void k_filter_build(const int2 *__restrict__ L, int32_t p, int32_t fshift,
+                                                      int32_t ngroups, int2 *__restrict__ F) {
+  // a wave per group (up to 64 columns a pass)
+  const int lane = threadIdx.x & (kWave - 1);
+  const int g = blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
+  if (g >= ngroups) return;
+  const int64_t first = (int64_t)g << fshift;
+  const int64_t last = min<int64_t>((int64_t)p, first + ((int64_t)1 << fshift));
+  int mlo = INT_MIN, mhi = INT_MAX;
+  bool empty = false;
+  for (int64_t c = first + lane; c < last; c += kWave) {
+    const int2 e = L[c];
+    empty |= e.x > e.y;
+    mlo = max(mlo, e.x);
+    mhi = min(mhi, e.y);
+  }
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    mlo = max(mlo, __shfl_xor(mlo, d, kWave));
+    mhi = min(mhi, __shfl_xor(mhi, d, kWave));
+  }
+  empty = __any(empty);
+  if (lane == 0) F[g] = empty ? make_int2(p + 1, -1) : make_int2(mlo, mhi);
+}
+
 // ---------------------------------------------------------------------------
 // Finish: one workgroup of 1024 threads per slab of 64 positions.
 // ---------------------------------------------------------------------------
@@ -124,7 +152,7 @@ __device__ __forceinline__ void finish_body(const FinishArgs &A, FinishShared &S
   int folded = 0;
   if (check) {
     if (tid == 0) S.folded = 0;
-    for (int j = tid; j < A.n_wg_err; j += kFinBlock) folded += A.wg_cnt[j];
+    for (int j = tid; j < A.n_wg_cnt; j += kFinBlock) folded += A.wg_cnt[j];
   }
 
   // ---- the slab's points --------------------------------------------------
@@ -1294,7 +1322,7 @@ static int dyn_static8() {
 }
 
 struct Layout {
-  size_t ctl, tree, wg_err, wg_cnt, slab_k, slab_s, slab_off, Lm, part, cand, keep, l2cnt, ccount, total;
+  size_t ctl, tree, wg_err, wg_cnt, filt, slab_k, slab_s, slab_off, Lm, part, cand, keep, l2cnt, ccount, total;
 };
 
 static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -1318,6 +1346,7 @@ static Layout make_layout(int64_t positions, int32_t p, int64_t part_pairs, cons
   Y.tree = o;     o = align_up(o + sizeof(int32_t) * (size_t)T.nodes);
   Y.wg_err = o;   o = align_up(o + sizeof(int32_t) * (size_t)kMaxGrid);
   Y.wg_cnt = o;   o = align_up(o + sizeof(int32_t) * (size_t)kMaxGrid);
+  Y.filt = o;     o = align_up(o + sizeof(int2) * (size_t)((p > 0 ? (int64_t)p + 63 : 0) / 64));
   Y.slab_k = o;   o = align_up(o + sizeof(int32_t) * (size_t)T.size[1]);
   Y.slab_s = o;   o = align_up(o + sizeof(int32_t) * (size_t)T.size[1]);
   Y.slab_off = o; o = align_up(o + sizeof(int32_t) * (size_t)T.size[1]);
@@ -1338,6 +1367,18 @@ struct Plan1 {
   int block, vpt, G;   // G: workgroups of the reduce
   int W, wc;           // column windows (HP_STRATEGY_WINDOW): count and columns each
 };
+
+// Sampled filter: used by default from this many points per column; the
+// sample is the first 1/sample_div() of the points (HP_SAMPLE_DIV, 2..64).
+constexpr int64_t kSampledMinPerCol = 16;
+static int64_t sample_div() {
+  static int64_t v = 0;
+  if (v == 0) {
+    const char *e = getenv("HP_SAMPLE_DIV");
+    v = e ? std::max<int64_t>(2, std::min<int64_t>(64, atoll(e))) : 8;
+  }
+  return v;
+}
 
 // Column windows: at most kWinMax windows, at most kWinMaxGroups chunk
 // groups (a multiple of 8: one per XCD slot).
@@ -1368,7 +1409,9 @@ static Plan1 choose(int64_t n, int32_t p) {
       P.W = (int)W;
       P.wc = (int)(((int64_t)p + W - 1) / W);
     } else {
-      s = HP_STRATEGY_GLOBAL;
+      // beyond the windows: a device L, with the sampled filter when every
+      // column gets enough points for the sample to bound it
+      s = n >= kSampledMinPerCol * (int64_t)p ? HP_STRATEGY_SAMPLED : HP_STRATEGY_GLOBAL;
     }
   }
   P.strategy = s;
@@ -1500,6 +1543,71 @@ static hipError_t dispatch_reduce(const Plan1 &P, const int32_t *pts, int64_t n,
   return hipErrorInvalidValue;
 }
 
+// The sampled-filter reduce: the sample pass (k_reduce_global over the
+// first ns points, G1 workgroups), the filter, a filtered pass up to point
+// n1, the filter again (from an L that has now seen n1 points, so it is
+// tighter), and the filtered pass over the rest; the filtered passes use
+// P.G workgroups each and only the last one shares chunks.  e0 is recorded
+// at the start of the sample pass and e1 at the end of the last pass.
+template <int BLOCK, int VPT>
+static hipError_t launch_sampled(const Plan1 &P, const int32_t *pts, int64_t n, int32_t p, int2 *Lm,
+                                 int2 *F, int fshift, int ngroups, int64_t ns, int64_t n1, int G1,
+                                 int32_t *wg_err, DynArgs D, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    const hipError_t e = hipFuncSetAttribute((const void *)k_reduce_filtered<BLOCK, VPT>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             device_info().lds_bytes);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  ResetArgs R;
+  memset(&R, 0, sizeof(R));
+  DynArgs D0 = D;
+  D0.ctr = nullptr;
+  if (e0) hipExtLaunchKernelGGL((k_reduce_global<BLOCK, VPT>), dim3(G1), dim3(BLOCK), 0, s, e0, nullptr, 0, pts, ns, p,
+                                Lm, wg_err, R, D0);
+  else hipLaunchKernelGGL((k_reduce_global<BLOCK, VPT>), dim3(G1), dim3(BLOCK), 0, s, pts, ns, p, Lm, wg_err, R, D0);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const size_t lds = sizeof(int2) * ((size_t)ngroups + 2);
+  // first filtered pass: points [ns, n1), static shares
+  hipLaunchKernelGGL(k_filter_build, dim3((ngroups + 3) / 4), dim3(256), 0, s, (const int2 *)Lm, p, fshift,
+                     ngroups, F);
+  hipLaunchKernelGGL((k_reduce_filtered<BLOCK, VPT>), dim3(P.G), dim3(BLOCK), lds, s, pts + 2 * ns, n1 - ns, p, Lm,
+                     (const int2 *)F, fshift, ngroups, wg_err + G1, D0);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // last pass: points [n1, n), with the filter of the first n1 points
+  hipLaunchKernelGGL(k_filter_build, dim3((ngroups + 3) / 4), dim3(256), 0, s, (const int2 *)Lm, p, fshift,
+                     ngroups, F);
+  if (e1) hipExtLaunchKernelGGL((k_reduce_filtered<BLOCK, VPT>), dim3(P.G), dim3(BLOCK), (uint32_t)lds, s, nullptr,
+                                e1, 0, pts + 2 * n1, n - n1, p, Lm, (const int2 *)F, fshift, ngroups,
+                                wg_err + G1 + P.G, D);
+  else hipLaunchKernelGGL((k_reduce_filtered<BLOCK, VPT>), dim3(P.G), dim3(BLOCK), lds, s, pts + 2 * n1, n - n1, p, Lm,
+                          (const int2 *)F, fshift, ngroups, wg_err + G1 + P.G, D);
+  return hipGetLastError();
+}
+
+static hipError_t dispatch_sampled(const Plan1 &P, const int32_t *pts, int64_t n, int32_t p, int2 *Lm, int2 *F,
+                                   int fshift, int ngroups, int64_t ns, int64_t n1, int G1, int32_t *wg_err,
+                                   DynArgs D, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+#define HP_CASE(B, V) \
+  if (P.block == B && P.vpt == V)   \
+    return launch_sampled<B, V>(P, pts, n, p, Lm, F, fshift, ngroups, ns, n1, G1, wg_err, D, s, e0, e1);
+  HP_CASE(1024, 4)
+  HP_CASE(1024, 2)
+  HP_CASE(1024, 8)
+  HP_CASE(512, 2)
+  HP_CASE(512, 4)
+  HP_CASE(512, 8)
+  HP_CASE(256, 2)
+  HP_CASE(256, 4)
+  HP_CASE(256, 8)
+#undef HP_CASE
+  return hipErrorInvalidValue;
+}
+
 // Hull levels 2..nlev: a test launch and a compaction launch per level (the
 // slab level ran in k_finish).  H must have its chain fields filled.
 static void hull_buffers(HullArgs &H, const TreeShape &T, int64_t positions, char *w, const Layout &Y) {
@@ -1602,12 +1710,33 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
   D.ctr = nullptr;
   D.wg_cnt = reinterpret_cast<int32_t *>(w + Y.wg_cnt);
   D.static_frac8 = dyn_static8();
-  const int64_t nchunks = dyn_chunks(n, (uintptr_t)pts, (int64_t)P.block * P.vpt);
+  // the sampled filter: the sample is an even-length prefix (the rest keeps
+  // the alignment of pts); 2^fshift columns per filter group, at least 64,
+  // as few as LDS holds
+  const bool sampled = P.strategy == HP_STRATEGY_SAMPLED;
+  const int64_t ns = sampled ? (n / sample_div()) & ~(int64_t)1 : 0;
+  const int64_t n1 = sampled ? std::min<int64_t>(n, 4 * ns) : 0;   // end of the first filtered pass (even)
+  int fshift = 6, ngroups = 0, G1 = 0;
+  if (sampled) {
+    const int64_t pairs = device_info().lds_bytes / 8 - 2;
+    while ((((int64_t)p + ((int64_t)1 << fshift) - 1) >> fshift) > pairs) ++fshift;
+    ngroups = (int)(((int64_t)p + ((int64_t)1 << fshift) - 1) >> fshift);
+    const int64_t per = (int64_t)P.block * P.vpt;
+    G1 = (int)std::max<int64_t>(1, std::min<int64_t>(P.G, (ns / 2 + per - 1) / per));
+    if (G1 + 2 * P.G > kMaxGrid) return set_error(HP_EINVAL, "reduce grid too large");
+  }
+  // the pass that may share chunks: all points, or the last filtered pass
+  const int32_t *main_pts = pts ? pts + 2 * n1 : pts;
+  const int64_t nchunks = dyn_chunks(n - n1, (uintptr_t)main_pts, (int64_t)P.block * P.vpt);
   if (D.static_frac8 >= 0 && P.strategy != HP_STRATEGY_WINDOW && nchunks >= kDynMinChunks * (int64_t)P.G)
     D.ctr = grab_counter();
   hipEvent_t e0 = nullptr, e1 = nullptr;
   timing_slot(&e0, &e1);
-  e = dispatch_reduce(P, pts, n, p, Lm, part, wg_err, R, D, s, e0, e1);
+  if (sampled)
+    e = dispatch_sampled(P, pts, n, p, Lm, reinterpret_cast<int2 *>(w + Y.filt), fshift, ngroups, ns, n1, G1,
+                         wg_err, D, s, e0, e1);
+  else
+    e = dispatch_reduce(P, pts, n, p, Lm, part, wg_err, R, D, s, e0, e1);
   if (e != hipSuccess) return set_error(HP_EDEVICE, "reduce launch: %s", hipGetErrorString(e));
 
   FinishArgs A;
@@ -1635,9 +1764,10 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
   A.ctl = ctl;
   A.info = info;
   A.wg_err = wg_err;
-  A.n_wg_err = P.G;
+  A.n_wg_err = (sampled ? G1 + P.G : 0) + P.G;
   A.dyn_ctr = D.ctr;
   A.wg_cnt = D.wg_cnt;
+  A.n_wg_cnt = P.G;
   A.dyn_expect = nchunks;
   // With the hull and more than one slab, level 2 is the all-vertex test,
   // which also writes the chain: from offsets it sums itself (up to
@@ -1666,7 +1796,7 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
   H.slab_k = A.slab_k;
   H.slab_s = A.slab_s;
   H.wg_err = wg_err;
-  H.n_wg_err = P.G;
+  H.n_wg_err = (sampled ? G1 + P.G : 0) + P.G;
   H.cx = cx;
   H.clo = clo;
   H.chi = chi;

@@ -41,9 +41,11 @@ def _candidates(n: int, p: int, cus: int, lds_max_p: int):
     if p <= lds_max_p and n >= 2 * p:
         strategies = [hp.HP_STRATEGY_LDS_PARTIAL, hp.HP_STRATEGY_LDS, hp.HP_STRATEGY_GLOBAL]
     elif windows <= 8 and n >= 2 * p:
-        strategies = [hp.HP_STRATEGY_WINDOW, hp.HP_STRATEGY_GLOBAL]
+        strategies = [hp.HP_STRATEGY_WINDOW, hp.HP_STRATEGY_GLOBAL, hp.HP_STRATEGY_SAMPLED]
+    elif n >= 16 * p:
+        strategies = [hp.HP_STRATEGY_SAMPLED, hp.HP_STRATEGY_GLOBAL]
     for s in strategies:
-        if s == hp.HP_STRATEGY_GLOBAL:
+        if s in (hp.HP_STRATEGY_GLOBAL, hp.HP_STRATEGY_SAMPLED):
             grids = sorted({max(1, int(cus * f)) for f in (1, 2, 4, 8)})
         elif s == hp.HP_STRATEGY_WINDOW:
             grids = [g * windows for g in (8, 16, 32, 64)]

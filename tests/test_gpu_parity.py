@@ -49,7 +49,7 @@ def _compare(got, want, label, check_L=True):
     assert np.array_equal(got["hull"], want["hull"]), f"{label}: hull differs"
 
 
-def _run_both(hp, pts_cpu: torch.Tensor, p: int, label: str, strategies=(1, 2, 3, 4), split=True):
+def _run_both(hp, pts_cpu: torch.Tensor, p: int, label: str, strategies=(1, 2, 3, 4, 5), split=True):
     print(f"[case] {label} n={pts_cpu.shape[0]} p={p}", flush=True)
     want = _oracle(pts_cpu.numpy(), p)
     dev = pts_cpu.cuda()
@@ -90,7 +90,7 @@ def test_gap_example(hp):
 ])
 def test_configs(hp, kind, n, p, seed):
     pts = synth.cloud(kind, n, p, seed)
-    strategies = (1, 2, 3, 4) if p <= hp.lds_max_p() else (2, 4)
+    strategies = (1, 2, 3, 4, 5) if p <= hp.lds_max_p() else (2, 4, 5)
     _run_both(hp, pts, p, f"{kind}-{n}-{p}", strategies)
 
 
@@ -120,7 +120,7 @@ def _edge_cases():
 @pytest.mark.parametrize("name", sorted(_edge_cases()))
 def test_edge_cases(hp, name):
     pts, p = _edge_cases()[name]
-    strategies = (1, 2, 3, 4) if p <= hp.lds_max_p() else (2, 4)
+    strategies = (1, 2, 3, 4, 5) if p <= hp.lds_max_p() else (2, 4, 5)
     _run_both(hp, torch.from_numpy(pts), p, name, strategies)
 
 
@@ -131,7 +131,7 @@ def test_unaligned_start(hp):
     want = _oracle(view_cpu.contiguous().numpy(), 777)
     dev = base.cuda()[1:]
     assert dev.data_ptr() % 16 == 8
-    for s in (1, 2, 3, 4):
+    for s in (1, 2, 3, 4, 5):
         hp.set_strategy(s)
         _compare(hp.run(dev, 777), want, f"unaligned/strategy{s}")
     hp.set_strategy(0)
@@ -141,11 +141,41 @@ def test_out_of_range_reports(hp):
     pts = synth.cloud("uniform", 10_000, 100, 12)
     pts[5000] = torch.tensor([101, 3], dtype=torch.int32)
     pts[17] = torch.tensor([4, 0], dtype=torch.int32)
-    for s in (1, 2, 3, 4):
+    for s in (1, 2, 3, 4, 5):
         hp.set_strategy(s)
         got = hp.run(pts.cuda(), 100)
         assert got["status"] == HP_ERANGE
     hp.set_strategy(0)
+
+
+@pytest.mark.parametrize("order", ["inside_first", "outside_first", "columns_late"])
+def test_sampled_filter_orders(hp, order):
+    """The sampled strategy against the oracle when the sample (the first
+    1/16 of the points) is unrepresentative: only interior points, only the
+    extreme points, or missing whole columns that appear later."""
+    p = 50_000
+    pts = synth.cloud("disc", 1_600_000, p, 41)
+    a = pts.numpy()
+    c = (p + 1) / 2.0
+    if order == "inside_first":
+        key = np.abs(a[:, 1] - c)                 # interior rows first
+    elif order == "outside_first":
+        key = -np.abs(a[:, 1] - c)                # extreme rows first
+    else:
+        key = (a[:, 0] % 97 == 0).astype(np.int64)  # a comb of columns only after the sample
+    a = np.ascontiguousarray(a[np.argsort(key, kind="stable")])
+    _run_both(hp, torch.from_numpy(a), p, f"sampled-{order}", strategies=(5, 2), split=False)
+
+
+@pytest.mark.parametrize("where", [100, 1_500_000])
+def test_sampled_range_error(hp, where):
+    """A point outside [1, p] in the sample prefix or in the filtered pass."""
+    pts = synth.cloud("uniform", 1_600_000, 40_000, 42)
+    pts[where] = torch.tensor([40_001, 5], dtype=torch.int32)
+    hp.set_strategy(5)
+    got = hp.run(pts.cuda(), 40_000)
+    hp.set_strategy(0)
+    assert got["status"] == HP_ERANGE
 
 
 def test_launch_shapes(hp):
@@ -153,7 +183,7 @@ def test_launch_shapes(hp):
     pts = synth.cloud("ellipsoids", 300_000, 2048, 13)
     want = _oracle(pts.numpy(), 2048)
     dev = pts.cuda()
-    for strategy in (1, 2, 3, 4):
+    for strategy in (1, 2, 3, 4, 5):
         for block in (256, 512, 1024):
             for vpt in (2, 4, 8):
                 for grid in (1, 7, 300):
@@ -177,7 +207,7 @@ def test_shared_chunks(hp, n, offset):
     want = _oracle(pts.numpy(), 1500)
     full = base.cuda()
     dev = full[offset:]
-    for strategy, grid in ((3, 7), (1, 5), (2, 3), (3, 1)):
+    for strategy, grid in ((3, 7), (1, 5), (2, 3), (3, 1), (5, 5)):
         hp.tune_set(strategy, 256, 2, grid)
         for rep in range(2):
             _compare(hp.run(dev, 1500), want, f"shared chunks n={n} off={offset} s={strategy} g={grid} rep={rep}")
@@ -211,4 +241,4 @@ def test_repeat_is_stable(hp):
 def test_column_windows(hp, kind, n, p, seed):
     """p above the LDS limit: the column-window reduce against the oracle."""
     pts = synth.cloud(kind, n, p, seed)
-    _run_both(hp, pts, p, f"window-{kind}-{n}-{p}", strategies=(4, 2))
+    _run_both(hp, pts, p, f"window-{kind}-{n}-{p}", strategies=(4, 2, 5))
