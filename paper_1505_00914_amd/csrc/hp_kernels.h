@@ -71,14 +71,45 @@ struct Batch {
   int2 cur[2 * VPT];
 };
 
-// FILT (device L only): a point goes on to the read of its column only when
-// its y lies outside the range filt[column >> fshift]; inside it, y can
-// improve neither extreme (the range is bounded by a lower L, see
-// k_reduce_filtered).
+// Filtered device-L folding.  A point goes on to its column of L only when
+// its y lies outside the range filt[column >> fshift] (inside it, y can
+// improve neither extreme; see k_reduce_filtered).  Passing points are
+// queued per wave in LDS as (column, y) and folded kFiltFlush or more at a
+// time, up to four coherent reads in flight per lane, so that the reads of
+// L cost one round trip per few hundred passing points instead of one per
+// batch of the stream.  A wave's LDS program order makes its queue writes
+// visible to its own later reads.
+constexpr int kFiltFlush = 128;
+__host__ __device__ constexpr int filt_queue_cap(int vpt) { return kFiltFlush + 2 * vpt * kWave; }
+
+__device__ __forceinline__ void filt_flush(int2 *L, const int2 *wq, int qn) {
+  const int lane = threadIdx.x & (kWave - 1);
+  for (int k = 0; k < qn; k += 4 * kWave) {
+    int2 e[4], cur[4];
+    bool ok[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = k + r * kWave + lane;
+      ok[r] = i < qn;
+      e[r] = ok[r] ? wq[i] : make_int2(0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) cur[r] = ok[r] ? load_coherent(&L[e[r].x]) : make_int2(0, 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if (ok[r] && e[r].y < cur[r].x)
+        __hip_atomic_fetch_min(&L[e[r].x].x, e[r].y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (ok[r] && e[r].y > cur[r].y)
+        __hip_atomic_fetch_max(&L[e[r].x].y, e[r].y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
 template <int VPT, bool LDS, bool WIN = false, bool FILT = false>
 __device__ __forceinline__ void gather(const int2 *L, int p, const int4 (&q)[VPT], Batch<VPT> &b,
                                        bool &bad, unsigned c0 = 0, unsigned wc = 0,
-                                       const int2 *filt = nullptr, int fshift = 0) {
+                                       const int2 *filt = nullptr, int fshift = 0, int2 *wq = nullptr,
+                                       int *qn = nullptr) {
 #pragma unroll
   for (int u = 0; u < VPT; ++u) {
     const int xs[2] = {q[u].x, q[u].z};
@@ -100,21 +131,34 @@ __device__ __forceinline__ void gather(const int2 *L, int p, const int4 (&q)[VPT
     }
   }
   if (FILT) {
+    const unsigned lane = threadIdx.x & (kWave - 1);
+    const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    int n = *qn;
 #pragma unroll
     for (int j = 0; j < 2 * VPT; ++j) {
       const int2 f = filt[b.c[j] >> fshift];
-      b.ok[j] = b.ok[j] & ((b.y[j] < f.x) | (b.y[j] > f.y));
+      const bool need = b.ok[j] & ((b.y[j] < f.x) | (b.y[j] > f.y));
+      const unsigned long long m = __ballot(need);
+      if (need) wq[n + __popcll(m & below)] = make_int2((int)b.c[j], b.y[j]);
+      n += __popcll(m);
+      b.ok[j] = false;   // folded from the queue instead
     }
-#pragma unroll
-    for (int j = 0; j < 2 * VPT; ++j) b.cur[j] = b.ok[j] ? load_coherent(&L[b.c[j]]) : make_int2(0, 0);
+    *qn = n;
     return;
   }
 #pragma unroll
   for (int j = 0; j < 2 * VPT; ++j) b.cur[j] = LDS ? L[b.c[j]] : load_coherent(&L[b.c[j]]);
 }
 
-template <int VPT, bool LDS>
-__device__ __forceinline__ void apply(int2 *L, const Batch<VPT> &b) {
+template <int VPT, bool LDS, bool FILT = false>
+__device__ __forceinline__ void apply(int2 *L, const Batch<VPT> &b, const int2 *wq = nullptr, int *qn = nullptr) {
+  if (FILT) {
+    if (*qn >= kFiltFlush) {
+      filt_flush(L, wq, *qn);
+      *qn = 0;
+    }
+    return;
+  }
 #pragma unroll
   for (int j = 0; j < 2 * VPT; ++j) {
     const unsigned c = b.c[j];

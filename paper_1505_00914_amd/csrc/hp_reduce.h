@@ -29,7 +29,9 @@ template <int BLOCK, int VPT, bool LDS, bool WIN = false, bool FILT = false>
 __device__ __forceinline__ void stream_points(const int32_t *__restrict__ pts, int64_t n, int p,
                                               int2 *L, int64_t wg, int64_t nwg, bool &bad,
                                               unsigned c0 = 0, unsigned wc = 0,
-                                              const int2 *filt = nullptr, int fshift = 0) {
+                                              const int2 *filt = nullptr, int fshift = 0,
+                                              int2 *wq = nullptr) {
+  int qn = 0;   // FILT: entries in this wave's queue
   // pts is 8-byte aligned (checked on the host); peel one point if the
   // vector body would otherwise start on an 8-byte boundary.
   const int64_t head = (n > 0 && ((uintptr_t)pts & 15) != 0) ? 1 : 0;
@@ -63,13 +65,13 @@ __device__ __forceinline__ void stream_points(const int32_t *__restrict__ pts, i
     const bool have_next = t1 + chunk <= nv;
     const int64_t tl = have_next ? t1 : t0;
     Batch<VPT> b;
-    gather<VPT, LDS, WIN, FILT>(L, p, q, b, bad, c0, wc, filt, fshift);
-    int4 qn[VPT];
+    gather<VPT, LDS, WIN, FILT>(L, p, q, b, bad, c0, wc, filt, fshift, wq, &qn);
+    int4 qv[VPT];
 #pragma unroll
-    for (int u = 0; u < VPT; ++u) qn[u] = WIN ? v[tl + u * BLOCK + threadIdx.x] : load_stream(&v[tl + u * BLOCK + threadIdx.x]);
-    apply<VPT, LDS>(L, b);
+    for (int u = 0; u < VPT; ++u) qv[u] = WIN ? v[tl + u * BLOCK + threadIdx.x] : load_stream(&v[tl + u * BLOCK + threadIdx.x]);
+    apply<VPT, LDS, FILT>(L, b, wq, &qn);
 #pragma unroll
-    for (int u = 0; u < VPT; ++u) q[u] = qn[u];
+    for (int u = 0; u < VPT; ++u) q[u] = qv[u];
     t0 = t1;
     have = have_next;
   }
@@ -90,6 +92,7 @@ __device__ __forceinline__ void stream_points(const int32_t *__restrict__ pts, i
       }
     }
   }
+  if (FILT) filt_flush(L, wq, qn);
 }
 
 // Work sharing of the single-cloud reduce.  The vector body is cut into
@@ -120,7 +123,9 @@ __host__ __device__ __forceinline__ int64_t dyn_chunks(int64_t n, uintptr_t pts,
 template <int BLOCK, int VPT, bool LDS, bool FILT = false>
 __device__ __forceinline__ void stream_points_dyn(const int32_t *__restrict__ pts, int64_t n, int p, int2 *L,
                                                   int64_t wg, int64_t nwg, bool &bad, const DynArgs &D,
-                                                  int *s_slot, const int2 *filt = nullptr, int fshift = 0) {
+                                                  int *s_slot, const int2 *filt = nullptr, int fshift = 0,
+                                                  int2 *wq = nullptr) {
+  int qn = 0;   // FILT: entries in this wave's queue
   const int64_t head = (n > 0 && ((uintptr_t)pts & 15) != 0) ? 1 : 0;
   const int64_t nv = (n - head) >> 1;
   const int64_t tail = head + 2 * nv;
@@ -202,15 +207,15 @@ __device__ __forceinline__ void stream_points_dyn(const int32_t *__restrict__ pt
   while (cur >= 0) {
     const int64_t tl = nx >= 0 ? nx : cur;
     Batch<VPT> b;
-    gather<VPT, LDS, false, FILT>(L, p, q, b, bad, 0, 0, filt, fshift);
-    int4 qn[VPT];
+    gather<VPT, LDS, false, FILT>(L, p, q, b, bad, 0, 0, filt, fshift, wq, &qn);
+    int4 qv[VPT];
 #pragma unroll
-    for (int u = 0; u < VPT; ++u) qn[u] = load_stream(&v[tl * chunk + u * BLOCK + threadIdx.x]);
-    apply<VPT, LDS>(L, b);
+    for (int u = 0; u < VPT; ++u) qv[u] = load_stream(&v[tl * chunk + u * BLOCK + threadIdx.x]);
+    apply<VPT, LDS, FILT>(L, b, wq, &qn);
     ++folded;
     const int64_t nn = nx >= 0 ? take(next()) : -1;
 #pragma unroll
-    for (int u = 0; u < VPT; ++u) q[u] = qn[u];
+    for (int u = 0; u < VPT; ++u) q[u] = qv[u];
     cur = nx;
     nx = nn;
   }
@@ -231,6 +236,7 @@ __device__ __forceinline__ void stream_points_dyn(const int32_t *__restrict__ pt
     }
     ++folded;
   }
+  if (FILT) filt_flush(L, wq, qn);
   if (threadIdx.x == 0) D.wg_cnt[wg] = folded;
 }
 
@@ -364,15 +370,20 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_filtered(const int32_t *__rest
                                                            int32_t p, int2 *L, const int2 *__restrict__ F,
                                                            int32_t fshift, int32_t ngroups,
                                                            int32_t *__restrict__ wg_err, DynArgs D) {
-  extern __shared__ int2 sF[];           // ngroups filter pairs, then the flag word and two grab slots
+  // LDS: ngroups filter pairs, the flag word and two grab slots (2 pairs),
+  // then one queue of filt_queue_cap(VPT) entries per wave
+  extern __shared__ int2 sF[];
   int &s_bad = sF[ngroups].x;
   int *s_slot = &sF[ngroups].y;          // sF[ngroups].y and sF[ngroups + 1].x
+  int2 *wq = sF + ngroups + 2 + (threadIdx.x / kWave) * filt_queue_cap(VPT);
   for (int g = threadIdx.x; g < ngroups; g += BLOCK) sF[g] = F[g];
   if (threadIdx.x == 0) s_bad = 0;
   __syncthreads();
   bool bad = false;
-  if (D.ctr) stream_points_dyn<BLOCK, VPT, false, true>(pts, n, p, L, blockIdx.x, gridDim.x, bad, D, s_slot, sF, fshift);
-  else stream_points<BLOCK, VPT, false, false, true>(pts, n, p, L, blockIdx.x, gridDim.x, bad, 0, 0, sF, fshift);
+  if (D.ctr)
+    stream_points_dyn<BLOCK, VPT, false, true>(pts, n, p, L, blockIdx.x, gridDim.x, bad, D, s_slot, sF, fshift, wq);
+  else
+    stream_points<BLOCK, VPT, false, false, true>(pts, n, p, L, blockIdx.x, gridDim.x, bad, 0, 0, sF, fshift, wq);
   if (bad) s_bad = 1;
   __syncthreads();
   if (threadIdx.x == 0) wg_err[blockIdx.x] = s_bad ? kErrRange : 0;

@@ -66,30 +66,36 @@ __global__ __launch_bounds__(256) void k_filter_build(const int2 *__restrict__ L
 }
 
 // ---------------------------------------------------------------------------
-// Finish: one workgroup of 1024 threads per slab of 64 positions.
+// Finish: one workgroup per slab of 64 positions, of FB threads: 1024, or
+// 256 when there are many slabs (the launch is then bound by how fast the
+// dispatcher starts waves, not by the work of a slab).
 // ---------------------------------------------------------------------------
 constexpr int kFinBlock = 1024;
-constexpr int kFinGroups = kFinBlock / kSlab;  // partial-merge thread groups
+constexpr int kFinBlockMany = 256;
 
-struct FinishShared {
-  int2 red[kFinGroups][kSlab]; // partial-merge scratch
+template <int FB>
+struct FinishSharedT {
+  int2 red[FB / kSlab][kSlab]; // partial-merge scratch
   int2 pt[2][kSlab];           // slab points: side 0 (x, lo), side 1 (x, -hi)
   int2 stage[2 * kSlab];       // slab hulls per side
-  unsigned char keep8[kFinBlock / kWave];  // slab-hull keep bits, 8 candidates per wave
+  uint32_t keepw[FB / kWave];  // slab-hull keep bits, one per candidate of the wave
   unsigned long long valid;    // valid positions of the slab
-  int tmp[kFinBlock / kWave + 1];
+  int tmp[FB / kWave + 1];
   int slab_cnt[2];
   int flag;
   int scan_carry;
   int folded;                  // chunks the reduce workgroups report (slab 0)
 };
+using FinishShared = FinishSharedT<kFinBlock>;
 
-// Exclusive scan of n ints in place (by one workgroup); returns the total.
+// Exclusive scan of n ints in place (by one workgroup of FB threads);
+// returns the total.
+template <int FB = kFinBlock>
 __device__ int block_exclusive_scan(int32_t *a, int32_t n, int *s_tmp, int *s_carry) {
   const int tid = threadIdx.x;
   if (tid == 0) *s_carry = 0;
   __syncthreads();
-  for (int base = 0; base < n; base += kFinBlock) {
+  for (int base = 0; base < n; base += FB) {
     const int i = base + tid;
     const int v = i < n ? a[i] : 0;
     // inclusive scan inside the wave
@@ -104,7 +110,7 @@ __device__ int block_exclusive_scan(int32_t *a, int32_t n, int *s_tmp, int *s_ca
     if (lane == kWave - 1) s_tmp[w] = incl;
     __syncthreads();
     int off = *s_carry, all = 0;
-    for (int j = 0; j < kFinBlock / kWave; ++j) {
+    for (int j = 0; j < FB / kWave; ++j) {
       if (j < w) off += s_tmp[j];
       all += s_tmp[j];
     }
@@ -132,15 +138,88 @@ __device__ bool last_arrival_flag(int32_t *ctr, int expected, int *s_flag) {
   return *s_flag != 0;
 }
 
-__device__ bool last_arrival(int32_t *ctr, int expected, FinishShared &S) {
+template <int FB>
+__device__ bool last_arrival(int32_t *ctr, int expected, FinishSharedT<FB> &S) {
   return last_arrival_flag(ctr, expected, &S.flag);
+}
+
+// Exclusive scan of the slab counts into slab_off, the k and s totals and
+// the range status, and (chain_inline) the chain itself: by one workgroup,
+// the last slab to finish or the scan launch that follows the slab step.
+template <int FB>
+__device__ void scan_slabs(const FinishArgs &A, FinishSharedT<FB> &S) {
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int grp = tid / kWave;
+  const int nslab = A.tree.size[1];
+  if (tid == 0) S.flag = 0;
+  // slab_off = exclusive scan of slab_k; k and s totals.  The counts,
+  // the s parts and the error words are all loaded before any is used.
+  int s_part = 0, err = 0;
+  for (int i = tid; i < nslab || i < A.n_wg_err; i += FB) {
+    const int kk = i < nslab ? A.slab_k[i] : 0;
+    const int ss = i < nslab ? A.slab_s[i] : 0;
+    const int ee = i < A.n_wg_err ? A.wg_err[i] : 0;
+    if (i < nslab) A.slab_off[i] = kk;
+    s_part += ss;
+    err |= ee;
+  }
+  __syncthreads();
+  const int k = block_exclusive_scan<FB>(A.slab_off, nslab, S.tmp, &S.scan_carry);
+  // block sum of s
+  for (int d = kWave / 2; d > 0; d >>= 1) s_part += __shfl_down(s_part, d, kWave);
+  __syncthreads();
+  if (lane == 0) S.tmp[grp] = s_part;
+  __syncthreads();
+  if (err) atomicOr(&S.flag, err);
+  __syncthreads();
+  if (tid == 0) {
+    int s = 0;
+    for (int w = 0; w < FB / kWave; ++w) s += S.tmp[w];
+    A.info[HP_INFO_K] = k;
+    A.info[HP_INFO_S] = s;
+    if (S.flag & kErrRange) atomicMin(&A.info[HP_INFO_STATUS], HP_ERANGE);
+  }
+  if (A.chain_inline) {
+    // every wave writes the chain of up to 4 slabs per round, all loads first
+    constexpr int kW = FB / kWave;
+    for (int sl0 = grp; sl0 < nslab; sl0 += 4 * kW) {
+      int2 Lv[4];
+      int offv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int sl = sl0 + u * kW;
+        const int64_t pos = (int64_t)sl * kSlab + lane;
+        Lv[u] = (sl < nslab && pos < A.p) ? A.Lm[pos] : make_int2(1, 0);
+        offv[u] = sl < nslab ? A.slab_off[sl] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int sl = sl0 + u * kW;
+        const bool valid = sl < nslab && Lv[u].x <= Lv[u].y;
+        int tot;
+        const int r = wave_rank(valid, &tot);
+        const int off = offv[u] + r;
+        if (valid) {
+          if (off < A.chain_cap) {
+            A.cx_out[off] = sl * kSlab + lane + 1;
+            A.clo_out[off] = Lv[u].x;
+            A.chi_out[off] = Lv[u].y;
+          } else {
+            atomicMin(&A.info[HP_INFO_STATUS], HP_ECAPACITY);
+          }
+        }
+      }
+    }
+  }
 }
 
 // Per-slab work of the finish step, for slab `slab` of the cloud described
 // by A (the single-cloud kernel passes its block index, the batched kernel
 // the slab of its work item).
-template <int FROM_CHAIN, bool SMALL>
-__device__ __forceinline__ void finish_body(const FinishArgs &A, FinishShared &S, const int slab) {
+template <int FROM_CHAIN, bool SMALL, int FB>
+__device__ __forceinline__ void finish_body(const FinishArgs &A, FinishSharedT<FB> &S, const int slab) {
+  constexpr int kFinGroups = FB / kSlab;   // partial-merge thread groups
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int grp = tid / kWave;
@@ -152,7 +231,7 @@ __device__ __forceinline__ void finish_body(const FinishArgs &A, FinishShared &S
   int folded = 0;
   if (check) {
     if (tid == 0) S.folded = 0;
-    for (int j = tid; j < A.n_wg_cnt; j += kFinBlock) folded += A.wg_cnt[j];
+    for (int j = tid; j < A.n_wg_cnt; j += FB) folded += A.wg_cnt[j];
   }
 
   // ---- the slab's points --------------------------------------------------
@@ -253,7 +332,7 @@ __device__ __forceinline__ void finish_body(const FinishArgs &A, FinishShared &S
   // left turn (collinear points dropped, Appendix).  Branch-free selects.
   if (A.do_hull) {
     {
-      constexpr int kG = kFinBlock / (2 * kSlab);   // lanes per candidate
+      constexpr int kG = FB / (2 * kSlab);   // lanes per candidate
       const unsigned long long vm = S.valid;
       const int cand = tid / kG, g = tid % kG;
       const int side = cand / kSlab, i = cand % kSlab;
@@ -296,7 +375,7 @@ __device__ __forceinline__ void finish_body(const FinishArgs &A, FinishShared &S
         unsigned bits = 0;
 #pragma unroll
         for (int q = 0; q < kWave / kG; ++q) bits |= (unsigned)((kb >> (q * kG)) & 1ull) << q;
-        S.keep8[grp] = (unsigned char)bits;
+        S.keepw[grp] = bits;
       }
     }
     __syncthreads();
@@ -304,9 +383,9 @@ __device__ __forceinline__ void finish_body(const FinishArgs &A, FinishShared &S
       // wave `side` compacts its side: position lane kept iff bit set
       const int side = grp;
       const int bitpos = side * kSlab + lane;   // candidate index
-      constexpr int kG = kFinBlock / (2 * kSlab);
+      constexpr int kG = FB / (2 * kSlab);
       constexpr int kPerWave = kWave / kG;      // candidates per wave
-      const bool keep = (S.keep8[bitpos / kPerWave] >> (bitpos % kPerWave)) & 1;
+      const bool keep = (S.keepw[bitpos / kPerWave] >> (bitpos % kPerWave)) & 1u;
       int tot;
       const int rk = wave_rank(keep, &tot);
       if (keep) S.stage[side * kSlab + rk] = S.pt[side][lane];
@@ -335,80 +414,26 @@ __device__ __forceinline__ void finish_body(const FinishArgs &A, FinishShared &S
   }
 
   // ---- last slab: scan the slab counts (when the chain is not written by
-  // the first hull level) ------------------------------------------------------
+  // the first hull level and no scan launch follows) ---------------------------
   if (!FROM_CHAIN && A.scan_root) {
     if (last_arrival(&A.ctl[kCtlSlabsDone], A.tree.size[1], S)) {
-      const int nslab = A.tree.size[1];
       __syncthreads();
-      if (tid == 0) S.flag = 0;
-      // slab_off = exclusive scan of slab_k; k and s totals.  The counts,
-      // the s parts and the error words are all loaded before any is used.
-      int s_part = 0, err = 0;
-      for (int i = tid; i < nslab || i < A.n_wg_err; i += kFinBlock) {
-        const int kk = i < nslab ? A.slab_k[i] : 0;
-        const int ss = i < nslab ? A.slab_s[i] : 0;
-        const int ee = i < A.n_wg_err ? A.wg_err[i] : 0;
-        if (i < nslab) A.slab_off[i] = kk;
-        s_part += ss;
-        err |= ee;
-      }
-      __syncthreads();
-      const int k = block_exclusive_scan(A.slab_off, nslab, S.tmp, &S.scan_carry);
-      // block sum of s
-      for (int d = kWave / 2; d > 0; d >>= 1) s_part += __shfl_down(s_part, d, kWave);
-      __syncthreads();
-      if (lane == 0) S.tmp[grp] = s_part;
-      __syncthreads();
-      if (err) atomicOr(&S.flag, err);
-      __syncthreads();
-      if (tid == 0) {
-        int s = 0;
-        for (int w = 0; w < kFinBlock / kWave; ++w) s += S.tmp[w];
-        A.info[HP_INFO_K] = k;
-        A.info[HP_INFO_S] = s;
-        if (S.flag & kErrRange) atomicMin(&A.info[HP_INFO_STATUS], HP_ERANGE);
-      }
-      if (A.chain_inline) {
-        // every wave writes the chain of up to 4 slabs per round, all loads first
-        constexpr int kW = kFinBlock / kWave;
-        for (int sl0 = grp; sl0 < nslab; sl0 += 4 * kW) {
-          int2 Lv[4];
-          int offv[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int sl = sl0 + u * kW;
-            const int64_t pos = (int64_t)sl * kSlab + lane;
-            Lv[u] = (sl < nslab && pos < A.p) ? A.Lm[pos] : make_int2(1, 0);
-            offv[u] = sl < nslab ? A.slab_off[sl] : 0;
-          }
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int sl = sl0 + u * kW;
-            const bool valid = sl < nslab && Lv[u].x <= Lv[u].y;
-            int tot;
-            const int r = wave_rank(valid, &tot);
-            const int off = offv[u] + r;
-            if (valid) {
-              if (off < A.chain_cap) {
-                A.cx_out[off] = sl * kSlab + lane + 1;
-                A.clo_out[off] = Lv[u].x;
-                A.chi_out[off] = Lv[u].y;
-              } else {
-                atomicMin(&A.info[HP_INFO_STATUS], HP_ECAPACITY);
-              }
-            }
-          }
-        }
-      }
+      scan_slabs(A, S);
     }
   }
-
 }
 
-template <int FROM_CHAIN, bool SMALL>
-__global__ __launch_bounds__(kFinBlock) void k_finish(FinishArgs A) {
+template <int FROM_CHAIN, bool SMALL, int FB = kFinBlock>
+__global__ __launch_bounds__(FB) void k_finish(FinishArgs A) {
+  __shared__ FinishSharedT<FB> S;
+  finish_body<FROM_CHAIN, SMALL, FB>(A, S, blockIdx.x);
+}
+
+// The slab scan as a launch of its own (many slabs: one last-arriver count
+// per slab would serialise thousands of device-scope atomics on one word).
+__global__ __launch_bounds__(kFinBlock) void k_slab_scan(FinishArgs A) {
   __shared__ FinishShared S;
-  finish_body<FROM_CHAIN, SMALL>(A, S, blockIdx.x);
+  scan_slabs(A, S);
 }
 
 // ---------------------------------------------------------------------------
@@ -771,7 +796,7 @@ constexpr int kNodeVerts = kFanIn * kSlab;   // 4096 positions per level-2 node
 constexpr int kL2Waves = kHullBlock / kWave; // one tested vertex per wave
 
 constexpr int kL2MaxParts = 128;             // test workgroups per node, at most
-constexpr int kL2TargetWgs = 512;            // test workgroups per launch, about
+constexpr int kL2TargetWgs = 2048;           // test workgroups per launch, about
 
 struct L2Shared {
   int2 P[2][kNodeVerts];     // the node's vertices per side, compacted in x order
@@ -1331,6 +1356,8 @@ static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 constexpr int kMaxGrid = 4096;
 // Largest p whose chain the scan root writes itself (no k_chain launch).
 constexpr int32_t kChainInline = 32768;
+// Most slabs whose scan the last slab to finish does (above: a scan launch).
+constexpr int32_t kScanRootMaxSlabs = 256;
 
 // Survival bytes per side: positions rounded up to whole level-2 nodes, so
 // the level-2 test's flags (node * 4096 + vertex) stay in range and aligned.
@@ -1570,7 +1597,7 @@ static hipError_t launch_sampled(const Plan1 &P, const int32_t *pts, int64_t n, 
   else hipLaunchKernelGGL((k_reduce_global<BLOCK, VPT>), dim3(G1), dim3(BLOCK), 0, s, pts, ns, p, Lm, wg_err, R, D0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const size_t lds = sizeof(int2) * ((size_t)ngroups + 2);
+  const size_t lds = sizeof(int2) * ((size_t)ngroups + 2 + (size_t)(BLOCK / kWave) * filt_queue_cap(VPT));
   // first filtered pass: points [ns, n1), static shares
   hipLaunchKernelGGL(k_filter_build, dim3((ngroups + 3) / 4), dim3(256), 0, s, (const int2 *)Lm, p, fshift,
                      ngroups, F);
@@ -1718,7 +1745,10 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
   const int64_t n1 = sampled ? std::min<int64_t>(n, 4 * ns) : 0;   // end of the first filtered pass (even)
   int fshift = 6, ngroups = 0, G1 = 0;
   if (sampled) {
-    const int64_t pairs = device_info().lds_bytes / 8 - 2;
+    // LDS pairs left for the filter after the flag and grab words and the
+    // per-wave queues of the filtered passes
+    const int64_t pairs = device_info().lds_bytes / 8 - 2 - (int64_t)(P.block / kWave) * filt_queue_cap(P.vpt);
+    if (pairs < 1) return set_error(HP_EINVAL, "launch shape leaves no LDS for the filter");
     while ((((int64_t)p + ((int64_t)1 << fshift) - 1) >> fshift) > pairs) ++fshift;
     ngroups = (int)(((int64_t)p + ((int64_t)1 << fshift) - 1) >> fshift);
     const int64_t per = (int64_t)P.block * P.vpt;
@@ -1775,7 +1805,10 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
   // slab's scan.  Without the hull the last slab scans and writes the chain.
   const bool l2path = do_hull && T.nlev >= 2;
   const bool l2scan = l2path && T.size[1] > kL2MaxSlabs;
-  A.scan_root = (l2path && !l2scan) ? 0 : 1;
+  const bool need_scan = !l2path || l2scan;
+  // many slabs: the scan is a launch of its own instead of the last slab's
+  const bool scan_launch = need_scan && T.size[1] > kScanRootMaxSlabs;
+  A.scan_root = (need_scan && !scan_launch) ? 1 : 0;
   A.chain_inline = (!l2path && p <= kChainInline) ? 1 : 0;
   A.cx_out = cx;
   A.clo_out = clo;
@@ -1801,12 +1834,24 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
   H.clo = clo;
   H.chi = chi;
   H.chain_cap = chain_cap;
-  if (small)
+  // many slabs: 256-thread slab workgroups (the last-slab scan, which needs
+  // 1024 threads, is then a launch of its own)
+  const bool many = T.size[1] > kScanRootMaxSlabs;
+  if (many && small)
+    hipLaunchKernelGGL((k_finish<0, true, kFinBlockMany>), dim3(T.size[1]), dim3(kFinBlockMany), 0, s, A);
+  else if (many)
+    hipLaunchKernelGGL((k_finish<0, false, kFinBlockMany>), dim3(T.size[1]), dim3(kFinBlockMany), 0, s, A);
+  else if (small)
     hipLaunchKernelGGL((k_finish<0, true>), dim3(T.size[1]), dim3(kFinBlock), 0, s, A);
   else
     hipLaunchKernelGGL((k_finish<0, false>), dim3(T.size[1]), dim3(kFinBlock), 0, s, A);
   e = hipGetLastError();
   if (e != hipSuccess) return set_error(HP_EDEVICE, "k_finish launch: %s", hipGetErrorString(e));
+  if (scan_launch) {
+    hipLaunchKernelGGL(k_slab_scan, dim3(1), dim3(kFinBlock), 0, s, A);
+    e = hipGetLastError();
+    if (e != hipSuccess) return set_error(HP_EDEVICE, "k_slab_scan launch: %s", hipGetErrorString(e));
+  }
   if (!l2path && !A.chain_inline) {
     const int nslab = T.size[1];
     hipLaunchKernelGGL(k_chain, dim3((nslab + 3) / 4), dim3(256), 0, s, Lm, p, A.slab_off, nslab, cx,
