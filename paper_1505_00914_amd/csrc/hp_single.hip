@@ -796,7 +796,7 @@ constexpr int kNodeVerts = kFanIn * kSlab;   // 4096 positions per level-2 node
 constexpr int kL2Waves = kHullBlock / kWave; // one tested vertex per wave
 
 constexpr int kL2MaxParts = 128;             // test workgroups per node, at most
-constexpr int kL2TargetWgs = 2048;           // test workgroups per launch, about
+constexpr int kL2TargetWgs = 512;            // test workgroups per launch, about
 
 struct L2Shared {
   int2 P[2][kNodeVerts];     // the node's vertices per side, compacted in x order
