@@ -121,6 +121,7 @@ def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_gfx950.txt"))
     ap.add_argument("--quick", action="store_true", help="only the 10M-point, p = 4096 regime")
+    ap.add_argument("--regimes", default="", help="comma-separated log2n:log2p pairs of the default list to tune")
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--verbose", action="store_true", help="print every shape's timing")
     args = ap.parse_args(argv)
@@ -130,7 +131,11 @@ def main(argv=None) -> int:
     log = lambda m: print(m, flush=True)  # noqa: E731
     rows = []
     t0 = time.time()
-    for ln, lp, kind in (QUICK if args.quick else REGIMES):
+    todo = QUICK if args.quick else REGIMES
+    if args.regimes:
+        want = {tuple(int(v) for v in r.split(":")) for r in args.regimes.split(",")}
+        todo = [r for r in REGIMES if (r[0], r[1]) in want]
+    for ln, lp, kind in todo:
         rows.append(tune_regime(ln, lp, kind, args.steps, log, args.verbose))
     name = torch.cuda.get_device_properties(0).name
     with open(args.out, "w") as f:
