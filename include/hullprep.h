@@ -112,7 +112,13 @@ int32_t hp_lds_max_p(void);
 
 /* Force a strategy for later calls on this process (HP_STRATEGY_*), e.g. for
  * tests; HP_STRATEGY_AUTO restores the tuned choice.  Also settable with the
- * environment variable HP_FORCE_STRATEGY=lds|global|lds_partial|window|sampled. */
+ * environment variable HP_FORCE_STRATEGY=lds|global|lds_partial|window|sampled.
+ * Other environment variables, read once per process: HP_TUNING_FILE (a
+ * tuning table to load instead of the one beside the library), HP_DYN_OFF=1
+ * (no chunk sharing in the reduce), HP_DYN_STATIC8 (static share of a
+ * shared-chunk reduce in eighths, 0..8, default 6) and HP_SAMPLE_DIV (the
+ * sampled strategy folds the first n / HP_SAMPLE_DIV points exactly, 2..64,
+ * default 8). */
 int hp_set_strategy(int strategy);
 
 /* Launch-shape override for later calls in this process (used by the tuner):
