@@ -242,3 +242,28 @@ def test_column_windows(hp, kind, n, p, seed):
     """p above the LDS limit: the column-window reduce against the oracle."""
     pts = synth.cloud(kind, n, p, seed)
     _run_both(hp, pts, p, f"window-{kind}-{n}-{p}", strategies=(4, 2, 5))
+
+
+def test_random_sweep(hp):
+    """Seeded random cases across cloud kinds, sizes, p, strategies and
+    launch shapes, each against the oracle (shape and seed are printed)."""
+    rng = np.random.default_rng(2024)
+    kinds = ["uniform", "ellipsoids", "disc", "gaussian"]
+    for case in range(80):
+        kind = kinds[int(rng.integers(len(kinds)))]
+        n = int(np.exp(rng.uniform(0, np.log(300_000))))
+        p = int(np.exp(rng.uniform(0, np.log(120_000))))
+        strategy = int(rng.integers(0, 6))
+        block = [0, 256, 512, 1024][int(rng.integers(4))]
+        vpt = [2, 4, 8][int(rng.integers(3))] if block else 0   # a block size needs its vpt
+        grid = int(rng.integers(1, 600)) if block else 0
+        seed = int(rng.integers(1 << 30))
+        label = f"sweep {case}: {kind} n={n} p={p} strategy={strategy} shape={block}/{vpt}/{grid} seed={seed}"
+        print("[case]", label, flush=True)
+        pts = synth.cloud(kind, n, p, seed)
+        want = _oracle(pts.numpy(), p)
+        hp.tune_set(strategy, block, vpt, grid)
+        try:
+            _compare(hp.run(pts.cuda(), p), want, label)
+        finally:
+            hp.tune_set(0, 0, 0, 0)
