@@ -7,5 +7,5 @@ baseline of the benchmark may import this package.  The product library under
 from .oracle import (  # noqa: F401
     OR_OK, OR_EINVAL, OR_ERANGE, OR_EORDER, OracleError,
     build, lib_path, reduce, mask, ctz_positions, extract, chain, reduced,
-    hull_chain, hull_full, precondition_and_hull,
+    hull_chain, hull_full, precondition_and_hull, bbox, translate, auto,
 )

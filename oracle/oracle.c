@@ -306,3 +306,45 @@ int64_t or_hull_full(const int32_t *pts, int64_t n, int32_t *vx, int32_t *vy)
     free(py);
     return h;
 }
+
+/* ---------------------------------------------------------------------------
+ * Steps 1 and 2 of the proposed heuristic.
+ *
+ * Step 1 finds the extremes of x and y over P.  Step 2 moves P so that the
+ * smallest x and the smallest y both become 1: x' = x - xmin + 1 and
+ * y' = y - ymin + 1.  Algorithm 1 then runs on P' with one side p for both
+ * coordinates, the larger of the two extents (xmax - xmin + 1 and
+ * ymax - ymin + 1), so that every translated point lies in [1, p]^2.
+ * ------------------------------------------------------------------------- */
+int or_bbox(const int32_t *pts, int64_t n, int32_t *box)
+{
+    if (n < 1 || pts == NULL || box == NULL) return OR_EINVAL;
+    int32_t xmin = pts[0], xmax = pts[0], ymin = pts[1], ymax = pts[1];
+    for (int64_t j = 1; j < n; ++j) {
+        int32_t x = pts[2 * j], y = pts[2 * j + 1];
+        if (x < xmin) xmin = x;
+        if (x > xmax) xmax = x;
+        if (y < ymin) ymin = y;
+        if (y > ymax) ymax = y;
+    }
+    box[0] = xmin;
+    box[1] = xmax;
+    box[2] = ymin;
+    box[3] = ymax;
+    return OR_OK;
+}
+
+int or_translate(const int32_t *pts, int64_t n, const int32_t *box, int32_t *out, int32_t *p)
+{
+    if (n < 1 || pts == NULL || box == NULL || out == NULL || p == NULL) return OR_EINVAL;
+    int64_t ex = (int64_t)box[1] - box[0] + 1, ey = (int64_t)box[3] - box[2] + 1;
+    int64_t side = ex > ey ? ex : ey;
+    if (side > OR_PMAX) return OR_EINVAL;
+    for (int64_t j = 0; j < n; ++j) {
+        out[2 * j] = (int32_t)((int64_t)pts[2 * j] - box[0] + 1);
+        out[2 * j + 1] = (int32_t)((int64_t)pts[2 * j + 1] - box[2] + 1);
+    }
+    *p = (int32_t)side;
+    return OR_OK;
+}
+

@@ -83,6 +83,16 @@ int32_t or_hull_chain(const int32_t *x, const int32_t *clo, const int32_t *chi,
  * OR_EINVAL on allocation failure. */
 int64_t or_hull_full(const int32_t *pts, int64_t n, int32_t *vx, int32_t *vy);
 
+/* Step 1 (Proposed heuristic): box = (xmin, xmax, ymin, ymax) over the n >= 1
+ * points.  OR_EINVAL for n < 1 or NULL arguments. */
+int or_bbox(const int32_t *pts, int64_t n, int32_t *box);
+
+/* Step 2 (Proposed heuristic): out[j] = (x - xmin + 1, y - ymin + 1) for the
+ * box of step 1, and *p = max(xmax - xmin, ymax - ymin) + 1, the side of the
+ * square Algorithm 1 then runs on.  OR_EINVAL if that side exceeds
+ * 2^31 - 2.  out needs 2n entries. */
+int or_translate(const int32_t *pts, int64_t n, const int32_t *box, int32_t *out, int32_t *p);
+
 #ifdef __cplusplus
 }
 #endif

@@ -67,6 +67,10 @@ def _load(path: str) -> ctypes.CDLL:
     lib.or_hull_chain.restype = ctypes.c_int32
     lib.or_hull_full.argtypes = [_i32p, ctypes.c_int64, _i32p, _i32p]
     lib.or_hull_full.restype = ctypes.c_int64
+    lib.or_bbox.argtypes = [_i32p, ctypes.c_int64, _i32p]
+    lib.or_bbox.restype = ctypes.c_int
+    lib.or_translate.argtypes = [_i32p, ctypes.c_int64, _i32p, _i32p, _i32p]
+    lib.or_translate.restype = ctypes.c_int
     return lib
 
 
@@ -189,3 +193,39 @@ def precondition_and_hull(pts, p: int, lib: str | None = None) -> dict:
     hull = hull_chain(x, cl, ch, lib)
     return {"lo": lo, "hi": hi, "mask": M, "x": x, "clo": cl, "chi": ch,
             "k": int(x.shape[0]), "hull": hull}
+
+
+def bbox(pts, lib: str | None = None) -> tuple[int, int, int, int]:
+    """Step 1: (xmin, xmax, ymin, ymax) of the points."""
+    a = _points(pts)
+    box = np.empty(4, np.int32)
+    rc = _lib(lib).or_bbox(_ptr(a), a.shape[0], _ptr(box))
+    if rc != OR_OK:
+        raise OracleError(f"or_bbox failed: {rc}")
+    return tuple(int(v) for v in box)
+
+
+def translate(pts, box, lib: str | None = None) -> tuple[np.ndarray, int]:
+    """Step 2: the translated points and the side p of their square."""
+    a = _points(pts)
+    b = np.asarray(box, np.int32)
+    out = np.empty_like(a)
+    p = np.zeros(1, np.int32)
+    rc = _lib(lib).or_translate(_ptr(a), a.shape[0], _ptr(b), _ptr(out), _ptr(p))
+    if rc != OR_OK:
+        raise OracleError(f"or_translate failed: {rc}")
+    return out, int(p[0])
+
+
+def auto(pts, lib: str | None = None) -> dict:
+    """Steps 1 to 3 and the hull: box, translation, then the whole path on
+    the translated points.  Outputs are in translated coordinates; ``origin``
+    (xmin - 1, ymin - 1) maps them back."""
+    box = bbox(pts, lib)
+    t, p = translate(pts, box, lib)
+    r = precondition_and_hull(t, p, lib)
+    r["p"] = p
+    r["box"] = box
+    r["origin"] = (box[0] - 1, box[2] - 1)
+    return r
+

@@ -321,11 +321,56 @@ def pin_errors(lib=None):
     return errs
 
 
+@_safe
+def pin_steps12(lib=None):
+    """Steps 1 and 2: the box is the coordinate extremes, the translation puts
+    the smallest x and y at 1, and a moved copy of the worked example gives
+    the paper's L and pentagon back."""
+    errs = []
+    rng = np.random.default_rng(12)
+    big = np.iinfo(np.int32)
+    for trial in range(40):
+        n = int(rng.integers(1, 300))
+        lo = int(rng.integers(big.min, big.max - 1000))
+        span = int(rng.integers(0, 1000))
+        pts = rng.integers(lo, lo + span + 1, size=(n, 2), dtype=np.int64).astype(np.int32)
+        box = oracle.bbox(pts, lib=lib)
+        want = (int(pts[:, 0].min()), int(pts[:, 0].max()), int(pts[:, 1].min()), int(pts[:, 1].max()))
+        if box != want:
+            errs.append(f"trial {trial}: box {box} != {want}")
+            continue
+        t, p = oracle.translate(pts, box, lib=lib)
+        if t[:, 0].min() != 1 or t[:, 1].min() != 1:
+            errs.append(f"trial {trial}: translated minimum {t.min(0)} != (1, 1)")
+        if p != max(want[1] - want[0], want[3] - want[2]) + 1 or t.max() != p:
+            errs.append(f"trial {trial}: side {p}, translated maximum {t.max()}")
+        if not np.array_equal(t.astype(np.int64) - 1 + [want[0], want[2]], pts.astype(np.int64)):
+            errs.append(f"trial {trial}: translation is not a shift")
+    f = fixtures.read("worked_example_p5.txt")
+    base = np.asarray(fixtures.pairs(f["points"]), np.int64)
+    want_L = fixtures.pairs(f["L"])
+    for off in [(0, 0), (1000, -500), (-2**31, -2**31), (2**31 - 6, 7)]:
+        moved = (base + np.asarray(off) + 0).astype(np.int32)
+        r = oracle.auto(moved, lib=lib)
+        got = list(zip(r["lo"].tolist(), r["hi"].tolist()))
+        if r["p"] != 5 or got != want_L:
+            errs.append(f"offset {off}: p {r['p']}, L {got} != paper {want_L}")
+        if [tuple(v) for v in r["hull"].tolist()] != [(1, 1), (5, 2), (5, 3), (3, 5), (1, 4)]:
+            errs.append(f"offset {off}: hull {r['hull'].tolist()}")
+    for bad in [[(-2**31, 0), (2**31 - 1, 0)], [(0, -2**31 + 1), (0, 2**31 - 1)]]:
+        try:
+            oracle.translate(bad, oracle.bbox(bad, lib=lib), lib=lib)
+            errs.append(f"extent of {bad} accepted")
+        except oracle.OracleError:
+            pass
+    return errs
+
+
 ALL_PINS = [pin_worked_example, pin_gap_example, pin_table1, pin_block_index,
             pin_closed_forms, pin_brute_random, pin_exhaustive_p3, pin_qhull,
-            pin_appendix, pin_invariants, pin_metamorphic, pin_errors]
+            pin_appendix, pin_invariants, pin_metamorphic, pin_errors, pin_steps12]
 
 # the cheap pins, run first against planted mistakes
 FAST_PINS = [pin_worked_example, pin_gap_example, pin_table1, pin_block_index,
-             pin_closed_forms, pin_errors, pin_brute_random]
+             pin_closed_forms, pin_errors, pin_brute_random, pin_steps12]
 

@@ -38,6 +38,10 @@ MUTANTS = {
     "reduced-repeats-single": ("if (chi[t] > clo[t]) {", "if (chi[t] >= clo[t]) {"),
     "range-check-off": ("if (x < 1 || x > p || y < 1 || y > p) return OR_ERANGE;",
                         "if (x < 1 || x > p || y < 1) return OR_ERANGE;"),
+    "bbox-ymin-from-x": ("if (y < ymin) ymin = y;", "if (x < ymin) ymin = x;"),
+    "translate-off-by-one": ("out[2 * j] = (int32_t)((int64_t)pts[2 * j] - box[0] + 1);",
+                             "out[2 * j] = (int32_t)((int64_t)pts[2 * j] - box[0]);"),
+    "side-from-x-only": ("int64_t side = ex > ey ? ex : ey;", "int64_t side = ex;"),
     "chain-skips-last": ("for (int32_t i = 1; i <= p; ++i) {\n        if (or_valid(lo[i - 1], hi[i - 1], p)) {\n            x[k] = i;",
                          "for (int32_t i = 1; i < p; ++i) {\n        if (or_valid(lo[i - 1], hi[i - 1], p)) {\n            x[k] = i;"),
 }
