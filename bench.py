@@ -571,6 +571,55 @@ def summarize_counters(fetch_dir: str, write_dir: str, copy_bytes: float, comman
     return "\n".join(out) + "\n"
 
 
+def bench_auto(args, torch, hp, synth) -> dict:
+    """Steps 1 and 2 on the main workload moved far from the origin: the
+    bounding-box pass alone, then bounding box + path on the moved points
+    (the path reads every point through the origin, no translated copy)."""
+    import numpy as np
+
+    import oracle
+
+    w = synth.WORKLOADS[args.workload]
+    off = (-1_000_000_007, 123_456_789)
+    pts = synth.cloud(w["kind"], w["n"], w["p"], w["seed"], device="cuda:0")
+    pts += torch.tensor(off, dtype=torch.int32, device=pts.device)
+    n = pts.shape[0]
+    stream = torch.cuda.current_stream()
+    xmin, xmax, ymin, ymax = hp.bbox(pts)
+    p = max(xmax - xmin, ymax - ymin) + 1
+    origin = (xmin - 1, ymin - 1)
+    buf = hp.Buffers.allocate(n, p, pts.device, export_L=False)
+    box = torch.empty(4, dtype=torch.int32, device=pts.device)
+    ws = torch.empty(hp.bbox_workspace_bytes(), dtype=torch.uint8, device=pts.device)
+    steps = max(10, args.steps)
+    for _ in range(3):
+        hp.hp_bbox(pts, box, ws, stream)
+        hp.hp_run_origin(pts, p, origin, buf, stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        hp.hp_bbox(pts, box, ws, stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        hp.hp_bbox(pts, box, ws, stream)
+        hp.hp_run_origin(pts, p, origin, buf, stream)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    got = hp.collect(buf)
+    want = oracle.auto(pts.cpu().numpy())
+    ok = (got["status"] == 0 and want["p"] == p and tuple(box.cpu().tolist()) == want["box"]
+          and got["k"] == want["k"] and np.array_equal(got["x"], want["x"])
+          and np.array_equal(got["clo"], want["clo"]) and np.array_equal(got["chi"], want["chi"])
+          and np.array_equal(got["hull"], want["hull"]))
+    bbox_ms = (t1 - t0) * 1e3 / steps
+    return {"workload": args.workload, "offset": list(off), "n": n, "p": p, "steps": steps,
+            "bbox_ms_avg": round(bbox_ms, 5), "bbox_gbs": round(8.0 * n / (bbox_ms * 1e-3) / 1e9, 1),
+            "gpoints_per_s_bbox_and_path": round(n * steps / (t2 - t1) / 1e9, 3),
+            "ms_per_step_bbox_and_path": round((t2 - t1) * 1e3 / steps, 5),
+            "parity_vs_oracle": bool(ok)}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -581,6 +630,7 @@ def main(argv=None):
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-auto", action="store_true", help="skip the bounding-box (steps 1 and 2) line")
     ap.add_argument("--regimes", default="uniform_100k_p1024,disc_2p28_p2p20,gaussian_2p28_p4096",
                     help="other single-cloud workloads timed beside the main one ('' for none)")
     ap.add_argument("--batch-clouds", type=int, default=4096)
@@ -634,6 +684,8 @@ def main(argv=None):
     out, host, p = bench_single(args, torch, hp, synth)
     if args.regimes:
         out["regimes"] = bench_regimes(args, torch, hp, synth)
+    if not args.no_auto:
+        out["auto_bbox"] = bench_auto(args, torch, hp, synth)
     if not args.no_batched:
         out["batched"] = bench_batched(args, torch, hp, synth)
     if not args.no_serve:

@@ -98,6 +98,29 @@ extern "C" {
                                        change L, the filter being rebuilt once
                                        half-way (for large p, n >= 16 p)         */
 
+/* Steps 1 and 2 of the proposed heuristic (the bounding box, then the
+ * translation that puts the points in [1, p]^2), on the device.
+ *
+ * hp_bbox: writes the bounding box of the n points to box[0..3] in device
+ * memory as (xmin, xmax, ymin, ymax); for n = 0 it writes (INT32_MAX,
+ * INT32_MIN, INT32_MAX, INT32_MIN).  One pass over the points (8n bytes).
+ * ws is caller-owned device memory of hp_bbox_workspace_bytes() bytes.
+ * Asynchronous on `stream`; errors as for hp_precondition.
+ *
+ * hp_run_origin: hp_run on the points translated by the origin (ox, oy):
+ * every point is read as (x - ox, y - oy), computed modulo 2^32, with no
+ * extra pass over the points.  All outputs (L, M, chain, hull) are those of
+ * the translated points, i.e. equal to hp_run on a translated copy; add
+ * (ox, oy) to map a vertex back.  With ox = xmin - 1, oy = ymin - 1 and
+ * p = max(xmax - xmin, ymax - ymin) + 1 from hp_bbox every point is in
+ * range; p must not exceed HP_P_MAX (the caller checks the extent). */
+int hp_bbox_workspace_bytes(size_t *bytes);
+int hp_bbox(const int32_t *pts, int64_t n, int32_t *box, void *ws, size_t ws_bytes, void *stream);
+int hp_run_origin(const int32_t *pts, int64_t n, int32_t p, int32_t ox, int32_t oy, int32_t *lo,
+                  int32_t *hi, uint64_t *mask, int32_t *cx, int32_t *clo, int32_t *chi,
+                  int32_t chain_cap, int32_t *hx, int32_t *hy, int32_t hull_cap, int32_t *info,
+                  void *ws, size_t ws_bytes, void *stream);
+
 /* Human-readable name of a status code (static string). */
 const char *hp_status_string(int code);
 

@@ -43,6 +43,10 @@ SIGNATURES = {
     "hp_precondition": (ctypes.c_int, [_vp, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _i32,
                                        _vp, _vp, _sz, _vp]),
     "hp_hull_workspace_bytes": (ctypes.c_int, [_i32, _szp]),
+    "hp_bbox_workspace_bytes": (ctypes.c_int, [_szp]),
+    "hp_bbox": (ctypes.c_int, [_vp, _i64, _vp, _vp, _sz, _vp]),
+    "hp_run_origin": (ctypes.c_int, [_vp, _i64, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp,
+                                     _i32, _vp, _vp, _sz, _vp]),
     "hp_hull": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp, _i32, _vp, _vp, _sz, _vp]),
     "hp_run": (ctypes.c_int, [_vp, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp,
                               _i32, _vp, _vp, _sz, _vp]),

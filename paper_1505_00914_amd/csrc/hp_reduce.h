@@ -20,6 +20,14 @@ namespace hp {
 // read exactly once, so the caches are better left to L and the partials
 // (measured: 4 % faster on 80 MB, 8 % on 2 GiB).  The column-window reduce
 // keeps plain loads: its W reads of one chunk group are meant to hit L2.
+// Translation by an origin (the heuristic's Step 2): a point is read as
+// (x - ox, y - oy), computed modulo 2^32 so that any int32 origin works; the
+// range check on the result then applies as usual.
+__device__ __forceinline__ int shift_by(int v, int o) { return (int)((unsigned)v - (unsigned)o); }
+__device__ __forceinline__ int4 shift_by(int4 q, int ox, int oy) {
+  return make_int4(shift_by(q.x, ox), shift_by(q.y, oy), shift_by(q.z, ox), shift_by(q.w, oy));
+}
+
 typedef int hp_v4i __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ int4 load_stream(const int4 *a) {
   const hp_v4i t = __builtin_nontemporal_load(reinterpret_cast<const hp_v4i *>(a));
@@ -30,7 +38,7 @@ __device__ __forceinline__ void stream_points(const int32_t *__restrict__ pts, i
                                               int2 *L, int64_t wg, int64_t nwg, bool &bad,
                                               unsigned c0 = 0, unsigned wc = 0,
                                               const int2 *filt = nullptr, int fshift = 0,
-                                              int2 *wq = nullptr) {
+                                              int2 *wq = nullptr, int ox = 0, int oy = 0) {
   int qn = 0;   // FILT: entries in this wave's queue
   // pts is 8-byte aligned (checked on the host); peel one point if the
   // vector body would otherwise start on an 8-byte boundary.
@@ -39,12 +47,14 @@ __device__ __forceinline__ void stream_points(const int32_t *__restrict__ pts, i
   const int64_t tail = head + 2 * nv;  // index of the odd last point, if any
   if (wg == 0 && threadIdx.x == 0) {
     if (head) {
-      if (LDS) fold_point_lds(L, p, pts[0], pts[1], bad, c0, wc);
-      else fold_point_global(L, p, pts[0], pts[1], bad);
+      const int x = shift_by(pts[0], ox), y = shift_by(pts[1], oy);
+      if (LDS) fold_point_lds(L, p, x, y, bad, c0, wc);
+      else fold_point_global(L, p, x, y, bad);
     }
     if (tail < n) {
-      if (LDS) fold_point_lds(L, p, pts[2 * tail], pts[2 * tail + 1], bad, c0, wc);
-      else fold_point_global(L, p, pts[2 * tail], pts[2 * tail + 1], bad);
+      const int x = shift_by(pts[2 * tail], ox), y = shift_by(pts[2 * tail + 1], oy);
+      if (LDS) fold_point_lds(L, p, x, y, bad, c0, wc);
+      else fold_point_global(L, p, x, y, bad);
     }
   }
   const int4 *v = reinterpret_cast<const int4 *>(pts + 2 * head);
@@ -58,7 +68,8 @@ __device__ __forceinline__ void stream_points(const int32_t *__restrict__ pts, i
   bool have = t0 + chunk <= nv;
   if (have) {
 #pragma unroll
-    for (int u = 0; u < VPT; ++u) q[u] = WIN ? v[t0 + u * BLOCK + threadIdx.x] : load_stream(&v[t0 + u * BLOCK + threadIdx.x]);
+    for (int u = 0; u < VPT; ++u)
+      q[u] = shift_by(WIN ? v[t0 + u * BLOCK + threadIdx.x] : load_stream(&v[t0 + u * BLOCK + threadIdx.x]), ox, oy);
   }
   while (have) {
     const int64_t t1 = t0 + step;
@@ -68,7 +79,8 @@ __device__ __forceinline__ void stream_points(const int32_t *__restrict__ pts, i
     gather<VPT, LDS, WIN, FILT>(L, p, q, b, bad, c0, wc, filt, fshift, wq, &qn);
     int4 qv[VPT];
 #pragma unroll
-    for (int u = 0; u < VPT; ++u) qv[u] = WIN ? v[tl + u * BLOCK + threadIdx.x] : load_stream(&v[tl + u * BLOCK + threadIdx.x]);
+    for (int u = 0; u < VPT; ++u)
+      qv[u] = shift_by(WIN ? v[tl + u * BLOCK + threadIdx.x] : load_stream(&v[tl + u * BLOCK + threadIdx.x]), ox, oy);
     apply<VPT, LDS, FILT>(L, b, wq, &qn);
 #pragma unroll
     for (int u = 0; u < VPT; ++u) q[u] = qv[u];
@@ -81,7 +93,7 @@ __device__ __forceinline__ void stream_points(const int32_t *__restrict__ pts, i
     for (int u = 0; u < VPT; ++u) {
       const int64_t idx = t0 + u * BLOCK + threadIdx.x;
       if (idx < nv) {
-        const int4 r = v[idx];
+        const int4 r = shift_by(v[idx], ox, oy);
         if (LDS) {
           fold_point_lds(L, p, r.x, r.y, bad, c0, wc);
           fold_point_lds(L, p, r.z, r.w, bad, c0, wc);
@@ -124,19 +136,21 @@ template <int BLOCK, int VPT, bool LDS, bool FILT = false>
 __device__ __forceinline__ void stream_points_dyn(const int32_t *__restrict__ pts, int64_t n, int p, int2 *L,
                                                   int64_t wg, int64_t nwg, bool &bad, const DynArgs &D,
                                                   int *s_slot, const int2 *filt = nullptr, int fshift = 0,
-                                                  int2 *wq = nullptr) {
+                                                  int2 *wq = nullptr, int ox = 0, int oy = 0) {
   int qn = 0;   // FILT: entries in this wave's queue
   const int64_t head = (n > 0 && ((uintptr_t)pts & 15) != 0) ? 1 : 0;
   const int64_t nv = (n - head) >> 1;
   const int64_t tail = head + 2 * nv;
   if (wg == 0 && threadIdx.x == 0) {
     if (head) {
-      if (LDS) fold_point_lds(L, p, pts[0], pts[1], bad);
-      else fold_point_global(L, p, pts[0], pts[1], bad);
+      const int x = shift_by(pts[0], ox), y = shift_by(pts[1], oy);
+      if (LDS) fold_point_lds(L, p, x, y, bad);
+      else fold_point_global(L, p, x, y, bad);
     }
     if (tail < n) {
-      if (LDS) fold_point_lds(L, p, pts[2 * tail], pts[2 * tail + 1], bad);
-      else fold_point_global(L, p, pts[2 * tail], pts[2 * tail + 1], bad);
+      const int x = shift_by(pts[2 * tail], ox), y = shift_by(pts[2 * tail + 1], oy);
+      if (LDS) fold_point_lds(L, p, x, y, bad);
+      else fold_point_global(L, p, x, y, bad);
     }
   }
   const int4 *v = reinterpret_cast<const int4 *>(pts + 2 * head);
@@ -202,7 +216,7 @@ __device__ __forceinline__ void stream_points_dyn(const int32_t *__restrict__ pt
   int4 q[VPT];
   if (cur >= 0) {
 #pragma unroll
-    for (int u = 0; u < VPT; ++u) q[u] = load_stream(&v[cur * chunk + u * BLOCK + threadIdx.x]);
+    for (int u = 0; u < VPT; ++u) q[u] = shift_by(load_stream(&v[cur * chunk + u * BLOCK + threadIdx.x]), ox, oy);
   }
   while (cur >= 0) {
     const int64_t tl = nx >= 0 ? nx : cur;
@@ -210,7 +224,7 @@ __device__ __forceinline__ void stream_points_dyn(const int32_t *__restrict__ pt
     gather<VPT, LDS, false, FILT>(L, p, q, b, bad, 0, 0, filt, fshift, wq, &qn);
     int4 qv[VPT];
 #pragma unroll
-    for (int u = 0; u < VPT; ++u) qv[u] = load_stream(&v[tl * chunk + u * BLOCK + threadIdx.x]);
+    for (int u = 0; u < VPT; ++u) qv[u] = shift_by(load_stream(&v[tl * chunk + u * BLOCK + threadIdx.x]), ox, oy);
     apply<VPT, LDS, FILT>(L, b, wq, &qn);
     ++folded;
     const int64_t nn = nx >= 0 ? take(next()) : -1;
@@ -224,7 +238,7 @@ __device__ __forceinline__ void stream_points_dyn(const int32_t *__restrict__ pt
     for (int u = 0; u < VPT; ++u) {
       const int64_t idx = part * chunk + u * BLOCK + threadIdx.x;
       if (idx < nv) {
-        const int4 r = v[idx];
+        const int4 r = shift_by(v[idx], ox, oy);
         if (LDS) {
           fold_point_lds(L, p, r.x, r.y, bad);
           fold_point_lds(L, p, r.z, r.w, bad);
@@ -264,7 +278,8 @@ __device__ __forceinline__ void reset_controls(const ResetArgs &R) {
 template <int BLOCK, int VPT, bool MERGE_ATOMIC>
 __global__ __launch_bounds__(BLOCK) void k_reduce_lds(const int32_t *__restrict__ pts, int64_t n,
                                                       int32_t p, int2 *__restrict__ out_L,
-                                                      int32_t *__restrict__ wg_err, ResetArgs R, DynArgs D) {
+                                                      int32_t *__restrict__ wg_err, ResetArgs R, DynArgs D,
+                                                      int2 org) {
   extern __shared__ int2 sL[];           // p pairs, then the flag word and the two grab slots
   int &s_bad = sL[p].x;
   int *s_slot = &sL[p].y;                // sL[p].y and sL[p + 1].x
@@ -273,8 +288,11 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_lds(const int32_t *__restrict_
   for (int c = threadIdx.x; c < p; c += BLOCK) sL[c] = make_int2(p + 1, -1);
   __syncthreads();
   bool bad = false;
-  if (D.ctr) stream_points_dyn<BLOCK, VPT, true>(pts, n, p, sL, blockIdx.x, gridDim.x, bad, D, s_slot);
-  else stream_points<BLOCK, VPT, true>(pts, n, p, sL, blockIdx.x, gridDim.x, bad);
+  if (D.ctr)
+    stream_points_dyn<BLOCK, VPT, true>(pts, n, p, sL, blockIdx.x, gridDim.x, bad, D, s_slot, nullptr, 0, nullptr,
+                                        org.x, org.y);
+  else
+    stream_points<BLOCK, VPT, true>(pts, n, p, sL, blockIdx.x, gridDim.x, bad, 0, 0, nullptr, 0, nullptr, org.x, org.y);
   if (bad) s_bad = 1;
   __syncthreads();
   if (MERGE_ATOMIC) {
@@ -308,7 +326,7 @@ template <int BLOCK, int VPT>
 __global__ __launch_bounds__(BLOCK) void k_reduce_window(const int32_t *__restrict__ pts, int64_t n,
                                                          int32_t p, int32_t W, int32_t wc,
                                                          uint32_t *__restrict__ out_part,
-                                                         int32_t *__restrict__ wg_err, ResetArgs R) {
+                                                         int32_t *__restrict__ wg_err, ResetArgs R, int2 org) {
   extern __shared__ int2 sL[];           // wc pairs, then one flag word
   int &s_bad = reinterpret_cast<int &>(sL[wc]);
   const int b = blockIdx.x, k = b >> 3;
@@ -320,7 +338,8 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_window(const int32_t *__restri
   for (int c = threadIdx.x; c < wc; c += BLOCK) sL[c] = make_int2(p + 1, -1);
   __syncthreads();
   bool bad = false;
-  stream_points<BLOCK, VPT, true, true>(pts, n, p, sL, cg, Gc, bad, c0, (unsigned)wc);
+  stream_points<BLOCK, VPT, true, true>(pts, n, p, sL, cg, Gc, bad, c0, (unsigned)wc, nullptr, 0, nullptr, org.x,
+                                        org.y);
   if (bad) s_bad = 1;
   __syncthreads();
   const int ncol = min(wc, p - (int)c0);
@@ -338,15 +357,19 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_window(const int32_t *__restri
 template <int BLOCK, int VPT>
 __global__ __launch_bounds__(BLOCK) void k_reduce_global(const int32_t *__restrict__ pts, int64_t n,
                                                          int32_t p, int2 *L,
-                                                         int32_t *__restrict__ wg_err, ResetArgs R, DynArgs D) {
+                                                         int32_t *__restrict__ wg_err, ResetArgs R, DynArgs D,
+                                                         int2 org) {
   __shared__ int s_bad;
   __shared__ int s_slot[2];
   reset_controls(R);
   if (threadIdx.x == 0) s_bad = 0;
   __syncthreads();
   bool bad = false;
-  if (D.ctr) stream_points_dyn<BLOCK, VPT, false>(pts, n, p, L, blockIdx.x, gridDim.x, bad, D, s_slot);
-  else stream_points<BLOCK, VPT, false>(pts, n, p, L, blockIdx.x, gridDim.x, bad);
+  if (D.ctr)
+    stream_points_dyn<BLOCK, VPT, false>(pts, n, p, L, blockIdx.x, gridDim.x, bad, D, s_slot, nullptr, 0, nullptr,
+                                         org.x, org.y);
+  else
+    stream_points<BLOCK, VPT, false>(pts, n, p, L, blockIdx.x, gridDim.x, bad, 0, 0, nullptr, 0, nullptr, org.x, org.y);
   if (bad) s_bad = 1;
   __syncthreads();
   if (threadIdx.x == 0) wg_err[blockIdx.x] = s_bad ? kErrRange : 0;
@@ -369,7 +392,7 @@ template <int BLOCK, int VPT>
 __global__ __launch_bounds__(BLOCK) void k_reduce_filtered(const int32_t *__restrict__ pts, int64_t n,
                                                            int32_t p, int2 *L, const int2 *__restrict__ F,
                                                            int32_t fshift, int32_t ngroups,
-                                                           int32_t *__restrict__ wg_err, DynArgs D) {
+                                                           int32_t *__restrict__ wg_err, DynArgs D, int2 org) {
   // LDS: ngroups filter pairs, the flag word and two grab slots (2 pairs),
   // then one queue of filt_queue_cap(VPT) entries per wave
   extern __shared__ int2 sF[];
@@ -381,9 +404,11 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_filtered(const int32_t *__rest
   __syncthreads();
   bool bad = false;
   if (D.ctr)
-    stream_points_dyn<BLOCK, VPT, false, true>(pts, n, p, L, blockIdx.x, gridDim.x, bad, D, s_slot, sF, fshift, wq);
+    stream_points_dyn<BLOCK, VPT, false, true>(pts, n, p, L, blockIdx.x, gridDim.x, bad, D, s_slot, sF, fshift, wq,
+                                               org.x, org.y);
   else
-    stream_points<BLOCK, VPT, false, false, true>(pts, n, p, L, blockIdx.x, gridDim.x, bad, 0, 0, sF, fshift, wq);
+    stream_points<BLOCK, VPT, false, false, true>(pts, n, p, L, blockIdx.x, gridDim.x, bad, 0, 0, sF, fshift, wq,
+                                                  org.x, org.y);
   if (bad) s_bad = 1;
   __syncthreads();
   if (threadIdx.x == 0) wg_err[blockIdx.x] = s_bad ? kErrRange : 0;

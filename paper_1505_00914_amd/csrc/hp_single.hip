@@ -66,6 +66,96 @@ __global__ __launch_bounds__(256) void k_filter_build(const int2 *__restrict__ L
 }
 
 // ---------------------------------------------------------------------------
+// Step 1 of the heuristic: the bounding box of the points.  One grid-stride
+// pass, four 16-byte loads in flight per lane; every workgroup writes its
+// (xmin, xmax, ymin, ymax) to part[workgroup] and k_bbox_fold folds them.
+// ---------------------------------------------------------------------------
+constexpr int kBoxBlock = 256;
+constexpr int kBoxMaxGrid = 2048;
+
+__device__ __forceinline__ void box_add(int4 &b, int x, int y) {
+  b.x = min(b.x, x);
+  b.y = max(b.y, x);
+  b.z = min(b.z, y);
+  b.w = max(b.w, y);
+}
+
+__device__ __forceinline__ int4 box_block(int4 b, int4 *s_part) {
+  // (xmin, xmax, ymin, ymax) over the workgroup, valid in thread 0
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    b.x = min(b.x, __shfl_xor(b.x, d, kWave));
+    b.y = max(b.y, __shfl_xor(b.y, d, kWave));
+    b.z = min(b.z, __shfl_xor(b.z, d, kWave));
+    b.w = max(b.w, __shfl_xor(b.w, d, kWave));
+  }
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  if (lane == 0) s_part[wave] = b;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int w = 1; w < kBoxBlock / kWave; ++w) {
+      const int4 o = s_part[w];
+      b.x = min(b.x, o.x);
+      b.y = max(b.y, o.y);
+      b.z = min(b.z, o.z);
+      b.w = max(b.w, o.w);
+    }
+  return b;
+}
+
+__global__ __launch_bounds__(kBoxBlock) void k_bbox(const int32_t *__restrict__ pts, int64_t n,
+                                                    int4 *__restrict__ part) {
+  __shared__ int4 s_part[kBoxBlock / kWave];
+  int4 b = make_int4(INT_MAX, INT_MIN, INT_MAX, INT_MIN);
+  const int64_t head = (n > 0 && ((uintptr_t)pts & 15) != 0) ? 1 : 0;
+  const int64_t nv = (n - head) >> 1;
+  const int4 *v = reinterpret_cast<const int4 *>(pts + 2 * head);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (head) box_add(b, pts[0], pts[1]);
+    if (head + 2 * nv < n) box_add(b, pts[2 * (head + 2 * nv)], pts[2 * (head + 2 * nv) + 1]);
+  }
+  const int64_t stride = (int64_t)gridDim.x * kBoxBlock;
+  int64_t i = (int64_t)blockIdx.x * kBoxBlock + threadIdx.x;
+  for (; i + 3 * stride < nv; i += 4 * stride) {
+    int4 q[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) q[u] = load_stream(&v[i + u * stride]);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      box_add(b, q[u].x, q[u].y);
+      box_add(b, q[u].z, q[u].w);
+    }
+  }
+  for (; i < nv; i += stride) {
+    const int4 q = load_stream(&v[i]);
+    box_add(b, q.x, q.y);
+    box_add(b, q.z, q.w);
+  }
+  b = box_block(b, s_part);
+  if (threadIdx.x == 0) part[blockIdx.x] = b;
+}
+
+__global__ __launch_bounds__(kBoxBlock) void k_bbox_fold(const int4 *__restrict__ part, int32_t nparts,
+                                                         int32_t *__restrict__ box) {
+  __shared__ int4 s_part[kBoxBlock / kWave];
+  int4 b = make_int4(INT_MAX, INT_MIN, INT_MAX, INT_MIN);
+  for (int i = threadIdx.x; i < nparts; i += kBoxBlock) {
+    const int4 o = part[i];
+    b.x = min(b.x, o.x);
+    b.y = max(b.y, o.y);
+    b.z = min(b.z, o.z);
+    b.w = max(b.w, o.w);
+  }
+  b = box_block(b, s_part);
+  if (threadIdx.x == 0) {
+    box[0] = b.x;
+    box[1] = b.y;
+    box[2] = b.z;
+    box[3] = b.w;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Finish: one workgroup per slab of 64 positions, of FB threads: 1024, or
 // 256 when there are many slabs (the launch is then bound by how fast the
 // dispatcher starts waves, not by the work of a slab).
@@ -1513,7 +1603,7 @@ static hipError_t launch(K kernel, dim3 grid, dim3 block, size_t lds, hipStream_
 
 template <int BLOCK, int VPT, bool ATOMIC>
 static hipError_t launch_lds(const Plan1 &P, const int32_t *pts, int64_t n, int32_t p, int2 *out,
-                             int32_t *wg_err, ResetArgs R, DynArgs D, hipStream_t s, hipEvent_t e0,
+                             int32_t *wg_err, ResetArgs R, DynArgs D, int2 org, hipStream_t s, hipEvent_t e0,
                              hipEvent_t e1) {
   static bool attr_set = false;
   if (!attr_set) {
@@ -1524,17 +1614,17 @@ static hipError_t launch_lds(const Plan1 &P, const int32_t *pts, int64_t n, int3
     attr_set = true;
   }
   return launch(k_reduce_lds<BLOCK, VPT, ATOMIC>, dim3(P.G), dim3(BLOCK), sizeof(int2) * ((size_t)p + 2), s,
-                e0, e1, pts, n, p, out, wg_err, R, D);
+                e0, e1, pts, n, p, out, wg_err, R, D, org);
 }
 
 template <int BLOCK, int VPT>
 static hipError_t launch_reduce(const Plan1 &P, const int32_t *pts, int64_t n, int32_t p, int2 *Lm,
-                                int2 *part, int32_t *wg_err, ResetArgs R, DynArgs D, hipStream_t s,
+                                int2 *part, int32_t *wg_err, ResetArgs R, DynArgs D, int2 org, hipStream_t s,
                                 hipEvent_t e0, hipEvent_t e1) {
   if (P.strategy == HP_STRATEGY_LDS)
-    return launch_lds<BLOCK, VPT, true>(P, pts, n, p, Lm, wg_err, R, D, s, e0, e1);
+    return launch_lds<BLOCK, VPT, true>(P, pts, n, p, Lm, wg_err, R, D, org, s, e0, e1);
   if (P.strategy == HP_STRATEGY_LDS_PARTIAL)
-    return launch_lds<BLOCK, VPT, false>(P, pts, n, p, part, wg_err, R, D, s, e0, e1);
+    return launch_lds<BLOCK, VPT, false>(P, pts, n, p, part, wg_err, R, D, org, s, e0, e1);
   if (P.strategy == HP_STRATEGY_WINDOW) {
     static bool attr_set = false;
     if (!attr_set) {
@@ -1545,18 +1635,18 @@ static hipError_t launch_reduce(const Plan1 &P, const int32_t *pts, int64_t n, i
       attr_set = true;
     }
     return launch(k_reduce_window<BLOCK, VPT>, dim3(P.G), dim3(BLOCK), sizeof(int2) * ((size_t)P.wc + 1), s,
-                  e0, e1, pts, n, p, P.W, P.wc, reinterpret_cast<uint32_t *>(part), wg_err, R);
+                  e0, e1, pts, n, p, P.W, P.wc, reinterpret_cast<uint32_t *>(part), wg_err, R, org);
   }
   return launch(k_reduce_global<BLOCK, VPT>, dim3(P.G), dim3(BLOCK), 0, s, e0, e1, pts, n, p, Lm,
-                wg_err, R, D);
+                wg_err, R, D, org);
 }
 
 static hipError_t dispatch_reduce(const Plan1 &P, const int32_t *pts, int64_t n, int32_t p, int2 *Lm,
-                                  int2 *part, int32_t *wg_err, ResetArgs R, DynArgs D, hipStream_t s,
+                                  int2 *part, int32_t *wg_err, ResetArgs R, DynArgs D, int2 org, hipStream_t s,
                                   hipEvent_t e0, hipEvent_t e1) {
 #define HP_CASE(B, V) \
   if (P.block == B && P.vpt == V)   \
-    return launch_reduce<B, V>(P, pts, n, p, Lm, part, wg_err, R, D, s, e0, e1);
+    return launch_reduce<B, V>(P, pts, n, p, Lm, part, wg_err, R, D, org, s, e0, e1);
   HP_CASE(1024, 4)
   HP_CASE(1024, 2)
   HP_CASE(1024, 8)
@@ -1579,7 +1669,8 @@ static hipError_t dispatch_reduce(const Plan1 &P, const int32_t *pts, int64_t n,
 template <int BLOCK, int VPT>
 static hipError_t launch_sampled(const Plan1 &P, const int32_t *pts, int64_t n, int32_t p, int2 *Lm,
                                  int2 *F, int fshift, int ngroups, int64_t ns, int64_t n1, int G1,
-                                 int32_t *wg_err, DynArgs D, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+                                 int32_t *wg_err, DynArgs D, int2 org, hipStream_t s, hipEvent_t e0,
+                                 hipEvent_t e1) {
   static bool attr_set = false;
   if (!attr_set) {
     const hipError_t e = hipFuncSetAttribute((const void *)k_reduce_filtered<BLOCK, VPT>,
@@ -1593,8 +1684,9 @@ static hipError_t launch_sampled(const Plan1 &P, const int32_t *pts, int64_t n, 
   DynArgs D0 = D;
   D0.ctr = nullptr;
   if (e0) hipExtLaunchKernelGGL((k_reduce_global<BLOCK, VPT>), dim3(G1), dim3(BLOCK), 0, s, e0, nullptr, 0, pts, ns, p,
-                                Lm, wg_err, R, D0);
-  else hipLaunchKernelGGL((k_reduce_global<BLOCK, VPT>), dim3(G1), dim3(BLOCK), 0, s, pts, ns, p, Lm, wg_err, R, D0);
+                                Lm, wg_err, R, D0, org);
+  else hipLaunchKernelGGL((k_reduce_global<BLOCK, VPT>), dim3(G1), dim3(BLOCK), 0, s, pts, ns, p, Lm, wg_err, R, D0,
+                          org);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const size_t lds = sizeof(int2) * ((size_t)ngroups + 2 + (size_t)(BLOCK / kWave) * filt_queue_cap(VPT));
@@ -1602,7 +1694,7 @@ static hipError_t launch_sampled(const Plan1 &P, const int32_t *pts, int64_t n, 
   hipLaunchKernelGGL(k_filter_build, dim3((ngroups + 3) / 4), dim3(256), 0, s, (const int2 *)Lm, p, fshift,
                      ngroups, F);
   hipLaunchKernelGGL((k_reduce_filtered<BLOCK, VPT>), dim3(P.G), dim3(BLOCK), lds, s, pts + 2 * ns, n1 - ns, p, Lm,
-                     (const int2 *)F, fshift, ngroups, wg_err + G1, D0);
+                     (const int2 *)F, fshift, ngroups, wg_err + G1, D0, org);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   // last pass: points [n1, n), with the filter of the first n1 points
@@ -1610,18 +1702,18 @@ static hipError_t launch_sampled(const Plan1 &P, const int32_t *pts, int64_t n, 
                      ngroups, F);
   if (e1) hipExtLaunchKernelGGL((k_reduce_filtered<BLOCK, VPT>), dim3(P.G), dim3(BLOCK), (uint32_t)lds, s, nullptr,
                                 e1, 0, pts + 2 * n1, n - n1, p, Lm, (const int2 *)F, fshift, ngroups,
-                                wg_err + G1 + P.G, D);
+                                wg_err + G1 + P.G, D, org);
   else hipLaunchKernelGGL((k_reduce_filtered<BLOCK, VPT>), dim3(P.G), dim3(BLOCK), lds, s, pts + 2 * n1, n - n1, p, Lm,
-                          (const int2 *)F, fshift, ngroups, wg_err + G1 + P.G, D);
+                          (const int2 *)F, fshift, ngroups, wg_err + G1 + P.G, D, org);
   return hipGetLastError();
 }
 
 static hipError_t dispatch_sampled(const Plan1 &P, const int32_t *pts, int64_t n, int32_t p, int2 *Lm, int2 *F,
                                    int fshift, int ngroups, int64_t ns, int64_t n1, int G1, int32_t *wg_err,
-                                   DynArgs D, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+                                   DynArgs D, int2 org, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
 #define HP_CASE(B, V) \
   if (P.block == B && P.vpt == V)   \
-    return launch_sampled<B, V>(P, pts, n, p, Lm, F, fshift, ngroups, ns, n1, G1, wg_err, D, s, e0, e1);
+    return launch_sampled<B, V>(P, pts, n, p, Lm, F, fshift, ngroups, ns, n1, G1, wg_err, D, org, s, e0, e1);
   HP_CASE(1024, 4)
   HP_CASE(1024, 2)
   HP_CASE(1024, 8)
@@ -1700,7 +1792,8 @@ static hipError_t launch_hull_levels(const TreeShape &T, int64_t positions, char
 int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *hi, uint64_t *mask,
                int32_t *cx, int32_t *clo, int32_t *chi, int32_t chain_cap, int32_t *hx, int32_t *hy,
                int32_t hull_cap, int32_t *info, void *ws, size_t ws_bytes, hipStream_t s,
-               bool do_hull) {
+               bool do_hull, int32_t ox, int32_t oy) {
+  const int2 org = make_int2(ox, oy);
   const Plan1 P = choose(n, p);
   const TreeShape T = make_tree(p);
   const Layout Y = make_layout(p, p, part_pairs_for(P, p), T);
@@ -1764,9 +1857,9 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
   timing_slot(&e0, &e1);
   if (sampled)
     e = dispatch_sampled(P, pts, n, p, Lm, reinterpret_cast<int2 *>(w + Y.filt), fshift, ngroups, ns, n1, G1,
-                         wg_err, D, s, e0, e1);
+                         wg_err, D, org, s, e0, e1);
   else
-    e = dispatch_reduce(P, pts, n, p, Lm, part, wg_err, R, D, s, e0, e1);
+    e = dispatch_reduce(P, pts, n, p, Lm, part, wg_err, R, D, org, s, e0, e1);
   if (e != hipSuccess) return set_error(HP_EDEVICE, "reduce launch: %s", hipGetErrorString(e));
 
   FinishArgs A;
@@ -1978,4 +2071,43 @@ extern "C" int hp_hull(const int32_t *cx, const int32_t *clo, const int32_t *chi
   e = launch_hull_levels(T, chain_cap, w, Y, H, false, s);
   if (e != hipSuccess) return set_error(HP_EDEVICE, "hull level launch: %s", hipGetErrorString(e));
   return HP_OK;
+}
+
+extern "C" int hp_bbox_workspace_bytes(size_t *bytes) {
+  if (!bytes) return set_error(HP_EINVAL, "bytes is NULL");
+  *bytes = sizeof(int4) * (size_t)kBoxMaxGrid;
+  return HP_OK;
+}
+
+extern "C" int hp_bbox(const int32_t *pts, int64_t n, int32_t *box, void *ws, size_t ws_bytes, void *stream) {
+  if (n < 0) return set_error(HP_EINVAL, "n = %lld < 0", (long long)n);
+  if (n > 0 && !pts) return set_error(HP_EINVAL, "pts is NULL");
+  if (pts && ((uintptr_t)pts & 7)) return set_error(HP_EINVAL, "pts is not 8-byte aligned");
+  if (!box) return set_error(HP_EINVAL, "box is NULL");
+  if (!ws || ws_bytes < sizeof(int4) * (size_t)kBoxMaxGrid)
+    return set_error(HP_ECAPACITY, "bounding-box workspace too small");
+  const int64_t nv = (n + 1) / 2;
+  const int64_t want = (nv + 4 * kBoxBlock - 1) / (4 * kBoxBlock);
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(kBoxMaxGrid, 4 * device_info().cus), want));
+  hipStream_t s = (hipStream_t)stream;
+  int4 *part = static_cast<int4 *>(ws);
+  hipLaunchKernelGGL(k_bbox, dim3(grid), dim3(kBoxBlock), 0, s, pts, n, part);
+  hipLaunchKernelGGL(k_bbox_fold, dim3(1), dim3(kBoxBlock), 0, s, (const int4 *)part, grid, box);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_error(HP_EDEVICE, "k_bbox launch: %s", hipGetErrorString(e));
+  return HP_OK;
+}
+
+extern "C" int hp_run_origin(const int32_t *pts, int64_t n, int32_t p, int32_t ox, int32_t oy, int32_t *lo,
+                             int32_t *hi, uint64_t *mask, int32_t *cx, int32_t *clo, int32_t *chi,
+                             int32_t chain_cap, int32_t *hx, int32_t *hy, int32_t hull_cap, int32_t *info,
+                             void *ws, size_t ws_bytes, void *stream) {
+  const int rc = check_common(pts, n, p, lo, hi, cx, clo, chi, chain_cap, info, ws);
+  if (rc != HP_OK) return rc;
+  if (!hx || !hy) return set_error(HP_EINVAL, "hull arrays must not be NULL");
+  const int64_t need = 2 * std::min<int64_t>(n, p);
+  if ((int64_t)hull_cap < need)
+    return set_error(HP_ECAPACITY, "hull_cap %d < 2 min(n, p) = %lld", hull_cap, (long long)need);
+  return run_single(pts, n, p, lo, hi, mask, cx, clo, chi, chain_cap, hx, hy, hull_cap, info, ws, ws_bytes,
+                    (hipStream_t)stream, true, ox, oy);
 }

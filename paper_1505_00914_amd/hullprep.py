@@ -13,7 +13,7 @@ from dataclasses import dataclass
 import torch
 
 from . import _lib
-from ._lib import (HP_INFO_H, HP_INFO_K, HP_INFO_S, HP_INFO_STATUS,  # noqa: F401
+from ._lib import (HP_EINVAL, HP_INFO_H, HP_INFO_K, HP_INFO_S, HP_INFO_STATUS,  # noqa: F401
                    HP_STRATEGY_AUTO, HP_STRATEGY_GLOBAL, HP_STRATEGY_LDS, HP_STRATEGY_LDS_PARTIAL,
                    HP_STRATEGY_SAMPLED, HP_STRATEGY_WINDOW, HullprepError)
 
@@ -135,6 +135,64 @@ def hp_run(points: torch.Tensor, p: int, buf: Buffers, stream=None) -> None:
               _ptr(buf.cx), _ptr(buf.clo), _ptr(buf.chi), buf.cx.numel(), _ptr(buf.hx),
               _ptr(buf.hy), buf.hx.numel(), _ptr(buf.info), _ptr(buf.ws), buf.ws.numel(),
               _stream(stream))
+
+
+def hp_run_origin(points: torch.Tensor, p: int, origin: tuple[int, int], buf: Buffers, stream=None) -> None:
+    """Enqueue the fused path on the points translated by ``origin`` (no sync)."""
+    n = _check_points(points)
+    _lib.call("hp_run_origin", _ptr(points), n, p, _to_i32(origin[0]), _to_i32(origin[1]), _ptr(buf.lo),
+              _ptr(buf.hi), _ptr(buf.mask), _ptr(buf.cx), _ptr(buf.clo), _ptr(buf.chi), buf.cx.numel(),
+              _ptr(buf.hx), _ptr(buf.hy), buf.hx.numel(), _ptr(buf.info), _ptr(buf.ws), buf.ws.numel(),
+              _stream(stream))
+
+
+def _to_i32(v: int) -> int:
+    """An int as the int32 with the same value modulo 2^32."""
+    return ((int(v) + (1 << 31)) % (1 << 32)) - (1 << 31)
+
+
+def bbox_workspace_bytes() -> int:
+    size = ctypes.c_size_t()
+    _lib.call("hp_bbox_workspace_bytes", ctypes.byref(size))
+    return size.value
+
+
+def hp_bbox(points: torch.Tensor, box: torch.Tensor, ws: torch.Tensor, stream=None) -> None:
+    """Enqueue step 1: box[0..3] = (xmin, xmax, ymin, ymax) (no sync)."""
+    n = _check_points(points)
+    if box.dtype != torch.int32 or box.numel() < 4 or not box.is_cuda:
+        raise ValueError("box must be an int32 device tensor of 4 entries")
+    _lib.call("hp_bbox", _ptr(points), n, _ptr(box), _ptr(ws), ws.numel(), _stream(stream))
+
+
+def bbox(points: torch.Tensor, stream=None) -> tuple[int, int, int, int]:
+    """(xmin, xmax, ymin, ymax) of the points, computed on the device."""
+    ws = torch.empty(bbox_workspace_bytes(), dtype=torch.uint8, device=points.device)
+    box = torch.empty(4, dtype=torch.int32, device=points.device)
+    hp_bbox(points, box, ws, stream)
+    torch.cuda.synchronize(points.device)
+    return tuple(int(v) for v in box.cpu().tolist())
+
+
+def run_auto(points: torch.Tensor, export_L: bool = True) -> dict:
+    """Steps 1 and 2, then the path: the bounding box on the device, p and the
+    origin from it, and the fused path on the translated points.  Outputs are
+    in translated coordinates; ``origin`` maps them back."""
+    n = _check_points(points)
+    if n == 0:
+        raise HullprepError(HP_EINVAL, "run_auto", "no points")
+    xmin, xmax, ymin, ymax = bbox(points)
+    p = max(xmax - xmin, ymax - ymin) + 1
+    if p > _lib.HP_P_MAX:
+        raise HullprepError(HP_EINVAL, "run_auto", f"extent {p} exceeds {_lib.HP_P_MAX}")
+    origin = (xmin - 1, ymin - 1)
+    buf = Buffers.allocate(n, p, points.device, export_L)
+    hp_run_origin(points, p, origin, buf)
+    out = collect(buf)
+    out["p"] = p
+    out["origin"] = origin
+    out["box"] = (xmin, xmax, ymin, ymax)
+    return out
 
 
 def collect(buf: Buffers) -> dict:

@@ -1,0 +1,111 @@
+"""Steps 1 and 2 on the device (bounding box, then the path on the points
+moved by an origin) against the oracle's steps 1 and 2, bit for bit."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1505_00914_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+I32 = np.iinfo(np.int32)
+
+
+@pytest.fixture(scope="module")
+def hp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1505_00914_amd import hullprep
+    yield hullprep
+    hullprep.set_strategy(0)
+
+
+def _moved(kind, n, p, seed, off):
+    base = synth.cloud(kind, n, p, seed).numpy().astype(np.int64)
+    return (base + np.asarray(off, np.int64)).astype(np.int32)
+
+
+def _compare_auto(got, want, label):
+    assert got["status"] == 0, f"{label}: status {got['status']}"
+    assert got["box"] == want["box"], f"{label}: box {got['box']} != {want['box']}"
+    assert got["p"] == want["p"], f"{label}: p {got['p']} != {want['p']}"
+    assert got["origin"] == want["origin"], f"{label}: origin"
+    assert got["k"] == want["k"], f"{label}: k {got['k']} != {want['k']}"
+    for key in ("lo", "hi", "mask", "x", "clo", "chi", "hull"):
+        assert np.array_equal(got[key], want[key]), f"{label}: {key} differs"
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 1000, 65_537, 3_000_001])
+@pytest.mark.parametrize("shift", [0, 1])
+def test_bbox(hp, n, shift):
+    rng = np.random.default_rng(n + shift)
+    pts = rng.integers(I32.min, I32.max, size=(n + shift, 2), dtype=np.int64, endpoint=True).astype(np.int32)
+    print(f"[case] bbox n={n} shift={shift}", flush=True)
+    dev = torch.from_numpy(pts).cuda()[shift:]
+    want = oracle.bbox(pts[shift:])
+    assert hp.bbox(dev) == want
+
+
+def test_bbox_single_extreme(hp):
+    """One extreme point in each corner of a large cloud, at various places."""
+    rng = np.random.default_rng(3)
+    pts = rng.integers(-1000, 1000, size=(1_000_003, 2)).astype(np.int32)
+    for i, (x, y) in zip([0, 17, 500_000, 1_000_002], [(I32.min, 0), (0, I32.max), (I32.max, 0), (0, I32.min)]):
+        pts[i] = (x, y)
+    print("[case] bbox extremes", flush=True)
+    assert hp.bbox(torch.from_numpy(pts).cuda()) == (I32.min, I32.max, I32.min, I32.max)
+
+
+@pytest.mark.parametrize("kind,n,p,seed,off", [
+    ("uniform", 100_000, 1024, 0, (0, 0)),
+    ("ellipsoids", 200_001, 4096, 2, (-123_456, 987_654)),
+    ("gaussian", 300_000, 4096, 4, (I32.min, I32.min)),
+    ("disc", 200_000, 65_536, 6, (I32.max - 65_536, -5)),
+    ("uniform", 1_000, 20_000, 7, (-7, -7)),
+    ("ellipsoids", 1_000_000, 16_384, 9, (1 << 30, -(1 << 30))),
+])
+def test_run_auto(hp, kind, n, p, seed, off):
+    pts = _moved(kind, n, p, seed, off)
+    print(f"[case] run_auto {kind} n={n} p={p} off={off}", flush=True)
+    want = oracle.auto(pts)
+    dev = torch.from_numpy(pts).cuda()
+    strategies = (1, 2, 3, 4, 5) if want["p"] <= hp.lds_max_p() else (2, 4, 5)
+    for s in strategies:
+        hp.set_strategy(s)
+        _compare_auto(hp.run_auto(dev), want, f"{kind}-{n}/strategy{s}")
+    hp.set_strategy(0)
+
+
+@pytest.mark.parametrize("pts", [
+    [(5, 5)],
+    [(-3, 8), (-3, 8), (-3, 8)],
+    [(I32.min, I32.min), (I32.min + 10, I32.min + 3)],
+    [(I32.max, I32.max), (I32.max - 2, I32.max - 9), (I32.max - 1, I32.max)],
+])
+def test_run_auto_small(hp, pts):
+    a = np.asarray(pts, np.int32)
+    print(f"[case] run_auto small {pts}", flush=True)
+    _compare_auto(hp.run_auto(torch.from_numpy(a).cuda()), oracle.auto(a), str(pts))
+
+
+def test_run_auto_extent_too_large(hp):
+    a = np.asarray([(I32.min, 0), (I32.max, 0)], np.int32)
+    with pytest.raises(hp.HullprepError):
+        hp.run_auto(torch.from_numpy(a).cuda())
+
+
+def test_origin_equals_translated_copy(hp):
+    """hp_run_origin on the raw points equals hp_run on a moved copy."""
+    pts = _moved("ellipsoids", 500_000, 8192, 21, (-40_000, 77))
+    origin = (int(pts[:, 0].min()) - 1, int(pts[:, 1].min()) - 1)
+    moved = pts.astype(np.int64) - np.asarray(origin)
+    assert moved.min() == 1
+    p = int(moved.max())
+    print(f"[case] origin vs copy p={p}", flush=True)
+    ref = hp.run(torch.from_numpy(moved.astype(np.int32)).cuda(), p)
+    buf = hp.Buffers.allocate(pts.shape[0], p, "cuda")
+    hp.hp_run_origin(torch.from_numpy(pts).cuda(), p, origin, buf)
+    got = hp.collect(buf)
+    for key in ("status", "k", "s", "h", "lo", "hi", "mask", "x", "clo", "chi", "hull"):
+        assert np.array_equal(np.asarray(got[key]), np.asarray(ref[key])), key
