@@ -348,3 +348,88 @@ int or_translate(const int32_t *pts, int64_t n, const int32_t *box, int32_t *out
     return OR_OK;
 }
 
+/* ---------------------------------------------------------------------------
+ * Discussion, "Extraction using an array of bits" and "Extraction using a
+ * tree structure", with w = 64.
+ *
+ * Array: setting column i is M[(i-1) >> 6] |= 1 << ((i-1) & 63), and
+ * extraction is or_extract above.
+ *
+ * Tree: level 0 is the array M.  A word of level k+1 holds one bit per word
+ * of level k, set when that word is non-zero, so a group of 64 words of one
+ * level maps to one word of the next.  Levels are added until a level holds
+ * a single word (for p = 2^24: 262144, 4096, 64 and 1 words, 266305 in all).
+ * The levels are stored one after another, level 0 first.  An insert sets the
+ * bit of the column at every level (the h + 1 steps of the text); extraction
+ * walks down from the top word, visiting the set bits of each word in
+ * ascending order with the Table I loop, so the columns come out ascending
+ * and empty words are never visited.
+ * ------------------------------------------------------------------------- */
+int32_t or_tree_levels(int32_t p, int64_t *offset)
+{
+    if (p < 1 || p > OR_PMAX) return OR_EINVAL;
+    int32_t levels = 0;
+    int64_t words = ((int64_t)p + 63) / 64, at = 0;
+    for (;;) {
+        if (offset != NULL) offset[levels] = at;
+        at += words;
+        ++levels;
+        if (words == 1) break;
+        words = (words + 63) / 64;
+    }
+    if (offset != NULL) offset[levels] = at;
+    return levels;
+}
+
+int or_array_insert(int32_t p, const int32_t *cols, int64_t s, uint64_t *M)
+{
+    if (p < 1 || p > OR_PMAX || s < 0 || M == NULL || (s > 0 && cols == NULL)) return OR_EINVAL;
+    for (int64_t j = 0; j < s; ++j)
+        if (cols[j] < 1 || cols[j] > p) return OR_ERANGE;
+    for (int64_t j = 0; j < s; ++j) {
+        int64_t i = cols[j];
+        M[(i - 1) >> 6] |= (uint64_t)1 << ((i - 1) & 63);
+    }
+    return OR_OK;
+}
+
+int or_tree_insert(int32_t p, const int32_t *cols, int64_t s, uint64_t *T)
+{
+    int64_t offset[8];
+    int32_t levels = or_tree_levels(p, offset);
+    if (levels < 0 || s < 0 || T == NULL || (s > 0 && cols == NULL)) return OR_EINVAL;
+    for (int64_t j = 0; j < s; ++j)
+        if (cols[j] < 1 || cols[j] > p) return OR_ERANGE;
+    for (int64_t j = 0; j < s; ++j) {
+        int64_t bit = cols[j] - 1;              /* bit index within level 0 */
+        for (int32_t k = 0; k < levels; ++k) {
+            T[offset[k] + (bit >> 6)] |= (uint64_t)1 << (bit & 63);
+            bit >>= 6;                          /* the word index becomes the bit index above */
+        }
+    }
+    return OR_OK;
+}
+
+static int32_t or_tree_visit(const uint64_t *T, const int64_t *offset, int32_t level, int64_t word,
+                             int32_t *cols, int32_t k)
+{
+    int32_t pos[64];
+    int32_t c = or_ctz_positions(T[offset[level] + word], pos);
+    for (int32_t t = 0; t < c; ++t) {
+        int64_t child = word * 64 + pos[t];
+        if (level == 0)
+            cols[k++] = (int32_t)(child + 1);
+        else
+            k = or_tree_visit(T, offset, level - 1, child, cols, k);
+    }
+    return k;
+}
+
+int32_t or_tree_extract(const uint64_t *T, int32_t p, int32_t *cols)
+{
+    int64_t offset[8];
+    int32_t levels = or_tree_levels(p, offset);
+    if (levels < 0 || T == NULL || cols == NULL) return OR_EINVAL;
+    return or_tree_visit(T, offset, levels - 1, 0, cols, 0);
+}
+

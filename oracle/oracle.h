@@ -93,6 +93,19 @@ int or_bbox(const int32_t *pts, int64_t n, int32_t *box);
  * 2^31 - 2.  out needs 2n entries. */
 int or_translate(const int32_t *pts, int64_t n, const int32_t *box, int32_t *out, int32_t *p);
 
+/* Bit array and w-ary tree (Discussion, extraction by an array of bits and
+ * by a tree structure; w = 64).  or_tree_levels writes the word offset of
+ * each level (level 0 = M) and the total word count at offset[levels] (offset
+ * needs room for 8 entries) and returns the level count.  The inserts OR the
+ * 1-based columns cols[0..s) into zeroed storage (M: ceil(p/64) words; T:
+ * offset[levels] words); OR_ERANGE, with nothing written, if any column lies
+ * outside [1, p].  or_tree_extract walks the tree from its top word and
+ * writes the set columns in ascending order; returns their count. */
+int32_t or_tree_levels(int32_t p, int64_t *offset);
+int or_array_insert(int32_t p, const int32_t *cols, int64_t s, uint64_t *M);
+int or_tree_insert(int32_t p, const int32_t *cols, int64_t s, uint64_t *T);
+int32_t or_tree_extract(const uint64_t *T, int32_t p, int32_t *cols);
+
 #ifdef __cplusplus
 }
 #endif

@@ -67,6 +67,15 @@ def _load(path: str) -> ctypes.CDLL:
     lib.or_hull_chain.restype = ctypes.c_int32
     lib.or_hull_full.argtypes = [_i32p, ctypes.c_int64, _i32p, _i32p]
     lib.or_hull_full.restype = ctypes.c_int64
+    _i64p = ctypes.POINTER(ctypes.c_int64)
+    lib.or_tree_levels.argtypes = [ctypes.c_int32, _i64p]
+    lib.or_tree_levels.restype = ctypes.c_int32
+    lib.or_array_insert.argtypes = [ctypes.c_int32, _i32p, ctypes.c_int64, _u64p]
+    lib.or_array_insert.restype = ctypes.c_int
+    lib.or_tree_insert.argtypes = [ctypes.c_int32, _i32p, ctypes.c_int64, _u64p]
+    lib.or_tree_insert.restype = ctypes.c_int
+    lib.or_tree_extract.argtypes = [_u64p, ctypes.c_int32, _i32p]
+    lib.or_tree_extract.restype = ctypes.c_int32
     lib.or_bbox.argtypes = [_i32p, ctypes.c_int64, _i32p]
     lib.or_bbox.restype = ctypes.c_int
     lib.or_translate.argtypes = [_i32p, ctypes.c_int64, _i32p, _i32p, _i32p]
@@ -228,4 +237,43 @@ def auto(pts, lib: str | None = None) -> dict:
     r["box"] = box
     r["origin"] = (box[0] - 1, box[2] - 1)
     return r
+
+
+def tree_levels(p: int, lib: str | None = None) -> list[int]:
+    """Word offsets of the tree's levels (level 0 = M), then the total."""
+    off = np.zeros(8, np.int64)
+    n = _lib(lib).or_tree_levels(p, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    if n < 0:
+        raise OracleError(f"or_tree_levels failed: {n}")
+    return off[:n + 1].tolist()
+
+
+def array_insert(cols, p: int, lib: str | None = None) -> np.ndarray:
+    """The bit array M with the given 1-based columns set."""
+    c = np.ascontiguousarray(np.asarray(cols, np.int32).reshape(-1))
+    M = np.zeros((p + 63) // 64, np.uint64)
+    rc = _lib(lib).or_array_insert(p, _ptr(c), c.shape[0], _ptr(M, _u64p))
+    if rc != OR_OK:
+        raise OracleError(f"or_array_insert failed: {rc}")
+    return M
+
+
+def tree_insert(cols, p: int, lib: str | None = None) -> np.ndarray:
+    """Every level of the w-ary tree with the given columns inserted."""
+    c = np.ascontiguousarray(np.asarray(cols, np.int32).reshape(-1))
+    T = np.zeros(tree_levels(p, lib)[-1], np.uint64)
+    rc = _lib(lib).or_tree_insert(p, _ptr(c), c.shape[0], _ptr(T, _u64p))
+    if rc != OR_OK:
+        raise OracleError(f"or_tree_insert failed: {rc}")
+    return T
+
+
+def tree_extract(T: np.ndarray, p: int, lib: str | None = None) -> np.ndarray:
+    """Set columns of a tree, ascending, by descent from the top word."""
+    t = np.ascontiguousarray(T, np.uint64)
+    cols = np.empty(p, np.int32)
+    k = _lib(lib).or_tree_extract(_ptr(t, _u64p), p, _ptr(cols))
+    if k < 0:
+        raise OracleError(f"or_tree_extract failed: {k}")
+    return cols[:k]
 

@@ -366,11 +366,74 @@ def pin_steps12(lib=None):
     return errs
 
 
+@_safe
+def pin_bitsets(lib=None):
+    """The bit array and the w-ary tree of the Discussion: the tree sizes the
+    text gives for p = 2^24, the gap example's word 10101, the block-index
+    example one level further up, and both extractions against numpy's
+    sorted unique columns for random sets (uniform and clustered)."""
+    errs = []
+    off = oracle.tree_levels(1 << 24, lib=lib)
+    # p = 2^24 with 64-bit words: height h = 3 (four levels), 266305 words in
+    # all against the array's 2^18 = 262144, an overhead of 4161 words
+    if len(off) - 1 != 4 or off[-1] != 266305 or off[1] != 262144 or off[-1] - off[1] != 4161:
+        errs.append(f"tree levels for 2^24: {off}")
+    if oracle.tree_levels(64, lib=lib) != [0, 1] or oracle.tree_levels(65, lib=lib) != [0, 2, 3]:
+        errs.append("tree levels for p = 64 / 65")
+    gap = [1, 3, 5]
+    if int(oracle.array_insert(gap, 5, lib=lib)[0]) != 0b10101:
+        errs.append("gap example word is not 10101")
+    if oracle.tree_extract(oracle.tree_insert(gap, 5, lib=lib), 5, lib=lib).tolist() != gap:
+        errs.append("gap example through the tree")
+    f = fixtures.read("block_index.txt")
+    i = int(f["i"][0])
+    b64, pb64 = (int(v) for v in f["w64"])
+    p = i + 100
+    T = oracle.tree_insert([i], p, lib=lib)
+    off = oracle.tree_levels(p, lib=lib)
+    nz = np.nonzero(T)[0].tolist()
+    # level 0: word 1612 bit 54; level 1: word 1612 >> 6 = 25, bit 1612 & 63 = 12;
+    # level 2 (the top): word 0, bit 25
+    want = {off[0] + b64: 1 << pb64, off[1] + (b64 >> 6): 1 << (b64 & 63), off[2]: 1 << (b64 >> 6)}
+    if {k: int(T[k]) for k in nz} != want or len(off) != 4:
+        errs.append(f"block-index example in the tree: {nz}")
+    rng = np.random.default_rng(24)
+    for trial, p in enumerate([1, 5, 63, 64, 65, 4095, 4097, 70_000, (1 << 18) + 3]):
+        for kind in ("uniform", "clustered"):
+            if kind == "uniform":
+                cols = rng.integers(1, p + 1, size=int(rng.integers(0, 2 * p + 1)))
+            else:
+                starts = rng.integers(1, p + 1, size=4)
+                cols = np.concatenate([np.arange(a, min(p, a + 100) + 1) for a in starts])
+                rng.shuffle(cols)
+            want = np.unique(cols).tolist()
+            M = oracle.array_insert(cols, p, lib=lib)
+            if oracle.extract(M, p, lib=lib).tolist() != want:
+                errs.append(f"p={p} {kind}: array extraction")
+            T = oracle.tree_insert(cols, p, lib=lib)
+            off = oracle.tree_levels(p, lib=lib)
+            if not np.array_equal(T[:off[1]], M):
+                errs.append(f"p={p} {kind}: tree level 0 differs from the array")
+            for k in range(1, len(off) - 1):
+                below = T[off[k - 1]:off[k]]
+                bits = [(int(T[off[k] + (j >> 6)]) >> (j & 63)) & 1 for j in range(below.shape[0])]
+                if bits != [int(v != 0) for v in below]:
+                    errs.append(f"p={p} {kind}: level {k} is not the non-zero map of level {k - 1}")
+            if oracle.tree_extract(T, p, lib=lib).tolist() != want:
+                errs.append(f"p={p} {kind}: tree extraction")
+    try:
+        oracle.tree_insert([0], 5, lib=lib)
+        errs.append("column 0 accepted")
+    except oracle.OracleError:
+        pass
+    return errs
+
+
 ALL_PINS = [pin_worked_example, pin_gap_example, pin_table1, pin_block_index,
             pin_closed_forms, pin_brute_random, pin_exhaustive_p3, pin_qhull,
-            pin_appendix, pin_invariants, pin_metamorphic, pin_errors, pin_steps12]
+            pin_appendix, pin_invariants, pin_metamorphic, pin_errors, pin_steps12, pin_bitsets]
 
 # the cheap pins, run first against planted mistakes
 FAST_PINS = [pin_worked_example, pin_gap_example, pin_table1, pin_block_index,
-             pin_closed_forms, pin_errors, pin_brute_random, pin_steps12]
+             pin_closed_forms, pin_errors, pin_brute_random, pin_steps12, pin_bitsets]
 

@@ -5,6 +5,7 @@ flipped comparison, a swapped operand, a dropped term, an off-by-one.  The
 real ``oracle.c`` is never modified; each mutant is compiled from a patched
 copy into a temporary directory, on the CPU.
 """
+import multiprocessing
 import os
 import shutil
 import subprocess
@@ -42,6 +43,11 @@ MUTANTS = {
     "translate-off-by-one": ("out[2 * j] = (int32_t)((int64_t)pts[2 * j] - box[0] + 1);",
                              "out[2 * j] = (int32_t)((int64_t)pts[2 * j] - box[0]);"),
     "side-from-x-only": ("int64_t side = ex > ey ? ex : ey;", "int64_t side = ex;"),
+    "tree-bit-not-shifted": ("            bit >>= 6;                          /* the word index becomes the bit index above */",
+                             "            bit >>= 5;                          /* the word index becomes the bit index above */"),
+    "tree-child-index": ("int64_t child = word * 64 + pos[t];", "int64_t child = word * 63 + pos[t];"),
+    "tree-one-level-short": ("        if (words == 1) break;\n        words = (words + 63) / 64;",
+                             "        words = (words + 63) / 64;\n        if (words == 1) break;"),
     "chain-skips-last": ("for (int32_t i = 1; i <= p; ++i) {\n        if (or_valid(lo[i - 1], hi[i - 1], p)) {\n            x[k] = i;",
                          "for (int32_t i = 1; i < p; ++i) {\n        if (or_valid(lo[i - 1], hi[i - 1], p)) {\n            x[k] = i;"),
 }
@@ -61,11 +67,25 @@ def _build_mutant(tmp_path, name, old, new):
     return str(out)
 
 
+def _pins_catch(lib: str) -> None:
+    """Child process: exit 0 as soon as a pin fails on ``lib``, 1 if none does."""
+    for pin in oracle_pins.FAST_PINS + [p for p in oracle_pins.ALL_PINS if p not in oracle_pins.FAST_PINS]:
+        if pin(lib):
+            os._exit(0)
+    os._exit(1)
+
+
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_mutant_is_caught(tmp_path, name):
     old, new = MUTANTS[name]
     lib = _build_mutant(tmp_path, name, old, new)
-    for pin in oracle_pins.FAST_PINS + [p for p in oracle_pins.ALL_PINS if p not in oracle_pins.FAST_PINS]:
-        if pin(lib):
-            return
-    pytest.fail(f"no pin catches mutant {name}")
+    # a mutant that writes out of bounds may crash the process that runs it:
+    # the pins run in a forked child, and a crash counts as a catch
+    proc = multiprocessing.get_context("fork").Process(target=_pins_catch, args=(lib,))
+    proc.start()
+    proc.join(300)
+    if proc.is_alive():
+        proc.kill()
+        proc.join()
+        pytest.fail(f"pins on mutant {name} did not finish")
+    assert proc.exitcode != 1, f"no pin catches mutant {name}"
