@@ -620,6 +620,66 @@ def bench_auto(args, torch, hp, synth) -> dict:
             "parity_vs_oracle": bool(ok)}
 
 
+def bench_bits(args, torch, hp) -> dict:
+    """The text's bit-vector experiment on the device: s distinct columns of
+    p = 2^24, in random order, inserted into the bit array or the w-ary tree
+    (after a clear) and then extracted in ascending order, for densities
+    s/p from 5 % to 85 %.  Times are per phase, averaged over the steps."""
+    import numpy as np
+
+    import oracle
+
+    p = 1 << 24
+    steps = max(5, min(args.steps, 50))
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    g = torch.Generator(device=dev)
+    g.manual_seed(24)
+    perm = (torch.randperm(p, generator=g, device=dev) + 1).to(torch.int32)
+    out = torch.empty(p, dtype=torch.int32, device=dev)
+    info = torch.zeros(2, dtype=torch.int32, device=dev)
+    ws = torch.empty(hp.bitset_extract_workspace_bytes(p), dtype=torch.uint8, device=dev)
+    rows = []
+    for density in (0.05, 0.25, 0.45, 0.65, 0.85):
+        s = int(density * p)
+        cols = perm[:s].contiguous()
+        want = None
+        row = {"density": density, "s": s}
+        for tree in (False, True):
+            words = torch.empty(hp.bitset_words(p, tree), dtype=torch.int64, device=dev)
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3 * steps)]
+            for i in range(2):
+                hp.hp_bitset_clear(words, stream)
+                hp.hp_bitset_insert(cols, p, tree, words, info, stream)
+                hp.hp_bitset_extract(words, p, tree, out, info, ws, stream)
+            for i in range(steps):
+                ev[3 * i].record(stream)
+                hp.hp_bitset_clear(words, stream)
+                hp.hp_bitset_insert(cols, p, tree, words, info, stream)
+                ev[3 * i + 1].record(stream)
+                hp.hp_bitset_extract(words, p, tree, out, info, ws, stream)
+                ev[3 * i + 2].record(stream)
+            torch.cuda.synchronize()
+            ins = sum(ev[3 * i].elapsed_time(ev[3 * i + 1]) for i in range(steps)) / steps
+            ext = sum(ev[3 * i + 1].elapsed_time(ev[3 * i + 2]) for i in range(steps)) / steps
+            got = out[:s].cpu().numpy()
+            if want is None:
+                want = oracle.extract(oracle.array_insert(cols.cpu().numpy(), p), p)
+            ok = int(info[0]) == 0 and int(info[1]) == s and np.array_equal(got, want)
+            key = "tree" if tree else "array"
+            row[key] = {"insert_us": round(ins * 1e3, 2), "extract_us": round(ext * 1e3, 2),
+                        "total_us": round((ins + ext) * 1e3, 2),
+                        "ns_per_set_bit": round((ins + ext) * 1e6 / s, 4), "parity_vs_oracle": bool(ok)}
+        rows.append(row)
+    # least-squares slope of total time against s, as the text regresses its timings
+    fit = {}
+    for key in ("array", "tree"):
+        x = np.array([r["s"] for r in rows], float)
+        y = np.array([r[key]["total_us"] * 1e-6 for r in rows])
+        fit[key + "_seconds_per_set_bit"] = float(np.polyfit(x, y, 1)[0])
+    return {"p": p, "steps": steps, "rows": rows, "fit": fit}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -631,6 +691,7 @@ def main(argv=None):
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-auto", action="store_true", help="skip the bounding-box (steps 1 and 2) line")
+    ap.add_argument("--no-bits", action="store_true", help="skip the bit array / tree extraction line")
     ap.add_argument("--regimes", default="uniform_100k_p1024,disc_2p28_p2p20,gaussian_2p28_p4096",
                     help="other single-cloud workloads timed beside the main one ('' for none)")
     ap.add_argument("--batch-clouds", type=int, default=4096)
@@ -686,6 +747,8 @@ def main(argv=None):
         out["regimes"] = bench_regimes(args, torch, hp, synth)
     if not args.no_auto:
         out["auto_bbox"] = bench_auto(args, torch, hp, synth)
+    if not args.no_bits:
+        out["bit_extraction"] = bench_bits(args, torch, hp)
     if not args.no_batched:
         out["batched"] = bench_batched(args, torch, hp, synth)
     if not args.no_serve:

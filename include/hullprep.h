@@ -121,6 +121,35 @@ int hp_run_origin(const int32_t *pts, int64_t n, int32_t p, int32_t ox, int32_t 
                   int32_t chain_cap, int32_t *hx, int32_t *hy, int32_t hull_cap, int32_t *info,
                   void *ws, size_t ws_bytes, void *stream);
 
+/* The bit array M and its w-ary tree, w = 64 (Discussion, extraction by an
+ * array of bits and by a tree structure).
+ *
+ * Storage is caller-owned DEVICE memory of hp_bitset_words(p, tree) uint64
+ * words.  Level 0 is the array: column i (1-based) is bit (i-1) & 63 of word
+ * (i-1) >> 6, the layout of the M that hp_precondition and hp_run write.
+ * With tree != 0, level k+1 follows level k and holds one bit per word of
+ * level k, set when that word is non-zero; the last level has one word.
+ *
+ * hp_bitset_clear: zero nwords words (a fill kernel, safe under graph
+ * capture).  hp_bitset_insert: OR the columns cols[0..s) into zeroed (or
+ * consistent) storage; with a tree the levels above are set as well.  info
+ * is a DEVICE int32[2]: [HP_INFO_STATUS] = HP_OK, or HP_ERANGE when a column
+ * lies outside [1, p] (such columns are skipped).  Duplicates are allowed.
+ * hp_bitset_extract: the set columns, ascending, into cols[0..cap);
+ * info[HP_INFO_K] = their count and info[HP_INFO_STATUS] = HP_ECAPACITY
+ * when the count exceeds cap (the first cap columns are still written).
+ * With a tree, a level-0 word whose level-1 bit is clear is not read.
+ * Bits of level 0 beyond column p are ignored.  ws is caller-owned device
+ * memory of hp_bitset_extract_workspace_bytes(p) bytes.  All of it is
+ * asynchronous on `stream`; argument errors return synchronously. */
+int hp_bitset_words(int32_t p, int32_t tree, int64_t *words);
+int hp_bitset_clear(uint64_t *words, int64_t nwords, void *stream);
+int hp_bitset_insert(const int32_t *cols, int64_t s, int32_t p, int32_t tree, uint64_t *words, int32_t *info,
+                     void *stream);
+int hp_bitset_extract_workspace_bytes(int32_t p, size_t *bytes);
+int hp_bitset_extract(const uint64_t *words, int32_t p, int32_t tree, int32_t *cols, int32_t cap, int32_t *info,
+                      void *ws, size_t ws_bytes, void *stream);
+
 /* Human-readable name of a status code (static string). */
 const char *hp_status_string(int code);
 

@@ -1,0 +1,280 @@
+// hp_bits.hip -- the bit array M and its w-ary tree on the device (w = 64):
+// inserts of columns, and extraction of the set columns in ascending order.
+//
+// Layout (Discussion, extraction by an array of bits and by a tree
+// structure): level 0 is the array itself, column i at bit (i-1) & 63 of
+// word (i-1) >> 6.  A word of level k+1 holds one bit per word of level k,
+// set when that word is non-zero; levels are added until one has a single
+// word, and they are stored one after another, level 0 first.
+//
+// Insert: one device-scope OR per column into its level-0 word.  In the
+// tree, the thread whose OR found the word empty (exactly one per word) goes
+// on to the level above, so the upper levels see one OR per non-empty word,
+// not one per column.
+//
+// Extraction: three launches.  k_bits_count gives each workgroup of 128
+// level-0 words its number of set bits, k_bits_scan turns those counts into
+// output offsets, and k_bits_write expands the set bits of each word with
+// the count-trailing-zeros loop of Table I into LDS and then copies the
+// workgroup's columns out with coalesced stores.  With the tree, each wave
+// reads the level-1 word over its 64 level-0 words first and reads only the
+// non-empty ones; a wave whose level-1 word is zero reads nothing.
+#include <climits>
+
+#include "hp_host.h"
+#include "hp_device.h"
+
+namespace hp {
+
+constexpr int kBitsBlock = 128;         // level-0 words per workgroup (two waves)
+constexpr int kBitsScanBlock = 1024;
+constexpr int kBitsMaxLevels = 8;
+
+struct BitLevels {
+  int64_t off[kBitsMaxLevels + 1];      // word offset of each level, total at [levels]
+  int32_t levels;
+};
+
+static BitLevels bit_levels(int32_t p, int32_t tree) {
+  BitLevels L{};
+  int64_t words = ((int64_t)p + 63) / 64, at = 0;
+  L.levels = 0;
+  for (;;) {
+    L.off[L.levels++] = at;
+    at += words;
+    if (!tree || words == 1) break;
+    words = (words + 63) / 64;
+  }
+  L.off[L.levels] = at;
+  return L;
+}
+
+__global__ void k_bits_fill(uint64_t *__restrict__ w, int64_t nwords) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += stride) w[i] = 0;
+}
+
+__global__ void k_bits_info(int32_t *info) {
+  info[HP_INFO_STATUS] = HP_OK;
+  info[HP_INFO_K] = 0;
+}
+
+template <bool TREE>
+__global__ __launch_bounds__(256) void k_bits_insert(const int32_t *__restrict__ cols, int64_t s, int32_t p,
+                                                     uint64_t *__restrict__ words, BitLevels L,
+                                                     int32_t *__restrict__ info) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  bool bad = false;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < s; j += stride) {
+    const int32_t c = cols[j];
+    if ((unsigned)(c - 1) >= (unsigned)p) {
+      bad = true;
+      continue;
+    }
+    uint64_t bit = (uint64_t)(c - 1);
+    unsigned long long old = atomicOr((unsigned long long *)&words[bit >> 6], 1ull << (bit & 63));
+    if (TREE) {
+      for (int k = 1; k < L.levels && old == 0; ++k) {
+        bit >>= 6;
+        old = atomicOr((unsigned long long *)&words[L.off[k] + (bit >> 6)], 1ull << (bit & 63));
+      }
+    }
+  }
+  if (bad) info[HP_INFO_STATUS] = HP_ERANGE;
+}
+
+// The level-0 word w as extraction sees it: bits beyond p cleared, and with
+// the tree, zero unless its bit in the level-1 word l1 is set.
+template <bool TREE>
+__device__ __forceinline__ uint64_t bits_leaf(const uint64_t *__restrict__ words, int64_t w, int64_t W0,
+                                              uint64_t lastmask, uint64_t l1) {
+  if (w >= W0) return 0;
+  if (TREE && !((l1 >> (w & 63)) & 1)) return 0;
+  const uint64_t v = __builtin_nontemporal_load(&words[w]);
+  return w == W0 - 1 ? (v & lastmask) : v;
+}
+
+template <bool TREE>
+__device__ __forceinline__ uint64_t bits_level1(const uint64_t *__restrict__ words, int64_t w, int64_t W0,
+                                                int64_t off1) {
+  // the level-1 word over the wave's 64 level-0 words (w is this lane's word)
+  if (!TREE || W0 <= 1) return ~0ull;
+  return words[off1 + (w >> 6)];
+}
+
+template <bool TREE>
+__global__ __launch_bounds__(kBitsBlock) void k_bits_count(const uint64_t *__restrict__ words, int64_t W0,
+                                                           uint64_t lastmask, int64_t off1,
+                                                           int32_t *__restrict__ blockcnt) {
+  __shared__ int s_part[kBitsBlock / kWave];
+  const int64_t w = (int64_t)blockIdx.x * kBitsBlock + threadIdx.x;
+  const int64_t wave0 = w & ~(int64_t)63;
+  const uint64_t l1 = wave0 < W0 ? bits_level1<TREE>(words, w, W0, off1) : 0;
+  int c = 0;
+  if (l1) c = __popcll(bits_leaf<TREE>(words, w, W0, lastmask, l1));
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) c += __shfl_xor(c, d, kWave);
+  if ((threadIdx.x & (kWave - 1)) == 0) s_part[threadIdx.x / kWave] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int i = 0; i < kBitsBlock / kWave; ++i) t += s_part[i];
+    blockcnt[blockIdx.x] = t;
+  }
+}
+
+// One workgroup: exclusive offsets of the nb block counts, total at [nb].
+__global__ __launch_bounds__(kBitsScanBlock) void k_bits_scan(const int32_t *__restrict__ blockcnt, int64_t nb,
+                                                              int64_t *__restrict__ blockoff) {
+  __shared__ int64_t s_sum[kBitsScanBlock];
+  const int64_t per = (nb + kBitsScanBlock - 1) / kBitsScanBlock;
+  const int64_t b0 = (int64_t)threadIdx.x * per, b1 = b0 + per < nb ? b0 + per : nb;
+  int64_t mine = 0;
+  for (int64_t b = b0; b < b1; ++b) mine += blockcnt[b];
+  s_sum[threadIdx.x] = mine;
+  __syncthreads();
+  for (int d = 1; d < kBitsScanBlock; d <<= 1) {  // Hillis-Steele over the thread sums
+    const int64_t add = threadIdx.x >= (unsigned)d ? s_sum[threadIdx.x - d] : 0;
+    __syncthreads();
+    s_sum[threadIdx.x] += add;
+    __syncthreads();
+  }
+  int64_t run = s_sum[threadIdx.x] - mine;
+  for (int64_t b = b0; b < b1; ++b) {
+    blockoff[b] = run;
+    run += blockcnt[b];
+  }
+  if (threadIdx.x == kBitsScanBlock - 1) blockoff[nb] = s_sum[threadIdx.x];
+}
+
+template <bool TREE>
+__global__ __launch_bounds__(kBitsBlock) void k_bits_write(const uint64_t *__restrict__ words, int64_t W0,
+                                                           uint64_t lastmask, int64_t off1,
+                                                           const int64_t *__restrict__ blockoff, int64_t nb,
+                                                           int32_t *__restrict__ cols, int32_t cap,
+                                                           int32_t *__restrict__ info) {
+  __shared__ int32_t s_out[kBitsBlock * 64];
+  __shared__ int s_wave[kBitsBlock / kWave];
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int64_t w = (int64_t)blockIdx.x * kBitsBlock + threadIdx.x;
+  const int64_t wave0 = w & ~(int64_t)63;
+  const uint64_t l1 = wave0 < W0 ? bits_level1<TREE>(words, w, W0, off1) : 0;
+  uint64_t v = l1 ? bits_leaf<TREE>(words, w, W0, lastmask, l1) : 0;
+  const int c = __popcll(v);
+  int x = c;  // inclusive scan over the wave
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int y = __shfl_up(x, d, kWave);
+    if (lane >= d) x += y;
+  }
+  if (lane == kWave - 1) s_wave[wave] = x;
+  __syncthreads();
+  int local = x - c, total = 0;
+  for (int i = 0; i < kBitsBlock / kWave; ++i) {
+    if (i < wave) local += s_wave[i];
+    total += s_wave[i];
+  }
+  const int32_t base = (int32_t)(w * 64 + 1);
+  while (v) {  // Table I: pos = ctz(v), then clear that bit
+    const int pos = __builtin_ctzll(v);
+    s_out[local++] = base + pos;
+    v ^= 1ull << pos;
+  }
+  __syncthreads();
+  const int64_t off = blockoff[blockIdx.x];
+  for (int i = threadIdx.x; i < total; i += kBitsBlock)
+    if (off + i < cap) cols[off + i] = s_out[i];
+  if (blockIdx.x == nb - 1 && threadIdx.x == 0) {
+    const int64_t all = blockoff[nb];
+    info[HP_INFO_K] = (int32_t)(all < INT_MAX ? all : INT_MAX);
+    info[HP_INFO_STATUS] = all > cap ? HP_ECAPACITY : HP_OK;
+  }
+}
+
+static int64_t bits_blocks(int32_t p) {
+  const int64_t W0 = ((int64_t)p + 63) / 64;
+  return (W0 + kBitsBlock - 1) / kBitsBlock;
+}
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+}  // namespace hp
+
+using namespace hp;
+
+extern "C" int hp_bitset_words(int32_t p, int32_t tree, int64_t *words) {
+  if (p < 1 || p > HP_P_MAX) return set_error(HP_EINVAL, "p = %d outside [1, %d]", p, HP_P_MAX);
+  if (!words) return set_error(HP_EINVAL, "words is NULL");
+  *words = bit_levels(p, tree).off[bit_levels(p, tree).levels];
+  return HP_OK;
+}
+
+extern "C" int hp_bitset_clear(uint64_t *words, int64_t nwords, void *stream) {
+  if (nwords < 0) return set_error(HP_EINVAL, "nwords < 0");
+  if (nwords == 0) return HP_OK;
+  if (!words) return set_error(HP_EINVAL, "words is NULL");
+  const int grid = (int)std::min<int64_t>(4 * device_info().cus, (nwords + 255) / 256);
+  hipLaunchKernelGGL(k_bits_fill, dim3(grid), dim3(256), 0, (hipStream_t)stream, words, nwords);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_error(HP_EDEVICE, "k_bits_fill launch: %s", hipGetErrorString(e));
+  return HP_OK;
+}
+
+extern "C" int hp_bitset_insert(const int32_t *cols, int64_t s, int32_t p, int32_t tree, uint64_t *words,
+                                int32_t *info, void *stream) {
+  if (p < 1 || p > HP_P_MAX) return set_error(HP_EINVAL, "p = %d outside [1, %d]", p, HP_P_MAX);
+  if (s < 0) return set_error(HP_EINVAL, "s < 0");
+  if ((s > 0 && !cols) || !words || !info) return set_error(HP_EINVAL, "NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_bits_info, dim3(1), dim3(1), 0, st, info);
+  if (s > 0) {
+    const BitLevels L = bit_levels(p, tree);
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(8 * device_info().cus, (s + 255) / 256));
+    if (tree)
+      hipLaunchKernelGGL(k_bits_insert<true>, dim3(grid), dim3(256), 0, st, cols, s, p, words, L, info);
+    else
+      hipLaunchKernelGGL(k_bits_insert<false>, dim3(grid), dim3(256), 0, st, cols, s, p, words, L, info);
+  }
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_error(HP_EDEVICE, "k_bits_insert launch: %s", hipGetErrorString(e));
+  return HP_OK;
+}
+
+extern "C" int hp_bitset_extract_workspace_bytes(int32_t p, size_t *bytes) {
+  if (p < 1 || p > HP_P_MAX) return set_error(HP_EINVAL, "p = %d outside [1, %d]", p, HP_P_MAX);
+  if (!bytes) return set_error(HP_EINVAL, "bytes is NULL");
+  const int64_t nb = bits_blocks(p);
+  *bytes = align256(sizeof(int32_t) * nb) + align256(sizeof(int64_t) * (nb + 1));
+  return HP_OK;
+}
+
+extern "C" int hp_bitset_extract(const uint64_t *words, int32_t p, int32_t tree, int32_t *cols, int32_t cap,
+                                 int32_t *info, void *ws, size_t ws_bytes, void *stream) {
+  if (p < 1 || p > HP_P_MAX) return set_error(HP_EINVAL, "p = %d outside [1, %d]", p, HP_P_MAX);
+  if (!words || !info || !ws) return set_error(HP_EINVAL, "NULL argument");
+  if (cap < 0 || (cap > 0 && !cols)) return set_error(HP_EINVAL, "bad output capacity");
+  if ((uintptr_t)words & 7) return set_error(HP_EINVAL, "words is not 8-byte aligned");
+  size_t need = 0;
+  hp_bitset_extract_workspace_bytes(p, &need);
+  if (ws_bytes < need) return set_error(HP_ECAPACITY, "workspace %zu < %zu bytes", ws_bytes, need);
+  const int64_t W0 = ((int64_t)p + 63) / 64, nb = bits_blocks(p);
+  const uint64_t lastmask = (p & 63) ? (1ull << (p & 63)) - 1 : ~0ull;
+  const int64_t off1 = W0;  // level 1 follows level 0 in a tree
+  int32_t *blockcnt = static_cast<int32_t *>(ws);
+  int64_t *blockoff = reinterpret_cast<int64_t *>(static_cast<char *>(ws) + align256(sizeof(int32_t) * nb));
+  hipStream_t st = (hipStream_t)stream;
+  if (tree) {
+    hipLaunchKernelGGL(k_bits_count<true>, dim3(nb), dim3(kBitsBlock), 0, st, words, W0, lastmask, off1, blockcnt);
+    hipLaunchKernelGGL(k_bits_scan, dim3(1), dim3(kBitsScanBlock), 0, st, (const int32_t *)blockcnt, nb, blockoff);
+    hipLaunchKernelGGL(k_bits_write<true>, dim3(nb), dim3(kBitsBlock), 0, st, words, W0, lastmask, off1,
+                       (const int64_t *)blockoff, nb, cols, cap, info);
+  } else {
+    hipLaunchKernelGGL(k_bits_count<false>, dim3(nb), dim3(kBitsBlock), 0, st, words, W0, lastmask, off1, blockcnt);
+    hipLaunchKernelGGL(k_bits_scan, dim3(1), dim3(kBitsScanBlock), 0, st, (const int32_t *)blockcnt, nb, blockoff);
+    hipLaunchKernelGGL(k_bits_write<false>, dim3(nb), dim3(kBitsBlock), 0, st, words, W0, lastmask, off1,
+                       (const int64_t *)blockoff, nb, cols, cap, info);
+  }
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_error(HP_EDEVICE, "bit extraction launch: %s", hipGetErrorString(e));
+  return HP_OK;
+}

@@ -195,6 +195,64 @@ def run_auto(points: torch.Tensor, export_L: bool = True) -> dict:
     return out
 
 
+# ---------------------------------------------------------------------------
+# Bit array and w-ary tree
+# ---------------------------------------------------------------------------
+def bitset_words(p: int, tree: bool) -> int:
+    w = ctypes.c_int64()
+    _lib.call("hp_bitset_words", p, int(tree), ctypes.byref(w))
+    return w.value
+
+
+def bitset_extract_workspace_bytes(p: int) -> int:
+    size = ctypes.c_size_t()
+    _lib.call("hp_bitset_extract_workspace_bytes", p, ctypes.byref(size))
+    return size.value
+
+
+def hp_bitset_clear(words: torch.Tensor, stream=None) -> None:
+    _lib.call("hp_bitset_clear", _ptr(words), words.numel(), _stream(stream))
+
+
+def hp_bitset_insert(cols: torch.Tensor, p: int, tree: bool, words: torch.Tensor, info: torch.Tensor,
+                     stream=None) -> None:
+    """Enqueue the inserts of the 1-based columns ``cols`` (int32, device)."""
+    if cols.dtype != torch.int32 or not cols.is_cuda or not cols.is_contiguous():
+        raise ValueError("cols must be a contiguous int32 device tensor")
+    if words.dtype != torch.int64 or words.numel() < bitset_words(p, tree):
+        raise ValueError("words must be an int64 device tensor of bitset_words(p, tree) entries")
+    _lib.call("hp_bitset_insert", _ptr(cols), cols.numel(), p, int(tree), _ptr(words), _ptr(info),
+              _stream(stream))
+
+
+def hp_bitset_extract(words: torch.Tensor, p: int, tree: bool, cols: torch.Tensor, info: torch.Tensor,
+                      ws: torch.Tensor, stream=None) -> None:
+    """Enqueue the extraction of the set columns into ``cols`` (ascending)."""
+    if words.dtype != torch.int64 or words.numel() < bitset_words(p, tree):
+        raise ValueError("words must be an int64 device tensor of bitset_words(p, tree) entries")
+    _lib.call("hp_bitset_extract", _ptr(words), p, int(tree), _ptr(cols), cols.numel(), _ptr(info),
+              _ptr(ws), ws.numel(), _stream(stream))
+
+
+def bitset_roundtrip(cols: torch.Tensor, p: int, tree: bool, cap: int | None = None) -> dict:
+    """Clear, insert ``cols`` and extract, on the device; host copies back."""
+    dev = cols.device
+    words = torch.empty(bitset_words(p, tree), dtype=torch.int64, device=dev)
+    info_i = torch.zeros(2, dtype=torch.int32, device=dev)
+    info_e = torch.zeros(2, dtype=torch.int32, device=dev)
+    out = torch.empty(max(1, p if cap is None else cap), dtype=torch.int32, device=dev)
+    ws = torch.empty(bitset_extract_workspace_bytes(p), dtype=torch.uint8, device=dev)
+    hp_bitset_clear(words)
+    hp_bitset_insert(cols, p, tree, words, info_i)
+    hp_bitset_extract(words, p, tree, out if cap != 0 else out[:0], info_e, ws)
+    torch.cuda.synchronize(dev)
+    ii, ie = info_i.cpu().tolist(), info_e.cpu().tolist()
+    k = ie[HP_INFO_K]
+    return {"insert_status": ii[HP_INFO_STATUS], "status": ie[HP_INFO_STATUS], "count": k,
+            "words": words.cpu().numpy().view("uint64"),
+            "cols": out[:min(k, out.numel() if cap != 0 else 0)].cpu().numpy()}
+
+
 def collect(buf: Buffers) -> dict:
     """Synchronise and return host copies of every output (trimmed)."""
     torch.cuda.synchronize(buf.info.device)

@@ -131,3 +131,22 @@ def test_clock_is_monotonic():
     a = lib.hp_clock_ns()
     b = lib.hp_clock_ns()
     assert 0 < a <= b
+
+
+def test_bitset_sizes_match_the_tree_of_the_text():
+    """Word counts of the bit array and the w-ary tree (host-side queries)."""
+    import oracle
+    lib = _lib.load()
+    w = ctypes.c_int64()
+    for p in [1, 5, 63, 64, 65, 4097, 70_000, 1 << 24, _lib.HP_P_MAX]:
+        assert lib.hp_bitset_words(p, 0, ctypes.byref(w)) == 0
+        assert w.value == (p + 63) // 64
+        assert lib.hp_bitset_words(p, 1, ctypes.byref(w)) == 0
+        assert w.value == oracle.tree_levels(p)[-1]
+    lib.hp_bitset_words(1 << 24, 1, ctypes.byref(w))
+    assert w.value == 266305
+    size = ctypes.c_size_t()
+    assert lib.hp_bitset_extract_workspace_bytes(1 << 24, ctypes.byref(size)) == 0 and size.value > 0
+    assert lib.hp_bitset_words(0, 1, ctypes.byref(w)) == _lib.HP_EINVAL
+    assert lib.hp_bitset_insert(None, 5, 10, 0, None, None, None) == _lib.HP_EINVAL
+    assert lib.hp_bitset_extract(None, 10, 0, None, 0, None, None, 0, None) == _lib.HP_EINVAL
