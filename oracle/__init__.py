@@ -8,5 +8,5 @@ from .oracle import (  # noqa: F401
     OR_OK, OR_EINVAL, OR_ERANGE, OR_EORDER, OracleError,
     build, lib_path, reduce, mask, ctz_positions, extract, chain, reduced,
     hull_chain, hull_full, precondition_and_hull, bbox, translate, auto,
-    tree_levels, array_insert, tree_insert, tree_extract,
+    tree_levels, array_insert, tree_insert, tree_extract, hull_melkman,
 )

@@ -433,3 +433,134 @@ int32_t or_tree_extract(const uint64_t *T, int32_t p, int32_t *cols)
     return or_tree_visit(T, offset, levels - 1, 0, cols, 0);
 }
 
+/* ---------------------------------------------------------------------------
+ * Melkman's algorithm on the Lemma 1 polyline (Results, the linear hull of a
+ * simple polyline; Conclusions).
+ *
+ * The reduced sequence R, walked column by column as (x, lo) then (x, hi),
+ * is a simple polyline (Lemma 1), so Melkman's deque algorithm finds its hull
+ * in one pass.  The deque holds the current hull counter-clockwise from
+ * bottom to top, with the newest hull point at both ends.  A new point that
+ * lies strictly left of both end edges is inside and skipped; otherwise the
+ * top is popped while the point is not strictly left of the top edge, the
+ * point is pushed on top, and the same is done at the bottom.  The result is
+ * then put in the canonical form of the other hulls: vertices with a
+ * straight angle removed, starting at the lexicographic minimum.
+ *
+ * The orientation test is written out here again on purpose, so that this
+ * hull shares no arithmetic with the monotone-chain one it is checked
+ * against.
+ * ------------------------------------------------------------------------- */
+static int64_t or_orient(const int32_t *a, const int32_t *b, const int32_t *c)
+{
+    /* twice the signed area of (a, b, c): > 0 when c is left of a -> b */
+    int64_t abx = (int64_t)b[0] - a[0], aby = (int64_t)b[1] - a[1];
+    int64_t acx = (int64_t)c[0] - a[0], acy = (int64_t)c[1] - a[1];
+    return abx * acy - aby * acx;
+}
+
+int32_t or_hull_melkman(const int32_t *x, const int32_t *clo, const int32_t *chi,
+                        int32_t k, int32_t *vx, int32_t *vy)
+{
+    if (k < 0) return OR_EINVAL;
+    for (int32_t t = 0; t + 1 < k; ++t)
+        if (!(x[t] < x[t + 1])) return OR_EORDER;
+    for (int32_t t = 0; t < k; ++t)
+        if (chi[t] < clo[t]) return OR_EORDER;
+
+    /* R as interleaved (x, y) pairs */
+    int64_t s = 0;
+    int32_t *R = (int32_t *)malloc((size_t)(4 * (int64_t)k + 2) * sizeof(int32_t));
+    int32_t *D = (int32_t *)malloc((size_t)(2 * (4 * (int64_t)k + 1) + 2) * sizeof(int32_t));
+    if (R == NULL || D == NULL) {
+        free(R);
+        free(D);
+        return OR_EINVAL;
+    }
+    for (int32_t t = 0; t < k; ++t) {
+        R[2 * s] = x[t];
+        R[2 * s + 1] = clo[t];
+        ++s;
+        if (chi[t] > clo[t]) {
+            R[2 * s] = x[t];
+            R[2 * s + 1] = chi[t];
+            ++s;
+        }
+    }
+    int64_t h = 0;
+    if (s <= 2) {
+        for (int64_t i = 0; i < s; ++i) {
+            vx[i] = R[2 * i];
+            vy[i] = R[2 * i + 1];
+        }
+        h = s;
+        goto done;
+    }
+    {
+        /* a, b: the first two points; points collinear with them move b along
+         * the line (the walk is x-monotone, so the newest is the far end) */
+        const int32_t *a = &R[0], *b = &R[2];
+        int64_t j = 2;
+        while (j < s && or_orient(a, b, &R[2 * j]) == 0) b = &R[2 * j++];
+        if (j == s) {
+            vx[0] = a[0];
+            vy[0] = a[1];
+            vx[1] = b[0];
+            vy[1] = b[1];
+            h = 2;
+            goto done;
+        }
+        const int32_t *c = &R[2 * j];
+        /* deque of points D[bot..top] (2 ints each), room for 2s + 1 */
+        int64_t bot = s, top = s + 3;
+        const int32_t *first = or_orient(a, b, c) > 0 ? a : b;
+        const int32_t *second = first == a ? b : a;
+#define DQ(i) (&D[2 * (i)])
+        DQ(bot)[0] = c[0], DQ(bot)[1] = c[1];
+        DQ(bot + 1)[0] = first[0], DQ(bot + 1)[1] = first[1];
+        DQ(bot + 2)[0] = second[0], DQ(bot + 2)[1] = second[1];
+        DQ(top)[0] = c[0], DQ(top)[1] = c[1];
+        for (int64_t i = j + 1; i < s; ++i) {
+            const int32_t *v = &R[2 * i];
+            if (or_orient(DQ(top - 1), DQ(top), v) > 0 && or_orient(DQ(bot), DQ(bot + 1), v) > 0) continue;
+            while (top - bot >= 2 && or_orient(DQ(top - 1), DQ(top), v) <= 0) --top;
+            ++top;
+            DQ(top)[0] = v[0], DQ(top)[1] = v[1];
+            while (top - bot >= 2 && or_orient(DQ(bot), DQ(bot + 1), v) <= 0) ++bot;
+            --bot;
+            DQ(bot)[0] = v[0], DQ(bot)[1] = v[1];
+        }
+        /* the hull, counter-clockwise: D[bot..top-1] (D[top] repeats D[bot]) */
+        int64_t m = top - bot;
+        int32_t *H = &D[2 * bot];
+        /* drop vertices with a straight angle until none is left */
+        int changed = 1;
+        while (changed && m > 2) {
+            changed = 0;
+            for (int64_t i = 0; i < m && m > 2; ++i) {
+                const int32_t *pv = &H[2 * ((i + m - 1) % m)], *cv = &H[2 * i], *nv = &H[2 * ((i + 1) % m)];
+                if (or_orient(pv, cv, nv) == 0) {
+                    memmove(&H[2 * i], &H[2 * i + 2], (size_t)(m - i - 1) * 2 * sizeof(int32_t));
+                    --m;
+                    changed = 1;
+                    --i;
+                }
+            }
+        }
+        /* start at the lexicographic minimum */
+        int64_t lo = 0;
+        for (int64_t i = 1; i < m; ++i)
+            if (H[2 * i] < H[2 * lo] || (H[2 * i] == H[2 * lo] && H[2 * i + 1] < H[2 * lo + 1])) lo = i;
+        for (int64_t i = 0; i < m; ++i) {
+            vx[i] = H[2 * ((lo + i) % m)];
+            vy[i] = H[2 * ((lo + i) % m) + 1];
+        }
+        h = m;
+#undef DQ
+    }
+done:
+    free(R);
+    free(D);
+    return (int32_t)h;
+}
+

@@ -106,6 +106,13 @@ int or_array_insert(int32_t p, const int32_t *cols, int64_t s, uint64_t *M);
 int or_tree_insert(int32_t p, const int32_t *cols, int64_t s, uint64_t *T);
 int32_t or_tree_extract(const uint64_t *T, int32_t p, int32_t *cols);
 
+/* Melkman's algorithm on the Lemma 1 polyline (the reduced sequence walked
+ * column by column), in the canonical form of or_hull_chain: straight angles
+ * removed, counter-clockwise from the lexicographic minimum.  Inputs and
+ * errors as for or_hull_chain; vx, vy need 2k entries. */
+int32_t or_hull_melkman(const int32_t *x, const int32_t *clo, const int32_t *chi,
+                        int32_t k, int32_t *vx, int32_t *vy);
+
 #ifdef __cplusplus
 }
 #endif

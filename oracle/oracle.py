@@ -76,6 +76,8 @@ def _load(path: str) -> ctypes.CDLL:
     lib.or_tree_insert.restype = ctypes.c_int
     lib.or_tree_extract.argtypes = [_u64p, ctypes.c_int32, _i32p]
     lib.or_tree_extract.restype = ctypes.c_int32
+    lib.or_hull_melkman.argtypes = [_i32p, _i32p, _i32p, ctypes.c_int32, _i32p, _i32p]
+    lib.or_hull_melkman.restype = ctypes.c_int32
     lib.or_bbox.argtypes = [_i32p, ctypes.c_int64, _i32p]
     lib.or_bbox.restype = ctypes.c_int
     lib.or_translate.argtypes = [_i32p, ctypes.c_int64, _i32p, _i32p, _i32p]
@@ -276,4 +278,16 @@ def tree_extract(T: np.ndarray, p: int, lib: str | None = None) -> np.ndarray:
     if k < 0:
         raise OracleError(f"or_tree_extract failed: {k}")
     return cols[:k]
+
+
+def hull_melkman(x, clo, chi, lib: str | None = None) -> np.ndarray:
+    """Melkman's hull of the Lemma 1 polyline, in canonical form."""
+    x, clo, chi = (np.ascontiguousarray(np.asarray(a, np.int32)) for a in (x, clo, chi))
+    k = x.shape[0]
+    vx = np.empty(max(2 * k, 1), np.int32)
+    vy = np.empty(max(2 * k, 1), np.int32)
+    h = _lib(lib).or_hull_melkman(_ptr(x), _ptr(clo), _ptr(chi), k, _ptr(vx), _ptr(vy))
+    if h < 0:
+        raise OracleError(f"or_hull_melkman failed: {h}")
+    return np.stack([vx[:h], vy[:h]], axis=1)
 

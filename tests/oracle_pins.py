@@ -429,9 +429,47 @@ def pin_bitsets(lib=None):
     return errs
 
 
+@_safe
+def pin_melkman(lib=None):
+    """Melkman's hull of the Lemma 1 polyline equals the monotone-chain hull
+    and the brute-force extreme points: the worked example's pentagon, random
+    tiny sets, sets on a few lines (many collinear points), and larger
+    clouds."""
+    errs = []
+    f = fixtures.read("worked_example_p5.txt")
+    r = _run_path(fixtures.pairs(f["points"]), 5, lib)
+    got = oracle.hull_melkman(r["x"], r["clo"], r["chi"], lib=lib)
+    if [tuple(v) for v in got.tolist()] != [(1, 1), (5, 2), (5, 3), (3, 5), (1, 4)]:
+        errs.append(f"worked example: {got.tolist()}")
+    rng = np.random.default_rng(1987)
+    for t in range(1500):
+        p = int(rng.integers(1, 30))
+        n = int(rng.integers(0, 40))
+        pts = rng.integers(1, p + 1, size=(n, 2))
+        if t % 3 == 0:
+            a = rng.integers(1, p + 1, size=n)
+            pts = np.stack([a, (a * int(rng.integers(-2, 3)) + int(rng.integers(0, p))) % p + 1], 1)
+        r = _run_path(pts, p, lib)
+        got = oracle.hull_melkman(r["x"], r["clo"], r["chi"], lib=lib)
+        if not np.array_equal(got, r["hull"]):
+            errs.append(f"p={p} {pts.tolist()}: melkman {got.tolist()} != {r['hull'].tolist()}")
+            continue
+        if t % 5 == 0:
+            errs += brute.check_canonical_hull(got.tolist(), pts.tolist())
+        if len(errs) > 5:
+            break
+    for p, n in [(4096, 200_000), (1 << 16, 3000)]:
+        pts = rng.integers(1, p + 1, size=(n, 2))
+        pts[:, 1] = np.clip((pts[:, 1] - p // 2) // 3 + p // 2 + (pts[:, 0] * 7) % 13, 1, p)
+        r = _run_path(pts, p, lib)
+        if not np.array_equal(oracle.hull_melkman(r["x"], r["clo"], r["chi"], lib=lib), r["hull"]):
+            errs.append(f"p={p} n={n}: melkman differs")
+    return errs
+
+
 ALL_PINS = [pin_worked_example, pin_gap_example, pin_table1, pin_block_index,
             pin_closed_forms, pin_brute_random, pin_exhaustive_p3, pin_qhull,
-            pin_appendix, pin_invariants, pin_metamorphic, pin_errors, pin_steps12, pin_bitsets]
+            pin_appendix, pin_invariants, pin_metamorphic, pin_errors, pin_steps12, pin_bitsets, pin_melkman]
 
 # the cheap pins, run first against planted mistakes
 FAST_PINS = [pin_worked_example, pin_gap_example, pin_table1, pin_block_index,

@@ -48,6 +48,10 @@ MUTANTS = {
     "tree-child-index": ("int64_t child = word * 64 + pos[t];", "int64_t child = word * 63 + pos[t];"),
     "tree-one-level-short": ("        if (words == 1) break;\n        words = (words + 63) / 64;",
                              "        words = (words + 63) / 64;\n        if (words == 1) break;"),
+    "melkman-skip-either-side": ("if (or_orient(DQ(top - 1), DQ(top), v) > 0 && or_orient(DQ(bot), DQ(bot + 1), v) > 0) continue;",
+                                 "if (or_orient(DQ(top - 1), DQ(top), v) > 0 || or_orient(DQ(bot), DQ(bot + 1), v) > 0) continue;"),
+    "melkman-clockwise-start": ("or_orient(a, b, c) > 0 ? a : b;", "or_orient(a, b, c) < 0 ? a : b;"),
+    "melkman-orient-term": ("return abx * acy - aby * acx;", "return abx * acy - aby * acy;"),
     "chain-skips-last": ("for (int32_t i = 1; i <= p; ++i) {\n        if (or_valid(lo[i - 1], hi[i - 1], p)) {\n            x[k] = i;",
                          "for (int32_t i = 1; i < p; ++i) {\n        if (or_valid(lo[i - 1], hi[i - 1], p)) {\n            x[k] = i;"),
 }
@@ -80,8 +84,10 @@ def test_mutant_is_caught(tmp_path, name):
     old, new = MUTANTS[name]
     lib = _build_mutant(tmp_path, name, old, new)
     # a mutant that writes out of bounds may crash the process that runs it:
-    # the pins run in a forked child, and a crash counts as a catch
-    proc = multiprocessing.get_context("fork").Process(target=_pins_catch, args=(lib,))
+    # the pins run in a child process (forked from a clean single-threaded
+    # server, never from this possibly multi-threaded one), and a crash
+    # counts as a catch
+    proc = multiprocessing.get_context("forkserver").Process(target=_pins_catch, args=(lib,))
     proc.start()
     proc.join(300)
     if proc.is_alive():
