@@ -680,6 +680,37 @@ def bench_bits(args, torch, hp) -> dict:
     return {"p": p, "steps": steps, "rows": rows, "fit": fit}
 
 
+def bench_melkman(args, torch, hp, synth) -> dict:
+    """Melkman's sequential hull of the main workload's chain against the
+    parallel hp_hull on the same chain (both after one hp_precondition)."""
+    import numpy as np
+
+    import oracle
+
+    w = synth.WORKLOADS[args.workload]
+    p = w["p"]
+    pts = synth.cloud(w["kind"], w["n"], p, w["seed"], device="cuda:0")
+    buf = hp.Buffers.allocate(pts.shape[0], p, pts.device, export_L=True)
+    stream = torch.cuda.current_stream()
+    hp.hp_precondition(pts, p, buf, stream)
+    steps = max(5, min(args.steps, 20))
+    res = {"workload": args.workload, "steps": steps}
+    for name, fn in (("hp_hull_melkman", hp.hp_hull_melkman), ("hp_hull", hp.hp_hull)):
+        fn(buf, stream)
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        for _ in range(steps):
+            fn(buf, stream)
+        stop.record(stream)
+        torch.cuda.synchronize()
+        got = hp.collect(buf)
+        want = oracle.precondition_and_hull(pts.cpu().numpy(), p)
+        res[name] = {"us_per_call": round(start.elapsed_time(stop) * 1e3 / steps, 2),
+                     "h": got["h"], "parity_vs_oracle": bool(np.array_equal(got["hull"], want["hull"]))}
+    res["k"] = got["k"]
+    return res
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -692,6 +723,7 @@ def main(argv=None):
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-auto", action="store_true", help="skip the bounding-box (steps 1 and 2) line")
     ap.add_argument("--no-bits", action="store_true", help="skip the bit array / tree extraction line")
+    ap.add_argument("--no-melkman", action="store_true", help="skip the Melkman cross-check line")
     ap.add_argument("--regimes", default="uniform_100k_p1024,disc_2p28_p2p20,gaussian_2p28_p4096",
                     help="other single-cloud workloads timed beside the main one ('' for none)")
     ap.add_argument("--batch-clouds", type=int, default=4096)
@@ -749,6 +781,8 @@ def main(argv=None):
         out["auto_bbox"] = bench_auto(args, torch, hp, synth)
     if not args.no_bits:
         out["bit_extraction"] = bench_bits(args, torch, hp)
+    if not args.no_melkman:
+        out["melkman"] = bench_melkman(args, torch, hp, synth)
     if not args.no_batched:
         out["batched"] = bench_batched(args, torch, hp, synth)
     if not args.no_serve:

@@ -226,6 +226,21 @@ int hp_hull(const int32_t *cx, const int32_t *clo, const int32_t *chi, int32_t c
             int32_t *hx, int32_t *hy, int32_t hull_cap,
             int32_t *info, void *ws, size_t ws_bytes, void *stream);
 
+/* Melkman's algorithm on the Lemma 1 polyline (Results, the linear hull of a
+ * simple polyline): the same hull as hp_hull, in the same canonical form
+ * (straight angles removed, counter-clockwise from the lexicographic
+ * minimum), by one sequential pass with a deque.  A cross-check of hp_hull,
+ * not a fast path: one lane runs it.  Arguments as for hp_hull (k is read
+ * from info[HP_INFO_K], h written to info[HP_INFO_H]); hull_cap >=
+ * max(2, 2 chain_cap).  The deque lives in LDS when chain_cap <= 5119, else
+ * in ws, of hp_hull_melkman_workspace_bytes(chain_cap) bytes (ws may be
+ * NULL in the LDS case).  A chain whose x is not strictly increasing or
+ * with lo > hi sets info[HP_INFO_STATUS] = HP_EINVAL and h = 0. */
+int hp_hull_melkman_workspace_bytes(int32_t chain_cap, size_t *bytes);
+int hp_hull_melkman(const int32_t *cx, const int32_t *clo, const int32_t *chi, int32_t chain_cap,
+                    int32_t *hx, int32_t *hy, int32_t hull_cap, int32_t *info, void *ws, size_t ws_bytes,
+                    void *stream);
+
 /* Steps 1-4 fused: the chain and its hull in one call (the hull is built
  * from L directly, in parallel with the chain write).  Arguments as above;
  * hull_cap >= 2 * min(n, p).  Uses the hp_workspace_bytes(n, p) workspace. */

@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libhullprep.so")
 
-SOURCES = ["hp_common.hip", "hp_single.hip", "hp_bits.hip", "hp_bkernels.hip", "hp_batched.hip", "hp_serve.hip"]
+SOURCES = ["hp_common.hip", "hp_single.hip", "hp_bits.hip", "hp_melkman.hip", "hp_bkernels.hip", "hp_batched.hip", "hp_serve.hip"]
 ARCH = os.environ.get("HP_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

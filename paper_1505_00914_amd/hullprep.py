@@ -128,6 +128,30 @@ def hp_hull(buf: Buffers, stream=None, ws: torch.Tensor | None = None) -> None:
               _stream(stream))
 
 
+def hull_melkman_workspace_bytes(chain_cap: int) -> int:
+    size = ctypes.c_size_t()
+    _lib.call("hp_hull_melkman_workspace_bytes", chain_cap, ctypes.byref(size))
+    return size.value
+
+
+def hp_hull_melkman(buf: Buffers, stream=None, ws: torch.Tensor | None = None) -> None:
+    """Enqueue Melkman's hull of the chain held in ``buf`` (k read on device)."""
+    cap = buf.cx.numel()
+    if ws is None:
+        need = hull_melkman_workspace_bytes(cap)
+        ws = buf.ws if buf.ws.numel() >= need else torch.empty(need, dtype=torch.uint8, device=buf.ws.device)
+    _lib.call("hp_hull_melkman", _ptr(buf.cx), _ptr(buf.clo), _ptr(buf.chi), cap, _ptr(buf.hx),
+              _ptr(buf.hy), buf.hx.numel(), _ptr(buf.info), _ptr(ws), ws.numel(), _stream(stream))
+
+
+def precondition_then_melkman(points: torch.Tensor, p: int) -> dict:
+    """hp_precondition followed by Melkman's hull of its chain."""
+    buf = Buffers.allocate(points.shape[0], p, points.device, True)
+    hp_precondition(points, p, buf)
+    hp_hull_melkman(buf)
+    return collect(buf)
+
+
 def hp_run(points: torch.Tensor, p: int, buf: Buffers, stream=None) -> None:
     """Enqueue the fused path: chain and hull (no sync)."""
     n = _check_points(points)
