@@ -7,6 +7,7 @@
  */
 #include "oracle.h"
 
+#include <math.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -562,5 +563,54 @@ done:
     free(R);
     free(D);
     return (int32_t)h;
+}
+
+/* ---------------------------------------------------------------------------
+ * Floating-point input (Conclusions: data with floating-point coordinates is
+ * brought to integers by a suitable scaling).
+ *
+ * Step 1 on float points: the extremes of x and y, NaN coordinates skipped.
+ * The scaling: X = floor((x - ox) * s) + 1 and Y = floor((y - oy) * s) + 1,
+ * evaluated in double precision as written (the float widened exactly, one
+ * subtraction, one multiplication, each rounded to nearest).  A coordinate
+ * whose result is NaN or outside [1, 2^31 - 2] is reported (OR_ERANGE) and
+ * written as 0.  With ox = xmin, oy = ymin and s = (p - 1) / max extent
+ * every point lands in [1, p]^2.
+ * ------------------------------------------------------------------------- */
+int or_bbox_f32(const float *pts, int64_t n, float *box)
+{
+    if (n < 0 || box == NULL || (n > 0 && pts == NULL)) return OR_EINVAL;
+    int any = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        float x = pts[2 * j], y = pts[2 * j + 1];
+        if (x != x || y != y) continue;             /* a NaN coordinate */
+        if (!any || x < box[0]) box[0] = x;
+        if (!any || x > box[1]) box[1] = x;
+        if (!any || y < box[2]) box[2] = y;
+        if (!any || y > box[3]) box[3] = y;
+        any = 1;
+    }
+    return any ? OR_OK : OR_ERANGE;
+}
+
+static int32_t or_scale_one(float v, double o, double s, int *bad)
+{
+    double t = floor(((double)v - o) * s);
+    if (!(t >= 0.0 && t <= (double)(OR_PMAX - 1))) {   /* also catches NaN */
+        *bad = 1;
+        return 0;
+    }
+    return (int32_t)t + 1;
+}
+
+int or_quantize_f32(const float *pts, int64_t n, double ox, double oy, double s, int32_t *out)
+{
+    if (n < 0 || out == NULL || (n > 0 && pts == NULL)) return OR_EINVAL;
+    int bad = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        out[2 * j] = or_scale_one(pts[2 * j], ox, s, &bad);
+        out[2 * j + 1] = or_scale_one(pts[2 * j + 1], oy, s, &bad);
+    }
+    return bad ? OR_ERANGE : OR_OK;
 }
 

@@ -113,6 +113,15 @@ int32_t or_tree_extract(const uint64_t *T, int32_t p, int32_t *cols);
 int32_t or_hull_melkman(const int32_t *x, const int32_t *clo, const int32_t *chi,
                         int32_t k, int32_t *vx, int32_t *vy);
 
+/* Floating-point input (Conclusions).  or_bbox_f32: (xmin, xmax, ymin, ymax)
+ * over the points, skipping any point with a NaN coordinate; OR_ERANGE when
+ * none is left.  or_quantize_f32: out = (floor((x - ox) * s) + 1,
+ * floor((y - oy) * s) + 1), in double precision, one rounding per operation;
+ * a coordinate that is NaN or falls outside [1, 2^31 - 2] is written as 0
+ * and makes the call return OR_ERANGE (the others are still written). */
+int or_bbox_f32(const float *pts, int64_t n, float *box);
+int or_quantize_f32(const float *pts, int64_t n, double ox, double oy, double s, int32_t *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -38,8 +38,10 @@ def build(force: bool = True, extra_flags: tuple[str, ...] = (), out: str | None
     ):
         return out
     tmp = out + ".tmp%d" % os.getpid()
-    cmd = ["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-fPIC", "-shared",
-           *extra_flags, "-o", tmp, _SRC]
+    # -ffp-contract=off: the scaling of float input is one rounding per
+    # operation, as written
+    cmd = ["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-ffp-contract=off", "-fPIC", "-shared",
+           *extra_flags, "-o", tmp, _SRC, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, out)
     return out
@@ -78,6 +80,12 @@ def _load(path: str) -> ctypes.CDLL:
     lib.or_tree_extract.restype = ctypes.c_int32
     lib.or_hull_melkman.argtypes = [_i32p, _i32p, _i32p, ctypes.c_int32, _i32p, _i32p]
     lib.or_hull_melkman.restype = ctypes.c_int32
+    _f32p = ctypes.POINTER(ctypes.c_float)
+    lib.or_bbox_f32.argtypes = [_f32p, ctypes.c_int64, _f32p]
+    lib.or_bbox_f32.restype = ctypes.c_int
+    lib.or_quantize_f32.argtypes = [_f32p, ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                    _i32p]
+    lib.or_quantize_f32.restype = ctypes.c_int
     lib.or_bbox.argtypes = [_i32p, ctypes.c_int64, _i32p]
     lib.or_bbox.restype = ctypes.c_int
     lib.or_translate.argtypes = [_i32p, ctypes.c_int64, _i32p, _i32p, _i32p]
@@ -290,4 +298,42 @@ def hull_melkman(x, clo, chi, lib: str | None = None) -> np.ndarray:
     if h < 0:
         raise OracleError(f"or_hull_melkman failed: {h}")
     return np.stack([vx[:h], vy[:h]], axis=1)
+
+
+def bbox_f32(pts, lib: str | None = None) -> tuple[float, float, float, float]:
+    """Step 1 on float points (NaN coordinates skipped)."""
+    a = np.ascontiguousarray(np.asarray(pts, np.float32).reshape(-1, 2))
+    box = np.zeros(4, np.float32)
+    f32p = ctypes.POINTER(ctypes.c_float)
+    rc = _lib(lib).or_bbox_f32(a.ctypes.data_as(f32p), a.shape[0], box.ctypes.data_as(f32p))
+    if rc != OR_OK:
+        raise OracleError(f"or_bbox_f32 failed: {rc}")
+    return tuple(float(v) for v in box)
+
+
+def quantize_f32(pts, origin, scale: float, lib: str | None = None) -> tuple[np.ndarray, int]:
+    """The scaling to integers: (points, status) with status OR_OK or OR_ERANGE."""
+    a = np.ascontiguousarray(np.asarray(pts, np.float32).reshape(-1, 2))
+    out = np.empty(a.shape, np.int32)
+    f32p = ctypes.POINTER(ctypes.c_float)
+    rc = _lib(lib).or_quantize_f32(a.ctypes.data_as(f32p), a.shape[0], float(origin[0]), float(origin[1]),
+                                   float(scale), _ptr(out))
+    if rc not in (OR_OK, OR_ERANGE):
+        raise OracleError(f"or_quantize_f32 failed: {rc}")
+    return out, rc
+
+
+def auto_f32(pts, p: int, lib: str | None = None) -> dict:
+    """Float points to the path: the box, origin (xmin, ymin), scale
+    (p - 1) / max extent (1 when the extent is 0), the quantised points, then
+    the whole path on them with side p."""
+    xmin, xmax, ymin, ymax = bbox_f32(pts, lib)
+    ext = max(float(xmax) - float(xmin), float(ymax) - float(ymin))
+    scale = (p - 1) / ext if ext > 0 else 1.0
+    q, rc = quantize_f32(pts, (xmin, ymin), scale, lib)
+    if rc != OR_OK:
+        raise OracleError("a coordinate is NaN or out of range")
+    r = precondition_and_hull(q, p, lib)
+    r.update({"box": (xmin, xmax, ymin, ymax), "scale": scale, "origin": (xmin, ymin), "points": q})
+    return r
 

@@ -467,9 +467,49 @@ def pin_melkman(lib=None):
     return errs
 
 
+@_safe
+def pin_float_input(lib=None):
+    """Scaling of float input: values worked by hand, the float box against
+    numpy, NaN and range reports, monotonicity, and the worked example given
+    as floats (halved and moved) coming back to the paper's L and pentagon."""
+    errs = []
+    pts = np.array([[0.0, 0.0], [1.5, 2.25], [0.49, 0.5], [-0.5, 3.0]], np.float32)
+    q, rc = oracle.quantize_f32(pts, (-1.0, 0.0), 2.0, lib=lib)
+    # x: floor((0+1)*2)+1 = 3, floor(2.5*2)+1 = 6, floor(1.49*2)+1 = 3, floor(0.5*2)+1 = 2
+    # y: floor(0)+1 = 1, floor(4.5)+1 = 5, floor(1.0)+1 = 2, floor(6)+1 = 7
+    if rc != oracle.OR_OK or q.tolist() != [[3, 1], [6, 5], [3, 2], [2, 7]]:
+        errs.append(f"hand values: {q.tolist()} rc={rc}")
+    q, rc = oracle.quantize_f32(np.array([[np.nan, 1.0], [-3.0, 1.0], [1e12, 1.0]], np.float32), (0.0, 0.0), 1.0,
+                                lib=lib)
+    if rc != oracle.OR_ERANGE or q[:, 0].tolist() != [0, 0, 0] or q[:, 1].tolist() != [2, 2, 2]:
+        errs.append(f"NaN / range: {q.tolist()} rc={rc}")
+    rng = np.random.default_rng(283)
+    a = (rng.standard_normal((5000, 2)) * 1e3).astype(np.float32)
+    a[17] = np.nan
+    a[18] = (1e5, np.nan)    # a NaN y alone also drops the point, extreme x and all
+    box = oracle.bbox_f32(a, lib=lib)
+    ok = ~np.isnan(a).any(1)
+    want = (float(a[ok, 0].min()), float(a[ok, 0].max()), float(a[ok, 1].min()), float(a[ok, 1].max()))
+    if box != want:
+        errs.append(f"float box {box} != {want}")
+    s = 4095 / max(box[1] - box[0], box[3] - box[2])
+    q, rc = oracle.quantize_f32(a[ok], (box[0], box[2]), s, lib=lib)
+    order = np.argsort(a[ok, 0], kind="stable")
+    if rc != oracle.OR_OK or q.min() < 1 or q.max() > 4096 or np.any(np.diff(q[order, 0]) < 0):
+        errs.append("scaled cloud out of [1, 4096] or not monotone")
+    f = fixtures.read("worked_example_p5.txt")
+    base = np.asarray(fixtures.pairs(f["points"]), np.float64)
+    r = oracle.auto_f32(((base - 1) * 0.5 + [-20.25, 7.0]).astype(np.float32), 5, lib=lib)
+    if list(zip(r["lo"].tolist(), r["hi"].tolist())) != fixtures.pairs(f["L"]) or r["scale"] != 2.0:
+        errs.append(f"float worked example: L {list(zip(r['lo'].tolist(), r['hi'].tolist()))}, scale {r['scale']}")
+    if [tuple(v) for v in r["hull"].tolist()] != [(1, 1), (5, 2), (5, 3), (3, 5), (1, 4)]:
+        errs.append(f"float worked example hull {r['hull'].tolist()}")
+    return errs
+
+
 ALL_PINS = [pin_worked_example, pin_gap_example, pin_table1, pin_block_index,
             pin_closed_forms, pin_brute_random, pin_exhaustive_p3, pin_qhull,
-            pin_appendix, pin_invariants, pin_metamorphic, pin_errors, pin_steps12, pin_bitsets, pin_melkman]
+            pin_appendix, pin_invariants, pin_metamorphic, pin_errors, pin_steps12, pin_bitsets, pin_melkman, pin_float_input]
 
 # the cheap pins, run first against planted mistakes
 FAST_PINS = [pin_worked_example, pin_gap_example, pin_table1, pin_block_index,

@@ -52,6 +52,9 @@ MUTANTS = {
                                  "if (or_orient(DQ(top - 1), DQ(top), v) > 0 || or_orient(DQ(bot), DQ(bot + 1), v) > 0) continue;"),
     "melkman-clockwise-start": ("or_orient(a, b, c) > 0 ? a : b;", "or_orient(a, b, c) < 0 ? a : b;"),
     "melkman-orient-term": ("return abx * acy - aby * acx;", "return abx * acy - aby * acy;"),
+    "scale-rounds-up": ("double t = floor(((double)v - o) * s);", "double t = ceil(((double)v - o) * s);"),
+    "scale-origin-added": ("double t = floor(((double)v - o) * s);", "double t = floor(((double)v + o) * s);"),
+    "float-box-keeps-nan": ("if (x != x || y != y) continue;", "if (x != x) continue;"),
     "chain-skips-last": ("for (int32_t i = 1; i <= p; ++i) {\n        if (or_valid(lo[i - 1], hi[i - 1], p)) {\n            x[k] = i;",
                          "for (int32_t i = 1; i < p; ++i) {\n        if (or_valid(lo[i - 1], hi[i - 1], p)) {\n            x[k] = i;"),
 }
@@ -66,7 +69,8 @@ def _build_mutant(tmp_path, name, old, new):
     shutil.copy(os.path.join(ROOT, "oracle", "oracle.h"), d / "oracle.h")
     (d / "oracle.c").write_text(src)
     out = d / "liboracle_mutant.so"
-    subprocess.run(["gcc", "-O1", "-std=c99", "-fPIC", "-shared", "-o", str(out), str(d / "oracle.c")],
+    subprocess.run(["gcc", "-O1", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared", "-o", str(out),
+                    str(d / "oracle.c"), "-lm"],
                    check=True)
     return str(out)
 
