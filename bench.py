@@ -613,7 +613,37 @@ def bench_auto(args, torch, hp, synth) -> dict:
           and np.array_equal(got["clo"], want["clo"]) and np.array_equal(got["chi"], want["chi"])
           and np.array_equal(got["hull"], want["hull"]))
     bbox_ms = (t1 - t0) * 1e3 / steps
+    # float input: the same cloud as float32 (scaled by 1/64, moved), taken
+    # through the float box, the scaling to [1, p]^2 and the path
+    fpts = (pts.to(torch.float64) / 64.0 + 1.0e5).to(torch.float32).contiguous()
+    fbox = torch.empty(4, dtype=torch.float32, device=pts.device)
+    qpts = torch.empty_like(pts)
+    qinfo = torch.zeros(4, dtype=torch.int32, device=pts.device)
+    fx0, fx1, fy0, fy1 = hp.bbox_f32(fpts)
+    scale = (p - 1) / max(fx1 - fx0, fy1 - fy0)
+    fbuf = hp.Buffers.allocate(n, p, pts.device, export_L=False)
+
+    def float_step():
+        hp.hp_bbox_f32(fpts, fbox, ws, stream)
+        hp.hp_quantize_f32(fpts, (fx0, fy0), scale, qpts, qinfo, stream)
+        hp.hp_run(qpts, p, fbuf, stream)
+
+    for _ in range(3):
+        float_step()
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    for _ in range(steps):
+        float_step()
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    fgot = hp.collect(fbuf)
+    fwant = oracle.auto_f32(fpts.cpu().numpy(), p)
+    fok = (fgot["status"] == 0 and int(qinfo[0]) == 0 and fgot["k"] == fwant["k"]
+           and np.array_equal(qpts.cpu().numpy(), fwant["points"]) and np.array_equal(fgot["hull"], fwant["hull"]))
     return {"workload": args.workload, "offset": list(off), "n": n, "p": p, "steps": steps,
+            "float_input": {"ms_per_step_box_scale_path": round((t4 - t3) * 1e3 / steps, 5),
+                            "gpoints_per_s": round(n * steps / (t4 - t3) / 1e9, 3),
+                            "parity_vs_oracle": bool(fok)},
             "bbox_ms_avg": round(bbox_ms, 5), "bbox_gbs": round(8.0 * n / (bbox_ms * 1e-3) / 1e9, 1),
             "gpoints_per_s_bbox_and_path": round(n * steps / (t2 - t1) / 1e9, 3),
             "ms_per_step_bbox_and_path": round((t2 - t1) * 1e3 / steps, 5),

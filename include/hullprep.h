@@ -115,6 +115,25 @@ extern "C" {
  * p = max(xmax - xmin, ymax - ymin) + 1 from hp_bbox every point is in
  * range; p must not exceed HP_P_MAX (the caller checks the extent). */
 int hp_bbox_workspace_bytes(size_t *bytes);
+
+/* Floating-point input (Conclusions: such data is brought to integers by a
+ * suitable scaling).  Points are interleaved float32 pairs, 8-byte aligned.
+ *
+ * hp_bbox_f32: box[0..3] = (xmin, xmax, ymin, ymax) as float32 in device
+ * memory, over the points without a NaN coordinate; (+inf, -inf, +inf, -inf)
+ * when there is none.  Same workspace as hp_bbox.
+ *
+ * hp_quantize_f32: out (device int32 pairs, n of them) = (floor((x - ox) *
+ * scale) + 1, floor((y - oy) * scale) + 1), evaluated in double precision
+ * with one rounding per operation, so results are reproducible bit for bit.
+ * A coordinate that is NaN or outside [1, HP_P_MAX] is written as 0 and sets
+ * info[HP_INFO_STATUS] = HP_ERANGE (device int32[1] at least; HP_OK
+ * otherwise).  With (ox, oy) = (xmin, ymin) from hp_bbox_f32 and scale =
+ * (p - 1) / max(xmax - xmin, ymax - ymin), every point lands in [1, p]^2
+ * and the output can go straight to hp_run with side p. */
+int hp_bbox_f32(const float *pts, int64_t n, float *box, void *ws, size_t ws_bytes, void *stream);
+int hp_quantize_f32(const float *pts, int64_t n, double ox, double oy, double scale, int32_t *out,
+                    int32_t *info, void *stream);
 int hp_bbox(const int32_t *pts, int64_t n, int32_t *box, void *ws, size_t ws_bytes, void *stream);
 int hp_run_origin(const int32_t *pts, int64_t n, int32_t p, int32_t ox, int32_t oy, int32_t *lo,
                   int32_t *hi, uint64_t *mask, int32_t *cx, int32_t *clo, int32_t *chi,

@@ -156,6 +156,99 @@ __global__ __launch_bounds__(kBoxBlock) void k_bbox_fold(const int4 *__restrict_
 }
 
 // ---------------------------------------------------------------------------
+// Float input (the scaling of floating-point data to integers): the box of
+// float points, skipping points with a NaN coordinate, and the scaling
+// X = floor((x - ox) * s) + 1 in double precision, one rounding per
+// operation.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void boxf_add(float4 &b, float x, float y) {
+  if (x != x || y != y) return;
+  b.x = fminf(b.x, x);
+  b.y = fmaxf(b.y, x);
+  b.z = fminf(b.z, y);
+  b.w = fmaxf(b.w, y);
+}
+
+__device__ __forceinline__ float4 boxf_block(float4 b, float4 *s_part) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    b.x = fminf(b.x, __shfl_xor(b.x, d, kWave));
+    b.y = fmaxf(b.y, __shfl_xor(b.y, d, kWave));
+    b.z = fminf(b.z, __shfl_xor(b.z, d, kWave));
+    b.w = fmaxf(b.w, __shfl_xor(b.w, d, kWave));
+  }
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  if (lane == 0) s_part[wave] = b;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int w = 1; w < kBoxBlock / kWave; ++w) {
+      const float4 o = s_part[w];
+      b.x = fminf(b.x, o.x);
+      b.y = fmaxf(b.y, o.y);
+      b.z = fminf(b.z, o.z);
+      b.w = fmaxf(b.w, o.w);
+    }
+  return b;
+}
+
+__global__ __launch_bounds__(kBoxBlock) void k_bbox_f32(const float2 *__restrict__ pts, int64_t n,
+                                                        float4 *__restrict__ part) {
+  __shared__ float4 s_part[kBoxBlock / kWave];
+  float4 b = make_float4(INFINITY, -INFINITY, INFINITY, -INFINITY);
+  const int64_t stride = (int64_t)gridDim.x * kBoxBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBoxBlock + threadIdx.x; i < n; i += stride) {
+    const float2 q = pts[i];
+    boxf_add(b, q.x, q.y);
+  }
+  b = boxf_block(b, s_part);
+  if (threadIdx.x == 0) part[blockIdx.x] = b;
+}
+
+__global__ __launch_bounds__(kBoxBlock) void k_bbox_fold_f32(const float4 *__restrict__ part, int32_t nparts,
+                                                             float *__restrict__ box) {
+  __shared__ float4 s_part[kBoxBlock / kWave];
+  float4 b = make_float4(INFINITY, -INFINITY, INFINITY, -INFINITY);
+  for (int i = threadIdx.x; i < nparts; i += kBoxBlock) {
+    const float4 o = part[i];
+    b.x = fminf(b.x, o.x);
+    b.y = fmaxf(b.y, o.y);
+    b.z = fminf(b.z, o.z);
+    b.w = fmaxf(b.w, o.w);
+  }
+  b = boxf_block(b, s_part);
+  if (threadIdx.x == 0) {
+    box[0] = b.x;
+    box[1] = b.y;
+    box[2] = b.z;
+    box[3] = b.w;
+  }
+}
+
+__device__ __forceinline__ int32_t scale_one(float v, double o, double s, bool &bad) {
+  const double t = floor(__dmul_rn(__dsub_rn((double)v, o), s));
+  if (!(t >= 0.0 && t <= (double)(HP_P_MAX - 1))) {  // also catches NaN
+    bad = true;
+    return 0;
+  }
+  return (int32_t)t + 1;
+}
+
+__global__ void k_quantize_init(int32_t *info) { info[HP_INFO_STATUS] = HP_OK; }
+
+__global__ __launch_bounds__(256) void k_quantize_f32(const float2 *__restrict__ pts, int64_t n, double ox, double oy,
+                                                      double s, int2 *__restrict__ out, int32_t *__restrict__ info) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const float2 q = pts[i];
+    const int32_t x = scale_one(q.x, ox, s, bad);
+    const int32_t y = scale_one(q.y, oy, s, bad);
+    out[i] = make_int2(x, y);
+  }
+  if (bad) info[HP_INFO_STATUS] = HP_ERANGE;
+}
+
+// ---------------------------------------------------------------------------
 // Finish: one workgroup per slab of 64 positions, of FB threads: 1024, or
 // 256 when there are many slabs (the launch is then bound by how fast the
 // dispatcher starts waves, not by the work of a slab).
@@ -2111,3 +2204,41 @@ extern "C" int hp_run_origin(const int32_t *pts, int64_t n, int32_t p, int32_t o
   return run_single(pts, n, p, lo, hi, mask, cx, clo, chi, chain_cap, hx, hy, hull_cap, info, ws, ws_bytes,
                     (hipStream_t)stream, true, ox, oy);
 }
+
+extern "C" int hp_bbox_f32(const float *pts, int64_t n, float *box, void *ws, size_t ws_bytes, void *stream) {
+  if (n < 0) return set_error(HP_EINVAL, "n = %lld < 0", (long long)n);
+  if (n > 0 && !pts) return set_error(HP_EINVAL, "pts is NULL");
+  if (pts && ((uintptr_t)pts & 7)) return set_error(HP_EINVAL, "pts is not 8-byte aligned");
+  if (!box) return set_error(HP_EINVAL, "box is NULL");
+  if (!ws || ws_bytes < sizeof(float4) * (size_t)kBoxMaxGrid)
+    return set_error(HP_ECAPACITY, "bounding-box workspace too small");
+  const int64_t want = (n + 4 * kBoxBlock - 1) / (4 * kBoxBlock);
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(kBoxMaxGrid, 4 * device_info().cus), want));
+  hipStream_t s = (hipStream_t)stream;
+  float4 *part = static_cast<float4 *>(ws);
+  hipLaunchKernelGGL(k_bbox_f32, dim3(grid), dim3(kBoxBlock), 0, s, reinterpret_cast<const float2 *>(pts), n, part);
+  hipLaunchKernelGGL(k_bbox_fold_f32, dim3(1), dim3(kBoxBlock), 0, s, (const float4 *)part, grid, box);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_error(HP_EDEVICE, "k_bbox_f32 launch: %s", hipGetErrorString(e));
+  return HP_OK;
+}
+
+extern "C" int hp_quantize_f32(const float *pts, int64_t n, double ox, double oy, double scale, int32_t *out,
+                               int32_t *info, void *stream) {
+  if (n < 0) return set_error(HP_EINVAL, "n = %lld < 0", (long long)n);
+  if (n > 0 && (!pts || !out)) return set_error(HP_EINVAL, "pts or out is NULL");
+  if ((pts && ((uintptr_t)pts & 7)) || (out && ((uintptr_t)out & 7)))
+    return set_error(HP_EINVAL, "pts or out is not 8-byte aligned");
+  if (!info) return set_error(HP_EINVAL, "info is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_quantize_init, dim3(1), dim3(1), 0, s, info);
+  if (n > 0) {
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(8 * device_info().cus, (n + 255) / 256));
+    hipLaunchKernelGGL(k_quantize_f32, dim3(grid), dim3(256), 0, s, reinterpret_cast<const float2 *>(pts), n, ox, oy,
+                       scale, reinterpret_cast<int2 *>(out), info);
+  }
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_error(HP_EDEVICE, "k_quantize_f32 launch: %s", hipGetErrorString(e));
+  return HP_OK;
+}
+

@@ -277,6 +277,66 @@ def bitset_roundtrip(cols: torch.Tensor, p: int, tree: bool, cap: int | None = N
             "cols": out[:min(k, out.numel() if cap != 0 else 0)].cpu().numpy()}
 
 
+def _check_points_f32(points: torch.Tensor) -> int:
+    if not points.is_cuda or points.dtype != torch.float32 or points.dim() != 2 or points.shape[1] != 2:
+        raise ValueError("points must be an (n, 2) float32 device tensor")
+    if not points.is_contiguous():
+        raise ValueError("points must be contiguous")
+    return points.shape[0]
+
+
+def hp_bbox_f32(points: torch.Tensor, box: torch.Tensor, ws: torch.Tensor, stream=None) -> None:
+    """Enqueue the float box into ``box`` (float32, 4 entries; no sync)."""
+    n = _check_points_f32(points)
+    if box.dtype != torch.float32 or box.numel() < 4 or not box.is_cuda:
+        raise ValueError("box must be a float32 device tensor of 4 entries")
+    _lib.call("hp_bbox_f32", _ptr(points), n, _ptr(box), _ptr(ws), ws.numel(), _stream(stream))
+
+
+def bbox_f32(points: torch.Tensor, stream=None) -> tuple[float, float, float, float]:
+    """(xmin, xmax, ymin, ymax) of float points (NaN points skipped), on the device."""
+    ws = torch.empty(bbox_workspace_bytes(), dtype=torch.uint8, device=points.device)
+    box = torch.empty(4, dtype=torch.float32, device=points.device)
+    hp_bbox_f32(points, box, ws, stream)
+    torch.cuda.synchronize(points.device)
+    return tuple(float(v) for v in box.cpu().tolist())
+
+
+def hp_quantize_f32(points: torch.Tensor, origin, scale: float, out: torch.Tensor, info: torch.Tensor,
+                    stream=None) -> None:
+    """Enqueue the scaling of float points to int32 points (no sync)."""
+    n = _check_points_f32(points)
+    if out.dtype != torch.int32 or tuple(out.shape) != (n, 2) or not out.is_contiguous():
+        raise ValueError("out must be a contiguous (n, 2) int32 device tensor")
+    _lib.call("hp_quantize_f32", _ptr(points), n, float(origin[0]), float(origin[1]), float(scale), _ptr(out),
+              _ptr(info), _stream(stream))
+
+
+def run_auto_f32(points: torch.Tensor, p: int, export_L: bool = True) -> dict:
+    """Float points through the path: the float box on the device, origin
+    (xmin, ymin) and scale (p - 1) / max extent, the scaling on the device,
+    then the fused path with side p on the integer points."""
+    n = _check_points_f32(points)
+    if n == 0:
+        raise HullprepError(HP_EINVAL, "run_auto_f32", "no points")
+    xmin, xmax, ymin, ymax = bbox_f32(points)
+    ext = max(xmax - xmin, ymax - ymin)
+    if not ext == ext or ext == float("inf") or xmin > xmax:
+        raise HullprepError(HP_EINVAL, "run_auto_f32", "no finite points")
+    scale = (p - 1) / ext if ext > 0 else 1.0
+    q = torch.empty((n, 2), dtype=torch.int32, device=points.device)
+    qinfo = torch.zeros(4, dtype=torch.int32, device=points.device)
+    hp_quantize_f32(points, (xmin, ymin), scale, q, qinfo)
+    buf = Buffers.allocate(n, p, points.device, export_L)
+    hp_run(q, p, buf)
+    out = collect(buf)
+    qs = int(qinfo[HP_INFO_STATUS].item())
+    if qs != 0:
+        out["status"] = qs
+    out.update({"box": (xmin, xmax, ymin, ymax), "scale": scale, "origin": (xmin, ymin), "points": q.cpu().numpy()})
+    return out
+
+
 def collect(buf: Buffers) -> dict:
     """Synchronise and return host copies of every output (trimmed)."""
     torch.cuda.synchronize(buf.info.device)

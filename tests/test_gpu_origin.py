@@ -109,3 +109,77 @@ def test_origin_equals_translated_copy(hp):
     got = hp.collect(buf)
     for key in ("status", "k", "s", "h", "lo", "hi", "mask", "x", "clo", "chi", "hull"):
         assert np.array_equal(np.asarray(got[key]), np.asarray(ref[key])), key
+
+
+# ---------------------------------------------------------------------------
+# Float input: the float box and the scaling to integers
+# ---------------------------------------------------------------------------
+def _floats(n, seed, spread=1e3, nan_every=0):
+    rng = np.random.default_rng(seed)
+    a = (rng.standard_normal((n, 2)) * spread + rng.uniform(-1e4, 1e4, size=2)).astype(np.float32)
+    if nan_every:
+        a[::nan_every, int(seed) % 2] = np.nan
+    return a
+
+
+@pytest.mark.parametrize("n,shift,nan_every", [(1, 0, 0), (7, 1, 0), (1000, 0, 7), (3_000_001, 1, 1001)])
+def test_bbox_f32(hp, n, shift, nan_every):
+    a = _floats(n + shift, n, nan_every=nan_every)
+    print(f"[case] bbox_f32 n={n} shift={shift}", flush=True)
+    got = hp.bbox_f32(torch.from_numpy(a).cuda()[shift:])
+    assert got == oracle.bbox_f32(a[shift:])
+
+
+@pytest.mark.parametrize("scale", [1.0, 0.37, 4095 / 7.5, 1e-3])
+def test_quantize_f32(hp, scale):
+    a = _floats(200_001, 3, spread=50.0)
+    # values sitting exactly on and next to cell boundaries of the scaling
+    k = np.arange(-500, 500, dtype=np.float64)
+    edge = (k / scale).astype(np.float32)
+    a[:1000, 0] = edge
+    a[1000:2000, 0] = np.nextafter(edge, np.float32(-np.inf))
+    a[2000:3000, 1] = np.nextafter(edge, np.float32(np.inf))
+    origin = (float(np.nanmin(a[:, 0])), float(np.nanmin(a[:, 1])))
+    print(f"[case] quantize scale={scale}", flush=True)
+    want, rc = oracle.quantize_f32(a, origin, scale)
+    dev = torch.from_numpy(a).cuda()
+    out = torch.empty((a.shape[0], 2), dtype=torch.int32, device="cuda")
+    info = torch.ones(4, dtype=torch.int32, device="cuda")
+    hp.hp_quantize_f32(dev, origin, scale, out, info)
+    torch.cuda.synchronize()
+    assert int(info[0]) == rc
+    assert np.array_equal(out.cpu().numpy(), want)
+
+
+def test_quantize_reports(hp):
+    a = np.array([[np.nan, 1.0], [-3.0, 1.0], [1e12, 1.0], [2.0, 2.0]], np.float32)
+    want, rc = oracle.quantize_f32(a, (0.0, 0.0), 1.0)
+    out = torch.empty((4, 2), dtype=torch.int32, device="cuda")
+    info = torch.zeros(4, dtype=torch.int32, device="cuda")
+    hp.hp_quantize_f32(torch.from_numpy(a).cuda(), (0.0, 0.0), 1.0, out, info)
+    torch.cuda.synchronize()
+    assert rc == -2 and int(info[0]) == -2
+    assert np.array_equal(out.cpu().numpy(), want)
+
+
+@pytest.mark.parametrize("n,p,seed", [(1000, 64, 1), (300_000, 4096, 2), (1_000_000, 16_384, 3)])
+def test_run_auto_f32(hp, n, p, seed):
+    a = _floats(n, seed)
+    print(f"[case] run_auto_f32 n={n} p={p}", flush=True)
+    want = oracle.auto_f32(a, p)
+    got = hp.run_auto_f32(torch.from_numpy(a).cuda(), p)
+    assert got["box"] == want["box"] and got["scale"] == want["scale"]
+    assert np.array_equal(got["points"], want["points"])
+    assert got["status"] == 0 and got["k"] == want["k"]
+    for key in ("lo", "hi", "mask", "x", "clo", "chi", "hull"):
+        assert np.array_equal(got[key], want[key]), key
+
+
+def test_run_auto_f32_worked_example(hp):
+    from tests.golden import fixtures
+    f = fixtures.read("worked_example_p5.txt")
+    base = np.asarray(fixtures.pairs(f["points"]), np.float64)
+    a = ((base - 1) * 0.5 + [-20.25, 7.0]).astype(np.float32)
+    got = hp.run_auto_f32(torch.from_numpy(a).cuda(), 5)
+    assert list(zip(got["lo"].tolist(), got["hi"].tolist())) == fixtures.pairs(f["L"])
+    assert [tuple(v) for v in got["hull"].tolist()] == [(1, 1), (5, 2), (5, 3), (3, 5), (1, 4)]
