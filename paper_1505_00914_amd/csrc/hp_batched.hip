@@ -78,13 +78,16 @@ void BatchTables::clear() {
 void BatchTables::add_cloud(int64_t n, int32_t p, const TreeShape &T, int64_t lds_p_max) {
   const int32_t b = B++;
   maxlev = std::max(maxlev, T.nlev);
-  // reduce: a dense cloud (n >= 4p, L fits in LDS, and the tuning table
-  // picks an LDS strategy for its (n, p) regime) goes through LDS, whole when
-  // it fits one item, else in chunks merged by atomics; any other cloud
-  // folds straight into its L in device memory
+  // reduce: a cloud whose L fits in LDS goes through LDS when it is dense
+  // (n >= 4p and the tuning table picks an LDS strategy for its (n, p)
+  // regime), whole when it fits one item, else in chunks merged by atomics,
+  // and also when it is sparse (n < 4p, always one item): a whole-cloud item
+  // writes its L once, where folding straight into device memory would cost
+  // a device-scope atomic for nearly every point.  Any other cloud folds
+  // straight into its L in device memory.
   const int tuned = tuned_strategy(n, p);
   const bool lds_family = tuned == HP_STRATEGY_LDS || tuned == HP_STRATEGY_LDS_PARTIAL;
-  const bool dense = (int64_t)p <= lds_p_max && n >= 4 * (int64_t)p && lds_family;
+  const bool dense = (int64_t)p <= lds_p_max && (n >= 4 * (int64_t)p ? lds_family : n <= chunk_for(p));
   uint8_t fill = 1;
   if (n > 0) {
     const int64_t chunk = chunk_for(p);
