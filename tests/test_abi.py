@@ -150,3 +150,29 @@ def test_bitset_sizes_match_the_tree_of_the_text():
     assert lib.hp_bitset_words(0, 1, ctypes.byref(w)) == _lib.HP_EINVAL
     assert lib.hp_bitset_insert(None, 5, 10, 0, None, None, None) == _lib.HP_EINVAL
     assert lib.hp_bitset_extract(None, 10, 0, None, 0, None, None, 0, None) == _lib.HP_EINVAL
+
+
+def test_new_entry_points_reject_bad_arguments_before_any_device_call():
+    """Bounding box, origin run, float scaling and Melkman: argument errors
+    come back synchronously, with no device call made."""
+    lib = _lib.load()
+    E = _lib.HP_EINVAL
+    size = ctypes.c_size_t()
+    assert lib.hp_bbox_workspace_bytes(ctypes.byref(size)) == 0 and size.value > 0
+    assert lib.hp_bbox(None, -1, None, None, 0, None) == E
+    assert lib.hp_bbox(None, 5, None, None, 0, None) == E
+    assert lib.hp_bbox(ctypes.c_void_p(8), 5, None, None, 0, None) == E           # box NULL
+    assert lib.hp_bbox(ctypes.c_void_p(12), 5, ctypes.c_void_p(16), None, 0, None) == E  # misaligned
+    assert lib.hp_bbox(ctypes.c_void_p(8), 5, ctypes.c_void_p(16), ctypes.c_void_p(32), 0, None) == \
+        _lib.HP_ECAPACITY
+    assert lib.hp_bbox_f32(None, 3, None, None, 0, None) == E
+    assert lib.hp_quantize_f32(None, 3, 0.0, 0.0, 1.0, None, None, None) == E
+    assert lib.hp_quantize_f32(ctypes.c_void_p(8), 3, 0.0, 0.0, 1.0, ctypes.c_void_p(16), None, None) == E
+    assert lib.hp_run_origin(None, 10, 0, 0, 0, None, None, None, None, None, None, 0, None, None, 0, None,
+                             None, 0, None) == E
+    assert lib.hp_hull_melkman_workspace_bytes(-1, ctypes.byref(size)) == E
+    assert lib.hp_hull_melkman_workspace_bytes(4096, ctypes.byref(size)) == 0 and size.value == 8 * (4 * 4096 + 4)
+    assert lib.hp_hull_melkman(None, None, None, 4, None, None, 8, None, None, 0, None) == E
+    assert lib.hp_hull_melkman(ctypes.c_void_p(8), ctypes.c_void_p(8), ctypes.c_void_p(8), 4, ctypes.c_void_p(8),
+                               ctypes.c_void_p(8), 7, ctypes.c_void_p(8), None, 0, None) == _lib.HP_ECAPACITY
+    assert lib.hp_last_error().decode()
