@@ -654,7 +654,9 @@ def bench_bits(args, torch, hp) -> dict:
     """The text's bit-vector experiment on the device: s distinct columns of
     p = 2^24, in random order, inserted into the bit array or the w-ary tree
     (after a clear) and then extracted in ascending order, for densities
-    s/p from 5 % to 85 %.  Times are per phase, averaged over the steps."""
+    s/p from 5 % to 85 %.  The inserts run one device atomic per column, or
+    as the partitioned bulk build ("_bulk").  Times are per phase, averaged
+    over the steps."""
     import numpy as np
 
     import oracle
@@ -675,17 +677,25 @@ def bench_bits(args, torch, hp) -> dict:
         cols = perm[:s].contiguous()
         want = None
         row = {"density": density, "s": s}
-        for tree in (False, True):
+        bws = torch.empty(max(1, hp.bitset_build_workspace_bytes(s, p)), dtype=torch.uint8, device=dev)
+        for tree, bulk in ((False, False), (True, False), (False, True), (True, True)):
             words = torch.empty(hp.bitset_words(p, tree), dtype=torch.int64, device=dev)
             ev = [torch.cuda.Event(enable_timing=True) for _ in range(3 * steps)]
+
+            def insert():
+                if bulk:
+                    hp.hp_bitset_build(cols, p, tree, words, info, bws, stream)
+                else:
+                    hp.hp_bitset_insert(cols, p, tree, words, info, stream)
+
             for i in range(2):
                 hp.hp_bitset_clear(words, stream)
-                hp.hp_bitset_insert(cols, p, tree, words, info, stream)
+                insert()
                 hp.hp_bitset_extract(words, p, tree, out, info, ws, stream)
             for i in range(steps):
                 ev[3 * i].record(stream)
                 hp.hp_bitset_clear(words, stream)
-                hp.hp_bitset_insert(cols, p, tree, words, info, stream)
+                insert()
                 ev[3 * i + 1].record(stream)
                 hp.hp_bitset_extract(words, p, tree, out, info, ws, stream)
                 ev[3 * i + 2].record(stream)
@@ -696,14 +706,14 @@ def bench_bits(args, torch, hp) -> dict:
             if want is None:
                 want = oracle.extract(oracle.array_insert(cols.cpu().numpy(), p), p)
             ok = int(info[0]) == 0 and int(info[1]) == s and np.array_equal(got, want)
-            key = "tree" if tree else "array"
+            key = ("tree" if tree else "array") + ("_bulk" if bulk else "")
             row[key] = {"insert_us": round(ins * 1e3, 2), "extract_us": round(ext * 1e3, 2),
                         "total_us": round((ins + ext) * 1e3, 2),
                         "ns_per_set_bit": round((ins + ext) * 1e6 / s, 4), "parity_vs_oracle": bool(ok)}
         rows.append(row)
     # least-squares slope of total time against s, as the text regresses its timings
     fit = {}
-    for key in ("array", "tree"):
+    for key in ("array", "tree", "array_bulk", "tree_bulk"):
         x = np.array([r["s"] for r in rows], float)
         y = np.array([r[key]["total_us"] * 1e-6 for r in rows])
         fit[key + "_seconds_per_set_bit"] = float(np.polyfit(x, y, 1)[0])

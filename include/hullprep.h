@@ -166,6 +166,18 @@ int hp_bitset_clear(uint64_t *words, int64_t nwords, void *stream);
 int hp_bitset_insert(const int32_t *cols, int64_t s, int32_t p, int32_t tree, uint64_t *words, int32_t *info,
                      void *stream);
 int hp_bitset_extract_workspace_bytes(int32_t p, size_t *bytes);
+
+/* hp_bitset_build: the same result as hp_bitset_insert (the columns ORed into
+ * the storage, and with a tree every level above), built without device-
+ * scope atomics on level 0: the columns are partitioned by window of
+ * level-0 words, each window is assembled in LDS and stored once, and the
+ * tree's upper levels are set from the finished words.  ws is caller-owned
+ * device memory of hp_bitset_build_workspace_bytes(s, p) bytes (0 when the
+ * shape is too small to partition, p < 2^18 or so: the call then performs
+ * hp_bitset_insert).  info as for hp_bitset_insert. */
+int hp_bitset_build_workspace_bytes(int64_t s, int32_t p, size_t *bytes);
+int hp_bitset_build(const int32_t *cols, int64_t s, int32_t p, int32_t tree, uint64_t *words, int32_t *info,
+                    void *ws, size_t ws_bytes, void *stream);
 int hp_bitset_extract(const uint64_t *words, int32_t p, int32_t tree, int32_t *cols, int32_t cap, int32_t *info,
                       void *ws, size_t ws_bytes, void *stream);
 

@@ -49,6 +49,8 @@ SIGNATURES = {
     "hp_bitset_clear": (ctypes.c_int, [_vp, _i64, _vp]),
     "hp_bitset_insert": (ctypes.c_int, [_vp, _i64, _i32, _i32, _vp, _vp, _vp]),
     "hp_bitset_extract_workspace_bytes": (ctypes.c_int, [_i32, _szp]),
+    "hp_bitset_build_workspace_bytes": (ctypes.c_int, [_i64, _i32, _szp]),
+    "hp_bitset_build": (ctypes.c_int, [_vp, _i64, _i32, _i32, _vp, _vp, _vp, _sz, _vp]),
     "hp_bitset_extract": (ctypes.c_int, [_vp, _i32, _i32, _vp, _i32, _vp, _vp, _sz, _vp]),
     "hp_bbox_workspace_bytes": (ctypes.c_int, [_szp]),
     "hp_bbox_f32": (ctypes.c_int, [_vp, _i64, _vp, _vp, _sz, _vp]),

@@ -191,6 +191,148 @@ __global__ __launch_bounds__(kBitsBlock) void k_bits_write(const uint64_t *__res
   }
 }
 
+// ---------------------------------------------------------------------------
+// Bulk build: the same result as the inserts, without device-scope atomics
+// on level 0.  The columns are partitioned by window (a run of 64-word-aligned
+// level-0 words) with a counting pass, a scan and a scatter; then one
+// workgroup per window ORs its columns into an LDS bitmap and writes its
+// words (old | new) with plain stores, and with a tree sets the level-1 words
+// over them by ballot (a window owns whole level-1 words) and carries the
+// non-zero level-1 words up with a few atomics.
+// ---------------------------------------------------------------------------
+constexpr int kPartBlock = 256;
+constexpr int kPartMaxWinWords = 2048;   // level-0 words per window (16 KB of LDS)
+constexpr int64_t kPartMaxHist = 65536;  // windows x chunks
+
+struct PartShape {
+  int32_t wshift;   // log2 of the columns per window
+  int32_t nwin, nchunk;
+  int64_t per;      // columns per chunk
+  bool bulk;        // false: use the atomic inserts
+};
+
+static PartShape part_shape(int64_t s, int32_t p) {
+  PartShape P{};
+  const int64_t W0 = ((int64_t)p + 63) / 64;
+  int64_t ww = 64;
+  while (ww < kPartMaxWinWords && ww * 256 < W0) ww <<= 1;
+  int sh = 0;
+  while ((64ll << sh) < ww * 64) ++sh;
+  P.wshift = 6 + sh;  // ww * 64 columns = 2^(6 + sh)
+  P.nwin = (int32_t)((W0 + ww - 1) / ww);
+  const int64_t want = (s + 8191) / 8192;
+  const int64_t cap = std::max<int64_t>(1, std::min<int64_t>(1024, kPartMaxHist / P.nwin));
+  P.nchunk = (int32_t)std::max<int64_t>(1, std::min(want, cap));
+  P.per = (s + P.nchunk - 1) / P.nchunk;
+  P.bulk = P.nwin >= 64 && s < (int64_t)INT_MAX && (int64_t)P.nwin <= 16384;
+  return P;
+}
+
+__global__ __launch_bounds__(kPartBlock) void k_part_count(const int32_t *__restrict__ cols, int64_t s, int32_t p,
+                                                           PartShape P, int32_t *__restrict__ hist,
+                                                           int32_t *__restrict__ info) {
+  extern __shared__ int32_t s_cnt[];
+  for (int w = threadIdx.x; w < P.nwin; w += kPartBlock) s_cnt[w] = 0;
+  __syncthreads();
+  const int64_t j0 = (int64_t)blockIdx.x * P.per, j1 = j0 + P.per < s ? j0 + P.per : s;
+  bool bad = false;
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += kPartBlock) {
+    const int32_t c = cols[j];
+    if ((unsigned)(c - 1) >= (unsigned)p) {
+      bad = true;
+      continue;
+    }
+    atomicAdd(&s_cnt[(unsigned)(c - 1) >> P.wshift], 1);
+  }
+  __syncthreads();
+  for (int w = threadIdx.x; w < P.nwin; w += kPartBlock) hist[(int64_t)w * P.nchunk + blockIdx.x] = s_cnt[w];
+  if (bad) info[HP_INFO_STATUS] = HP_ERANGE;
+}
+
+// One workgroup: exclusive offsets of the h window-major counts, total at [h].
+__global__ __launch_bounds__(kBitsScanBlock) void k_part_scan(const int32_t *__restrict__ hist, int64_t h,
+                                                              int64_t *__restrict__ off) {
+  __shared__ int64_t s_sum[kBitsScanBlock];
+  const int64_t per = (h + kBitsScanBlock - 1) / kBitsScanBlock;
+  const int64_t b0 = (int64_t)threadIdx.x * per, b1 = b0 + per < h ? b0 + per : h;
+  int64_t mine = 0;
+  for (int64_t b = b0; b < b1; ++b) mine += hist[b];
+  s_sum[threadIdx.x] = mine;
+  __syncthreads();
+  for (int d = 1; d < kBitsScanBlock; d <<= 1) {
+    const int64_t add = threadIdx.x >= (unsigned)d ? s_sum[threadIdx.x - d] : 0;
+    __syncthreads();
+    s_sum[threadIdx.x] += add;
+    __syncthreads();
+  }
+  int64_t run = s_sum[threadIdx.x] - mine;
+  for (int64_t b = b0; b < b1; ++b) {
+    off[b] = run;
+    run += hist[b];
+  }
+  if (threadIdx.x == kBitsScanBlock - 1) off[h] = s_sum[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kPartBlock) void k_part_scatter(const int32_t *__restrict__ cols, int64_t s, int32_t p,
+                                                             PartShape P, const int64_t *__restrict__ off,
+                                                             int32_t *__restrict__ part) {
+  extern __shared__ int32_t s_cur[];
+  for (int w = threadIdx.x; w < P.nwin; w += kPartBlock) s_cur[w] = 0;
+  __syncthreads();
+  const int64_t j0 = (int64_t)blockIdx.x * P.per, j1 = j0 + P.per < s ? j0 + P.per : s;
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += kPartBlock) {
+    const int32_t c = cols[j];
+    if ((unsigned)(c - 1) >= (unsigned)p) continue;
+    const int w = (int)((unsigned)(c - 1) >> P.wshift);
+    const int k = atomicAdd(&s_cur[w], 1);
+    part[off[(int64_t)w * P.nchunk + blockIdx.x] + k] = c;
+  }
+}
+
+template <bool TREE>
+__global__ __launch_bounds__(kPartBlock) void k_part_window(const int32_t *__restrict__ part,
+                                                            const int64_t *__restrict__ off, PartShape P,
+                                                            int64_t W0, uint64_t *__restrict__ words,
+                                                            BitLevels L) {
+  __shared__ unsigned long long s_bm[kPartMaxWinWords];
+  const int64_t ww = 1ll << (P.wshift - 6);
+  const int64_t g0 = (int64_t)blockIdx.x * ww;
+  for (int t = threadIdx.x; t < ww; t += kPartBlock) s_bm[t] = 0;
+  __syncthreads();
+  const int64_t i0 = off[(int64_t)blockIdx.x * P.nchunk], i1 = off[(int64_t)(blockIdx.x + 1) * P.nchunk];
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += kPartBlock) {
+    const uint32_t b = (uint32_t)(part[i] - 1);
+    atomicOr(&s_bm[(int64_t)(b >> 6) - g0], 1ull << (b & 63));
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & (kWave - 1);
+  for (int64_t t0 = 0; t0 < ww; t0 += kPartBlock) {
+    const int64_t t = t0 + threadIdx.x, g = g0 + t;
+    uint64_t v = 0;
+    if (t < ww && g < W0) {
+      v = words[g] | s_bm[t];
+      words[g] = v;
+    }
+    if (TREE && L.levels > 1) {
+      // a wave covers 64 consecutive level-0 words: one level-1 word
+      const unsigned long long nz = __ballot(v != 0);
+      const int64_t g1 = g >> 6;
+      if (lane == 0 && t < ww && g < W0 && nz) {
+        const uint64_t old = words[L.off[1] + g1];
+        words[L.off[1] + g1] = old | nz;
+        if (old == 0) {  // the level-1 word became non-zero: carry it up
+          uint64_t bit = (uint64_t)g1;
+          unsigned long long o = 0;
+          for (int k = 2; k < L.levels && o == 0; ++k) {
+            o = atomicOr((unsigned long long *)&words[L.off[k] + (bit >> 6)], 1ull << (bit & 63));
+            bit >>= 6;
+          }
+        }
+      }
+    }
+  }
+}
+
 static int64_t bits_blocks(int32_t p) {
   const int64_t W0 = ((int64_t)p + 63) / 64;
   return (W0 + kBitsBlock - 1) / kBitsBlock;
@@ -278,3 +420,51 @@ extern "C" int hp_bitset_extract(const uint64_t *words, int32_t p, int32_t tree,
   if (e != hipSuccess) return set_error(HP_EDEVICE, "bit extraction launch: %s", hipGetErrorString(e));
   return HP_OK;
 }
+
+extern "C" int hp_bitset_build_workspace_bytes(int64_t s, int32_t p, size_t *bytes) {
+  if (p < 1 || p > HP_P_MAX) return set_error(HP_EINVAL, "p = %d outside [1, %d]", p, HP_P_MAX);
+  if (s < 0 || !bytes) return set_error(HP_EINVAL, "bad argument");
+  const PartShape P = part_shape(s, p);
+  const int64_t h = (int64_t)P.nwin * P.nchunk;
+  *bytes = P.bulk ? align256(sizeof(int32_t) * (size_t)s) + align256(sizeof(int32_t) * (size_t)h) +
+                        align256(sizeof(int64_t) * (size_t)(h + 1))
+                  : 0;
+  return HP_OK;
+}
+
+extern "C" int hp_bitset_build(const int32_t *cols, int64_t s, int32_t p, int32_t tree, uint64_t *words,
+                               int32_t *info, void *ws, size_t ws_bytes, void *stream) {
+  if (p < 1 || p > HP_P_MAX) return set_error(HP_EINVAL, "p = %d outside [1, %d]", p, HP_P_MAX);
+  if (s < 0) return set_error(HP_EINVAL, "s < 0");
+  if ((s > 0 && !cols) || !words || !info) return set_error(HP_EINVAL, "NULL argument");
+  const PartShape P = part_shape(s, p);
+  if (!P.bulk || s == 0) return hp_bitset_insert(cols, s, p, tree, words, info, stream);
+  size_t need = 0;
+  hp_bitset_build_workspace_bytes(s, p, &need);
+  if (!ws || ws_bytes < need) return set_error(HP_ECAPACITY, "workspace %zu < %zu bytes", ws_bytes, need);
+  const int64_t h = (int64_t)P.nwin * P.nchunk;
+  char *w = static_cast<char *>(ws);
+  int32_t *part = reinterpret_cast<int32_t *>(w);
+  int32_t *hist = reinterpret_cast<int32_t *>(w + align256(sizeof(int32_t) * (size_t)s));
+  int64_t *off = reinterpret_cast<int64_t *>(w + align256(sizeof(int32_t) * (size_t)s) +
+                                             align256(sizeof(int32_t) * (size_t)h));
+  const BitLevels L = bit_levels(p, tree);
+  const int64_t W0 = ((int64_t)p + 63) / 64;
+  const size_t lds = sizeof(int32_t) * (size_t)P.nwin;
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_bits_info, dim3(1), dim3(1), 0, st, info);
+  hipLaunchKernelGGL(k_part_count, dim3(P.nchunk), dim3(kPartBlock), lds, st, cols, s, p, P, hist, info);
+  hipLaunchKernelGGL(k_part_scan, dim3(1), dim3(kBitsScanBlock), 0, st, (const int32_t *)hist, h, off);
+  hipLaunchKernelGGL(k_part_scatter, dim3(P.nchunk), dim3(kPartBlock), lds, st, cols, s, p, P,
+                     (const int64_t *)off, part);
+  if (tree)
+    hipLaunchKernelGGL(k_part_window<true>, dim3(P.nwin), dim3(kPartBlock), 0, st, (const int32_t *)part,
+                       (const int64_t *)off, P, W0, words, L);
+  else
+    hipLaunchKernelGGL(k_part_window<false>, dim3(P.nwin), dim3(kPartBlock), 0, st, (const int32_t *)part,
+                       (const int64_t *)off, P, W0, words, L);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_error(HP_EDEVICE, "bulk build launch: %s", hipGetErrorString(e));
+  return HP_OK;
+}
+

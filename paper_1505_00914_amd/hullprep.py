@@ -258,16 +258,42 @@ def hp_bitset_extract(words: torch.Tensor, p: int, tree: bool, cols: torch.Tenso
               _ptr(ws), ws.numel(), _stream(stream))
 
 
-def bitset_roundtrip(cols: torch.Tensor, p: int, tree: bool, cap: int | None = None) -> dict:
-    """Clear, insert ``cols`` and extract, on the device; host copies back."""
+def bitset_build_workspace_bytes(s: int, p: int) -> int:
+    size = ctypes.c_size_t()
+    _lib.call("hp_bitset_build_workspace_bytes", s, p, ctypes.byref(size))
+    return size.value
+
+
+def hp_bitset_build(cols: torch.Tensor, p: int, tree: bool, words: torch.Tensor, info: torch.Tensor,
+                    ws: torch.Tensor | None, stream=None) -> None:
+    """Enqueue the bulk build (same result as hp_bitset_insert)."""
+    if cols.dtype != torch.int32 or not cols.is_cuda or not cols.is_contiguous():
+        raise ValueError("cols must be a contiguous int32 device tensor")
+    if words.dtype != torch.int64 or words.numel() < bitset_words(p, tree):
+        raise ValueError("words must be an int64 device tensor of bitset_words(p, tree) entries")
+    _lib.call("hp_bitset_build", _ptr(cols), cols.numel(), p, int(tree), _ptr(words), _ptr(info), _ptr(ws),
+              0 if ws is None else ws.numel(), _stream(stream))
+
+
+def bitset_roundtrip(cols: torch.Tensor, p: int, tree: bool, cap: int | None = None, bulk: bool = False,
+                     words: torch.Tensor | None = None) -> dict:
+    """Clear (unless ``words`` is given), insert ``cols`` (or build them in
+    bulk) and extract, on the device; host copies back."""
     dev = cols.device
-    words = torch.empty(bitset_words(p, tree), dtype=torch.int64, device=dev)
+    fresh = words is None
+    if fresh:
+        words = torch.empty(bitset_words(p, tree), dtype=torch.int64, device=dev)
     info_i = torch.zeros(2, dtype=torch.int32, device=dev)
     info_e = torch.zeros(2, dtype=torch.int32, device=dev)
     out = torch.empty(max(1, p if cap is None else cap), dtype=torch.int32, device=dev)
     ws = torch.empty(bitset_extract_workspace_bytes(p), dtype=torch.uint8, device=dev)
-    hp_bitset_clear(words)
-    hp_bitset_insert(cols, p, tree, words, info_i)
+    if fresh:
+        hp_bitset_clear(words)
+    if bulk:
+        bws = torch.empty(max(1, bitset_build_workspace_bytes(cols.numel(), p)), dtype=torch.uint8, device=dev)
+        hp_bitset_build(cols, p, tree, words, info_i, bws)
+    else:
+        hp_bitset_insert(cols, p, tree, words, info_i)
     hp_bitset_extract(words, p, tree, out if cap != 0 else out[:0], info_e, ws)
     torch.cuda.synchronize(dev)
     ii, ie = info_i.cpu().tolist(), info_e.cpu().tolist()

@@ -32,9 +32,9 @@ def _cols(kind, p, density, seed):
     return c
 
 
-def _check(hp, cols, p, tree, label):
-    print(f"[case] {label} p={p} s={cols.shape[0]} tree={tree}", flush=True)
-    got = hp.bitset_roundtrip(torch.from_numpy(cols).cuda(), p, tree)
+def _check(hp, cols, p, tree, label, bulk=False):
+    print(f"[case] {label} p={p} s={cols.shape[0]} tree={tree} bulk={bulk}", flush=True)
+    got = hp.bitset_roundtrip(torch.from_numpy(cols).cuda(), p, tree, bulk=bulk)
     want_words = oracle.tree_insert(cols, p) if tree else oracle.array_insert(cols, p)
     want = oracle.tree_extract(want_words, p) if tree else oracle.extract(want_words, p)
     assert got["insert_status"] == 0 and got["status"] == 0, label
@@ -111,3 +111,46 @@ def test_tree_skips_words_its_summary_marks_empty(hp):
     hp.hp_bitset_extract(words, p, False, out, info, ws)
     torch.cuda.synchronize()
     assert out[:int(info[1])].cpu().tolist() == [5, 70, 74, 4000, (30_000 - 1) // 64 * 64 + 4, 65_000]
+
+
+# ---------------------------------------------------------------------------
+# Bulk build: partitioned by window, assembled in LDS
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("tree", [False, True])
+@pytest.mark.parametrize("p", [70_000, (1 << 18) - 1, 1 << 18, (1 << 18) + 3, 3_000_017, 1 << 24, (1 << 26) + 5])
+def test_bulk_build(hp, p, tree):
+    for kind, density in [("uniform", 0.3), ("distinct", 0.05), ("clustered", 0.01)]:
+        _check(hp, _cols(kind, p, density, p + 3 * tree), p, tree, f"bulk-{kind}-{density}", bulk=True)
+
+
+@pytest.mark.parametrize("tree", [False, True])
+@pytest.mark.parametrize("density", [0.05, 0.85])
+def test_bulk_build_2p24(hp, density, tree):
+    _check(hp, _cols("distinct", 1 << 24, density, 13), 1 << 24, tree, f"bulk-2^24-{density}", bulk=True)
+
+
+@pytest.mark.parametrize("tree", [False, True])
+def test_bulk_build_onto_existing_words(hp, tree):
+    """Two builds in a row OR into what is there, like two inserts."""
+    p = 1 << 22
+    a, b = _cols("distinct", p, 0.02, 1), _cols("clustered", p, 0.01, 2)
+    words = torch.zeros(hp.bitset_words(p, tree), dtype=torch.int64, device="cuda")
+    hp.bitset_roundtrip(torch.from_numpy(a).cuda(), p, tree, bulk=True, words=words)
+    got = hp.bitset_roundtrip(torch.from_numpy(b).cuda(), p, tree, bulk=True, words=words)
+    both = np.concatenate([a, b])
+    want_words = oracle.tree_insert(both, p) if tree else oracle.array_insert(both, p)
+    assert np.array_equal(got["words"], want_words)
+    assert np.array_equal(got["cols"], np.unique(both))
+
+
+@pytest.mark.parametrize("tree", [False, True])
+def test_bulk_build_out_of_range(hp, tree):
+    p = 1 << 20
+    cols = _cols("distinct", p, 0.1, 4)
+    cols[::97] = 0
+    cols[5] = p + 1
+    got = hp.bitset_roundtrip(torch.from_numpy(cols).cuda(), p, tree, bulk=True)
+    keep = cols[(cols >= 1) & (cols <= p)]
+    assert got["insert_status"] == -2
+    assert np.array_equal(got["cols"], np.unique(keep))
+
