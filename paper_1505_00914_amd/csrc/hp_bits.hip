@@ -202,7 +202,7 @@ __global__ __launch_bounds__(kBitsBlock) void k_bits_write(const uint64_t *__res
 // ---------------------------------------------------------------------------
 constexpr int kPartBlock = 256;
 constexpr int kPartMaxWinWords = 2048;   // level-0 words per window (16 KB of LDS)
-constexpr int64_t kPartMaxHist = 65536;  // windows x chunks
+constexpr int64_t kPartMaxHist = 262144;  // windows x chunks
 
 struct PartShape {
   int32_t wshift;   // log2 of the columns per window
@@ -220,7 +220,7 @@ static PartShape part_shape(int64_t s, int32_t p) {
   while ((64ll << sh) < ww * 64) ++sh;
   P.wshift = 6 + sh;  // ww * 64 columns = 2^(6 + sh)
   P.nwin = (int32_t)((W0 + ww - 1) / ww);
-  const int64_t want = (s + 8191) / 8192;
+  const int64_t want = (s + 4095) / 4096;
   const int64_t cap = std::max<int64_t>(1, std::min<int64_t>(1024, kPartMaxHist / P.nwin));
   P.nchunk = (int32_t)std::max<int64_t>(1, std::min(want, cap));
   P.per = (s + P.nchunk - 1) / P.nchunk;
@@ -249,32 +249,43 @@ __global__ __launch_bounds__(kPartBlock) void k_part_count(const int32_t *__rest
   if (bad) info[HP_INFO_STATUS] = HP_ERANGE;
 }
 
-// One workgroup: exclusive offsets of the h window-major counts, total at [h].
-__global__ __launch_bounds__(kBitsScanBlock) void k_part_scan(const int32_t *__restrict__ hist, int64_t h,
-                                                              int64_t *__restrict__ off) {
-  __shared__ int64_t s_sum[kBitsScanBlock];
-  const int64_t per = (h + kBitsScanBlock - 1) / kBitsScanBlock;
-  const int64_t b0 = (int64_t)threadIdx.x * per, b1 = b0 + per < h ? b0 + per : h;
-  int64_t mine = 0;
-  for (int64_t b = b0; b < b1; ++b) mine += hist[b];
+// One workgroup per window: exclusive offsets of the window's chunk counts
+// within the window (loc), and the window's total (wtot).  The totals are
+// then scanned by k_bits_scan into the windows' bases.
+__global__ __launch_bounds__(kPartBlock) void k_part_scan_win(const int32_t *__restrict__ hist, int32_t nchunk,
+                                                              int32_t *__restrict__ loc,
+                                                              int32_t *__restrict__ wtot) {
+  __shared__ int32_t s_sum[kPartBlock];
+  const int64_t row = (int64_t)blockIdx.x * nchunk;
+  const int per = (nchunk + kPartBlock - 1) / kPartBlock;  // at most 4
+  const int j0 = threadIdx.x * per;
+  int v[4] = {0, 0, 0, 0};
+  int mine = 0;
+  for (int u = 0; u < per; ++u)
+    if (j0 + u < nchunk) {
+      v[u] = hist[row + j0 + u];
+      mine += v[u];
+    }
   s_sum[threadIdx.x] = mine;
   __syncthreads();
-  for (int d = 1; d < kBitsScanBlock; d <<= 1) {
-    const int64_t add = threadIdx.x >= (unsigned)d ? s_sum[threadIdx.x - d] : 0;
+  for (int d = 1; d < kPartBlock; d <<= 1) {
+    const int add = threadIdx.x >= (unsigned)d ? s_sum[threadIdx.x - d] : 0;
     __syncthreads();
     s_sum[threadIdx.x] += add;
     __syncthreads();
   }
-  int64_t run = s_sum[threadIdx.x] - mine;
-  for (int64_t b = b0; b < b1; ++b) {
-    off[b] = run;
-    run += hist[b];
-  }
-  if (threadIdx.x == kBitsScanBlock - 1) off[h] = s_sum[threadIdx.x];
+  int run = s_sum[threadIdx.x] - mine;
+  for (int u = 0; u < per; ++u)
+    if (j0 + u < nchunk) {
+      loc[row + j0 + u] = run;
+      run += v[u];
+    }
+  if (threadIdx.x == kPartBlock - 1) wtot[blockIdx.x] = s_sum[threadIdx.x];
 }
 
 __global__ __launch_bounds__(kPartBlock) void k_part_scatter(const int32_t *__restrict__ cols, int64_t s, int32_t p,
-                                                             PartShape P, const int64_t *__restrict__ off,
+                                                             PartShape P, const int64_t *__restrict__ base,
+                                                             const int32_t *__restrict__ loc,
                                                              int32_t *__restrict__ part) {
   extern __shared__ int32_t s_cur[];
   for (int w = threadIdx.x; w < P.nwin; w += kPartBlock) s_cur[w] = 0;
@@ -285,13 +296,13 @@ __global__ __launch_bounds__(kPartBlock) void k_part_scatter(const int32_t *__re
     if ((unsigned)(c - 1) >= (unsigned)p) continue;
     const int w = (int)((unsigned)(c - 1) >> P.wshift);
     const int k = atomicAdd(&s_cur[w], 1);
-    part[off[(int64_t)w * P.nchunk + blockIdx.x] + k] = c;
+    part[base[w] + loc[(int64_t)w * P.nchunk + blockIdx.x] + k] = c;
   }
 }
 
 template <bool TREE>
 __global__ __launch_bounds__(kPartBlock) void k_part_window(const int32_t *__restrict__ part,
-                                                            const int64_t *__restrict__ off, PartShape P,
+                                                            const int64_t *__restrict__ base, PartShape P,
                                                             int64_t W0, uint64_t *__restrict__ words,
                                                             BitLevels L) {
   __shared__ unsigned long long s_bm[kPartMaxWinWords];
@@ -299,7 +310,7 @@ __global__ __launch_bounds__(kPartBlock) void k_part_window(const int32_t *__res
   const int64_t g0 = (int64_t)blockIdx.x * ww;
   for (int t = threadIdx.x; t < ww; t += kPartBlock) s_bm[t] = 0;
   __syncthreads();
-  const int64_t i0 = off[(int64_t)blockIdx.x * P.nchunk], i1 = off[(int64_t)(blockIdx.x + 1) * P.nchunk];
+  const int64_t i0 = base[blockIdx.x], i1 = base[blockIdx.x + 1];
   for (int64_t i = i0 + threadIdx.x; i < i1; i += kPartBlock) {
     const uint32_t b = (uint32_t)(part[i] - 1);
     atomicOr(&s_bm[(int64_t)(b >> 6) - g0], 1ull << (b & 63));
@@ -426,8 +437,8 @@ extern "C" int hp_bitset_build_workspace_bytes(int64_t s, int32_t p, size_t *byt
   if (s < 0 || !bytes) return set_error(HP_EINVAL, "bad argument");
   const PartShape P = part_shape(s, p);
   const int64_t h = (int64_t)P.nwin * P.nchunk;
-  *bytes = P.bulk ? align256(sizeof(int32_t) * (size_t)s) + align256(sizeof(int32_t) * (size_t)h) +
-                        align256(sizeof(int64_t) * (size_t)(h + 1))
+  *bytes = P.bulk ? align256(sizeof(int32_t) * (size_t)s) + 2 * align256(sizeof(int32_t) * (size_t)h) +
+                        align256(sizeof(int32_t) * (size_t)P.nwin) + align256(sizeof(int64_t) * (size_t)(P.nwin + 1))
                   : 0;
   return HP_OK;
 }
@@ -444,27 +455,32 @@ extern "C" int hp_bitset_build(const int32_t *cols, int64_t s, int32_t p, int32_
   if (!ws || ws_bytes < need) return set_error(HP_ECAPACITY, "workspace %zu < %zu bytes", ws_bytes, need);
   const int64_t h = (int64_t)P.nwin * P.nchunk;
   char *w = static_cast<char *>(ws);
-  int32_t *part = reinterpret_cast<int32_t *>(w);
-  int32_t *hist = reinterpret_cast<int32_t *>(w + align256(sizeof(int32_t) * (size_t)s));
-  int64_t *off = reinterpret_cast<int64_t *>(w + align256(sizeof(int32_t) * (size_t)s) +
-                                             align256(sizeof(int32_t) * (size_t)h));
+  size_t at = 0;
+  auto take = [&](size_t bytes) { char *q = w + at; at += align256(bytes); return q; };
+  int32_t *part = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)s));
+  int32_t *hist = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)h));
+  int32_t *loc = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)h));
+  int32_t *wtot = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)P.nwin));
+  int64_t *base = reinterpret_cast<int64_t *>(take(sizeof(int64_t) * (size_t)(P.nwin + 1)));
   const BitLevels L = bit_levels(p, tree);
   const int64_t W0 = ((int64_t)p + 63) / 64;
   const size_t lds = sizeof(int32_t) * (size_t)P.nwin;
   hipStream_t st = (hipStream_t)stream;
   hipLaunchKernelGGL(k_bits_info, dim3(1), dim3(1), 0, st, info);
   hipLaunchKernelGGL(k_part_count, dim3(P.nchunk), dim3(kPartBlock), lds, st, cols, s, p, P, hist, info);
-  hipLaunchKernelGGL(k_part_scan, dim3(1), dim3(kBitsScanBlock), 0, st, (const int32_t *)hist, h, off);
+  hipLaunchKernelGGL(k_part_scan_win, dim3(P.nwin), dim3(kPartBlock), 0, st, (const int32_t *)hist, P.nchunk, loc,
+                     wtot);
+  hipLaunchKernelGGL(k_bits_scan, dim3(1), dim3(kBitsScanBlock), 0, st, (const int32_t *)wtot, (int64_t)P.nwin,
+                     base);
   hipLaunchKernelGGL(k_part_scatter, dim3(P.nchunk), dim3(kPartBlock), lds, st, cols, s, p, P,
-                     (const int64_t *)off, part);
+                     (const int64_t *)base, (const int32_t *)loc, part);
   if (tree)
     hipLaunchKernelGGL(k_part_window<true>, dim3(P.nwin), dim3(kPartBlock), 0, st, (const int32_t *)part,
-                       (const int64_t *)off, P, W0, words, L);
+                       (const int64_t *)base, P, W0, words, L);
   else
     hipLaunchKernelGGL(k_part_window<false>, dim3(P.nwin), dim3(kPartBlock), 0, st, (const int32_t *)part,
-                       (const int64_t *)off, P, W0, words, L);
+                       (const int64_t *)base, P, W0, words, L);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return set_error(HP_EDEVICE, "bulk build launch: %s", hipGetErrorString(e));
   return HP_OK;
 }
-
