@@ -10,7 +10,9 @@
 // Insert: one device-scope OR per column into its level-0 word.  In the
 // tree, the thread whose OR found the word empty (exactly one per word) goes
 // on to the level above, so the upper levels see one OR per non-empty word,
-// not one per column.
+// not one per column.  The bulk build (further down) gives the same words
+// without device-scope atomics on level 0, by partitioning the columns by
+// window and assembling each window in LDS.
 //
 // Extraction: three launches.  k_bits_count gives each workgroup of 128
 // level-0 words its number of set bits, k_bits_scan turns those counts into
