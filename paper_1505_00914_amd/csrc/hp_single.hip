@@ -314,8 +314,12 @@ __device__ int block_exclusive_scan(int32_t *a, int32_t n, int *s_tmp, int *s_ca
 __device__ bool last_arrival_flag(int32_t *ctr, int expected, int *s_flag) {
   __syncthreads();
   if (threadIdx.x == 0) {
-    const int old = __hip_atomic_fetch_add(ctr, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    *s_flag = (old == expected - 1) ? 1 : 0;
+    // release only: an acquire costs every arriver an invalidation of its
+    // XCD's L2, and only the last arriver reads what the others wrote
+    const int old = __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    const int last = (old == expected - 1) ? 1 : 0;
+    if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    *s_flag = last;
   }
   __syncthreads();
   return *s_flag != 0;
