@@ -1594,6 +1594,22 @@ static int64_t sample_div() {
   return v;
 }
 
+// End of the filtered pass that starts after `lo` points: four times lo, or
+// n (a pass that starts at 0, after an empty sample, takes every point).
+static int64_t sampled_stage_end(int64_t lo, int64_t n) { return lo <= 0 ? n : std::min<int64_t>(n, 4 * lo); }
+
+// Filtered passes after a sample of ns points, and where the last one starts.
+static int sampled_stages(int64_t ns, int64_t n, int64_t *last_start = nullptr) {
+  int k = 0;
+  int64_t at = ns;
+  for (int64_t lo = ns; lo < n; lo = sampled_stage_end(lo, n)) {
+    ++k;
+    at = lo;
+  }
+  if (last_start) *last_start = at;
+  return k;
+}
+
 // Column windows: at most kWinMax windows, at most kWinMaxGroups chunk
 // groups (a multiple of 8: one per XCD slot).
 constexpr int kWinMax = 8;
@@ -1758,14 +1774,15 @@ static hipError_t dispatch_reduce(const Plan1 &P, const int32_t *pts, int64_t n,
 }
 
 // The sampled-filter reduce: the sample pass (k_reduce_global over the
-// first ns points, G1 workgroups), the filter, a filtered pass up to point
-// n1, the filter again (from an L that has now seen n1 points, so it is
-// tighter), and the filtered pass over the rest; the filtered passes use
-// P.G workgroups each and only the last one shares chunks.  e0 is recorded
-// at the start of the sample pass and e1 at the end of the last pass.
+// first ns points, G1 workgroups), then filtered passes, each over up to
+// three times the points folded before it and each after a filter rebuilt
+// from the fuller L (so tighter); with the default sample of n/8 these are
+// [n/8, n/2) and [n/2, n).  The filtered passes use P.G workgroups each and
+// only the last one shares chunks.  e0 is recorded at the start of the
+// sample pass and e1 at the end of the last pass.
 template <int BLOCK, int VPT>
 static hipError_t launch_sampled(const Plan1 &P, const int32_t *pts, int64_t n, int32_t p, int2 *Lm,
-                                 int2 *F, int fshift, int ngroups, int64_t ns, int64_t n1, int G1,
+                                 int2 *F, int fshift, int ngroups, int64_t ns, int G1,
                                  int32_t *wg_err, DynArgs D, int2 org, hipStream_t s, hipEvent_t e0,
                                  hipEvent_t e1) {
   static bool attr_set = false;
@@ -1787,30 +1804,34 @@ static hipError_t launch_sampled(const Plan1 &P, const int32_t *pts, int64_t n, 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const size_t lds = sizeof(int2) * ((size_t)ngroups + 2 + (size_t)(BLOCK / kWave) * filt_queue_cap(VPT));
-  // first filtered pass: points [ns, n1), static shares
-  hipLaunchKernelGGL(k_filter_build, dim3((ngroups + 3) / 4), dim3(256), 0, s, (const int2 *)Lm, p, fshift,
-                     ngroups, F);
-  hipLaunchKernelGGL((k_reduce_filtered<BLOCK, VPT>), dim3(P.G), dim3(BLOCK), lds, s, pts + 2 * ns, n1 - ns, p, Lm,
-                     (const int2 *)F, fshift, ngroups, wg_err + G1, D0, org);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  // last pass: points [n1, n), with the filter of the first n1 points
-  hipLaunchKernelGGL(k_filter_build, dim3((ngroups + 3) / 4), dim3(256), 0, s, (const int2 *)Lm, p, fshift,
-                     ngroups, F);
-  if (e1) hipExtLaunchKernelGGL((k_reduce_filtered<BLOCK, VPT>), dim3(P.G), dim3(BLOCK), (uint32_t)lds, s, nullptr,
-                                e1, 0, pts + 2 * n1, n - n1, p, Lm, (const int2 *)F, fshift, ngroups,
-                                wg_err + G1 + P.G, D, org);
-  else hipLaunchKernelGGL((k_reduce_filtered<BLOCK, VPT>), dim3(P.G), dim3(BLOCK), lds, s, pts + 2 * n1, n - n1, p, Lm,
-                          (const int2 *)F, fshift, ngroups, wg_err + G1 + P.G, D, org);
-  return hipGetLastError();
+  // the filtered passes: each folds up to three times the points folded
+  // before it, with the filter rebuilt from the fuller L in between
+  int stage = 0;
+  for (int64_t lo = ns; lo < n; ++stage) {
+    const int64_t hi = sampled_stage_end(lo, n);
+    const bool last = hi == n;
+    hipLaunchKernelGGL(k_filter_build, dim3((ngroups + 3) / 4), dim3(256), 0, s, (const int2 *)Lm, p, fshift,
+                       ngroups, F);
+    int32_t *err = wg_err + G1 + (size_t)stage * P.G;
+    if (last && e1)
+      hipExtLaunchKernelGGL((k_reduce_filtered<BLOCK, VPT>), dim3(P.G), dim3(BLOCK), (uint32_t)lds, s, nullptr, e1, 0,
+                            pts + 2 * lo, hi - lo, p, Lm, (const int2 *)F, fshift, ngroups, err, D, org);
+    else
+      hipLaunchKernelGGL((k_reduce_filtered<BLOCK, VPT>), dim3(P.G), dim3(BLOCK), lds, s, pts + 2 * lo, hi - lo, p,
+                         Lm, (const int2 *)F, fshift, ngroups, err, last ? D : D0, org);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    lo = hi;
+  }
+  return hipSuccess;
 }
 
 static hipError_t dispatch_sampled(const Plan1 &P, const int32_t *pts, int64_t n, int32_t p, int2 *Lm, int2 *F,
-                                   int fshift, int ngroups, int64_t ns, int64_t n1, int G1, int32_t *wg_err,
+                                   int fshift, int ngroups, int64_t ns, int G1, int32_t *wg_err,
                                    DynArgs D, int2 org, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
 #define HP_CASE(B, V) \
   if (P.block == B && P.vpt == V)   \
-    return launch_sampled<B, V>(P, pts, n, p, Lm, F, fshift, ngroups, ns, n1, G1, wg_err, D, org, s, e0, e1);
+    return launch_sampled<B, V>(P, pts, n, p, Lm, F, fshift, ngroups, ns, G1, wg_err, D, org, s, e0, e1);
   HP_CASE(1024, 4)
   HP_CASE(1024, 2)
   HP_CASE(1024, 8)
@@ -1932,7 +1953,8 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
   // as few as LDS holds
   const bool sampled = P.strategy == HP_STRATEGY_SAMPLED;
   const int64_t ns = sampled ? (n / sample_div()) & ~(int64_t)1 : 0;
-  const int64_t n1 = sampled ? std::min<int64_t>(n, 4 * ns) : 0;   // end of the first filtered pass (even)
+  int64_t n1 = 0;   // start of the pass that may share chunks
+  const int nstages = sampled ? sampled_stages(ns, n, &n1) : 0;
   int fshift = 6, ngroups = 0, G1 = 0;
   if (sampled) {
     // LDS pairs left for the filter after the flag and grab words and the
@@ -1943,7 +1965,7 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
     ngroups = (int)(((int64_t)p + ((int64_t)1 << fshift) - 1) >> fshift);
     const int64_t per = (int64_t)P.block * P.vpt;
     G1 = (int)std::max<int64_t>(1, std::min<int64_t>(P.G, (ns / 2 + per - 1) / per));
-    if (G1 + 2 * P.G > kMaxGrid) return set_error(HP_EINVAL, "reduce grid too large");
+    if (G1 + (int64_t)nstages * P.G > kMaxGrid) return set_error(HP_EINVAL, "reduce grid too large");
   }
   // the pass that may share chunks: all points, or the last filtered pass
   const int32_t *main_pts = pts ? pts + 2 * n1 : pts;
@@ -1953,7 +1975,7 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
   hipEvent_t e0 = nullptr, e1 = nullptr;
   timing_slot(&e0, &e1);
   if (sampled)
-    e = dispatch_sampled(P, pts, n, p, Lm, reinterpret_cast<int2 *>(w + Y.filt), fshift, ngroups, ns, n1, G1,
+    e = dispatch_sampled(P, pts, n, p, Lm, reinterpret_cast<int2 *>(w + Y.filt), fshift, ngroups, ns, G1,
                          wg_err, D, org, s, e0, e1);
   else
     e = dispatch_reduce(P, pts, n, p, Lm, part, wg_err, R, D, org, s, e0, e1);
@@ -1984,7 +2006,7 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
   A.ctl = ctl;
   A.info = info;
   A.wg_err = wg_err;
-  A.n_wg_err = (sampled ? G1 + P.G : 0) + P.G;
+  A.n_wg_err = sampled ? G1 + nstages * P.G : P.G;
   A.dyn_ctr = D.ctr;
   A.wg_cnt = D.wg_cnt;
   A.n_wg_cnt = P.G;
@@ -2019,7 +2041,7 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
   H.slab_k = A.slab_k;
   H.slab_s = A.slab_s;
   H.wg_err = wg_err;
-  H.n_wg_err = (sampled ? G1 + P.G : 0) + P.G;
+  H.n_wg_err = sampled ? G1 + nstages * P.G : P.G;
   H.cx = cx;
   H.clo = clo;
   H.chi = chi;
