@@ -13,9 +13,13 @@
 
 namespace hp {
 
+// Twice the signed area of (a, b, c).  Coordinates are int32, so every
+// difference fits in 33 bits and each product in 64; when every coordinate
+// lies in [0, 2^15) (SMALL) the differences fit in 16 bits and the whole
+// expression in 32.
+template <bool SMALL>
 __device__ __forceinline__ long long melk_orient(int2 a, int2 b, int2 c) {
-  // twice the signed area of (a, b, c); coordinates are int32, so every
-  // difference fits in 33 bits and each product in 64
+  if (SMALL) return (long long)((b.x - a.x) * (c.y - a.y) - (b.y - a.y) * (c.x - a.x));
   return ((long long)b.x - a.x) * ((long long)c.y - a.y) - ((long long)b.y - a.y) * ((long long)c.x - a.x);
 }
 
@@ -62,23 +66,12 @@ struct ChainWalk {
   }
 };
 
-__global__ __launch_bounds__(64) void k_melkman(const int32_t *__restrict__ cx, const int32_t *__restrict__ clo,
-                                                const int32_t *__restrict__ chi, int32_t chain_cap,
-                                                int32_t *__restrict__ hx, int32_t *__restrict__ hy,
-                                                int32_t *__restrict__ info, int2 *__restrict__ gdeque,
-                                                int32_t use_lds) {
-  extern __shared__ int2 s_deque[];
+template <bool SMALL>
+__device__ void melkman_walk(const int32_t *__restrict__ cx, const int32_t *__restrict__ clo,
+                             const int32_t *__restrict__ chi, int32_t chain_cap, int32_t k,
+                             int32_t *__restrict__ hx, int32_t *__restrict__ hy, int32_t *__restrict__ info,
+                             int2 *D) {
   const bool lead = threadIdx.x == 0;  // every lane computes; lane 0 stores
-  int2 *D = use_lds ? s_deque : gdeque;
-  const int32_t k = info[HP_INFO_K];
-  __syncthreads();
-  if (k < 0 || k > chain_cap) {
-    if (lead) {
-      info[HP_INFO_STATUS] = HP_ECAPACITY;
-      info[HP_INFO_H] = 0;
-    }
-    return;
-  }
   ChainWalk W{cx, clo, chi, k, 0, -64, 0, 0, 0, 0, false, false};
   int2 a, b, c;
   int32_t h = 0;
@@ -94,7 +87,7 @@ __global__ __launch_bounds__(64) void k_melkman(const int32_t *__restrict__ cx, 
     // points collinear with a and b move b along the line (the walk is
     // x-monotone, so the newest point is the far end)
     bool more;
-    while ((more = W.next(c)) && melk_orient(a, b, c) == 0) b = c;
+    while ((more = W.next(c)) && melk_orient<SMALL>(a, b, c) == 0) b = c;
     if (!more) {
       if (lead) {
         hx[0] = a.x;
@@ -110,7 +103,7 @@ __global__ __launch_bounds__(64) void k_melkman(const int32_t *__restrict__ cx, 
       // T0 = D[top], T1 = D[top-1], B0 = D[bot], B1 = D[bot+1] are kept in
       // registers; memory is read only when a pop exposes an older entry.
       int64_t bot = 2 * (int64_t)chain_cap, top = bot + 3;
-      const bool ccw = melk_orient(a, b, c) > 0;
+      const bool ccw = melk_orient<SMALL>(a, b, c) > 0;
       int2 B0 = c, B1 = ccw ? a : b, T1 = ccw ? b : a, T0 = c;
       if (lead) {
         D[bot] = B0;
@@ -119,10 +112,13 @@ __global__ __launch_bounds__(64) void k_melkman(const int32_t *__restrict__ cx, 
         D[top] = T0;
       }
       __syncthreads();
+      // The rest of the walk.  The chain comes in increasing x, so nearly
+      // every point lies outside the hull so far and takes the deque update;
+      // the skip test rarely fires.
       int2 v;
       while (W.next(v)) {
-        if (melk_orient(T1, T0, v) > 0 && melk_orient(B0, B1, v) > 0) continue;
-        while (top - bot >= 2 && melk_orient(T1, T0, v) <= 0) {
+        if (melk_orient<SMALL>(T1, T0, v) > 0 && melk_orient<SMALL>(B0, B1, v) > 0) continue;
+        while (top - bot >= 2 && melk_orient<SMALL>(T1, T0, v) <= 0) {
           --top;
           T0 = T1;
           T1 = D[top - 1];
@@ -138,7 +134,7 @@ __global__ __launch_bounds__(64) void k_melkman(const int32_t *__restrict__ cx, 
           B0 = D[bot];
           B1 = D[bot + 1];
         }
-        while (top - bot >= 2 && melk_orient(B0, B1, v) <= 0) {
+        while (top - bot >= 2 && melk_orient<SMALL>(B0, B1, v) <= 0) {
           ++bot;
           B0 = B1;
           B1 = D[bot + 1];
@@ -163,14 +159,14 @@ __global__ __launch_bounds__(64) void k_melkman(const int32_t *__restrict__ cx, 
         int64_t first = -1;
         for (int64_t i = 0; i < m; ++i) {
           const int2 cur = H[i];
-          if (melk_orient(H[(i + m - 1) % m], cur, H[(i + 1) % m]) == 0) continue;
+          if (melk_orient<SMALL>(H[(i + m - 1) % m], cur, H[(i + 1) % m]) == 0) continue;
           if (first < 0 || cur.x < H[first].x || (cur.x == H[first].x && cur.y < H[first].y)) first = i;
         }
         if (first < 0) first = 0;  // unreachable: a non-degenerate hull has corners
         for (int64_t j = 0; j < m; ++j) {
           const int64_t i = (first + j) % m;
           const int2 cur = H[i];
-          if (melk_orient(H[(i + m - 1) % m], cur, H[(i + 1) % m]) == 0) continue;
+          if (melk_orient<SMALL>(H[(i + m - 1) % m], cur, H[(i + 1) % m]) == 0) continue;
           if (lead) {
             hx[h] = cur.x;
             hy[h] = cur.y;
@@ -184,6 +180,45 @@ __global__ __launch_bounds__(64) void k_melkman(const int32_t *__restrict__ cx, 
     if (W.bad) info[HP_INFO_STATUS] = HP_EINVAL;
     info[HP_INFO_H] = W.bad ? 0 : h;
   }
+}
+
+__global__ __launch_bounds__(64) void k_melkman(const int32_t *__restrict__ cx, const int32_t *__restrict__ clo,
+                                                const int32_t *__restrict__ chi, int32_t chain_cap,
+                                                int32_t *__restrict__ hx, int32_t *__restrict__ hy,
+                                                int32_t *__restrict__ info, int2 *__restrict__ gdeque,
+                                                int32_t use_lds) {
+  extern __shared__ int2 s_deque[];
+  int2 *D = use_lds ? s_deque : gdeque;
+  const int32_t k = info[HP_INFO_K];
+  __syncthreads();
+  if (k < 0 || k > chain_cap) {
+    if (threadIdx.x == 0) {
+      info[HP_INFO_STATUS] = HP_ECAPACITY;
+      info[HP_INFO_H] = 0;
+    }
+    return;
+  }
+  // one pass of the wave over the chain: is it well formed (x strictly
+  // increasing, lo <= hi), and does every coordinate lie in [0, 2^15), where
+  // the 32-bit orientation applies
+  bool small = true, bad = false;
+  for (int32_t t = threadIdx.x; t < k; t += 64) {
+    const int32_t x = cx[t], lo = clo[t], hi = chi[t];
+    small = small && (unsigned)x < 32768u && (unsigned)lo < 32768u && (unsigned)hi < 32768u;
+    bad = bad || hi < lo || (t > 0 && cx[t - 1] >= x);
+  }
+  small = __ballot(!small) == 0;
+  if (__ballot(bad) != 0) {
+    if (threadIdx.x == 0) {
+      info[HP_INFO_STATUS] = HP_EINVAL;
+      info[HP_INFO_H] = 0;
+    }
+    return;
+  }
+  if (small)
+    melkman_walk<true>(cx, clo, chi, chain_cap, k, hx, hy, info, D);
+  else
+    melkman_walk<false>(cx, clo, chi, chain_cap, k, hx, hy, info, D);
 }
 
 static int64_t melkman_deque_entries(int32_t chain_cap) { return 4 * (int64_t)chain_cap + 4; }
