@@ -183,3 +183,55 @@ def test_run_auto_f32_worked_example(hp):
     got = hp.run_auto_f32(torch.from_numpy(a).cuda(), 5)
     assert list(zip(got["lo"].tolist(), got["hi"].tolist())) == fixtures.pairs(f["L"])
     assert [tuple(v) for v in got["hull"].tolist()] == [(1, 1), (5, 2), (5, 3), (3, 5), (1, 4)]
+
+
+# ---------------------------------------------------------------------------
+# Edge cases of the new entry points
+# ---------------------------------------------------------------------------
+def test_bbox_empty(hp):
+    box = torch.empty(4, dtype=torch.int32, device="cuda")
+    ws = torch.empty(hp.bbox_workspace_bytes(), dtype=torch.uint8, device="cuda")
+    hp.hp_bbox(torch.empty((0, 2), dtype=torch.int32, device="cuda"), box, ws)
+    torch.cuda.synchronize()
+    assert box.cpu().tolist() == [I32.max, I32.min, I32.max, I32.min]
+
+
+def test_bbox_f32_all_nan(hp):
+    a = np.full((5, 2), np.nan, np.float32)
+    x0, x1, y0, y1 = hp.bbox_f32(torch.from_numpy(a).cuda())
+    assert x0 == float("inf") and x1 == float("-inf") and y0 == float("inf") and y1 == float("-inf")
+    with pytest.raises(hp.HullprepError):
+        hp.run_auto_f32(torch.from_numpy(a).cuda(), 64)
+
+
+def test_quantize_empty(hp):
+    out = torch.empty((0, 2), dtype=torch.int32, device="cuda")
+    info = torch.ones(4, dtype=torch.int32, device="cuda")
+    hp.hp_quantize_f32(torch.empty((0, 2), dtype=torch.float32, device="cuda"), (0.0, 0.0), 1.0, out, info)
+    torch.cuda.synchronize()
+    assert int(info[0]) == 0
+
+
+@pytest.mark.parametrize("strategy", [1, 2, 3, 4, 5])
+def test_origin_out_of_range_reports(hp, strategy):
+    """A point that the origin moves outside [1, p]^2 is reported, as in hp_run."""
+    pts = _moved("uniform", 50_000, 1024, 3, (5000, -7000))
+    origin = (int(pts[:, 0].min()) - 1, int(pts[:, 1].min()) - 1)
+    pts[12_345] = (origin[0], origin[1] + 5)          # x maps to 0
+    pts[40_000] = (origin[0] + 3, origin[1] + 1025)   # y maps to p + 1
+    buf = hp.Buffers.allocate(pts.shape[0], 1024, "cuda")
+    hp.set_strategy(strategy)
+    try:
+        hp.hp_run_origin(torch.from_numpy(pts).cuda(), 1024, origin, buf)
+        got = hp.collect(buf)
+    finally:
+        hp.set_strategy(0)
+    assert got["status"] == -2
+
+
+@pytest.mark.parametrize("tree", [False, True])
+def test_bitset_p1(hp, tree):
+    got = hp.bitset_roundtrip(torch.tensor([1, 1, 1], dtype=torch.int32, device="cuda"), 1, tree)
+    assert got["status"] == 0 and got["cols"].tolist() == [1]
+    got = hp.bitset_roundtrip(torch.tensor([], dtype=torch.int32, device="cuda"), 1, tree)
+    assert got["status"] == 0 and got["count"] == 0
