@@ -302,6 +302,76 @@ __global__ __launch_bounds__(kPartBlock) void k_part_scatter(const int32_t *__re
   }
 }
 
+// The scatter with a local sort: each tile of kPartTile columns of the chunk
+// is ordered by window in LDS (ranks from an LDS histogram, offsets from its
+// scan), and then written out in that order, so that consecutive lanes
+// store consecutive addresses of one window's run instead of 4 bytes each
+// into many windows.  For at most kPartSortMaxWin windows.
+constexpr int kPartTile = 2048;
+constexpr int kPartSortMaxWin = 2048;
+constexpr int kPartPerThread = kPartTile / kPartBlock;   // 8
+
+__global__ __launch_bounds__(kPartBlock) void k_part_scatter_sorted(const int32_t *__restrict__ cols, int64_t s,
+                                                                    int32_t p, PartShape P,
+                                                                    const int64_t *__restrict__ base,
+                                                                    const int32_t *__restrict__ loc,
+                                                                    int32_t *__restrict__ part) {
+  __shared__ int32_t s_cur[kPartSortMaxWin];    // columns of the chunk already written, per window
+  __shared__ int32_t s_hist[kPartSortMaxWin];   // this tile's count, per window
+  __shared__ int32_t s_toff[kPartSortMaxWin];   // this tile's first slot, per window
+  __shared__ int32_t s_tile[kPartTile];
+  __shared__ int32_t s_sum[kPartBlock];
+  const int nw = P.nwin;
+  for (int w = threadIdx.x; w < nw; w += kPartBlock) s_cur[w] = 0;
+  const int64_t j0 = (int64_t)blockIdx.x * P.per, j1 = j0 + P.per < s ? j0 + P.per : s;
+  for (int64_t t0 = j0; t0 < j1; t0 += kPartTile) {
+    for (int w = threadIdx.x; w < nw; w += kPartBlock) s_hist[w] = 0;
+    __syncthreads();
+    int32_t c[kPartPerThread];
+    int wv[kPartPerThread], rk[kPartPerThread];
+#pragma unroll
+    for (int u = 0; u < kPartPerThread; ++u) {
+      const int64_t j = t0 + u * kPartBlock + threadIdx.x;
+      c[u] = j < j1 ? cols[j] : 0;
+      const bool ok = j < j1 && (unsigned)(c[u] - 1) < (unsigned)p;
+      wv[u] = ok ? (int)((unsigned)(c[u] - 1) >> P.wshift) : -1;
+      rk[u] = ok ? atomicAdd(&s_hist[wv[u]], 1) : 0;
+    }
+    __syncthreads();
+    // exclusive scan of the tile's window counts: a run of windows per thread
+    const int per = (nw + kPartBlock - 1) / kPartBlock;
+    const int w0 = threadIdx.x * per;
+    int mine = 0;
+    for (int w = w0; w < w0 + per && w < nw; ++w) mine += s_hist[w];
+    s_sum[threadIdx.x] = mine;
+    __syncthreads();
+    for (int d = 1; d < kPartBlock; d <<= 1) {
+      const int add = threadIdx.x >= (unsigned)d ? s_sum[threadIdx.x - d] : 0;
+      __syncthreads();
+      s_sum[threadIdx.x] += add;
+      __syncthreads();
+    }
+    int run = s_sum[threadIdx.x] - mine;
+    for (int w = w0; w < w0 + per && w < nw; ++w) {
+      s_toff[w] = run;
+      run += s_hist[w];
+    }
+    const int valid = s_sum[kPartBlock - 1];
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kPartPerThread; ++u)
+      if (wv[u] >= 0) s_tile[s_toff[wv[u]] + rk[u]] = c[u];
+    __syncthreads();
+    for (int i = threadIdx.x; i < valid; i += kPartBlock) {
+      const int32_t cc = s_tile[i];
+      const int w = (int)((unsigned)(cc - 1) >> P.wshift);
+      part[base[w] + loc[(int64_t)w * P.nchunk + blockIdx.x] + s_cur[w] + (i - s_toff[w])] = cc;
+    }
+    __syncthreads();
+    for (int w = threadIdx.x; w < nw; w += kPartBlock) s_cur[w] += s_hist[w];
+  }
+}
+
 template <bool TREE>
 __global__ __launch_bounds__(kPartBlock) void k_part_window(const int32_t *__restrict__ part,
                                                             const int64_t *__restrict__ base, PartShape P,
@@ -474,8 +544,12 @@ extern "C" int hp_bitset_build(const int32_t *cols, int64_t s, int32_t p, int32_
                      wtot);
   hipLaunchKernelGGL(k_bits_scan, dim3(1), dim3(kBitsScanBlock), 0, st, (const int32_t *)wtot, (int64_t)P.nwin,
                      base);
-  hipLaunchKernelGGL(k_part_scatter, dim3(P.nchunk), dim3(kPartBlock), lds, st, cols, s, p, P,
-                     (const int64_t *)base, (const int32_t *)loc, part);
+  if (P.nwin <= kPartSortMaxWin)
+    hipLaunchKernelGGL(k_part_scatter_sorted, dim3(P.nchunk), dim3(kPartBlock), 0, st, cols, s, p, P,
+                       (const int64_t *)base, (const int32_t *)loc, part);
+  else
+    hipLaunchKernelGGL(k_part_scatter, dim3(P.nchunk), dim3(kPartBlock), lds, st, cols, s, p, P,
+                       (const int64_t *)base, (const int32_t *)loc, part);
   if (tree)
     hipLaunchKernelGGL(k_part_window<true>, dim3(P.nwin), dim3(kPartBlock), 0, st, (const int32_t *)part,
                        (const int64_t *)base, P, W0, words, L);
