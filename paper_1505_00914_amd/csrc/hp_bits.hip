@@ -372,24 +372,26 @@ __global__ __launch_bounds__(kPartBlock) void k_part_scatter_sorted(const int32_
   }
 }
 
+constexpr int kWinBlock = 1024;   // threads per window workgroup
+
 template <bool TREE>
-__global__ __launch_bounds__(kPartBlock) void k_part_window(const int32_t *__restrict__ part,
+__global__ __launch_bounds__(kWinBlock) void k_part_window(const int32_t *__restrict__ part,
                                                             const int64_t *__restrict__ base, PartShape P,
                                                             int64_t W0, uint64_t *__restrict__ words,
                                                             BitLevels L) {
   __shared__ unsigned long long s_bm[kPartMaxWinWords];
   const int64_t ww = 1ll << (P.wshift - 6);
   const int64_t g0 = (int64_t)blockIdx.x * ww;
-  for (int t = threadIdx.x; t < ww; t += kPartBlock) s_bm[t] = 0;
+  for (int t = threadIdx.x; t < ww; t += kWinBlock) s_bm[t] = 0;
   __syncthreads();
   const int64_t i0 = base[blockIdx.x], i1 = base[blockIdx.x + 1];
-  for (int64_t i = i0 + threadIdx.x; i < i1; i += kPartBlock) {
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += kWinBlock) {
     const uint32_t b = (uint32_t)(part[i] - 1);
     atomicOr(&s_bm[(int64_t)(b >> 6) - g0], 1ull << (b & 63));
   }
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1);
-  for (int64_t t0 = 0; t0 < ww; t0 += kPartBlock) {
+  for (int64_t t0 = 0; t0 < ww; t0 += kWinBlock) {
     const int64_t t = t0 + threadIdx.x, g = g0 + t;
     uint64_t v = 0;
     if (t < ww && g < W0) {
@@ -551,10 +553,10 @@ extern "C" int hp_bitset_build(const int32_t *cols, int64_t s, int32_t p, int32_
     hipLaunchKernelGGL(k_part_scatter, dim3(P.nchunk), dim3(kPartBlock), lds, st, cols, s, p, P,
                        (const int64_t *)base, (const int32_t *)loc, part);
   if (tree)
-    hipLaunchKernelGGL(k_part_window<true>, dim3(P.nwin), dim3(kPartBlock), 0, st, (const int32_t *)part,
+    hipLaunchKernelGGL(k_part_window<true>, dim3(P.nwin), dim3(kWinBlock), 0, st, (const int32_t *)part,
                        (const int64_t *)base, P, W0, words, L);
   else
-    hipLaunchKernelGGL(k_part_window<false>, dim3(P.nwin), dim3(kPartBlock), 0, st, (const int32_t *)part,
+    hipLaunchKernelGGL(k_part_window<false>, dim3(P.nwin), dim3(kWinBlock), 0, st, (const int32_t *)part,
                        (const int64_t *)base, P, W0, words, L);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return set_error(HP_EDEVICE, "bulk build launch: %s", hipGetErrorString(e));
