@@ -184,8 +184,18 @@ __global__ __launch_bounds__(kBitsBlock) void k_bits_write(const uint64_t *__res
   }
   __syncthreads();
   const int64_t off = blockoff[blockIdx.x];
-  for (int i = threadIdx.x; i < total; i += kBitsBlock)
-    if (off + i < cap) cols[off + i] = s_out[i];
+  // the run cols[off .. off + n), n = total clipped to cap: 4-byte stores
+  // up to a 16-byte boundary of cols, 16-byte stores, 4-byte stores after
+  const int n = (int)(off + total <= cap ? total : (cap > off ? cap - off : 0));
+  const int head = (int)min<int64_t>(n, (4 - ((((uintptr_t)(cols + off)) >> 2) & 3)) & 3);
+  const int nq = (n - head) >> 2;
+  if (threadIdx.x < head) cols[off + threadIdx.x] = s_out[threadIdx.x];
+  int4 *c4 = reinterpret_cast<int4 *>(cols + off + head);
+  for (int q = threadIdx.x; q < nq; q += kBitsBlock) {
+    const int i = head + 4 * q;
+    c4[q] = make_int4(s_out[i], s_out[i + 1], s_out[i + 2], s_out[i + 3]);
+  }
+  for (int i = head + 4 * nq + threadIdx.x; i < n; i += kBitsBlock) cols[off + i] = s_out[i];
   if (blockIdx.x == nb - 1 && threadIdx.x == 0) {
     const int64_t all = blockoff[nb];
     info[HP_INFO_K] = (int32_t)(all < INT_MAX ? all : INT_MAX);
