@@ -195,10 +195,31 @@ __global__ __launch_bounds__(kBoxBlock) void k_bbox_f32(const float2 *__restrict
                                                         float4 *__restrict__ part) {
   __shared__ float4 s_part[kBoxBlock / kWave];
   float4 b = make_float4(INFINITY, -INFINITY, INFINITY, -INFINITY);
+  // two points per 16-byte load, four loads in flight per lane; an odd
+  // leading point (8-byte aligned start) and an odd last point on their own
+  const int64_t head = (n > 0 && ((uintptr_t)pts & 15) != 0) ? 1 : 0;
+  const int64_t nv = (n - head) >> 1;
+  const float4 *v = reinterpret_cast<const float4 *>(pts + head);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (head) boxf_add(b, pts[0].x, pts[0].y);
+    if (head + 2 * nv < n) boxf_add(b, pts[head + 2 * nv].x, pts[head + 2 * nv].y);
+  }
   const int64_t stride = (int64_t)gridDim.x * kBoxBlock;
-  for (int64_t i = (int64_t)blockIdx.x * kBoxBlock + threadIdx.x; i < n; i += stride) {
-    const float2 q = pts[i];
+  int64_t i = (int64_t)blockIdx.x * kBoxBlock + threadIdx.x;
+  for (; i + 3 * stride < nv; i += 4 * stride) {
+    float4 q[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) q[u] = v[i + u * stride];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      boxf_add(b, q[u].x, q[u].y);
+      boxf_add(b, q[u].z, q[u].w);
+    }
+  }
+  for (; i < nv; i += stride) {
+    const float4 q = v[i];
     boxf_add(b, q.x, q.y);
+    boxf_add(b, q.z, q.w);
   }
   b = boxf_block(b, s_part);
   if (threadIdx.x == 0) part[blockIdx.x] = b;
@@ -2238,7 +2259,7 @@ extern "C" int hp_bbox_f32(const float *pts, int64_t n, float *box, void *ws, si
   if (!box) return set_error(HP_EINVAL, "box is NULL");
   if (!ws || ws_bytes < sizeof(float4) * (size_t)kBoxMaxGrid)
     return set_error(HP_ECAPACITY, "bounding-box workspace too small");
-  const int64_t want = (n + 4 * kBoxBlock - 1) / (4 * kBoxBlock);
+  const int64_t want = ((n + 1) / 2 + 4 * kBoxBlock - 1) / (4 * kBoxBlock);
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(kBoxMaxGrid, 4 * device_info().cus), want));
   hipStream_t s = (hipStream_t)stream;
   float4 *part = static_cast<float4 *>(ws);
