@@ -211,7 +211,10 @@ int hp_set_strategy(int strategy);
 int hp_tune_set(int32_t strategy, int32_t block, int32_t vpt, int32_t grid);
 
 /* Load a tuning table written by the tuner: one line per regime
- * "log2n log2p strategy block vpt grid"; '#' starts a comment line. */
+ * "log2n log2p strategy block vpt grid"; '#' starts a comment line.  A line
+ * with a field the launch code cannot honour (strategy outside 1..5, block
+ * not 256/512/1024, vpt not 2/4/8, grid outside 0..2^20) fails the load
+ * with HP_EINVAL naming the line, and the table in use stays as it was. */
 int hp_tune_load(const char *path);
 
 /* Measurement hook.  While enabled, every reduce-kernel launch (the

@@ -155,11 +155,22 @@ int tune_load(const char *path) {
   if (!f) return set_error(HP_EINVAL, "cannot open tuning table %s", path);
   std::vector<TuneEntry> tab;
   char line[256];
+  int lineno = 0;
   while (fgets(line, sizeof line, f)) {
+    ++lineno;
     if (line[0] == '#' || line[0] == '\n') continue;
     TuneEntry t;
-    if (sscanf(line, "%d %d %d %d %d %d", &t.ln, &t.lp, &t.strategy, &t.block, &t.vpt, &t.G) == 6)
-      tab.push_back(t);
+    if (sscanf(line, "%d %d %d %d %d %d", &t.ln, &t.lp, &t.strategy, &t.block, &t.vpt, &t.G) != 6) continue;
+    // a line the launch code cannot honour fails the whole load, and the
+    // table in use stays as it was
+    const bool ok = t.ln >= 0 && t.ln < 64 && t.lp >= 0 && t.lp < 32 && t.strategy >= HP_STRATEGY_LDS &&
+                    t.strategy <= HP_STRATEGY_SAMPLED && (t.block == 256 || t.block == 512 || t.block == 1024) &&
+                    (t.vpt == 2 || t.vpt == 4 || t.vpt == 8) && t.G >= 0 && t.G <= (1 << 20);
+    if (!ok) {
+      fclose(f);
+      return set_error(HP_EINVAL, "tuning table %s line %d: unsupported entry", path, lineno);
+    }
+    tab.push_back(t);
   }
   fclose(f);
   std::lock_guard<std::mutex> lk(g_mu);

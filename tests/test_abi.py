@@ -176,3 +176,25 @@ def test_new_entry_points_reject_bad_arguments_before_any_device_call():
     assert lib.hp_hull_melkman(ctypes.c_void_p(8), ctypes.c_void_p(8), ctypes.c_void_p(8), 4, ctypes.c_void_p(8),
                                ctypes.c_void_p(8), 7, ctypes.c_void_p(8), None, 0, None) == _lib.HP_ECAPACITY
     assert lib.hp_last_error().decode()
+
+
+def test_tuning_table(tmp_path):
+    """The shipped table loads; a table with an entry the launch code cannot
+    honour is refused as a whole; every shape the tuner tries is accepted."""
+    from paper_1505_00914_amd import tune
+    lib = _lib.load()
+    shipped = os.path.join(os.path.dirname(_lib.LIB_PATH), "tuning_gfx950.txt")
+    assert lib.hp_tune_load(shipped.encode()) == 0
+    bad = tmp_path / "bad.txt"
+    bad.write_text("# ln lp strategy block vpt grid\n23 12 3 1024 2 256\n24 12 3 300 2 256\n")
+    assert lib.hp_tune_load(str(bad).encode()) == _lib.HP_EINVAL
+    assert "line 3" in lib.hp_last_error().decode()
+    bad.write_text("23 12 9 1024 2 256\n")
+    assert lib.hp_tune_load(str(bad).encode()) == _lib.HP_EINVAL
+    assert lib.hp_tune_load(shipped.encode()) == 0
+    for n, p in [(1 << 17, 1 << 10), (1 << 23, 1 << 12), (1 << 26, 1 << 16), (1 << 28, 1 << 20), (1000, 20_000)]:
+        shapes = list(tune._candidates(n, p, 256, 20_478))
+        assert shapes
+        for strategy, block, vpt, grid in shapes:
+            assert lib.hp_tune_set(strategy, block, vpt, grid) == 0, (strategy, block, vpt, grid)
+    assert lib.hp_tune_set(0, 0, 0, 0) == 0
