@@ -9,5 +9,5 @@ from .oracle import (  # noqa: F401
     build, lib_path, reduce, mask, ctz_positions, extract, chain, reduced,
     hull_chain, hull_full, precondition_and_hull, bbox, translate, auto,
     tree_levels, array_insert, tree_insert, tree_extract, hull_melkman,
-    bbox_f32, quantize_f32, auto_f32,
+    bbox_f32, quantize_f32, auto_f32, rescan_y,
 )

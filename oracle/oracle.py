@@ -337,3 +337,16 @@ def auto_f32(pts, p: int, lib: str | None = None) -> dict:
     r.update({"box": (xmin, xmax, ymin, ymax), "scale": scale, "origin": (xmin, ymin), "points": q})
     return r
 
+
+def rescan_y(x, clo, chi, p: int, lib: str | None = None) -> dict:
+    """The second sweep along y (Results, rx -> rxy): Algorithm 1 on the
+    reduced set of a chain with x and y exchanged, then its chain: per row y
+    the smallest and largest x.  Composed of the pinned functions above."""
+    R = reduced(x, clo, chi, lib)
+    T = np.ascontiguousarray(np.stack([R[:, 1], R[:, 0]], axis=1)) if R.shape[0] else np.zeros((0, 2), np.int32)
+    lo, hi = reduce(T, p, lib)
+    y, xlo, xhi = chain(lo, hi, p, lib)
+    s2 = int(reduced(y, xlo, xhi, lib).shape[0])
+    return {"lo": lo, "hi": hi, "mask": mask(lo, hi, p, lib), "y": y, "xlo": xlo, "xhi": xhi, "k": int(y.shape[0]),
+            "s": s2}
+

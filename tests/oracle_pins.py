@@ -507,9 +507,40 @@ def pin_float_input(lib=None):
     return errs
 
 
+@_safe
+def pin_rescan_y(lib=None):
+    """The second sweep along y: on the worked example, worked by hand from the
+    paper's L, rows 1..5 keep x ranges 1-1, 2-5, 4-5, 1-2 and 3-3, so the nine
+    reduced points become eight (the row y = 2 drops (3, 2)); on random clouds
+    the second set is never larger and has the same hull."""
+    errs = []
+    f = fixtures.read("worked_example_p5.txt")
+    r = _run_path(fixtures.pairs(f["points"]), 5, lib)
+    q = oracle.rescan_y(r["x"], r["clo"], r["chi"], 5, lib=lib)
+    rows = list(zip(q["y"].tolist(), q["xlo"].tolist(), q["xhi"].tolist()))
+    if rows != [(1, 1, 1), (2, 2, 5), (3, 4, 5), (4, 1, 2), (5, 3, 3)] or q["s"] != 8:
+        errs.append(f"worked example rescan: {rows}, s2 = {q['s']}")
+    rng = np.random.default_rng(117)
+    for t in range(60):
+        p = int(rng.integers(1, 60))
+        pts = rng.integers(1, p + 1, size=(int(rng.integers(1, 400)), 2))
+        r = _run_path(pts, p, lib)
+        q = oracle.rescan_y(r["x"], r["clo"], r["chi"], p, lib=lib)
+        s1 = oracle.reduced(r["x"], r["clo"], r["chi"], lib=lib).shape[0]
+        if q["s"] > s1:
+            errs.append(f"p={p}: rxy {q['s']} > rx {s1}")
+        R2 = oracle.reduced(q["y"], q["xlo"], q["xhi"], lib=lib)
+        back = np.stack([R2[:, 1], R2[:, 0]], 1)
+        if not np.array_equal(oracle.hull_full(back, lib=lib), r["hull"]):
+            errs.append(f"p={p}: hull of the rescanned set differs")
+        if len(errs) > 5:
+            break
+    return errs
+
+
 ALL_PINS = [pin_worked_example, pin_gap_example, pin_table1, pin_block_index,
             pin_closed_forms, pin_brute_random, pin_exhaustive_p3, pin_qhull,
-            pin_appendix, pin_invariants, pin_metamorphic, pin_errors, pin_steps12, pin_bitsets, pin_melkman, pin_float_input]
+            pin_appendix, pin_invariants, pin_metamorphic, pin_errors, pin_steps12, pin_bitsets, pin_melkman, pin_float_input, pin_rescan_y]
 
 # the cheap pins, run first against planted mistakes
 FAST_PINS = [pin_worked_example, pin_gap_example, pin_table1, pin_block_index,
