@@ -748,6 +748,23 @@ def bench_melkman(args, torch, hp, synth) -> dict:
         res[name] = {"us_per_call": round(start.elapsed_time(stop) * 1e3 / steps, 2),
                      "h": got["h"], "parity_vs_oracle": bool(np.array_equal(got["hull"], want["hull"]))}
     res["k"] = got["k"]
+    # the second sweep along y on the same chain (rx -> rxy)
+    rb = hp.RescanBuffers.allocate(got["k"], p, pts.device)
+    hp.hp_rescan_y(buf, rb, stream)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(steps):
+        hp.hp_rescan_y(buf, rb, stream)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    want = oracle.rescan_y(got["x"], got["clo"], got["chi"], p)
+    info = rb.info.cpu().tolist()
+    k2 = info[1]
+    ok = (info[0] == 0 and k2 == want["k"] and info[2] == want["s"]
+          and np.array_equal(rb.ry[:k2].cpu().numpy(), want["y"]) and np.array_equal(rb.rlo[:k2].cpu().numpy(), want["xlo"])
+          and np.array_equal(rb.rhi[:k2].cpu().numpy(), want["xhi"]))
+    res["rescan_y"] = {"us_per_call": round(start.elapsed_time(stop) * 1e3 / steps, 2), "rx": got["s"], "rxy": info[2],
+                       "rows": k2, "parity_vs_oracle": bool(ok)}
     return res
 
 

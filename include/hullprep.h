@@ -275,6 +275,23 @@ int hp_hull_melkman(const int32_t *cx, const int32_t *clo, const int32_t *chi, i
                     int32_t *hx, int32_t *hy, int32_t hull_cap, int32_t *info, void *ws, size_t ws_bytes,
                     void *stream);
 
+/* The second sweep along y (Results: the rx -> rxy rescan): Algorithm 1 run
+ * again on the reduced set of a chain with rows for columns, keeping per row
+ * y the smallest and largest x, then compacted like hp_precondition.  The
+ * hull of the result (read back as (x, y)) is the hull of the chain.
+ *   cx, clo, chi  device chain of k columns (k: a HOST value, e.g. read from
+ *                 info[HP_INFO_K] after the call that produced the chain)
+ *   p             the side of the square (rows run over [1, p])
+ *   lo, hi, mask  optional per-row extremes and row bit array, as in
+ *                 hp_precondition (lo = smallest x, hi = largest x)
+ *   ry, rlo, rhi  device, chain_cap >= min(2k, p) each: the rows in ascending y
+ *   info          device int32[4]: status, rows k2, points s2 (rxy)
+ *   ws            hp_rescan_y_workspace_bytes(k, p) bytes of device memory */
+int hp_rescan_y_workspace_bytes(int32_t k, int32_t p, size_t *bytes);
+int hp_rescan_y(const int32_t *cx, const int32_t *clo, const int32_t *chi, int32_t k, int32_t p, int32_t *lo,
+                int32_t *hi, uint64_t *mask, int32_t *ry, int32_t *rlo, int32_t *rhi, int32_t chain_cap,
+                int32_t *info, void *ws, size_t ws_bytes, void *stream);
+
 /* Steps 1-4 fused: the chain and its hull in one call (the hull is built
  * from L directly, in parallel with the chain write).  Arguments as above;
  * hull_cap >= 2 * min(n, p).  Uses the hp_workspace_bytes(n, p) workspace. */

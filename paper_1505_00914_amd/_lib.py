@@ -43,6 +43,9 @@ SIGNATURES = {
     "hp_precondition": (ctypes.c_int, [_vp, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _i32,
                                        _vp, _vp, _sz, _vp]),
     "hp_hull_workspace_bytes": (ctypes.c_int, [_i32, _szp]),
+    "hp_rescan_y_workspace_bytes": (ctypes.c_int, [_i32, _i32, _szp]),
+    "hp_rescan_y": (ctypes.c_int, [_vp, _vp, _vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _sz,
+                                   _vp]),
     "hp_hull_melkman_workspace_bytes": (ctypes.c_int, [_i32, _szp]),
     "hp_hull_melkman": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp, _i32, _vp, _vp, _sz, _vp]),
     "hp_bitset_words": (ctypes.c_int, [_i32, _i32, _i64p]),

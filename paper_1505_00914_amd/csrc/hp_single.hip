@@ -269,6 +269,23 @@ __global__ __launch_bounds__(256) void k_quantize_f32(const float2 *__restrict__
   if (bad) info[HP_INFO_STATUS] = HP_ERANGE;
 }
 
+// The second sweep: the reduced set of a chain turned into row points
+// (y, x), two per column -- (lo, x) and (hi, x) -- so that Algorithm 1 run
+// on them with rows for columns keeps, per row, the smallest and largest x.
+// A column with lo == hi gives the same point twice, which changes no
+// per-row extreme.
+__global__ __launch_bounds__(256) void k_chain_transpose(const int32_t *__restrict__ cx,
+                                                         const int32_t *__restrict__ clo,
+                                                         const int32_t *__restrict__ chi, int32_t k,
+                                                         int2 *__restrict__ out) {
+  const int stride = gridDim.x * blockDim.x;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < k; t += stride) {
+    const int32_t x = cx[t];
+    out[2 * t] = make_int2(clo[t], x);
+    out[2 * t + 1] = make_int2(chi[t], x);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Finish: one workgroup per slab of 64 positions, of FB threads: 1024, or
 // 256 when there are many slabs (the launch is then bound by how fast the
@@ -2287,5 +2304,40 @@ extern "C" int hp_quantize_f32(const float *pts, int64_t n, double ox, double oy
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return set_error(HP_EDEVICE, "k_quantize_f32 launch: %s", hipGetErrorString(e));
   return HP_OK;
+}
+
+extern "C" int hp_rescan_y_workspace_bytes(int32_t k, int32_t p, size_t *bytes) {
+  if (!bytes) return set_error(HP_EINVAL, "bytes is NULL");
+  if (k < 0 || p < 1 || p > HP_P_MAX) return set_error(HP_EINVAL, "bad k or p");
+  *bytes = align_up(sizeof(int2) * 2 * (size_t)k) + ws_bytes_for(2 * (int64_t)k, p);
+  return HP_OK;
+}
+
+extern "C" int hp_rescan_y(const int32_t *cx, const int32_t *clo, const int32_t *chi, int32_t k, int32_t p,
+                           int32_t *lo, int32_t *hi, uint64_t *mask, int32_t *ry, int32_t *rlo, int32_t *rhi,
+                           int32_t chain_cap, int32_t *info, void *ws, size_t ws_bytes, void *stream) {
+  if (k < 0) return set_error(HP_EINVAL, "k < 0");
+  if (k > 0 && (!cx || !clo || !chi)) return set_error(HP_EINVAL, "chain arrays must not be NULL");
+  if (!ws) return set_error(HP_EINVAL, "workspace is NULL");
+  size_t need = 0;
+  const int rq = hp_rescan_y_workspace_bytes(k, p, &need);
+  if (rq != HP_OK) return rq;
+  if (ws_bytes < need) return set_error(HP_ECAPACITY, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+  int2 *rows = static_cast<int2 *>(ws);
+  const size_t head = align_up(sizeof(int2) * 2 * (size_t)k);
+  void *ws2 = static_cast<char *>(ws) + head;
+  const int64_t n2 = 2 * (int64_t)k;
+  const int rc = check_common(reinterpret_cast<const int32_t *>(rows), n2, p, lo, hi, ry, rlo, rhi, chain_cap, info,
+                              ws2);
+  if (rc != HP_OK) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if (k > 0) {
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(4 * device_info().cus, (k + 255) / 256));
+    hipLaunchKernelGGL(k_chain_transpose, dim3(grid), dim3(256), 0, s, cx, clo, chi, k, rows);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(HP_EDEVICE, "k_chain_transpose launch: %s", hipGetErrorString(e));
+  }
+  return run_single(reinterpret_cast<const int32_t *>(rows), n2, p, lo, hi, mask, ry, rlo, rhi, chain_cap, nullptr,
+                    nullptr, 0, info, ws2, ws_bytes - head, s, false);
 }
 

@@ -144,6 +144,56 @@ def hp_hull_melkman(buf: Buffers, stream=None, ws: torch.Tensor | None = None) -
               _ptr(buf.hy), buf.hx.numel(), _ptr(buf.info), _ptr(ws), ws.numel(), _stream(stream))
 
 
+@dataclass
+class RescanBuffers:
+    """Caller-owned device buffers of the second sweep for a chain of k columns."""
+    k: int
+    p: int
+    ry: torch.Tensor
+    rlo: torch.Tensor
+    rhi: torch.Tensor
+    lo: torch.Tensor
+    hi: torch.Tensor
+    mask: torch.Tensor
+    info: torch.Tensor
+    ws: torch.Tensor
+
+    @staticmethod
+    def allocate(k: int, p: int, device) -> "RescanBuffers":
+        cap = max(1, min(2 * k, p))
+        i32 = dict(dtype=torch.int32, device=device)
+        size = ctypes.c_size_t()
+        _lib.call("hp_rescan_y_workspace_bytes", k, p, ctypes.byref(size))
+        return RescanBuffers(k, p, torch.empty(cap, **i32), torch.empty(cap, **i32), torch.empty(cap, **i32),
+                             torch.empty(p, **i32), torch.empty(p, **i32),
+                             torch.empty((p + 63) // 64, dtype=torch.int64, device=device), torch.zeros(4, **i32),
+                             torch.empty(max(1, size.value), dtype=torch.uint8, device=device))
+
+
+def hp_rescan_y(buf: Buffers, rb: RescanBuffers, stream=None) -> None:
+    """Enqueue the second sweep along y on the chain in ``buf`` (of rb.k
+    columns, a host value) into ``rb`` (no sync)."""
+    _lib.call("hp_rescan_y", _ptr(buf.cx), _ptr(buf.clo), _ptr(buf.chi), rb.k, rb.p, _ptr(rb.lo), _ptr(rb.hi),
+              _ptr(rb.mask), _ptr(rb.ry), _ptr(rb.rlo), _ptr(rb.rhi), rb.ry.numel(), _ptr(rb.info), _ptr(rb.ws),
+              rb.ws.numel(), _stream(stream))
+
+
+def rescan_y(buf: Buffers, p: int) -> dict:
+    """The second sweep along y on the chain held in ``buf`` (after a run):
+    per row y the smallest and largest x of the reduced set, as a chain of
+    rows with its counts (k2 rows, s2 points)."""
+    torch.cuda.synchronize(buf.info.device)
+    k = int(buf.info[HP_INFO_K].item())
+    rb = RescanBuffers.allocate(k, p, buf.info.device)
+    hp_rescan_y(buf, rb)
+    torch.cuda.synchronize(buf.info.device)
+    inf = rb.info.cpu().tolist()
+    k2 = inf[HP_INFO_K]
+    return {"status": inf[HP_INFO_STATUS], "k": k2, "s": inf[HP_INFO_S], "y": rb.ry[:k2].cpu().numpy(),
+            "xlo": rb.rlo[:k2].cpu().numpy(), "xhi": rb.rhi[:k2].cpu().numpy(), "lo": rb.lo.cpu().numpy(),
+            "hi": rb.hi.cpu().numpy(), "mask": rb.mask.cpu().numpy().view("uint64")}
+
+
 def precondition_then_melkman(points: torch.Tensor, p: int) -> dict:
     """hp_precondition followed by Melkman's hull of its chain."""
     buf = Buffers.allocate(points.shape[0], p, points.device, True)

@@ -75,3 +75,42 @@ def test_bad_chain_reports(hp):
     torch.cuda.synchronize()
     info = buf.info.cpu().tolist()
     assert info[0] == -1 and info[3] == 0
+
+
+# ---------------------------------------------------------------------------
+# The second sweep along y, on the device, against the oracle's
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("kind,n,p,seed", [
+    ("uniform", 100_000, 1024, 0),
+    ("ellipsoids", 200_001, 4096, 2),
+    ("disc", 200_000, 65_536, 6),
+    ("uniform", 1_000, 20_000, 7),
+])
+def test_rescan_y(hp, kind, n, p, seed):
+    pts = synth.cloud(kind, n, p, seed)
+    print(f"[case] rescan {kind} n={n} p={p}", flush=True)
+    r = oracle.precondition_and_hull(pts.numpy(), p)
+    want = oracle.rescan_y(r["x"], r["clo"], r["chi"], p)
+    buf = hp.Buffers.allocate(n, p, "cuda")
+    hp.hp_run(pts.cuda(), p, buf)
+    got = hp.rescan_y(buf, p)
+    assert got["status"] == 0 and got["k"] == want["k"] and got["s"] == want["s"]
+    for key in ("y", "xlo", "xhi", "lo", "hi", "mask"):
+        assert np.array_equal(got[key], want[key]), key
+
+
+def test_rescan_y_worked_example(hp):
+    f = fixtures.read("worked_example_p5.txt")
+    buf = hp.Buffers.allocate(16, 5, "cuda")
+    hp.hp_run(torch.tensor(fixtures.pairs(f["points"]), dtype=torch.int32).cuda(), 5, buf)
+    got = hp.rescan_y(buf, 5)
+    assert list(zip(got["y"].tolist(), got["xlo"].tolist(), got["xhi"].tolist())) == \
+        [(1, 1, 1), (2, 2, 5), (3, 4, 5), (4, 1, 2), (5, 3, 3)]
+    assert got["s"] == 8
+
+
+def test_rescan_y_empty(hp):
+    buf = hp.Buffers.allocate(0, 9, "cuda")
+    hp.hp_run(torch.zeros((0, 2), dtype=torch.int32).cuda(), 9, buf)
+    got = hp.rescan_y(buf, 9)
+    assert got["status"] == 0 and got["k"] == 0 and got["s"] == 0
