@@ -198,3 +198,28 @@ def test_tuning_table(tmp_path):
         for strategy, block, vpt, grid in shapes:
             assert lib.hp_tune_set(strategy, block, vpt, grid) == 0, (strategy, block, vpt, grid)
     assert lib.hp_tune_set(0, 0, 0, 0) == 0
+
+
+def test_binding_rejects_bad_tensors_before_any_device_call():
+    """The Python layer refuses host tensors, wrong dtypes and shapes with
+    ValueError before it calls the library."""
+    import torch
+
+    from paper_1505_00914_amd import hullprep as hp
+    host_pts = torch.ones((4, 2), dtype=torch.int32)
+    with pytest.raises(ValueError):
+        hp.bbox(host_pts)
+    with pytest.raises(ValueError):
+        hp.run_auto(host_pts)
+    with pytest.raises(ValueError):
+        hp.bbox_f32(torch.ones((4, 2), dtype=torch.float32))
+    with pytest.raises(ValueError):
+        hp.run_auto_f32(torch.ones((4, 3), dtype=torch.float32), 8)
+    with pytest.raises(ValueError):
+        hp.hp_bitset_insert(torch.ones(3, dtype=torch.int64), 8, False, torch.zeros(1, dtype=torch.int64),
+                            torch.zeros(2, dtype=torch.int32))
+    with pytest.raises(ValueError):
+        hp.hp_bitset_extract(torch.zeros(1, dtype=torch.int32), 8, False, torch.zeros(8, dtype=torch.int32),
+                             torch.zeros(2, dtype=torch.int32), torch.zeros(1, dtype=torch.uint8))
+    assert hp.bitset_words(1 << 24, True) == 266305
+    assert hp.bitset_words(64, False) == 1
