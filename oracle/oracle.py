@@ -236,16 +236,26 @@ def translate(pts, box, lib: str | None = None) -> tuple[np.ndarray, int]:
     return out, int(p[0])
 
 
-def auto(pts, lib: str | None = None) -> dict:
+def auto(pts, lib: str | None = None, axis: str = "x") -> dict:
     """Steps 1 to 3 and the hull: box, translation, then the whole path on
     the translated points.  Outputs are in translated coordinates; ``origin``
-    (xmin - 1, ymin - 1) maps them back."""
+    (xmin - 1, ymin - 1) maps them back.  ``axis`` "y" sweeps along y (the
+    points with x and y exchanged); "auto" picks the axis of the shorter side
+    of the box (Results)."""
+    if axis != "x":
+        b = bbox(pts, lib)
+        if axis == "y" or (b[3] - b[2]) < (b[1] - b[0]):
+            a = _points(pts)
+            r = auto(np.ascontiguousarray(a[:, ::-1]), lib, "x")
+            r["axis"] = "y"
+            return r
     box = bbox(pts, lib)
     t, p = translate(pts, box, lib)
     r = precondition_and_hull(t, p, lib)
     r["p"] = p
     r["box"] = box
     r["origin"] = (box[0] - 1, box[2] - 1)
+    r["axis"] = "x"
     return r
 
 

@@ -538,9 +538,31 @@ def pin_rescan_y(lib=None):
     return errs
 
 
+@_safe
+def pin_sweep_axis(lib=None):
+    """The choice of sweep axis: the hull of the y sweep, read back as (x, y),
+    is the hull of the x sweep; "auto" sweeps along the shorter side."""
+    errs = []
+    rng = np.random.default_rng(117_2)
+    for t in range(30):
+        wx, wy = int(rng.integers(1, 80)), int(rng.integers(1, 80))
+        pts = np.stack([rng.integers(0, wx, 300), rng.integers(0, wy, 300)], 1) + rng.integers(-50, 50, 2)
+        rx = oracle.auto(pts, lib=lib, axis="x")
+        ry = oracle.auto(pts, lib=lib, axis="y")
+        back = ry["hull"][:, ::-1] + [ry["origin"][1], ry["origin"][0]]
+        want = rx["hull"] + [rx["origin"][0], rx["origin"][1]]
+        if not np.array_equal(oracle.hull_full(back, lib=lib), oracle.hull_full(want, lib=lib)):
+            errs.append(f"case {t}: hulls of the two sweeps differ")
+        ra = oracle.auto(pts, lib=lib, axis="auto")
+        ex, ey = pts[:, 0].max() - pts[:, 0].min(), pts[:, 1].max() - pts[:, 1].min()
+        if ra["axis"] != ("y" if ey < ex else "x"):
+            errs.append(f"case {t}: auto swept {ra['axis']} for extents {ex}, {ey}")
+    return errs
+
+
 ALL_PINS = [pin_worked_example, pin_gap_example, pin_table1, pin_block_index,
             pin_closed_forms, pin_brute_random, pin_exhaustive_p3, pin_qhull,
-            pin_appendix, pin_invariants, pin_metamorphic, pin_errors, pin_steps12, pin_bitsets, pin_melkman, pin_float_input, pin_rescan_y]
+            pin_appendix, pin_invariants, pin_metamorphic, pin_errors, pin_steps12, pin_bitsets, pin_melkman, pin_float_input, pin_rescan_y, pin_sweep_axis]
 
 # the cheap pins, run first against planted mistakes
 FAST_PINS = [pin_worked_example, pin_gap_example, pin_table1, pin_block_index,
