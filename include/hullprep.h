@@ -131,6 +131,12 @@ int hp_bbox_workspace_bytes(size_t *bytes);
  * otherwise).  With (ox, oy) = (xmin, ymin) from hp_bbox_f32 and scale =
  * (p - 1) / max(xmax - xmin, ymax - ymin), every point lands in [1, p]^2
  * and the output can go straight to hp_run with side p. */
+/* Choice of sweep axis (Results: sweeping along the shorter side of the box
+ * keeps fewer points): out (device, n int32 pairs) = the points with x and y
+ * exchanged, so that the path on out sweeps along y.  One pass, 16n bytes.
+ * pts and out are 8-byte aligned and must not overlap (HP_EINVAL). */
+int hp_transpose_points(const int32_t *pts, int64_t n, int32_t *out, void *stream);
+
 int hp_bbox_f32(const float *pts, int64_t n, float *box, void *ws, size_t ws_bytes, void *stream);
 int hp_quantize_f32(const float *pts, int64_t n, double ox, double oy, double scale, int32_t *out,
                     int32_t *info, void *stream);

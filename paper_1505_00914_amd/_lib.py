@@ -56,6 +56,7 @@ SIGNATURES = {
     "hp_bitset_build": (ctypes.c_int, [_vp, _i64, _i32, _i32, _vp, _vp, _vp, _sz, _vp]),
     "hp_bitset_extract": (ctypes.c_int, [_vp, _i32, _i32, _vp, _i32, _vp, _vp, _sz, _vp]),
     "hp_bbox_workspace_bytes": (ctypes.c_int, [_szp]),
+    "hp_transpose_points": (ctypes.c_int, [_vp, _i64, _vp, _vp]),
     "hp_bbox_f32": (ctypes.c_int, [_vp, _i64, _vp, _vp, _sz, _vp]),
     "hp_quantize_f32": (ctypes.c_int, [_vp, _i64, ctypes.c_double, ctypes.c_double, ctypes.c_double, _vp, _vp,
                                        _vp]),

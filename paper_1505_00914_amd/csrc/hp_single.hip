@@ -286,6 +286,43 @@ __global__ __launch_bounds__(256) void k_chain_transpose(const int32_t *__restri
   }
 }
 
+// Sweep axis (Results: sweeping along the shorter side keeps fewer points):
+// the points with x and y exchanged, two points per 16-byte load and store;
+// an odd leading point (8-byte aligned start) and an odd last point on their
+// own.  pts and out must not overlap.
+__global__ __launch_bounds__(256) void k_points_transpose(const int32_t *__restrict__ pts, int64_t n,
+                                                          int32_t *__restrict__ out) {
+  const int64_t head = (n > 0 && ((uintptr_t)pts & 15) != 0) ? 1 : 0;
+  const int64_t nv = (n - head) >> 1;
+  const int4 *v = reinterpret_cast<const int4 *>(pts + 2 * head);
+  const bool out_aligned = (((uintptr_t)(out + 2 * head)) & 15) == 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i0 == 0) {
+    if (head) {
+      out[0] = pts[1];
+      out[1] = pts[0];
+    }
+    const int64_t t = head + 2 * nv;
+    if (t < n) {
+      out[2 * t] = pts[2 * t + 1];
+      out[2 * t + 1] = pts[2 * t];
+    }
+  }
+  for (int64_t i = i0; i < nv; i += stride) {
+    const int4 q = load_stream(&v[i]);
+    const int64_t o = 2 * head + 4 * i;
+    if (out_aligned) {
+      *reinterpret_cast<int4 *>(out + o) = make_int4(q.y, q.x, q.w, q.z);
+    } else {
+      out[o] = q.y;
+      out[o + 1] = q.x;
+      out[o + 2] = q.w;
+      out[o + 3] = q.z;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Finish: one workgroup per slab of 64 positions, of FB threads: 1024, or
 // 256 when there are many slabs (the launch is then bound by how fast the
@@ -2339,5 +2376,19 @@ extern "C" int hp_rescan_y(const int32_t *cx, const int32_t *clo, const int32_t 
   }
   return run_single(reinterpret_cast<const int32_t *>(rows), n2, p, lo, hi, mask, ry, rlo, rhi, chain_cap, nullptr,
                     nullptr, 0, info, ws2, ws_bytes - head, s, false);
+}
+
+extern "C" int hp_transpose_points(const int32_t *pts, int64_t n, int32_t *out, void *stream) {
+  if (n < 0) return set_error(HP_EINVAL, "n = %lld < 0", (long long)n);
+  if (n == 0) return HP_OK;
+  if (!pts || !out) return set_error(HP_EINVAL, "pts or out is NULL");
+  if (((uintptr_t)pts & 7) || ((uintptr_t)out & 7)) return set_error(HP_EINVAL, "pts or out is not 8-byte aligned");
+  const uintptr_t a = (uintptr_t)pts, b = (uintptr_t)out, bytes = (uintptr_t)(8 * n);
+  if (a < b + bytes && b < a + bytes) return set_error(HP_EINVAL, "pts and out overlap");
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(8 * device_info().cus, ((n + 1) / 2 + 255) / 256));
+  hipLaunchKernelGGL(k_points_transpose, dim3(grid), dim3(256), 0, (hipStream_t)stream, pts, n, out);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_error(HP_EDEVICE, "k_points_transpose launch: %s", hipGetErrorString(e));
+  return HP_OK;
 }
 

@@ -248,13 +248,37 @@ def bbox(points: torch.Tensor, stream=None) -> tuple[int, int, int, int]:
     return tuple(int(v) for v in box.cpu().tolist())
 
 
-def run_auto(points: torch.Tensor, export_L: bool = True) -> dict:
+def hp_transpose_points(points: torch.Tensor, out: torch.Tensor, stream=None) -> None:
+    """Enqueue out = the points with x and y exchanged (no sync)."""
+    n = _check_points(points)
+    if out.dtype != torch.int32 or tuple(out.shape) != (n, 2) or not out.is_contiguous() or not out.is_cuda:
+        raise ValueError("out must be a contiguous (n, 2) int32 device tensor")
+    _lib.call("hp_transpose_points", _ptr(points), n, _ptr(out), _stream(stream))
+
+
+def run_auto(points: torch.Tensor, export_L: bool = True, axis: str = "x") -> dict:
     """Steps 1 and 2, then the path: the bounding box on the device, p and the
     origin from it, and the fused path on the translated points.  Outputs are
-    in translated coordinates; ``origin`` maps them back."""
+    in translated coordinates; ``origin`` maps them back.
+
+    ``axis`` picks the sweep: "x" (Algorithm 1 as written), "y" (the points
+    with x and y exchanged, one extra pass), or "auto", the axis of the
+    shorter side of the box.  With "y" every output is in exchanged
+    coordinates (L per row y, hull of the (y, x) points); ``axis`` in the
+    result says which."""
     n = _check_points(points)
     if n == 0:
         raise HullprepError(HP_EINVAL, "run_auto", "no points")
+    if axis not in ("x", "y", "auto"):
+        raise ValueError("axis must be 'x', 'y' or 'auto'")
+    if axis != "x":
+        xmin, xmax, ymin, ymax = bbox(points)
+        if axis == "y" or (ymax - ymin) < (xmax - xmin):
+            t = torch.empty_like(points)
+            hp_transpose_points(points, t)
+            out = run_auto(t, export_L, "x")
+            out["axis"] = "y"
+            return out
     xmin, xmax, ymin, ymax = bbox(points)
     p = max(xmax - xmin, ymax - ymin) + 1
     if p > _lib.HP_P_MAX:
@@ -266,6 +290,7 @@ def run_auto(points: torch.Tensor, export_L: bool = True) -> dict:
     out["p"] = p
     out["origin"] = origin
     out["box"] = (xmin, xmax, ymin, ymax)
+    out["axis"] = "x"
     return out
 
 

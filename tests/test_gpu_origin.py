@@ -235,3 +235,32 @@ def test_bitset_p1(hp, tree):
     assert got["status"] == 0 and got["cols"].tolist() == [1]
     got = hp.bitset_roundtrip(torch.tensor([], dtype=torch.int32, device="cuda"), 1, tree)
     assert got["status"] == 0 and got["count"] == 0
+
+
+# ---------------------------------------------------------------------------
+# Choice of sweep axis
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("shift", [0, 1])
+def test_transpose_points(hp, shift):
+    a = _moved("uniform", 100_001, 5000, 8, (-77, 9))
+    dev = torch.from_numpy(a).cuda()[shift:]
+    for out_shift in (0, 1):
+        out = torch.empty((a.shape[0] - shift + out_shift, 2), dtype=torch.int32, device="cuda")[out_shift:]
+        hp.hp_transpose_points(dev, out)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), a[shift:, ::-1])
+
+
+@pytest.mark.parametrize("axis", ["x", "y", "auto"])
+@pytest.mark.parametrize("wide", [True, False])
+def test_run_auto_axis(hp, axis, wide):
+    rng = np.random.default_rng(31 + wide)
+    w, h = (4000, 300) if wide else (300, 4000)
+    a = np.stack([rng.integers(0, w, 200_000), rng.integers(0, h, 200_000)], 1).astype(np.int32) - 1234
+    print(f"[case] run_auto axis={axis} wide={wide}", flush=True)
+    want = oracle.auto(a, axis=axis)
+    got = hp.run_auto(torch.from_numpy(a).cuda(), axis=axis)
+    assert got["axis"] == want["axis"]
+    if axis == "auto":
+        assert got["axis"] == ("y" if wide else "x")
+    _compare_auto(got, want, f"axis {axis}")
