@@ -271,15 +271,13 @@ def run_auto(points: torch.Tensor, export_L: bool = True, axis: str = "x") -> di
         raise HullprepError(HP_EINVAL, "run_auto", "no points")
     if axis not in ("x", "y", "auto"):
         raise ValueError("axis must be 'x', 'y' or 'auto'")
-    if axis != "x":
-        xmin, xmax, ymin, ymax = bbox(points)
-        if axis == "y" or (ymax - ymin) < (xmax - xmin):
-            t = torch.empty_like(points)
-            hp_transpose_points(points, t)
-            out = run_auto(t, export_L, "x")
-            out["axis"] = "y"
-            return out
     xmin, xmax, ymin, ymax = bbox(points)
+    if axis == "y" or (axis == "auto" and (ymax - ymin) < (xmax - xmin)):
+        t = torch.empty_like(points)
+        hp_transpose_points(points, t)
+        out = run_auto(t, export_L, "x")
+        out["axis"] = "y"
+        return out
     p = max(xmax - xmin, ymax - ymin) + 1
     if p > _lib.HP_P_MAX:
         raise HullprepError(HP_EINVAL, "run_auto", f"extent {p} exceeds {_lib.HP_P_MAX}")
