@@ -223,3 +223,15 @@ def test_binding_rejects_bad_tensors_before_any_device_call():
                              torch.zeros(2, dtype=torch.int32), torch.zeros(1, dtype=torch.uint8))
     assert hp.bitset_words(1 << 24, True) == 266305
     assert hp.bitset_words(64, False) == 1
+
+
+def test_transpose_points_arguments():
+    lib = _lib.load()
+    assert lib.hp_transpose_points(None, 0, None, None) == 0                      # nothing to do
+    assert lib.hp_transpose_points(None, 4, ctypes.c_void_p(64), None) == _lib.HP_EINVAL
+    assert lib.hp_transpose_points(ctypes.c_void_p(64), 4, ctypes.c_void_p(68), None) == _lib.HP_EINVAL  # misaligned
+    assert lib.hp_transpose_points(ctypes.c_void_p(64), 4, ctypes.c_void_p(72), None) == _lib.HP_EINVAL  # overlap
+    assert "overlap" in lib.hp_last_error().decode()
+    assert lib.hp_rescan_y_workspace_bytes(-1, 8, ctypes.byref(ctypes.c_size_t())) == _lib.HP_EINVAL
+    assert lib.hp_rescan_y(None, None, None, 3, 8, None, None, None, None, None, None, 6, None, None, 0,
+                           None) == _lib.HP_EINVAL
