@@ -23,8 +23,12 @@
  *   (the square of side p of the "Proposed heuristic" section).  Points
  *   outside that square are skipped and reported through the device status
  *   word (HP_ERANGE); the other outputs of that cloud are then unspecified.
- * - 1 <= p <= HP_P_MAX so that the sentinel p+1 fits in int32.  n >= 0 is a
- *   64-bit count.
+ * - 1 <= p <= HP_P_MAX.  The paper only needs p + 1 to fit the coordinate
+ *   type; the library's bound is lower because the compaction launches one
+ *   256-thread workgroup per 64 columns and one dispatch holds fewer than
+ *   2^32 work-items (ceil(HP_P_MAX / 64) * 256 = 2^32 - 256), which also
+ *   keeps every count (k <= p, s <= 2p) inside int32.  n >= 0 is a 64-bit
+ *   count.
  * - L is two int32 arrays lo[p], hi[p]; column x lives at index x-1.
  * - The bit array M uses 64-bit words: column i is bit (i-1)&63 of word
  *   (i-1)>>6 (Discussion, "Extraction using an array of bits", w = 64).
@@ -70,7 +74,7 @@ extern "C" {
 #define HP_ENOMEM    (-5)  /* host or device allocation failed (plans, servers)  */
 #define HP_ETIMEOUT  (-6)  /* hp_server_wait: the request has not completed yet */
 
-#define HP_P_MAX 2147483646
+#define HP_P_MAX 1073741760  /* 2^30 - 64 */
 
 #define HP_INFO_STATUS 0
 #define HP_INFO_K      1
@@ -126,7 +130,7 @@ int hp_bbox_workspace_bytes(size_t *bytes);
  * hp_quantize_f32: out (device int32 pairs, n of them) = (floor((x - ox) *
  * scale) + 1, floor((y - oy) * scale) + 1), evaluated in double precision
  * with one rounding per operation, so results are reproducible bit for bit.
- * A coordinate that is NaN or outside [1, HP_P_MAX] is written as 0 and sets
+ * A coordinate that is NaN or outside [1, 2^31 - 2] is written as 0 and sets
  * info[HP_INFO_STATUS] = HP_ERANGE (device int32[1] at least; HP_OK
  * otherwise).  With (ox, oy) = (xmin, ymin) from hp_bbox_f32 and scale =
  * (p - 1) / max(xmax - xmin, ymax - ymin), every point lands in [1, p]^2

@@ -13,7 +13,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libhullprep.so")
 
 HP_OK, HP_EINVAL, HP_ERANGE, HP_ECAPACITY, HP_EDEVICE, HP_ENOMEM, HP_ETIMEOUT = 0, -1, -2, -3, -4, -5, -6
-HP_P_MAX = 2147483646
+HP_P_MAX = (1 << 30) - 64
 HP_INFO_STATUS, HP_INFO_K, HP_INFO_S, HP_INFO_H, HP_INFO_WORDS = 0, 1, 2, 3, 4
 HP_STRATEGY_AUTO, HP_STRATEGY_LDS, HP_STRATEGY_GLOBAL, HP_STRATEGY_LDS_PARTIAL, HP_STRATEGY_WINDOW = 0, 1, 2, 3, 4
 HP_STRATEGY_SAMPLED = 5

@@ -62,8 +62,8 @@ __device__ __forceinline__ void stream_points(const int32_t *__restrict__ pts, i
   const int64_t step = nwg * chunk;
   int64_t t0 = wg * chunk;
   // Full chunks, software-pipelined: the next chunk's loads are issued
-  // (unconditionally, from a valid address) before the current chunk is
-  // folded into L, so VPT 16-byte loads per lane stay in flight.
+  // before the current chunk is folded into L, so VPT 16-byte loads per
+  // lane stay in flight.
   int4 q[VPT];
   bool have = t0 + chunk <= nv;
   if (have) {
@@ -74,13 +74,19 @@ __device__ __forceinline__ void stream_points(const int32_t *__restrict__ pts, i
   while (have) {
     const int64_t t1 = t0 + step;
     const bool have_next = t1 + chunk <= nv;
-    const int64_t tl = have_next ? t1 : t0;
     Batch<VPT> b;
     gather<VPT, LDS, WIN, FILT>(L, p, q, b, bad, c0, wc, filt, fshift, wq, &qn);
+    // the next chunk's loads, only when there is one (a workgroup's last
+    // full chunk issues none, so no vector is read twice)
     int4 qv[VPT];
 #pragma unroll
-    for (int u = 0; u < VPT; ++u)
-      qv[u] = shift_by(WIN ? v[tl + u * BLOCK + threadIdx.x] : load_stream(&v[tl + u * BLOCK + threadIdx.x]), ox, oy);
+    for (int u = 0; u < VPT; ++u) qv[u] = q[u];
+    if (have_next) {
+#pragma unroll
+      for (int u = 0; u < VPT; ++u)
+        qv[u] = shift_by(WIN ? v[t1 + u * BLOCK + threadIdx.x] : load_stream(&v[t1 + u * BLOCK + threadIdx.x]), ox,
+                         oy);
+    }
     apply<VPT, LDS, FILT>(L, b, wq, &qn);
 #pragma unroll
     for (int u = 0; u < VPT; ++u) q[u] = qv[u];
@@ -219,12 +225,15 @@ __device__ __forceinline__ void stream_points_dyn(const int32_t *__restrict__ pt
     for (int u = 0; u < VPT; ++u) q[u] = shift_by(load_stream(&v[cur * chunk + u * BLOCK + threadIdx.x]), ox, oy);
   }
   while (cur >= 0) {
-    const int64_t tl = nx >= 0 ? nx : cur;
     Batch<VPT> b;
     gather<VPT, LDS, false, FILT>(L, p, q, b, bad, 0, 0, filt, fshift, wq, &qn);
     int4 qv[VPT];
 #pragma unroll
-    for (int u = 0; u < VPT; ++u) qv[u] = shift_by(load_stream(&v[tl * chunk + u * BLOCK + threadIdx.x]), ox, oy);
+    for (int u = 0; u < VPT; ++u) qv[u] = q[u];
+    if (nx >= 0) {
+#pragma unroll
+      for (int u = 0; u < VPT; ++u) qv[u] = shift_by(load_stream(&v[nx * chunk + u * BLOCK + threadIdx.x]), ox, oy);
+    }
     apply<VPT, LDS, FILT>(L, b, wq, &qn);
     ++folded;
     const int64_t nn = nx >= 0 ? take(next()) : -1;

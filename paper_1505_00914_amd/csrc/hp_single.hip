@@ -245,9 +245,11 @@ __global__ __launch_bounds__(kBoxBlock) void k_bbox_fold_f32(const float4 *__res
   }
 }
 
+// Scaled coordinates must lie in [1, 2^31 - 2], the integer range of a point.
+constexpr double kScaledMax = 2147483646.0;
 __device__ __forceinline__ int32_t scale_one(float v, double o, double s, bool &bad) {
   const double t = floor(__dmul_rn(__dsub_rn((double)v, o), s));
-  if (!(t >= 0.0 && t <= (double)(HP_P_MAX - 1))) {  // also catches NaN
+  if (!(t >= 0.0 && t <= kScaledMax - 1.0)) {  // also catches NaN
     bad = true;
     return 0;
   }
@@ -2212,7 +2214,7 @@ extern "C" int hp_run(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int
 
 extern "C" int hp_hull_workspace_bytes(int32_t chain_cap, size_t *bytes) {
   if (!bytes) return set_error(HP_EINVAL, "bytes is NULL");
-  if (chain_cap < 0) return set_error(HP_EINVAL, "chain_cap < 0");
+  if (chain_cap < 0 || chain_cap > HP_P_MAX) return set_error(HP_EINVAL, "chain_cap outside [0, %d]", HP_P_MAX);
   const TreeShape T = make_tree(chain_cap);
   *bytes = make_layout(chain_cap, 0, 0, T).total;
   return HP_OK;
@@ -2221,7 +2223,7 @@ extern "C" int hp_hull_workspace_bytes(int32_t chain_cap, size_t *bytes) {
 extern "C" int hp_hull(const int32_t *cx, const int32_t *clo, const int32_t *chi, int32_t chain_cap,
                        int32_t *hx, int32_t *hy, int32_t hull_cap, int32_t *info, void *ws,
                        size_t ws_bytes, void *stream) {
-  if (chain_cap < 0) return set_error(HP_EINVAL, "chain_cap < 0");
+  if (chain_cap < 0 || chain_cap > HP_P_MAX) return set_error(HP_EINVAL, "chain_cap outside [0, %d]", HP_P_MAX);
   if (chain_cap > 0 && (!cx || !clo || !chi)) return set_error(HP_EINVAL, "chain arrays must not be NULL");
   if (!hx || !hy || !info || !ws) return set_error(HP_EINVAL, "NULL output, info or workspace");
   if ((int64_t)hull_cap < 2 * (int64_t)chain_cap)
@@ -2253,7 +2255,12 @@ extern "C" int hp_hull(const int32_t *cx, const int32_t *clo, const int32_t *chi
   A.hull_cap = hull_cap;
   A.ctl = ctl;
   A.info = info;
-  hipLaunchKernelGGL((k_finish<1, false>), dim3(T.size[1]), dim3(kFinBlock), 0, s, A);
+  // many slabs: 256-thread slab workgroups, so the grid stays below 2^32
+  // work-items up to chain_cap = HP_P_MAX
+  if (T.size[1] > kScanRootMaxSlabs)
+    hipLaunchKernelGGL((k_finish<1, false, kFinBlockMany>), dim3(T.size[1]), dim3(kFinBlockMany), 0, s, A);
+  else
+    hipLaunchKernelGGL((k_finish<1, false>), dim3(T.size[1]), dim3(kFinBlock), 0, s, A);
   e = hipGetLastError();
   if (e != hipSuccess) return set_error(HP_EDEVICE, "k_finish launch: %s", hipGetErrorString(e));
   HullArgs H;

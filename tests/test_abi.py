@@ -235,3 +235,25 @@ def test_transpose_points_arguments():
     assert lib.hp_rescan_y_workspace_bytes(-1, 8, ctypes.byref(ctypes.c_size_t())) == _lib.HP_EINVAL
     assert lib.hp_rescan_y(None, None, None, 3, 8, None, None, None, None, None, None, 6, None, None, 0,
                            None) == _lib.HP_EINVAL
+
+
+def test_largest_p_fits_one_dispatch_and_is_enforced():
+    """HP_P_MAX is the largest p whose compaction launch (one 256-thread
+    workgroup per 64-column slab) stays below 2^32 work-items per dispatch,
+    and p + 1 and s <= 2p stay inside int32; the next p up is rejected
+    synchronously by every entry point that takes p."""
+    P = _lib.HP_P_MAX
+    slab_items = lambda p: -(-p // 64) * 256
+    assert slab_items(P) < 1 << 32 <= slab_items(P + 64)
+    assert 2 * P < 1 << 31 and P + 1 < 1 << 31
+    lib = _lib.load()
+    v = ctypes.c_size_t()
+    assert lib.hp_workspace_bytes(1000, P, ctypes.byref(v)) == 0 and v.value > 8 * P
+    assert lib.hp_workspace_bytes(1000, P + 1, ctypes.byref(v)) == _lib.HP_EINVAL
+    d = ctypes.c_void_p(1 << 20)
+    assert lib.hp_run(d, 50, P + 1, None, None, None, d, d, d, 50, d, d, 100, d, d, 1 << 30, None) == _lib.HP_EINVAL
+    assert lib.hp_precondition(d, 50, P + 1, None, None, None, d, d, d, 50, d, d, 1 << 30, None) == _lib.HP_EINVAL
+    w = ctypes.c_int64()
+    assert lib.hp_bitset_words(P, 1, ctypes.byref(w)) == 0
+    assert lib.hp_bitset_words(P + 1, 0, ctypes.byref(w)) == _lib.HP_EINVAL
+    assert lib.hp_rescan_y_workspace_bytes(4, P + 1, ctypes.byref(v)) == _lib.HP_EINVAL

@@ -134,3 +134,45 @@ def test_batched_large_hulls(hp):
     plan.run(torch.from_numpy(pts).cuda(), buf)
     _check(plan.collect(buf), pts, offsets, ps, "parabolas")
     plan.close()
+
+
+def _oracle_cloud(args):
+    seg, p = args
+    want = oracle.precondition_and_hull(seg, p)
+    return want, int(oracle.reduced(want["x"], want["clo"], want["chi"]).shape[0])
+
+
+def test_full_batch_4096_clouds_against_the_oracle(hp):
+    """The benchmark's batch at full size, generated exactly as the benchmark
+    generates it (4096 clouds, n log-uniform in [1e3, 1e6], p log-uniform in
+    [256, 16384], uniform or ellipsoid points, spec seed 5, on the device):
+    every cloud's k, s, chain and hull against the oracle on that cloud
+    alone, in the recorded launch sequence the benchmark times."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    spec = synth.batch_spec(4096, seed=5)
+    print(f"[case] full batch of {len(spec)} clouds", flush=True)
+    pts, offsets, ps = synth.batch(spec, device="cuda:0", ellipsoid_count=4)
+    plan = hp.Plan(offsets.numpy(), ps.numpy())
+    buf = plan.allocate("cuda:0")
+    plan.run(pts, buf)
+    plan.run(pts, buf)   # the replay of the recorded graph, as timed
+    got = plan.collect(buf)
+    host = pts.cpu().numpy()
+    del pts
+    offs, pv = offsets.numpy(), ps.numpy()
+    print(f"[case] full batch: {int(offs[-1])} points, oracle on every cloud", flush=True)
+    jobs = [(host[offs[b]:offs[b + 1]], int(pv[b])) for b in range(len(spec))]
+    bad = []
+    # the oracle is plain single-threaded C; ctypes releases the GIL, so
+    # clouds are checked on several host threads at once
+    with ThreadPoolExecutor(max_workers=8) as ex:
+        for b, (want, s) in enumerate(ex.map(_oracle_cloud, jobs)):
+            g = got[b]
+            ok = (g["status"] == 0 and g["k"] == want["k"] and g["s"] == s
+                  and np.array_equal(g["x"], want["x"]) and np.array_equal(g["clo"], want["clo"])
+                  and np.array_equal(g["chi"], want["chi"]) and np.array_equal(g["hull"], want["hull"]))
+            if not ok:
+                bad.append((b, spec[b]))
+    plan.close()
+    assert not bad, f"{len(bad)} clouds differ from the oracle, first: {bad[:4]}"
