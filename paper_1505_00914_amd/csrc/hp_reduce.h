@@ -71,27 +71,28 @@ __device__ __forceinline__ void stream_points(const int32_t *__restrict__ pts, i
     for (int u = 0; u < VPT; ++u)
       q[u] = shift_by(WIN ? v[t0 + u * BLOCK + threadIdx.x] : load_stream(&v[t0 + u * BLOCK + threadIdx.x]), ox, oy);
   }
-  while (have) {
+  // The loop runs while a next full chunk exists; the workgroup's last full
+  // chunk is folded after it with no loads issued, so no vector is read
+  // twice (a select of the load address would keep the loop branch-free but
+  // re-read the last chunk).
+  while (have && t0 + step + chunk <= nv) {
     const int64_t t1 = t0 + step;
-    const bool have_next = t1 + chunk <= nv;
     Batch<VPT> b;
     gather<VPT, LDS, WIN, FILT>(L, p, q, b, bad, c0, wc, filt, fshift, wq, &qn);
-    // the next chunk's loads, only when there is one (a workgroup's last
-    // full chunk issues none, so no vector is read twice)
     int4 qv[VPT];
 #pragma unroll
-    for (int u = 0; u < VPT; ++u) qv[u] = q[u];
-    if (have_next) {
-#pragma unroll
-      for (int u = 0; u < VPT; ++u)
-        qv[u] = shift_by(WIN ? v[t1 + u * BLOCK + threadIdx.x] : load_stream(&v[t1 + u * BLOCK + threadIdx.x]), ox,
-                         oy);
-    }
+    for (int u = 0; u < VPT; ++u)
+      qv[u] = shift_by(WIN ? v[t1 + u * BLOCK + threadIdx.x] : load_stream(&v[t1 + u * BLOCK + threadIdx.x]), ox, oy);
     apply<VPT, LDS, FILT>(L, b, wq, &qn);
 #pragma unroll
     for (int u = 0; u < VPT; ++u) q[u] = qv[u];
     t0 = t1;
-    have = have_next;
+  }
+  if (have) {
+    Batch<VPT> b;
+    gather<VPT, LDS, WIN, FILT>(L, p, q, b, bad, c0, wc, filt, fshift, wq, &qn);
+    apply<VPT, LDS, FILT>(L, b, wq, &qn);
+    t0 += step;
   }
   // at most one partial chunk remains for this workgroup
   if (t0 < nv) {
@@ -224,23 +225,27 @@ __device__ __forceinline__ void stream_points_dyn(const int32_t *__restrict__ pt
 #pragma unroll
     for (int u = 0; u < VPT; ++u) q[u] = shift_by(load_stream(&v[cur * chunk + u * BLOCK + threadIdx.x]), ox, oy);
   }
-  while (cur >= 0) {
+  // as in stream_points, the last chunk is folded after the loop with no
+  // loads issued
+  while (cur >= 0 && nx >= 0) {
     Batch<VPT> b;
     gather<VPT, LDS, false, FILT>(L, p, q, b, bad, 0, 0, filt, fshift, wq, &qn);
     int4 qv[VPT];
 #pragma unroll
-    for (int u = 0; u < VPT; ++u) qv[u] = q[u];
-    if (nx >= 0) {
-#pragma unroll
-      for (int u = 0; u < VPT; ++u) qv[u] = shift_by(load_stream(&v[nx * chunk + u * BLOCK + threadIdx.x]), ox, oy);
-    }
+    for (int u = 0; u < VPT; ++u) qv[u] = shift_by(load_stream(&v[nx * chunk + u * BLOCK + threadIdx.x]), ox, oy);
     apply<VPT, LDS, FILT>(L, b, wq, &qn);
     ++folded;
-    const int64_t nn = nx >= 0 ? take(next()) : -1;
+    const int64_t nn = take(next());
 #pragma unroll
     for (int u = 0; u < VPT; ++u) q[u] = qv[u];
     cur = nx;
     nx = nn;
+  }
+  if (cur >= 0) {
+    Batch<VPT> b;
+    gather<VPT, LDS, false, FILT>(L, p, q, b, bad, 0, 0, filt, fshift, wq, &qn);
+    apply<VPT, LDS, FILT>(L, b, wq, &qn);
+    ++folded;
   }
   if (part >= 0) {
 #pragma unroll
