@@ -311,6 +311,23 @@ int hp_run(const int32_t *pts, int64_t n, int32_t p,
            int32_t *hx, int32_t *hy, int32_t hull_cap,
            int32_t *info, void *ws, size_t ws_bytes, void *stream);
 
+/* hp_run for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same outputs as hp_run, with the workspace taken from a scratch array of
+ * HP_NOALLOC_SCRATCH_BYTES that the library itself holds on each device (no
+ * hipMalloc, hipFree or other allocating call is made).  A call whose
+ * hp_workspace_bytes(n, p) exceeds it returns HP_ECAPACITY before anything
+ * is enqueued (on gfx950 every p up to about 3 million fits).  Every call
+ * on one device shares that device's array and needs none of its previous
+ * contents: calls that may overlap on one device (different streams or host
+ * threads) race, so issue them on one stream. */
+#define HP_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+int hp_run_noalloc(const int32_t *pts, int64_t n, int32_t p,
+                   int32_t *lo, int32_t *hi, uint64_t *mask,
+                   int32_t *cx, int32_t *clo, int32_t *chi, int32_t chain_cap,
+                   int32_t *hx, int32_t *hy, int32_t hull_cap,
+                   int32_t *info, void *stream);
+
 /* ------------------------------------------------------------------------
  * Batches of ragged clouds (one persistent launch, replayed from a HIP graph)
  * ---------------------------------------------------------------------- */

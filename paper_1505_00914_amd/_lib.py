@@ -17,6 +17,7 @@ HP_P_MAX = (1 << 30) - 64
 HP_INFO_STATUS, HP_INFO_K, HP_INFO_S, HP_INFO_H, HP_INFO_WORDS = 0, 1, 2, 3, 4
 HP_STRATEGY_AUTO, HP_STRATEGY_LDS, HP_STRATEGY_GLOBAL, HP_STRATEGY_LDS_PARTIAL, HP_STRATEGY_WINDOW = 0, 1, 2, 3, 4
 HP_STRATEGY_SAMPLED = 5
+HP_NOALLOC_SCRATCH_BYTES = 128 << 20
 
 # every entry point the header declares, with (restype, argtypes)
 _vp = ctypes.c_void_p
@@ -66,6 +67,8 @@ SIGNATURES = {
     "hp_hull": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp, _i32, _vp, _vp, _sz, _vp]),
     "hp_run": (ctypes.c_int, [_vp, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp,
                               _i32, _vp, _vp, _sz, _vp]),
+    "hp_run_noalloc": (ctypes.c_int, [_vp, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp,
+                                      _i32, _vp, _vp]),
     "hp_plan_create": (ctypes.c_int, [_i64p, _i32p, _i32, ctypes.POINTER(_vp)]),
     "hp_plan_query": (ctypes.c_int, [_vp, _i64p, _i64p, _szp, _i64p, _i64p]),
     "hp_batched_run": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),

@@ -2212,6 +2212,48 @@ extern "C" int hp_run(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int
                     ws_bytes, (hipStream_t)stream, true);
 }
 
+namespace hp {
+
+// Scratch memory of hp_run_noalloc: the hp_run workspace, held by the module
+// itself for callers that cannot allocate (one copy per device the library
+// runs on, kept until the process ends).  Host code never passes the name of
+// the array to a kernel: that is only a host-side stand-in; the device address
+// comes from hipGetSymbolAddress.
+constexpr size_t kNoallocScratchBytes = HP_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+// This device's copy of `scratch`, looked up once per device with that device
+// current (the first hp_run_noalloc call on it); null if the lookup fails.
+static void *scratch_ptr() {
+  static std::mutex mu;
+  static void *base[64] = {};
+  const int d = device_info().device;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!base[d]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+    base[d] = ptr;
+  }
+  return base[d];
+}
+
+}  // namespace hp
+
+extern "C" int hp_run_noalloc(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *hi, uint64_t *mask,
+                              int32_t *cx, int32_t *clo, int32_t *chi, int32_t chain_cap, int32_t *hx, int32_t *hy,
+                              int32_t hull_cap, int32_t *info, void *stream) {
+  if (p < 1 || p > HP_P_MAX) return set_error(HP_EINVAL, "p = %d outside [1, %d]", p, HP_P_MAX);
+  if (n < 0) return set_error(HP_EINVAL, "n = %lld < 0", (long long)n);
+  const size_t need = ws_bytes_for(n, p);
+  if (need > kNoallocScratchBytes)
+    return set_error(HP_ECAPACITY, "hp_run_noalloc: n = %lld, p = %d needs %zu bytes of scratch, the library holds %zu",
+                     (long long)n, p, need, kNoallocScratchBytes);
+  void *ws = scratch_ptr();
+  if (!ws) return set_error(HP_EDEVICE, "hp_run_noalloc: no device address for the scratch array");
+  return hp_run(pts, n, p, lo, hi, mask, cx, clo, chi, chain_cap, hx, hy, hull_cap, info, ws, kNoallocScratchBytes,
+                stream);
+}
+
 extern "C" int hp_hull_workspace_bytes(int32_t chain_cap, size_t *bytes) {
   if (!bytes) return set_error(HP_EINVAL, "bytes is NULL");
   if (chain_cap < 0 || chain_cap > HP_P_MAX) return set_error(HP_EINVAL, "chain_cap outside [0, %d]", HP_P_MAX);

@@ -211,6 +211,16 @@ def hp_run(points: torch.Tensor, p: int, buf: Buffers, stream=None) -> None:
               _stream(stream))
 
 
+def hp_run_noalloc(points: torch.Tensor, p: int, buf: Buffers, stream=None) -> None:
+    """Enqueue the fused path with the library's own scratch memory instead
+    of ``buf.ws`` (no device allocation in the call; calls that may overlap
+    on one device race)."""
+    n = _check_points(points)
+    _lib.call("hp_run_noalloc", _ptr(points), n, p, _ptr(buf.lo), _ptr(buf.hi), _ptr(buf.mask),
+              _ptr(buf.cx), _ptr(buf.clo), _ptr(buf.chi), buf.cx.numel(), _ptr(buf.hx),
+              _ptr(buf.hy), buf.hx.numel(), _ptr(buf.info), _stream(stream))
+
+
 def hp_run_origin(points: torch.Tensor, p: int, origin: tuple[int, int], buf: Buffers, stream=None) -> None:
     """Enqueue the fused path on the points translated by ``origin`` (no sync)."""
     n = _check_points(points)
