@@ -101,6 +101,16 @@ extern "C" {
                                        the rest skip every point that cannot
                                        change L, the filter being rebuilt once
                                        half-way (for large p, n >= 16 p)         */
+#define HP_STRATEGY_BINNED       6  /* p <= 2^20: the points are binned by window
+                                       of 4096 columns (32-bit entries written in
+                                       128-byte blocks), then every window is
+                                       folded in LDS into a partial array; from
+                                       n >= 32 p the first quarter of the points
+                                       builds a per-64-column filter that drops
+                                       every later point that cannot change L.
+                                       Needs the full hp_workspace_bytes(n, p)
+                                       (about 4n bytes more); with less, the
+                                       sampled or device-L strategy runs     */
 
 /* Steps 1 and 2 of the proposed heuristic (the bounding box, then the
  * translation that puts the points in [1, p]^2), on the device.
@@ -205,7 +215,7 @@ int32_t hp_lds_max_p(void);
 
 /* Force a strategy for later calls on this process (HP_STRATEGY_*), e.g. for
  * tests; HP_STRATEGY_AUTO restores the tuned choice.  Also settable with the
- * environment variable HP_FORCE_STRATEGY=lds|global|lds_partial|window|sampled.
+ * environment variable HP_FORCE_STRATEGY=lds|global|lds_partial|window|sampled|binned.
  * Other environment variables, read once per process: HP_TUNING_FILE (a
  * tuning table to load instead of the one beside the library), HP_DYN_OFF=1
  * (no chunk sharing in the reduce), HP_DYN_STATIC8 (static share of a
@@ -222,7 +232,7 @@ int hp_tune_set(int32_t strategy, int32_t block, int32_t vpt, int32_t grid);
 
 /* Load a tuning table written by the tuner: one line per regime
  * "log2n log2p strategy block vpt grid"; '#' starts a comment line.  A line
- * with a field the launch code cannot honour (strategy outside 1..5, block
+ * with a field the launch code cannot honour (strategy outside 1..6, block
  * not 256/512/1024, vpt not 2/4/8, grid outside 0..2^20) fails the load
  * with HP_EINVAL naming the line, and the table in use stays as it was. */
 int hp_tune_load(const char *path);

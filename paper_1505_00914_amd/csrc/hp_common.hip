@@ -59,6 +59,7 @@ int forced_strategy() {
       else if (!strcmp(e, "lds_partial")) g_forced = HP_STRATEGY_LDS_PARTIAL;
       else if (!strcmp(e, "window")) g_forced = HP_STRATEGY_WINDOW;
       else if (!strcmp(e, "sampled")) g_forced = HP_STRATEGY_SAMPLED;
+      else if (!strcmp(e, "binned")) g_forced = HP_STRATEGY_BINNED;
     }
   }
   return g_forced;
@@ -164,7 +165,7 @@ int tune_load(const char *path) {
     // a line the launch code cannot honour fails the whole load, and the
     // table in use stays as it was
     const bool ok = t.ln >= 0 && t.ln < 64 && t.lp >= 0 && t.lp < 32 && t.strategy >= HP_STRATEGY_LDS &&
-                    t.strategy <= HP_STRATEGY_SAMPLED && (t.block == 256 || t.block == 512 || t.block == 1024) &&
+                    t.strategy <= HP_STRATEGY_BINNED && (t.block == 256 || t.block == 512 || t.block == 1024) &&
                     (t.vpt == 2 || t.vpt == 4 || t.vpt == 8) && t.G >= 0 && t.G <= (1 << 20);
     if (!ok) {
       fclose(f);
@@ -262,7 +263,7 @@ extern "C" int hp_abi_version(void) { return HP_ABI_VERSION; }
 extern "C" int32_t hp_lds_max_p(void) { return (int32_t)device_info().lds_max_p; }
 
 extern "C" int hp_set_strategy(int strategy) {
-  if (strategy < HP_STRATEGY_AUTO || strategy > HP_STRATEGY_SAMPLED)
+  if (strategy < HP_STRATEGY_AUTO || strategy > HP_STRATEGY_BINNED)
     return set_error(HP_EINVAL, "unknown strategy %d", strategy);
   forced_strategy();
   std::lock_guard<std::mutex> lk(g_mu);
@@ -271,7 +272,7 @@ extern "C" int hp_set_strategy(int strategy) {
 }
 
 extern "C" int hp_tune_set(int32_t strategy, int32_t block, int32_t vpt, int32_t grid) {
-  if (strategy < 0 || strategy > HP_STRATEGY_SAMPLED)
+  if (strategy < 0 || strategy > HP_STRATEGY_BINNED)
     return set_error(HP_EINVAL, "unknown strategy %d", strategy);
   const bool ok_shape = (block == 0 && vpt == 0) ||
                         ((block == 256 || block == 512 || block == 1024) && (vpt == 2 || vpt == 4 || vpt == 8));

@@ -10,6 +10,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "hullprep.h"
+
 namespace hp {
 
 constexpr int kWave = 64;        // CDNA wavefront width
@@ -28,6 +30,15 @@ constexpr int kCtlWords = 64;
 
 constexpr int kErrRange = 1;     // a point outside [1, p]
 constexpr int kErrCapacity = 2;  // an output capacity was exceeded
+constexpr int kErrBinOverflow = 4;  // the binned reduce ran out of pages (a sizing bug, never expected)
+
+// Status of the per-workgroup error bits of a reduce: a range error is a data
+// error; a binning overflow means the L is incomplete (reported as a device
+// error rather than as a silently wrong result).
+__device__ __forceinline__ void report_reduce_errors(int err, int32_t *info) {
+  if (err & kErrRange) atomicMin(&info[HP_INFO_STATUS], HP_ERANGE);
+  if (err & kErrBinOverflow) atomicMin(&info[HP_INFO_STATUS], HP_EDEVICE);
+}
 
 // Shape of the last-arriver hull tree over `positions` slots: level 1 has one
 // node per slab of kSlab positions, level l+1 one node per kFanIn nodes of

@@ -11,6 +11,7 @@
 #include "hp_args.h"
 #include "hp_output.h"
 #include "hp_reduce.h"
+#include "hp_binned.h"
 
 namespace hp {
 
@@ -442,7 +443,7 @@ __device__ void scan_slabs(const FinishArgs &A, FinishSharedT<FB> &S) {
     for (int w = 0; w < FB / kWave; ++w) s += S.tmp[w];
     A.info[HP_INFO_K] = k;
     A.info[HP_INFO_S] = s;
-    if (S.flag & kErrRange) atomicMin(&A.info[HP_INFO_STATUS], HP_ERANGE);
+    report_reduce_errors(S.flag, A.info);
   }
   if (A.chain_inline) {
     // every wave writes the chain of up to 4 slabs per round, all loads first
@@ -1200,7 +1201,7 @@ __device__ __forceinline__ void l2_totals(const HullArgs &H, L2Shared &S) {
   if (tid == 0) {
     H.info[HP_INFO_K] = S.sum[0];
     H.info[HP_INFO_S] = S.sum[1];
-    if (S.sum[2] & kErrRange) atomicMin(&H.info[HP_INFO_STATUS], HP_ERANGE);
+    report_reduce_errors(S.sum[2], H.info);
   }
 }
 
@@ -1481,7 +1482,7 @@ __global__ __launch_bounds__(kHullBlock) void k_l2_root(HullArgs H) {
     if (lane == 0) {
       H.info[HP_INFO_K] = tk;
       H.info[HP_INFO_S] = ts;
-      if (te & kErrRange) atomicMin(&H.info[HP_INFO_STATUS], HP_ERANGE);
+      report_reduce_errors(te, H.info);
     }
   }
   if (!last_arrival_flag(&H.ctl[kCtlTestDone], parts, &s_flag)) return;
@@ -1611,7 +1612,8 @@ static int dyn_static8() {
 }
 
 struct Layout {
-  size_t ctl, tree, wg_err, wg_cnt, filt, slab_k, slab_s, slab_off, Lm, part, cand, keep, l2cnt, ccount, total;
+  size_t ctl, tree, wg_err, wg_cnt, filt, slab_k, slab_s, slab_off, Lm, part, cand, keep, l2cnt, ccount, bins,
+      total;
 };
 
 static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -1630,7 +1632,8 @@ static size_t keep_side_bytes(int64_t positions) {
   return (size_t)((P + kNodeVerts - 1) / kNodeVerts) * kNodeVerts;
 }
 
-static Layout make_layout(int64_t positions, int32_t p, int64_t part_pairs, const TreeShape &T) {
+static Layout make_layout(int64_t positions, int32_t p, int64_t part_pairs, const TreeShape &T,
+                          size_t bins_bytes = 0) {
   Layout Y;
   size_t o = 0;
   Y.ctl = o;      o = align_up(o + sizeof(int32_t) * kCtlWords);
@@ -1647,6 +1650,7 @@ static Layout make_layout(int64_t positions, int32_t p, int64_t part_pairs, cons
   Y.keep = o;     o = align_up(o + 2 * keep_side_bytes(positions));
   Y.l2cnt = o;    o = align_up(o + sizeof(int32_t) * 2 * kL2MaxParts * (size_t)(T.nlev >= 2 ? T.size[2] : 1));
   Y.ccount = o;   o = align_up(o + sizeof(int32_t) * 2 * (size_t)T.nodes);
+  Y.bins = o;     o = align_up(o + bins_bytes);
   Y.total = o;
   return Y;
 }
@@ -1658,6 +1662,59 @@ struct Plan1 {
   int block, vpt, G;   // G: workgroups of the reduce
   int W, wc;           // column windows (HP_STRATEGY_WINDOW): count and columns each
 };
+
+// Shape of the binned reduce for (n, p), p <= kBinPMax: G binning workgroups
+// (one per CU), S fold slices per window, one round, or two from n >= 32 p
+// (the first over the first quarter of the points, an even count so that
+// the second round's points keep the alignment of pts), and the pages each
+// binning workgroup may need: its points of the larger round over the page
+// size, plus one partly filled page per window.
+struct BinPlan {
+  int G, S, nw, pages, rounds;
+  int64_t split;   // points of the first round
+};
+
+constexpr int64_t kBinRoundsMinPerCol = 32;
+
+// Points per binning workgroup and round at most, so that a stream's page
+// index fits the 16 bits the page records give it.
+constexpr int64_t kBinMaxPerWg = (int64_t)1 << 25;
+
+static BinPlan bin_plan(int64_t n, int32_t p) {
+  BinPlan B;
+  B.nw = (int)(((int64_t)p + kBinWc - 1) / kBinWc);
+  B.rounds = n >= kBinRoundsMinPerCol * (int64_t)p ? 2 : 1;
+  B.split = B.rounds == 2 ? (n / 4) & ~(int64_t)1 : n;
+  const int64_t m = std::max<int64_t>(B.split, n - B.split);
+  const int64_t nv = m / 2 + 1;
+  const int64_t ntiles = (nv + kBinTileV - 1) / kBinTileV;
+  B.G = (int)std::max<int64_t>(device_info().cus, (m + kBinMaxPerWg - 1) / kBinMaxPerWg);
+  B.S = (int)std::max<int64_t>(1, std::min<int64_t>(B.G, 2048 / B.nw));
+  const int64_t tpw = (ntiles + B.G - 1) / B.G;
+  const int64_t per_wg = tpw * 2 * (int64_t)kBinTileV + 2;
+  B.pages = (int)((per_wg + kBinPage - 1) / kBinPage + B.nw + 1);
+  return B;
+}
+
+// Partial arrays of the binned reduce: S per round, plus the running L when
+// there are two rounds.
+static int bin_partials(const BinPlan &B) { return B.S + (B.rounds > 1 ? 1 : 0); }
+
+// Device bytes of the binned reduce's pages and tables.
+struct BinLayout {
+  size_t pool, E, pg_off, pg_list, pwin, total;
+};
+static BinLayout bin_layout(const BinPlan &B) {
+  BinLayout Z;
+  size_t o = 0;
+  Z.pool = o;    o = align_up(o + sizeof(uint32_t) * (size_t)B.G * (size_t)B.pages * kBinPage);
+  Z.E = o;       o = align_up(o + sizeof(int32_t) * (size_t)B.G * (size_t)B.nw);
+  Z.pg_off = o;  o = align_up(o + sizeof(int32_t) * (size_t)B.G * (size_t)(B.nw + 1));
+  Z.pg_list = o; o = align_up(o + sizeof(int32_t) * (size_t)B.G * (size_t)B.pages);
+  Z.pwin = o;    o = align_up(o + sizeof(int32_t) * (size_t)B.G * (size_t)B.pages);
+  Z.total = o;
+  return Z;
+}
 
 // Sampled filter: used by default from this many points per column; the
 // sample is the first 1/sample_div() of the points (HP_SAMPLE_DIV, 2..64).
@@ -1693,19 +1750,24 @@ constexpr int kWinMax = 8;
 constexpr int kWinMaxGroups = 64;
 
 // Partial arrays the reduce writes (each p packed words), or 0.
-static int partial_count(const Plan1 &P) {
+static int partial_count(const Plan1 &P, int64_t n, int32_t p) {
   if (P.strategy == HP_STRATEGY_LDS_PARTIAL) return P.G;
   if (P.strategy == HP_STRATEGY_WINDOW) return P.G / P.W;
+  if (P.strategy == HP_STRATEGY_BINNED) return bin_partials(bin_plan(n, p));
   return 0;
 }
 
 static bool is_lds(int s) { return s == HP_STRATEGY_LDS || s == HP_STRATEGY_LDS_PARTIAL; }
 
-static Plan1 choose(int64_t n, int32_t p) {
+// allow_binned: the workspace holds the binned reduce's pages (else a plan
+// that would bin uses the sampled filter or the device L instead).
+static Plan1 choose(int64_t n, int32_t p, bool allow_binned = true) {
   const DeviceInfo &D = device_info();
   Plan1 P;
   int s = forced_strategy();
   if (s == HP_STRATEGY_AUTO) s = tuned_strategy(n, p);
+  if (s == HP_STRATEGY_BINNED && ((int64_t)p > kBinPMax || !allow_binned)) s = HP_STRATEGY_SAMPLED;
+  if (s == HP_STRATEGY_SAMPLED && n < kSampledMinPerCol * (int64_t)p) s = HP_STRATEGY_GLOBAL;
   P.W = 1;
   P.wc = p;
   if ((is_lds(s) && (int64_t)p > D.lds_max_p) || s == HP_STRATEGY_WINDOW) {
@@ -1735,6 +1797,8 @@ static Plan1 choose(int64_t n, int32_t p) {
     P.G = (int)G;
   } else if (s == HP_STRATEGY_WINDOW) {
     P.G = D.cus;   // chunk groups x windows, fixed below
+  } else if (s == HP_STRATEGY_BINNED) {
+    P.G = bin_plan(n, p).G;
   } else {
     const int64_t vecs = (n + 1) / 2;
     int64_t G = (vecs + (int64_t)P.block * P.vpt - 1) / ((int64_t)P.block * P.vpt);
@@ -1743,6 +1807,7 @@ static Plan1 choose(int64_t n, int32_t p) {
     if (G < 1) G = 1;
     P.G = (int)G;
   }
+  if (s == HP_STRATEGY_BINNED) return P;   // fixed launch shapes
   tune_override(n, p, &P.block, &P.vpt, &P.G);
   if (s == HP_STRATEGY_WINDOW) {
     int groups = (P.G / P.W) / 8 * 8;
@@ -1757,19 +1822,25 @@ static Plan1 choose(int64_t n, int32_t p) {
 
 // Pairs of the reduce output region: G partial L arrays for the partial
 // variant, otherwise nothing (the device L is the merged-L region).
-static int64_t part_pairs_for(const Plan1 &P, int32_t p) {
-  // packed partial words take half a pair slot each
-  const int64_t entries = (int64_t)partial_count(P) * p;
+static int64_t part_pairs_for(const Plan1 &P, int64_t n, int32_t p) {
+  // the binned reduce writes pairs; the other partials pack into half a pair
+  const int64_t entries = (int64_t)partial_count(P, n, p) * p;
+  if (P.strategy == HP_STRATEGY_BINNED) return entries;
   return partial_packs(p) ? (entries + 1) / 2 : entries;
+}
+
+static size_t bins_bytes_for(const Plan1 &P, int64_t n, int32_t p) {
+  return P.strategy == HP_STRATEGY_BINNED ? bin_layout(bin_plan(n, p)).total : 0;
 }
 
 // Largest grid the LDS strategies may use (also bounds tuned overrides).
 static int64_t lds_grid_max() { return (int64_t)device_info().cus * 4; }
 
-static size_t ws_bytes_for(int64_t n, int32_t p) {
-  // sized for the largest partial-L array any strategy or override may use,
-  // so that a later strategy change still fits the same workspace
-  (void)n;
+// Workspace for (n, p): sized for the largest partial-L array any strategy or
+// override may use, so that a later strategy change still fits the same
+// workspace; with_bins adds the binned reduce's pages (for p <= kBinPMax),
+// without them a plan that would bin falls back (see choose).
+static size_t ws_bytes_for(int64_t n, int32_t p, bool with_bins = true) {
   const TreeShape T = make_tree(p);
   const int64_t lds_max = device_info().lds_max_p;
   int64_t part = 0;
@@ -1778,7 +1849,13 @@ static size_t ws_bytes_for(int64_t n, int32_t p) {
     const int64_t entries = (int64_t)kWinMaxGroups * p;
     part = std::max<int64_t>(part, partial_packs(p) ? (entries + 1) / 2 : entries);
   }
-  return make_layout(p, p, part, T).total;
+  size_t bins = 0;
+  if (with_bins && (int64_t)p <= kBinPMax) {
+    const BinPlan B = bin_plan(n, p);
+    part = std::max<int64_t>(part, (int64_t)bin_partials(B) * p);
+    bins = bin_layout(B).total;
+  }
+  return make_layout(p, p, part, T, bins).total;
 }
 
 template <typename K, typename... Args>
@@ -1922,6 +1999,64 @@ static hipError_t dispatch_sampled(const Plan1 &P, const int32_t *pts, int64_t n
   return hipErrorInvalidValue;
 }
 
+// The binned reduce (p <= kBinPMax): per round k_bin over the round's points,
+// k_bin_fold into S partial arrays, and between rounds k_bin_merge into the
+// running L (array S) and the filter of the next round.  e0 is recorded at
+// the start of the first k_bin and e1 at the end of the last k_bin_fold.
+static hipError_t launch_binned(const int32_t *pts, int64_t n, int32_t p, int2 *part, uint16_t *F, char *bins,
+                                int32_t *wg_err, ResetArgs R, int2 org, hipStream_t s, hipEvent_t e0,
+                                hipEvent_t e1) {
+  const BinPlan B = bin_plan(n, p);
+  const BinLayout Z = bin_layout(B);
+  BinArgs A;
+  A.pool = reinterpret_cast<uint32_t *>(bins + Z.pool);
+  A.E = reinterpret_cast<int32_t *>(bins + Z.E);
+  A.pg_off = reinterpret_cast<int32_t *>(bins + Z.pg_off);
+  A.pg_list = reinterpret_cast<int32_t *>(bins + Z.pg_list);
+  A.pwin = reinterpret_cast<int32_t *>(bins + Z.pwin);
+  A.pages = B.pages;
+  A.nw = B.nw;
+  A.G = B.G;
+  const int nf = (int)(((int64_t)p + (1 << kBinFilterShift) - 1) >> kBinFilterShift);
+  // filter bounds in 8 bits: y - 1 < p in steps of 2^qs
+  int qs = 0;
+  while ((((int64_t)p - 1) >> qs) > 255) ++qs;
+  if (B.nw > kBinNwMax || bin_lds_bytes(nf) > (size_t)device_info().lds_bytes || B.rounds * B.G > kMaxGrid)
+    return hipErrorInvalidValue;
+  static bool attr_set = false;
+  if (!attr_set) {
+    const hipError_t e = hipFuncSetAttribute((const void *)k_bin, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             device_info().lds_bytes);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  for (int r = 0; r < B.rounds; ++r) {
+    const int64_t a = r == 0 ? 0 : B.split, b = r == 0 ? B.split : n;
+    ResetArgs Rr = R;
+    if (r > 0) Rr.ctl = nullptr;
+    const uint16_t *Fr = r > 0 ? F : nullptr;
+    const uint32_t lds = (uint32_t)bin_lds_bytes(r > 0 ? nf : 0);
+    const int32_t *pr = pts ? pts + 2 * a : pts;
+    int32_t *err = wg_err + (size_t)r * B.G;
+    if (r == 0 && e0)
+      hipExtLaunchKernelGGL(k_bin, dim3(B.G), dim3(kBinThreads), lds, s, e0, nullptr, 0, pr, b - a, p, Fr, nf, qs, A,
+                            err, org, Rr);
+    else
+      hipLaunchKernelGGL(k_bin, dim3(B.G), dim3(kBinThreads), lds, s, pr, b - a, p, Fr, nf, qs, A, err, org, Rr);
+    const dim3 gf((unsigned)(B.nw * B.S));
+    if (r + 1 == B.rounds && e1)
+      hipExtLaunchKernelGGL(k_bin_fold, gf, dim3(kBinFoldThreads), 0, s, nullptr, e1, 0, A, p, B.S, part);
+    else
+      hipLaunchKernelGGL(k_bin_fold, gf, dim3(kBinFoldThreads), 0, s, A, p, B.S, part);
+    if (r + 1 < B.rounds)
+      hipLaunchKernelGGL(k_bin_merge, dim3((unsigned)(((int64_t)p + 255) / 256)), dim3(256), 0, s, part, B.S,
+                         r > 0 ? 1 : 0, p, qs, F);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 // Hull levels 2..nlev: a test launch and a compaction launch per level (the
 // slab level ran in k_finish).  H must have its chain fields filled.
 static void hull_buffers(HullArgs &H, const TreeShape &T, int64_t positions, char *w, const Layout &Y) {
@@ -1989,16 +2124,20 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
                int32_t hull_cap, int32_t *info, void *ws, size_t ws_bytes, hipStream_t s,
                bool do_hull, int32_t ox, int32_t oy) {
   const int2 org = make_int2(ox, oy);
-  const Plan1 P = choose(n, p);
   const TreeShape T = make_tree(p);
-  const Layout Y = make_layout(p, p, part_pairs_for(P, p), T);
+  Plan1 P = choose(n, p);
+  if (P.strategy == HP_STRATEGY_BINNED &&
+      ws_bytes < make_layout(p, p, part_pairs_for(P, n, p), T, bins_bytes_for(P, n, p)).total)
+    P = choose(n, p, false);   // a workspace without room for the bins
+  const bool binned = P.strategy == HP_STRATEGY_BINNED;
+  const Layout Y = make_layout(p, p, part_pairs_for(P, n, p), T, bins_bytes_for(P, n, p));
   if (ws_bytes < Y.total) return set_error(HP_ECAPACITY, "workspace too small: %zu < %zu bytes", ws_bytes, Y.total);
   char *w = static_cast<char *>(ws);
   int32_t *ctl = reinterpret_cast<int32_t *>(w + Y.ctl);
   int32_t *tree = reinterpret_cast<int32_t *>(w + Y.tree);
   int2 *part = reinterpret_cast<int2 *>(w + Y.part);
   int2 *Lm = reinterpret_cast<int2 *>(w + Y.Lm);
-  const bool partial = partial_count(P) > 0;
+  const bool partial = partial_count(P, n, p) > 0;
   int32_t *wg_err = reinterpret_cast<int32_t *>(w + Y.wg_err);
 
   // The partial strategy writes every merged column itself, so only the
@@ -2047,22 +2186,28 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
   // the pass that may share chunks: all points, or the last filtered pass
   const int32_t *main_pts = pts ? pts + 2 * n1 : pts;
   const int64_t nchunks = dyn_chunks(n - n1, (uintptr_t)main_pts, (int64_t)P.block * P.vpt);
-  if (D.static_frac8 >= 0 && P.strategy != HP_STRATEGY_WINDOW && nchunks >= kDynMinChunks * (int64_t)P.G)
+  if (D.static_frac8 >= 0 && P.strategy != HP_STRATEGY_WINDOW && !binned && nchunks >= kDynMinChunks * (int64_t)P.G)
     D.ctr = grab_counter();
   hipEvent_t e0 = nullptr, e1 = nullptr;
   timing_slot(&e0, &e1);
-  if (sampled)
+  int n_wg_err = P.G;
+  if (sampled) {
     e = dispatch_sampled(P, pts, n, p, Lm, reinterpret_cast<int2 *>(w + Y.filt), fshift, ngroups, ns, G1,
                          wg_err, D, org, s, e0, e1);
-  else
+    n_wg_err = G1 + nstages * P.G;
+  } else if (binned) {
+    e = launch_binned(pts, n, p, part, reinterpret_cast<uint16_t *>(w + Y.filt), w + Y.bins, wg_err, R, org, s, e0,
+                      e1);
+    n_wg_err = bin_plan(n, p).rounds * bin_plan(n, p).G;
+  } else
     e = dispatch_reduce(P, pts, n, p, Lm, part, wg_err, R, D, org, s, e0, e1);
   if (e != hipSuccess) return set_error(HP_EDEVICE, "reduce launch: %s", hipGetErrorString(e));
 
   FinishArgs A;
   memset(&A, 0, sizeof(A));
   A.part = partial ? part : Lm;
-  A.G = partial ? partial_count(P) : 1;
-  A.packed = partial && partial_packs(p) ? 1 : 0;
+  A.G = partial ? partial_count(P, n, p) : 1;
+  A.packed = partial && !binned && partial_packs(p) ? 1 : 0;
   A.positions = p;
   A.p = p;
   A.Lm = Lm;
@@ -2083,7 +2228,7 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
   A.ctl = ctl;
   A.info = info;
   A.wg_err = wg_err;
-  A.n_wg_err = sampled ? G1 + nstages * P.G : P.G;
+  A.n_wg_err = n_wg_err;
   A.dyn_ctr = D.ctr;
   A.wg_cnt = D.wg_cnt;
   A.n_wg_cnt = P.G;
@@ -2118,7 +2263,7 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
   H.slab_k = A.slab_k;
   H.slab_s = A.slab_s;
   H.wg_err = wg_err;
-  H.n_wg_err = sampled ? G1 + nstages * P.G : P.G;
+  H.n_wg_err = n_wg_err;
   H.cx = cx;
   H.clo = clo;
   H.chi = chi;
@@ -2158,7 +2303,9 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
 
 void tree_shape(int64_t positions, TreeShape *out) { *out = make_tree(positions); }
 
-size_t single_ws_bytes(int64_t n, int32_t p) { return ws_bytes_for(n, p); }
+// Workspace of the single-cloud sequence inside batches and served requests:
+// without the binned reduce's pages (their clouds fall back from it).
+size_t single_ws_bytes(int64_t n, int32_t p) { return ws_bytes_for(n, p, false); }
 
 static int check_common(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *hi,
                         int32_t *cx, int32_t *clo, int32_t *chi, int32_t chain_cap, int32_t *info,
@@ -2244,7 +2391,7 @@ extern "C" int hp_run_noalloc(const int32_t *pts, int64_t n, int32_t p, int32_t 
                               int32_t hull_cap, int32_t *info, void *stream) {
   if (p < 1 || p > HP_P_MAX) return set_error(HP_EINVAL, "p = %d outside [1, %d]", p, HP_P_MAX);
   if (n < 0) return set_error(HP_EINVAL, "n = %lld < 0", (long long)n);
-  const size_t need = ws_bytes_for(n, p);
+  const size_t need = ws_bytes_for(n, p, false);
   if (need > kNoallocScratchBytes)
     return set_error(HP_ECAPACITY, "hp_run_noalloc: n = %lld, p = %d needs %zu bytes of scratch, the library holds %zu",
                      (long long)n, p, need, kNoallocScratchBytes);

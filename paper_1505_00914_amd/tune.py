@@ -45,7 +45,12 @@ def _candidates(n: int, p: int, cus: int, lds_max_p: int):
         strategies = [hp.HP_STRATEGY_WINDOW, hp.HP_STRATEGY_GLOBAL, hp.HP_STRATEGY_SAMPLED]
     elif n >= 16 * p:
         strategies = [hp.HP_STRATEGY_SAMPLED, hp.HP_STRATEGY_GLOBAL]
+    if p <= 1 << 20 and p > lds_max_p and n >= 2 * p:
+        strategies = [hp.HP_STRATEGY_BINNED] + strategies
     for s in strategies:
+        if s == hp.HP_STRATEGY_BINNED:
+            yield s, 1024, 4, 0   # fixed launch shapes
+            continue
         if s in (hp.HP_STRATEGY_GLOBAL, hp.HP_STRATEGY_SAMPLED):
             grids = sorted({max(1, int(cus * f)) for f in (1, 2, 4, 8)})
         elif s == hp.HP_STRATEGY_WINDOW:

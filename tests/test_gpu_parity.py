@@ -49,7 +49,7 @@ def _compare(got, want, label, check_L=True):
     assert np.array_equal(got["hull"], want["hull"]), f"{label}: hull differs"
 
 
-def _run_both(hp, pts_cpu: torch.Tensor, p: int, label: str, strategies=(1, 2, 3, 4, 5), split=True):
+def _run_both(hp, pts_cpu: torch.Tensor, p: int, label: str, strategies=(1, 2, 3, 4, 5, 6), split=True):
     print(f"[case] {label} n={pts_cpu.shape[0]} p={p}", flush=True)
     want = _oracle(pts_cpu.numpy(), p)
     dev = pts_cpu.cuda()
@@ -90,7 +90,7 @@ def test_gap_example(hp):
 ])
 def test_configs(hp, kind, n, p, seed):
     pts = synth.cloud(kind, n, p, seed)
-    strategies = (1, 2, 3, 4, 5) if p <= hp.lds_max_p() else (2, 4, 5)
+    strategies = (1, 2, 3, 4, 5, 6) if p <= hp.lds_max_p() else (2, 4, 5, 6)
     _run_both(hp, pts, p, f"{kind}-{n}-{p}", strategies)
 
 
@@ -120,7 +120,7 @@ def _edge_cases():
 @pytest.mark.parametrize("name", sorted(_edge_cases()))
 def test_edge_cases(hp, name):
     pts, p = _edge_cases()[name]
-    strategies = (1, 2, 3, 4, 5) if p <= hp.lds_max_p() else (2, 4, 5)
+    strategies = (1, 2, 3, 4, 5, 6) if p <= hp.lds_max_p() else (2, 4, 5, 6)
     _run_both(hp, torch.from_numpy(pts), p, name, strategies)
 
 
@@ -131,7 +131,7 @@ def test_unaligned_start(hp):
     want = _oracle(view_cpu.contiguous().numpy(), 777)
     dev = base.cuda()[1:]
     assert dev.data_ptr() % 16 == 8
-    for s in (1, 2, 3, 4, 5):
+    for s in (1, 2, 3, 4, 5, 6):
         hp.set_strategy(s)
         _compare(hp.run(dev, 777), want, f"unaligned/strategy{s}")
     hp.set_strategy(0)
@@ -141,7 +141,7 @@ def test_out_of_range_reports(hp):
     pts = synth.cloud("uniform", 10_000, 100, 12)
     pts[5000] = torch.tensor([101, 3], dtype=torch.int32)
     pts[17] = torch.tensor([4, 0], dtype=torch.int32)
-    for s in (1, 2, 3, 4, 5):
+    for s in (1, 2, 3, 4, 5, 6):
         hp.set_strategy(s)
         got = hp.run(pts.cuda(), 100)
         assert got["status"] == HP_ERANGE
@@ -150,9 +150,10 @@ def test_out_of_range_reports(hp):
 
 @pytest.mark.parametrize("order", ["inside_first", "outside_first", "columns_late"])
 def test_sampled_filter_orders(hp, order):
-    """The sampled strategy against the oracle when the sample (the first
-    1/16 of the points) is unrepresentative: only interior points, only the
-    extreme points, or missing whole columns that appear later."""
+    """The sampled and the binned strategies against the oracle when the
+    sample (the first 1/8, resp. the first round's quarter, of the points) is
+    unrepresentative: only interior points, only the extreme points, or
+    missing whole columns that appear later."""
     p = 50_000
     pts = synth.cloud("disc", 1_600_000, p, 41)
     a = pts.numpy()
@@ -164,15 +165,17 @@ def test_sampled_filter_orders(hp, order):
     else:
         key = (a[:, 0] % 97 == 0).astype(np.int64)  # a comb of columns only after the sample
     a = np.ascontiguousarray(a[np.argsort(key, kind="stable")])
-    _run_both(hp, torch.from_numpy(a), p, f"sampled-{order}", strategies=(5, 2), split=False)
+    _run_both(hp, torch.from_numpy(a), p, f"sampled-{order}", strategies=(5, 6, 2), split=False)
 
 
+@pytest.mark.parametrize("strategy", [5, 6])
 @pytest.mark.parametrize("where", [100, 1_500_000])
-def test_sampled_range_error(hp, where):
-    """A point outside [1, p] in the sample prefix or in the filtered pass."""
+def test_sampled_range_error(hp, where, strategy):
+    """A point outside [1, p] in the sample prefix or in the filtered pass
+    (for the binned strategy: in its first or its second round)."""
     pts = synth.cloud("uniform", 1_600_000, 40_000, 42)
     pts[where] = torch.tensor([40_001, 5], dtype=torch.int32)
-    hp.set_strategy(5)
+    hp.set_strategy(strategy)
     got = hp.run(pts.cuda(), 40_000)
     hp.set_strategy(0)
     assert got["status"] == HP_ERANGE
@@ -241,7 +244,7 @@ def test_repeat_is_stable(hp):
 def test_column_windows(hp, kind, n, p, seed):
     """p above the LDS limit: the column-window reduce against the oracle."""
     pts = synth.cloud(kind, n, p, seed)
-    _run_both(hp, pts, p, f"window-{kind}-{n}-{p}", strategies=(4, 2, 5))
+    _run_both(hp, pts, p, f"window-{kind}-{n}-{p}", strategies=(4, 2, 5, 6))
 
 
 def test_random_sweep(hp):
@@ -267,3 +270,26 @@ def test_random_sweep(hp):
             _compare(hp.run(pts.cuda(), p), want, label)
         finally:
             hp.tune_set(0, 0, 0, 0)
+
+
+@pytest.mark.parametrize("kind,n,p,seed", [
+    ("disc", 3_000_000, 1 << 20, 51),          # 256 windows, one round
+    ("disc", 2_400_000, 65_536, 52),           # 16 windows, two rounds
+    ("gaussian", 1_000_000, 20_000, 53),       # heavy columns, two rounds, ragged last window
+    ("uniform", 8_193, 4_097, 54),             # a tile and a point, two windows
+    ("ellipsoids", 1_200_000, 300_000, 55),    # sparse columns, 74 windows
+])
+def test_binned(hp, kind, n, p, seed):
+    """The binned reduce against the oracle, through hp_run, hp_precondition
+    + hp_hull and the origin entry point (points moved far away, read back
+    through the origin)."""
+    pts = synth.cloud(kind, n, p, seed)
+    want = _run_both(hp, pts, p, f"binned-{kind}-{n}-{p}", strategies=(6,))
+    hp.set_strategy(6)
+    try:
+        moved = (pts.to(torch.int64) + torch.tensor([-2_000_000_000, 1_000_000_000])).to(torch.int32).cuda()
+        buf = hp.Buffers.allocate(n, p, moved.device)
+        hp.hp_run_origin(moved, p, (-2_000_000_000, 1_000_000_000), buf)
+        _compare(hp.collect(buf), want, f"binned-{kind}-{n}-{p}/origin")
+    finally:
+        hp.set_strategy(0)
