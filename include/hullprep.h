@@ -160,6 +160,60 @@ int hp_run_origin(const int32_t *pts, int64_t n, int32_t p, int32_t ox, int32_t 
                   int32_t chain_cap, int32_t *hx, int32_t *hy, int32_t hull_cap, int32_t *info,
                   void *ws, size_t ws_bytes, void *stream);
 
+/* Steps 1 to 3 of the proposed heuristic in one call (Algorithm 1 preceded
+ * by the bounding box, the side p and the translation into [1, p]^2; the
+ * sweep along the shorter side of the box from Results).
+ *
+ * hp_run_auto: the box of the n int32 points on the device, then, after one
+ * synchronisation of `stream` (this call blocks until the box is known),
+ * on the host: the side p = max(xmax - xmin, ymax - ymin) + 1, the origin
+ * (xmin - 1, ymin - 1) and the sweep axis; then the path of hp_run_origin
+ * is enqueued on `stream` and the call returns.
+ *   axis   0: sweep along x (Algorithm 1 as written); 1: along y, i.e. the
+ *          path runs on the points with x and y exchanged (one transposing
+ *          pass into the workspace); 2: along y exactly when the y extent
+ *          of the box is the smaller one
+ *   p_cap  capacity of lo, hi and mask in columns (they hold p_cap int32,
+ *          p_cap int32 and ceil(p_cap / 64) uint64).  0 asks for the plan
+ *          alone: nothing after the box is enqueued and the outputs other
+ *          than plan may be NULL.  p > p_cap returns HP_ECAPACITY with the
+ *          plan written
+ *   plan   HOST int64[8]: xmin, xmax, ymin, ymax of the box, p, ox, oy and
+ *          the axis taken (0 or 1).  With axis 1 the box and the origin are
+ *          those of the exchanged points, and so are L, M, the chain and
+ *          the hull
+ *   other outputs as for hp_run_origin (chain_cap >= min(n, p), hull_cap >=
+ *          2 min(n, p)); ws is caller-owned device memory of
+ *          hp_run_auto_workspace_bytes(n, axis, p_cap) bytes (the path's
+ *          workspace for every p <= p_cap, plus the box and, for axis != 0,
+ *          8n bytes for the exchanged points)
+ * n = 0 and an extent beyond HP_P_MAX return HP_EINVAL (the plan is written
+ * in the second case).
+ *
+ * hp_run_auto_f32: the same for float32 points and a given side p (the
+ * Conclusions' scaling of floating-point data): the float box on the
+ * device, one synchronisation, then on the host the origin (xmin, ymin) and
+ * scale = (p - 1) / max(xmax - xmin, ymax - ymin) in double precision (1
+ * for a zero extent), then hp_quantize_f32 and hp_run with side p on the
+ * scaled points.
+ *   plan   HOST double[7]: the float box widened to double, scale, ox, oy
+ *   qpts   DEVICE int32 pairs (n of them), 8-byte aligned: receives the
+ *          scaled points; NULL keeps them in the workspace
+ *   ws     hp_run_auto_f32_workspace_bytes(n, p) bytes
+ * A coordinate that cannot be scaled into range sets info[HP_INFO_STATUS] =
+ * HP_ERANGE once the path has completed.  No finite point returns
+ * HP_EINVAL. */
+int hp_run_auto_workspace_bytes(int64_t n, int32_t axis, int32_t p_cap, size_t *bytes);
+int hp_run_auto(const int32_t *pts, int64_t n, int32_t axis, int32_t p_cap, int64_t *plan, int32_t *lo,
+                int32_t *hi, uint64_t *mask, int32_t *cx, int32_t *clo, int32_t *chi, int32_t chain_cap,
+                int32_t *hx, int32_t *hy, int32_t hull_cap, int32_t *info, void *ws, size_t ws_bytes,
+                void *stream);
+int hp_run_auto_f32_workspace_bytes(int64_t n, int32_t p, size_t *bytes);
+int hp_run_auto_f32(const float *pts, int64_t n, int32_t p, double *plan, int32_t *qpts, int32_t *lo,
+                    int32_t *hi, uint64_t *mask, int32_t *cx, int32_t *clo, int32_t *chi, int32_t chain_cap,
+                    int32_t *hx, int32_t *hy, int32_t hull_cap, int32_t *info, void *ws, size_t ws_bytes,
+                    void *stream);
+
 /* The bit array M and its w-ary tree, w = 64 (Discussion, extraction by an
  * array of bits and by a tree structure).
  *
@@ -391,8 +445,10 @@ typedef struct hp_server hp_server;
  * block (its points when they come from host memory, its workspace, its
  * device outputs): a request is admitted, in arrival order, only when its
  * block fits.  max_batch bounds the requests joined into one launch
- * sequence.  Up to two batches are in flight; the points of the next batch
- * are copied while the current one computes. */
+ * sequence.  Up to four batches are in flight: host points are copied on
+ * one stream, batches compute in order on a second and their outputs return
+ * on a third, so the copies of later batches overlap the current one's
+ * kernels. */
 int hp_server_create(size_t device_budget_bytes, int32_t max_batch, hp_server **server);
 
 /* Device bytes of the arena block a request of n points with side p needs

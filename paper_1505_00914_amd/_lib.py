@@ -65,6 +65,12 @@ SIGNATURES = {
     "hp_bbox": (ctypes.c_int, [_vp, _i64, _vp, _vp, _sz, _vp]),
     "hp_run_origin": (ctypes.c_int, [_vp, _i64, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp,
                                      _i32, _vp, _vp, _sz, _vp]),
+    "hp_run_auto_workspace_bytes": (ctypes.c_int, [_i64, _i32, _i32, _szp]),
+    "hp_run_auto": (ctypes.c_int, [_vp, _i64, _i32, _i32, _i64p, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp,
+                                   _i32, _vp, _vp, _sz, _vp]),
+    "hp_run_auto_f32_workspace_bytes": (ctypes.c_int, [_i64, _i32, _szp]),
+    "hp_run_auto_f32": (ctypes.c_int, [_vp, _i64, _i32, ctypes.POINTER(ctypes.c_double), _vp, _vp, _vp, _vp, _vp,
+                                       _vp, _vp, _i32, _vp, _vp, _i32, _vp, _vp, _sz, _vp]),
     "hp_hull": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp, _i32, _vp, _vp, _sz, _vp]),
     "hp_run": (ctypes.c_int, [_vp, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp,
                               _i32, _vp, _vp, _sz, _vp]),

@@ -1,6 +1,7 @@
 // hp_single.hip -- single-cloud kernels and entry points of libhullprep.
 #include <atomic>
 #include <climits>
+#include <cmath>
 #include <cstdlib>
 #include <mutex>
 #include <cstring>
@@ -2536,6 +2537,196 @@ extern "C" int hp_quantize_f32(const float *pts, int64_t n, double ox, double oy
   }
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return set_error(HP_EDEVICE, "k_quantize_f32 launch: %s", hipGetErrorString(e));
+  return HP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Steps 1-3 in one call: the box on the device, then the side, the origin
+// (or the scale) and the sweep axis on the host after one synchronisation,
+// then the path
+// ---------------------------------------------------------------------------
+__global__ void k_merge_status(const int32_t *__restrict__ from, int32_t *__restrict__ info) {
+  if (threadIdx.x == 0 && from[0] != HP_OK) atomicMin(&info[HP_INFO_STATUS], from[0]);
+}
+
+namespace hp {
+
+// Path workspace for every side up to p_cap.  The sizes grow with p
+// between the points where a strategy's buffers drop out or change shape
+// (the LDS and window limits, packed partials, the two binned rounds, every
+// window count of the binned reduce), so the largest is at one of those
+// points or at p_cap itself.
+static size_t ws_bytes_upto(int64_t n, int32_t p_cap) {
+  size_t m = ws_bytes_for(n, p_cap);
+  const auto at = [&](int64_t q) {
+    if (q >= 1 && q < p_cap) m = std::max(m, ws_bytes_for(n, (int32_t)q));
+  };
+  const int64_t lm = device_info().lds_max_p;
+  at(lm);
+  at((int64_t)kWinMax * lm);
+  at(65534);
+  at(n / kBinRoundsMinPerCol);
+  for (int64_t q = kBinWc; q <= kBinPMax; q += kBinWc) at(q);
+  return m;
+}
+
+struct AutoLayout {
+  size_t parts, box, status, pts, path;
+};
+
+// Box partials, the box, a status word, a copy of the points (transposed or
+// scaled; 8n bytes when `copy`), then the path's workspace.
+static AutoLayout auto_layout(int64_t n, bool copy) {
+  AutoLayout A;
+  size_t o = 0;
+  A.parts = o;  o = align_up(o + sizeof(int4) * (size_t)kBoxMaxGrid);
+  A.box = o;    o = align_up(o + sizeof(int4));
+  A.status = o; o = align_up(o + sizeof(int32_t));
+  A.pts = o;    o = align_up(o + (copy ? (size_t)8 * (size_t)n : 0));
+  A.path = o;
+  return A;
+}
+
+static int check_hull_out(int64_t n, int32_t p, const int32_t *hx, const int32_t *hy, int32_t hull_cap) {
+  if (!hx || !hy) return set_error(HP_EINVAL, "hull arrays must not be NULL");
+  const int64_t need = 2 * std::min<int64_t>(n, p);
+  if ((int64_t)hull_cap < need)
+    return set_error(HP_ECAPACITY, "hull_cap %d < 2 min(n, p) = %lld", hull_cap, (long long)need);
+  return HP_OK;
+}
+
+}  // namespace hp
+
+extern "C" int hp_run_auto_workspace_bytes(int64_t n, int32_t axis, int32_t p_cap, size_t *bytes) {
+  if (!bytes) return set_error(HP_EINVAL, "bytes is NULL");
+  if (n < 0 || axis < 0 || axis > 2 || p_cap < 0 || p_cap > HP_P_MAX)
+    return set_error(HP_EINVAL, "bad n, axis or p_cap");
+  *bytes = auto_layout(n, axis != 0 && p_cap > 0).path + (p_cap > 0 ? ws_bytes_upto(n, p_cap) : 0);
+  return HP_OK;
+}
+
+extern "C" int hp_run_auto(const int32_t *pts, int64_t n, int32_t axis, int32_t p_cap, int64_t *plan,
+                           int32_t *lo, int32_t *hi, uint64_t *mask, int32_t *cx, int32_t *clo, int32_t *chi,
+                           int32_t chain_cap, int32_t *hx, int32_t *hy, int32_t hull_cap, int32_t *info, void *ws,
+                           size_t ws_bytes, void *stream) {
+  if (n < 1) return set_error(HP_EINVAL, "n = %lld: the box of no points is undefined", (long long)n);
+  if (!pts || ((uintptr_t)pts & 7)) return set_error(HP_EINVAL, "pts is NULL or not 8-byte aligned");
+  if (axis < 0 || axis > 2) return set_error(HP_EINVAL, "axis %d is not 0 (x), 1 (y) or 2 (shorter side)", axis);
+  if (p_cap < 0 || p_cap > HP_P_MAX) return set_error(HP_EINVAL, "p_cap = %d outside [0, %d]", p_cap, HP_P_MAX);
+  if (!plan || !ws) return set_error(HP_EINVAL, "plan or workspace is NULL");
+  const AutoLayout A = auto_layout(n, axis != 0 && p_cap > 0);
+  if (ws_bytes < A.path) return set_error(HP_ECAPACITY, "workspace too small: %zu < %zu bytes", ws_bytes, A.path);
+  hipStream_t s = (hipStream_t)stream;
+  char *w = static_cast<char *>(ws);
+  // Step 1 on the device
+  const int64_t want = ((n + 1) / 2 + 4 * kBoxBlock - 1) / (4 * kBoxBlock);
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(kBoxMaxGrid, 4 * device_info().cus), want));
+  int4 *parts = reinterpret_cast<int4 *>(w + A.parts);
+  int32_t *dbox = reinterpret_cast<int32_t *>(w + A.box);
+  hipLaunchKernelGGL(k_bbox, dim3(grid), dim3(kBoxBlock), 0, s, pts, n, parts);
+  hipLaunchKernelGGL(k_bbox_fold, dim3(1), dim3(kBoxBlock), 0, s, (const int4 *)parts, grid, dbox);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_error(HP_EDEVICE, "k_bbox launch: %s", hipGetErrorString(e));
+  int32_t box[4];
+  e = hipMemcpyAsync(box, dbox, sizeof(box), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return set_error(HP_EDEVICE, "reading the box: %s", hipGetErrorString(e));
+  // Step 2 and the sweep axis: the side of the square that holds every
+  // point, the origin that moves the smallest x and y to 1, and the axis of
+  // the shorter side (exchanging x and y when the sweep runs along y)
+  const int64_t ex = (int64_t)box[1] - box[0], ey = (int64_t)box[3] - box[2];
+  const bool swap = axis == 1 || (axis == 2 && ey < ex);
+  const int64_t bx0 = swap ? box[2] : box[0], bx1 = swap ? box[3] : box[1];
+  const int64_t by0 = swap ? box[0] : box[2], by1 = swap ? box[1] : box[3];
+  const int64_t side = std::max(ex, ey) + 1;
+  plan[0] = bx0;
+  plan[1] = bx1;
+  plan[2] = by0;
+  plan[3] = by1;
+  plan[4] = side;
+  plan[5] = bx0 - 1;
+  plan[6] = by0 - 1;
+  plan[7] = swap ? 1 : 0;
+  if (side > HP_P_MAX) return set_error(HP_EINVAL, "extent %lld exceeds HP_P_MAX", (long long)side);
+  if (p_cap == 0) return HP_OK;   // the plan alone
+  const int32_t p = (int32_t)side;
+  if (p > p_cap) return set_error(HP_ECAPACITY, "side %d > p_cap %d", p, p_cap);
+  int rc = check_common(pts, n, p, lo, hi, cx, clo, chi, chain_cap, info, ws);
+  if (rc == HP_OK) rc = check_hull_out(n, p, hx, hy, hull_cap);
+  if (rc != HP_OK) return rc;
+  const size_t need = A.path + ws_bytes_for(n, p);
+  if (ws_bytes < need) return set_error(HP_ECAPACITY, "workspace too small for p = %d: %zu < %zu bytes", p, ws_bytes, need);
+  const int32_t *src = pts;
+  if (swap) {
+    int32_t *t = reinterpret_cast<int32_t *>(w + A.pts);
+    rc = hp_transpose_points(pts, n, t, stream);
+    if (rc != HP_OK) return rc;
+    src = t;
+  }
+  // the origin is read modulo 2^32 by the reduce
+  const int32_t ox = (int32_t)(uint32_t)(uint64_t)(bx0 - 1), oy = (int32_t)(uint32_t)(uint64_t)(by0 - 1);
+  return run_single(src, n, p, lo, hi, mask, cx, clo, chi, chain_cap, hx, hy, hull_cap, info, w + A.path,
+                    ws_bytes - A.path, s, true, ox, oy);
+}
+
+extern "C" int hp_run_auto_f32_workspace_bytes(int64_t n, int32_t p, size_t *bytes) {
+  if (!bytes) return set_error(HP_EINVAL, "bytes is NULL");
+  if (n < 0 || p < 1 || p > HP_P_MAX) return set_error(HP_EINVAL, "bad n or p");
+  *bytes = auto_layout(n, true).path + ws_bytes_for(n, p);
+  return HP_OK;
+}
+
+extern "C" int hp_run_auto_f32(const float *pts, int64_t n, int32_t p, double *plan, int32_t *qpts, int32_t *lo,
+                               int32_t *hi, uint64_t *mask, int32_t *cx, int32_t *clo, int32_t *chi,
+                               int32_t chain_cap, int32_t *hx, int32_t *hy, int32_t hull_cap, int32_t *info, void *ws,
+                               size_t ws_bytes, void *stream) {
+  if (n < 1) return set_error(HP_EINVAL, "n = %lld: the box of no points is undefined", (long long)n);
+  if (!pts || ((uintptr_t)pts & 7)) return set_error(HP_EINVAL, "pts is NULL or not 8-byte aligned");
+  if (qpts && ((uintptr_t)qpts & 7)) return set_error(HP_EINVAL, "qpts is not 8-byte aligned");
+  if (p < 1 || p > HP_P_MAX) return set_error(HP_EINVAL, "p = %d outside [1, %d]", p, HP_P_MAX);
+  if (!plan || !ws) return set_error(HP_EINVAL, "plan or workspace is NULL");
+  int rc = check_common(reinterpret_cast<const int32_t *>(pts), n, p, lo, hi, cx, clo, chi, chain_cap, info, ws);
+  if (rc == HP_OK) rc = check_hull_out(n, p, hx, hy, hull_cap);
+  if (rc != HP_OK) return rc;
+  const AutoLayout A = auto_layout(n, true);
+  const size_t need = A.path + ws_bytes_for(n, p);
+  if (ws_bytes < need) return set_error(HP_ECAPACITY, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+  hipStream_t s = (hipStream_t)stream;
+  char *w = static_cast<char *>(ws);
+  const int64_t want = ((n + 1) / 2 + 4 * kBoxBlock - 1) / (4 * kBoxBlock);
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(kBoxMaxGrid, 4 * device_info().cus), want));
+  float4 *parts = reinterpret_cast<float4 *>(w + A.parts);
+  float *dbox = reinterpret_cast<float *>(w + A.box);
+  hipLaunchKernelGGL(k_bbox_f32, dim3(grid), dim3(kBoxBlock), 0, s, reinterpret_cast<const float2 *>(pts), n, parts);
+  hipLaunchKernelGGL(k_bbox_fold_f32, dim3(1), dim3(kBoxBlock), 0, s, (const float4 *)parts, grid, dbox);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_error(HP_EDEVICE, "k_bbox_f32 launch: %s", hipGetErrorString(e));
+  float box[4];
+  e = hipMemcpyAsync(box, dbox, sizeof(box), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return set_error(HP_EDEVICE, "reading the box: %s", hipGetErrorString(e));
+  // the scaling of floating-point input: origin (xmin, ymin) and scale
+  // (p - 1) / (largest extent), in double precision (1 for a zero extent)
+  for (int i = 0; i < 4; ++i) plan[i] = (double)box[i];
+  if (!(box[0] <= box[1]) || !(box[2] <= box[3]) || !std::isfinite(box[0]) || !std::isfinite(box[1]) ||
+      !std::isfinite(box[2]) || !std::isfinite(box[3]))
+    return set_error(HP_EINVAL, "no finite points");
+  const double ext = std::max((double)box[1] - (double)box[0], (double)box[3] - (double)box[2]);
+  const double scale = ext > 0 ? (double)(p - 1) / ext : 1.0;
+  plan[4] = scale;
+  plan[5] = (double)box[0];
+  plan[6] = (double)box[2];
+  int32_t *q = qpts ? qpts : reinterpret_cast<int32_t *>(w + A.pts);
+  int32_t *qstat = reinterpret_cast<int32_t *>(w + A.status);
+  rc = hp_quantize_f32(pts, n, plan[5], plan[6], scale, q, qstat, stream);
+  if (rc != HP_OK) return rc;
+  rc = run_single(q, n, p, lo, hi, mask, cx, clo, chi, chain_cap, hx, hy, hull_cap, info, w + A.path,
+                  ws_bytes - A.path, s, true);
+  if (rc != HP_OK) return rc;
+  // a coordinate that could not be scaled is reported in the path's status
+  hipLaunchKernelGGL(k_merge_status, dim3(1), dim3(64), 0, s, (const int32_t *)qstat, info);
+  e = hipGetLastError();
+  if (e != hipSuccess) return set_error(HP_EDEVICE, "k_merge_status launch: %s", hipGetErrorString(e));
   return HP_OK;
 }
 

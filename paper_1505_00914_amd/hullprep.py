@@ -13,7 +13,7 @@ from dataclasses import dataclass
 import torch
 
 from . import _lib
-from ._lib import (HP_EINVAL, HP_INFO_H, HP_INFO_K, HP_INFO_S, HP_INFO_STATUS,  # noqa: F401
+from ._lib import (HP_ECAPACITY, HP_EINVAL, HP_INFO_H, HP_INFO_K, HP_INFO_S, HP_INFO_STATUS,  # noqa: F401
                    HP_STRATEGY_AUTO, HP_STRATEGY_GLOBAL, HP_STRATEGY_LDS, HP_STRATEGY_LDS_PARTIAL,
                    HP_STRATEGY_BINNED, HP_STRATEGY_SAMPLED, HP_STRATEGY_WINDOW, HullprepError)
 
@@ -95,7 +95,7 @@ class Buffers:
     ws: torch.Tensor
 
     @staticmethod
-    def allocate(n: int, p: int, device, export_L: bool = True) -> "Buffers":
+    def allocate(n: int, p: int, device, export_L: bool = True, ws_bytes: int | None = None) -> "Buffers":
         cap = max(1, min(n, p))
         i32 = dict(dtype=torch.int32, device=device)
         lo = torch.empty(p, **i32) if export_L else None
@@ -105,7 +105,8 @@ class Buffers:
                        torch.empty(cap, **i32), torch.empty(cap, **i32), torch.empty(cap, **i32),
                        torch.empty(2 * cap, **i32), torch.empty(2 * cap, **i32),
                        torch.zeros(4, **i32),
-                       torch.empty(workspace_bytes(n, p), dtype=torch.uint8, device=device))
+                       torch.empty(workspace_bytes(n, p) if ws_bytes is None else ws_bytes, dtype=torch.uint8,
+                                   device=device))
 
 
 def hp_precondition(points: torch.Tensor, p: int, buf: Buffers, stream=None) -> None:
@@ -266,39 +267,67 @@ def hp_transpose_points(points: torch.Tensor, out: torch.Tensor, stream=None) ->
     _lib.call("hp_transpose_points", _ptr(points), n, _ptr(out), _stream(stream))
 
 
-def run_auto(points: torch.Tensor, export_L: bool = True, axis: str = "x") -> dict:
-    """Steps 1 and 2, then the path: the bounding box on the device, p and the
-    origin from it, and the fused path on the translated points.  Outputs are
-    in translated coordinates; ``origin`` maps them back.
+_AXES = {"x": 0, "y": 1, "auto": 2}
+
+
+def run_auto_workspace_bytes(n: int, axis: str, p_cap: int) -> int:
+    size = ctypes.c_size_t()
+    _lib.call("hp_run_auto_workspace_bytes", n, _AXES[axis], p_cap, ctypes.byref(size))
+    return size.value
+
+
+def hp_run_auto(points: torch.Tensor, axis: str, p_cap: int, buf: Buffers | None, stream=None) -> dict:
+    """Box, side, origin and axis in the library, then the path enqueued on
+    ``stream`` (the call itself waits for the box).  ``buf`` holds outputs
+    for sides up to ``p_cap`` and a workspace of
+    run_auto_workspace_bytes(n, axis, p_cap) bytes; with p_cap = 0 only the
+    plan is computed (buf may then hold just the workspace).  Returns the
+    plan: box, p, origin and the axis taken."""
+    n = _check_points(points)
+    if axis not in _AXES:
+        raise ValueError("axis must be 'x', 'y' or 'auto'")
+    plan = (ctypes.c_int64 * 8)()
+    b = buf
+    cap = b.cx.numel() if b is not None and b.cx is not None else 0
+    hcap = b.hx.numel() if b is not None and b.hx is not None else 0
+    _lib.call("hp_run_auto", _ptr(points), n, _AXES[axis], p_cap, plan,
+              _ptr(b.lo) if b else None, _ptr(b.hi) if b else None, _ptr(b.mask) if b else None,
+              _ptr(b.cx) if b else None, _ptr(b.clo) if b else None, _ptr(b.chi) if b else None, cap,
+              _ptr(b.hx) if b else None, _ptr(b.hy) if b else None, hcap, _ptr(b.info) if b else None,
+              _ptr(b.ws) if b else None, b.ws.numel() if b else 0, _stream(stream))
+    v = list(plan)
+    return {"box": tuple(v[0:4]), "p": v[4], "origin": (v[5], v[6]), "axis": "y" if v[7] else "x"}
+
+
+def run_auto(points: torch.Tensor, export_L: bool = True, axis: str = "x", p_cap: int | None = None) -> dict:
+    """Steps 1 and 2, then the path, all in hp_run_auto: the bounding box on
+    the device, p and the origin from it, and the fused path on the
+    translated points.  Outputs are in translated coordinates; ``origin``
+    maps them back.
 
     ``axis`` picks the sweep: "x" (Algorithm 1 as written), "y" (the points
     with x and y exchanged, one extra pass), or "auto", the axis of the
     shorter side of the box.  With "y" every output is in exchanged
     coordinates (L per row y, hull of the (y, x) points); ``axis`` in the
-    result says which."""
+    result says which.  With a known bound ``p_cap`` on the side this is one
+    library call; without, a first call computes the plan alone."""
     n = _check_points(points)
     if n == 0:
         raise HullprepError(HP_EINVAL, "run_auto", "no points")
-    if axis not in ("x", "y", "auto"):
+    if axis not in _AXES:
         raise ValueError("axis must be 'x', 'y' or 'auto'")
-    xmin, xmax, ymin, ymax = bbox(points)
-    if axis == "y" or (axis == "auto" and (ymax - ymin) < (xmax - xmin)):
-        t = torch.empty_like(points)
-        hp_transpose_points(points, t)
-        out = run_auto(t, export_L, "x")
-        out["axis"] = "y"
-        return out
-    p = max(xmax - xmin, ymax - ymin) + 1
-    if p > _lib.HP_P_MAX:
-        raise HullprepError(HP_EINVAL, "run_auto", f"extent {p} exceeds {_lib.HP_P_MAX}")
-    origin = (xmin - 1, ymin - 1)
-    buf = Buffers.allocate(n, p, points.device, export_L)
-    hp_run_origin(points, p, origin, buf)
+    if p_cap is None:
+        ws = torch.empty(run_auto_workspace_bytes(n, axis, 0), dtype=torch.uint8, device=points.device)
+        p_cap = hp_run_auto(points, axis, 0, Buffers(n, 0, None, None, None, None, None, None, None, None,
+                                                     None, ws))["p"]
+    buf = Buffers.allocate(n, p_cap, points.device, export_L, run_auto_workspace_bytes(n, axis, p_cap))
+    plan = hp_run_auto(points, axis, p_cap, buf)
     out = collect(buf)
-    out["p"] = p
-    out["origin"] = origin
-    out["box"] = (xmin, xmax, ymin, ymax)
-    out["axis"] = "x"
+    p = plan["p"]
+    if export_L:
+        out["lo"], out["hi"] = out["lo"][:p], out["hi"][:p]
+        out["mask"] = out["mask"][:(p + 63) // 64]
+    out.update(plan)
     return out
 
 
@@ -421,28 +450,44 @@ def hp_quantize_f32(points: torch.Tensor, origin, scale: float, out: torch.Tenso
               _ptr(info), _stream(stream))
 
 
+def run_auto_f32_workspace_bytes(n: int, p: int) -> int:
+    size = ctypes.c_size_t()
+    _lib.call("hp_run_auto_f32_workspace_bytes", n, p, ctypes.byref(size))
+    return size.value
+
+
+def hp_run_auto_f32(points: torch.Tensor, p: int, buf: Buffers, qpts: torch.Tensor | None = None,
+                    stream=None) -> dict:
+    """Float box, origin and scale in the library, then the scaling and the
+    path enqueued on ``stream`` (the call itself waits for the box).
+    ``buf.ws`` holds run_auto_f32_workspace_bytes(n, p) bytes; ``qpts``, if
+    given, receives the scaled points.  Returns the box, scale and origin."""
+    n = _check_points_f32(points)
+    if qpts is not None and (qpts.dtype != torch.int32 or tuple(qpts.shape) != (n, 2) or not qpts.is_contiguous()
+                             or not qpts.is_cuda):
+        raise ValueError("qpts must be a contiguous (n, 2) int32 device tensor")
+    plan = (ctypes.c_double * 7)()
+    _lib.call("hp_run_auto_f32", _ptr(points), n, p, plan, _ptr(qpts), _ptr(buf.lo), _ptr(buf.hi),
+              _ptr(buf.mask), _ptr(buf.cx), _ptr(buf.clo), _ptr(buf.chi), buf.cx.numel(), _ptr(buf.hx),
+              _ptr(buf.hy), buf.hx.numel(), _ptr(buf.info), _ptr(buf.ws), buf.ws.numel(), _stream(stream))
+    v = list(plan)
+    return {"box": tuple(v[0:4]), "scale": v[4], "origin": (v[5], v[6])}
+
+
 def run_auto_f32(points: torch.Tensor, p: int, export_L: bool = True) -> dict:
-    """Float points through the path: the float box on the device, origin
-    (xmin, ymin) and scale (p - 1) / max extent, the scaling on the device,
-    then the fused path with side p on the integer points."""
+    """Float points through the path in one library call: the float box on
+    the device, origin (xmin, ymin) and scale (p - 1) / max extent, the
+    scaling on the device, then the fused path with side p on the integer
+    points."""
     n = _check_points_f32(points)
     if n == 0:
         raise HullprepError(HP_EINVAL, "run_auto_f32", "no points")
-    xmin, xmax, ymin, ymax = bbox_f32(points)
-    ext = max(xmax - xmin, ymax - ymin)
-    if not ext == ext or ext == float("inf") or xmin > xmax:
-        raise HullprepError(HP_EINVAL, "run_auto_f32", "no finite points")
-    scale = (p - 1) / ext if ext > 0 else 1.0
+    buf = Buffers.allocate(n, p, points.device, export_L, run_auto_f32_workspace_bytes(n, p))
     q = torch.empty((n, 2), dtype=torch.int32, device=points.device)
-    qinfo = torch.zeros(4, dtype=torch.int32, device=points.device)
-    hp_quantize_f32(points, (xmin, ymin), scale, q, qinfo)
-    buf = Buffers.allocate(n, p, points.device, export_L)
-    hp_run(q, p, buf)
+    plan = hp_run_auto_f32(points, p, buf, q)
     out = collect(buf)
-    qs = int(qinfo[HP_INFO_STATUS].item())
-    if qs != 0:
-        out["status"] = qs
-    out.update({"box": (xmin, xmax, ymin, ymax), "scale": scale, "origin": (xmin, ymin), "points": q.cpu().numpy()})
+    out.update(plan)
+    out["points"] = q.cpu().numpy()
     return out
 
 

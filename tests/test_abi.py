@@ -257,3 +257,63 @@ def test_largest_p_fits_one_dispatch_and_is_enforced():
     assert lib.hp_bitset_words(P, 1, ctypes.byref(w)) == 0
     assert lib.hp_bitset_words(P + 1, 0, ctypes.byref(w)) == _lib.HP_EINVAL
     assert lib.hp_rescan_y_workspace_bytes(4, P + 1, ctypes.byref(v)) == _lib.HP_EINVAL
+
+
+def test_run_auto_arguments_rejected_before_any_device_call():
+    """hp_run_auto and hp_run_auto_f32: argument and capacity errors come back
+    before the box is computed, so no device is touched."""
+    lib = _lib.load()
+    E, C = _lib.HP_EINVAL, _lib.HP_ECAPACITY
+    d = ctypes.c_void_p(1 << 20)
+    plan = (ctypes.c_int64 * 8)()
+    fplan = (ctypes.c_double * 7)()
+    size = ctypes.c_size_t()
+    assert lib.hp_run_auto_workspace_bytes(100, 3, 64, ctypes.byref(size)) == E
+    assert lib.hp_run_auto_workspace_bytes(100, 0, _lib.HP_P_MAX + 1, ctypes.byref(size)) == E
+    assert lib.hp_run_auto_workspace_bytes(100, 0, 0, ctypes.byref(size)) == 0
+    plan_only = size.value
+    args = lambda pts=d, n=100, axis=0, p_cap=64, pl=plan, ws_bytes=plan_only: (
+        pts, n, axis, p_cap, pl, None, None, None, d, d, d, 100, d, d, 200, d, d, ws_bytes, None)
+    assert lib.hp_run_auto(*args(n=0)) == E                          # no points: no box
+    assert lib.hp_run_auto(*args(pts=ctypes.c_void_p((1 << 20) + 4))) == E   # misaligned
+    assert lib.hp_run_auto(*args(axis=-1)) == E
+    assert lib.hp_run_auto(*args(p_cap=_lib.HP_P_MAX + 1)) == E
+    assert lib.hp_run_auto(*args(pl=None)) == E
+    assert lib.hp_run_auto(*args(ws_bytes=plan_only - 1, p_cap=0)) == C
+    assert lib.hp_run_auto(*args(axis=1, p_cap=64)) == C             # no room for the exchanged points
+    assert lib.hp_run_auto_f32_workspace_bytes(100, 0, ctypes.byref(size)) == E
+    assert lib.hp_run_auto_f32_workspace_bytes(100, 64, ctypes.byref(size)) == 0
+    need = size.value
+    fargs = lambda n=100, p=64, cap=100, hcap=200, ws_bytes=need, pl=fplan: (
+        d, n, p, pl, None, None, None, None, d, d, d, cap, d, d, hcap, d, d, ws_bytes, None)
+    assert lib.hp_run_auto_f32(*fargs(n=0)) == E
+    assert lib.hp_run_auto_f32(*fargs(p=_lib.HP_P_MAX + 1)) == E
+    assert lib.hp_run_auto_f32(*fargs(pl=None)) == E
+    assert lib.hp_run_auto_f32(*fargs(cap=63)) == C                  # chain_cap < min(n, p)
+    assert lib.hp_run_auto_f32(*fargs(hcap=127)) == C                # hull_cap < 2 min(n, p)
+    assert lib.hp_run_auto_f32(*fargs(ws_bytes=need - 1)) == C
+
+
+@pytest.mark.parametrize("n", [1000, 3_000_000, 40_000_000])
+def test_run_auto_workspace_covers_every_side_up_to_the_cap(n):
+    """The workspace hp_run_auto asks for at p_cap holds the path's workspace
+    at every side p <= p_cap (the per-strategy sizes are not monotone in p:
+    the binned reduce's partial arrays shrink as its window count grows)."""
+    lib = _lib.load()
+    v = ctypes.c_size_t()
+
+    def auto(axis, cap):
+        assert lib.hp_run_auto_workspace_bytes(n, axis, cap, ctypes.byref(v)) == 0
+        return v.value
+
+    def path(p):
+        assert lib.hp_workspace_bytes(n, p, ctypes.byref(v)) == 0
+        return v.value
+
+    for cap in (4096, 70_000, (1 << 20) + 4097):
+        have = auto(0, cap) - auto(0, 0)
+        ps = set(range(64, cap + 1, 509)) | {cap} | {q + e for q in range(4096, cap + 1, 4096) for e in (-1, 0, 1)}
+        ps |= {n // 32 + e for e in (-1, 0, 1)}
+        worst = max(path(p) for p in ps if 1 <= p <= cap)
+        assert have >= worst, (cap, have, worst)
+        assert auto(1, cap) >= auto(0, cap) + 8 * n

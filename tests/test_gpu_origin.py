@@ -264,3 +264,27 @@ def test_run_auto_axis(hp, axis, wide):
     if axis == "auto":
         assert got["axis"] == ("y" if wide else "x")
     _compare_auto(got, want, f"axis {axis}")
+
+
+@pytest.mark.parametrize("axis", ["x", "auto"])
+def test_run_auto_one_call_with_cap(hp, axis):
+    """With a bound on the side known beforehand run_auto is one library call;
+    outputs sized for the bound give the same result, and a bound below the
+    side is refused with the plan still returned."""
+    rng = np.random.default_rng(77)
+    a = np.stack([rng.integers(0, 9000, 300_000), rng.integers(0, 2500, 300_000)], 1).astype(np.int32) + 4321
+    want = oracle.auto(a, axis=axis)
+    dev = torch.from_numpy(a).cuda()
+    print(f"[case] run_auto one call axis={axis} p={want['p']}", flush=True)
+    for cap in (want["p"], want["p"] + 70_000, 1 << 20):
+        got = hp.run_auto(dev, axis=axis, p_cap=cap)
+        assert got["axis"] == want["axis"]
+        _compare_auto(got, want, f"cap {cap}")
+    buf = hp.Buffers.allocate(a.shape[0], want["p"] - 1, "cuda", True,
+                              hp.run_auto_workspace_bytes(a.shape[0], axis, want["p"] - 1))
+    with pytest.raises(hp.HullprepError) as e:
+        hp.hp_run_auto(dev, axis, want["p"] - 1, buf)
+    assert e.value.code == hp.HP_ECAPACITY
+    plan_ws = torch.empty(hp.run_auto_workspace_bytes(a.shape[0], axis, 0), dtype=torch.uint8, device="cuda")
+    plan = hp.hp_run_auto(dev, axis, 0, hp.Buffers(a.shape[0], 0, *([None] * 9), plan_ws))
+    assert plan["p"] == want["p"] and plan["box"] == want["box"] and plan["origin"] == want["origin"]
