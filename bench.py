@@ -1,19 +1,21 @@
 """Benchmark of the preconditioner + hull path on one MI355X.
 
-Default workload: one scan-like cloud of 10,000,000 int32 points (20 random
-ellipsoid surfaces, area-uniform samples, projected to xy and quantised to
-[1, 4096]); a step is one hp_run (L init, Algorithm 1, slab finish with the
-hull tree, chain write) over that cloud.  Inputs are resident in device
-memory before timing starts; the timed steps rotate over enough copies of the
-cloud (6 x 80 MB) that no step finds its input in the 256 MiB last-level
-cache.
+Default workload: the largest single cloud, 2^28 int32 points uniform in the
+disc of radius p/2 with p = 2^20; a step is one hp_run (L init, Algorithm 1,
+slab finish with the hull tree, chain write) over that cloud.  Inputs are
+resident in device memory before timing starts; the timed steps rotate over
+copies of the cloud (two 2 GiB copies; six for clouds under 128 MiB) so that
+no step finds its input in the 256 MiB last-level cache.
 
-Prints ONE JSON line: whole-path Gpoints/s, the reduce kernel's achieved HBM
-bandwidth against the 8 TB/s peak (HIP events around every reduce launch on
-its own stream), the HBM traffic from committed rocprofv3 counters when they
-match the current kernel source, and the CPU oracle timed on a bounded
-sample, plus the batched form (4096 ragged clouds) against the per-cloud
-launch sequence, and optionally the served form (--serve).
+Prints ONE JSON line: whole-path Gpoints/s, the reduce's achieved HBM
+bandwidth against the 8 TB/s peak (HIP events around the reduce's kernels on
+the stream they are launched on: one kernel, or from the first to the last
+kernel of the binned reduce), the HBM traffic from committed rocprofv3
+counters when they match the current kernel source, and the CPU oracle timed
+on a bounded sample, plus the other single-cloud regimes, the batched form
+(4096 ragged clouds) against the per-cloud launch sequence and the served
+form (Poisson arrivals at 2000/s for 60 s, points in host memory).  Progress
+lines go to stderr.
 """
 from __future__ import annotations
 
@@ -31,7 +33,17 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 # sources of the single-cloud reduce kernel (the counter summary names their hash)
 REDUCE_SOURCES = ["paper_1505_00914_amd/csrc/hp_reduce.h", "paper_1505_00914_amd/csrc/hp_kernels.h",
-                  "paper_1505_00914_amd/csrc/hp_device.h"]
+                  "paper_1505_00914_amd/csrc/hp_device.h", "paper_1505_00914_amd/csrc/hp_binned.h"]
+STRATEGY_NAMES = {1: "lds", 2: "global", 3: "lds_partial", 4: "window", 5: "sampled", 6: "binned"}
+REDUCE_KERNELS = {
+    "binned": "k_bin, k_bin_fold (per round) and k_bin_merge between the rounds: the reduce from the first "
+              "kernel's start to the last kernel's end",
+    "sampled": "k_reduce_global on the sample, k_filter_build, k_reduce_filtered",
+}
+
+
+def progress(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_source_sha() -> str:
@@ -92,8 +104,10 @@ def bench_single(args, torch, hp, synth):
     dev = torch.device("cuda:0")
     pts = synth.cloud(w["kind"], w["n"], p, w["seed"], device=dev)
     n = pts.shape[0]
-    copies = [pts] + [pts.clone() for _ in range(args.copies - 1)]
+    ncopies = args.copies if 8 * n < (128 << 20) else 2
+    copies = [pts] + [pts.clone() for _ in range(ncopies - 1)]
     buf = hp.Buffers.allocate(n, p, dev, export_L=False)
+    strategy = STRATEGY_NAMES.get(hp.reduce_strategy(n, p), "?")
     stream = torch.cuda.current_stream()
 
     for i in range(args.warmup):
@@ -118,6 +132,7 @@ def bench_single(args, torch, hp, synth):
     tm = hp.timing_read()
     hp.timing_enable(False)
 
+    progress(f"{args.workload}: {args.steps} steps timed, checking the last against the oracle")
     # the last step's outputs against the oracle (outside the timed region)
     got = hp.collect(buf)
     host = pts.cpu()
@@ -145,9 +160,10 @@ def bench_single(args, torch, hp, synth):
         "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": args.workload, "kind": w["kind"], "n": n, "p": p, "seed": w["seed"],
-                   "input_copies": args.copies, "parity_vs_oracle": bool(parity),
+                   "input_copies": ncopies, "reduce_strategy": strategy, "parity_vs_oracle": bool(parity),
                    "k": got["k"], "s": got["s"], "h": got["h"]},
-        "roofline": {"bound": "hbm", "kernel": "k_reduce (Algorithm 1)",
+        "roofline": {"bound": "hbm",
+                     "kernel": "reduce (Algorithm 1): " + REDUCE_KERNELS.get(strategy, f"k_reduce ({strategy})"),
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
@@ -200,7 +216,9 @@ def bench_regimes(args, torch, hp, synth) -> list:
               and np.array_equal(got["hull"], want["hull"]))
         red_ms = tm["total_ms"] / max(1, tm["count"])
         gbs = 8.0 * n / (red_ms * 1e-3) / 1e9
+        progress(f"regime {name} done")
         res.append({"workload": name, "n": n, "p": p, "steps": steps,
+                    "reduce_strategy": STRATEGY_NAMES.get(hp.reduce_strategy(n, p), "?"),
                     "gpoints_per_s": round(n * steps / (t1 - t0) / 1e9, 3),
                     "ms_per_step": round((t1 - t0) * 1e3 / steps, 5),
                     "reduce_ms_avg": round(red_ms, 5), "reduce_gbs": round(gbs, 1),
@@ -260,6 +278,7 @@ def bench_batched(args, torch, hp, synth) -> dict:
                   and np.array_equal(g["clo"], want["clo"]) and np.array_equal(g["chi"], want["chi"])
                   and np.array_equal(g["hull"], want["hull"]))
     plan.close()
+    progress("batched done")
     return {"clouds": len(spec), "points": total, "bytes": 8 * total,
             "ms_per_batch": round(t_b * 1e3, 4), "gpoints_per_s": round(total / t_b / 1e9, 3),
             "hbm_gbs": round(8 * total / t_b / 1e9, 1),
@@ -304,12 +323,14 @@ def _wait_until(hp, due_ns: int) -> None:
 
 
 def bench_serve(args, torch, hp, synth) -> dict:
-    """Open-loop Poisson arrivals (rate args.serve_rate per second for
-    args.serve_seconds) drawn from a pool of pre-generated requests, served
-    (a) by the library's server (continuous batching, memory admission) from
-    page-locked host memory, (b) by the same server with the points already in
-    device memory, and (c) as a baseline, first-in first-out, one request at a
-    time with the plain single-cloud launch sequence.  Latency = the time the
+    """Open-loop Poisson arrivals drawn from a pool of pre-generated requests,
+    served (a) by the library's server (continuous batching, memory
+    admission) from page-locked host memory, and (b) as a baseline,
+    first-in first-out, one request at a time with the plain single-cloud
+    launch sequence, both on the full trace (args.serve_rate per second for
+    args.serve_seconds); then both again, on a shorter trace
+    (args.serve_device_seconds), with the points already in device memory, at
+    the same rate and at args.serve_stress_rate.  Latency = the time the
     result is in host memory minus the scheduled arrival time."""
     import threading
 
@@ -318,10 +339,14 @@ def bench_serve(args, torch, hp, synth) -> dict:
     sys.setswitchinterval(0.0005)
     spec, host, dev = _serve_pool(torch, synth, args.serve_pool, 6, True)
     rng = np.random.default_rng(7)
-    gaps = rng.exponential(1.0 / args.serve_rate, size=int(args.serve_rate * args.serve_seconds * 1.2) + 16)
-    arrivals = np.cumsum(gaps)
-    arrivals = arrivals[arrivals < args.serve_seconds]
-    picks = rng.integers(0, len(spec), size=arrivals.shape[0])
+
+    def trace(rate: float, seconds: float):
+        gaps = rng.exponential(1.0 / rate, size=int(rate * seconds * 1.2) + 16)
+        a = np.cumsum(gaps)
+        a = a[a < seconds]
+        return a, rng.integers(0, len(spec), size=a.shape[0])
+
+    arrivals, picks = trace(args.serve_rate, args.serve_seconds)
 
     # reference result of every pool entry: each request alone
     ref = []
@@ -337,7 +362,7 @@ def bench_serve(args, torch, hp, synth) -> dict:
                 and a["h"] == b["h"] and np.array_equal(a["x"], b["x"]) and np.array_equal(a["clo"], b["clo"])
                 and np.array_equal(a["chi"], b["chi"]) and np.array_equal(a["hull"], b["hull"]))
 
-    def run_server(on_device: bool) -> dict:
+    def run_server(on_device: bool, arrivals, picks) -> dict:
         srv = hp.Server(args.serve_budget << 30, max_batch=args.serve_max_batch)
         max_n = max(sp[1] for sp in spec)
         max_p = max(sp[2] for sp in spec)
@@ -397,9 +422,10 @@ def bench_serve(args, torch, hp, synth) -> dict:
         if bad[0]:
             out["mismatches"] = bad[0]
             out["first_mismatches"] = first_bad
+        progress(f"serve: server ({'device' if on_device else 'host'} points, {len(arrivals)} requests) done")
         return out
 
-    def run_fifo(on_device: bool = False) -> dict:
+    def run_fifo(on_device: bool, arrivals, picks) -> dict:
         """One request at a time, plain single-cloud launches, FIFO."""
         dev_pts = torch.empty((max(s[1] for s in spec), 2), dtype=torch.int32, device="cuda:0")
         maxp = max(s[2] for s in spec)
@@ -436,6 +462,7 @@ def bench_serve(args, torch, hp, synth) -> dict:
         t_end = hp.clock_ns()
         out = _percentiles(lat)
         out.update({"requests": len(arrivals), "req_per_s": round(len(arrivals) / ((t_end - t0) / 1e9), 1)})
+        progress(f"serve: FIFO ({'device' if on_device else 'host'} points, {len(arrivals)} requests) done")
         return out
 
     # host-to-device copy rate of page-locked memory, for context
@@ -455,20 +482,20 @@ def bench_serve(args, torch, hp, synth) -> dict:
            "trace": f"Poisson {args.serve_rate}/s for {args.serve_seconds} s, pool of {len(spec)} requests "
                     f"(n log-uniform 1e4..1e7, p log-uniform 1024..65536, uniform/gaussian/ellipsoids)",
            "budget_gib": args.serve_budget, "max_batch": args.serve_max_batch}
-    res["server_host_points"] = run_server(False)
-    res["server_device_points"] = run_server(True)
-    res["fifo_percloud_host_points"] = run_fifo(False)
-    res["fifo_percloud_device_points"] = run_fifo(True)
-    # the same comparison at a higher arrival rate, points in device memory
-    if args.serve_stress_rate > 0:
-        gaps = rng.exponential(1.0 / args.serve_stress_rate,
-                               size=int(args.serve_stress_rate * args.serve_seconds * 1.2) + 16)
-        a2 = np.cumsum(gaps)
-        arrivals = a2[a2 < args.serve_seconds]
-        picks = rng.integers(0, len(spec), size=arrivals.shape[0])
-        res["stress_rate"] = args.serve_stress_rate
-        res["stress_server_device_points"] = run_server(True)
-        res["stress_fifo_percloud_device_points"] = run_fifo(True)
+    res["server_host_points"] = run_server(False, arrivals, picks)
+    res["fifo_percloud_host_points"] = run_fifo(False, arrivals, picks)
+    # points already in device memory, on a shorter trace at the same rate
+    # and at a higher one
+    if args.serve_device_seconds > 0:
+        a_dev, p_dev = trace(args.serve_rate, args.serve_device_seconds)
+        res["device_trace_seconds"] = args.serve_device_seconds
+        res["server_device_points"] = run_server(True, a_dev, p_dev)
+        res["fifo_percloud_device_points"] = run_fifo(True, a_dev, p_dev)
+        if args.serve_stress_rate > 0:
+            a_st, p_st = trace(args.serve_stress_rate, args.serve_device_seconds)
+            res["stress_rate"] = args.serve_stress_rate
+            res["stress_server_device_points"] = run_server(True, a_st, p_st)
+            res["stress_fifo_percloud_device_points"] = run_fifo(True, a_st, p_st)
     return res
 
 
@@ -518,80 +545,104 @@ def copy_calibration(torch, mbytes: int) -> None:
     torch.cuda.synchronize()
 
 
-def summarize_counters(fetch_dir: str, write_dir: str, copy_bytes: float, command: str, workload: str) -> str:
-    """HBM bytes per reduce launch from two rocprofv3 --pmc runs (FETCH_SIZE,
-    then WRITE_SIZE, in KiB per dispatch), each scaled by what the counter
-    reads for the copy kernel of known size in the same run."""
+def summarize_counters(fetch_dir: str, write_dir: str, copy_bytes: float, command: str, workload: str,
+                       runs: int) -> str:
+    """HBM bytes per step of the reduce's kernels from two rocprofv3 --pmc
+    runs (FETCH_SIZE, then WRITE_SIZE, in KiB per dispatch), each scaled by
+    what the counter reads for the copy kernel of known size in the same
+    run.  ``runs`` is the number of hp_run calls the counted command made: a
+    kernel with r dispatches per run contributes, for each of its r places in
+    the run, the median over the runs."""
     import csv
     import glob
+    import re
+
+    reduce_re = re.compile(r"k_reduce|k_bin|k_filter_build")
 
     def per_kernel(directory, counter):
         files = glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True)
         if not files:
             raise SystemExit(f"no counter_collection.csv under {directory}")
+        rows = [r for r in csv.DictReader(open(files[0])) if r.get("Counter_Name") == counter]
+        if rows and "Dispatch_Id" in rows[0]:
+            rows.sort(key=lambda r: int(r["Dispatch_Id"]))
         acc = {}
-        for r in csv.DictReader(open(files[0])):
-            if r.get("Counter_Name") != counter:
-                continue
-            name = r["Kernel_Name"]
-            acc.setdefault(name, []).append(float(r["Counter_Value"]))
+        for r in rows:
+            acc.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
         return acc
 
-    out = []
-    factors = {}
-    values = {}
+    def med(v):
+        v = sorted(v)
+        return v[len(v) // 2]
+
+    factors, per_step, copies, table = {}, {}, {}, {}
     for counter, directory in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         acc = per_kernel(directory, counter)
         copy = [v for k, vs in acc.items() if "bitwise_not" in k for v in vs]
-        red = [v for k, vs in acc.items() if "k_reduce" in k for v in vs]
+        red = {k: vs for k, vs in acc.items() if reduce_re.search(k)}
         if not copy or not red:
             raise SystemExit(f"{counter}: copy or reduce dispatches missing")
         # medians: a dispatch whose counters were not collected reads 0
-        c_kib = sorted(copy)[len(copy) // 2]
-        r_kib = sorted(red)[len(red) // 2]
+        c_kib = med(copy)
         factors[counter] = copy_bytes / (c_kib * 1024.0)
-        values[counter] = (r_kib, len(red), c_kib, len(copy))
-    f_r, nf, f_c, ncf = values["FETCH_SIZE"]
-    w_r, nw, w_c, ncw = values["WRITE_SIZE"]
-    hbm = f_r * 1024.0 * factors["FETCH_SIZE"] + w_r * 1024.0 * factors["WRITE_SIZE"]
-    out += [f"# HBM traffic of the reduce kernel on {workload}", "",
-            "Commands (from the repository root, on one MI355X), one counter per run:", ""]
+        copies[counter] = (c_kib, len(copy))
+        total = 0.0
+        for k, vs in red.items():
+            r = max(1, round(len(vs) / runs))
+            kib = sum(med(vs[j::r]) for j in range(r))
+            short = k.replace("void ", "").split("(")[0]
+            table.setdefault(short, {})[counter] = (kib * 1024.0 * factors[counter], len(vs), r)
+            total += kib * 1024.0 * factors[counter]
+        per_step[counter] = total
+    hbm = per_step["FETCH_SIZE"] + per_step["WRITE_SIZE"]
+    out = [f"# HBM traffic of the reduce on {workload}", "",
+           "Commands (from the repository root, on one MI355X), one counter per run:", ""]
     for c in ("FETCH_SIZE", "WRITE_SIZE"):
         out.append("    " + command.replace("COUNTER", c))
     out += ["",
             f"copy kernel of known size: {copy_bytes:.0f} bytes read and written per dispatch",
-            f"  FETCH_SIZE {f_c:.1f} KiB per dispatch (median of {ncf}) -> scale {factors['FETCH_SIZE']:.4f}",
-            f"  WRITE_SIZE {w_c:.1f} KiB per dispatch (median of {ncw}) -> scale {factors['WRITE_SIZE']:.4f}",
-            f"reduce kernel (k_reduce_*), median per dispatch:",
-            f"  FETCH_SIZE {f_r:.1f} KiB ({nf} dispatches) -> {f_r * 1024 * factors['FETCH_SIZE']:.0f} bytes",
-            f"  WRITE_SIZE {w_r:.1f} KiB ({nw} dispatches) -> {w_r * 1024 * factors['WRITE_SIZE']:.0f} bytes",
-            "",
+            f"  FETCH_SIZE {copies['FETCH_SIZE'][0]:.1f} KiB per dispatch (median of {copies['FETCH_SIZE'][1]})"
+            f" -> scale {factors['FETCH_SIZE']:.4f}",
+            f"  WRITE_SIZE {copies['WRITE_SIZE'][0]:.1f} KiB per dispatch (median of {copies['WRITE_SIZE'][1]})"
+            f" -> scale {factors['WRITE_SIZE']:.4f}",
+            f"reduce kernels, scaled bytes per run ({runs} runs counted):", "",
+            f"{'kernel':44s} {'per run':>8s} {'FETCH bytes':>14s} {'WRITE bytes':>14s}"]
+    for k in sorted(table):
+        f = table[k].get("FETCH_SIZE", (0.0, 0, 0))
+        w = table[k].get("WRITE_SIZE", (0.0, 0, 0))
+        out.append(f"{k:44s} {f[2]:8d} {f[0]:14.0f} {w[0]:14.0f}")
+    out += ["",
+            f"fetch_bytes_per_launch: {per_step['FETCH_SIZE']:.0f}",
+            f"write_bytes_per_launch: {per_step['WRITE_SIZE']:.0f}",
             f"kernel_source_sha: {kernel_source_sha()}",
             f"hbm_bytes_per_launch: {hbm:.0f}"]
     return "\n".join(out) + "\n"
 
 
 def bench_auto(args, torch, hp, synth) -> dict:
-    """Steps 1 and 2 on the main workload moved far from the origin: the
-    bounding-box pass alone, then bounding box + path on the moved points
-    (the path reads every point through the origin, no translated copy)."""
+    """Steps 1 and 2 on the auxiliary workload moved far from the origin: the
+    bounding-box pass alone; box + path enqueued back to back (hp_bbox, then
+    hp_run_origin with the origin known from a first call); and hp_run_auto,
+    which waits for the box on the host before it enqueues the path.  Then
+    the same cloud as float32 through hp_run_auto_f32."""
     import numpy as np
 
     import oracle
 
-    w = synth.WORKLOADS[args.workload]
+    w = synth.WORKLOADS[args.aux_workload]
     off = (-1_000_000_007, 123_456_789)
     pts = synth.cloud(w["kind"], w["n"], w["p"], w["seed"], device="cuda:0")
     pts += torch.tensor(off, dtype=torch.int32, device=pts.device)
     n = pts.shape[0]
     stream = torch.cuda.current_stream()
-    xmin, xmax, ymin, ymax = hp.bbox(pts)
-    p = max(xmax - xmin, ymax - ymin) + 1
-    origin = (xmin - 1, ymin - 1)
+    p_cap = w["p"]
+    abuf = hp.Buffers.allocate(n, p_cap, pts.device, False, hp.run_auto_workspace_bytes(n, "x", p_cap))
+    plan = hp.hp_run_auto(pts, "x", p_cap, abuf, stream)
+    p, origin = plan["p"], plan["origin"]
     buf = hp.Buffers.allocate(n, p, pts.device, export_L=False)
     box = torch.empty(4, dtype=torch.int32, device=pts.device)
     ws = torch.empty(hp.bbox_workspace_bytes(), dtype=torch.uint8, device=pts.device)
-    steps = max(10, args.steps)
+    steps = max(10, min(args.steps, 100))
     for _ in range(3):
         hp.hp_bbox(pts, box, ws, stream)
         hp.hp_run_origin(pts, p, origin, buf, stream)
@@ -606,47 +657,47 @@ def bench_auto(args, torch, hp, synth) -> dict:
         hp.hp_run_origin(pts, p, origin, buf, stream)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    got = hp.collect(buf)
+    for _ in range(steps):
+        hp.hp_run_auto(pts, "x", p_cap, abuf, stream)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
     want = oracle.auto(pts.cpu().numpy())
-    ok = (got["status"] == 0 and want["p"] == p and tuple(box.cpu().tolist()) == want["box"]
-          and got["k"] == want["k"] and np.array_equal(got["x"], want["x"])
-          and np.array_equal(got["clo"], want["clo"]) and np.array_equal(got["chi"], want["chi"])
-          and np.array_equal(got["hull"], want["hull"]))
+    ok = True
+    for got in (hp.collect(buf), hp.collect(abuf)):
+        ok = ok and (got["status"] == 0 and want["p"] == p and tuple(box.cpu().tolist()) == want["box"]
+                     and plan["box"] == want["box"] and plan["origin"] == want["origin"]
+                     and got["k"] == want["k"] and np.array_equal(got["x"], want["x"])
+                     and np.array_equal(got["clo"], want["clo"]) and np.array_equal(got["chi"], want["chi"])
+                     and np.array_equal(got["hull"], want["hull"]))
     bbox_ms = (t1 - t0) * 1e3 / steps
     # float input: the same cloud as float32 (scaled by 1/64, moved), taken
     # through the float box, the scaling to [1, p]^2 and the path
     fpts = (pts.to(torch.float64) / 64.0 + 1.0e5).to(torch.float32).contiguous()
-    fbox = torch.empty(4, dtype=torch.float32, device=pts.device)
     qpts = torch.empty_like(pts)
-    qinfo = torch.zeros(4, dtype=torch.int32, device=pts.device)
-    fx0, fx1, fy0, fy1 = hp.bbox_f32(fpts)
-    scale = (p - 1) / max(fx1 - fx0, fy1 - fy0)
-    fbuf = hp.Buffers.allocate(n, p, pts.device, export_L=False)
-
-    def float_step():
-        hp.hp_bbox_f32(fpts, fbox, ws, stream)
-        hp.hp_quantize_f32(fpts, (fx0, fy0), scale, qpts, qinfo, stream)
-        hp.hp_run(qpts, p, fbuf, stream)
-
+    fbuf = hp.Buffers.allocate(n, p, pts.device, False, hp.run_auto_f32_workspace_bytes(n, p))
     for _ in range(3):
-        float_step()
-    torch.cuda.synchronize()
-    t3 = time.perf_counter()
-    for _ in range(steps):
-        float_step()
+        hp.hp_run_auto_f32(fpts, p, fbuf, qpts, stream)
     torch.cuda.synchronize()
     t4 = time.perf_counter()
+    for _ in range(steps):
+        hp.hp_run_auto_f32(fpts, p, fbuf, qpts, stream)
+    torch.cuda.synchronize()
+    t5 = time.perf_counter()
     fgot = hp.collect(fbuf)
     fwant = oracle.auto_f32(fpts.cpu().numpy(), p)
-    fok = (fgot["status"] == 0 and int(qinfo[0]) == 0 and fgot["k"] == fwant["k"]
+    fok = (fgot["status"] == 0 and fgot["k"] == fwant["k"]
            and np.array_equal(qpts.cpu().numpy(), fwant["points"]) and np.array_equal(fgot["hull"], fwant["hull"]))
-    return {"workload": args.workload, "offset": list(off), "n": n, "p": p, "steps": steps,
-            "float_input": {"ms_per_step_box_scale_path": round((t4 - t3) * 1e3 / steps, 5),
-                            "gpoints_per_s": round(n * steps / (t4 - t3) / 1e9, 3),
-                            "parity_vs_oracle": bool(fok)},
+    progress("steps 1-2 done")
+    return {"workload": args.aux_workload, "offset": list(off), "n": n, "p": p, "steps": steps,
             "bbox_ms_avg": round(bbox_ms, 5), "bbox_gbs": round(8.0 * n / (bbox_ms * 1e-3) / 1e9, 1),
             "gpoints_per_s_bbox_and_path": round(n * steps / (t2 - t1) / 1e9, 3),
             "ms_per_step_bbox_and_path": round((t2 - t1) * 1e3 / steps, 5),
+            "hp_run_auto": {"ms_per_call": round((t3 - t2) * 1e3 / steps, 5),
+                            "gpoints_per_s": round(n * steps / (t3 - t2) / 1e9, 3)},
+            "float_input": {"entry_point": "hp_run_auto_f32",
+                            "ms_per_call": round((t5 - t4) * 1e3 / steps, 5),
+                            "gpoints_per_s": round(n * steps / (t5 - t4) / 1e9, 3),
+                            "parity_vs_oracle": bool(fok)},
             "parity_vs_oracle": bool(ok)}
 
 
@@ -717,24 +768,25 @@ def bench_bits(args, torch, hp) -> dict:
         x = np.array([r["s"] for r in rows], float)
         y = np.array([r[key]["total_us"] * 1e-6 for r in rows])
         fit[key + "_seconds_per_set_bit"] = float(np.polyfit(x, y, 1)[0])
+    progress("bit array and tree done")
     return {"p": p, "steps": steps, "rows": rows, "fit": fit}
 
 
 def bench_melkman(args, torch, hp, synth) -> dict:
-    """Melkman's sequential hull of the main workload's chain against the
+    """Melkman's sequential hull of the auxiliary workload's chain against the
     parallel hp_hull on the same chain (both after one hp_precondition)."""
     import numpy as np
 
     import oracle
 
-    w = synth.WORKLOADS[args.workload]
+    w = synth.WORKLOADS[args.aux_workload]
     p = w["p"]
     pts = synth.cloud(w["kind"], w["n"], p, w["seed"], device="cuda:0")
     buf = hp.Buffers.allocate(pts.shape[0], p, pts.device, export_L=True)
     stream = torch.cuda.current_stream()
     hp.hp_precondition(pts, p, buf, stream)
     steps = max(5, min(args.steps, 20))
-    res = {"workload": args.workload, "steps": steps}
+    res = {"workload": args.aux_workload, "steps": steps}
     for name, fn in (("hp_hull_melkman", hp.hp_hull_melkman), ("hp_hull", hp.hp_hull)):
         fn(buf, stream)
         start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -765,6 +817,7 @@ def bench_melkman(args, torch, hp, synth) -> dict:
           and np.array_equal(rb.rhi[:k2].cpu().numpy(), want["xhi"]))
     res["rescan_y"] = {"us_per_call": round(start.elapsed_time(stop) * 1e3 / steps, 2), "rx": got["s"], "rxy": info[2],
                        "rows": k2, "parity_vs_oracle": bool(ok)}
+    progress("Melkman and second sweep done")
     return res
 
 
@@ -773,7 +826,9 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="ellipsoids_10m_p4096")
+    ap.add_argument("--workload", default="disc_2p28_p2p20")
+    ap.add_argument("--aux-workload", default="ellipsoids_10m_p4096",
+                    help="cloud of the steps 1-2 and Melkman lines")
     ap.add_argument("--copies", type=int, default=6)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -781,7 +836,7 @@ def main(argv=None):
     ap.add_argument("--no-auto", action="store_true", help="skip the bounding-box (steps 1 and 2) line")
     ap.add_argument("--no-bits", action="store_true", help="skip the bit array / tree extraction line")
     ap.add_argument("--no-melkman", action="store_true", help="skip the Melkman cross-check line")
-    ap.add_argument("--regimes", default="uniform_100k_p1024,disc_2p28_p2p20,gaussian_2p28_p4096",
+    ap.add_argument("--regimes", default="ellipsoids_10m_p4096,uniform_100k_p1024,gaussian_2p28_p4096",
                     help="other single-cloud workloads timed beside the main one ('' for none)")
     ap.add_argument("--batch-clouds", type=int, default=4096)
     ap.add_argument("--batch-steps", type=int, default=10)
@@ -789,7 +844,9 @@ def main(argv=None):
     ap.add_argument("--no-serve", action="store_true", help="skip the served form")
     ap.add_argument("--serve", action="store_true", help="(default) run the served form")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
-    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--serve-seconds", type=float, default=60.0, help="length of the host-memory trace")
+    ap.add_argument("--serve-device-seconds", type=float, default=10.0,
+                    help="length of the device-memory traces (0 skips them)")
     ap.add_argument("--serve-pool", type=int, default=32)
     ap.add_argument("--serve-budget", type=int, default=8, help="device arena, GiB")
     ap.add_argument("--serve-max-batch", type=int, default=64)
@@ -801,6 +858,8 @@ def main(argv=None):
                     help="run a plain copy kernel of this many MB first (for counter runs)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="summarise two rocprofv3 --pmc directories (FETCH_SIZE, WRITE_SIZE) and exit")
+    ap.add_argument("--counter-runs", type=int, default=0,
+                    help="hp_run calls in the counted command (default warmup + 2 steps, as bench_single makes)")
     ap.add_argument("--summarize-trace", metavar="DIR", help="summarise a rocprofv3 kernel-trace directory and exit")
     ap.add_argument("--summary-command", default="", help="command line recorded in the summary")
     ap.add_argument("--summary-title", default="kernel trace")
@@ -808,7 +867,8 @@ def main(argv=None):
 
     if args.summarize_counters:
         print(summarize_counters(args.summarize_counters[0], args.summarize_counters[1],
-                                 args.copy_calibration * 1e6, args.summary_command, args.workload), end="")
+                                 args.copy_calibration * 1e6, args.summary_command, args.workload,
+                                 args.counter_runs or args.warmup + 2 * args.steps), end="")
         return 0
     if args.summarize_trace:
         print(summarize_trace(args.summarize_trace, args.summary_command, args.summary_title), end="")

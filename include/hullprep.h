@@ -278,6 +278,11 @@ int32_t hp_lds_max_p(void);
  * default 8). */
 int hp_set_strategy(int strategy);
 
+/* The reduce strategy (HP_STRATEGY_*) that hp_run, hp_run_origin and
+ * hp_precondition take for n points of side p, given the forced strategy and
+ * the tuning table, when the workspace has hp_workspace_bytes(n, p) bytes. */
+int hp_reduce_strategy(int64_t n, int32_t p, int32_t *strategy);
+
 /* Launch-shape override for later calls in this process (used by the tuner):
  * strategy (HP_STRATEGY_*), reduce block size (256, 512 or 1024), 16-byte
  * vectors per lane per step (2, 4 or 8) and grid size; 0 leaves a field to

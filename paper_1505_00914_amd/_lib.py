@@ -35,6 +35,7 @@ SIGNATURES = {
     "hp_abi_version": (ctypes.c_int, []),
     "hp_lds_max_p": (_i32, []),
     "hp_set_strategy": (ctypes.c_int, [ctypes.c_int]),
+    "hp_reduce_strategy": (ctypes.c_int, [_i64, _i32, _i32p]),
     "hp_tune_set": (ctypes.c_int, [_i32, _i32, _i32, _i32]),
     "hp_tune_load": (ctypes.c_int, [ctypes.c_char_p]),
     "hp_timing_enable": (ctypes.c_int, [ctypes.c_int]),

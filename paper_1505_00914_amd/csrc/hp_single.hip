@@ -2329,6 +2329,13 @@ static int check_common(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, i
 
 using namespace hp;
 
+extern "C" int hp_reduce_strategy(int64_t n, int32_t p, int32_t *strategy) {
+  if (!strategy) return set_error(HP_EINVAL, "strategy is NULL");
+  if (p < 1 || p > HP_P_MAX || n < 0) return set_error(HP_EINVAL, "bad n or p");
+  *strategy = choose(n, p).strategy;
+  return HP_OK;
+}
+
 extern "C" int hp_workspace_bytes(int64_t n, int32_t p, size_t *bytes) {
   if (!bytes) return set_error(HP_EINVAL, "bytes is NULL");
   if (p < 1 || p > HP_P_MAX || n < 0) return set_error(HP_EINVAL, "bad n or p");

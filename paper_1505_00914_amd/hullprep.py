@@ -74,6 +74,13 @@ def timing_read() -> dict:
     return {"count": c.value, "total_ms": t.value, "min_ms": lo.value, "max_ms": hi.value}
 
 
+def reduce_strategy(n: int, p: int) -> int:
+    """The reduce strategy the library takes for n points of side p."""
+    v = ctypes.c_int32()
+    _lib.call("hp_reduce_strategy", n, p, ctypes.byref(v))
+    return v.value
+
+
 def lds_max_p() -> int:
     return int(_lib.load().hp_lds_max_p())
 

@@ -317,3 +317,21 @@ def test_run_auto_workspace_covers_every_side_up_to_the_cap(n):
         worst = max(path(p) for p in ps if 1 <= p <= cap)
         assert have >= worst, (cap, have, worst)
         assert auto(1, cap) >= auto(0, cap) + 8 * n
+
+
+def test_reduce_strategy_of_the_tuned_regimes():
+    """The choice the library makes for the full-size workloads (host logic:
+    the tuning table beside the library and the fall-backs of the choice)."""
+    lib = _lib.load()
+    v = ctypes.c_int32()
+
+    def pick(n, p):
+        assert lib.hp_reduce_strategy(n, p, ctypes.byref(v)) == 0
+        return v.value
+
+    assert pick(1 << 28, 1 << 20) == _lib.HP_STRATEGY_BINNED
+    assert pick(1 << 28, 4096) == _lib.HP_STRATEGY_LDS_PARTIAL
+    assert pick(10_000_000, 4096) == _lib.HP_STRATEGY_LDS_PARTIAL
+    assert pick(100_000, 1 << 24) == _lib.HP_STRATEGY_GLOBAL     # n < 16 p: no sampled or binned pass
+    assert pick(1 << 28, (1 << 20) + 1) != _lib.HP_STRATEGY_BINNED   # windows beyond the binned range
+    assert lib.hp_reduce_strategy(10, 0, ctypes.byref(v)) == _lib.HP_EINVAL

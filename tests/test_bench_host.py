@@ -38,7 +38,7 @@ def test_summarize_counters_and_traffic(tmp_path, monkeypatch):
         rows.append(['"hp::k_reduce_lds<1024, 2, false>"', counter, 0.0])   # a dispatch read as 0
         _write(str(tmp_path / counter / "host" / "run_counter_collection.csv"), hdr, rows)
     text = bench.summarize_counters(str(tmp_path / "FETCH_SIZE"), str(tmp_path / "WRITE_SIZE"), 80e6,
-                                    "rocprofv3 --pmc COUNTER -- python bench.py", "some_workload")
+                                    "rocprofv3 --pmc COUNTER -- python bench.py", "some_workload", 8)
     # FETCH scale 80e6 / (39062.5 KiB) = 2.0, WRITE scale 1.0
     assert "scale 2.0000" in text and "scale 1.0000" in text
     want = 40000.0 * 1024 * 2.0 + 4000.0 * 1024 * 1.0
@@ -53,6 +53,31 @@ def test_summarize_counters_and_traffic(tmp_path, monkeypatch):
     assert bench.committed_traffic("w") == pytest.approx(want)
     monkeypatch.setattr(bench, "kernel_source_sha", lambda: "0000")
     assert bench.committed_traffic("w") is None
+
+
+def test_summarize_counters_sums_a_multi_kernel_reduce(tmp_path):
+    """The binned reduce runs k_bin and k_bin_fold twice per run (rounds of
+    different sizes) and k_bin_merge once: each place in the run counts with
+    its own median, and the run's figure is their sum."""
+    hdr = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
+    runs = 3
+    for counter in ("FETCH_SIZE", "WRITE_SIZE"):
+        rows, d = [], 0
+        for i in range(5):
+            d += 1
+            rows.append([d, '"bitwise_not_kernel"', counter, 1000.0])
+        for r in range(runs):
+            for name, kib in (("k_bin", 100.0), ("k_bin_fold", 10.0), ("k_bin_merge", 1.0), ("k_bin", 300.0),
+                              ("k_bin_fold", 30.0), ("k_finish", 5000.0)):
+                d += 1
+                rows.append([d, f'"void hp::{name}(int)"', counter, kib + (r if name == "k_bin" else 0)])
+        rows.reverse()       # file order need not be dispatch order
+        _write(str(tmp_path / counter / "host" / "run_counter_collection.csv"), hdr, rows)
+    text = bench.summarize_counters(str(tmp_path / "FETCH_SIZE"), str(tmp_path / "WRITE_SIZE"), 1000 * 1024.0,
+                                    "cmd COUNTER", "w", runs)
+    per_run_kib = (100 + 1) + (300 + 1) + 10 + 30 + 1      # medians over the runs; k_finish is not the reduce
+    assert f"hbm_bytes_per_launch: {2 * per_run_kib * 1024:.0f}" in text
+    assert "hp::k_bin " in text and "k_finish" not in text
 
 
 def test_more_than_one_gpu_is_refused(capsys):
