@@ -557,7 +557,7 @@ def summarize_counters(fetch_dir: str, write_dir: str, copy_bytes: float, comman
     import glob
     import re
 
-    reduce_re = re.compile(r"k_reduce|k_bin|k_filter_build")
+    reduce_re = re.compile(r"hp::(k_reduce|k_bin|k_filter_build)")
 
     def per_kernel(directory, counter):
         files = glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True)

@@ -1552,6 +1552,327 @@ __global__ __launch_bounds__(kHullBlock) void k_l2_root(HullArgs H) {
   }
 }
 // ---------------------------------------------------------------------------
+// Clouds of more than one level-2 node: one workgroup per node of 64 slabs
+// (4096 columns) finishes its columns and builds the node's hulls.
+//  1. the partial L arrays folded per column: the L export, M and the slab
+//     counts; the node's columns stay in LDS
+//  2. the slab hulls: one lane per slab and side runs Andrew's monotone
+//     chain over the slab's 64 columns; meanwhile one wave finds the node's
+//     first chain index from the nodes before it (a decoupled look-back
+//     over nodes numbered in the order their workgroups start, so a node
+//     only waits for nodes that are already running)
+//  3. the node's hull per side: four lanes run the chain over the slab
+//     hulls of 16 slabs each, then one lane over the four results; the
+//     other waves write the node's part of the chain (Lemma 1)
+//  4. the node's hulls to the level-2 slot of the hull tree; the last
+//     workgroup to finish writes k, s and the reduce's range status
+// The chain keeps a vertex only when it makes a strict left turn with its
+// neighbours, so collinear points are dropped (Appendix).  Each side is the
+// lower hull of (x, lo) or of (x, -hi).
+// ---------------------------------------------------------------------------
+constexpr int kNodeBlock = 1024;
+constexpr int kNodeWaves = kNodeBlock / kWave;
+constexpr int kNodeCols = kFanIn * kSlab;
+constexpr int kNodeQuarter = kNodeCols / 4;
+constexpr int kCtlNodeTicket = 3;  // node numbers, in workgroup start order
+constexpr int kCtlNodeDone = 4;    // nodes finished
+constexpr int kCtlNodeK = 5;       // sum of the nodes' column counts
+constexpr int kCtlNodeS = 6;       // sum of the nodes' chain point counts
+constexpr uint32_t kLbAgg = 1u << 30, kLbIncl = 2u << 30, kLbMask = (1u << 30) - 1;
+constexpr int kLbSpinMax = 1 << 20;
+
+struct NodeShared {
+  int2 col[kNodeCols];          // (lo, hi) per column, slab-swizzled
+  uint16_t stk[2][kNodeCols];   // hull vertices as column indices, slab-swizzled
+  int32_t slab_k[kFanIn], slab_s[kFanIn], slab_off[kFanIn];
+  int32_t cnt[2][kFanIn];       // slab hull sizes
+  int32_t qcnt[2][4];           // quarter hull sizes
+  int32_t hcnt[2];              // node hull sizes
+  int32_t ticket, base, flag, err;
+};
+
+// Position t of a slab-major array of 64-entry rows, rotated by the row
+// index so that the lanes of a wave, one row each, fall in different banks.
+__device__ __forceinline__ int node_sw(int t) { return (t & ~(kSlab - 1)) | ((t + (t >> 6)) & (kSlab - 1)); }
+
+__device__ __forceinline__ int2 node_point(const NodeShared &S, int side, int32_t x0, int c) {
+  const int2 L = S.col[node_sw(c)];
+  return make_int2(x0 + c, side ? -L.y : L.x);
+}
+
+// Andrew's monotone chain for a lower hull, as column indices at linear
+// positions out0, out0 + 1, ... of one side's stack; the top two vertices
+// stay in registers.  An input may be read from a position at or after the
+// one the next push writes.
+template <bool SMALL>
+struct NodeChain {
+  uint16_t *stk;
+  int out0, n;
+  int2 a, b;
+  __device__ __forceinline__ void push(const NodeShared &S, int side, int32_t x0, int c, int2 v) {
+    while (n >= 2 && !cross_pos<SMALL>(a, b, v)) {
+      --n;
+      b = a;
+      if (n >= 2) a = node_point(S, side, x0, stk[node_sw(out0 + n - 2)]);
+    }
+    stk[node_sw(out0 + n)] = (uint16_t)c;
+    ++n;
+    a = b;
+    b = v;
+  }
+};
+
+template <bool SMALL>
+__global__ __launch_bounds__(kNodeBlock) void k_node_finish(FinishArgs A, int2 *__restrict__ l2_out,
+                                                            int32_t *__restrict__ ccount) {
+  __shared__ NodeShared S;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  const TreeShape &T = A.tree;
+  const int nnodes = T.size[2], nslab = T.size[1];
+  if (tid == 0) S.ticket = __hip_atomic_fetch_add(&A.ctl[kCtlNodeTicket], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  const int g = S.ticket;
+  if (g >= nnodes) {   // the control words were not cleared: no node to take
+    if (tid == 0) atomicMin(&A.info[HP_INFO_STATUS], HP_EDEVICE);
+    return;
+  }
+  const int64_t g0 = (int64_t)g * kNodeCols;
+  const int32_t x0 = (int32_t)g0 + 1;   // x of the node's column 0
+  const int64_t p = A.p;
+
+  // ---- 1. fold the partial arrays, four columns per thread ---------------
+  {
+    int mlo[4], mhi[4];
+    int64_t pos[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      mlo[j] = INT_MAX;
+      mhi[j] = INT_MIN;
+      pos[j] = g0 + tid + j * kNodeBlock;
+    }
+    const int G = A.G;
+    const bool full = g0 + kNodeCols <= p;
+    if (A.packed) {
+      const uint32_t *src = reinterpret_cast<const uint32_t *>(A.part);
+      for (int q = 0; q < G; ++q) {
+        uint32_t w[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) w[j] = (full || pos[j] < p) ? src[(size_t)q * p + pos[j]] : 0xFFFFFFFFu;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int2 e = unpack_partial(w[j]);
+          mlo[j] = min(mlo[j], e.x);
+          mhi[j] = max(mhi[j], e.y);
+        }
+      }
+    } else {
+      int q = 0;
+      for (; q + 1 < G; q += 2) {
+        int2 w[8];
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            w[4 * u + j] = (full || pos[j] < p) ? A.part[(size_t)(q + u) * p + pos[j]] : make_int2(INT_MAX, INT_MIN);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          mlo[u & 3] = min(mlo[u & 3], w[u].x);
+          mhi[u & 3] = max(mhi[u & 3], w[u].y);
+        }
+      }
+      if (q < G) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int2 e = (full || pos[j] < p) ? A.part[(size_t)q * p + pos[j]] : make_int2(INT_MAX, INT_MIN);
+          mlo[j] = min(mlo[j], e.x);
+          mhi[j] = max(mhi[j], e.y);
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const bool inside = pos[j] < p;
+      const bool valid = inside && mlo[j] <= mhi[j];
+      if (inside && A.lo) {
+        A.lo[pos[j]] = mlo[j];
+        A.hi[pos[j]] = mhi[j];
+      }
+      const int c = tid + j * kNodeBlock;
+      S.col[node_sw(c)] = valid ? make_int2(mlo[j], mhi[j]) : make_int2(1, 0);
+      const unsigned long long vm = __ballot(valid);
+      const unsigned long long sm = __ballot(valid && mlo[j] < mhi[j]);
+      const int sl = wave + j * kNodeWaves;   // the node's slab of these 64 columns
+      if (lane == 0) {
+        if (A.mask && (int64_t)g * kFanIn + sl < nslab) A.mask[(int64_t)g * kFanIn + sl] = vm;
+        S.slab_k[sl] = __popcll(vm);
+        S.slab_s[sl] = __popcll(vm) + __popcll(sm);
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- 2. slab hulls (waves 0 and 1), look-back (wave 2), chunk check -----
+  if (wave < 2) {
+    const int side = wave, sl = lane;
+    NodeChain<SMALL> ch;
+    ch.stk = S.stk[side];
+    ch.out0 = sl * kSlab;
+    ch.n = 0;
+    ch.a = ch.b = make_int2(0, 0);
+    int2 nxt = S.col[node_sw(sl * kSlab)];
+    for (int i = 0; i < kSlab; ++i) {
+      const int2 L = nxt;
+      if (i + 1 < kSlab) nxt = S.col[node_sw(sl * kSlab + i + 1)];
+      if (L.x <= L.y) {
+        const int c = sl * kSlab + i;
+        ch.push(S, side, x0, c, make_int2(x0 + c, side ? -L.y : L.x));
+      }
+    }
+    S.cnt[side][sl] = ch.n;
+  } else if (wave == 2) {
+    const int kk = S.slab_k[lane], ss = S.slab_s[lane];
+    int incl = kk, stot = ss;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const int o = __shfl_up(incl, d, kWave);
+      if (lane >= d) incl += o;
+    }
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) stot += __shfl_xor(stot, d, kWave);
+    S.slab_off[lane] = incl - kk;
+    const uint32_t kg = (uint32_t)__shfl(incl, kWave - 1, kWave);
+    uint32_t *flags = reinterpret_cast<uint32_t *>(A.tree_ctr + T.base[2]);
+    uint32_t prefix = 0;
+    if (g > 0) {
+      if (lane == 0) __hip_atomic_store(&flags[g], kLbAgg | kg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      for (int j = g - 1;; j -= kWave) {
+        const int idx = j - lane;
+        uint32_t v = idx >= 0 ? __hip_atomic_load(&flags[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : kLbIncl;
+        // every node numbered before this one is running and publishes its
+        // count right after its fold; the bound only turns a broken
+        // invariant into an error instead of a wait without end
+        for (int spin = 0; __ballot((v >> 30) == 0) != 0ull; ++spin) {
+          if (spin == kLbSpinMax) {
+            if (lane == 0) atomicMin(&A.info[HP_INFO_STATUS], HP_EDEVICE);
+            v = (v >> 30) == 0 ? kLbIncl : v;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+          if ((v >> 30) == 0) v = __hip_atomic_load(&flags[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        const unsigned long long incm = __ballot((v >> 30) == 2);
+        const int first = incm ? __builtin_ctzll(incm) : kWave;
+        uint32_t add = lane <= first ? (v & kLbMask) : 0u;
+#pragma unroll
+        for (int d = kWave / 2; d > 0; d >>= 1) add += __shfl_xor(add, d, kWave);
+        prefix += add;
+        if (incm) break;
+      }
+    }
+    if (lane == 0) {
+      __hip_atomic_store(&flags[g], kLbIncl | (prefix + kg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      S.base = (int)prefix;
+      atomicAdd(&A.ctl[kCtlNodeK], (int)kg);
+      atomicAdd(&A.ctl[kCtlNodeS], stot);
+    }
+  } else if (wave == 3 && g == 0 && A.dyn_ctr != nullptr) {
+    // every chunk of the reduce folded exactly once; the counter is zero
+    // again for the next run that uses its slot
+    int folded = 0;
+    for (int j = lane; j < A.n_wg_cnt; j += kWave) folded += A.wg_cnt[j];
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) folded += __shfl_xor(folded, d, kWave);
+    if (lane == 0) {
+      if ((int64_t)folded != A.dyn_expect) atomicMin(&A.info[HP_INFO_STATUS], HP_EDEVICE);
+      __hip_atomic_store(A.dyn_ctr, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  __syncthreads();
+
+  // ---- 3. quarter hulls (wave 0, lanes 0..7), the chain (other waves) -----
+  if (wave == 0) {
+    if (lane < 8) {
+      const int side = lane >> 2, qt = lane & 3;
+      NodeChain<SMALL> ch;
+      ch.stk = S.stk[side];
+      ch.out0 = qt * kNodeQuarter;
+      ch.n = 0;
+      ch.a = ch.b = make_int2(0, 0);
+      for (int sl = qt * (kFanIn / 4); sl < (qt + 1) * (kFanIn / 4); ++sl) {
+        const int m = S.cnt[side][sl];
+        for (int k = 0; k < m; ++k) {
+          const int c = ch.stk[node_sw(sl * kSlab + k)];
+          ch.push(S, side, x0, c, node_point(S, side, x0, c));
+        }
+      }
+      S.qcnt[side][qt] = ch.n;
+    }
+  } else {
+    for (int sl = wave - 1; sl < kFanIn; sl += kNodeWaves - 1) {
+      const int c = sl * kSlab + lane;
+      const int2 L = S.col[node_sw(c)];
+      const bool valid = L.x <= L.y;
+      int tot;
+      const int r = wave_rank(valid, &tot);
+      if (valid) {
+        const int off = S.base + S.slab_off[sl] + r;
+        if (off < A.chain_cap) {
+          A.cx_out[off] = x0 + c;
+          A.clo_out[off] = L.x;
+          A.chi_out[off] = L.y;
+        } else {
+          atomicMin(&A.info[HP_INFO_STATUS], HP_ECAPACITY);
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- 4. the node's hull per side (wave 0, lanes 0 and 1) ----------------
+  if (wave == 0 && lane < 2) {
+    const int side = lane;
+    NodeChain<SMALL> ch;
+    ch.stk = S.stk[side];
+    ch.out0 = 0;
+    ch.n = 0;
+    ch.a = ch.b = make_int2(0, 0);
+    for (int qt = 0; qt < 4; ++qt) {
+      const int m = S.qcnt[side][qt];
+      for (int k = 0; k < m; ++k) {
+        const int c = ch.stk[node_sw(qt * kNodeQuarter + k)];
+        ch.push(S, side, x0, c, node_point(S, side, x0, c));
+      }
+    }
+    S.hcnt[side] = ch.n;
+  }
+  __syncthreads();
+  const int64_t P = A.positions;
+  for (int side = 0; side < 2; ++side) {
+    const int m = S.hcnt[side];
+    int2 *dst = l2_out + (size_t)side * P + (size_t)g * kNodeCols;
+    for (int j = tid; j < m; j += kNodeBlock) dst[j] = node_point(S, side, x0, S.stk[side][node_sw(j)]);
+    if (tid == 0) ccount[side * T.nodes + T.base[2] + g] = m;
+  }
+
+  // ---- totals: the last node to finish ------------------------------------
+  if (last_arrival_flag(&A.ctl[kCtlNodeDone], nnodes, &S.flag)) {
+    int err = 0;
+    for (int j = tid; j < A.n_wg_err; j += kNodeBlock) err |= A.wg_err[j];
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) err |= __shfl_xor(err, d, kWave);
+    if (tid == 0) S.err = 0;
+    __syncthreads();
+    if (lane == 0 && err) atomicOr(&S.err, err);
+    __syncthreads();
+    if (tid == 0) {
+      A.info[HP_INFO_K] = __hip_atomic_load(&A.ctl[kCtlNodeK], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      A.info[HP_INFO_S] = __hip_atomic_load(&A.ctl[kCtlNodeS], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      report_reduce_errors(S.err, A.info);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
 static TreeShape make_tree(int64_t positions) {
@@ -1602,6 +1923,17 @@ constexpr int64_t kDynMinChunks = 32;
 
 // Static share of the shared-chunk reduce in eighths (HP_DYN_STATIC8, 0..8;
 // HP_DYN_OFF=1 turns chunk sharing off).
+// HP_NODE_FINISH_OFF=1: the slab-per-workgroup finish and the all-vertex
+// level-2 test also for clouds of more than one level-2 node.
+static bool node_finish_off() {
+  static int v = -1;
+  if (v < 0) {
+    const char *e = getenv("HP_NODE_FINISH_OFF");
+    v = (e && atoi(e) == 1) ? 1 : 0;
+  }
+  return v == 1;
+}
+
 static int dyn_static8() {
   static int v = -2;
   if (v == -2) {
@@ -2072,10 +2404,16 @@ static void hull_buffers(HullArgs &H, const TreeShape &T, int64_t positions, cha
 }
 
 static hipError_t launch_hull_levels(const TreeShape &T, int64_t positions, char *w, const Layout &Y,
-                                     HullArgs H, bool small, hipStream_t s, bool l2path = false) {
+                                     HullArgs H, bool small, hipStream_t s, bool l2path = false,
+                                     bool l2_done = false) {
   if (T.nlev < 2) return hipSuccess;
   hull_buffers(H, T, positions, w, Y);
   int first = 2;
+  if (l2_done) {
+    // the level-2 nodes' hulls are in place (k_node_finish)
+    first = 3;
+    l2path = false;
+  }
   if (l2path && T.nlev == 2) {
     // a single level-2 node: its test workgroups also write the hull (two
     // per slab, at least one per slab for the chain)
@@ -2269,6 +2607,22 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
   H.clo = clo;
   H.chi = chi;
   H.chain_cap = chain_cap;
+  // more than one level-2 node: one launch finishes the columns, the chain
+  // and the level-2 hulls
+  if (do_hull && T.nlev >= 3 && !node_finish_off()) {
+    HullArgs Hn = H;
+    hull_buffers(Hn, T, p, w, Y);
+    if (small)
+      hipLaunchKernelGGL((k_node_finish<true>), dim3(T.size[2]), dim3(kNodeBlock), 0, s, A, Hn.buf[1], Hn.ccount);
+    else
+      hipLaunchKernelGGL((k_node_finish<false>), dim3(T.size[2]), dim3(kNodeBlock), 0, s, A, Hn.buf[1], Hn.ccount);
+    e = hipGetLastError();
+    if (e != hipSuccess) return set_error(HP_EDEVICE, "k_node_finish launch: %s", hipGetErrorString(e));
+    H.ctl = ctl;
+    e = launch_hull_levels(T, p, w, Y, H, small, s, false, true);
+    if (e != hipSuccess) return set_error(HP_EDEVICE, "hull level launch: %s", hipGetErrorString(e));
+    return HP_OK;
+  }
   // many slabs: 256-thread slab workgroups (the last-slab scan, which needs
   // 1024 threads, is then a launch of its own)
   const bool many = T.size[1] > kScanRootMaxSlabs;
