@@ -1554,41 +1554,53 @@ __global__ __launch_bounds__(kHullBlock) void k_l2_root(HullArgs H) {
 // ---------------------------------------------------------------------------
 // Clouds of more than one level-2 node: one workgroup per node of 64 slabs
 // (4096 columns) finishes its columns and builds the node's hulls.
-//  1. the partial L arrays folded per column: the L export, M and the slab
-//     counts; the node's columns stay in LDS
-//  2. the slab hulls: one lane per slab and side runs Andrew's monotone
-//     chain over the slab's 64 columns; meanwhile one wave finds the node's
-//     first chain index from the nodes before it (a decoupled look-back
-//     over nodes numbered in the order their workgroups start, so a node
-//     only waits for nodes that are already running)
-//  3. the node's hull per side: four lanes run the chain over the slab
-//     hulls of 16 slabs each, then one lane over the four results; the
-//     other waves write the node's part of the chain (Lemma 1)
-//  4. the node's hulls to the level-2 slot of the hull tree; the last
-//     workgroup to finish writes k, s and the reduce's range status
-// The chain keeps a vertex only when it makes a strict left turn with its
-// neighbours, so collinear points are dropped (Appendix).  Each side is the
-// lower hull of (x, lo) or of (x, -hi).
+//  1. the partial L arrays folded per column: the L export, M, the slab
+//     counts and, per slab and side, the lowest point and the first and
+//     last columns; the node's columns stay in LDS
+//  2. a filter drops every point on or above the segment between two
+//     points of the node around it (the lowest points of its slab and of
+//     the next slab on its side, or its slab's end column): such a point is
+//     no vertex of the node's hull.  The survivors of each slab are listed.
+//     One wave finds the node's first chain index from the nodes before it
+//     (a look-back over nodes numbered in the order their workgroups start,
+//     so a node only waits for nodes that are already running)
+//  3. the slab hulls of the survivors: one lane per slab and side runs
+//     Andrew's monotone chain; the other waves write the node's part of the
+//     chain (Lemma 1)
+//  4. the node merge: a slab-hull vertex v is kept when the steepest slope
+//     into v from the points left of it is below the flattest slope out of
+//     v to the points right of it, both found per slab hull by binary search
+//     for the tangent from v (16 lanes per vertex, 4 slabs each)
+//  5. the node's hulls to the level-2 slot of the hull tree; the node
+//     numbered last writes k, s and the reduce's range status
+// Both steps keep a vertex only at a strict left turn, so collinear points
+// are dropped (Appendix).  Each side is the lower hull of (x, lo) or of
+// (x, -hi).
 // ---------------------------------------------------------------------------
 constexpr int kNodeBlock = 1024;
 constexpr int kNodeWaves = kNodeBlock / kWave;
 constexpr int kNodeCols = kFanIn * kSlab;
-constexpr int kNodeQuarter = kNodeCols / 4;
-constexpr int kCtlNodeTicket = 3;  // node numbers, in workgroup start order
-constexpr int kCtlNodeDone = 4;    // nodes finished
-constexpr int kCtlNodeK = 5;       // sum of the nodes' column counts
-constexpr int kCtlNodeS = 6;       // sum of the nodes' chain point counts
-constexpr uint32_t kLbAgg = 1u << 30, kLbIncl = 2u << 30, kLbMask = (1u << 30) - 1;
+constexpr int kNodeGroup = 16;                  // lanes per vertex in the merge
+constexpr int kCtlNodeTicket = 3;               // node numbers, in workgroup start order
+// look-back words: status in bits 62-63 (1: the node's own counts, 2: the
+// counts of every node up to it), counts below
+constexpr uint64_t kLbAgg = 1ull << 62, kLbIncl = 2ull << 62, kLbMask = (1ull << 62) - 1;
 constexpr int kLbSpinMax = 1 << 20;
 
 struct NodeShared {
-  int2 col[kNodeCols];          // (lo, hi) per column, slab-swizzled
-  uint16_t stk[2][kNodeCols];   // hull vertices as column indices, slab-swizzled
+  int2 col[kNodeCols];            // (lo, hi) per column, slab-swizzled
+  int2 hp[2][kNodeCols];          // slab-hull vertices, in x order per side
+  uint16_t stk[2][kNodeCols];     // survivors, then slab hulls (column indices, slab-swizzled)
+  uint8_t hslab[2][kNodeCols];    // slab of each slab-hull vertex
+  uint8_t keep[2][kNodeCols];     // merge verdicts
   int32_t slab_k[kFanIn], slab_s[kFanIn], slab_off[kFanIn];
-  int32_t cnt[2][kFanIn];       // slab hull sizes
-  int32_t qcnt[2][4];           // quarter hull sizes
-  int32_t hcnt[2];              // node hull sizes
-  int32_t ticket, base, flag, err;
+  int32_t mn[2][kFanIn];          // column in its slab of the lowest point, -1 when empty
+  int32_t first[kFanIn], last[kFanIn];
+  int32_t scnt[2][kFanIn];        // survivors per slab
+  int32_t cnt[2][kFanIn];         // slab-hull sizes
+  int32_t hoff[2][kFanIn];        // first vertex of each slab hull in hp
+  int32_t tot[2];
+  int32_t ticket, base;
 };
 
 // Position t of a slab-major array of 64-entry rows, rotated by the row
@@ -1600,32 +1612,25 @@ __device__ __forceinline__ int2 node_point(const NodeShared &S, int side, int32_
   return make_int2(x0 + c, side ? -L.y : L.x);
 }
 
-// Andrew's monotone chain for a lower hull, as column indices at linear
-// positions out0, out0 + 1, ... of one side's stack; the top two vertices
-// stay in registers.  An input may be read from a position at or after the
-// one the next push writes.
+// Sign of cross(o, a, b) for points of one node: x differences below 2^12
+// and y differences below 2^31, so the products (below 2^43) and their
+// comparison are exact in double precision.
 template <bool SMALL>
-struct NodeChain {
-  uint16_t *stk;
-  int out0, n;
-  int2 a, b;
-  __device__ __forceinline__ void push(const NodeShared &S, int side, int32_t x0, int c, int2 v) {
-    while (n >= 2 && !cross_pos<SMALL>(a, b, v)) {
-      --n;
-      b = a;
-      if (n >= 2) a = node_point(S, side, x0, stk[node_sw(out0 + n - 2)]);
-    }
-    stk[node_sw(out0 + n)] = (uint16_t)c;
-    ++n;
-    a = b;
-    b = v;
-  }
-};
+__device__ __forceinline__ bool ncross_pos(int2 o, int2 a, int2 b) {
+  if (SMALL) return cross_pos<true>(o, a, b);
+  return (double)(a.x - o.x) * (double)(b.y - o.y) > (double)(a.y - o.y) * (double)(b.x - o.x);
+}
+template <bool SMALL>
+__device__ __forceinline__ bool ncross_neg(int2 o, int2 a, int2 b) {
+  if (SMALL) return cross_neg<true>(o, a, b);
+  return (double)(a.x - o.x) * (double)(b.y - o.y) < (double)(a.y - o.y) * (double)(b.x - o.x);
+}
 
 template <bool SMALL>
 __global__ __launch_bounds__(kNodeBlock) void k_node_finish(FinishArgs A, int2 *__restrict__ l2_out,
                                                             int32_t *__restrict__ ccount) {
-  __shared__ NodeShared S;
+  extern __shared__ __align__(16) unsigned char node_smem[];
+  NodeShared &S = *reinterpret_cast<NodeShared *>(node_smem);
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const TreeShape &T = A.tree;
   const int nnodes = T.size[2], nslab = T.size[1];
@@ -1640,9 +1645,11 @@ __global__ __launch_bounds__(kNodeBlock) void k_node_finish(FinishArgs A, int2 *
   const int32_t x0 = (int32_t)g0 + 1;   // x of the node's column 0
   const int64_t p = A.p;
 
-  // ---- 1. fold the partial arrays, four columns per thread ---------------
+  // ---- 1. fold the partial arrays, four columns per thread (column
+  // tid + 1024 j is column `lane` of the node's slab wave + 16 j) ----------
+  int mlo[4], mhi[4];
+  bool valid[4];
   {
-    int mlo[4], mhi[4];
     int64_t pos[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -1692,44 +1699,75 @@ __global__ __launch_bounds__(kNodeBlock) void k_node_finish(FinishArgs A, int2 *
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const bool inside = pos[j] < p;
-      const bool valid = inside && mlo[j] <= mhi[j];
+      valid[j] = inside && mlo[j] <= mhi[j];
       if (inside && A.lo) {
         A.lo[pos[j]] = mlo[j];
         A.hi[pos[j]] = mhi[j];
       }
       const int c = tid + j * kNodeBlock;
-      S.col[node_sw(c)] = valid ? make_int2(mlo[j], mhi[j]) : make_int2(1, 0);
-      const unsigned long long vm = __ballot(valid);
-      const unsigned long long sm = __ballot(valid && mlo[j] < mhi[j]);
-      const int sl = wave + j * kNodeWaves;   // the node's slab of these 64 columns
+      S.col[node_sw(c)] = valid[j] ? make_int2(mlo[j], mhi[j]) : make_int2(1, 0);
+      const unsigned long long vm = __ballot(valid[j]);
+      const unsigned long long sm = __ballot(valid[j] && mlo[j] < mhi[j]);
+      const int sl = wave + j * kNodeWaves;
+      // lowest point of the slab on each side: smallest lo, largest hi (the
+      // leftmost of equal ones)
+      uint64_t k0 = valid[j] ? ((uint64_t)(uint32_t)mlo[j] << 6) | (uint64_t)lane : ~0ull;
+      uint64_t k1 = valid[j] ? ((uint64_t)(uint32_t)(INT_MAX - mhi[j]) << 6) | (uint64_t)lane : ~0ull;
+#pragma unroll
+      for (int d = kWave / 2; d > 0; d >>= 1) {
+        const uint64_t o0 = __shfl_xor(k0, d, kWave), o1 = __shfl_xor(k1, d, kWave);
+        k0 = o0 < k0 ? o0 : k0;
+        k1 = o1 < k1 ? o1 : k1;
+      }
       if (lane == 0) {
         if (A.mask && (int64_t)g * kFanIn + sl < nslab) A.mask[(int64_t)g * kFanIn + sl] = vm;
         S.slab_k[sl] = __popcll(vm);
         S.slab_s[sl] = __popcll(vm) + __popcll(sm);
+        S.mn[0][sl] = vm ? (int)(k0 & 63) : -1;
+        S.mn[1][sl] = vm ? (int)(k1 & 63) : -1;
+        S.first[sl] = vm ? __builtin_ctzll(vm) : -1;
+        S.last[sl] = vm ? 63 - __builtin_clzll(vm) : -1;
       }
     }
   }
   __syncthreads();
 
-  // ---- 2. slab hulls (waves 0 and 1), look-back (wave 2), chunk check -----
-  if (wave < 2) {
-    const int side = wave, sl = lane;
-    NodeChain<SMALL> ch;
-    ch.stk = S.stk[side];
-    ch.out0 = sl * kSlab;
-    ch.n = 0;
-    ch.a = ch.b = make_int2(0, 0);
-    int2 nxt = S.col[node_sw(sl * kSlab)];
-    for (int i = 0; i < kSlab; ++i) {
-      const int2 L = nxt;
-      if (i + 1 < kSlab) nxt = S.col[node_sw(sl * kSlab + i + 1)];
-      if (L.x <= L.y) {
-        const int c = sl * kSlab + i;
-        ch.push(S, side, x0, c, make_int2(x0 + c, side ? -L.y : L.x));
+  // ---- 2. the filter and the survivor lists (every wave, its 4 slabs); the
+  // look-back (last wave), the reduce's chunk check (node 0, wave 14) -------
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int sl = wave + j * kNodeWaves;
+    const int c = sl * kSlab + lane;
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      bool keep = false;
+      if (valid[j]) {
+        const int m = S.mn[side][sl];
+        const int2 v = make_int2(x0 + c, side ? -mhi[j] : mlo[j]);
+        if (lane == m) {
+          keep = true;
+        } else {
+          int cu, cw;
+          if (lane < m) {
+            const int pm = sl > 0 ? S.mn[side][sl - 1] : -1;
+            cu = pm >= 0 ? (sl - 1) * kSlab + pm : sl * kSlab + S.first[sl];
+            cw = sl * kSlab + m;
+          } else {
+            const int nm = sl + 1 < kFanIn ? S.mn[side][sl + 1] : -1;
+            cu = sl * kSlab + m;
+            cw = nm >= 0 ? (sl + 1) * kSlab + nm : sl * kSlab + S.last[sl];
+          }
+          keep = c == cu || c == cw ||
+                 ncross_neg<SMALL>(node_point(S, side, x0, cu), node_point(S, side, x0, cw), v);
+        }
       }
+      int tot;
+      const int r = wave_rank(keep, &tot);
+      if (keep) S.stk[side][node_sw(sl * kSlab + r)] = (uint16_t)c;
+      if (lane == 0) S.scnt[side][sl] = tot;
     }
-    S.cnt[side][sl] = ch.n;
-  } else if (wave == 2) {
+  }
+  if (wave == kNodeWaves - 1) {
     const int kk = S.slab_k[lane], ss = S.slab_s[lane];
     int incl = kk, stot = ss;
 #pragma unroll
@@ -1740,29 +1778,31 @@ __global__ __launch_bounds__(kNodeBlock) void k_node_finish(FinishArgs A, int2 *
 #pragma unroll
     for (int d = kWave / 2; d > 0; d >>= 1) stot += __shfl_xor(stot, d, kWave);
     S.slab_off[lane] = incl - kk;
-    const uint32_t kg = (uint32_t)__shfl(incl, kWave - 1, kWave);
-    uint32_t *flags = reinterpret_cast<uint32_t *>(A.tree_ctr + T.base[2]);
-    uint32_t prefix = 0;
+    // the node's (k, s) as one word: k in bits 0-30, s in bits 31-61 (sums
+    // of either stay below 2^31, so packed words add field by field)
+    const uint64_t mine = (uint64_t)(uint32_t)__shfl(incl, kWave - 1, kWave) | ((uint64_t)(uint32_t)stot << 31);
+    uint64_t *flags = reinterpret_cast<uint64_t *>(A.tree_ctr);
+    uint64_t prefix = 0;
     if (g > 0) {
-      if (lane == 0) __hip_atomic_store(&flags[g], kLbAgg | kg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (lane == 0) __hip_atomic_store(&flags[g], kLbAgg | mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       for (int j = g - 1;; j -= kWave) {
         const int idx = j - lane;
-        uint32_t v = idx >= 0 ? __hip_atomic_load(&flags[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : kLbIncl;
+        uint64_t v = idx >= 0 ? __hip_atomic_load(&flags[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : kLbIncl;
         // every node numbered before this one is running and publishes its
-        // count right after its fold; the bound only turns a broken
+        // counts right after its fold; the bound only turns a broken
         // invariant into an error instead of a wait without end
-        for (int spin = 0; __ballot((v >> 30) == 0) != 0ull; ++spin) {
+        for (int spin = 0; __ballot((v >> 62) == 0) != 0ull; ++spin) {
           if (spin == kLbSpinMax) {
             if (lane == 0) atomicMin(&A.info[HP_INFO_STATUS], HP_EDEVICE);
-            v = (v >> 30) == 0 ? kLbIncl : v;
+            v = (v >> 62) == 0 ? kLbIncl : v;
             break;
           }
           __builtin_amdgcn_s_sleep(1);
-          if ((v >> 30) == 0) v = __hip_atomic_load(&flags[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if ((v >> 62) == 0) v = __hip_atomic_load(&flags[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        const unsigned long long incm = __ballot((v >> 30) == 2);
+        const unsigned long long incm = __ballot((v >> 62) == 2);
         const int first = incm ? __builtin_ctzll(incm) : kWave;
-        uint32_t add = lane <= first ? (v & kLbMask) : 0u;
+        uint64_t add = lane <= first ? (v & kLbMask) : 0ull;
 #pragma unroll
         for (int d = kWave / 2; d > 0; d >>= 1) add += __shfl_xor(add, d, kWave);
         prefix += add;
@@ -1770,12 +1810,23 @@ __global__ __launch_bounds__(kNodeBlock) void k_node_finish(FinishArgs A, int2 *
       }
     }
     if (lane == 0) {
-      __hip_atomic_store(&flags[g], kLbIncl | (prefix + kg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      S.base = (int)prefix;
-      atomicAdd(&A.ctl[kCtlNodeK], (int)kg);
-      atomicAdd(&A.ctl[kCtlNodeS], stot);
+      __hip_atomic_store(&flags[g], kLbIncl | (prefix + mine), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      S.base = (int)(prefix & 0x7FFFFFFFull);
     }
-  } else if (wave == 3 && g == 0 && A.dyn_ctr != nullptr) {
+    if (g == nnodes - 1) {
+      // the last node holds the totals; it also reads the reduce's error words
+      int err = 0;
+      for (int j = lane; j < A.n_wg_err; j += kWave) err |= A.wg_err[j];
+#pragma unroll
+      for (int d = kWave / 2; d > 0; d >>= 1) err |= __shfl_xor(err, d, kWave);
+      if (lane == 0) {
+        const uint64_t tot = prefix + mine;
+        A.info[HP_INFO_K] = (int32_t)(tot & 0x7FFFFFFFull);
+        A.info[HP_INFO_S] = (int32_t)((tot >> 31) & 0x7FFFFFFFull);
+        report_reduce_errors(err, A.info);
+      }
+    }
+  } else if (wave == kNodeWaves - 2 && g == 0 && A.dyn_ctr != nullptr) {
     // every chunk of the reduce folded exactly once; the counter is zero
     // again for the next run that uses its slot
     int folded = 0;
@@ -1789,32 +1840,45 @@ __global__ __launch_bounds__(kNodeBlock) void k_node_finish(FinishArgs A, int2 *
   }
   __syncthreads();
 
-  // ---- 3. quarter hulls (wave 0, lanes 0..7), the chain (other waves) -----
-  if (wave == 0) {
-    if (lane < 8) {
-      const int side = lane >> 2, qt = lane & 3;
-      NodeChain<SMALL> ch;
-      ch.stk = S.stk[side];
-      ch.out0 = qt * kNodeQuarter;
-      ch.n = 0;
-      ch.a = ch.b = make_int2(0, 0);
-      for (int sl = qt * (kFanIn / 4); sl < (qt + 1) * (kFanIn / 4); ++sl) {
-        const int m = S.cnt[side][sl];
-        for (int k = 0; k < m; ++k) {
-          const int c = ch.stk[node_sw(sl * kSlab + k)];
-          ch.push(S, side, x0, c, node_point(S, side, x0, c));
-        }
+  // ---- 3. slab hulls (waves 0 and 1: side, lane = slab), the chain --------
+  if (wave < 2) {
+    const int side = wave, sl = lane;
+    uint16_t *stk = S.stk[side];
+    const int m = S.scnt[side][sl];
+    int n = 0;
+    int2 a = make_int2(0, 0), b = make_int2(0, 0);
+    // Andrew's monotone chain, in place: the top two vertices in registers
+    for (int k = 0; k < m; ++k) {
+      const int c = stk[node_sw(sl * kSlab + k)];
+      const int2 v = node_point(S, side, x0, c);
+      while (n >= 2 && !ncross_pos<SMALL>(a, b, v)) {
+        --n;
+        b = a;
+        if (n >= 2) a = node_point(S, side, x0, stk[node_sw(sl * kSlab + n - 2)]);
       }
-      S.qcnt[side][qt] = ch.n;
+      stk[node_sw(sl * kSlab + n)] = (uint16_t)c;
+      ++n;
+      a = b;
+      b = v;
     }
+    S.cnt[side][sl] = n;
+    // first vertex of each slab hull in the side's vertex list
+    int incl = n;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const int o = __shfl_up(incl, d, kWave);
+      if (lane >= d) incl += o;
+    }
+    S.hoff[side][sl] = incl - n;
+    if (lane == kWave - 1) S.tot[side] = incl;
   } else {
-    for (int sl = wave - 1; sl < kFanIn; sl += kNodeWaves - 1) {
+    for (int sl = wave - 2; sl < kFanIn; sl += kNodeWaves - 2) {
       const int c = sl * kSlab + lane;
       const int2 L = S.col[node_sw(c)];
-      const bool valid = L.x <= L.y;
+      const bool v = L.x <= L.y;
       int tot;
-      const int r = wave_rank(valid, &tot);
-      if (valid) {
+      const int r = wave_rank(v, &tot);
+      if (v) {
         const int off = S.base + S.slab_off[sl] + r;
         if (off < A.chain_cap) {
           A.cx_out[off] = x0 + c;
@@ -1827,48 +1891,99 @@ __global__ __launch_bounds__(kNodeBlock) void k_node_finish(FinishArgs A, int2 *
     }
   }
   __syncthreads();
-
-  // ---- 4. the node's hull per side (wave 0, lanes 0 and 1) ----------------
-  if (wave == 0 && lane < 2) {
-    const int side = lane;
-    NodeChain<SMALL> ch;
-    ch.stk = S.stk[side];
-    ch.out0 = 0;
-    ch.n = 0;
-    ch.a = ch.b = make_int2(0, 0);
-    for (int qt = 0; qt < 4; ++qt) {
-      const int m = S.qcnt[side][qt];
-      for (int k = 0; k < m; ++k) {
-        const int c = ch.stk[node_sw(qt * kNodeQuarter + k)];
-        ch.push(S, side, x0, c, node_point(S, side, x0, c));
+  // the slab-hull vertices as points, in x order per side
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int sl = wave + j * kNodeWaves;
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      if (lane < S.cnt[side][sl]) {
+        const int o = S.hoff[side][sl] + lane;
+        S.hp[side][o] = node_point(S, side, x0, S.stk[side][node_sw(sl * kSlab + lane)]);
+        S.hslab[side][o] = (uint8_t)sl;
       }
     }
-    S.hcnt[side] = ch.n;
   }
   __syncthreads();
-  const int64_t P = A.positions;
-  for (int side = 0; side < 2; ++side) {
-    const int m = S.hcnt[side];
-    int2 *dst = l2_out + (size_t)side * P + (size_t)g * kNodeCols;
-    for (int j = tid; j < m; j += kNodeBlock) dst[j] = node_point(S, side, x0, S.stk[side][node_sw(j)]);
-    if (tid == 0) ccount[side * T.nodes + T.base[2] + g] = m;
-  }
 
-  // ---- totals: the last node to finish ------------------------------------
-  if (last_arrival_flag(&A.ctl[kCtlNodeDone], nnodes, &S.flag)) {
-    int err = 0;
-    for (int j = tid; j < A.n_wg_err; j += kNodeBlock) err |= A.wg_err[j];
+  // ---- 4. node merge: 16 lanes per vertex, slabs gl, gl + 16, ... each ----
+  {
+    const int gl = tid & (kNodeGroup - 1), grp = tid / kNodeGroup;
+    const int t0 = S.tot[0], all = t0 + S.tot[1];
+    for (int q = grp; q < all; q += kNodeBlock / kNodeGroup) {
+      const int side = q < t0 ? 0 : 1, idx = side ? q - t0 : q;
+      const int2 *H = S.hp[side];
+      const int2 v = H[idx];
+      const int i = S.hslab[side][idx];
+      int2 uL = v, wR = v;
+      bool hasL = false, hasR = false;
 #pragma unroll
-    for (int d = kWave / 2; d > 0; d >>= 1) err |= __shfl_xor(err, d, kWave);
-    if (tid == 0) S.err = 0;
-    __syncthreads();
-    if (lane == 0 && err) atomicOr(&S.err, err);
-    __syncthreads();
-    if (tid == 0) {
-      A.info[HP_INFO_K] = __hip_atomic_load(&A.ctl[kCtlNodeK], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      A.info[HP_INFO_S] = __hip_atomic_load(&A.ctl[kCtlNodeS], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      report_reduce_errors(S.err, A.info);
+      for (int r = 0; r < kFanIn / kNodeGroup; ++r) {
+        const int jsl = gl + r * kNodeGroup;
+        const int m = S.cnt[side][jsl], o = S.hoff[side][jsl];
+        if (m == 0) continue;
+        if (jsl == i) {
+          // the vertex's own slab hull: its neighbours there
+          if (idx > o) {
+            const int2 u = H[idx - 1];
+            if (!hasL || steeper_left<SMALL>(u, uL, v)) { uL = u; hasL = true; }
+          }
+          if (idx + 1 < o + m) {
+            const int2 w = H[idx + 1];
+            if (!hasR || flatter_right<SMALL>(w, wR, v)) { wR = w; hasR = true; }
+          }
+        } else if (jsl < i) {
+          // tangent from v to a hull on its left: the first vertex whose
+          // next edge does not turn left towards v
+          int lo = 0, hi = m - 1;
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (ncross_pos<SMALL>(H[o + mid], H[o + mid + 1], v)) lo = mid + 1;
+            else hi = mid;
+          }
+          const int2 u = H[o + lo];
+          if (!hasL || steeper_left<SMALL>(u, uL, v)) { uL = u; hasL = true; }
+        } else {
+          // tangent from v to a hull on its right: the first vertex whose
+          // next edge does not turn right towards v
+          int lo = 0, hi = m - 1;
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (ncross_neg<SMALL>(H[o + mid], H[o + mid + 1], v)) lo = mid + 1;
+            else hi = mid;
+          }
+          const int2 w = H[o + lo];
+          if (!hasR || flatter_right<SMALL>(w, wR, v)) { wR = w; hasR = true; }
+        }
+      }
+#pragma unroll
+      for (int d = kNodeGroup / 2; d > 0; d >>= 1) {
+        const int2 ou = make_int2(__shfl_xor(uL.x, d, kNodeGroup), __shfl_xor(uL.y, d, kNodeGroup));
+        const int2 ow = make_int2(__shfl_xor(wR.x, d, kNodeGroup), __shfl_xor(wR.y, d, kNodeGroup));
+        const bool ohL = __shfl_xor((int)hasL, d, kNodeGroup) != 0;
+        const bool ohR = __shfl_xor((int)hasR, d, kNodeGroup) != 0;
+        if (ohL && (!hasL || steeper_left<SMALL>(ou, uL, v))) { uL = ou; hasL = true; }
+        if (ohR && (!hasR || flatter_right<SMALL>(ow, wR, v))) { wR = ow; hasR = true; }
+      }
+      if (gl == 0) S.keep[side][idx] = (!hasL || !hasR || cross_pos<SMALL>(uL, v, wR)) ? 1 : 0;
     }
+  }
+  __syncthreads();
+
+  // ---- 5. the node's hull per side (waves 0 and 1) ------------------------
+  if (wave < 2) {
+    const int side = wave, m = S.tot[side];
+    int2 *dst = l2_out + (size_t)side * A.positions + (size_t)g * kNodeCols;
+    int n = 0;
+    for (int j0 = 0; j0 < m; j0 += kWave) {
+      const int j = j0 + lane;
+      const bool k = j < m && S.keep[side][j] != 0;
+      int tot;
+      const int r = wave_rank(k, &tot);
+      if (k) dst[n + r] = S.hp[side][j];
+      n += tot;
+    }
+    if (lane == 0) ccount[side * T.nodes + T.base[2] + g] = n;
   }
 }
 
@@ -2612,10 +2727,22 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
   if (do_hull && T.nlev >= 3 && !node_finish_off()) {
     HullArgs Hn = H;
     hull_buffers(Hn, T, p, w, Y);
+    static bool node_attr = false;
+    if (!node_attr) {
+      const int bytes = (int)sizeof(NodeShared);
+      if (hipFuncSetAttribute((const void *)k_node_finish<true>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) !=
+              hipSuccess ||
+          hipFuncSetAttribute((const void *)k_node_finish<false>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) !=
+              hipSuccess)
+        return set_error(HP_EDEVICE, "k_node_finish: %zu bytes of LDS not available", sizeof(NodeShared));
+      node_attr = true;
+    }
     if (small)
-      hipLaunchKernelGGL((k_node_finish<true>), dim3(T.size[2]), dim3(kNodeBlock), 0, s, A, Hn.buf[1], Hn.ccount);
+      hipLaunchKernelGGL((k_node_finish<true>), dim3(T.size[2]), dim3(kNodeBlock), sizeof(NodeShared), s, A, Hn.buf[1],
+                         Hn.ccount);
     else
-      hipLaunchKernelGGL((k_node_finish<false>), dim3(T.size[2]), dim3(kNodeBlock), 0, s, A, Hn.buf[1], Hn.ccount);
+      hipLaunchKernelGGL((k_node_finish<false>), dim3(T.size[2]), dim3(kNodeBlock), sizeof(NodeShared), s, A,
+                         Hn.buf[1], Hn.ccount);
     e = hipGetLastError();
     if (e != hipSuccess) return set_error(HP_EDEVICE, "k_node_finish launch: %s", hipGetErrorString(e));
     H.ctl = ctl;
