@@ -761,9 +761,10 @@ struct HullShared {
 // Wave-wide combine of each lane's steepest-left / flattest-right extreme
 // for the wave's candidate v; true iff v is a strict lower-hull vertex.
 template <bool SMALL>
-__device__ __forceinline__ bool wave_extremes_keep(int2 v, int2 uL, bool hasL, int2 wR, bool hasR) {
+__device__ __forceinline__ bool wave_extremes_keep(int2 v, int2 uL, bool hasL, int2 wR, bool hasR,
+                                                   int width = kWave) {
 #pragma unroll 1
-  for (int d = kWave / 2; d > 0; d >>= 1) {
+  for (int d = width / 2; d > 0; d >>= 1) {
     const int2 ou = make_int2(__shfl_xor(uL.x, d, kWave), __shfl_xor(uL.y, d, kWave));
     const int2 ow = make_int2(__shfl_xor(wR.x, d, kWave), __shfl_xor(wR.y, d, kWave));
     const bool ohL = __shfl_xor((int)hasL, d, kWave) != 0;
@@ -863,29 +864,36 @@ __device__ __forceinline__ void hull_test_body(const HullArgs &H, HullShared &S,
   };
 
   // this workgroup's share of the child's vertices: index q runs over the
-  // lower side then the upper side; one wavefront per vertex
+  // lower side then the upper side; `width` lanes per vertex (the sibling
+  // count rounded up to a power of two), lane t of a vertex's group taking
+  // sibling t
   const int n0 = S.cc[0][j], n1 = S.cc[1][j];
   const int nq = n0 + n1;
   uint8_t *keep = H.keep + (size_t)c * span_c * 2;
-  for (int q = part * kWaves + wave; q < nq; q += H.split * kWaves) {
+  int width = 1;
+  while (width < nsib) width <<= 1;
+  const int per_wave = kWave / width;
+  const int t = lane & (width - 1);
+  for (int q0 = (part * kWaves + wave) * per_wave; q0 < nq; q0 += H.split * kWaves * per_wave) {
+    const int q = q0 + lane / width;
+    const bool on = q < nq;
     const int side = q < n0 ? 0 : 1;
     const int r = side ? q - n0 : q;
     const int *cc = S.cc[side];
     const int2 *own = child_ptr(side, j);
-    const int2 v = own[r];
+    const int2 v = on ? own[r] : make_int2(0, 0);
     int2 uL = v, wR = v;
     bool hasL = false, hasR = false;
-    const int t = lane;
-    if (t == j) {
+    if (on && t == j) {
       if (r > 0) { uL = own[r - 1]; hasL = true; }
       if (r + 1 < cc[j]) { wR = own[r + 1]; hasR = true; }
-    } else if (t < nsib && cc[t] > 0) {
+    } else if (on && t < nsib && cc[t] > 0) {
       const int2 *a = child_ptr(side, t);
       if (t < j) { uL = a[tangent_left<SMALL>(a, cc[t], v)]; hasL = true; }
       else { wR = a[tangent_right<SMALL>(a, cc[t], v)]; hasR = true; }
     }
-    const bool k = wave_extremes_keep<SMALL>(v, uL, hasL, wR, hasR);
-    if (lane == 0) keep[q] = k ? 1 : 0;
+    const bool k = wave_extremes_keep<SMALL>(v, uL, hasL, wR, hasR, width);
+    if (on && t == 0) keep[q] = k ? 1 : 0;
   }
 }
 
@@ -1557,25 +1565,26 @@ __global__ __launch_bounds__(kHullBlock) void k_l2_root(HullArgs H) {
 //  1. the partial L arrays folded per column: the L export, M, the slab
 //     counts and, per slab and side, the lowest point and the first and
 //     last columns; the node's columns stay in LDS
-//  2. a filter drops every point on or above the segment between two
-//     points of the node around it (the lowest points of its slab and of
-//     the next slab on its side, or its slab's end column): such a point is
-//     no vertex of the node's hull.  The survivors of each slab are listed.
-//     One wave finds the node's first chain index from the nodes before it
-//     (a look-back over nodes numbered in the order their workgroups start,
-//     so a node only waits for nodes that are already running)
-//  3. the slab hulls of the survivors: one lane per slab and side runs
-//     Andrew's monotone chain; the other waves write the node's part of the
-//     chain (Lemma 1)
-//  4. the node merge: a slab-hull vertex v is kept when the steepest slope
+//  2. the lower hull of the 64 lowest points (each against its neighbours
+//     up to 8 slabs away, in single precision: it only picks reference
+//     points for the filter); one wave finds the node's
+//     first chain index from the nodes before it (a look-back over nodes
+//     numbered in the order their workgroups start, so a node only waits
+//     for nodes that are already running)
+//  3. the filter drops every point on or above the segment between two
+//     points of the node around it (the nearest lowest points on that hull,
+//     or its slab's end column; the test is exact): such a point is no
+//     vertex of the node's hull.  The survivors of each slab are listed
+//  4. the slab hulls: each survivor against the others of its slab; the
+//     node's part of the chain (Lemma 1)
+//  5. the node merge: a slab-hull vertex v is kept when the steepest slope
 //     into v from the points left of it is below the flattest slope out of
 //     v to the points right of it, both found per slab hull by binary search
 //     for the tangent from v (16 lanes per vertex, 4 slabs each)
-//  5. the node's hulls to the level-2 slot of the hull tree; the node
+//  6. the node's hulls to the level-2 slot of the hull tree; the node
 //     numbered last writes k, s and the reduce's range status
-// Both steps keep a vertex only at a strict left turn, so collinear points
-// are dropped (Appendix).  Each side is the lower hull of (x, lo) or of
-// (x, -hi).
+// Vertices are kept only at a strict left turn, so collinear points are
+// dropped (Appendix).  Each side is the lower hull of (x, lo) or of (x, -hi).
 // ---------------------------------------------------------------------------
 constexpr int kNodeBlock = 1024;
 constexpr int kNodeWaves = kNodeBlock / kWave;
@@ -1586,19 +1595,24 @@ constexpr int kCtlNodeTicket = 3;               // node numbers, in workgroup st
 // counts of every node up to it), counts below
 constexpr uint64_t kLbAgg = 1ull << 62, kLbIncl = 2ull << 62, kLbMask = (1ull << 62) - 1;
 constexpr int kLbSpinMax = 1 << 20;
+constexpr int kMinWin = 8;                      // slabs each way in the hull of the lowest points
 
 struct NodeShared {
   int2 col[kNodeCols];            // (lo, hi) per column, slab-swizzled
-  int2 hp[2][kNodeCols];          // slab-hull vertices, in x order per side
-  uint16_t stk[2][kNodeCols];     // survivors, then slab hulls (column indices, slab-swizzled)
-  uint8_t hslab[2][kNodeCols];    // slab of each slab-hull vertex
+  int2 hp[2][kNodeCols];          // per slab row of 64: survivors, then the slab hull
+  uint16_t vidx[2][kNodeCols];    // slab-hull vertices in x order: their places in hp
   uint8_t keep[2][kNodeCols];     // merge verdicts
   int32_t slab_k[kFanIn], slab_s[kFanIn], slab_off[kFanIn];
   int32_t mn[2][kFanIn];          // column in its slab of the lowest point, -1 when empty
   int32_t first[kFanIn], last[kFanIn];
+  // per slab and side, the filter's reference points: the nearest lowest
+  // points left and right on the hull of the lowest points (or the slab's
+  // first and last columns), the slab's own lowest point, and whether that
+  // one is on the hull
+  int2 refL[2][kFanIn], refM[2][kFanIn], refR[2][kFanIn];
+  uint8_t ish[2][kFanIn];
   int32_t scnt[2][kFanIn];        // survivors per slab
   int32_t cnt[2][kFanIn];         // slab-hull sizes
-  int32_t hoff[2][kFanIn];        // first vertex of each slab hull in hp
   int32_t tot[2];
   int32_t ticket, base;
 };
@@ -1612,9 +1626,12 @@ __device__ __forceinline__ int2 node_point(const NodeShared &S, int side, int32_
   return make_int2(x0 + c, side ? -L.y : L.x);
 }
 
-// Sign of cross(o, a, b) for points of one node: x differences below 2^12
-// and y differences below 2^31, so the products (below 2^43) and their
-// comparison are exact in double precision.
+// Exact predicates for points of one node: x differences below 2^12 and y
+// differences below 2^31, so every product (below 2^43) and each comparison
+// is exact in double precision.
+//   ncross_pos / ncross_neg: cross(o, a, b) > 0 / < 0
+//   nsteeper_left: slope(u1, v) > slope(u2, v), u1 and u2 left of v
+//   nflatter_right: slope(v, w1) < slope(v, w2), w1 and w2 right of v
 template <bool SMALL>
 __device__ __forceinline__ bool ncross_pos(int2 o, int2 a, int2 b) {
   if (SMALL) return cross_pos<true>(o, a, b);
@@ -1624,6 +1641,16 @@ template <bool SMALL>
 __device__ __forceinline__ bool ncross_neg(int2 o, int2 a, int2 b) {
   if (SMALL) return cross_neg<true>(o, a, b);
   return (double)(a.x - o.x) * (double)(b.y - o.y) < (double)(a.y - o.y) * (double)(b.x - o.x);
+}
+template <bool SMALL>
+__device__ __forceinline__ bool nsteeper_left(int2 u1, int2 u2, int2 v) {
+  if (SMALL) return steeper_left<true>(u1, u2, v);
+  return (double)(v.y - u1.y) * (double)(v.x - u2.x) > (double)(v.y - u2.y) * (double)(v.x - u1.x);
+}
+template <bool SMALL>
+__device__ __forceinline__ bool nflatter_right(int2 w1, int2 w2, int2 v) {
+  if (SMALL) return flatter_right<true>(w1, w2, v);
+  return (double)(w1.y - v.y) * (double)(w2.x - v.x) < (double)(w2.y - v.y) * (double)(w1.x - v.x);
 }
 
 template <bool SMALL>
@@ -1673,27 +1700,22 @@ __global__ __launch_bounds__(kNodeBlock) void k_node_finish(FinishArgs A, int2 *
         }
       }
     } else {
-      int q = 0;
-      for (; q + 1 < G; q += 2) {
-        int2 w[8];
+      // up to 8 partial arrays x 4 columns of loads in flight per thread
+      for (int q0 = 0; q0 < G; q0 += 8) {
+        int2 w[8][4];
 #pragma unroll
-        for (int u = 0; u < 2; ++u)
+        for (int u = 0; u < 8; ++u)
 #pragma unroll
           for (int j = 0; j < 4; ++j)
-            w[4 * u + j] = (full || pos[j] < p) ? A.part[(size_t)(q + u) * p + pos[j]] : make_int2(INT_MAX, INT_MIN);
+            w[u][j] = (q0 + u < G && (full || pos[j] < p)) ? A.part[(size_t)(q0 + u) * p + pos[j]]
+                                                          : make_int2(INT_MAX, INT_MIN);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          mlo[u & 3] = min(mlo[u & 3], w[u].x);
-          mhi[u & 3] = max(mhi[u & 3], w[u].y);
-        }
-      }
-      if (q < G) {
+        for (int u = 0; u < 8; ++u)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int2 e = (full || pos[j] < p) ? A.part[(size_t)q * p + pos[j]] : make_int2(INT_MAX, INT_MIN);
-          mlo[j] = min(mlo[j], e.x);
-          mhi[j] = max(mhi[j], e.y);
-        }
+          for (int j = 0; j < 4; ++j) {
+            mlo[j] = min(mlo[j], w[u][j].x);
+            mhi[j] = max(mhi[j], w[u][j].y);
+          }
       }
     }
 #pragma unroll
@@ -1732,42 +1754,52 @@ __global__ __launch_bounds__(kNodeBlock) void k_node_finish(FinishArgs A, int2 *
   }
   __syncthreads();
 
-  // ---- 2. the filter and the survivor lists (every wave, its 4 slabs); the
-  // look-back (last wave), the reduce's chunk check (node 0, wave 14) -------
+  // ---- 2. the hull of the slabs' lowest points (waves 0 and 1: side, lane
+  // = slab); the look-back (last wave); the reduce's chunk check (node 0,
+  // the wave before) ---------------------------------------------------------
+  if (wave < 2) {
+    const int side = wave, sl = lane;
+    const int ml = S.mn[side][sl];
+    const int2 M = ml >= 0 ? node_point(S, side, x0, sl * kSlab + ml) : make_int2(0, 0);
+    // against the lowest points of the slabs up to kMinWin away only: the
+    // result is a superset of the hull's vertices, which still gives valid
+    // reference points
+    float lx = 0.f, ly = 0.f, rx = 0.f, ry = 0.f;   // steepest in, flattest out (as vectors)
+    bool hasL = false, hasR = false;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int sl = wave + j * kNodeWaves;
-    const int c = sl * kSlab + lane;
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      bool keep = false;
-      if (valid[j]) {
-        const int m = S.mn[side][sl];
-        const int2 v = make_int2(x0 + c, side ? -mhi[j] : mlo[j]);
-        if (lane == m) {
-          keep = true;
-        } else {
-          int cu, cw;
-          if (lane < m) {
-            const int pm = sl > 0 ? S.mn[side][sl - 1] : -1;
-            cu = pm >= 0 ? (sl - 1) * kSlab + pm : sl * kSlab + S.first[sl];
-            cw = sl * kSlab + m;
-          } else {
-            const int nm = sl + 1 < kFanIn ? S.mn[side][sl + 1] : -1;
-            cu = sl * kSlab + m;
-            cw = nm >= 0 ? (sl + 1) * kSlab + nm : sl * kSlab + S.last[sl];
-          }
-          keep = c == cu || c == cw ||
-                 ncross_neg<SMALL>(node_point(S, side, x0, cu), node_point(S, side, x0, cw), v);
-        }
-      }
-      int tot;
-      const int r = wave_rank(keep, &tot);
-      if (keep) S.stk[side][node_sw(sl * kSlab + r)] = (uint16_t)c;
-      if (lane == 0) S.scnt[side][sl] = tot;
+    for (int d = -kMinWin; d <= kMinWin; ++d) {
+      if (d == 0) continue;
+      const int j = sl + d;
+      const int src = j < 0 ? 0 : (j > kWave - 1 ? kWave - 1 : j);
+      const int mj = __shfl(ml, src, kWave);
+      const float dx = (float)(__shfl(M.x, src, kWave) - M.x);
+      const float dy = (float)(__shfl(M.y, src, kWave) - M.y);
+      const bool there = j >= 0 && j < kWave && mj >= 0;
+      // from the left: slope dy/dx (dx < 0) steeper than the best so far
+      const bool tL = there & (d < 0) & (!hasL | (dy * lx > ly * dx));
+      const bool tR = there & (d > 0) & (!hasR | (dy * rx < ry * dx));
+      lx = tL ? dx : lx;
+      ly = tL ? dy : ly;
+      hasL |= tL;
+      rx = tR ? dx : rx;
+      ry = tR ? dy : ry;
+      hasR |= tR;
     }
-  }
-  if (wave == kNodeWaves - 1) {
+    // a strict left turn: slope in below slope out (lx < 0 < rx)
+    const bool on = ml >= 0 && (!hasL || !hasR || ly * rx > ry * lx);
+    const unsigned long long hm = __ballot(on);
+    const unsigned long long lm = hm & ((1ull << sl) - 1ull);
+    const unsigned long long rm = sl == kWave - 1 ? 0ull : hm & ~((2ull << sl) - 1ull);
+    const int hl = lm ? 63 - __builtin_clzll(lm) : 0, hr = rm ? __builtin_ctzll(rm) : 0;
+    const int2 PL = make_int2(__shfl(M.x, hl, kWave), __shfl(M.y, hl, kWave));
+    const int2 PR = make_int2(__shfl(M.x, hr, kWave), __shfl(M.y, hr, kWave));
+    if (ml >= 0) {
+      S.refL[side][sl] = lm ? PL : node_point(S, side, x0, sl * kSlab + S.first[sl]);
+      S.refR[side][sl] = rm ? PR : node_point(S, side, x0, sl * kSlab + S.last[sl]);
+      S.refM[side][sl] = M;
+      S.ish[side][sl] = on ? 1 : 0;
+    }
+  } else if (wave == kNodeWaves - 1) {
     const int kk = S.slab_k[lane], ss = S.slab_s[lane];
     int incl = kk, stot = ss;
 #pragma unroll
@@ -1840,120 +1872,142 @@ __global__ __launch_bounds__(kNodeBlock) void k_node_finish(FinishArgs A, int2 *
   }
   __syncthreads();
 
-  // ---- 3. slab hulls (waves 0 and 1: side, lane = slab), the chain --------
-  if (wave < 2) {
-    const int side = wave, sl = lane;
-    uint16_t *stk = S.stk[side];
-    const int m = S.scnt[side][sl];
-    int n = 0;
-    int2 a = make_int2(0, 0), b = make_int2(0, 0);
-    // Andrew's monotone chain, in place: the top two vertices in registers
-    for (int k = 0; k < m; ++k) {
-      const int c = stk[node_sw(sl * kSlab + k)];
-      const int2 v = node_point(S, side, x0, c);
-      while (n >= 2 && !ncross_pos<SMALL>(a, b, v)) {
-        --n;
-        b = a;
-        if (n >= 2) a = node_point(S, side, x0, stk[node_sw(sl * kSlab + n - 2)]);
-      }
-      stk[node_sw(sl * kSlab + n)] = (uint16_t)c;
-      ++n;
-      a = b;
-      b = v;
-    }
-    S.cnt[side][sl] = n;
-    // first vertex of each slab hull in the side's vertex list
-    int incl = n;
+  // ---- 3. the filter (every wave, its 4 slabs): survivors to their row ---
 #pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-      const int o = __shfl_up(incl, d, kWave);
-      if (lane >= d) incl += o;
-    }
-    S.hoff[side][sl] = incl - n;
-    if (lane == kWave - 1) S.tot[side] = incl;
-  } else {
-    for (int sl = wave - 2; sl < kFanIn; sl += kNodeWaves - 2) {
-      const int c = sl * kSlab + lane;
-      const int2 L = S.col[node_sw(c)];
-      const bool v = L.x <= L.y;
-      int tot;
-      const int r = wave_rank(v, &tot);
-      if (v) {
-        const int off = S.base + S.slab_off[sl] + r;
-        if (off < A.chain_cap) {
-          A.cx_out[off] = x0 + c;
-          A.clo_out[off] = L.x;
-          A.chi_out[off] = L.y;
-        } else {
-          atomicMin(&A.info[HP_INFO_STATUS], HP_ECAPACITY);
+  for (int j = 0; j < 4; ++j) {
+    const int sl = wave + j * kNodeWaves;
+    const int c = sl * kSlab + lane;
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      bool keep = false;
+      const int2 v = make_int2(x0 + c, side ? -mhi[j] : mlo[j]);
+      if (valid[j]) {
+        const int2 PM = S.refM[side][sl];
+        int2 u = S.refL[side][sl], w = S.refR[side][sl];
+        if (S.ish[side][sl]) {
+          if (v.x < PM.x) w = PM;
+          else u = PM;
         }
+        keep = v.x == u.x || v.x == w.x || ncross_neg<SMALL>(u, w, v);
       }
+      int tot;
+      const int r = wave_rank(keep, &tot);
+      if (keep) S.hp[side][sl * kSlab + r] = v;
+      if (lane == 0) S.scnt[side][sl] = tot;
     }
   }
   __syncthreads();
-  // the slab-hull vertices as points, in x order per side
+
+  // ---- 4. slab hulls (every wave, its 4 slabs: lane k tests survivor k
+  // against the others of its slab, then the row is compacted in place);
+  // the node's part of the chain -------------------------------------------
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int sl = wave + j * kNodeWaves;
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
-      if (lane < S.cnt[side][sl]) {
-        const int o = S.hoff[side][sl] + lane;
-        S.hp[side][o] = node_point(S, side, x0, S.stk[side][node_sw(sl * kSlab + lane)]);
-        S.hslab[side][o] = (uint8_t)sl;
+      const int m = S.scnt[side][sl];
+      int2 *row = S.hp[side] + sl * kSlab;
+      const int2 v = lane < m ? row[lane] : make_int2(0, 0);
+      int2 uL = v, wR = v;
+      bool hasL = false, hasR = false;
+      for (int i = 0; i < m; ++i) {
+        const int2 u = row[i];
+        const bool tL = (i < lane) & (!hasL | nsteeper_left<SMALL>(u, uL, v));
+        const bool tR = (i > lane) & (!hasR | nflatter_right<SMALL>(u, wR, v));
+        uL = tL ? u : uL;
+        hasL |= tL;
+        wR = tR ? u : wR;
+        hasR |= tR;
+      }
+      const bool keep = lane < m && (!hasL || !hasR || ncross_pos<SMALL>(uL, v, wR));
+      int tot;
+      const int r = wave_rank(keep, &tot);
+      if (keep) row[r] = v;
+      if (lane == 0) S.cnt[side][sl] = tot;
+    }
+    const int c = sl * kSlab + lane;
+    int tot;
+    const int r = wave_rank(valid[j], &tot);
+    if (valid[j]) {
+      const int off = S.base + S.slab_off[sl] + r;
+      if (off < A.chain_cap) {
+        A.cx_out[off] = x0 + c;
+        A.clo_out[off] = mlo[j];
+        A.chi_out[off] = mhi[j];
+      } else {
+        atomicMin(&A.info[HP_INFO_STATUS], HP_ECAPACITY);
       }
     }
   }
   __syncthreads();
+  // the slab-hull vertices in x order per side (every wave scans the counts)
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    const int cn = S.cnt[side][lane];
+    int incl = cn;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const int o = __shfl_up(incl, d, kWave);
+      if (lane >= d) incl += o;
+    }
+    const int excl = incl - cn;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int sl = wave + j * kNodeWaves;
+      const int o = __builtin_amdgcn_readlane(excl, sl), m = __builtin_amdgcn_readlane(cn, sl);
+      if (lane < m) S.vidx[side][o + lane] = (uint16_t)(sl * kSlab + lane);
+    }
+    if (wave == 0 && lane == kWave - 1) S.tot[side] = incl;
+  }
+  __syncthreads();
 
-  // ---- 4. node merge: 16 lanes per vertex, slabs gl, gl + 16, ... each ----
+  // ---- 5. node merge: 16 lanes per vertex, slabs gl, gl + 16, ... each ----
   {
     const int gl = tid & (kNodeGroup - 1), grp = tid / kNodeGroup;
     const int t0 = S.tot[0], all = t0 + S.tot[1];
     for (int q = grp; q < all; q += kNodeBlock / kNodeGroup) {
       const int side = q < t0 ? 0 : 1, idx = side ? q - t0 : q;
-      const int2 *H = S.hp[side];
-      const int2 v = H[idx];
-      const int i = S.hslab[side][idx];
+      const int2 *Hs = S.hp[side];
+      const int at = S.vidx[side][idx];
+      const int2 v = Hs[at];
+      const int i = at >> 6, k = at & (kSlab - 1);
       int2 uL = v, wR = v;
       bool hasL = false, hasR = false;
 #pragma unroll
       for (int r = 0; r < kFanIn / kNodeGroup; ++r) {
         const int jsl = gl + r * kNodeGroup;
-        const int m = S.cnt[side][jsl], o = S.hoff[side][jsl];
+        const int m = S.cnt[side][jsl];
         if (m == 0) continue;
+        const int2 *H = Hs + jsl * kSlab;
         if (jsl == i) {
           // the vertex's own slab hull: its neighbours there
-          if (idx > o) {
-            const int2 u = H[idx - 1];
-            if (!hasL || steeper_left<SMALL>(u, uL, v)) { uL = u; hasL = true; }
+          if (k > 0) {
+            const int2 u = H[k - 1];
+            if (!hasL || nsteeper_left<SMALL>(u, uL, v)) { uL = u; hasL = true; }
           }
-          if (idx + 1 < o + m) {
-            const int2 w = H[idx + 1];
-            if (!hasR || flatter_right<SMALL>(w, wR, v)) { wR = w; hasR = true; }
+          if (k + 1 < m) {
+            const int2 w = H[k + 1];
+            if (!hasR || nflatter_right<SMALL>(w, wR, v)) { wR = w; hasR = true; }
           }
-        } else if (jsl < i) {
-          // tangent from v to a hull on its left: the first vertex whose
-          // next edge does not turn left towards v
-          int lo = 0, hi = m - 1;
-          while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (ncross_pos<SMALL>(H[o + mid], H[o + mid + 1], v)) lo = mid + 1;
-            else hi = mid;
-          }
-          const int2 u = H[o + lo];
-          if (!hasL || steeper_left<SMALL>(u, uL, v)) { uL = u; hasL = true; }
         } else {
-          // tangent from v to a hull on its right: the first vertex whose
-          // next edge does not turn right towards v
+          // tangent from v: on a hull to its left the first vertex whose next
+          // edge does not turn left towards v, on a hull to its right the
+          // first whose next edge does not turn right
+          const bool left = jsl < i;
           int lo = 0, hi = m - 1;
           while (lo < hi) {
             const int mid = (lo + hi) >> 1;
-            if (ncross_neg<SMALL>(H[o + mid], H[o + mid + 1], v)) lo = mid + 1;
+            const bool go = left ? ncross_pos<SMALL>(H[mid], H[mid + 1], v) : ncross_neg<SMALL>(H[mid], H[mid + 1], v);
+            if (go) lo = mid + 1;
             else hi = mid;
           }
-          const int2 w = H[o + lo];
-          if (!hasR || flatter_right<SMALL>(w, wR, v)) { wR = w; hasR = true; }
+          const int2 t = H[lo];
+          if (left) {
+            if (!hasL || nsteeper_left<SMALL>(t, uL, v)) { uL = t; hasL = true; }
+          } else {
+            if (!hasR || nflatter_right<SMALL>(t, wR, v)) { wR = t; hasR = true; }
+          }
         }
       }
 #pragma unroll
@@ -1962,25 +2016,25 @@ __global__ __launch_bounds__(kNodeBlock) void k_node_finish(FinishArgs A, int2 *
         const int2 ow = make_int2(__shfl_xor(wR.x, d, kNodeGroup), __shfl_xor(wR.y, d, kNodeGroup));
         const bool ohL = __shfl_xor((int)hasL, d, kNodeGroup) != 0;
         const bool ohR = __shfl_xor((int)hasR, d, kNodeGroup) != 0;
-        if (ohL && (!hasL || steeper_left<SMALL>(ou, uL, v))) { uL = ou; hasL = true; }
-        if (ohR && (!hasR || flatter_right<SMALL>(ow, wR, v))) { wR = ow; hasR = true; }
+        if (ohL && (!hasL || nsteeper_left<SMALL>(ou, uL, v))) { uL = ou; hasL = true; }
+        if (ohR && (!hasR || nflatter_right<SMALL>(ow, wR, v))) { wR = ow; hasR = true; }
       }
-      if (gl == 0) S.keep[side][idx] = (!hasL || !hasR || cross_pos<SMALL>(uL, v, wR)) ? 1 : 0;
+      if (gl == 0) S.keep[side][idx] = (!hasL || !hasR || ncross_pos<SMALL>(uL, v, wR)) ? 1 : 0;
     }
   }
   __syncthreads();
 
-  // ---- 5. the node's hull per side (waves 0 and 1) ------------------------
+  // ---- 6. the node's hull per side (waves 0 and 1) ------------------------
   if (wave < 2) {
     const int side = wave, m = S.tot[side];
     int2 *dst = l2_out + (size_t)side * A.positions + (size_t)g * kNodeCols;
     int n = 0;
     for (int j0 = 0; j0 < m; j0 += kWave) {
       const int j = j0 + lane;
-      const bool k = j < m && S.keep[side][j] != 0;
+      const bool kp = j < m && S.keep[side][j] != 0;
       int tot;
-      const int r = wave_rank(k, &tot);
-      if (k) dst[n + r] = S.hp[side][j];
+      const int r = wave_rank(kp, &tot);
+      if (kp) dst[n + r] = S.hp[side][S.vidx[side][j]];
       n += tot;
     }
     if (lane == 0) ccount[side * T.nodes + T.base[2] + g] = n;
@@ -2518,6 +2572,9 @@ static void hull_buffers(HullArgs &H, const TreeShape &T, int64_t positions, cha
   H.positions = (int32_t)positions;
 }
 
+constexpr int kHullTestWgs = 256;   // test workgroups per node level, about
+constexpr int kHullMaxSplit = 64;   // test workgroups per child, at most
+
 static hipError_t launch_hull_levels(const TreeShape &T, int64_t positions, char *w, const Layout &Y,
                                      HullArgs H, bool small, hipStream_t s, bool l2path = false,
                                      bool l2_done = false) {
@@ -2555,8 +2612,10 @@ static hipError_t launch_hull_levels(const TreeShape &T, int64_t positions, char
     first = 3;
   }
   for (int lev = first; lev <= T.nlev; ++lev) {
-    // slab children get kSplitSlab test workgroups each, node children kSplit
-    H.split = lev == 2 ? kSplitSlab : kSplit;
+    // slab children get kSplitSlab test workgroups each; node children
+    // enough for about kHullTestWgs in all (each stages every sibling's hull)
+    H.split = lev == 2 ? kSplitSlab
+                       : std::max(1, std::min(kHullMaxSplit, kHullTestWgs / std::max(1, T.size[lev - 1])));
     const dim3 gt(T.size[lev - 1] * H.split), gc(T.size[lev]);
     if (small) {
       hipLaunchKernelGGL((k_hull_test<true>), gt, dim3(kHullBlock), 0, s, H, lev);
