@@ -718,6 +718,7 @@ __global__ __launch_bounds__(kFinBlock) void k_slab_scan(FinishArgs A) {
 constexpr int kHullBlock = 1024;
 constexpr int kWaves = kHullBlock / kWave;      // candidates per round
 constexpr int kStage = 4096;                    // sibling vertices per side in LDS
+constexpr int kTestLanes = 16;                  // lanes per tested vertex, at most
 
 // Copy `total` pairs laid out as nseg segments (segment t: cnt[t] pairs at
 // src + seg_pos(t)) into dst[0..total), where cs[t] is the prefix of cnt.
@@ -865,15 +866,15 @@ __device__ __forceinline__ void hull_test_body(const HullArgs &H, HullShared &S,
 
   // this workgroup's share of the child's vertices: index q runs over the
   // lower side then the upper side; `width` lanes per vertex (the sibling
-  // count rounded up to a power of two), lane t of a vertex's group taking
-  // sibling t
+  // count rounded up to a power of two, at most kTestLanes), lane t of a
+  // vertex's group taking siblings t, t + width, ...
   const int n0 = S.cc[0][j], n1 = S.cc[1][j];
   const int nq = n0 + n1;
   uint8_t *keep = H.keep + (size_t)c * span_c * 2;
   int width = 1;
-  while (width < nsib) width <<= 1;
+  while (width < nsib && width < kTestLanes) width <<= 1;
   const int per_wave = kWave / width;
-  const int t = lane & (width - 1);
+  const int t0 = lane & (width - 1);
   for (int q0 = (part * kWaves + wave) * per_wave; q0 < nq; q0 += H.split * kWaves * per_wave) {
     const int q = q0 + lane / width;
     const bool on = q < nq;
@@ -884,16 +885,26 @@ __device__ __forceinline__ void hull_test_body(const HullArgs &H, HullShared &S,
     const int2 v = on ? own[r] : make_int2(0, 0);
     int2 uL = v, wR = v;
     bool hasL = false, hasR = false;
-    if (on && t == j) {
-      if (r > 0) { uL = own[r - 1]; hasL = true; }
-      if (r + 1 < cc[j]) { wR = own[r + 1]; hasR = true; }
-    } else if (on && t < nsib && cc[t] > 0) {
-      const int2 *a = child_ptr(side, t);
-      if (t < j) { uL = a[tangent_left<SMALL>(a, cc[t], v)]; hasL = true; }
-      else { wR = a[tangent_right<SMALL>(a, cc[t], v)]; hasR = true; }
+    for (int t = t0; on && t < nsib; t += width) {
+      int2 u = v, w = v;
+      bool hu = false, hw = false;
+      if (t == j) {
+        if (r > 0) { u = own[r - 1]; hu = true; }
+        if (r + 1 < cc[j]) { w = own[r + 1]; hw = true; }
+      } else if (cc[t] > 0) {
+        const int2 *a = child_ptr(side, t);
+        if (t < j) { u = a[tangent_left<SMALL>(a, cc[t], v)]; hu = true; }
+        else { w = a[tangent_right<SMALL>(a, cc[t], v)]; hw = true; }
+      }
+      const bool tL = hu & (!hasL | steeper_left<SMALL>(u, uL, v));
+      const bool tR = hw & (!hasR | flatter_right<SMALL>(w, wR, v));
+      uL = tL ? u : uL;
+      hasL |= tL;
+      wR = tR ? w : wR;
+      hasR |= tR;
     }
     const bool k = wave_extremes_keep<SMALL>(v, uL, hasL, wR, hasR, width);
-    if (on && t == 0) keep[q] = k ? 1 : 0;
+    if (on && t0 == 0) keep[q] = k ? 1 : 0;
   }
 }
 
@@ -2572,7 +2583,7 @@ static void hull_buffers(HullArgs &H, const TreeShape &T, int64_t positions, cha
   H.positions = (int32_t)positions;
 }
 
-constexpr int kHullTestWgs = 256;   // test workgroups per node level, about
+constexpr int kHullTestWgs = 1024;  // test workgroups per node level, about
 constexpr int kHullMaxSplit = 64;   // test workgroups per child, at most
 
 static hipError_t launch_hull_levels(const TreeShape &T, int64_t positions, char *w, const Layout &Y,
