@@ -111,6 +111,14 @@ extern "C" {
                                        Needs the full hp_workspace_bytes(n, p)
                                        (about 4n bytes more); with less, the
                                        sampled or device-L strategy runs     */
+#define HP_STRATEGY_SPARSE       7  /* n * 8 < p (the automatic choice): M and a
+                                       summary bit per M word are built from
+                                       the points, the occupied columns are
+                                       listed through the summary and the
+                                       points folded into their chain entries
+                                       with device atomics; the work is in n,
+                                       the occupied columns and p/64 words,
+                                       and L is written only as the export   */
 
 /* Steps 1 and 2 of the proposed heuristic (the bounding box, then the
  * translation that puts the points in [1, p]^2), on the device.
@@ -269,7 +277,7 @@ int32_t hp_lds_max_p(void);
 
 /* Force a strategy for later calls on this process (HP_STRATEGY_*), e.g. for
  * tests; HP_STRATEGY_AUTO restores the tuned choice.  Also settable with the
- * environment variable HP_FORCE_STRATEGY=lds|global|lds_partial|window|sampled|binned.
+ * environment variable HP_FORCE_STRATEGY=lds|global|lds_partial|window|sampled|binned|sparse.
  * Other environment variables, read once per process: HP_TUNING_FILE (a
  * tuning table to load instead of the one beside the library), HP_DYN_OFF=1
  * (no chunk sharing in the reduce), HP_DYN_STATIC8 (static share of a

@@ -18,6 +18,7 @@ HP_INFO_STATUS, HP_INFO_K, HP_INFO_S, HP_INFO_H, HP_INFO_WORDS = 0, 1, 2, 3, 4
 HP_STRATEGY_AUTO, HP_STRATEGY_LDS, HP_STRATEGY_GLOBAL, HP_STRATEGY_LDS_PARTIAL, HP_STRATEGY_WINDOW = 0, 1, 2, 3, 4
 HP_STRATEGY_SAMPLED = 5
 HP_STRATEGY_BINNED = 6
+HP_STRATEGY_SPARSE = 7
 HP_NOALLOC_SCRATCH_BYTES = 128 << 20
 
 # every entry point the header declares, with (restype, argtypes)

@@ -60,6 +60,7 @@ int forced_strategy() {
       else if (!strcmp(e, "window")) g_forced = HP_STRATEGY_WINDOW;
       else if (!strcmp(e, "sampled")) g_forced = HP_STRATEGY_SAMPLED;
       else if (!strcmp(e, "binned")) g_forced = HP_STRATEGY_BINNED;
+      else if (!strcmp(e, "sparse")) g_forced = HP_STRATEGY_SPARSE;
     }
   }
   return g_forced;
@@ -263,7 +264,7 @@ extern "C" int hp_abi_version(void) { return HP_ABI_VERSION; }
 extern "C" int32_t hp_lds_max_p(void) { return (int32_t)device_info().lds_max_p; }
 
 extern "C" int hp_set_strategy(int strategy) {
-  if (strategy < HP_STRATEGY_AUTO || strategy > HP_STRATEGY_BINNED)
+  if (strategy < HP_STRATEGY_AUTO || strategy > HP_STRATEGY_SPARSE)
     return set_error(HP_EINVAL, "unknown strategy %d", strategy);
   forced_strategy();
   std::lock_guard<std::mutex> lk(g_mu);
@@ -272,7 +273,7 @@ extern "C" int hp_set_strategy(int strategy) {
 }
 
 extern "C" int hp_tune_set(int32_t strategy, int32_t block, int32_t vpt, int32_t grid) {
-  if (strategy < 0 || strategy > HP_STRATEGY_BINNED)
+  if (strategy < 0 || strategy > HP_STRATEGY_BINNED)   // the sparse path has fixed launch shapes
     return set_error(HP_EINVAL, "unknown strategy %d", strategy);
   const bool ok_shape = (block == 0 && vpt == 0) ||
                         ((block == 256 || block == 512 || block == 1024) && (vpt == 2 || vpt == 4 || vpt == 8));

@@ -2053,6 +2053,181 @@ __global__ __launch_bounds__(kNodeBlock) void k_node_finish(FinishArgs A, int2 *
 }
 
 // ---------------------------------------------------------------------------
+// Sparse clouds (n well below p): the path visits only the occupied columns
+// (Proposed heuristic, quick analysis: unused entries are skipped when
+// p > n; Discussion, extraction with a w-ary tree of bits, w = 64).
+//  1. M (one bit per column) and its summary level (one bit per M word)
+//     cleared: ceil(p/64) + ceil(p/4096) words
+//  2. every point sets its column's bit; the point whose OR found its M
+//     word empty sets the word's summary bit
+//  3. per summary word, the occupied columns under it (one wave per summary
+//     word, reading only the M words its bits name); their scan
+//  4. the chain positions: every occupied column in x order, with (lo, hi)
+//     at the sentinel, and per occupied M word the chain index of its first
+//     column
+//  5. every point folds its y into its column's chain entry (device atomics;
+//     the index is the word's first index plus the bits below it)
+//  6. s, and the L export when asked for
+// ---------------------------------------------------------------------------
+constexpr int kSparseRatio = 8;     // n * kSparseRatio < p: the automatic choice takes the sparse path
+constexpr int kSparseBlock = 256;
+constexpr int kSparseScan = 1024;
+
+__global__ void k_sp_clear(uint64_t *__restrict__ L0, int64_t W0, uint64_t *__restrict__ L1, int64_t W1,
+                           int32_t *__restrict__ info) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t i = i0; i < W0; i += stride) L0[i] = 0;
+  for (int64_t i = i0; i < W1; i += stride) L1[i] = 0;
+  if (i0 == 0) {
+    info[HP_INFO_STATUS] = HP_OK;
+    info[HP_INFO_K] = 0;
+    info[HP_INFO_S] = 0;
+    info[HP_INFO_H] = 0;
+  }
+}
+
+__global__ __launch_bounds__(kSparseBlock) void k_sp_mark(const int2 *__restrict__ pts, int64_t n, int32_t p,
+                                                          int2 org, uint64_t *__restrict__ L0,
+                                                          uint64_t *__restrict__ L1, int32_t *__restrict__ info) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const int2 q = pts[i];
+    const unsigned xi = (unsigned)(shift_by(q.x, org.x) - 1), yi = (unsigned)(shift_by(q.y, org.y) - 1);
+    if (xi >= (unsigned)p || yi >= (unsigned)p) {
+      bad = true;
+      continue;
+    }
+    const unsigned long long old = atomicOr((unsigned long long *)&L0[xi >> 6], 1ull << (xi & 63));
+    if (old == 0) atomicOr((unsigned long long *)&L1[xi >> 12], 1ull << ((xi >> 6) & 63));
+  }
+  if (bad) atomicMin(&info[HP_INFO_STATUS], HP_ERANGE);
+}
+
+// One wave per summary word: the occupied columns of its M words.
+__global__ __launch_bounds__(kSparseBlock) void k_sp_count(const uint64_t *__restrict__ L0,
+                                                           const uint64_t *__restrict__ L1, int64_t W1,
+                                                           int32_t *__restrict__ cnt1) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t i = (int64_t)blockIdx.x * (kSparseBlock / kWave) + threadIdx.x / kWave;
+  if (i >= W1) return;
+  const uint64_t s1 = L1[i];
+  int c = ((s1 >> lane) & 1ull) ? __popcll(L0[i * kWave + lane]) : 0;
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) c += __shfl_xor(c, d, kWave);
+  if (lane == 0) cnt1[i] = c;
+}
+
+// One workgroup: exclusive offsets of the summary words' counts; k.
+__global__ __launch_bounds__(kSparseScan) void k_sp_scan(const int32_t *__restrict__ cnt1, int64_t W1,
+                                                         int32_t *__restrict__ off1, int32_t chain_cap,
+                                                         int32_t *__restrict__ info) {
+  __shared__ int32_t s_sum[kSparseScan];
+  const int64_t per = (W1 + kSparseScan - 1) / kSparseScan;
+  const int64_t b0 = (int64_t)threadIdx.x * per, b1 = b0 + per < W1 ? b0 + per : W1;
+  int32_t mine = 0;
+  for (int64_t b = b0; b < b1; ++b) mine += cnt1[b];
+  s_sum[threadIdx.x] = mine;
+  __syncthreads();
+  for (int d = 1; d < kSparseScan; d <<= 1) {
+    const int32_t add = threadIdx.x >= (unsigned)d ? s_sum[threadIdx.x - d] : 0;
+    __syncthreads();
+    s_sum[threadIdx.x] += add;
+    __syncthreads();
+  }
+  int32_t run = s_sum[threadIdx.x] - mine;
+  for (int64_t b = b0; b < b1; ++b) {
+    off1[b] = run;
+    run += cnt1[b];
+  }
+  if (threadIdx.x == kSparseScan - 1) {
+    const int32_t k = s_sum[threadIdx.x];
+    info[HP_INFO_K] = k;
+    if (k > chain_cap) atomicMin(&info[HP_INFO_STATUS], HP_ECAPACITY);
+  }
+}
+
+// One wave per summary word: its occupied columns in x order into the chain,
+// (lo, hi) at the sentinel, and each occupied M word's first chain index.
+__global__ __launch_bounds__(kSparseBlock) void k_sp_write(const uint64_t *__restrict__ L0,
+                                                           const uint64_t *__restrict__ L1, int64_t W1,
+                                                           const int32_t *__restrict__ off1,
+                                                           int32_t *__restrict__ wordbase, int32_t *__restrict__ cx,
+                                                           int32_t *__restrict__ clo, int32_t *__restrict__ chi,
+                                                           int32_t chain_cap, int32_t p) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t i = (int64_t)blockIdx.x * (kSparseBlock / kWave) + threadIdx.x / kWave;
+  if (i >= W1) return;
+  const uint64_t s1 = L1[i];
+  const int64_t w = i * kWave + lane;
+  uint64_t v = ((s1 >> lane) & 1ull) ? L0[w] : 0ull;
+  const int c = __popcll(v);
+  int incl = c;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int o = __shfl_up(incl, d, kWave);
+    if (lane >= d) incl += o;
+  }
+  int j = off1[i] + incl - c;
+  if (v) wordbase[w] = j;
+  for (; v; v &= v - 1, ++j) {
+    if (j >= chain_cap) continue;
+    cx[j] = (int32_t)(w * kWave + __builtin_ctzll(v) + 1);
+    clo[j] = p + 1;
+    chi[j] = -1;
+  }
+}
+
+__global__ __launch_bounds__(kSparseBlock) void k_sp_fold(const int2 *__restrict__ pts, int64_t n, int32_t p,
+                                                          int2 org, const uint64_t *__restrict__ L0,
+                                                          const int32_t *__restrict__ wordbase,
+                                                          int32_t *__restrict__ clo, int32_t *__restrict__ chi,
+                                                          int32_t chain_cap) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const int2 q = pts[i];
+    const int y = shift_by(q.y, org.y);
+    const unsigned xi = (unsigned)(shift_by(q.x, org.x) - 1), yi = (unsigned)(y - 1);
+    if (xi >= (unsigned)p || yi >= (unsigned)p) continue;
+    const int idx = wordbase[xi >> 6] + __popcll(L0[xi >> 6] & ((1ull << (xi & 63)) - 1ull));
+    if (idx >= chain_cap) continue;
+    atomicMin(&clo[idx], y);
+    atomicMax(&chi[idx], y);
+  }
+}
+
+__global__ void k_sp_fill(int32_t *__restrict__ lo, int32_t *__restrict__ hi, int32_t p) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < p; i += stride) {
+    lo[i] = p + 1;
+    hi[i] = -1;
+  }
+}
+
+// s (a column with lo < hi gives two chain points) and the L export.
+__global__ __launch_bounds__(kSparseBlock) void k_sp_tail(const int32_t *__restrict__ cx,
+                                                          const int32_t *__restrict__ clo,
+                                                          const int32_t *__restrict__ chi, int32_t chain_cap,
+                                                          int32_t *__restrict__ lo, int32_t *__restrict__ hi,
+                                                          int32_t *__restrict__ info) {
+  const int k = min(info[HP_INFO_K], chain_cap);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int s = 0;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < k; j += stride) {
+    const int a = clo[j], b = chi[j];
+    s += 1 + (a < b ? 1 : 0);
+    if (lo) {
+      lo[cx[j] - 1] = a;
+      hi[cx[j] - 1] = b;
+    }
+  }
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) s += __shfl_xor(s, d, kWave);
+  if ((threadIdx.x & (kWave - 1)) == 0 && s) atomicAdd(&info[HP_INFO_S], s);
+}
+
+// ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
 static TreeShape make_tree(int64_t positions) {
@@ -2278,7 +2453,16 @@ static Plan1 choose(int64_t n, int32_t p, bool allow_binned = true) {
   const DeviceInfo &D = device_info();
   Plan1 P;
   int s = forced_strategy();
-  if (s == HP_STRATEGY_AUTO) s = tuned_strategy(n, p);
+  if (s == HP_STRATEGY_AUTO) s = n * kSparseRatio < (int64_t)p ? HP_STRATEGY_SPARSE : tuned_strategy(n, p);
+  if (s == HP_STRATEGY_SPARSE) {
+    P.strategy = s;
+    P.block = kSparseBlock;
+    P.vpt = 1;
+    P.G = 1;
+    P.W = 1;
+    P.wc = p;
+    return P;
+  }
   if (s == HP_STRATEGY_BINNED && ((int64_t)p > kBinPMax || !allow_binned)) s = HP_STRATEGY_SAMPLED;
   if (s == HP_STRATEGY_SAMPLED && n < kSampledMinPerCol * (int64_t)p) s = HP_STRATEGY_GLOBAL;
   P.W = 1;
@@ -2353,7 +2537,33 @@ static int64_t lds_grid_max() { return (int64_t)device_info().cus * 4; }
 // override may use, so that a later strategy change still fits the same
 // workspace; with_bins adds the binned reduce's pages (for p <= kBinPMax),
 // without them a plan that would bin falls back (see choose).
+// The sparse path's workspace: the hull of a chain of min(n, p) positions,
+// then M (used when the caller gives no M export), its summary level, the
+// summary counts and offsets, and a first chain index per M word.
+struct SparseLayout {
+  int32_t hpos;
+  TreeShape T;
+  Layout Yh;
+  size_t L0, L1, cnt1, off1, wordbase, total;
+};
+static SparseLayout sparse_layout(int64_t n, int32_t p) {
+  SparseLayout Z;
+  Z.hpos = (int32_t)std::max<int64_t>(1, std::min<int64_t>(n, p));
+  Z.T = make_tree(Z.hpos);
+  Z.Yh = make_layout(Z.hpos, 0, 0, Z.T);
+  const int64_t W0 = ((int64_t)p + 63) / 64, W1 = (W0 + 63) / 64;
+  size_t o = Z.Yh.total;
+  Z.L0 = o;       o = align_up(o + sizeof(uint64_t) * (size_t)W0);
+  Z.L1 = o;       o = align_up(o + sizeof(uint64_t) * (size_t)W1);
+  Z.cnt1 = o;     o = align_up(o + sizeof(int32_t) * (size_t)W1);
+  Z.off1 = o;     o = align_up(o + sizeof(int32_t) * (size_t)W1);
+  Z.wordbase = o; o = align_up(o + sizeof(int32_t) * (size_t)W0);
+  Z.total = o;
+  return Z;
+}
+
 static size_t ws_bytes_for(int64_t n, int32_t p, bool with_bins = true) {
+  const size_t sparse = sparse_layout(n, p).total;
   const TreeShape T = make_tree(p);
   const int64_t lds_max = device_info().lds_max_p;
   int64_t part = 0;
@@ -2368,7 +2578,7 @@ static size_t ws_bytes_for(int64_t n, int32_t p, bool with_bins = true) {
     part = std::max<int64_t>(part, (int64_t)bin_partials(B) * p);
     bins = bin_layout(B).total;
   }
-  return make_layout(p, p, part, T, bins).total;
+  return std::max(sparse, make_layout(p, p, part, T, bins).total);
 }
 
 template <typename K, typename... Args>
@@ -2641,6 +2851,52 @@ static hipError_t launch_hull_levels(const TreeShape &T, int64_t positions, char
   return hipSuccess;
 }
 
+static int hull_of_chain(const int32_t *cx, const int32_t *clo, const int32_t *chi, int32_t positions,
+                         int32_t *hx, int32_t *hy, int32_t hull_cap, int32_t *info, char *w, const Layout &Y,
+                         const TreeShape &T, hipStream_t s);
+
+// The sparse path (HP_STRATEGY_SPARSE): work in the points and the occupied
+// columns, plus ceil(p/64) words of M; L is written only as the export.
+static int run_sparse(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *hi, uint64_t *mask,
+                      int32_t *cx, int32_t *clo, int32_t *chi, int32_t chain_cap, int32_t *hx, int32_t *hy,
+                      int32_t hull_cap, int32_t *info, char *w, size_t ws_bytes, hipStream_t s, bool do_hull,
+                      int2 org) {
+  const SparseLayout Z = sparse_layout(n, p);
+  if (ws_bytes < Z.total) return set_error(HP_ECAPACITY, "workspace too small: %zu < %zu bytes", ws_bytes, Z.total);
+  const int64_t W0 = ((int64_t)p + 63) / 64, W1 = (W0 + 63) / 64;
+  uint64_t *L0 = mask ? mask : reinterpret_cast<uint64_t *>(w + Z.L0);
+  uint64_t *L1 = reinterpret_cast<uint64_t *>(w + Z.L1);
+  int32_t *cnt1 = reinterpret_cast<int32_t *>(w + Z.cnt1);
+  int32_t *off1 = reinterpret_cast<int32_t *>(w + Z.off1);
+  int32_t *wordbase = reinterpret_cast<int32_t *>(w + Z.wordbase);
+  const int cus = device_info().cus;
+  const int gw = (int)std::max<int64_t>(1, std::min<int64_t>(4 * cus, (W0 + kSparseBlock - 1) / kSparseBlock));
+  const int gp = (int)std::max<int64_t>(1, std::min<int64_t>(8 * cus, (n + kSparseBlock - 1) / kSparseBlock));
+  const int gs = (int)((W1 + kSparseBlock / kWave - 1) / (kSparseBlock / kWave));
+  const int2 *P2 = reinterpret_cast<const int2 *>(pts);
+  hipLaunchKernelGGL(k_sp_clear, dim3(gw), dim3(kSparseBlock), 0, s, L0, W0, L1, W1, info);
+  if (n > 0) hipLaunchKernelGGL(k_sp_mark, dim3(gp), dim3(kSparseBlock), 0, s, P2, n, p, org, L0, L1, info);
+  hipLaunchKernelGGL(k_sp_count, dim3(gs), dim3(kSparseBlock), 0, s, (const uint64_t *)L0, (const uint64_t *)L1,
+                     W1, cnt1);
+  hipLaunchKernelGGL(k_sp_scan, dim3(1), dim3(kSparseScan), 0, s, (const int32_t *)cnt1, W1, off1, chain_cap, info);
+  hipLaunchKernelGGL(k_sp_write, dim3(gs), dim3(kSparseBlock), 0, s, (const uint64_t *)L0, (const uint64_t *)L1, W1,
+                     (const int32_t *)off1, wordbase, cx, clo, chi, chain_cap, p);
+  if (n > 0)
+    hipLaunchKernelGGL(k_sp_fold, dim3(gp), dim3(kSparseBlock), 0, s, P2, n, p, org, (const uint64_t *)L0,
+                       (const int32_t *)wordbase, clo, chi, chain_cap);
+  if (lo) {
+    const int gl = (int)std::max<int64_t>(1, std::min<int64_t>(8 * cus, ((int64_t)p + kSparseBlock - 1) / kSparseBlock));
+    hipLaunchKernelGGL(k_sp_fill, dim3(gl), dim3(kSparseBlock), 0, s, lo, hi, p);
+  }
+  const int gk = (int)std::max<int64_t>(1, std::min<int64_t>(4 * cus, ((int64_t)Z.hpos + kSparseBlock - 1) / kSparseBlock));
+  hipLaunchKernelGGL(k_sp_tail, dim3(gk), dim3(kSparseBlock), 0, s, (const int32_t *)cx, (const int32_t *)clo,
+                     (const int32_t *)chi, chain_cap, lo, hi, info);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_error(HP_EDEVICE, "sparse path launch: %s", hipGetErrorString(e));
+  if (!do_hull) return HP_OK;
+  return hull_of_chain(cx, clo, chi, Z.hpos, hx, hy, hull_cap, info, w, Z.Yh, Z.T, s);
+}
+
 // Enqueue the whole single-cloud sequence.  Shared by hp_precondition,
 // hp_run and the per-cloud baseline of the batched form.
 int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *hi, uint64_t *mask,
@@ -2648,8 +2904,11 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
                int32_t hull_cap, int32_t *info, void *ws, size_t ws_bytes, hipStream_t s,
                bool do_hull, int32_t ox, int32_t oy) {
   const int2 org = make_int2(ox, oy);
-  const TreeShape T = make_tree(p);
   Plan1 P = choose(n, p);
+  if (P.strategy == HP_STRATEGY_SPARSE)   // the callers have checked the arguments
+    return run_sparse(pts, n, p, lo, hi, mask, cx, clo, chi, chain_cap, hx, hy, hull_cap, info,
+                      static_cast<char *>(ws), ws_bytes, s, do_hull, org);
+  const TreeShape T = make_tree(p);
   if (P.strategy == HP_STRATEGY_BINNED &&
       ws_bytes < make_layout(p, p, part_pairs_for(P, n, p), T, bins_bytes_for(P, n, p)).total)
     P = choose(n, p, false);   // a workspace without room for the bins
@@ -2968,19 +3227,13 @@ extern "C" int hp_hull_workspace_bytes(int32_t chain_cap, size_t *bytes) {
   return HP_OK;
 }
 
-extern "C" int hp_hull(const int32_t *cx, const int32_t *clo, const int32_t *chi, int32_t chain_cap,
-                       int32_t *hx, int32_t *hy, int32_t hull_cap, int32_t *info, void *ws,
-                       size_t ws_bytes, void *stream) {
-  if (chain_cap < 0 || chain_cap > HP_P_MAX) return set_error(HP_EINVAL, "chain_cap outside [0, %d]", HP_P_MAX);
-  if (chain_cap > 0 && (!cx || !clo || !chi)) return set_error(HP_EINVAL, "chain arrays must not be NULL");
-  if (!hx || !hy || !info || !ws) return set_error(HP_EINVAL, "NULL output, info or workspace");
-  if ((int64_t)hull_cap < 2 * (int64_t)chain_cap)
-    return set_error(HP_ECAPACITY, "hull_cap %d < 2 chain_cap", hull_cap);
-  const TreeShape T = make_tree(chain_cap);
-  const Layout Y = make_layout(chain_cap, 0, 0, T);
-  if (ws_bytes < Y.total) return set_error(HP_ECAPACITY, "workspace too small: %zu < %zu bytes", ws_bytes, Y.total);
-  hipStream_t s = (hipStream_t)stream;
-  char *w = static_cast<char *>(ws);
+namespace hp {
+
+// Step 4 on a chain of `positions` entries whose length is read on the
+// device: the slab finish from the chain, then the hull levels.
+static int hull_of_chain(const int32_t *cx, const int32_t *clo, const int32_t *chi, int32_t positions,
+                         int32_t *hx, int32_t *hy, int32_t hull_cap, int32_t *info, char *w, const Layout &Y,
+                         const TreeShape &T, hipStream_t s) {
   int32_t *ctl = reinterpret_cast<int32_t *>(w + Y.ctl);
   int32_t *tree = reinterpret_cast<int32_t *>(w + Y.tree);
   hipLaunchKernelGGL(k_init, dim3(std::max(1, std::min(1024, (T.nodes + 255) / 256))), dim3(256), 0, s,
@@ -2992,7 +3245,7 @@ extern "C" int hp_hull(const int32_t *cx, const int32_t *clo, const int32_t *chi
   A.cx = cx;
   A.clo = clo;
   A.chi = chi;
-  A.positions = chain_cap;
+  A.positions = positions;
   A.do_hull = 1;
   A.cand = reinterpret_cast<int2 *>(w + Y.cand);
   A.ccount = reinterpret_cast<int32_t *>(w + Y.ccount);
@@ -3004,7 +3257,7 @@ extern "C" int hp_hull(const int32_t *cx, const int32_t *clo, const int32_t *chi
   A.ctl = ctl;
   A.info = info;
   // many slabs: 256-thread slab workgroups, so the grid stays below 2^32
-  // work-items up to chain_cap = HP_P_MAX
+  // work-items up to positions = HP_P_MAX
   if (T.size[1] > kScanRootMaxSlabs)
     hipLaunchKernelGGL((k_finish<1, false, kFinBlockMany>), dim3(T.size[1]), dim3(kFinBlockMany), 0, s, A);
   else
@@ -3017,9 +3270,26 @@ extern "C" int hp_hull(const int32_t *cx, const int32_t *clo, const int32_t *chi
   H.hy = hy;
   H.hull_cap = hull_cap;
   H.info = info;
-  e = launch_hull_levels(T, chain_cap, w, Y, H, false, s);
+  e = launch_hull_levels(T, positions, w, Y, H, false, s);
   if (e != hipSuccess) return set_error(HP_EDEVICE, "hull level launch: %s", hipGetErrorString(e));
   return HP_OK;
+}
+
+}  // namespace hp
+
+extern "C" int hp_hull(const int32_t *cx, const int32_t *clo, const int32_t *chi, int32_t chain_cap,
+                       int32_t *hx, int32_t *hy, int32_t hull_cap, int32_t *info, void *ws,
+                       size_t ws_bytes, void *stream) {
+  if (chain_cap < 0 || chain_cap > HP_P_MAX) return set_error(HP_EINVAL, "chain_cap outside [0, %d]", HP_P_MAX);
+  if (chain_cap > 0 && (!cx || !clo || !chi)) return set_error(HP_EINVAL, "chain arrays must not be NULL");
+  if (!hx || !hy || !info || !ws) return set_error(HP_EINVAL, "NULL output, info or workspace");
+  if ((int64_t)hull_cap < 2 * (int64_t)chain_cap)
+    return set_error(HP_ECAPACITY, "hull_cap %d < 2 chain_cap", hull_cap);
+  const TreeShape T = make_tree(chain_cap);
+  const Layout Y = make_layout(chain_cap, 0, 0, T);
+  if (ws_bytes < Y.total) return set_error(HP_ECAPACITY, "workspace too small: %zu < %zu bytes", ws_bytes, Y.total);
+  return hull_of_chain(cx, clo, chi, chain_cap, hx, hy, hull_cap, info, static_cast<char *>(ws), Y, T,
+                       (hipStream_t)stream);
 }
 
 extern "C" int hp_bbox_workspace_bytes(size_t *bytes) {

@@ -15,7 +15,8 @@ import torch
 from . import _lib
 from ._lib import (HP_ECAPACITY, HP_EINVAL, HP_INFO_H, HP_INFO_K, HP_INFO_S, HP_INFO_STATUS,  # noqa: F401
                    HP_STRATEGY_AUTO, HP_STRATEGY_GLOBAL, HP_STRATEGY_LDS, HP_STRATEGY_LDS_PARTIAL,
-                   HP_STRATEGY_BINNED, HP_STRATEGY_SAMPLED, HP_STRATEGY_WINDOW, HullprepError)
+                   HP_STRATEGY_BINNED, HP_STRATEGY_SAMPLED, HP_STRATEGY_SPARSE, HP_STRATEGY_WINDOW,
+                   HullprepError)
 
 
 def _ptr(t: torch.Tensor | None) -> int | None:

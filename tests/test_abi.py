@@ -85,8 +85,10 @@ def test_workspace_queries():
 
 def test_strategy_and_tuning_setters():
     lib = _lib.load()
-    assert lib.hp_set_strategy(7) == _lib.HP_EINVAL
+    assert lib.hp_set_strategy(8) == _lib.HP_EINVAL
+    assert lib.hp_set_strategy(_lib.HP_STRATEGY_SPARSE) == 0
     assert lib.hp_set_strategy(0) == 0
+    assert lib.hp_tune_set(_lib.HP_STRATEGY_SPARSE, 256, 4, 10) == _lib.HP_EINVAL
     assert lib.hp_tune_set(1, 300, 4, 10) == _lib.HP_EINVAL
     assert lib.hp_tune_set(1, 256, 4, 10) == 0
     assert lib.hp_tune_set(0, 0, 0, 0) == 0
@@ -332,6 +334,7 @@ def test_reduce_strategy_of_the_tuned_regimes():
     assert pick(1 << 28, 1 << 20) == _lib.HP_STRATEGY_BINNED
     assert pick(1 << 28, 4096) == _lib.HP_STRATEGY_LDS_PARTIAL
     assert pick(10_000_000, 4096) == _lib.HP_STRATEGY_LDS_PARTIAL
-    assert pick(100_000, 1 << 24) == _lib.HP_STRATEGY_GLOBAL     # n < 16 p: no sampled or binned pass
+    assert pick(100_000, 1 << 24) == _lib.HP_STRATEGY_SPARSE     # n * 8 < p: the occupied columns only
+    assert pick((1 << 21) + 1, 1 << 24) == _lib.HP_STRATEGY_GLOBAL   # n < 16 p: no sampled or binned pass
     assert pick(1 << 28, (1 << 20) + 1) != _lib.HP_STRATEGY_BINNED   # windows beyond the binned range
     assert lib.hp_reduce_strategy(10, 0, ctypes.byref(v)) == _lib.HP_EINVAL

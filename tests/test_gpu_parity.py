@@ -90,7 +90,7 @@ def test_gap_example(hp):
 ])
 def test_configs(hp, kind, n, p, seed):
     pts = synth.cloud(kind, n, p, seed)
-    strategies = (1, 2, 3, 4, 5, 6) if p <= hp.lds_max_p() else (2, 4, 5, 6)
+    strategies = (1, 2, 3, 4, 5, 6, 7) if p <= hp.lds_max_p() else (2, 4, 5, 6, 7)
     _run_both(hp, pts, p, f"{kind}-{n}-{p}", strategies)
 
 
@@ -120,7 +120,7 @@ def _edge_cases():
 @pytest.mark.parametrize("name", sorted(_edge_cases()))
 def test_edge_cases(hp, name):
     pts, p = _edge_cases()[name]
-    strategies = (1, 2, 3, 4, 5, 6) if p <= hp.lds_max_p() else (2, 4, 5, 6)
+    strategies = (1, 2, 3, 4, 5, 6, 7) if p <= hp.lds_max_p() else (2, 4, 5, 6, 7)
     _run_both(hp, torch.from_numpy(pts), p, name, strategies)
 
 
@@ -131,7 +131,7 @@ def test_unaligned_start(hp):
     want = _oracle(view_cpu.contiguous().numpy(), 777)
     dev = base.cuda()[1:]
     assert dev.data_ptr() % 16 == 8
-    for s in (1, 2, 3, 4, 5, 6):
+    for s in (1, 2, 3, 4, 5, 6, 7):
         hp.set_strategy(s)
         _compare(hp.run(dev, 777), want, f"unaligned/strategy{s}")
     hp.set_strategy(0)
@@ -141,7 +141,7 @@ def test_out_of_range_reports(hp):
     pts = synth.cloud("uniform", 10_000, 100, 12)
     pts[5000] = torch.tensor([101, 3], dtype=torch.int32)
     pts[17] = torch.tensor([4, 0], dtype=torch.int32)
-    for s in (1, 2, 3, 4, 5, 6):
+    for s in (1, 2, 3, 4, 5, 6, 7):
         hp.set_strategy(s)
         got = hp.run(pts.cuda(), 100)
         assert got["status"] == HP_ERANGE
