@@ -34,7 +34,7 @@ HBM_PEAK_GBS = 8000.0
 # sources of the single-cloud reduce kernel (the counter summary names their hash)
 REDUCE_SOURCES = ["paper_1505_00914_amd/csrc/hp_reduce.h", "paper_1505_00914_amd/csrc/hp_kernels.h",
                   "paper_1505_00914_amd/csrc/hp_device.h", "paper_1505_00914_amd/csrc/hp_binned.h"]
-STRATEGY_NAMES = {1: "lds", 2: "global", 3: "lds_partial", 4: "window", 5: "sampled", 6: "binned"}
+STRATEGY_NAMES = {1: "lds", 2: "global", 3: "lds_partial", 4: "window", 5: "sampled", 6: "binned", 7: "sparse"}
 REDUCE_KERNELS = {
     "binned": "k_bin, k_bin_fold (per round) and k_bin_merge between the rounds: the reduce from the first "
               "kernel's start to the last kernel's end",
@@ -144,7 +144,7 @@ def bench_single(args, torch, hp, synth):
     ms_step = (t1 - t0) * 1e3 / args.steps
     value = n * args.steps / (t1 - t0) / 1e9
     red_ms = tm["total_ms"] / max(1, tm["count"])
-    achieved = 8.0 * n / (red_ms * 1e-3) / 1e9
+    achieved = 8.0 * n / (red_ms * 1e-3) / 1e9 if red_ms > 0 else 0.0
     traffic = committed_traffic(args.workload)
     out = {
         "metric": "Gpoints/s reduce+hull and % HBM peak; batched vs per-cloud speedup; p99 latency",
@@ -215,10 +215,30 @@ def bench_regimes(args, torch, hp, synth) -> list:
               and np.array_equal(got["clo"], want["clo"]) and np.array_equal(got["chi"], want["chi"])
               and np.array_equal(got["hull"], want["hull"]))
         red_ms = tm["total_ms"] / max(1, tm["count"])
-        gbs = 8.0 * n / (red_ms * 1e-3) / 1e9
+        gbs = 8.0 * n / (red_ms * 1e-3) / 1e9 if red_ms > 0 else 0.0
+        strategy = STRATEGY_NAMES.get(hp.reduce_strategy(n, p), "?")
+        extra = {}
+        if strategy == "sparse":
+            # the same cloud through the dense path (a device L of p columns)
+            hp.set_strategy(2)
+            dbuf = hp.Buffers.allocate(n, p, pts.device, export_L=False)
+            for i in range(3):
+                hp.hp_run(copies[i % len(copies)], p, dbuf, stream)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            for i in range(steps):
+                hp.hp_run(copies[i % len(copies)], p, dbuf, stream)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            hp.set_strategy(args.strategy)
+            dg = hp.collect(dbuf)
+            extra = {"dense_ms_per_step": round((t3 - t2) * 1e3 / steps, 5),
+                     "speedup_vs_dense": round((t3 - t2) / (t1 - t0), 2),
+                     "dense_parity_vs_oracle": bool(dg["k"] == want["k"] and np.array_equal(dg["hull"], want["hull"]))}
+            del dbuf
         progress(f"regime {name} done")
-        res.append({"workload": name, "n": n, "p": p, "steps": steps,
-                    "reduce_strategy": STRATEGY_NAMES.get(hp.reduce_strategy(n, p), "?"),
+        res.append({"workload": name, "n": n, "p": p, "steps": steps, **extra,
+                    "reduce_strategy": strategy,
                     "gpoints_per_s": round(n * steps / (t1 - t0) / 1e9, 3),
                     "ms_per_step": round((t1 - t0) * 1e3 / steps, 5),
                     "reduce_ms_avg": round(red_ms, 5), "reduce_gbs": round(gbs, 1),
@@ -836,7 +856,7 @@ def main(argv=None):
     ap.add_argument("--no-auto", action="store_true", help="skip the bounding-box (steps 1 and 2) line")
     ap.add_argument("--no-bits", action="store_true", help="skip the bit array / tree extraction line")
     ap.add_argument("--no-melkman", action="store_true", help="skip the Melkman cross-check line")
-    ap.add_argument("--regimes", default="ellipsoids_10m_p4096,uniform_100k_p1024,gaussian_2p28_p4096",
+    ap.add_argument("--regimes", default="ellipsoids_10m_p4096,uniform_100k_p1024,gaussian_2p28_p4096,uniform_1e5_p2p24",
                     help="other single-cloud workloads timed beside the main one ('' for none)")
     ap.add_argument("--batch-clouds", type=int, default=4096)
     ap.add_argument("--batch-steps", type=int, default=10)

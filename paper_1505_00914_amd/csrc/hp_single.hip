@@ -1609,7 +1609,8 @@ constexpr int kLbSpinMax = 1 << 20;
 constexpr int kMinWin = 8;                      // slabs each way in the hull of the lowest points
 
 struct NodeShared {
-  int2 col[kNodeCols];            // (lo, hi) per column, slab-swizzled
+  int2 col[kNodeCols];            // (lo, hi) per position, slab-swizzled
+  int32_t xs[kNodeCols];          // x per position, slab-swizzled
   int2 hp[2][kNodeCols];          // per slab row of 64: survivors, then the slab hull
   uint16_t vidx[2][kNodeCols];    // slab-hull vertices in x order: their places in hp
   uint8_t keep[2][kNodeCols];     // merge verdicts
@@ -1632,39 +1633,49 @@ struct NodeShared {
 // index so that the lanes of a wave, one row each, fall in different banks.
 __device__ __forceinline__ int node_sw(int t) { return (t & ~(kSlab - 1)) | ((t + (t >> 6)) & (kSlab - 1)); }
 
-__device__ __forceinline__ int2 node_point(const NodeShared &S, int side, int32_t x0, int c) {
+__device__ __forceinline__ int2 node_point(const NodeShared &S, int side, int c) {
   const int2 L = S.col[node_sw(c)];
-  return make_int2(x0 + c, side ? -L.y : L.x);
+  return make_int2(S.xs[node_sw(c)], side ? -L.y : L.x);
 }
 
-// Exact predicates for points of one node: x differences below 2^12 and y
-// differences below 2^31, so every product (below 2^43) and each comparison
-// is exact in double precision.
+// Exact predicates for the points of one node, in one of three forms:
+// kPrecSmall, coordinates below 2^15 (24-bit products); kPrecNode, columns
+// of one node (x differences below 2^12, y differences below 2^31, so every
+// product is below 2^43 and exact in double precision); kPrecWide, any int32
+// coordinates (products in 64-bit integers).
 //   ncross_pos / ncross_neg: cross(o, a, b) > 0 / < 0
 //   nsteeper_left: slope(u1, v) > slope(u2, v), u1 and u2 left of v
 //   nflatter_right: slope(v, w1) < slope(v, w2), w1 and w2 right of v
-template <bool SMALL>
+constexpr int kPrecSmall = 0, kPrecNode = 1, kPrecWide = 2;
+template <int PREC>
 __device__ __forceinline__ bool ncross_pos(int2 o, int2 a, int2 b) {
-  if (SMALL) return cross_pos<true>(o, a, b);
+  if (PREC == kPrecSmall) return cross_pos<true>(o, a, b);
+  if (PREC == kPrecWide) return cross_pos<false>(o, a, b);
   return (double)(a.x - o.x) * (double)(b.y - o.y) > (double)(a.y - o.y) * (double)(b.x - o.x);
 }
-template <bool SMALL>
+template <int PREC>
 __device__ __forceinline__ bool ncross_neg(int2 o, int2 a, int2 b) {
-  if (SMALL) return cross_neg<true>(o, a, b);
+  if (PREC == kPrecSmall) return cross_neg<true>(o, a, b);
+  if (PREC == kPrecWide) return cross_neg<false>(o, a, b);
   return (double)(a.x - o.x) * (double)(b.y - o.y) < (double)(a.y - o.y) * (double)(b.x - o.x);
 }
-template <bool SMALL>
+template <int PREC>
 __device__ __forceinline__ bool nsteeper_left(int2 u1, int2 u2, int2 v) {
-  if (SMALL) return steeper_left<true>(u1, u2, v);
+  if (PREC == kPrecSmall) return steeper_left<true>(u1, u2, v);
+  if (PREC == kPrecWide) return steeper_left<false>(u1, u2, v);
   return (double)(v.y - u1.y) * (double)(v.x - u2.x) > (double)(v.y - u2.y) * (double)(v.x - u1.x);
 }
-template <bool SMALL>
+template <int PREC>
 __device__ __forceinline__ bool nflatter_right(int2 w1, int2 w2, int2 v) {
-  if (SMALL) return flatter_right<true>(w1, w2, v);
+  if (PREC == kPrecSmall) return flatter_right<true>(w1, w2, v);
+  if (PREC == kPrecWide) return flatter_right<false>(w1, w2, v);
   return (double)(w1.y - v.y) * (double)(w2.x - v.x) < (double)(w2.y - v.y) * (double)(w1.x - v.x);
 }
 
-template <bool SMALL>
+// CHAIN: the node's positions are chain entries (x, lo, hi) (A.cx, A.clo,
+// A.chi, the first info[K] of A.positions valid) rather than columns; the
+// chain and the totals are then inputs, and only the hulls are written.
+template <int PREC, bool CHAIN>
 __global__ __launch_bounds__(kNodeBlock) void k_node_finish(FinishArgs A, int2 *__restrict__ l2_out,
                                                             int32_t *__restrict__ ccount) {
   extern __shared__ __align__(16) unsigned char node_smem[];
@@ -1685,9 +1696,19 @@ __global__ __launch_bounds__(kNodeBlock) void k_node_finish(FinishArgs A, int2 *
 
   // ---- 1. fold the partial arrays, four columns per thread (column
   // tid + 1024 j is column `lane` of the node's slab wave + 16 j) ----------
-  int mlo[4], mhi[4];
+  int mlo[4], mhi[4], xv[4];
   bool valid[4];
-  {
+  if (CHAIN) {
+    const int64_t kk = min<int64_t>(A.info[HP_INFO_K], A.positions);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t pos = g0 + tid + j * kNodeBlock;
+      valid[j] = pos < kk;
+      xv[j] = valid[j] ? A.cx[pos] : 0;
+      mlo[j] = valid[j] ? A.clo[pos] : 1;
+      mhi[j] = valid[j] ? A.chi[pos] : 0;
+    }
+  } else {
     int64_t pos[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -1733,19 +1754,26 @@ __global__ __launch_bounds__(kNodeBlock) void k_node_finish(FinishArgs A, int2 *
     for (int j = 0; j < 4; ++j) {
       const bool inside = pos[j] < p;
       valid[j] = inside && mlo[j] <= mhi[j];
+      xv[j] = x0 + tid + j * kNodeBlock;
       if (inside && A.lo) {
         A.lo[pos[j]] = mlo[j];
         A.hi[pos[j]] = mhi[j];
       }
+    }
+  }
+  {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
       const int c = tid + j * kNodeBlock;
       S.col[node_sw(c)] = valid[j] ? make_int2(mlo[j], mhi[j]) : make_int2(1, 0);
+      S.xs[node_sw(c)] = xv[j];
       const unsigned long long vm = __ballot(valid[j]);
       const unsigned long long sm = __ballot(valid[j] && mlo[j] < mhi[j]);
       const int sl = wave + j * kNodeWaves;
       // lowest point of the slab on each side: smallest lo, largest hi (the
-      // leftmost of equal ones)
-      uint64_t k0 = valid[j] ? ((uint64_t)(uint32_t)mlo[j] << 6) | (uint64_t)lane : ~0ull;
-      uint64_t k1 = valid[j] ? ((uint64_t)(uint32_t)(INT_MAX - mhi[j]) << 6) | (uint64_t)lane : ~0ull;
+      // leftmost of equal ones); the keys order int32 values as unsigned
+      uint64_t k0 = valid[j] ? ((uint64_t)((uint32_t)mlo[j] ^ 0x80000000u) << 6) | (uint64_t)lane : ~0ull;
+      uint64_t k1 = valid[j] ? ((uint64_t)(~((uint32_t)mhi[j] ^ 0x80000000u)) << 6) | (uint64_t)lane : ~0ull;
 #pragma unroll
       for (int d = kWave / 2; d > 0; d >>= 1) {
         const uint64_t o0 = __shfl_xor(k0, d, kWave), o1 = __shfl_xor(k1, d, kWave);
@@ -1753,7 +1781,7 @@ __global__ __launch_bounds__(kNodeBlock) void k_node_finish(FinishArgs A, int2 *
         k1 = o1 < k1 ? o1 : k1;
       }
       if (lane == 0) {
-        if (A.mask && (int64_t)g * kFanIn + sl < nslab) A.mask[(int64_t)g * kFanIn + sl] = vm;
+        if (!CHAIN && A.mask && (int64_t)g * kFanIn + sl < nslab) A.mask[(int64_t)g * kFanIn + sl] = vm;
         S.slab_k[sl] = __popcll(vm);
         S.slab_s[sl] = __popcll(vm) + __popcll(sm);
         S.mn[0][sl] = vm ? (int)(k0 & 63) : -1;
@@ -1771,7 +1799,7 @@ __global__ __launch_bounds__(kNodeBlock) void k_node_finish(FinishArgs A, int2 *
   if (wave < 2) {
     const int side = wave, sl = lane;
     const int ml = S.mn[side][sl];
-    const int2 M = ml >= 0 ? node_point(S, side, x0, sl * kSlab + ml) : make_int2(0, 0);
+    const int2 M = ml >= 0 ? node_point(S, side, sl * kSlab + ml) : make_int2(0, 0);
     // against the lowest points of the slabs up to kMinWin away only: the
     // result is a superset of the hull's vertices, which still gives valid
     // reference points
@@ -1805,12 +1833,12 @@ __global__ __launch_bounds__(kNodeBlock) void k_node_finish(FinishArgs A, int2 *
     const int2 PL = make_int2(__shfl(M.x, hl, kWave), __shfl(M.y, hl, kWave));
     const int2 PR = make_int2(__shfl(M.x, hr, kWave), __shfl(M.y, hr, kWave));
     if (ml >= 0) {
-      S.refL[side][sl] = lm ? PL : node_point(S, side, x0, sl * kSlab + S.first[sl]);
-      S.refR[side][sl] = rm ? PR : node_point(S, side, x0, sl * kSlab + S.last[sl]);
+      S.refL[side][sl] = lm ? PL : node_point(S, side, sl * kSlab + S.first[sl]);
+      S.refR[side][sl] = rm ? PR : node_point(S, side, sl * kSlab + S.last[sl]);
       S.refM[side][sl] = M;
       S.ish[side][sl] = on ? 1 : 0;
     }
-  } else if (wave == kNodeWaves - 1) {
+  } else if (!CHAIN && wave == kNodeWaves - 1) {
     const int kk = S.slab_k[lane], ss = S.slab_s[lane];
     int incl = kk, stot = ss;
 #pragma unroll
@@ -1869,7 +1897,7 @@ __global__ __launch_bounds__(kNodeBlock) void k_node_finish(FinishArgs A, int2 *
         report_reduce_errors(err, A.info);
       }
     }
-  } else if (wave == kNodeWaves - 2 && g == 0 && A.dyn_ctr != nullptr) {
+  } else if (!CHAIN && wave == kNodeWaves - 2 && g == 0 && A.dyn_ctr != nullptr) {
     // every chunk of the reduce folded exactly once; the counter is zero
     // again for the next run that uses its slot
     int folded = 0;
@@ -1891,7 +1919,7 @@ __global__ __launch_bounds__(kNodeBlock) void k_node_finish(FinishArgs A, int2 *
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
       bool keep = false;
-      const int2 v = make_int2(x0 + c, side ? -mhi[j] : mlo[j]);
+      const int2 v = make_int2(xv[j], side ? -mhi[j] : mlo[j]);
       if (valid[j]) {
         const int2 PM = S.refM[side][sl];
         int2 u = S.refL[side][sl], w = S.refR[side][sl];
@@ -1899,7 +1927,7 @@ __global__ __launch_bounds__(kNodeBlock) void k_node_finish(FinishArgs A, int2 *
           if (v.x < PM.x) w = PM;
           else u = PM;
         }
-        keep = v.x == u.x || v.x == w.x || ncross_neg<SMALL>(u, w, v);
+        keep = v.x == u.x || v.x == w.x || ncross_neg<PREC>(u, w, v);
       }
       int tot;
       const int r = wave_rank(keep, &tot);
@@ -1924,19 +1952,20 @@ __global__ __launch_bounds__(kNodeBlock) void k_node_finish(FinishArgs A, int2 *
       bool hasL = false, hasR = false;
       for (int i = 0; i < m; ++i) {
         const int2 u = row[i];
-        const bool tL = (i < lane) & (!hasL | nsteeper_left<SMALL>(u, uL, v));
-        const bool tR = (i > lane) & (!hasR | nflatter_right<SMALL>(u, wR, v));
+        const bool tL = (i < lane) & (!hasL | nsteeper_left<PREC>(u, uL, v));
+        const bool tR = (i > lane) & (!hasR | nflatter_right<PREC>(u, wR, v));
         uL = tL ? u : uL;
         hasL |= tL;
         wR = tR ? u : wR;
         hasR |= tR;
       }
-      const bool keep = lane < m && (!hasL || !hasR || ncross_pos<SMALL>(uL, v, wR));
+      const bool keep = lane < m && (!hasL || !hasR || ncross_pos<PREC>(uL, v, wR));
       int tot;
       const int r = wave_rank(keep, &tot);
       if (keep) row[r] = v;
       if (lane == 0) S.cnt[side][sl] = tot;
     }
+    if (CHAIN) continue;
     const int c = sl * kSlab + lane;
     int tot;
     const int r = wave_rank(valid[j], &tot);
@@ -1995,11 +2024,11 @@ __global__ __launch_bounds__(kNodeBlock) void k_node_finish(FinishArgs A, int2 *
           // the vertex's own slab hull: its neighbours there
           if (k > 0) {
             const int2 u = H[k - 1];
-            if (!hasL || nsteeper_left<SMALL>(u, uL, v)) { uL = u; hasL = true; }
+            if (!hasL || nsteeper_left<PREC>(u, uL, v)) { uL = u; hasL = true; }
           }
           if (k + 1 < m) {
             const int2 w = H[k + 1];
-            if (!hasR || nflatter_right<SMALL>(w, wR, v)) { wR = w; hasR = true; }
+            if (!hasR || nflatter_right<PREC>(w, wR, v)) { wR = w; hasR = true; }
           }
         } else {
           // tangent from v: on a hull to its left the first vertex whose next
@@ -2009,15 +2038,15 @@ __global__ __launch_bounds__(kNodeBlock) void k_node_finish(FinishArgs A, int2 *
           int lo = 0, hi = m - 1;
           while (lo < hi) {
             const int mid = (lo + hi) >> 1;
-            const bool go = left ? ncross_pos<SMALL>(H[mid], H[mid + 1], v) : ncross_neg<SMALL>(H[mid], H[mid + 1], v);
+            const bool go = left ? ncross_pos<PREC>(H[mid], H[mid + 1], v) : ncross_neg<PREC>(H[mid], H[mid + 1], v);
             if (go) lo = mid + 1;
             else hi = mid;
           }
           const int2 t = H[lo];
           if (left) {
-            if (!hasL || nsteeper_left<SMALL>(t, uL, v)) { uL = t; hasL = true; }
+            if (!hasL || nsteeper_left<PREC>(t, uL, v)) { uL = t; hasL = true; }
           } else {
-            if (!hasR || nflatter_right<SMALL>(t, wR, v)) { wR = t; hasR = true; }
+            if (!hasR || nflatter_right<PREC>(t, wR, v)) { wR = t; hasR = true; }
           }
         }
       }
@@ -2027,10 +2056,10 @@ __global__ __launch_bounds__(kNodeBlock) void k_node_finish(FinishArgs A, int2 *
         const int2 ow = make_int2(__shfl_xor(wR.x, d, kNodeGroup), __shfl_xor(wR.y, d, kNodeGroup));
         const bool ohL = __shfl_xor((int)hasL, d, kNodeGroup) != 0;
         const bool ohR = __shfl_xor((int)hasR, d, kNodeGroup) != 0;
-        if (ohL && (!hasL || nsteeper_left<SMALL>(ou, uL, v))) { uL = ou; hasL = true; }
-        if (ohR && (!hasR || nflatter_right<SMALL>(ow, wR, v))) { wR = ow; hasR = true; }
+        if (ohL && (!hasL || nsteeper_left<PREC>(ou, uL, v))) { uL = ou; hasL = true; }
+        if (ohR && (!hasR || nflatter_right<PREC>(ow, wR, v))) { wR = ow; hasR = true; }
       }
-      if (gl == 0) S.keep[side][idx] = (!hasL || !hasR || ncross_pos<SMALL>(uL, v, wR)) ? 1 : 0;
+      if (gl == 0) S.keep[side][idx] = (!hasL || !hasR || ncross_pos<PREC>(uL, v, wR)) ? 1 : 0;
     }
   }
   __syncthreads();
@@ -2222,9 +2251,17 @@ __global__ __launch_bounds__(kSparseBlock) void k_sp_tail(const int32_t *__restr
       hi[cx[j] - 1] = b;
     }
   }
+  // one device atomic per workgroup
+  __shared__ int s_part[kSparseBlock / kWave];
 #pragma unroll
   for (int d = kWave / 2; d > 0; d >>= 1) s += __shfl_xor(s, d, kWave);
-  if ((threadIdx.x & (kWave - 1)) == 0 && s) atomicAdd(&info[HP_INFO_S], s);
+  if ((threadIdx.x & (kWave - 1)) == 0) s_part[threadIdx.x / kWave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int i = 0; i < kSparseBlock / kWave; ++i) t += s_part[i];
+    if (t) atomicAdd(&info[HP_INFO_S], t);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -2853,7 +2890,21 @@ static hipError_t launch_hull_levels(const TreeShape &T, int64_t positions, char
 
 static int hull_of_chain(const int32_t *cx, const int32_t *clo, const int32_t *chi, int32_t positions,
                          int32_t *hx, int32_t *hy, int32_t hull_cap, int32_t *info, char *w, const Layout &Y,
-                         const TreeShape &T, hipStream_t s);
+                         const TreeShape &T, hipStream_t s, bool small);
+
+// The node finish's LDS beyond the default limit, set once per process.
+static bool node_lds_ready() {
+  static int state = 0;
+  if (state == 0) {
+    const int bytes = (int)sizeof(NodeShared);
+    const void *k[] = {(const void *)k_node_finish<kPrecSmall, false>, (const void *)k_node_finish<kPrecNode, false>,
+                       (const void *)k_node_finish<kPrecSmall, true>, (const void *)k_node_finish<kPrecWide, true>};
+    bool ok = true;
+    for (const void *f : k) ok = ok && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) == hipSuccess;
+    state = ok ? 1 : 2;
+  }
+  return state == 1;
+}
 
 // The sparse path (HP_STRATEGY_SPARSE): work in the points and the occupied
 // columns, plus ceil(p/64) words of M; L is written only as the export.
@@ -2874,14 +2925,23 @@ static int run_sparse(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int
   const int gp = (int)std::max<int64_t>(1, std::min<int64_t>(8 * cus, (n + kSparseBlock - 1) / kSparseBlock));
   const int gs = (int)((W1 + kSparseBlock / kWave - 1) / (kSparseBlock / kWave));
   const int2 *P2 = reinterpret_cast<const int2 *>(pts);
-  hipLaunchKernelGGL(k_sp_clear, dim3(gw), dim3(kSparseBlock), 0, s, L0, W0, L1, W1, info);
+  // the timed reduce runs from the clearing of M to the fold of the points
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  timing_slot(&e0, &e1);
+  if (e0)
+    hipExtLaunchKernelGGL(k_sp_clear, dim3(gw), dim3(kSparseBlock), 0, s, e0, nullptr, 0, L0, W0, L1, W1, info);
+  else
+    hipLaunchKernelGGL(k_sp_clear, dim3(gw), dim3(kSparseBlock), 0, s, L0, W0, L1, W1, info);
   if (n > 0) hipLaunchKernelGGL(k_sp_mark, dim3(gp), dim3(kSparseBlock), 0, s, P2, n, p, org, L0, L1, info);
   hipLaunchKernelGGL(k_sp_count, dim3(gs), dim3(kSparseBlock), 0, s, (const uint64_t *)L0, (const uint64_t *)L1,
                      W1, cnt1);
   hipLaunchKernelGGL(k_sp_scan, dim3(1), dim3(kSparseScan), 0, s, (const int32_t *)cnt1, W1, off1, chain_cap, info);
   hipLaunchKernelGGL(k_sp_write, dim3(gs), dim3(kSparseBlock), 0, s, (const uint64_t *)L0, (const uint64_t *)L1, W1,
                      (const int32_t *)off1, wordbase, cx, clo, chi, chain_cap, p);
-  if (n > 0)
+  if (e1)   // with no points the fold is an empty grid-stride loop, kept for the stop event
+    hipExtLaunchKernelGGL(k_sp_fold, dim3(gp), dim3(kSparseBlock), 0, s, nullptr, e1, 0, P2, n, p, org,
+                          (const uint64_t *)L0, (const int32_t *)wordbase, clo, chi, chain_cap);
+  else if (n > 0)
     hipLaunchKernelGGL(k_sp_fold, dim3(gp), dim3(kSparseBlock), 0, s, P2, n, p, org, (const uint64_t *)L0,
                        (const int32_t *)wordbase, clo, chi, chain_cap);
   if (lo) {
@@ -2894,7 +2954,8 @@ static int run_sparse(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return set_error(HP_EDEVICE, "sparse path launch: %s", hipGetErrorString(e));
   if (!do_hull) return HP_OK;
-  return hull_of_chain(cx, clo, chi, Z.hpos, hx, hy, hull_cap, info, w, Z.Yh, Z.T, s);
+  // chain coordinates are at most p: below 2^15 the hull runs on 24-bit products
+  return hull_of_chain(cx, clo, chi, Z.hpos, hx, hy, hull_cap, info, w, Z.Yh, Z.T, s, p < (1 << 15));
 }
 
 // Enqueue the whole single-cloud sequence.  Shared by hp_precondition,
@@ -3056,22 +3117,13 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
   if (do_hull && T.nlev >= 3 && !node_finish_off()) {
     HullArgs Hn = H;
     hull_buffers(Hn, T, p, w, Y);
-    static bool node_attr = false;
-    if (!node_attr) {
-      const int bytes = (int)sizeof(NodeShared);
-      if (hipFuncSetAttribute((const void *)k_node_finish<true>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) !=
-              hipSuccess ||
-          hipFuncSetAttribute((const void *)k_node_finish<false>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) !=
-              hipSuccess)
-        return set_error(HP_EDEVICE, "k_node_finish: %zu bytes of LDS not available", sizeof(NodeShared));
-      node_attr = true;
-    }
+    if (!node_lds_ready()) return set_error(HP_EDEVICE, "k_node_finish: %zu bytes of LDS not available", sizeof(NodeShared));
     if (small)
-      hipLaunchKernelGGL((k_node_finish<true>), dim3(T.size[2]), dim3(kNodeBlock), sizeof(NodeShared), s, A, Hn.buf[1],
-                         Hn.ccount);
+      hipLaunchKernelGGL((k_node_finish<kPrecSmall, false>), dim3(T.size[2]), dim3(kNodeBlock), sizeof(NodeShared), s,
+                         A, Hn.buf[1], Hn.ccount);
     else
-      hipLaunchKernelGGL((k_node_finish<false>), dim3(T.size[2]), dim3(kNodeBlock), sizeof(NodeShared), s, A,
-                         Hn.buf[1], Hn.ccount);
+      hipLaunchKernelGGL((k_node_finish<kPrecNode, false>), dim3(T.size[2]), dim3(kNodeBlock), sizeof(NodeShared), s,
+                         A, Hn.buf[1], Hn.ccount);
     e = hipGetLastError();
     if (e != hipSuccess) return set_error(HP_EDEVICE, "k_node_finish launch: %s", hipGetErrorString(e));
     H.ctl = ctl;
@@ -3233,7 +3285,7 @@ namespace hp {
 // device: the slab finish from the chain, then the hull levels.
 static int hull_of_chain(const int32_t *cx, const int32_t *clo, const int32_t *chi, int32_t positions,
                          int32_t *hx, int32_t *hy, int32_t hull_cap, int32_t *info, char *w, const Layout &Y,
-                         const TreeShape &T, hipStream_t s) {
+                         const TreeShape &T, hipStream_t s, bool small) {
   int32_t *ctl = reinterpret_cast<int32_t *>(w + Y.ctl);
   int32_t *tree = reinterpret_cast<int32_t *>(w + Y.tree);
   hipLaunchKernelGGL(k_init, dim3(std::max(1, std::min(1024, (T.nodes + 255) / 256))), dim3(256), 0, s,
@@ -3256,6 +3308,30 @@ static int hull_of_chain(const int32_t *cx, const int32_t *clo, const int32_t *c
   A.hull_cap = hull_cap;
   A.ctl = ctl;
   A.info = info;
+  if (T.nlev >= 3 && !node_finish_off()) {
+    // more than one level-2 node: the node finish on the chain's entries
+    HullArgs Hn;
+    memset(&Hn, 0, sizeof(Hn));
+    hull_buffers(Hn, T, positions, w, Y);
+    if (!node_lds_ready()) return set_error(HP_EDEVICE, "k_node_finish: %zu bytes of LDS not available", sizeof(NodeShared));
+    if (small)
+      hipLaunchKernelGGL((k_node_finish<kPrecSmall, true>), dim3(T.size[2]), dim3(kNodeBlock), sizeof(NodeShared), s,
+                         A, Hn.buf[1], Hn.ccount);
+    else
+      hipLaunchKernelGGL((k_node_finish<kPrecWide, true>), dim3(T.size[2]), dim3(kNodeBlock), sizeof(NodeShared), s,
+                         A, Hn.buf[1], Hn.ccount);
+    e = hipGetLastError();
+    if (e != hipSuccess) return set_error(HP_EDEVICE, "k_node_finish launch: %s", hipGetErrorString(e));
+    HullArgs H;
+    memset(&H, 0, sizeof(H));
+    H.hx = hx;
+    H.hy = hy;
+    H.hull_cap = hull_cap;
+    H.info = info;
+    e = launch_hull_levels(T, positions, w, Y, H, small, s, false, true);
+    if (e != hipSuccess) return set_error(HP_EDEVICE, "hull level launch: %s", hipGetErrorString(e));
+    return HP_OK;
+  }
   // many slabs: 256-thread slab workgroups, so the grid stays below 2^32
   // work-items up to positions = HP_P_MAX
   if (T.size[1] > kScanRootMaxSlabs)
@@ -3288,8 +3364,9 @@ extern "C" int hp_hull(const int32_t *cx, const int32_t *clo, const int32_t *chi
   const TreeShape T = make_tree(chain_cap);
   const Layout Y = make_layout(chain_cap, 0, 0, T);
   if (ws_bytes < Y.total) return set_error(HP_ECAPACITY, "workspace too small: %zu < %zu bytes", ws_bytes, Y.total);
+  // a chain from the caller may hold any int32 coordinates
   return hull_of_chain(cx, clo, chi, chain_cap, hx, hy, hull_cap, info, static_cast<char *>(ws), Y, T,
-                       (hipStream_t)stream);
+                       (hipStream_t)stream, false);
 }
 
 extern "C" int hp_bbox_workspace_bytes(size_t *bytes) {

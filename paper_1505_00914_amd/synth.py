@@ -161,6 +161,8 @@ WORKLOADS = {
     "ellipsoids_10m_p4096": dict(kind="ellipsoids", n=10_000_000, p=4096, seed=2),
     "disc_2p28_p2p20": dict(kind="disc", n=1 << 28, p=1 << 20, seed=3),
     "gaussian_2p28_p4096": dict(kind="gaussian", n=1 << 28, p=4096, seed=4),
+    # the sparse regime (p far above n): 10^5 uniform points on [1, 2^24]^2
+    "uniform_1e5_p2p24": dict(kind="uniform", n=100_000, p=1 << 24, seed=5),
 }
 
 
