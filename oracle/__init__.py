@@ -10,4 +10,5 @@ from .oracle import (  # noqa: F401
     hull_chain, hull_full, precondition_and_hull, bbox, translate, auto,
     tree_levels, array_insert, tree_insert, tree_extract, hull_melkman,
     bbox_f32, quantize_f32, auto_f32, rescan_y,
+    reduce_rect, precondition_and_hull_rect, translate_rect, auto_rect,
 )

@@ -15,50 +15,46 @@
 #define OR_PMAX 2147483646
 
 /* ---------------------------------------------------------------------------
- * Algorithm 1 (Proposed heuristic, "Reduction of Points").
- *
- * L holds one (ly, hy) pair per column and starts as (p+1, -1) in every
- * column.  Each point (x, y) of P, taken in the order given, replaces the
- * pair of its column by (min(y, ly), max(y, hy)).  Coordinates are assumed
- * to lie in 1..p (the square of side p in the same section); anything else
- * is reported instead of being folded in.
+ * Algorithm 1 (Proposed heuristic, "Reduction of Points"), on the p x q box
+ * of Step 1 ("define p, q"): one (lo, hi) pair per column x in 1..p, all
+ * starting at the empty value (q+1, -1), one past either end of the y range
+ * 1..q.  A point only ever lowers the lo and raises the hi of its own column,
+ * so after all n points a column holds the smallest and the largest y among
+ * its points, or is still empty.  The square of side p is the case q = p.
+ * A point outside the box is reported instead of folded in.
  * ------------------------------------------------------------------------- */
-int or_reduce(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *hi)
+int or_reduce_rect(const int32_t *pts, int64_t n, int32_t p, int32_t q, int32_t *lo, int32_t *hi)
 {
-    if (p < 1 || p > OR_PMAX || n < 0) return OR_EINVAL;
+    if (p < 1 || p > OR_PMAX || q < 1 || q > OR_PMAX || n < 0) return OR_EINVAL;
     if (n > 0 && pts == NULL) return OR_EINVAL;
     if (lo == NULL || hi == NULL) return OR_EINVAL;
 
     for (int64_t j = 0; j < n; ++j) {
-        int32_t x = pts[2 * j], y = pts[2 * j + 1];
-        if (x < 1 || x > p || y < 1 || y > p) return OR_ERANGE;
+        const int32_t x = pts[2 * j], y = pts[2 * j + 1];
+        if (x < 1 || x > p || y < 1 || y > q) return OR_ERANGE;
     }
-
-    /* L = [(p+1, -1), ..., (p+1, -1)] */
-    for (int32_t i = 0; i < p; ++i) {
-        lo[i] = p + 1;
-        hi[i] = -1;
+    for (int32_t c = 0; c < p; ++c) {
+        lo[c] = q + 1;
+        hi[c] = -1;
     }
-
-    /* foreach point in P */
     for (int64_t j = 0; j < n; ++j) {
-        int32_t xi = pts[2 * j], yi = pts[2 * j + 1];
-        int32_t yv = lo[xi - 1], yu = hi[xi - 1];      /* (yv, yu) = L[xi]   */
-        int32_t ly = yi < yv ? yi : yv;                /* ly = min(yi, yv)   */
-        int32_t hy = yi > yu ? yi : yu;                /* hy = max(yi, yu)   */
-        lo[xi - 1] = ly;                               /* L[xi] = (ly, hy)   */
-        hi[xi - 1] = hy;
+        const int32_t c = pts[2 * j] - 1, y = pts[2 * j + 1];
+        if (y < lo[c]) lo[c] = y;
+        if (y > hi[c]) hi[c] = y;
     }
     return OR_OK;
 }
 
-/* An entry of L is valid when it differs from the sentinel (p+1, -1).  After
- * Algorithm 1 a column is either untouched (exactly the sentinel) or holds
- * 1 <= ly <= hy <= p, so "differs from the sentinel" is the test written
- * here, literally. */
-static int or_valid(int32_t lo, int32_t hi, int32_t p)
+int or_reduce(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *hi)
 {
-    return !(lo == p + 1 && hi == -1);
+    return or_reduce_rect(pts, n, p, p, lo, hi);
+}
+
+/* A column of L is occupied when it no longer holds the empty value
+ * (q+1, -1): after Algorithm 1 it then holds 1 <= lo <= hi <= q. */
+static int or_valid(int32_t lo, int32_t hi, int32_t q)
+{
+    return !(lo == q + 1 && hi == -1);
 }
 
 /* ---------------------------------------------------------------------------
@@ -66,21 +62,23 @@ static int or_valid(int32_t lo, int32_t hi, int32_t p)
  * exactly for the valid columns i; with w-bit words, column i is bit
  * (i-1) & (w-1) of word (i-1) >> log2(w).  Here w = 64.
  * ------------------------------------------------------------------------- */
-int64_t or_mask(const int32_t *lo, const int32_t *hi, int32_t p, uint64_t *M)
+int64_t or_mask_rect(const int32_t *lo, const int32_t *hi, int32_t p, int32_t q, uint64_t *M)
 {
-    if (p < 1 || p > OR_PMAX || lo == NULL || hi == NULL || M == NULL) return OR_EINVAL;
-    int64_t words = ((int64_t)p + 63) / 64;
+    if (p < 1 || p > OR_PMAX || q < 1 || q > OR_PMAX || lo == NULL || hi == NULL || M == NULL) return OR_EINVAL;
+    const int64_t words = ((int64_t)p + 63) / 64;
     memset(M, 0, (size_t)words * sizeof(uint64_t));
     int64_t set = 0;
-    for (int64_t i = 1; i <= p; ++i) {
-        if (or_valid(lo[i - 1], hi[i - 1], p)) {
-            int64_t b = (i - 1) >> 6;          /* block word   */
-            int64_t pb = (i - 1) & 63;         /* bit in block */
-            M[b] |= (uint64_t)1 << pb;
-            ++set;
-        }
+    for (int64_t c = 0; c < p; ++c) {
+        if (!or_valid(lo[c], hi[c], q)) continue;
+        M[c / 64] |= (uint64_t)1 << (c % 64);
+        ++set;
     }
     return set;
+}
+
+int64_t or_mask(const int32_t *lo, const int32_t *hi, int32_t p, uint64_t *M)
+{
+    return or_mask_rect(lo, hi, p, p, M);
 }
 
 /* Count of trailing zero bits of a non-zero word, by plain shifting (the
@@ -96,16 +94,13 @@ static int32_t or_ctz64(uint64_t x)
     return c;
 }
 
-/* Table I: while the word is non-zero, report pos = ctz(word) and clear that
- * bit with word ^= 1 << pos.  Positions come out in ascending order. */
+/* Table I: the set bits of a word in ascending order, by counting the
+ * trailing zeros of what is left and then dropping its lowest set bit
+ * (w & (w - 1) clears exactly that bit). */
 int32_t or_ctz_positions(uint64_t word, int32_t *pos)
 {
     int32_t c = 0;
-    while (word != 0) {
-        int32_t q = or_ctz64(word);
-        pos[c++] = q;
-        word ^= (uint64_t)1 << q;
-    }
+    for (uint64_t w = word; w != 0; w &= w - 1) pos[c++] = or_ctz64(w);
     return c;
 }
 
@@ -128,20 +123,25 @@ int32_t or_extract(const uint64_t *M, int32_t p, int32_t *cols)
  * entries that still hold the sentinel gives the valid columns in ascending
  * x.  The chain is stored as (x, lo, hi) per valid column.
  * ------------------------------------------------------------------------- */
+int32_t or_chain_rect(const int32_t *lo, const int32_t *hi, int32_t p, int32_t q,
+                      int32_t *x, int32_t *clo, int32_t *chi)
+{
+    if (p < 1 || p > OR_PMAX || q < 1 || q > OR_PMAX || lo == NULL || hi == NULL) return OR_EINVAL;
+    int32_t k = 0;
+    for (int32_t c = 0; c < p; ++c) {
+        if (!or_valid(lo[c], hi[c], q)) continue;
+        x[k] = c + 1;
+        clo[k] = lo[c];
+        chi[k] = hi[c];
+        ++k;
+    }
+    return k;
+}
+
 int32_t or_chain(const int32_t *lo, const int32_t *hi, int32_t p,
                  int32_t *x, int32_t *clo, int32_t *chi)
 {
-    if (p < 1 || p > OR_PMAX || lo == NULL || hi == NULL) return OR_EINVAL;
-    int32_t k = 0;
-    for (int32_t i = 1; i <= p; ++i) {
-        if (or_valid(lo[i - 1], hi[i - 1], p)) {
-            x[k] = i;
-            clo[k] = lo[i - 1];
-            chi[k] = hi[i - 1];
-            ++k;
-        }
-    }
-    return k;
+    return or_chain_rect(lo, hi, p, p, x, clo, chi);
 }
 
 /* The points the chain joins, in the order Lemma 1 walks them: within a
@@ -332,6 +332,22 @@ int or_bbox(const int32_t *pts, int64_t n, int32_t *box)
     box[1] = xmax;
     box[2] = ymin;
     box[3] = ymax;
+    return OR_OK;
+}
+
+/* Step 2 on the p x q box: the same translation, with p = xmax - xmin + 1
+ * columns and q = ymax - ymin + 1 rows. */
+int or_translate_rect(const int32_t *pts, int64_t n, const int32_t *box, int32_t *out, int32_t *p, int32_t *q)
+{
+    if (n < 1 || pts == NULL || box == NULL || out == NULL || p == NULL || q == NULL) return OR_EINVAL;
+    const int64_t ex = (int64_t)box[1] - box[0] + 1, ey = (int64_t)box[3] - box[2] + 1;
+    if (ex > OR_PMAX || ey > OR_PMAX) return OR_EINVAL;
+    for (int64_t j = 0; j < n; ++j) {
+        out[2 * j] = (int32_t)((int64_t)pts[2 * j] - box[0] + 1);
+        out[2 * j + 1] = (int32_t)((int64_t)pts[2 * j + 1] - box[2] + 1);
+    }
+    *p = (int32_t)ex;
+    *q = (int32_t)ey;
     return OR_OK;
 }
 

@@ -47,6 +47,17 @@ extern "C" {
  * points are folded in, in input order, by per-column min/max. */
 int or_reduce(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *hi);
 
+/* Algorithm 1 on the p x q box of Step 1: lo/hi receive p entries, points
+ * must satisfy 1 <= x <= p and 1 <= y <= q, and an empty column holds
+ * (q+1, -1).  or_reduce is the case q = p; or_mask_rect and or_chain_rect
+ * read L with that sentinel, or_translate_rect gives the p x q box of the
+ * points (p columns along x, q rows along y). */
+int or_reduce_rect(const int32_t *pts, int64_t n, int32_t p, int32_t q, int32_t *lo, int32_t *hi);
+int64_t or_mask_rect(const int32_t *lo, const int32_t *hi, int32_t p, int32_t q, uint64_t *M);
+int32_t or_chain_rect(const int32_t *lo, const int32_t *hi, int32_t p, int32_t q,
+                      int32_t *x, int32_t *clo, int32_t *chi);
+int or_translate_rect(const int32_t *pts, int64_t n, const int32_t *box, int32_t *out, int32_t *p, int32_t *q);
+
 /* Bit array M (Discussion, "Extraction using an array of bits"): word
  * (i-1)>>6, bit (i-1)&63 is set iff column i holds a valid entry.  M must
  * have ceil(p/64) words.  Returns the number of set bits. */

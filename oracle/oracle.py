@@ -90,6 +90,14 @@ def _load(path: str) -> ctypes.CDLL:
     lib.or_bbox.restype = ctypes.c_int
     lib.or_translate.argtypes = [_i32p, ctypes.c_int64, _i32p, _i32p, _i32p]
     lib.or_translate.restype = ctypes.c_int
+    lib.or_reduce_rect.argtypes = [_i32p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _i32p, _i32p]
+    lib.or_reduce_rect.restype = ctypes.c_int
+    lib.or_mask_rect.argtypes = [_i32p, _i32p, ctypes.c_int32, ctypes.c_int32, _u64p]
+    lib.or_mask_rect.restype = ctypes.c_int64
+    lib.or_chain_rect.argtypes = [_i32p, _i32p, ctypes.c_int32, ctypes.c_int32, _i32p, _i32p, _i32p]
+    lib.or_chain_rect.restype = ctypes.c_int32
+    lib.or_translate_rect.argtypes = [_i32p, ctypes.c_int64, _i32p, _i32p, _i32p, _i32p]
+    lib.or_translate_rect.restype = ctypes.c_int
     return lib
 
 
@@ -256,6 +264,66 @@ def auto(pts, lib: str | None = None, axis: str = "x") -> dict:
     r["box"] = box
     r["origin"] = (box[0] - 1, box[2] - 1)
     r["axis"] = "x"
+    return r
+
+
+def reduce_rect(pts, p: int, q: int, lib: str | None = None) -> tuple[np.ndarray, np.ndarray]:
+    """Algorithm 1 on the p x q box: (lo, hi) of length p, empty (q+1, -1)."""
+    a = _points(pts)
+    lo = np.empty(p, np.int32)
+    hi = np.empty(p, np.int32)
+    rc = _lib(lib).or_reduce_rect(_ptr(a), a.shape[0], p, q, _ptr(lo), _ptr(hi))
+    if rc != OR_OK:
+        raise OracleError(f"or_reduce_rect failed: {rc}")
+    return lo, hi
+
+
+def precondition_and_hull_rect(pts, p: int, q: int, lib: str | None = None) -> dict:
+    """The whole path on the p x q box: L (sentinel q+1), M, chain, hull."""
+    lo, hi = reduce_rect(pts, p, q, lib)
+    M = np.empty((p + 63) // 64, np.uint64)
+    if _lib(lib).or_mask_rect(_ptr(lo), _ptr(hi), p, q, _ptr(M, _u64p)) < 0:
+        raise OracleError("or_mask_rect failed")
+    x = np.empty(p, np.int32)
+    cl = np.empty(p, np.int32)
+    ch = np.empty(p, np.int32)
+    k = _lib(lib).or_chain_rect(_ptr(lo), _ptr(hi), p, q, _ptr(x), _ptr(cl), _ptr(ch))
+    if k < 0:
+        raise OracleError(f"or_chain_rect failed: {k}")
+    x, cl, ch = x[:k].copy(), cl[:k].copy(), ch[:k].copy()
+    return {"lo": lo, "hi": hi, "mask": M, "x": x, "clo": cl, "chi": ch, "k": int(k),
+            "hull": hull_chain(x, cl, ch, lib)}
+
+
+def translate_rect(pts, box, lib: str | None = None) -> tuple[np.ndarray, int, int]:
+    """Step 2 on the p x q box: the translated points, p columns, q rows."""
+    a = _points(pts)
+    b = np.asarray(box, np.int32)
+    out = np.empty_like(a)
+    p = np.zeros(1, np.int32)
+    q = np.zeros(1, np.int32)
+    rc = _lib(lib).or_translate_rect(_ptr(a), a.shape[0], _ptr(b), _ptr(out), _ptr(p), _ptr(q))
+    if rc != OR_OK:
+        raise OracleError(f"or_translate_rect failed: {rc}")
+    return out, int(p[0]), int(q[0])
+
+
+def auto_rect(pts, lib: str | None = None, axis: str = "x") -> dict:
+    """Steps 1 to 3 and the hull on the p x q box (Step 1 defines p and q):
+    L has one entry per column of the sweep axis and the sentinel q + 1.
+    ``axis`` "y" sweeps along y (x and y exchanged); "auto" takes the
+    shorter side of the box, so that L has min(p, q) entries."""
+    if axis != "x":
+        b = bbox(pts, lib)
+        if axis == "y" or (b[3] - b[2]) < (b[1] - b[0]):
+            a = _points(pts)
+            r = auto_rect(np.ascontiguousarray(a[:, ::-1]), lib, "x")
+            r["axis"] = "y"
+            return r
+    box = bbox(pts, lib)
+    t, p, q = translate_rect(pts, box, lib)
+    r = precondition_and_hull_rect(t, p, q, lib)
+    r.update({"p": p, "q": q, "box": box, "origin": (box[0] - 1, box[2] - 1), "axis": "x"})
     return r
 
 

@@ -560,11 +560,73 @@ def pin_sweep_axis(lib=None):
     return errs
 
 
+@_safe
+def pin_rect(lib=None):
+    """The p x q box: the hand-worked example (sentinel q + 1 in the empty
+    column), the square as the case q = p, the empty value and the range
+    check of y against q, and the sweep along the shorter side keeping an L
+    of min(p, q) entries with the hull of the points."""
+    errs = []
+    f = fixtures.read("rect_example_p6_q3.txt")
+    p, q = int(f["p"][0]), int(f["q"][0])
+    pts = fixtures.pairs(f["points"])
+    r = oracle.precondition_and_hull_rect(pts, p, q, lib=lib)
+    if list(zip(r["lo"].tolist(), r["hi"].tolist())) != fixtures.pairs(f["L"]):
+        errs.append(f"L {list(zip(r['lo'].tolist(), r['hi'].tolist()))}")
+    if int(r["mask"][0]) != int(f["mask"][0]):
+        errs.append(f"M {int(r['mask'][0])}")
+    for key, name in (("x", "chain_x"), ("clo", "chain_lo"), ("chi", "chain_hi")):
+        if r[key].tolist() != [int(v) for v in f[name]]:
+            errs.append(f"{name} {r[key].tolist()}")
+    if oracle.reduced(r["x"], r["clo"], r["chi"], lib=lib).shape[0] != int(f["s"][0]):
+        errs.append("s")
+    if [tuple(v) for v in r["hull"].tolist()] != fixtures.pairs(f["hull"]):
+        errs.append(f"hull {r['hull'].tolist()}")
+    rng = np.random.default_rng(1818)
+    for t in range(40):
+        pp, qq = int(rng.integers(1, 120)), int(rng.integers(1, 120))
+        a = np.stack([rng.integers(1, pp + 1, 200), rng.integers(1, qq + 1, 200)], 1)
+        rr = oracle.precondition_and_hull_rect(a, pp, qq, lib=lib)
+        side = max(pp, qq)
+        sq = oracle.precondition_and_hull(a, side, lib=lib)
+        used = sq["lo"][:pp] <= sq["hi"][:pp]
+        # occupied columns as in the square of the larger side, empty ones at (q+1, -1)
+        if not (np.array_equal(rr["lo"][used], sq["lo"][:pp][used]) and np.array_equal(rr["hi"][used], sq["hi"][:pp][used])
+                and np.all(rr["lo"][~used] == qq + 1) and np.all(rr["hi"][~used] == -1)):
+            errs.append(f"case {t}: L against the square of side {side}")
+        for key in ("x", "clo", "chi", "hull"):
+            if not np.array_equal(rr[key], sq[key]):
+                errs.append(f"case {t}: {key} against the square")
+        if not np.array_equal(rr["hull"], oracle.hull_full(a, lib=lib)):
+            errs.append(f"case {t}: hull against the hull of all points")
+        if pp == qq and not np.array_equal(rr["lo"], sq["lo"]):
+            errs.append(f"case {t}: q = p is not the square")
+    # y = q + 1 is outside the box even when it is within the columns
+    try:
+        oracle.reduce_rect([(1, 4)], 6, 3, lib=lib)
+        errs.append("y = q + 1 accepted")
+    except oracle.OracleError:
+        pass
+    for t in range(20):
+        w, h = int(rng.integers(1, 300)), int(rng.integers(1, 300))
+        a = np.stack([rng.integers(0, w, 400), rng.integers(0, h, 400)], 1) - 77
+        ra = oracle.auto_rect(a, lib=lib, axis="auto")
+        ex, ey = int(a[:, 0].max() - a[:, 0].min()) + 1, int(a[:, 1].max() - a[:, 1].min()) + 1
+        if ra["lo"].shape[0] != min(ex, ey) or ra["q"] != max(ex, ey) or ra["p"] != min(ex, ey):
+            errs.append(f"case {t}: L of {ra['lo'].shape[0]} entries for a {ex} x {ey} box")
+        moved = ra["hull"] + [ra["origin"][0], ra["origin"][1]]
+        if ra["axis"] == "y":
+            moved = moved[:, ::-1]
+        if not np.array_equal(oracle.hull_full(moved, lib=lib), oracle.hull_full(a, lib=lib)):
+            errs.append(f"case {t}: hull of the {ra['axis']} sweep")
+    return errs
+
+
 ALL_PINS = [pin_worked_example, pin_gap_example, pin_table1, pin_block_index,
             pin_closed_forms, pin_brute_random, pin_exhaustive_p3, pin_qhull,
-            pin_appendix, pin_invariants, pin_metamorphic, pin_errors, pin_steps12, pin_bitsets, pin_melkman, pin_float_input, pin_rescan_y, pin_sweep_axis]
+            pin_appendix, pin_invariants, pin_metamorphic, pin_errors, pin_steps12, pin_bitsets, pin_melkman, pin_float_input, pin_rescan_y, pin_sweep_axis, pin_rect]
 
 # the cheap pins, run first against planted mistakes
 FAST_PINS = [pin_worked_example, pin_gap_example, pin_table1, pin_block_index,
-             pin_closed_forms, pin_errors, pin_brute_random, pin_steps12, pin_bitsets]
+             pin_closed_forms, pin_errors, pin_brute_random, pin_steps12, pin_bitsets, pin_rect]
 

@@ -18,13 +18,14 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 MUTANTS = {
     "collinear-kept": ("<= 0) --t;", "< 0) --t;"),
-    "min-as-max": ("int32_t ly = yi < yv ? yi : yv;", "int32_t ly = yi > yv ? yi : yv;"),
-    "max-as-min": ("int32_t hy = yi > yu ? yi : yu;", "int32_t hy = yi < yu ? yi : yu;"),
-    "sentinel-lo": ("lo[i] = p + 1;", "lo[i] = p;"),
-    "sentinel-hi": ("hi[i] = -1;", "hi[i] = 0;"),
-    "x-y-swapped": ("int32_t xi = pts[2 * j], yi = pts[2 * j + 1];",
-                    "int32_t yi = pts[2 * j], xi = pts[2 * j + 1];"),
-    "store-lo-into-hi": ("hi[xi - 1] = hy;", "hi[xi - 1] = ly;"),
+    "min-as-max": ("if (y < lo[c]) lo[c] = y;", "if (y > lo[c]) lo[c] = y;"),
+    "max-as-min": ("if (y > hi[c]) hi[c] = y;", "if (y < hi[c]) hi[c] = y;"),
+    "sentinel-lo": ("lo[c] = q + 1;", "lo[c] = q;"),
+    "sentinel-from-p": ("lo[c] = q + 1;", "lo[c] = p + 1;"),
+    "sentinel-hi": ("hi[c] = -1;", "hi[c] = 0;"),
+    "x-y-swapped": ("const int32_t c = pts[2 * j] - 1, y = pts[2 * j + 1];",
+                    "const int32_t c = pts[2 * j + 1] - 1, y = pts[2 * j];"),
+    "store-lo-into-hi": ("if (y > hi[c]) hi[c] = y;", "if (y > hi[c]) hi[c] = lo[c];"),
     "cross-sign": ("return (ax - ox) * (by - oy) - (ay - oy) * (bx - ox);",
                    "return (ay - oy) * (bx - ox) - (ax - ox) * (by - oy);"),
     "cross-dropped-term": ("return (ax - ox) * (by - oy) - (ay - oy) * (bx - ox);",
@@ -33,12 +34,15 @@ MUTANTS = {
                          "return (ax - ox) * (by - oy) - (ay - oy) * (bx - oy);"),
     "keep-last-of-lower": ("    for (int64_t i = 0; i + 1 < t; ++i) {\n        vx[h] = sx[i];",
                            "    for (int64_t i = 0; i < t; ++i) {\n        vx[h] = sx[i];"),
-    "mask-bit-off-by-one": ("int64_t pb = (i - 1) & 63;", "int64_t pb = i & 63;"),
-    "ctz-pos-off-by-one": ("pos[c++] = q;", "pos[c++] = q + 1;"),
-    "valid-inverted": ("return !(lo == p + 1 && hi == -1);", "return (lo == p + 1 && hi == -1);"),
+    "mask-bit-off-by-one": ("M[c / 64] |= (uint64_t)1 << (c % 64);", "M[c / 64] |= (uint64_t)1 << ((c + 1) % 64);"),
+    "ctz-pos-off-by-one": ("pos[c++] = or_ctz64(w);", "pos[c++] = or_ctz64(w) + 1;"),
+    "ctz-clears-two-bits": ("w &= w - 1) pos", "w &= w - 2) pos"),
+    "valid-inverted": ("return !(lo == q + 1 && hi == -1);", "return (lo == q + 1 && hi == -1);"),
     "reduced-repeats-single": ("if (chi[t] > clo[t]) {", "if (chi[t] >= clo[t]) {"),
-    "range-check-off": ("if (x < 1 || x > p || y < 1 || y > p) return OR_ERANGE;",
+    "range-check-off": ("if (x < 1 || x > p || y < 1 || y > q) return OR_ERANGE;",
                         "if (x < 1 || x > p || y < 1) return OR_ERANGE;"),
+    "range-check-y-against-p": ("if (x < 1 || x > p || y < 1 || y > q) return OR_ERANGE;",
+                                "if (x < 1 || x > p || y < 1 || y > p) return OR_ERANGE;"),
     "bbox-ymin-from-x": ("if (y < ymin) ymin = y;", "if (x < ymin) ymin = x;"),
     "translate-off-by-one": ("out[2 * j] = (int32_t)((int64_t)pts[2 * j] - box[0] + 1);",
                              "out[2 * j] = (int32_t)((int64_t)pts[2 * j] - box[0]);"),
@@ -55,8 +59,9 @@ MUTANTS = {
     "scale-rounds-up": ("double t = floor(((double)v - o) * s);", "double t = ceil(((double)v - o) * s);"),
     "scale-origin-added": ("double t = floor(((double)v - o) * s);", "double t = floor(((double)v + o) * s);"),
     "float-box-keeps-nan": ("if (x != x || y != y) continue;", "if (x != x) continue;"),
-    "chain-skips-last": ("for (int32_t i = 1; i <= p; ++i) {\n        if (or_valid(lo[i - 1], hi[i - 1], p)) {\n            x[k] = i;",
-                         "for (int32_t i = 1; i < p; ++i) {\n        if (or_valid(lo[i - 1], hi[i - 1], p)) {\n            x[k] = i;"),
+    "chain-skips-last": ("for (int32_t c = 0; c < p; ++c) {\n        if (!or_valid(lo[c], hi[c], q)) continue;\n        x[k] = c + 1;",
+                         "for (int32_t c = 0; c + 1 < p; ++c) {\n        if (!or_valid(lo[c], hi[c], q)) continue;\n        x[k] = c + 1;"),
+    "rect-rows-from-columns": ("*q = (int32_t)ey;", "*q = (int32_t)ex;"),
 }
 
 
