@@ -642,7 +642,7 @@ def summarize_counters(fetch_dir: str, write_dir: str, copy_bytes: float, comman
 def bench_auto(args, torch, hp, synth) -> dict:
     """Steps 1 and 2 on the auxiliary workload moved far from the origin: the
     bounding-box pass alone; box + path enqueued back to back (hp_bbox, then
-    hp_run_origin with the origin known from a first call); and hp_run_auto,
+    hp_run_rect on the p x q box known from a first call); and hp_run_auto,
     which waits for the box on the host before it enqueues the path.  Then
     the same cloud as float32 through hp_run_auto_f32."""
     import numpy as np
@@ -658,14 +658,14 @@ def bench_auto(args, torch, hp, synth) -> dict:
     p_cap = w["p"]
     abuf = hp.Buffers.allocate(n, p_cap, pts.device, False, hp.run_auto_workspace_bytes(n, "x", p_cap))
     plan = hp.hp_run_auto(pts, "x", p_cap, abuf, stream)
-    p, origin = plan["p"], plan["origin"]
-    buf = hp.Buffers.allocate(n, p, pts.device, export_L=False)
+    p, q, origin = plan["p"], plan["q"], plan["origin"]
+    buf = hp.Buffers.allocate(n, p, pts.device, False, hp.workspace_bytes_rect(n, p, q))
     box = torch.empty(4, dtype=torch.int32, device=pts.device)
     ws = torch.empty(hp.bbox_workspace_bytes(), dtype=torch.uint8, device=pts.device)
     steps = max(10, min(args.steps, 100))
     for _ in range(3):
         hp.hp_bbox(pts, box, ws, stream)
-        hp.hp_run_origin(pts, p, origin, buf, stream)
+        hp.hp_run_rect(pts, p, q, origin, buf, stream)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -674,17 +674,17 @@ def bench_auto(args, torch, hp, synth) -> dict:
     t1 = time.perf_counter()
     for _ in range(steps):
         hp.hp_bbox(pts, box, ws, stream)
-        hp.hp_run_origin(pts, p, origin, buf, stream)
+        hp.hp_run_rect(pts, p, q, origin, buf, stream)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     for _ in range(steps):
         hp.hp_run_auto(pts, "x", p_cap, abuf, stream)
     torch.cuda.synchronize()
     t3 = time.perf_counter()
-    want = oracle.auto(pts.cpu().numpy())
+    want = oracle.auto_rect(pts.cpu().numpy())
     ok = True
     for got in (hp.collect(buf), hp.collect(abuf)):
-        ok = ok and (got["status"] == 0 and want["p"] == p and tuple(box.cpu().tolist()) == want["box"]
+        ok = ok and (got["status"] == 0 and want["p"] == p and want["q"] == q and tuple(box.cpu().tolist()) == want["box"]
                      and plan["box"] == want["box"] and plan["origin"] == want["origin"]
                      and got["k"] == want["k"] and np.array_equal(got["x"], want["x"])
                      and np.array_equal(got["clo"], want["clo"]) and np.array_equal(got["chi"], want["chi"])
@@ -694,21 +694,22 @@ def bench_auto(args, torch, hp, synth) -> dict:
     # through the float box, the scaling to [1, p]^2 and the path
     fpts = (pts.to(torch.float64) / 64.0 + 1.0e5).to(torch.float32).contiguous()
     qpts = torch.empty_like(pts)
-    fbuf = hp.Buffers.allocate(n, p, pts.device, False, hp.run_auto_f32_workspace_bytes(n, p))
+    fp = max(p, q)   # the float input is scaled into a square of this side
+    fbuf = hp.Buffers.allocate(n, fp, pts.device, False, hp.run_auto_f32_workspace_bytes(n, fp))
     for _ in range(3):
-        hp.hp_run_auto_f32(fpts, p, fbuf, qpts, stream)
+        hp.hp_run_auto_f32(fpts, fp, fbuf, qpts, stream)
     torch.cuda.synchronize()
     t4 = time.perf_counter()
     for _ in range(steps):
-        hp.hp_run_auto_f32(fpts, p, fbuf, qpts, stream)
+        hp.hp_run_auto_f32(fpts, fp, fbuf, qpts, stream)
     torch.cuda.synchronize()
     t5 = time.perf_counter()
     fgot = hp.collect(fbuf)
-    fwant = oracle.auto_f32(fpts.cpu().numpy(), p)
+    fwant = oracle.auto_f32(fpts.cpu().numpy(), fp)
     fok = (fgot["status"] == 0 and fgot["k"] == fwant["k"]
            and np.array_equal(qpts.cpu().numpy(), fwant["points"]) and np.array_equal(fgot["hull"], fwant["hull"]))
     progress("steps 1-2 done")
-    return {"workload": args.aux_workload, "offset": list(off), "n": n, "p": p, "steps": steps,
+    return {"workload": args.aux_workload, "offset": list(off), "n": n, "p": p, "q": q, "steps": steps,
             "bbox_ms_avg": round(bbox_ms, 5), "bbox_gbs": round(8.0 * n / (bbox_ms * 1e-3) / 1e9, 1),
             "gpoints_per_s_bbox_and_path": round(n * steps / (t2 - t1) / 1e9, 3),
             "ms_per_step_bbox_and_path": round((t2 - t1) * 1e3 / steps, 5),

@@ -168,33 +168,48 @@ int hp_run_origin(const int32_t *pts, int64_t n, int32_t p, int32_t ox, int32_t 
                   int32_t chain_cap, int32_t *hx, int32_t *hy, int32_t hull_cap, int32_t *info,
                   void *ws, size_t ws_bytes, void *stream);
 
+/* The p x q box of Step 1 (Implementation of the proposed heuristic: Step 1
+ * defines p and q; Lemma 1 works in that box): hp_run_origin with p columns
+ * and q rows.  Every translated point must satisfy 1 <= x <= p and
+ * 1 <= y <= q (HP_ERANGE otherwise); L has p entries and an empty column
+ * holds (q + 1, -1); M, the chain and the hull are as for hp_run.  q = p is
+ * hp_run_origin.  ws: hp_workspace_bytes_rect(n, p, q) bytes; 1 <= q <=
+ * HP_P_MAX (HP_EINVAL otherwise). */
+int hp_workspace_bytes_rect(int64_t n, int32_t p, int32_t q, size_t *bytes);
+int hp_run_rect(const int32_t *pts, int64_t n, int32_t p, int32_t q, int32_t ox, int32_t oy, int32_t *lo,
+                int32_t *hi, uint64_t *mask, int32_t *cx, int32_t *clo, int32_t *chi, int32_t chain_cap,
+                int32_t *hx, int32_t *hy, int32_t hull_cap, int32_t *info, void *ws, size_t ws_bytes,
+                void *stream);
+
 /* Steps 1 to 3 of the proposed heuristic in one call (Algorithm 1 preceded
- * by the bounding box, the side p and the translation into [1, p]^2; the
- * sweep along the shorter side of the box from Results).
+ * by the bounding box, the p x q box of Step 1 and the translation into
+ * [1, p] x [1, q]; the sweep along the shorter side of the box from
+ * Results).
  *
  * hp_run_auto: the box of the n int32 points on the device, then, after one
  * synchronisation of `stream` (this call blocks until the box is known),
- * on the host: the side p = max(xmax - xmin, ymax - ymin) + 1, the origin
- * (xmin - 1, ymin - 1) and the sweep axis; then the path of hp_run_origin
- * is enqueued on `stream` and the call returns.
+ * on the host: p = the extent along the sweep axis + 1 (the columns of L),
+ * q = the extent across it + 1 (the rows), the origin (xmin - 1, ymin - 1)
+ * and the sweep axis; then the path of hp_run_rect is enqueued on `stream`
+ * and the call returns.
  *   axis   0: sweep along x (Algorithm 1 as written); 1: along y, i.e. the
  *          path runs on the points with x and y exchanged (one transposing
  *          pass into the workspace); 2: along y exactly when the y extent
- *          of the box is the smaller one
+ *          of the box is the smaller one, so that L has min(p, q) entries
  *   p_cap  capacity of lo, hi and mask in columns (they hold p_cap int32,
  *          p_cap int32 and ceil(p_cap / 64) uint64).  0 asks for the plan
  *          alone: nothing after the box is enqueued and the outputs other
  *          than plan may be NULL.  p > p_cap returns HP_ECAPACITY with the
  *          plan written
- *   plan   HOST int64[8]: xmin, xmax, ymin, ymax of the box, p, ox, oy and
- *          the axis taken (0 or 1).  With axis 1 the box and the origin are
- *          those of the exchanged points, and so are L, M, the chain and
+ *   plan   HOST int64[9]: xmin, xmax, ymin, ymax of the box, p, q, ox, oy
+ *          and the axis taken (0 or 1).  With axis 1 the box and the origin
+ *          are those of the exchanged points, and so are L, M, the chain and
  *          the hull
- *   other outputs as for hp_run_origin (chain_cap >= min(n, p), hull_cap >=
+ *   other outputs as for hp_run_rect (chain_cap >= min(n, p), hull_cap >=
  *          2 min(n, p)); ws is caller-owned device memory of
  *          hp_run_auto_workspace_bytes(n, axis, p_cap) bytes (the path's
- *          workspace for every p <= p_cap, plus the box and, for axis != 0,
- *          8n bytes for the exchanged points)
+ *          workspace for every p <= p_cap and any q, plus the box and, for
+ *          axis != 0, 8n bytes for the exchanged points)
  * n = 0 and an extent beyond HP_P_MAX return HP_EINVAL (the plan is written
  * in the second case).
  *

@@ -67,6 +67,9 @@ SIGNATURES = {
     "hp_bbox": (ctypes.c_int, [_vp, _i64, _vp, _vp, _sz, _vp]),
     "hp_run_origin": (ctypes.c_int, [_vp, _i64, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp,
                                      _i32, _vp, _vp, _sz, _vp]),
+    "hp_workspace_bytes_rect": (ctypes.c_int, [_i64, _i32, _i32, _szp]),
+    "hp_run_rect": (ctypes.c_int, [_vp, _i64, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp,
+                                   _i32, _vp, _vp, _sz, _vp]),
     "hp_run_auto_workspace_bytes": (ctypes.c_int, [_i64, _i32, _i32, _szp]),
     "hp_run_auto": (ctypes.c_int, [_vp, _i64, _i32, _i32, _i64p, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp,
                                    _i32, _vp, _vp, _sz, _vp]),

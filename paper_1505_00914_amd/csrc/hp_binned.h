@@ -230,7 +230,7 @@ __device__ __forceinline__ int bin_windows(const BinLds &S, const BinArgs &B, in
 // (in the other buffer when the window writes blocks this tile, whose old
 // carry bin_flush still reads).  bin_flush, by every lane: each completed
 // block (old carry first, then sbuf) is written to its window's stream.
-__device__ __forceinline__ void bin_rank(const BinLds &S, int *cnt, int p, bool filtered, int qs,
+__device__ __forceinline__ void bin_rank(const BinLds &S, int *cnt, Extent p, bool filtered, int qs,
                                          const int (&xs)[2 * kBinVpt], const int (&ys)[2 * kBinVpt],
                                          const bool (&in)[2 * kBinVpt], bool &bad, int (&wr)[2 * kBinVpt],
                                          uint32_t (&val)[2 * kBinVpt]) {
@@ -242,7 +242,7 @@ __device__ __forceinline__ void bin_rank(const BinLds &S, int *cnt, int p, bool 
 #pragma unroll
   for (int j = 0; j < PP; ++j) {
     const unsigned xi = (unsigned)(xs[j] - 1), yi = (unsigned)(ys[j] - 1);
-    const bool ok = in[j] & (xi < (unsigned)p) & (yi < (unsigned)p);
+    const bool ok = in[j] & (xi < (unsigned)p.p) & (yi < (unsigned)p.q);
     bad |= in[j] & !ok;
     pass[j] = ok;
     val[j] = ((xi & (unsigned)(kBinWc - 1)) << kBinYBits) | yi;
@@ -324,7 +324,7 @@ __device__ __forceinline__ void bin_flush(const BinLds &S, const BinArgs &B, int
 // words, bounds in steps of 2^qs) is the filter of the previous rounds, or
 // null in the first round.  Workgroup 0 of the first round also clears the
 // finish step's control words (R).
-__global__ __launch_bounds__(kBinThreads) void k_bin(const int32_t *__restrict__ pts, int64_t n, int32_t p,
+__global__ __launch_bounds__(kBinThreads) void k_bin(const int32_t *__restrict__ pts, int64_t n, Extent p,
                                                      const uint16_t *__restrict__ F, int32_t nf, int32_t qs,
                                                      BinArgs B, int32_t *__restrict__ wg_err, int2 org,
                                                      ResetArgs R) {
@@ -545,7 +545,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const int32_t *__restrict__
 constexpr int kBinFoldList = 1024;
 constexpr int kBinFoldStep = 8;
 
-__global__ __launch_bounds__(kBinFoldThreads) void k_bin_fold(BinArgs B, int32_t p, int32_t S_,
+__global__ __launch_bounds__(kBinFoldThreads) void k_bin_fold(BinArgs B, Extent p, int32_t S_,
                                                               int2 *__restrict__ part) {
   __shared__ int2 sL[kBinWc];
   __shared__ int lpid[kBinFoldList];
@@ -556,7 +556,7 @@ __global__ __launch_bounds__(kBinFoldThreads) void k_bin_fold(BinArgs B, int32_t
   const int nw = B.nw;
   const int64_t c0 = (int64_t)w * kBinWc;
   const int ncol = (int)min<int64_t>(kBinWc, (int64_t)p - c0);
-  for (int c = tid; c < kBinWc; c += kBinFoldThreads) sL[c] = make_int2(p + 1, -1);
+  for (int c = tid; c < kBinWc; c += kBinFoldThreads) sL[c] = make_int2(p.q + 1, -1);
   const int g0 = (int)((int64_t)s * B.G / S_), g1 = (int)((int64_t)(s + 1) * B.G / S_);
   for (int gc = g0; gc < g1; gc += kBinFoldThreads) {
     // slot tid: binning workgroup gc + tid, its stream for window w
@@ -622,11 +622,11 @@ __global__ __launch_bounds__(kBinFoldThreads) void k_bin_fold(BinArgs B, int32_t
 // rounded up and the smallest hi rounded down to multiples of 2^qs in y - 1
 // (8 bits each), or a range that holds nothing when a column of the group is
 // empty or the lo bound does not fit 8 bits.
-__global__ __launch_bounds__(256) void k_bin_merge(int2 *__restrict__ part, int32_t S_, int32_t has_prev, int32_t p,
+__global__ __launch_bounds__(256) void k_bin_merge(int2 *__restrict__ part, int32_t S_, int32_t has_prev, Extent p,
                                                    int32_t qs, uint16_t *__restrict__ F) {
   const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int lane = threadIdx.x & (kWave - 1);
-  int2 L = make_int2(p + 1, -1);
+  int2 L = make_int2(p.q + 1, -1);
   if (c < p) {
     int2 a[8];
     int s = 0;

@@ -22,6 +22,18 @@ constexpr int kMaxLevels = 12;   // hull-tree levels (slab level is 1)
 constexpr int kSplit = 4;        // hull-test workgroups per child node above the slabs
 constexpr int kSplitSlab = 4;    // hull-test workgroups per slab
 
+// The box Algorithm 1 runs on: p columns (x in 1..p) and q rows (y in
+// 1..q), an empty column holding (q + 1, -1) (Implementation of the proposed
+// heuristic, Step 1 defines p and q).  It converts from a single side (the
+// square, q = p) and to its column count, which is what sizes L.
+struct Extent {
+  int32_t p, q;
+  Extent() = default;
+  __host__ __device__ constexpr Extent(int32_t s) : p(s), q(s) {}
+  __host__ __device__ constexpr Extent(int32_t a, int32_t b) : p(a), q(b) {}
+  __host__ __device__ constexpr operator int32_t() const { return p; }
+};
+
 // Control words at the head of every workspace.
 constexpr int kCtlErr = 0;       // bitmask of data errors seen by kernels
 constexpr int kCtlSlabsDone = 1; // slabs finished (last-arriver scan)

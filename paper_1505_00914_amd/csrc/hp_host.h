@@ -50,7 +50,7 @@ bool timing_slot(hipEvent_t *e0, hipEvent_t *e1);
 int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *hi, uint64_t *mask,
                int32_t *cx, int32_t *clo, int32_t *chi, int32_t chain_cap, int32_t *hx, int32_t *hy,
                int32_t hull_cap, int32_t *info, void *ws, size_t ws_bytes, hipStream_t s,
-               bool do_hull, int32_t ox = 0, int32_t oy = 0);
+               bool do_hull, int32_t ox = 0, int32_t oy = 0, int32_t q = 0);
 size_t single_ws_bytes(int64_t n, int32_t p);
 
 // Hull-tree shape over `positions` slots (slabs of 64, fan-in 64).

@@ -14,10 +14,10 @@ namespace hp {
 // missed one.
 // With a column window (wc > 0) L holds columns c0 .. c0 + wc - 1 only and
 // points of other columns are skipped (after their range check).
-__device__ __forceinline__ void fold_point_lds(int2 *L, int p, int x, int y, bool &bad, unsigned c0 = 0,
+__device__ __forceinline__ void fold_point_lds(int2 *L, Extent p, int x, int y, bool &bad, unsigned c0 = 0,
                                                unsigned wc = 0) {
   const unsigned xi = (unsigned)(x - 1), yi = (unsigned)(y - 1);
-  bool ok = (xi < (unsigned)p) & (yi < (unsigned)p);
+  bool ok = (xi < (unsigned)p.p) & (yi < (unsigned)p.q);
   bad |= !ok;
   const unsigned xr = xi - c0;
   if (wc) ok = ok & (xr < wc);
@@ -28,7 +28,7 @@ __device__ __forceinline__ void fold_point_lds(int2 *L, int p, int x, int y, boo
 }
 
 // A partial L entry in 32 bits: lo - 1 in the low half, hi + 1 in the high
-// half (the sentinel (p+1, -1) becomes (p, 0)); valid for p < 65535.
+// half (the sentinel (q+1, -1) becomes (q, 0)); valid for q < 65535 rows.
 __host__ __device__ __forceinline__ bool partial_packs(int64_t p) { return p < 65535; }
 __device__ __forceinline__ uint32_t pack_partial(int2 L) {
   return (uint32_t)(L.x - 1) | ((uint32_t)(L.y + 1) << 16);
@@ -46,9 +46,9 @@ __device__ __forceinline__ int2 load_coherent(const int2 *a) {
   return make_int2((int)(unsigned)(v & 0xffffffffull), (int)(unsigned)(v >> 32));
 }
 
-__device__ __forceinline__ void fold_point_global(int2 *L, int p, int x, int y, bool &bad) {
+__device__ __forceinline__ void fold_point_global(int2 *L, Extent p, int x, int y, bool &bad) {
   const unsigned xi = (unsigned)(x - 1), yi = (unsigned)(y - 1);
-  const bool ok = (xi < (unsigned)p) & (yi < (unsigned)p);
+  const bool ok = (xi < (unsigned)p.p) & (yi < (unsigned)p.q);
   bad |= !ok;
   if (ok) {
     const int2 cur = load_coherent(&L[xi]);
@@ -106,7 +106,7 @@ __device__ __forceinline__ void filt_flush(int2 *L, const int2 *wq, int qn) {
 }
 
 template <int VPT, bool LDS, bool WIN = false, bool FILT = false>
-__device__ __forceinline__ void gather(const int2 *L, int p, const int4 (&q)[VPT], Batch<VPT> &b,
+__device__ __forceinline__ void gather(const int2 *L, Extent p, const int4 (&q)[VPT], Batch<VPT> &b,
                                        bool &bad, unsigned c0 = 0, unsigned wc = 0,
                                        const int2 *filt = nullptr, int fshift = 0, int2 *wq = nullptr,
                                        int *qn = nullptr) {
@@ -118,7 +118,7 @@ __device__ __forceinline__ void gather(const int2 *L, int p, const int4 (&q)[VPT
     for (int h = 0; h < 2; ++h) {
       const int j = 2 * u + h;
       const unsigned xi = (unsigned)(xs[h] - 1), yi = (unsigned)(ys[h] - 1);
-      b.ok[j] = (xi < (unsigned)p) & (yi < (unsigned)p);
+      b.ok[j] = (xi < (unsigned)p.p) & (yi < (unsigned)p.q);
       bad |= !b.ok[j];
       if (WIN) {
         const unsigned xr = xi - c0;

@@ -34,7 +34,7 @@ __device__ __forceinline__ int4 load_stream(const int4 *a) {
   return make_int4(t.x, t.y, t.z, t.w);
 }
 template <int BLOCK, int VPT, bool LDS, bool WIN = false, bool FILT = false>
-__device__ __forceinline__ void stream_points(const int32_t *__restrict__ pts, int64_t n, int p,
+__device__ __forceinline__ void stream_points(const int32_t *__restrict__ pts, int64_t n, Extent p,
                                               int2 *L, int64_t wg, int64_t nwg, bool &bad,
                                               unsigned c0 = 0, unsigned wc = 0,
                                               const int2 *filt = nullptr, int fshift = 0,
@@ -140,7 +140,7 @@ __host__ __device__ __forceinline__ int64_t dyn_chunks(int64_t n, uintptr_t pts,
 }
 
 template <int BLOCK, int VPT, bool LDS, bool FILT = false>
-__device__ __forceinline__ void stream_points_dyn(const int32_t *__restrict__ pts, int64_t n, int p, int2 *L,
+__device__ __forceinline__ void stream_points_dyn(const int32_t *__restrict__ pts, int64_t n, Extent p, int2 *L,
                                                   int64_t wg, int64_t nwg, bool &bad, const DynArgs &D,
                                                   int *s_slot, const int2 *filt = nullptr, int fshift = 0,
                                                   int2 *wq = nullptr, int ox = 0, int oy = 0) {
@@ -291,7 +291,7 @@ __device__ __forceinline__ void reset_controls(const ResetArgs &R) {
 // and merged by k_finish.  Every workgroup writes its own range-error word.
 template <int BLOCK, int VPT, bool MERGE_ATOMIC>
 __global__ __launch_bounds__(BLOCK) void k_reduce_lds(const int32_t *__restrict__ pts, int64_t n,
-                                                      int32_t p, int2 *__restrict__ out_L,
+                                                      Extent p, int2 *__restrict__ out_L,
                                                       int32_t *__restrict__ wg_err, ResetArgs R, DynArgs D,
                                                       int2 org) {
   extern __shared__ int2 sL[];           // p pairs, then the flag word and the two grab slots
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_lds(const int32_t *__restrict_
   int *s_slot = &sL[p].y;                // sL[p].y and sL[p + 1].x
   reset_controls(R);
   if (threadIdx.x == 0) s_bad = 0;
-  for (int c = threadIdx.x; c < p; c += BLOCK) sL[c] = make_int2(p + 1, -1);
+  for (int c = threadIdx.x; c < p; c += BLOCK) sL[c] = make_int2(p.q + 1, -1);
   __syncthreads();
   bool bad = false;
   if (D.ctr)
@@ -320,8 +320,8 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_lds(const int32_t *__restrict_
         __hip_atomic_fetch_max(&out_L[c].y, mine.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   } else {
-    // the partial L packs (lo - 1, hi + 1) into 16 bits each (p is below
-    // the LDS limit, far below 2^16 - 1): half the bytes of the pairs
+    // the partial L packs (lo - 1, hi + 1) into 16 bits each (the strategy
+    // is taken only for fewer than 2^16 - 1 rows): half the bytes of the pairs
     uint32_t *out = reinterpret_cast<uint32_t *>(out_L) + (size_t)blockIdx.x * (size_t)p;
     for (int c = threadIdx.x; c < p; c += BLOCK) out[c] = pack_partial(sL[c]);
   }
@@ -338,7 +338,7 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_lds(const int32_t *__restrict_
 // folds the Gc partials.
 template <int BLOCK, int VPT>
 __global__ __launch_bounds__(BLOCK) void k_reduce_window(const int32_t *__restrict__ pts, int64_t n,
-                                                         int32_t p, int32_t W, int32_t wc,
+                                                         Extent p, int32_t W, int32_t wc,
                                                          uint32_t *__restrict__ out_part,
                                                          int32_t *__restrict__ wg_err, ResetArgs R, int2 org) {
   extern __shared__ int2 sL[];           // wc pairs, then one flag word
@@ -349,7 +349,7 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_window(const int32_t *__restri
   const unsigned c0 = (unsigned)w * (unsigned)wc;
   reset_controls(R);
   if (threadIdx.x == 0) s_bad = 0;
-  for (int c = threadIdx.x; c < wc; c += BLOCK) sL[c] = make_int2(p + 1, -1);
+  for (int c = threadIdx.x; c < wc; c += BLOCK) sL[c] = make_int2(p.q + 1, -1);
   __syncthreads();
   bool bad = false;
   stream_points<BLOCK, VPT, true, true>(pts, n, p, sL, cg, Gc, bad, c0, (unsigned)wc, nullptr, 0, nullptr, org.x,
@@ -357,7 +357,7 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_window(const int32_t *__restri
   if (bad) s_bad = 1;
   __syncthreads();
   const int ncol = min(wc, p - (int)c0);
-  if (partial_packs(p)) {
+  if (partial_packs(p.q)) {
     uint32_t *out = out_part + (size_t)cg * (size_t)p + c0;
     for (int c = threadIdx.x; c < ncol; c += BLOCK) out[c] = pack_partial(sL[c]);
   } else {
@@ -370,7 +370,7 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_window(const int32_t *__restri
 // One L in device memory, updated with filtered device-scope atomics.
 template <int BLOCK, int VPT>
 __global__ __launch_bounds__(BLOCK) void k_reduce_global(const int32_t *__restrict__ pts, int64_t n,
-                                                         int32_t p, int2 *L,
+                                                         Extent p, int2 *L,
                                                          int32_t *__restrict__ wg_err, ResetArgs R, DynArgs D,
                                                          int2 org) {
   __shared__ int s_bad;
@@ -394,7 +394,7 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_global(const int32_t *__restri
 // pass folds a sample of the points into L exactly (k_reduce_global over a
 // prefix of the points).  k_filter_build then bounds, per group of 2^fshift
 // columns, the largest sampled lo and the smallest sampled hi: F[g] =
-// (max lo, min hi), or (p + 1, -1) -- filter nothing -- when a column of the
+// (max lo, min hi), or (q + 1, -1) -- filter nothing -- when a column of the
 // group has no sampled point.  The main pass (k_reduce_filtered) keeps F in
 // LDS and sends a point on to the read of its column in L only when y < F.x
 // or y > F.y.  A point it skips has lo_final <= lo_sample <= F.x <= y and,
@@ -404,7 +404,7 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_global(const int32_t *__restri
 // ---------------------------------------------------------------------------
 template <int BLOCK, int VPT>
 __global__ __launch_bounds__(BLOCK) void k_reduce_filtered(const int32_t *__restrict__ pts, int64_t n,
-                                                           int32_t p, int2 *L, const int2 *__restrict__ F,
+                                                           Extent p, int2 *L, const int2 *__restrict__ F,
                                                            int32_t fshift, int32_t ngroups,
                                                            int32_t *__restrict__ wg_err, DynArgs D, int2 org) {
   // LDS: ngroups filter pairs, the flag word and two grab slots (2 pairs),

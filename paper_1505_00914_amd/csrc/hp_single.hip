@@ -20,7 +20,7 @@ namespace hp {
 // L initialisation and control words
 // ---------------------------------------------------------------------------
 __global__ void k_init(int32_t *ctl, int32_t *tree_ctr, int32_t nodes, int32_t *info,
-                       int32_t info_mode, int2 *L, int32_t p) {
+                       int32_t info_mode, int2 *L, Extent p) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t j = i; j < kCtlWords; j += stride) ctl[j] = 0;
@@ -36,13 +36,13 @@ __global__ void k_init(int32_t *ctl, int32_t *tree_ctr, int32_t nodes, int32_t *
     }
   }
   if (L)
-    for (int64_t c = i; c < p; c += stride) L[c] = make_int2(p + 1, -1);
+    for (int64_t c = i; c < p; c += stride) L[c] = make_int2(p.q + 1, -1);
 }
 
 // The sampled filter of the device-L reduce: per group of 2^fshift columns,
-// (largest sampled lo, smallest sampled hi), or (p + 1, -1) when a column of
+// (largest sampled lo, smallest sampled hi), or (q + 1, -1) when a column of
 // the group has no sampled point (see k_reduce_filtered).
-__global__ __launch_bounds__(256) void k_filter_build(const int2 *__restrict__ L, int32_t p, int32_t fshift,
+__global__ __launch_bounds__(256) void k_filter_build(const int2 *__restrict__ L, Extent p, int32_t fshift,
                                                       int32_t ngroups, int2 *__restrict__ F) {
   // a wave per group (up to 64 columns a pass)
   const int lane = threadIdx.x & (kWave - 1);
@@ -64,7 +64,7 @@ __global__ __launch_bounds__(256) void k_filter_build(const int2 *__restrict__ L
     mhi = min(mhi, __shfl_xor(mhi, d, kWave));
   }
   empty = __any(empty);
-  if (lane == 0) F[g] = empty ? make_int2(p + 1, -1) : make_int2(mlo, mhi);
+  if (lane == 0) F[g] = empty ? make_int2(p.q + 1, -1) : make_int2(mlo, mhi);
 }
 
 // ---------------------------------------------------------------------------
@@ -2116,7 +2116,7 @@ __global__ void k_sp_clear(uint64_t *__restrict__ L0, int64_t W0, uint64_t *__re
   }
 }
 
-__global__ __launch_bounds__(kSparseBlock) void k_sp_mark(const int2 *__restrict__ pts, int64_t n, int32_t p,
+__global__ __launch_bounds__(kSparseBlock) void k_sp_mark(const int2 *__restrict__ pts, int64_t n, Extent p,
                                                           int2 org, uint64_t *__restrict__ L0,
                                                           uint64_t *__restrict__ L1, int32_t *__restrict__ info) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -2124,7 +2124,7 @@ __global__ __launch_bounds__(kSparseBlock) void k_sp_mark(const int2 *__restrict
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     const int2 q = pts[i];
     const unsigned xi = (unsigned)(shift_by(q.x, org.x) - 1), yi = (unsigned)(shift_by(q.y, org.y) - 1);
-    if (xi >= (unsigned)p || yi >= (unsigned)p) {
+    if (xi >= (unsigned)p.p || yi >= (unsigned)p.q) {
       bad = true;
       continue;
     }
@@ -2184,7 +2184,7 @@ __global__ __launch_bounds__(kSparseBlock) void k_sp_write(const uint64_t *__res
                                                            const int32_t *__restrict__ off1,
                                                            int32_t *__restrict__ wordbase, int32_t *__restrict__ cx,
                                                            int32_t *__restrict__ clo, int32_t *__restrict__ chi,
-                                                           int32_t chain_cap, int32_t p) {
+                                                           int32_t chain_cap, int32_t q) {
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t i = (int64_t)blockIdx.x * (kSparseBlock / kWave) + threadIdx.x / kWave;
   if (i >= W1) return;
@@ -2203,12 +2203,12 @@ __global__ __launch_bounds__(kSparseBlock) void k_sp_write(const uint64_t *__res
   for (; v; v &= v - 1, ++j) {
     if (j >= chain_cap) continue;
     cx[j] = (int32_t)(w * kWave + __builtin_ctzll(v) + 1);
-    clo[j] = p + 1;
+    clo[j] = q + 1;
     chi[j] = -1;
   }
 }
 
-__global__ __launch_bounds__(kSparseBlock) void k_sp_fold(const int2 *__restrict__ pts, int64_t n, int32_t p,
+__global__ __launch_bounds__(kSparseBlock) void k_sp_fold(const int2 *__restrict__ pts, int64_t n, Extent p,
                                                           int2 org, const uint64_t *__restrict__ L0,
                                                           const int32_t *__restrict__ wordbase,
                                                           int32_t *__restrict__ clo, int32_t *__restrict__ chi,
@@ -2218,7 +2218,7 @@ __global__ __launch_bounds__(kSparseBlock) void k_sp_fold(const int2 *__restrict
     const int2 q = pts[i];
     const int y = shift_by(q.y, org.y);
     const unsigned xi = (unsigned)(shift_by(q.x, org.x) - 1), yi = (unsigned)(y - 1);
-    if (xi >= (unsigned)p || yi >= (unsigned)p) continue;
+    if (xi >= (unsigned)p.p || yi >= (unsigned)p.q) continue;
     const int idx = wordbase[xi >> 6] + __popcll(L0[xi >> 6] & ((1ull << (xi & 63)) - 1ull));
     if (idx >= chain_cap) continue;
     atomicMin(&clo[idx], y);
@@ -2226,10 +2226,10 @@ __global__ __launch_bounds__(kSparseBlock) void k_sp_fold(const int2 *__restrict
   }
 }
 
-__global__ void k_sp_fill(int32_t *__restrict__ lo, int32_t *__restrict__ hi, int32_t p) {
+__global__ void k_sp_fill(int32_t *__restrict__ lo, int32_t *__restrict__ hi, Extent p) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < p; i += stride) {
-    lo[i] = p + 1;
+    lo[i] = p.q + 1;
     hi[i] = -1;
   }
 }
@@ -2486,8 +2486,11 @@ static bool is_lds(int s) { return s == HP_STRATEGY_LDS || s == HP_STRATEGY_LDS_
 
 // allow_binned: the workspace holds the binned reduce's pages (else a plan
 // that would bin uses the sampled filter or the device L instead).
-static Plan1 choose(int64_t n, int32_t p, bool allow_binned = true) {
+// q: the rows of the box (0: the square, q = p).  Packed partial words need
+// fewer than 2^16 - 1 rows and the binned entries at most kBinPMax.
+static Plan1 choose(int64_t n, int32_t p, bool allow_binned = true, int32_t q = 0) {
   const DeviceInfo &D = device_info();
+  if (q <= 0) q = p;
   Plan1 P;
   int s = forced_strategy();
   if (s == HP_STRATEGY_AUTO) s = n * kSparseRatio < (int64_t)p ? HP_STRATEGY_SPARSE : tuned_strategy(n, p);
@@ -2500,7 +2503,9 @@ static Plan1 choose(int64_t n, int32_t p, bool allow_binned = true) {
     P.wc = p;
     return P;
   }
-  if (s == HP_STRATEGY_BINNED && ((int64_t)p > kBinPMax || !allow_binned)) s = HP_STRATEGY_SAMPLED;
+  if (s == HP_STRATEGY_BINNED && ((int64_t)p > kBinPMax || (int64_t)q > kBinPMax || !allow_binned))
+    s = HP_STRATEGY_SAMPLED;
+  if (s == HP_STRATEGY_LDS_PARTIAL && !partial_packs(q)) s = HP_STRATEGY_LDS;
   if (s == HP_STRATEGY_SAMPLED && n < kSampledMinPerCol * (int64_t)p) s = HP_STRATEGY_GLOBAL;
   P.W = 1;
   P.wc = p;
@@ -2556,11 +2561,12 @@ static Plan1 choose(int64_t n, int32_t p, bool allow_binned = true) {
 
 // Pairs of the reduce output region: G partial L arrays for the partial
 // variant, otherwise nothing (the device L is the merged-L region).
-static int64_t part_pairs_for(const Plan1 &P, int64_t n, int32_t p) {
+static int64_t part_pairs_for(const Plan1 &P, int64_t n, int32_t p, int32_t q = 0) {
   // the binned reduce writes pairs; the other partials pack into half a pair
+  // when the rows allow
   const int64_t entries = (int64_t)partial_count(P, n, p) * p;
   if (P.strategy == HP_STRATEGY_BINNED) return entries;
-  return partial_packs(p) ? (entries + 1) / 2 : entries;
+  return partial_packs(q > 0 ? q : p) ? (entries + 1) / 2 : entries;
 }
 
 static size_t bins_bytes_for(const Plan1 &P, int64_t n, int32_t p) {
@@ -2599,18 +2605,19 @@ static SparseLayout sparse_layout(int64_t n, int32_t p) {
   return Z;
 }
 
-static size_t ws_bytes_for(int64_t n, int32_t p, bool with_bins = true) {
+static size_t ws_bytes_for(int64_t n, int32_t p, bool with_bins = true, int32_t q = 0) {
+  if (q <= 0) q = p;
   const size_t sparse = sparse_layout(n, p).total;
   const TreeShape T = make_tree(p);
   const int64_t lds_max = device_info().lds_max_p;
   int64_t part = 0;
-  if ((int64_t)p <= lds_max) part = (lds_grid_max() * p + 1) / 2;
+  if ((int64_t)p <= lds_max && partial_packs(q)) part = (lds_grid_max() * p + 1) / 2;
   if ((int64_t)p <= kWinMax * lds_max) {
     const int64_t entries = (int64_t)kWinMaxGroups * p;
-    part = std::max<int64_t>(part, partial_packs(p) ? (entries + 1) / 2 : entries);
+    part = std::max<int64_t>(part, partial_packs(q) ? (entries + 1) / 2 : entries);
   }
   size_t bins = 0;
-  if (with_bins && (int64_t)p <= kBinPMax) {
+  if (with_bins && (int64_t)p <= kBinPMax && (int64_t)q <= kBinPMax) {
     const BinPlan B = bin_plan(n, p);
     part = std::max<int64_t>(part, (int64_t)bin_partials(B) * p);
     bins = bin_layout(B).total;
@@ -2629,7 +2636,7 @@ static hipError_t launch(K kernel, dim3 grid, dim3 block, size_t lds, hipStream_
 }
 
 template <int BLOCK, int VPT, bool ATOMIC>
-static hipError_t launch_lds(const Plan1 &P, const int32_t *pts, int64_t n, int32_t p, int2 *out,
+static hipError_t launch_lds(const Plan1 &P, const int32_t *pts, int64_t n, Extent p, int2 *out,
                              int32_t *wg_err, ResetArgs R, DynArgs D, int2 org, hipStream_t s, hipEvent_t e0,
                              hipEvent_t e1) {
   static bool attr_set = false;
@@ -2645,7 +2652,7 @@ static hipError_t launch_lds(const Plan1 &P, const int32_t *pts, int64_t n, int3
 }
 
 template <int BLOCK, int VPT>
-static hipError_t launch_reduce(const Plan1 &P, const int32_t *pts, int64_t n, int32_t p, int2 *Lm,
+static hipError_t launch_reduce(const Plan1 &P, const int32_t *pts, int64_t n, Extent p, int2 *Lm,
                                 int2 *part, int32_t *wg_err, ResetArgs R, DynArgs D, int2 org, hipStream_t s,
                                 hipEvent_t e0, hipEvent_t e1) {
   if (P.strategy == HP_STRATEGY_LDS)
@@ -2668,7 +2675,7 @@ static hipError_t launch_reduce(const Plan1 &P, const int32_t *pts, int64_t n, i
                 wg_err, R, D, org);
 }
 
-static hipError_t dispatch_reduce(const Plan1 &P, const int32_t *pts, int64_t n, int32_t p, int2 *Lm,
+static hipError_t dispatch_reduce(const Plan1 &P, const int32_t *pts, int64_t n, Extent p, int2 *Lm,
                                   int2 *part, int32_t *wg_err, ResetArgs R, DynArgs D, int2 org, hipStream_t s,
                                   hipEvent_t e0, hipEvent_t e1) {
 #define HP_CASE(B, V) \
@@ -2695,7 +2702,7 @@ static hipError_t dispatch_reduce(const Plan1 &P, const int32_t *pts, int64_t n,
 // only the last one shares chunks.  e0 is recorded at the start of the
 // sample pass and e1 at the end of the last pass.
 template <int BLOCK, int VPT>
-static hipError_t launch_sampled(const Plan1 &P, const int32_t *pts, int64_t n, int32_t p, int2 *Lm,
+static hipError_t launch_sampled(const Plan1 &P, const int32_t *pts, int64_t n, Extent p, int2 *Lm,
                                  int2 *F, int fshift, int ngroups, int64_t ns, int G1,
                                  int32_t *wg_err, DynArgs D, int2 org, hipStream_t s, hipEvent_t e0,
                                  hipEvent_t e1) {
@@ -2740,7 +2747,7 @@ static hipError_t launch_sampled(const Plan1 &P, const int32_t *pts, int64_t n, 
   return hipSuccess;
 }
 
-static hipError_t dispatch_sampled(const Plan1 &P, const int32_t *pts, int64_t n, int32_t p, int2 *Lm, int2 *F,
+static hipError_t dispatch_sampled(const Plan1 &P, const int32_t *pts, int64_t n, Extent p, int2 *Lm, int2 *F,
                                    int fshift, int ngroups, int64_t ns, int G1, int32_t *wg_err,
                                    DynArgs D, int2 org, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
 #define HP_CASE(B, V) \
@@ -2763,7 +2770,7 @@ static hipError_t dispatch_sampled(const Plan1 &P, const int32_t *pts, int64_t n
 // k_bin_fold into S partial arrays, and between rounds k_bin_merge into the
 // running L (array S) and the filter of the next round.  e0 is recorded at
 // the start of the first k_bin and e1 at the end of the last k_bin_fold.
-static hipError_t launch_binned(const int32_t *pts, int64_t n, int32_t p, int2 *part, uint16_t *F, char *bins,
+static hipError_t launch_binned(const int32_t *pts, int64_t n, Extent p, int2 *part, uint16_t *F, char *bins,
                                 int32_t *wg_err, ResetArgs R, int2 org, hipStream_t s, hipEvent_t e0,
                                 hipEvent_t e1) {
   const BinPlan B = bin_plan(n, p);
@@ -2778,9 +2785,9 @@ static hipError_t launch_binned(const int32_t *pts, int64_t n, int32_t p, int2 *
   A.nw = B.nw;
   A.G = B.G;
   const int nf = (int)(((int64_t)p + (1 << kBinFilterShift) - 1) >> kBinFilterShift);
-  // filter bounds in 8 bits: y - 1 < p in steps of 2^qs
+  // filter bounds in 8 bits: y - 1 < q in steps of 2^qs
   int qs = 0;
-  while ((((int64_t)p - 1) >> qs) > 255) ++qs;
+  while ((((int64_t)p.q - 1) >> qs) > 255) ++qs;
   if (B.nw > kBinNwMax || bin_lds_bytes(nf) > (size_t)device_info().lds_bytes || B.rounds * B.G > kMaxGrid)
     return hipErrorInvalidValue;
   static bool attr_set = false;
@@ -2908,7 +2915,7 @@ static bool node_lds_ready() {
 
 // The sparse path (HP_STRATEGY_SPARSE): work in the points and the occupied
 // columns, plus ceil(p/64) words of M; L is written only as the export.
-static int run_sparse(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *hi, uint64_t *mask,
+static int run_sparse(const int32_t *pts, int64_t n, Extent p, int32_t *lo, int32_t *hi, uint64_t *mask,
                       int32_t *cx, int32_t *clo, int32_t *chi, int32_t chain_cap, int32_t *hx, int32_t *hy,
                       int32_t hull_cap, int32_t *info, char *w, size_t ws_bytes, hipStream_t s, bool do_hull,
                       int2 org) {
@@ -2937,7 +2944,7 @@ static int run_sparse(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int
                      W1, cnt1);
   hipLaunchKernelGGL(k_sp_scan, dim3(1), dim3(kSparseScan), 0, s, (const int32_t *)cnt1, W1, off1, chain_cap, info);
   hipLaunchKernelGGL(k_sp_write, dim3(gs), dim3(kSparseBlock), 0, s, (const uint64_t *)L0, (const uint64_t *)L1, W1,
-                     (const int32_t *)off1, wordbase, cx, clo, chi, chain_cap, p);
+                     (const int32_t *)off1, wordbase, cx, clo, chi, chain_cap, p.q);
   if (e1)   // with no points the fold is an empty grid-stride loop, kept for the stop event
     hipExtLaunchKernelGGL(k_sp_fold, dim3(gp), dim3(kSparseBlock), 0, s, nullptr, e1, 0, P2, n, p, org,
                           (const uint64_t *)L0, (const int32_t *)wordbase, clo, chi, chain_cap);
@@ -2954,8 +2961,9 @@ static int run_sparse(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return set_error(HP_EDEVICE, "sparse path launch: %s", hipGetErrorString(e));
   if (!do_hull) return HP_OK;
-  // chain coordinates are at most p: below 2^15 the hull runs on 24-bit products
-  return hull_of_chain(cx, clo, chi, Z.hpos, hx, hy, hull_cap, info, w, Z.Yh, Z.T, s, p < (1 << 15));
+  // chain coordinates are at most max(p, q): below 2^15 the hull runs on 24-bit products
+  return hull_of_chain(cx, clo, chi, Z.hpos, hx, hy, hull_cap, info, w, Z.Yh, Z.T, s,
+                       std::max(p.p, p.q) < (1 << 15));
 }
 
 // Enqueue the whole single-cloud sequence.  Shared by hp_precondition,
@@ -2963,18 +2971,20 @@ static int run_sparse(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int
 int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *hi, uint64_t *mask,
                int32_t *cx, int32_t *clo, int32_t *chi, int32_t chain_cap, int32_t *hx, int32_t *hy,
                int32_t hull_cap, int32_t *info, void *ws, size_t ws_bytes, hipStream_t s,
-               bool do_hull, int32_t ox, int32_t oy) {
+               bool do_hull, int32_t ox, int32_t oy, int32_t q) {
   const int2 org = make_int2(ox, oy);
-  Plan1 P = choose(n, p);
+  if (q <= 0) q = p;
+  const Extent E(p, q);   // p columns of L, q rows
+  Plan1 P = choose(n, p, true, q);
   if (P.strategy == HP_STRATEGY_SPARSE)   // the callers have checked the arguments
-    return run_sparse(pts, n, p, lo, hi, mask, cx, clo, chi, chain_cap, hx, hy, hull_cap, info,
+    return run_sparse(pts, n, E, lo, hi, mask, cx, clo, chi, chain_cap, hx, hy, hull_cap, info,
                       static_cast<char *>(ws), ws_bytes, s, do_hull, org);
   const TreeShape T = make_tree(p);
   if (P.strategy == HP_STRATEGY_BINNED &&
-      ws_bytes < make_layout(p, p, part_pairs_for(P, n, p), T, bins_bytes_for(P, n, p)).total)
-    P = choose(n, p, false);   // a workspace without room for the bins
+      ws_bytes < make_layout(p, p, part_pairs_for(P, n, p, q), T, bins_bytes_for(P, n, p)).total)
+    P = choose(n, p, false, q);   // a workspace without room for the bins
   const bool binned = P.strategy == HP_STRATEGY_BINNED;
-  const Layout Y = make_layout(p, p, part_pairs_for(P, n, p), T, bins_bytes_for(P, n, p));
+  const Layout Y = make_layout(p, p, part_pairs_for(P, n, p, q), T, bins_bytes_for(P, n, p));
   if (ws_bytes < Y.total) return set_error(HP_ECAPACITY, "workspace too small: %zu < %zu bytes", ws_bytes, Y.total);
   char *w = static_cast<char *>(ws);
   int32_t *ctl = reinterpret_cast<int32_t *>(w + Y.ctl);
@@ -2997,7 +3007,7 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
     R.ctl = ctl;
   } else {
     const int ninit = (int)std::min<int64_t>(1024, std::max<int64_t>(1, ((int64_t)std::max<int64_t>(p, T.nodes) + 255) / 256));
-    hipLaunchKernelGGL(k_init, dim3(ninit), dim3(256), 0, s, ctl, tree, T.nodes, info, 0, Lm, p);
+    hipLaunchKernelGGL(k_init, dim3(ninit), dim3(256), 0, s, ctl, tree, T.nodes, info, 0, Lm, E);
     e = hipGetLastError();
     if (e != hipSuccess) return set_error(HP_EDEVICE, "k_init launch: %s", hipGetErrorString(e));
   }
@@ -3036,22 +3046,22 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
   timing_slot(&e0, &e1);
   int n_wg_err = P.G;
   if (sampled) {
-    e = dispatch_sampled(P, pts, n, p, Lm, reinterpret_cast<int2 *>(w + Y.filt), fshift, ngroups, ns, G1,
+    e = dispatch_sampled(P, pts, n, E, Lm, reinterpret_cast<int2 *>(w + Y.filt), fshift, ngroups, ns, G1,
                          wg_err, D, org, s, e0, e1);
     n_wg_err = G1 + nstages * P.G;
   } else if (binned) {
-    e = launch_binned(pts, n, p, part, reinterpret_cast<uint16_t *>(w + Y.filt), w + Y.bins, wg_err, R, org, s, e0,
+    e = launch_binned(pts, n, E, part, reinterpret_cast<uint16_t *>(w + Y.filt), w + Y.bins, wg_err, R, org, s, e0,
                       e1);
     n_wg_err = bin_plan(n, p).rounds * bin_plan(n, p).G;
   } else
-    e = dispatch_reduce(P, pts, n, p, Lm, part, wg_err, R, D, org, s, e0, e1);
+    e = dispatch_reduce(P, pts, n, E, Lm, part, wg_err, R, D, org, s, e0, e1);
   if (e != hipSuccess) return set_error(HP_EDEVICE, "reduce launch: %s", hipGetErrorString(e));
 
   FinishArgs A;
   memset(&A, 0, sizeof(A));
   A.part = partial ? part : Lm;
   A.G = partial ? partial_count(P, n, p) : 1;
-  A.packed = partial && !binned && partial_packs(p) ? 1 : 0;
+  A.packed = partial && !binned && partial_packs(q) ? 1 : 0;
   A.positions = p;
   A.p = p;
   A.Lm = Lm;
@@ -3093,7 +3103,7 @@ int run_single(const int32_t *pts, int64_t n, int32_t p, int32_t *lo, int32_t *h
   A.chi_out = chi;
   A.chain_cap = chain_cap;
   // coordinates of L are at most p: below 2^15 the hull runs on 24-bit products
-  const bool small = p < (1 << 15);
+  const bool small = std::max(p, q) < (1 << 15);
   HullArgs H;
   memset(&H, 0, sizeof(H));
   H.hx = hx;
@@ -3408,6 +3418,31 @@ extern "C" int hp_run_origin(const int32_t *pts, int64_t n, int32_t p, int32_t o
                     (hipStream_t)stream, true, ox, oy);
 }
 
+extern "C" int hp_workspace_bytes_rect(int64_t n, int32_t p, int32_t q, size_t *bytes) {
+  if (!bytes) return set_error(HP_EINVAL, "bytes is NULL");
+  if (p < 1 || p > HP_P_MAX || q < 1 || q > HP_P_MAX || n < 0) return set_error(HP_EINVAL, "bad n, p or q");
+  *bytes = ws_bytes_for(n, p, true, q);
+  return HP_OK;
+}
+
+extern "C" int hp_run_rect(const int32_t *pts, int64_t n, int32_t p, int32_t q, int32_t ox, int32_t oy,
+                           int32_t *lo, int32_t *hi, uint64_t *mask, int32_t *cx, int32_t *clo, int32_t *chi,
+                           int32_t chain_cap, int32_t *hx, int32_t *hy, int32_t hull_cap, int32_t *info, void *ws,
+                           size_t ws_bytes, void *stream) {
+  if (q < 1 || q > HP_P_MAX) return set_error(HP_EINVAL, "q = %d outside [1, %d]", q, HP_P_MAX);
+  const int rc = check_common(pts, n, p, lo, hi, cx, clo, chi, chain_cap, info, ws);
+  if (rc != HP_OK) return rc;
+  if (!hx || !hy) return set_error(HP_EINVAL, "hull arrays must not be NULL");
+  const int64_t need = 2 * std::min<int64_t>(n, p);
+  if ((int64_t)hull_cap < need)
+    return set_error(HP_ECAPACITY, "hull_cap %d < 2 min(n, p) = %lld", hull_cap, (long long)need);
+  const size_t want = ws_bytes_for(n, p, true, q);
+  if (ws_bytes < want && ws_bytes < ws_bytes_for(n, p, false, q))
+    return set_error(HP_ECAPACITY, "workspace too small: %zu < %zu bytes", ws_bytes, want);
+  return run_single(pts, n, p, lo, hi, mask, cx, clo, chi, chain_cap, hx, hy, hull_cap, info, ws, ws_bytes,
+                    (hipStream_t)stream, true, ox, oy, q);
+}
+
 extern "C" int hp_bbox_f32(const float *pts, int64_t n, float *box, void *ws, size_t ws_bytes, void *stream) {
   if (n < 0) return set_error(HP_EINVAL, "n = %lld < 0", (long long)n);
   if (n > 0 && !pts) return set_error(HP_EINVAL, "pts is NULL");
@@ -3461,10 +3496,16 @@ namespace hp {
 // (the LDS and window limits, packed partials, the two binned rounds, every
 // window count of the binned reduce), so the largest is at one of those
 // points or at p_cap itself.
+static size_t ws_bytes_any_q(int64_t n, int32_t c) {
+  // for any number of rows: packed partials and bins (q = c), unpacked
+  // partials with bins (q = 65535), neither (q = HP_P_MAX)
+  return std::max({ws_bytes_for(n, c, true, c), ws_bytes_for(n, c, true, 65535), ws_bytes_for(n, c, true, HP_P_MAX)});
+}
+
 static size_t ws_bytes_upto(int64_t n, int32_t p_cap) {
-  size_t m = ws_bytes_for(n, p_cap);
+  size_t m = ws_bytes_any_q(n, p_cap);
   const auto at = [&](int64_t q) {
-    if (q >= 1 && q < p_cap) m = std::max(m, ws_bytes_for(n, (int32_t)q));
+    if (q >= 1 && q < p_cap) m = std::max(m, ws_bytes_any_q(n, (int32_t)q));
   };
   const int64_t lm = device_info().lds_max_p;
   at(lm);
@@ -3536,30 +3577,33 @@ extern "C" int hp_run_auto(const int32_t *pts, int64_t n, int32_t axis, int32_t 
   e = hipMemcpyAsync(box, dbox, sizeof(box), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return set_error(HP_EDEVICE, "reading the box: %s", hipGetErrorString(e));
-  // Step 2 and the sweep axis: the side of the square that holds every
-  // point, the origin that moves the smallest x and y to 1, and the axis of
-  // the shorter side (exchanging x and y when the sweep runs along y)
+  // Step 2 and the sweep axis: the p x q box that holds every point (p
+  // columns along the sweep, q rows across it), the origin that moves the
+  // smallest x and y to 1, and the axis of the shorter side (exchanging x
+  // and y when the sweep runs along y), so that L has min(p, q) entries
   const int64_t ex = (int64_t)box[1] - box[0], ey = (int64_t)box[3] - box[2];
   const bool swap = axis == 1 || (axis == 2 && ey < ex);
   const int64_t bx0 = swap ? box[2] : box[0], bx1 = swap ? box[3] : box[1];
   const int64_t by0 = swap ? box[0] : box[2], by1 = swap ? box[1] : box[3];
-  const int64_t side = std::max(ex, ey) + 1;
+  const int64_t cols = bx1 - bx0 + 1, rows = by1 - by0 + 1;
   plan[0] = bx0;
   plan[1] = bx1;
   plan[2] = by0;
   plan[3] = by1;
-  plan[4] = side;
-  plan[5] = bx0 - 1;
-  plan[6] = by0 - 1;
-  plan[7] = swap ? 1 : 0;
-  if (side > HP_P_MAX) return set_error(HP_EINVAL, "extent %lld exceeds HP_P_MAX", (long long)side);
+  plan[4] = cols;
+  plan[5] = rows;
+  plan[6] = bx0 - 1;
+  plan[7] = by0 - 1;
+  plan[8] = swap ? 1 : 0;
+  if (cols > HP_P_MAX || rows > HP_P_MAX)
+    return set_error(HP_EINVAL, "extent %lld x %lld exceeds HP_P_MAX", (long long)cols, (long long)rows);
   if (p_cap == 0) return HP_OK;   // the plan alone
-  const int32_t p = (int32_t)side;
-  if (p > p_cap) return set_error(HP_ECAPACITY, "side %d > p_cap %d", p, p_cap);
+  const int32_t p = (int32_t)cols, q = (int32_t)rows;
+  if (p > p_cap) return set_error(HP_ECAPACITY, "p = %d columns > p_cap %d", p, p_cap);
   int rc = check_common(pts, n, p, lo, hi, cx, clo, chi, chain_cap, info, ws);
   if (rc == HP_OK) rc = check_hull_out(n, p, hx, hy, hull_cap);
   if (rc != HP_OK) return rc;
-  const size_t need = A.path + ws_bytes_for(n, p);
+  const size_t need = A.path + ws_bytes_for(n, p, true, q);
   if (ws_bytes < need) return set_error(HP_ECAPACITY, "workspace too small for p = %d: %zu < %zu bytes", p, ws_bytes, need);
   const int32_t *src = pts;
   if (swap) {
@@ -3571,7 +3615,7 @@ extern "C" int hp_run_auto(const int32_t *pts, int64_t n, int32_t axis, int32_t 
   // the origin is read modulo 2^32 by the reduce
   const int32_t ox = (int32_t)(uint32_t)(uint64_t)(bx0 - 1), oy = (int32_t)(uint32_t)(uint64_t)(by0 - 1);
   return run_single(src, n, p, lo, hi, mask, cx, clo, chi, chain_cap, hx, hy, hull_cap, info, w + A.path,
-                    ws_bytes - A.path, s, true, ox, oy);
+                    ws_bytes - A.path, s, true, ox, oy, q);
 }
 
 extern "C" int hp_run_auto_f32_workspace_bytes(int64_t n, int32_t p, size_t *bytes) {

@@ -244,6 +244,30 @@ def _to_i32(v: int) -> int:
     return ((int(v) + (1 << 31)) % (1 << 32)) - (1 << 31)
 
 
+def workspace_bytes_rect(n: int, p: int, q: int) -> int:
+    size = ctypes.c_size_t()
+    _lib.call("hp_workspace_bytes_rect", n, p, q, ctypes.byref(size))
+    return size.value
+
+
+def hp_run_rect(points: torch.Tensor, p: int, q: int, origin: tuple[int, int], buf: Buffers, stream=None) -> None:
+    """Enqueue the fused path on the p x q box (p columns, q rows), the
+    points read through ``origin`` (no sync)."""
+    n = _check_points(points)
+    _lib.call("hp_run_rect", _ptr(points), n, p, q, _to_i32(origin[0]), _to_i32(origin[1]), _ptr(buf.lo),
+              _ptr(buf.hi), _ptr(buf.mask), _ptr(buf.cx), _ptr(buf.clo), _ptr(buf.chi), buf.cx.numel(),
+              _ptr(buf.hx), _ptr(buf.hy), buf.hx.numel(), _ptr(buf.info), _ptr(buf.ws), buf.ws.numel(),
+              _stream(stream))
+
+
+def run_rect(points: torch.Tensor, p: int, q: int, export_L: bool = True, origin=(0, 0)) -> dict:
+    """One cloud on the p x q box end to end (allocates its buffers)."""
+    n = points.shape[0]
+    buf = Buffers.allocate(n, p, points.device, export_L, workspace_bytes_rect(n, p, q))
+    hp_run_rect(points, p, q, origin, buf)
+    return collect(buf)
+
+
 def bbox_workspace_bytes() -> int:
     size = ctypes.c_size_t()
     _lib.call("hp_bbox_workspace_bytes", ctypes.byref(size))
@@ -294,7 +318,7 @@ def hp_run_auto(points: torch.Tensor, axis: str, p_cap: int, buf: Buffers | None
     n = _check_points(points)
     if axis not in _AXES:
         raise ValueError("axis must be 'x', 'y' or 'auto'")
-    plan = (ctypes.c_int64 * 8)()
+    plan = (ctypes.c_int64 * 9)()
     b = buf
     cap = b.cx.numel() if b is not None and b.cx is not None else 0
     hcap = b.hx.numel() if b is not None and b.hx is not None else 0
@@ -304,14 +328,15 @@ def hp_run_auto(points: torch.Tensor, axis: str, p_cap: int, buf: Buffers | None
               _ptr(b.hx) if b else None, _ptr(b.hy) if b else None, hcap, _ptr(b.info) if b else None,
               _ptr(b.ws) if b else None, b.ws.numel() if b else 0, _stream(stream))
     v = list(plan)
-    return {"box": tuple(v[0:4]), "p": v[4], "origin": (v[5], v[6]), "axis": "y" if v[7] else "x"}
+    return {"box": tuple(v[0:4]), "p": v[4], "q": v[5], "origin": (v[6], v[7]), "axis": "y" if v[8] else "x"}
 
 
 def run_auto(points: torch.Tensor, export_L: bool = True, axis: str = "x", p_cap: int | None = None) -> dict:
     """Steps 1 and 2, then the path, all in hp_run_auto: the bounding box on
-    the device, p and the origin from it, and the fused path on the
-    translated points.  Outputs are in translated coordinates; ``origin``
-    maps them back.
+    the device, the p x q box (p columns along the sweep, q rows) and the
+    origin from it, and the fused path on the translated points, L holding
+    p entries with the empty value (q + 1, -1).  Outputs are in translated
+    coordinates; ``origin`` maps them back.
 
     ``axis`` picks the sweep: "x" (Algorithm 1 as written), "y" (the points
     with x and y exchanged, one extra pass), or "auto", the axis of the

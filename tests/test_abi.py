@@ -267,7 +267,7 @@ def test_run_auto_arguments_rejected_before_any_device_call():
     lib = _lib.load()
     E, C = _lib.HP_EINVAL, _lib.HP_ECAPACITY
     d = ctypes.c_void_p(1 << 20)
-    plan = (ctypes.c_int64 * 8)()
+    plan = (ctypes.c_int64 * 9)()
     fplan = (ctypes.c_double * 7)()
     size = ctypes.c_size_t()
     assert lib.hp_run_auto_workspace_bytes(100, 3, 64, ctypes.byref(size)) == E
@@ -294,6 +294,33 @@ def test_run_auto_arguments_rejected_before_any_device_call():
     assert lib.hp_run_auto_f32(*fargs(cap=63)) == C                  # chain_cap < min(n, p)
     assert lib.hp_run_auto_f32(*fargs(hcap=127)) == C                # hull_cap < 2 min(n, p)
     assert lib.hp_run_auto_f32(*fargs(ws_bytes=need - 1)) == C
+
+
+def test_rect_arguments_rejected_before_any_device_call():
+    """hp_run_rect: q outside [1, HP_P_MAX] and the usual argument errors
+    come back before any device call; the workspace query covers the rows."""
+    lib = _lib.load()
+    E, C = _lib.HP_EINVAL, _lib.HP_ECAPACITY
+    d = ctypes.c_void_p(1 << 20)
+    v = ctypes.c_size_t()
+    assert lib.hp_workspace_bytes_rect(100, 64, 0, ctypes.byref(v)) == E
+    assert lib.hp_workspace_bytes_rect(100, 64, _lib.HP_P_MAX + 1, ctypes.byref(v)) == E
+    assert lib.hp_workspace_bytes_rect(100_000, 4096, 4096, ctypes.byref(v)) == 0
+    square = v.value
+    assert lib.hp_workspace_bytes(100_000, 4096, ctypes.byref(v)) == 0 and v.value == square
+    # 2^16 rows and more: the partial words no longer pack (no LDS-partial
+    # area, unpacked window entries); beyond 2^20 rows no binned area at all
+    assert lib.hp_workspace_bytes_rect(100_000, 4096, 1 << 16, ctypes.byref(v)) == 0 and v.value > 0
+    wide_rows = v.value
+    assert lib.hp_workspace_bytes_rect(100_000, 4096, 1 << 21, ctypes.byref(v)) == 0
+    assert 0 < v.value <= wide_rows
+    args = lambda q=64, n=100, p=64, cap=100, ws_bytes=1 << 30: (d, n, p, q, 0, 0, None, None, None, d, d, d, cap,
+                                                                   d, d, 200, d, d, ws_bytes, None)
+    assert lib.hp_run_rect(*args(q=0)) == E
+    assert lib.hp_run_rect(*args(q=_lib.HP_P_MAX + 1)) == E
+    assert lib.hp_run_rect(*args(p=0)) == E
+    assert lib.hp_run_rect(*args(cap=63)) == C
+    assert lib.hp_run_rect(*args(ws_bytes=16)) == C
 
 
 @pytest.mark.parametrize("n", [1000, 3_000_000, 40_000_000])

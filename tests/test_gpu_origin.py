@@ -29,7 +29,7 @@ def _moved(kind, n, p, seed, off):
 def _compare_auto(got, want, label):
     assert got["status"] == 0, f"{label}: status {got['status']}"
     assert got["box"] == want["box"], f"{label}: box {got['box']} != {want['box']}"
-    assert got["p"] == want["p"], f"{label}: p {got['p']} != {want['p']}"
+    assert got["p"] == want["p"] and got["q"] == want["q"], f"{label}: p x q {got['p']} x {got['q']}"
     assert got["origin"] == want["origin"], f"{label}: origin"
     assert got["k"] == want["k"], f"{label}: k {got['k']} != {want['k']}"
     for key in ("lo", "hi", "mask", "x", "clo", "chi", "hull"):
@@ -68,9 +68,9 @@ def test_bbox_single_extreme(hp):
 def test_run_auto(hp, kind, n, p, seed, off):
     pts = _moved(kind, n, p, seed, off)
     print(f"[case] run_auto {kind} n={n} p={p} off={off}", flush=True)
-    want = oracle.auto(pts)
+    want = oracle.auto_rect(pts)
     dev = torch.from_numpy(pts).cuda()
-    strategies = (1, 2, 3, 4, 5) if want["p"] <= hp.lds_max_p() else (2, 4, 5)
+    strategies = (1, 2, 3, 4, 5, 7) if want["p"] <= hp.lds_max_p() else (2, 4, 5, 7)
     for s in strategies:
         hp.set_strategy(s)
         _compare_auto(hp.run_auto(dev), want, f"{kind}-{n}/strategy{s}")
@@ -86,7 +86,7 @@ def test_run_auto(hp, kind, n, p, seed, off):
 def test_run_auto_small(hp, pts):
     a = np.asarray(pts, np.int32)
     print(f"[case] run_auto small {pts}", flush=True)
-    _compare_auto(hp.run_auto(torch.from_numpy(a).cuda()), oracle.auto(a), str(pts))
+    _compare_auto(hp.run_auto(torch.from_numpy(a).cuda()), oracle.auto_rect(a), str(pts))
 
 
 def test_run_auto_extent_too_large(hp):
@@ -258,11 +258,13 @@ def test_run_auto_axis(hp, axis, wide):
     w, h = (4000, 300) if wide else (300, 4000)
     a = np.stack([rng.integers(0, w, 200_000), rng.integers(0, h, 200_000)], 1).astype(np.int32) - 1234
     print(f"[case] run_auto axis={axis} wide={wide}", flush=True)
-    want = oracle.auto(a, axis=axis)
+    want = oracle.auto_rect(a, axis=axis)
     got = hp.run_auto(torch.from_numpy(a).cuda(), axis=axis)
     assert got["axis"] == want["axis"]
     if axis == "auto":
+        # L of the shorter side, rows of the longer
         assert got["axis"] == ("y" if wide else "x")
+        assert got["lo"].shape[0] == got["p"] == min(got["p"], got["q"])
     _compare_auto(got, want, f"axis {axis}")
 
 
@@ -273,7 +275,7 @@ def test_run_auto_one_call_with_cap(hp, axis):
     side is refused with the plan still returned."""
     rng = np.random.default_rng(77)
     a = np.stack([rng.integers(0, 9000, 300_000), rng.integers(0, 2500, 300_000)], 1).astype(np.int32) + 4321
-    want = oracle.auto(a, axis=axis)
+    want = oracle.auto_rect(a, axis=axis)
     dev = torch.from_numpy(a).cuda()
     print(f"[case] run_auto one call axis={axis} p={want['p']}", flush=True)
     for cap in (want["p"], want["p"] + 70_000, 1 << 20):

@@ -102,9 +102,10 @@ def test_sparse_auto_moved_and_axis(hp):
     dev = torch.from_numpy(a).cuda()
     for axis in ("x", "auto"):
         print(f"[case] sparse run_auto axis={axis}", flush=True)
-        want = oracle.auto(a, axis=axis)
+        want = oracle.auto_rect(a, axis=axis)
         got = hp.run_auto(dev, axis=axis)
-        assert got["axis"] == want["axis"] and got["p"] == want["p"] and got["origin"] == want["origin"]
+        assert got["axis"] == want["axis"] and got["origin"] == want["origin"]
+        assert (got["p"], got["q"]) == (want["p"], want["q"])
         for key in ("lo", "hi", "mask", "x", "clo", "chi", "hull"):
             assert np.array_equal(got[key], want[key]), key
 
