@@ -473,10 +473,13 @@ typedef struct hp_server hp_server;
  * block (its points when they come from host memory, its workspace, its
  * device outputs): a request is admitted, in arrival order, only when its
  * block fits.  max_batch bounds the requests joined into one launch
- * sequence.  Up to four batches are in flight: host points are copied on
- * one stream, batches compute in order on a second and their outputs return
- * on a third, so the copies of later batches overlap the current one's
- * kernels. */
+ * sequence.  Up to four batches are in flight, each on a stream of its own
+ * that carries its points in, its kernels and its outputs back, so batches
+ * (and the copies of one with the kernels of another) run concurrently; a
+ * request that arrives while others are in flight starts on the next free
+ * stream; a request that finds the server idle is issued by the thread
+ * that submits it.  The scheduler thread polls for 2 ms after its last work
+ * before it sleeps. */
 int hp_server_create(size_t device_budget_bytes, int32_t max_batch, hp_server **server);
 
 /* Device bytes of the arena block a request of n points with side p needs
@@ -493,7 +496,11 @@ int hp_server_request_bytes(int64_t n, int32_t p, int32_t on_device, size_t *byt
  *   chain_cap  >= min(n, p)
  *   info       HOST int32[HP_INFO_WORDS]: status, k, s, h
  * Outputs are written before the request completes (page-locked memory
- * keeps those copies asynchronous too).  Returns HP_OK and *ticket;
+ * keeps those copies asynchronous too).  When the six output arrays lie
+ * back to back in one host buffer with c = min(n, p) entries per chain
+ * array (cx at b, clo at b + c, chi at b + 2c, hx at b + 3c, hy at b + 5c,
+ * info at b + 7c), they come back in a single copy; otherwise one copy
+ * each.  Returns HP_OK and *ticket;
  * HP_ECAPACITY when the request alone exceeds the budget; HP_EINVAL for bad
  * arguments.  Data errors (a point outside [1, p]) go to info[0]. */
 int hp_server_submit(hp_server *server, const int32_t *pts, int64_t n, int32_t p, int32_t on_device,

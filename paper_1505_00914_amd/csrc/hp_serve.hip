@@ -6,20 +6,25 @@
 // outputs and info words).  The arena is allocated once, at creation, with
 // the caller's budget; a request waits in FIFO order until its block fits.
 //
-// Scheduling: up to kSlots batches are in flight.  Whenever a slot is free
-// and requests are waiting, the thread admits as many as fit (at most
-// max_batch), copies their points and the batch's work tables to the device
-// on the copy stream and, once those copies are done, runs on the compute
-// stream one batched launch sequence for the small requests and the
-// single-cloud sequence for each request of at least kServeSingleN points
-// (which fills the device by itself); every request's outputs are then
-// copied back into the caller's host buffers behind them.  A batch completes when its last copy
-// has landed; its requests are then marked done with the completion time
-// and their blocks return to the arena.  Copies of the next batch overlap
-// the kernels of the current one.
+// Scheduling: up to kSlots batches are in flight, each on a stream of its
+// own.  Whenever a slot is free and requests are waiting, the thread admits
+// as many as fit (at most max_batch) and enqueues on the slot's stream, in
+// order: their points and the batch's work tables (host to device), one
+// batched launch sequence for the small requests or the single-cloud
+// sequence for each request of at least kServeSingleN points (which fills
+// the device by itself), and every request's outputs (device to host) right
+// behind its kernels.  A request completes when its last copy has landed; it
+// is then marked done with the completion time and its block returns to the
+// arena.  Batches in different slots run concurrently: the copies and
+// kernels of a request that arrives while another is being served start at
+// once on the next free slot's stream instead of queueing behind it.  A
+// request that finds nothing waiting and a slot free is issued by the
+// submitting thread itself.  When idle, the scheduler keeps polling for
+// kIdleSpinNs before it sleeps, so completions are seen without a wake-up.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -38,7 +43,8 @@ namespace hp {
 
 namespace {
 
-constexpr int kSlots = 4;                   // batches in flight
+constexpr int kSlots = 4;                   // batches in flight, one stream each
+constexpr int64_t kIdleSpinNs = 2000000;    // polling before the thread sleeps
 constexpr size_t kTableBytes = 8u << 20;    // work-table image capacity of one batch
 // Requests with at least this many points run the single-cloud launch
 // sequence, which spreads one cloud over the whole device; smaller ones
@@ -70,7 +76,8 @@ struct Request {
   size_t o_pts = 0, o_slots = 0, o_chain = 0, o_hull = 0, o_info = 0, bytes = 0;
   size_t table_bound = 0;
   size_t block = Arena::kFail;
-  hipEvent_t ev = nullptr;       // recorded after the request's last output copy
+  hipEvent_t ev = nullptr;       // recorded after the request's last output copy; none for the
+                                 // slot's last request, which completes when the stream is idle
   bool done = false;
   int64_t done_ns = 0;
 };
@@ -78,7 +85,9 @@ struct Request {
 using RequestPtr = std::shared_ptr<Request>;
 
 struct Slot {
-  bool busy = false;
+  hipStream_t stream = nullptr;  // copies in, kernels and copies out of this slot's batches
+  std::atomic<bool> busy{false}; // claimed (changed under the lock)
+  std::atomic<bool> live{false}; // reqs published: the scheduler may poll the slot
   std::vector<RequestPtr> reqs;  // in the order their events are recorded
   size_t head = 0;               // reqs[0, head) have completed and are not touched again
   std::vector<hipEvent_t> events;  // taken from the pool for this batch
@@ -97,12 +106,13 @@ struct hp_server {
   int64_t lds_p_max = 1;
   hp::Arena arena;
   char *dmem = nullptr;
-  hipStream_t copy = nullptr, comp = nullptr, out = nullptr;   // copies in, kernels, copies out
   hp::Slot slot[hp::kSlots];
-  std::vector<hipEvent_t> ev_pool;   // used by the scheduler thread only
+  std::mutex ev_mu;                  // guards ev_pool (issuing threads and the scheduler)
+  std::vector<hipEvent_t> ev_pool;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<hp::RequestPtr> pending;
+  std::atomic<int64_t> npending{0};   // pending.size(), readable without the lock
   std::unordered_map<int64_t, hp::RequestPtr> live;   // submitted and not yet waited for
   int64_t next_id = 0;
   bool stop = false;
@@ -128,12 +138,11 @@ void layout_request(Request &r) {
   if (!r.on_device) o = align256(o + 8 * (size_t)r.n);
   r.o_slots = o;
   o += r.ws_bytes;
+  // chain, hull and info back to back, as one host buffer may hold them
   r.o_chain = o;
-  o = align256(o + 3 * sizeof(int32_t) * (size_t)r.cap);
-  r.o_hull = o;
-  o = align256(o + 4 * sizeof(int32_t) * (size_t)r.cap);
-  r.o_info = o;
-  o = align256(o + sizeof(int32_t) * HP_INFO_WORDS);
+  r.o_hull = o + 3 * sizeof(int32_t) * (size_t)r.cap;
+  r.o_info = r.o_hull + 4 * sizeof(int32_t) * (size_t)r.cap;
+  o = align256(r.o_info + sizeof(int32_t) * HP_INFO_WORDS);
   r.bytes = o;
   r.table_bound = r.single ? 0 : BatchTables::cloud_image_bound(r.n, r.p, r.tree);
 }
@@ -150,11 +159,22 @@ void finish(hp_server *S, Request *r, int status, int64_t t) {
 
 // Free a slot whose requests are all done: its events go back to the pool.
 void release_slot(hp_server *S, Slot &sl) {
-  for (hipEvent_t e : sl.events) S->ev_pool.push_back(e);
+  {
+    std::lock_guard<std::mutex> g(S->ev_mu);
+    for (hipEvent_t e : sl.events) S->ev_pool.push_back(e);
+  }
   sl.events.clear();
   sl.reqs.clear();
   sl.head = 0;
+  sl.live.store(false, std::memory_order_release);
   sl.busy = false;
+}
+
+// Whether a request's copies have landed: its event, or for the slot's last
+// request (no event recorded behind it) the slot's stream being idle, which
+// the runtime reports sooner than an event placed after the same copy.
+hipError_t request_state(const Slot &sl, const Request *r) {
+  return r->ev ? hipEventQuery(r->ev) : hipStreamQuery(sl.stream);
 }
 
 // Complete the requests of a slot whose events have fired (in recording
@@ -164,7 +184,7 @@ bool poll_slot(hp_server *S, Slot &sl, bool &busy) {
   const int64_t t = now_ns();
   while (sl.head < sl.reqs.size()) {
     Request *r = sl.reqs[sl.head].get();
-    const hipError_t q = hipEventQuery(r->ev);
+    const hipError_t q = request_state(sl, r);
     if (q == hipErrorNotReady) break;
     finish(S, r, q == hipSuccess ? HP_OK : HP_EDEVICE, t);
     ++sl.head;
@@ -178,12 +198,14 @@ bool poll_slot(hp_server *S, Slot &sl, bool &busy) {
 
 hipEvent_t pool_event(hp_server *S, Slot &sl) {
   hipEvent_t e = nullptr;
-  if (!S->ev_pool.empty()) {
-    e = S->ev_pool.back();
-    S->ev_pool.pop_back();
-  } else if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
-    return nullptr;
+  {
+    std::lock_guard<std::mutex> g(S->ev_mu);
+    if (!S->ev_pool.empty()) {
+      e = S->ev_pool.back();
+      S->ev_pool.pop_back();
+    }
   }
+  if (!e && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
   sl.events.push_back(e);
   return e;
 }
@@ -206,6 +228,7 @@ hipError_t issue(hp_server *S, Slot &sl, std::vector<RequestPtr> &take) {
   std::vector<const int32_t *> cpts;
   std::vector<const int32_t *> dpts(take.size());
   hipError_t e = hipSuccess;
+  const hipStream_t st = sl.stream;
   auto outputs = [&](Request &r) {
     char *base = S->dmem + r.block;
     CloudOut o;
@@ -231,22 +254,28 @@ hipError_t issue(hp_server *S, Slot &sl, std::vector<RequestPtr> &take) {
     int32_t *dst = reinterpret_cast<int32_t *>(S->dmem + r.block + r.o_pts);
     dpts[b] = dst;
     if (r.n == 0) return hipSuccess;
-    return hipMemcpyAsync(dst, r.pts, 8 * (size_t)r.n, hipMemcpyHostToDevice, S->copy);
+    return hipMemcpyAsync(dst, r.pts, 8 * (size_t)r.n, hipMemcpyHostToDevice, st);
   };
   auto copy_out = [&](Request &r) -> hipError_t {
     const char *base = S->dmem + r.block;
+    const int32_t *h = r.cx;
+    const size_t c4 = (size_t)r.cap;
+    if (h && r.clo == h + c4 && r.chi == h + 2 * c4 && r.hx == h + 3 * c4 && r.hy == h + 5 * c4 &&
+        r.info == h + 7 * c4)   // one host buffer laid out as the device block
+      return hipMemcpyAsync(r.cx, base + r.o_chain, sizeof(int32_t) * (7 * c4 + HP_INFO_WORDS),
+                            hipMemcpyDeviceToHost, st);
     const int32_t *chain = reinterpret_cast<const int32_t *>(base + r.o_chain);
     const int32_t *hull = reinterpret_cast<const int32_t *>(base + r.o_hull);
     const size_t c = sizeof(int32_t) * (size_t)r.cap;
     hipError_t x = hipSuccess;
     if (r.cap > 0) {
-      if ((x = hipMemcpyAsync(r.cx, chain, c, hipMemcpyDeviceToHost, S->out)) != hipSuccess) return x;
-      if ((x = hipMemcpyAsync(r.clo, chain + r.cap, c, hipMemcpyDeviceToHost, S->out)) != hipSuccess) return x;
-      if ((x = hipMemcpyAsync(r.chi, chain + 2 * (size_t)r.cap, c, hipMemcpyDeviceToHost, S->out)) != hipSuccess) return x;
-      if ((x = hipMemcpyAsync(r.hx, hull, 2 * c, hipMemcpyDeviceToHost, S->out)) != hipSuccess) return x;
-      if ((x = hipMemcpyAsync(r.hy, hull + 2 * (size_t)r.cap, 2 * c, hipMemcpyDeviceToHost, S->out)) != hipSuccess) return x;
+      if ((x = hipMemcpyAsync(r.cx, chain, c, hipMemcpyDeviceToHost, st)) != hipSuccess) return x;
+      if ((x = hipMemcpyAsync(r.clo, chain + r.cap, c, hipMemcpyDeviceToHost, st)) != hipSuccess) return x;
+      if ((x = hipMemcpyAsync(r.chi, chain + 2 * (size_t)r.cap, c, hipMemcpyDeviceToHost, st)) != hipSuccess) return x;
+      if ((x = hipMemcpyAsync(r.hx, hull, 2 * c, hipMemcpyDeviceToHost, st)) != hipSuccess) return x;
+      if ((x = hipMemcpyAsync(r.hy, hull + 2 * (size_t)r.cap, 2 * c, hipMemcpyDeviceToHost, st)) != hipSuccess) return x;
     }
-    return hipMemcpyAsync(r.info, base + r.o_info, sizeof(int32_t) * HP_INFO_WORDS, hipMemcpyDeviceToHost, S->out);
+    return hipMemcpyAsync(r.info, base + r.o_info, sizeof(int32_t) * HP_INFO_WORDS, hipMemcpyDeviceToHost, st);
   };
   // small requests: points, tables, one batched launch, outputs, one event
   size_t nsmall = 0;
@@ -264,43 +293,41 @@ hipError_t issue(hp_server *S, Slot &sl, std::vector<RequestPtr> &take) {
     if (img > kTableBytes) return hipErrorInvalidValue;   // excluded by admission
     DeviceBatch D;
     batch_image(t, clouds, cpts, sl.himg, static_cast<char *>(sl.dimg), D);
-    if ((e = hipMemcpyAsync(sl.dimg, sl.himg, img, hipMemcpyHostToDevice, S->copy)) != hipSuccess) return e;
-    hipEvent_t copied = pool_event(S, sl), computed = pool_event(S, sl), done = pool_event(S, sl);
-    if (!copied || !computed || !done) return hipErrorOutOfMemory;
-    if ((e = hipEventRecord(copied, S->copy)) != hipSuccess) return e;
-    if ((e = hipStreamWaitEvent(S->comp, copied, 0)) != hipSuccess) return e;
-    if ((e = enqueue_batch(D, S->comp)) != hipSuccess) return e;
-    if ((e = hipEventRecord(computed, S->comp)) != hipSuccess) return e;
-    if ((e = hipStreamWaitEvent(S->out, computed, 0)) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(sl.dimg, sl.himg, img, hipMemcpyHostToDevice, st)) != hipSuccess) return e;
+    if ((e = enqueue_batch(D, st)) != hipSuccess) return e;
     for (size_t b = 0; b < nsmall; ++b)
       if ((e = copy_out(*take[b])) != hipSuccess) return e;
-    if ((e = hipEventRecord(done, S->out)) != hipSuccess) return e;
+    hipEvent_t done = nullptr;   // the slot's last work: completes with its stream
+    if (nsmall < take.size()) {
+      if (!(done = pool_event(S, sl))) return hipErrorOutOfMemory;
+      if ((e = hipEventRecord(done, st)) != hipSuccess) return e;
+    }
     for (size_t b = 0; b < nsmall; ++b) take[b]->ev = done;
   }
-  // large requests, each behind its own copy
+  // the other requests one by one, each with its own copies
   for (size_t b = nsmall; b < take.size(); ++b) {
     Request &r = *take[b];
     if ((e = copy_in(b)) != hipSuccess) return e;
-    hipEvent_t copied = pool_event(S, sl), computed = pool_event(S, sl), done = pool_event(S, sl);
-    if (!copied || !computed || !done) return hipErrorOutOfMemory;
-    if ((e = hipEventRecord(copied, S->copy)) != hipSuccess) return e;
-    if ((e = hipStreamWaitEvent(S->comp, copied, 0)) != hipSuccess) return e;
     const CloudOut o = outputs(r);
     if (run_single(dpts[b], r.n, r.p, nullptr, nullptr, nullptr, o.cx, o.clo, o.chi, o.chain_cap, o.hx, o.hy,
-                   o.hull_cap, o.info, S->dmem + r.block + r.o_slots, r.ws_bytes, S->comp, true) != HP_OK)
+                   o.hull_cap, o.info, S->dmem + r.block + r.o_slots, r.ws_bytes, st, true) != HP_OK)
       return hipErrorLaunchFailure;
-    if ((e = hipEventRecord(computed, S->comp)) != hipSuccess) return e;
-    if ((e = hipStreamWaitEvent(S->out, computed, 0)) != hipSuccess) return e;
     if ((e = copy_out(r)) != hipSuccess) return e;
-    if ((e = hipEventRecord(done, S->out)) != hipSuccess) return e;
+    hipEvent_t done = nullptr;
+    if (b + 1 < take.size()) {
+      if (!(done = pool_event(S, sl))) return hipErrorOutOfMemory;
+      if ((e = hipEventRecord(done, st)) != hipSuccess) return e;
+    }
     r.ev = done;
   }
   return hipSuccess;
 }
 
 // Admit the waiting requests that fit (FIFO, stop at the first that does
-// not) into a free slot and issue them.  Called with the lock held; drops
-// it around the device calls.  Returns true if a batch was issued.
+// not) into a free slot and issue them.  Called with the lock held, by the
+// scheduler thread or by a submitting thread that found the server idle;
+// drops the lock around the device calls.  Returns true if a batch was
+// issued.
 bool launch(hp_server *S, Slot &sl, std::unique_lock<std::mutex> &lk) {
   std::vector<RequestPtr> take;
   size_t table = BatchTables::kImageSlack;
@@ -314,6 +341,7 @@ bool launch(hp_server *S, Slot &sl, std::unique_lock<std::mutex> &lk) {
     take.push_back(r);
     S->pending.pop_front();
   }
+  S->npending.store((int64_t)S->pending.size(), std::memory_order_release);
   if (take.empty()) return false;
   S->peak_in_use = std::max<int64_t>(S->peak_in_use, (int64_t)S->arena.in_use());
   sl.busy = true;
@@ -323,9 +351,7 @@ bool launch(hp_server *S, Slot &sl, std::unique_lock<std::mutex> &lk) {
   const hipError_t e = issue(S, sl, take);
   if (e != hipSuccess) {
     // nothing of this batch may still touch its blocks when they are freed
-    (void)hipStreamSynchronize(S->copy);
-    (void)hipStreamSynchronize(S->comp);
-    (void)hipStreamSynchronize(S->out);
+    (void)hipStreamSynchronize(sl.stream);
   }
   lk.lock();
   sl.reqs = take;
@@ -335,33 +361,63 @@ bool launch(hp_server *S, Slot &sl, std::unique_lock<std::mutex> &lk) {
     for (const RequestPtr &r : take) finish(S, r.get(), HP_EDEVICE, t);
     S->cv_done.notify_all();
     release_slot(S, sl);
+  } else {
+    sl.live.store(true, std::memory_order_release);
   }
   return true;
 }
 
 void serve_loop(hp_server *S) {
   (void)hipSetDevice(S->device);
-  std::unique_lock<std::mutex> lk(S->mu);
+  int64_t active = now_ns();   // the last time there was work
   for (;;) {
-    bool progressed = false, busy = false;
-    for (Slot &sl : S->slot)
-      if (sl.busy && poll_slot(S, sl, busy)) progressed = true;
+    // Only this thread completes requests, and a slot's requests and head
+    // change after it is published (live) only here, so the published
+    // slots are polled without the lock; the lock is taken only when a
+    // request has completed, when requests wait, and to sleep.  A
+    // submitting thread therefore rarely finds the lock held.
+    bool busy = false, ready = false;
     for (Slot &sl : S->slot) {
-      if (sl.busy || S->pending.empty()) continue;
-      if (launch(S, sl, lk)) {
-        progressed = true;
-        busy = true;
+      if (!sl.live.load(std::memory_order_acquire)) continue;
+      busy = true;
+      if (request_state(sl, sl.reqs[sl.head].get()) != hipErrorNotReady) ready = true;
+    }
+    if (ready || S->npending.load(std::memory_order_acquire) > 0) {
+      std::unique_lock<std::mutex> lk(S->mu);
+      bool progressed = false, still = false;
+      for (Slot &sl : S->slot)
+        if (sl.live.load(std::memory_order_relaxed) && poll_slot(S, sl, still)) progressed = true;
+      for (Slot &sl : S->slot) {
+        if (sl.busy || S->pending.empty()) continue;
+        if (launch(S, sl, lk)) progressed = true;
       }
-    }
-    if (progressed) continue;
-    if (S->stop && S->pending.empty() && !busy) break;
-    if (busy) {
       lk.unlock();
-      std::this_thread::yield();
-      lk.lock();
-    } else {
-      S->cv_work.wait(lk, [&] { return S->stop || !S->pending.empty(); });
+      active = now_ns();
+      if (!progressed) std::this_thread::yield();   // waiting for room
+      continue;
     }
+    bool claimed = false;   // a slot a submitting thread is still issuing into
+    for (Slot &sl : S->slot) claimed |= sl.busy && !sl.live.load(std::memory_order_acquire);
+    if (busy || claimed) {
+      active = now_ns();
+      std::this_thread::yield();
+      continue;
+    }
+    if (now_ns() - active < kIdleSpinNs) {
+      std::this_thread::yield();
+      continue;
+    }
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto any_busy = [&] {
+      for (Slot &sl : S->slot)
+        if (sl.busy) return true;
+      return false;
+    };
+    if (any_busy()) continue;   // claimed by a submitting thread meanwhile
+    if (S->stop && S->pending.empty()) break;
+    // woken by a request queued for this thread or issued by its submitter
+    S->cv_work.wait(lk, [&] { return S->stop || !S->pending.empty() || any_busy(); });
+    active = now_ns();
   }
 }
 
@@ -386,11 +442,9 @@ extern "C" int hp_server_destroy(hp_server *S) {
     for (hipEvent_t e : sl.events) (void)hipEventDestroy(e);
     if (sl.himg) (void)hipHostFree(sl.himg);
     if (sl.dimg) (void)hipFree(sl.dimg);
+    if (sl.stream) (void)hipStreamDestroy(sl.stream);
   }
   for (hipEvent_t e : S->ev_pool) (void)hipEventDestroy(e);
-  if (S->copy) (void)hipStreamDestroy(S->copy);
-  if (S->out) (void)hipStreamDestroy(S->out);
-  if (S->comp) (void)hipStreamDestroy(S->comp);
   if (S->dmem) (void)hipFree(S->dmem);
   delete S;
   return HP_OK;
@@ -414,12 +468,12 @@ extern "C" int hp_server_create(size_t device_budget_bytes, int32_t max_batch, h
   int rc = HP_OK;
   if (hipMalloc(reinterpret_cast<void **>(&S->dmem), S->budget) != hipSuccess)
     rc = set_error(HP_ENOMEM, "device arena of %zu bytes could not be allocated", S->budget);
-  if (rc == HP_OK && (hipStreamCreateWithFlags(&S->copy, hipStreamNonBlocking) != hipSuccess ||
-                      hipStreamCreateWithFlags(&S->comp, hipStreamNonBlocking) != hipSuccess ||
-                      hipStreamCreateWithFlags(&S->out, hipStreamNonBlocking) != hipSuccess))
-    rc = set_error(HP_EDEVICE, "stream creation failed");
   for (Slot &sl : S->slot) {
     if (rc != HP_OK) break;
+    if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess) {
+      rc = set_error(HP_EDEVICE, "stream creation failed");
+      break;
+    }
     if (hipHostMalloc(reinterpret_cast<void **>(&sl.himg), kTableBytes, hipHostMallocDefault) != hipSuccess ||
         hipMalloc(&sl.dimg, kTableBytes) != hipSuccess)
       rc = set_error(HP_ENOMEM, "server slot resources could not be allocated");
@@ -487,14 +541,28 @@ extern "C" int hp_server_submit(hp_server *S, const int32_t *pts, int64_t n, int
     const size_t need = r->bytes;
     return set_error(HP_ECAPACITY, "request needs %zu device bytes, the server budget is %zu", need, S->budget);
   }
+  // A request that finds nothing waiting and a slot free is issued here, on
+  // the submitting thread (when its current device is the server's), which
+  // saves the hand-over to the scheduler thread; the scheduler still
+  // completes it.
+  int cur = -1;
+  const bool direct = hipGetDevice(&cur) == hipSuccess && cur == S->device;
   {
-    std::lock_guard<std::mutex> g(S->mu);
+    std::unique_lock<std::mutex> lk(S->mu);
     r->id = S->next_id++;
     S->live[r->id] = r;
+    const bool idle = S->pending.empty();
     S->pending.push_back(r);
+    S->npending.store((int64_t)S->pending.size(), std::memory_order_release);
     *ticket = r->id;
+    if (direct && idle && !S->stop)
+      for (Slot &sl : S->slot)
+        if (!sl.busy) {
+          launch(S, sl, lk);
+          break;
+        }
   }
-  S->cv_work.notify_one();
+  S->cv_work.notify_one();   // a sleeping scheduler polls the issued request too
   return HP_OK;
 }
 

@@ -665,16 +665,33 @@ class Request:
     server before the request completes."""
 
     def __init__(self, n: int, p: int, points: torch.Tensor | None = None):
-        """Buffers for any request with min(n, p) up to min(n, p) here."""
+        """Buffers for any request with min(n, p) up to min(n, p) here: one
+        page-locked array that holds, for a cloud with c = min(n, p), the
+        chain (3, c), the hull (2, 2c) and info back to back, the layout the
+        server returns in a single copy."""
         cap = max(1, min(n, p))
-        pin = dict(dtype=torch.int32, pin_memory=True)
         self.n, self.p, self.points = n, p, points
         self.cap = cap
-        self.chain = torch.empty((3, cap), **pin)
-        self.hull = torch.empty((2, 2 * cap), **pin)
-        self.info = torch.zeros(4, **pin)
+        self.flat = torch.zeros(7 * cap + 4, dtype=torch.int32, pin_memory=True)
+        self._base = self.flat.data_ptr()
+        self._c = cap
         self.ticket = -1
         self.done_ns = 0
+
+    @property
+    def chain(self) -> torch.Tensor:
+        c = self._c
+        return self.flat[:3 * c].view(3, c)
+
+    @property
+    def hull(self) -> torch.Tensor:
+        c = self._c
+        return self.flat[3 * c:7 * c].view(2, 2 * c)
+
+    @property
+    def info(self) -> torch.Tensor:
+        c = self._c
+        return self.flat[7 * c:7 * c + 4]
 
     def result(self) -> dict:
         import numpy as np
@@ -709,11 +726,13 @@ class Server:
         elif req.cap < min(n, p):
             raise ValueError("the request's buffers are too small for this cloud")
         req.n, req.p, req.points = n, p, points
+        c = min(n, p)
+        req._c = c
+        base = req._base
         t = ctypes.c_int64()
         _lib.call("hp_server_submit", self._h, points.data_ptr() if n else None, n, p,
-                  1 if points.is_cuda else 0, req.chain[0].data_ptr(), req.chain[1].data_ptr(),
-                  req.chain[2].data_ptr(), req.cap, req.hull[0].data_ptr(), req.hull[1].data_ptr(),
-                  req.info.data_ptr(), ctypes.byref(t))
+                  1 if points.is_cuda else 0, base, base + 4 * c, base + 8 * c, c, base + 12 * c,
+                  base + 20 * c, base + 28 * c, ctypes.byref(t))
         req.ticket = t.value
         return req
 

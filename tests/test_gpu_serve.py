@@ -140,20 +140,57 @@ def test_range_error_stays_with_its_request(hp):
 def test_queued_requests_join_a_batch(hp):
     """Requests that queue behind large ones are issued together: the small
     ones then share one batched launch sequence, and every result still
-    equals the oracle's."""
-    big = [synth.cloud("uniform", 1 << 24, 4096, 40 + i).pin_memory() for i in range(4)]
+    equals the oracle's.  Eight large host-resident requests hold the four
+    slots (and queue) while the small ones arrive."""
+    big = [synth.cloud("uniform", 1 << 24, 4096, 40 + i).pin_memory() for i in range(8)]
     small = [(synth.cloud("uniform", 5_000 + 17 * i, 1000 + i, 100 + i).pin_memory(), 1000 + i)
              for i in range(40)]
-    srv = hp.Server(budget_bytes=2 << 30, max_batch=64)
-    rb = [srv.submit(b, 4096) for b in big]
-    rs = [srv.submit(c, p) for c, p in small]
+    # output buffers made beforehand, so that the submissions follow each
+    # other closely
+    qb = [hp.Request(1 << 24, 4096) for _ in big]
+    qs = [hp.Request(c.shape[0], p) for c, p in small]
+    srv = hp.Server(budget_bytes=4 << 30, max_batch=64)
+    rb = [srv.submit(b, 4096, q) for b, q in zip(big, qb)]
+    rs = [srv.submit(c, p, q) for (c, p), q in zip(small, qs)]
     for r in rb + rs:
         assert srv.wait(r, timeout_us=60_000_000)
     st = srv.stats()
     srv.close()
-    assert st["completed"] == 44
-    assert st["batches"] < 44 - 8, f"queued requests were not joined: {st}"
+    assert st["completed"] == 48
+    assert st["batches"] < 48 - 8, f"queued requests were not joined: {st}"
     for r, b in zip(rb, big):
         _check_oracle(r.result(), b, 4096, "large request")
     for r, (c, p) in zip(rs, small):
         _check_oracle(r.result(), c, p, "queued small request")
+
+
+def test_separate_output_buffers(hp):
+    """Outputs in six separate host arrays (one copy each) and in the one
+    back-to-back buffer (a single copy) hold the same results."""
+    import ctypes
+
+    from paper_1505_00914_amd import _lib
+
+    spec = [("ellipsoids", 80_000, 4096, 5), ("uniform", 3_000, 20_000, 6), ("gaussian", 50_000, 777, 7)]
+    clouds = _clouds(spec)
+    srv = hp.Server(budget_bytes=1 << 30, max_batch=8)
+    for c, (kind, n, p, _) in zip(clouds, spec):
+        cap = min(n, p) + 5                     # wider than the cloud needs
+        pin = dict(dtype=torch.int32, pin_memory=True)
+        cx, clo, chi = (torch.full((cap,), -7, **pin) for _ in range(3))
+        hx, hy = (torch.full((2 * cap,), -7, **pin) for _ in range(2))
+        info = torch.zeros(4, **pin)
+        t = ctypes.c_int64()
+        _lib.call("hp_server_submit", srv._h, c.data_ptr(), n, p, 0, cx.data_ptr(), clo.data_ptr(),
+                  chi.data_ptr(), cap, hx.data_ptr(), hy.data_ptr(), info.data_ptr(), ctypes.byref(t))
+        r_sep = hp.Request(n, p, c)
+        r_sep.ticket = t.value
+        assert srv.wait(r_sep, timeout_us=60_000_000)
+        st, k, s, h = (int(v) for v in info.tolist())
+        sep = {"status": st, "k": k, "s": s, "h": h, "x": cx[:k].numpy(), "clo": clo[:k].numpy(),
+               "chi": chi[:k].numpy(), "hull": np.stack([hx[:h].numpy(), hy[:h].numpy()], 1)}
+        r = srv.submit(c, p)
+        assert srv.wait(r, timeout_us=60_000_000)
+        assert _same(sep, r.result()), f"{kind}: separate buffers != one buffer"
+        _check_oracle(sep, c, p, f"{kind} (separate buffers)")
+    srv.close()
