@@ -22,7 +22,11 @@
 // group of 64 columns the largest lo and the smallest hi, quantised inwards
 // to 8 bits each.  A later round drops a point whose y lies inside its
 // group's range: its column already holds points at or below and at or
-// above it, so it cannot change L.
+// above it, so it cannot change L.  The later round first streams its
+// points through k_bin_compact, which keeps only those the filter cannot
+// drop, back to back in one segment per binning workgroup; k_bin then bins
+// those short lists, unfiltered.  When a segment overflows, k_bin bins the
+// whole range with the filter.
 #pragma once
 
 #include <climits>
@@ -324,12 +328,24 @@ __device__ __forceinline__ void bin_flush(const BinLds &S, const BinArgs &B, int
 // words, bounds in steps of 2^qs) is the filter of the previous rounds, or
 // null in the first round.  Workgroup 0 of the first round also clears the
 // finish step's control words (R).
+// With `cpts`, workgroup g bins segment g of the points k_bin_compact kept
+// (ccount[g] of them, moved by the origin) in place of its share of pts,
+// unfiltered and with no origin, unless a segment overflowed (*cover).
 __global__ __launch_bounds__(kBinThreads) void k_bin(const int32_t *__restrict__ pts, int64_t n, Extent p,
                                                      const uint16_t *__restrict__ F, int32_t nf, int32_t qs,
                                                      BinArgs B, int32_t *__restrict__ wg_err, int2 org,
-                                                     ResetArgs R) {
+                                                     ResetArgs R, const int2 *__restrict__ cpts,
+                                                     const int64_t *__restrict__ ccount, int64_t segcap,
+                                                     const int32_t *__restrict__ cover) {
   extern __shared__ uint32_t bin_smem[];
   reset_controls(R);
+  const bool segment = cpts != nullptr && *cover == 0;
+  if (segment) {
+    pts = reinterpret_cast<const int32_t *>(cpts + (size_t)blockIdx.x * (size_t)segcap);
+    n = ccount[blockIdx.x];
+    F = nullptr;
+    org = make_int2(0, 0);
+  }
   const BinLds S = bin_carve(bin_smem, F ? nf : 0);
   const int tid = threadIdx.x, g = blockIdx.x;
   const bool filtered = F != nullptr;
@@ -351,12 +367,13 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const int32_t *__restrict__
   const int64_t nv = (n - head) >> 1;
   const int64_t tail = head + 2 * nv;
   const int4 *v = reinterpret_cast<const int4 *>(pts + 2 * head);
+  // a workgroup's share: its segment, or its tiles of the whole range
   const int64_t ntiles = (nv + kBinTileV - 1) / kBinTileV;
-  const int64_t tpw = (ntiles + B.G - 1) / B.G;
-  const int64_t vbeg = (int64_t)g * tpw * kBinTileV;
+  const int64_t tpw = segment ? ntiles : (ntiles + B.G - 1) / B.G;
+  const int64_t vbeg = segment ? 0 : (int64_t)g * tpw * kBinTileV;
   const int64_t vend = min(nv, vbeg + tpw * kBinTileV);
   const int nvt = vbeg < vend ? (int)((vend - vbeg + kBinTileV - 1) / kBinTileV) : 0;
-  const bool ht = g == 0 && (head || tail < n);   // a first tile of the odd points
+  const bool ht = (segment || g == 0) && (head || tail < n);   // a first tile of the odd points
   // Wave 0 keeps the per-window books; the other waves hold the points.
   // Tiles run as a two-stage pipeline: while wave 0 turns tile t's counts
   // into offsets, the point waves rank tile t + 1 (into the other count
@@ -535,6 +552,131 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const int32_t *__restrict__
   if (tid == 0) wg_err[g] = S.scalars[3];
 }
 
+// First pass of a filtered round, one workgroup per binning workgroup g:
+// the points of its share of [pts, pts + 2n) (a contiguous range of 16-byte
+// vectors; workgroup 0 also takes the point before the aligned body and the
+// odd last point), moved by the origin, each tested against the filter F
+// (nf words, bounds in steps of 2^qs) as in bin_rank.  Every point that
+// passes, or lies outside the box (which the binning pass then reports), is
+// written to segment g of out (segcap points), back to back in an arbitrary
+// order; count[g] receives the number kept.  A workgroup that keeps more than
+// segcap writes no further and sets *over, and k_bin then bins the whole
+// range instead.  Each wave takes its room in the segment with an LDS
+// atomic, so the waves never wait for one another, and gathers its kept
+// points in LDS first, so that they leave in whole 512-byte stores.
+constexpr int kCpThreads = 1024;
+constexpr int kCpVpt = 4;                          // 16-byte vectors per lane and step
+constexpr int kCpStepV = kCpThreads * kCpVpt;      // 8192 points per step
+constexpr int kCpFilterMax = (int)(kBinPMax >> kBinFilterShift);
+
+__global__ __launch_bounds__(kCpThreads) void k_bin_compact(const int32_t *__restrict__ pts, int64_t n, Extent p,
+                                                            const uint16_t *__restrict__ F, int32_t nf, int32_t qs,
+                                                            int2 org, int2 *__restrict__ out, int64_t segcap,
+                                                            int64_t *__restrict__ count, int32_t *__restrict__ over) {
+  constexpr int PP = 2 * kCpVpt;   // points per lane and step
+  __shared__ uint16_t sF[kCpFilterMax];
+  __shared__ int2 stg[kCpThreads / kWave][kWave * PP];   // a wave's kept points, in order
+  __shared__ unsigned long long skept;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave, g = blockIdx.x;
+  for (int i = tid; i < nf; i += kCpThreads) sF[i] = F[i];
+  auto keep = [&](int x, int y) -> bool {
+    const unsigned xi = (unsigned)(x - 1), yi = (unsigned)(y - 1);
+    if (!((xi < (unsigned)p.p) & (yi < (unsigned)p.q))) return true;
+    const unsigned f = sF[xi >> kBinFilterShift];
+    return (yi < ((f & 0xFFu) << qs)) | (yi > ((f >> 8) << qs));
+  };
+  int2 *const seg = out + (size_t)g * (size_t)segcap;
+  const int64_t head = (n > 0 && ((uintptr_t)pts & 15) != 0) ? 1 : 0;
+  const int64_t nv = (n - head) >> 1;
+  const int64_t tail = head + 2 * nv;
+  const int64_t vpw = (nv + gridDim.x - 1) / gridDim.x;
+  const int64_t vb = (int64_t)g * vpw, ve = min(nv, vb + vpw);
+  if (tid == 0) skept = 0;
+  __syncthreads();
+  if (g == 0 && tid == 0) {
+    unsigned long long c = 0;
+    for (int k = 0; k < 2; ++k) {
+      const int64_t i = k == 0 ? 0 : tail;
+      if ((k == 0 && !head) || (k == 1 && tail >= n)) continue;
+      const int x = shift_by(pts[2 * i], org.x), y = shift_by(pts[2 * i + 1], org.y);
+      if (!keep(x, y)) continue;
+      if (c < (unsigned long long)segcap) seg[c] = make_int2(x, y);
+      ++c;
+    }
+    skept = c;
+  }
+  __syncthreads();
+  const int4 *v = reinterpret_cast<const int4 *>(pts + 2 * head);
+  int4 q[kCpVpt], qn[kCpVpt];
+  // a lane past the end loads the last vector of the range (a valid
+  // address, since the loop runs only when the range is not empty) and its
+  // points are not used; no branch, so the loads of a step stay in flight
+  // together and only the previous step's are waited for
+  auto load = [&](int4 (&r)[kCpVpt], int64_t b0) {
+#pragma unroll
+    for (int u = 0; u < kCpVpt; ++u) r[u] = load_stream(&v[min(b0 + (int64_t)u * kCpThreads + tid, ve - 1)]);
+  };
+  if (vb < ve) load(q, vb);
+  for (int64_t b0 = vb; b0 < ve; b0 += kCpStepV) {
+    // the next step's vectors are in flight meanwhile; issued on every step
+    // (past the end they repeat the last vector), so that the wait for this
+    // step's vectors counts the same loads on every path
+    load(qn, b0 + kCpStepV);
+    __builtin_amdgcn_sched_barrier(0);   // keep those loads ahead of this step's work
+    // every filter word is read before any test, so the LDS reads share one wait
+    int xs[PP], ys[PP];
+    bool ok[PP], in[PP];
+    unsigned f[PP];
+#pragma unroll
+    for (int u = 0; u < kCpVpt; ++u) {
+      const int4 r = shift_by(q[u], org.x, org.y);
+      xs[2 * u] = r.x;
+      ys[2 * u] = r.y;
+      xs[2 * u + 1] = r.z;
+      ys[2 * u + 1] = r.w;
+      in[2 * u] = in[2 * u + 1] = b0 + (int64_t)u * kCpThreads + tid < ve;
+    }
+#pragma unroll
+    for (int j = 0; j < PP; ++j) {
+      const unsigned xi = (unsigned)(xs[j] - 1), yi = (unsigned)(ys[j] - 1);
+      ok[j] = (xi < (unsigned)p.p) & (yi < (unsigned)p.q);
+      f[j] = sF[ok[j] ? (xi >> kBinFilterShift) : 0u];
+    }
+    unsigned km = 0;   // bit j: point j of the lane is kept
+#pragma unroll
+    for (int j = 0; j < PP; ++j) {
+      const unsigned yi = (unsigned)(ys[j] - 1);
+      const bool kept = !ok[j] | (yi < ((f[j] & 0xFFu) << qs)) | (yi > ((f[j] >> 8) << qs));
+      km |= (in[j] & kept ? 1u : 0u) << j;
+    }
+    const int c = __popc(km);
+    const int incl = wave_incl_sum(c);
+    const int wtot = __builtin_amdgcn_readlane(incl, kWave - 1);
+    if (wtot > 0) {   // the same in every lane
+      unsigned long long wb = 0;
+      if (lane == 0) wb = atomicAdd(&skept, (unsigned long long)wtot);
+      wb = __shfl(wb, 0, kWave);
+      int k = incl - c;
+#pragma unroll
+      for (int j = 0; j < PP; ++j)
+        if ((km >> j) & 1u) stg[wv][k++] = make_int2(xs[j], ys[j]);
+      // LDS accesses of one wave complete in order: the gathered points are
+      // read back in place, a run of 64 consecutive points per store
+      for (int i = lane; i < wtot; i += kWave) {
+        const unsigned long long o = wb + (unsigned long long)i;
+        if (o < (unsigned long long)segcap) seg[o] = stg[wv][i];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kCpVpt; ++u) q[u] = qn[u];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    count[g] = (int64_t)skept;
+    if (skept > (unsigned long long)segcap) atomicOr(over, 1);
+  }
+}
+
 // Fold of the binned entries: workgroup (w, s) folds the streams for window
 // w of binning workgroups [s G / S, (s + 1) G / S) into the window's L in
 // LDS, then writes that window of partial array s (pairs).  Every workgroup
@@ -617,14 +759,16 @@ __global__ __launch_bounds__(kBinFoldThreads) void k_bin_fold(BinArgs B, Extent 
 }
 
 // Between rounds: the running L (array S_ of part; absent in the first
-// round) and the S_ partial arrays folded into array S_, and the filter of
-// the next round from it: per group of 64 columns (one wave), the largest lo
+// round) and the S_ partial arrays folded into array S_, the overflow flag of
+// the next round's k_bin_compact cleared, and the filter of the next round: per group of 64 columns (one wave), the largest lo
 // rounded up and the smallest hi rounded down to multiples of 2^qs in y - 1
 // (8 bits each), or a range that holds nothing when a column of the group is
 // empty or the lo bound does not fit 8 bits.
 __global__ __launch_bounds__(256) void k_bin_merge(int2 *__restrict__ part, int32_t S_, int32_t has_prev, Extent p,
-                                                   int32_t qs, uint16_t *__restrict__ F) {
+                                                   int32_t qs, uint16_t *__restrict__ F,
+                                                   int32_t *__restrict__ cover) {
   const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (c == 0 && cover) *cover = 0;   // the next round's k_bin_compact starts with no overflow
   const int lane = threadIdx.x & (kWave - 1);
   int2 L = make_int2(p.q + 1, -1);
   if (c < p) {

@@ -2397,7 +2397,22 @@ struct Plan1 {
 struct BinPlan {
   int G, S, nw, pages, rounds;
   int64_t split;   // points of the first round
+  int64_t segcap;  // points a workgroup's compaction segment holds (0: no compaction)
 };
+
+// The second round's compaction keeps at most this fraction of a
+// workgroup's points (1 / kBinCompactDiv); when more pass the filter in some
+// workgroup, the round bins all of its points with the filter instead.
+// HP_BIN_COMPACT_OFF=1 turns it off.
+constexpr int64_t kBinCompactDiv = 4;
+static bool bin_compact_off() {
+  static int v = -1;
+  if (v < 0) {
+    const char *e = getenv("HP_BIN_COMPACT_OFF");
+    v = (e && atoi(e) == 1) ? 1 : 0;
+  }
+  return v == 1;
+}
 
 constexpr int64_t kBinRoundsMinPerCol = 32;
 
@@ -2418,6 +2433,11 @@ static BinPlan bin_plan(int64_t n, int32_t p) {
   const int64_t tpw = (ntiles + B.G - 1) / B.G;
   const int64_t per_wg = tpw * 2 * (int64_t)kBinTileV + 2;
   B.pages = (int)((per_wg + kBinPage - 1) / kBinPage + B.nw + 1);
+  B.segcap = 0;
+  if (B.rounds == 2 && !bin_compact_off()) {
+    const int64_t vpw = ((n - B.split + 1) / 2 + B.G - 1) / B.G;   // vectors per workgroup, at most
+    B.segcap = ((2 * vpw + kBinCompactDiv - 1) / kBinCompactDiv + 2 + 1) & ~(int64_t)1;
+  }
   return B;
 }
 
@@ -2427,7 +2447,7 @@ static int bin_partials(const BinPlan &B) { return B.S + (B.rounds > 1 ? 1 : 0);
 
 // Device bytes of the binned reduce's pages and tables.
 struct BinLayout {
-  size_t pool, E, pg_off, pg_list, pwin, total;
+  size_t pool, E, pg_off, pg_list, pwin, cpts, ccount, cover, total;
 };
 static BinLayout bin_layout(const BinPlan &B) {
   BinLayout Z;
@@ -2437,6 +2457,9 @@ static BinLayout bin_layout(const BinPlan &B) {
   Z.pg_off = o;  o = align_up(o + sizeof(int32_t) * (size_t)B.G * (size_t)(B.nw + 1));
   Z.pg_list = o; o = align_up(o + sizeof(int32_t) * (size_t)B.G * (size_t)B.pages);
   Z.pwin = o;    o = align_up(o + sizeof(int32_t) * (size_t)B.G * (size_t)B.pages);
+  Z.cpts = o;    o = align_up(o + sizeof(int2) * (size_t)B.G * (size_t)B.segcap);
+  Z.ccount = o;  o = align_up(o + sizeof(int64_t) * (size_t)B.G);
+  Z.cover = o;   o = align_up(o + sizeof(int32_t));
   Z.total = o;
   return Z;
 }
@@ -2768,7 +2791,9 @@ static hipError_t dispatch_sampled(const Plan1 &P, const int32_t *pts, int64_t n
 
 // The binned reduce (p <= kBinPMax): per round k_bin over the round's points,
 // k_bin_fold into S partial arrays, and between rounds k_bin_merge into the
-// running L (array S) and the filter of the next round.  e0 is recorded at
+// running L (array S) and the filter of the next round; in the second round
+// k_bin_compact first keeps the points that filter cannot drop, and k_bin
+// bins those.  e0 is recorded at
 // the start of the first k_bin and e1 at the end of the last k_bin_fold.
 static hipError_t launch_binned(const int32_t *pts, int64_t n, Extent p, int2 *part, uint16_t *F, char *bins,
                                 int32_t *wg_err, ResetArgs R, int2 org, hipStream_t s, hipEvent_t e0,
@@ -2797,6 +2822,10 @@ static hipError_t launch_binned(const int32_t *pts, int64_t n, Extent p, int2 *p
     if (e != hipSuccess) return e;
     attr_set = true;
   }
+  int2 *cpts = reinterpret_cast<int2 *>(bins + Z.cpts);
+  int64_t *ccount = reinterpret_cast<int64_t *>(bins + Z.ccount);
+  int32_t *cover = reinterpret_cast<int32_t *>(bins + Z.cover);
+  if (B.segcap > 0 && nf > kCpFilterMax) return hipErrorInvalidValue;
   for (int r = 0; r < B.rounds; ++r) {
     const int64_t a = r == 0 ? 0 : B.split, b = r == 0 ? B.split : n;
     ResetArgs Rr = R;
@@ -2805,11 +2834,17 @@ static hipError_t launch_binned(const int32_t *pts, int64_t n, Extent p, int2 *p
     const uint32_t lds = (uint32_t)bin_lds_bytes(r > 0 ? nf : 0);
     const int32_t *pr = pts ? pts + 2 * a : pts;
     int32_t *err = wg_err + (size_t)r * B.G;
+    const bool compact = r > 0 && B.segcap > 0;
+    if (compact)   // the points the filter keeps, a segment per binning workgroup
+      hipLaunchKernelGGL(k_bin_compact, dim3(B.G), dim3(kCpThreads), 0, s, pr, b - a, p, F, nf, qs, org, cpts,
+                         B.segcap, ccount, cover);
+    const int2 *cp = compact ? cpts : nullptr;
     if (r == 0 && e0)
       hipExtLaunchKernelGGL(k_bin, dim3(B.G), dim3(kBinThreads), lds, s, e0, nullptr, 0, pr, b - a, p, Fr, nf, qs, A,
-                            err, org, Rr);
+                            err, org, Rr, cp, (const int64_t *)ccount, B.segcap, (const int32_t *)cover);
     else
-      hipLaunchKernelGGL(k_bin, dim3(B.G), dim3(kBinThreads), lds, s, pr, b - a, p, Fr, nf, qs, A, err, org, Rr);
+      hipLaunchKernelGGL(k_bin, dim3(B.G), dim3(kBinThreads), lds, s, pr, b - a, p, Fr, nf, qs, A, err, org, Rr, cp,
+                         (const int64_t *)ccount, B.segcap, (const int32_t *)cover);
     const dim3 gf((unsigned)(B.nw * B.S));
     if (r + 1 == B.rounds && e1)
       hipExtLaunchKernelGGL(k_bin_fold, gf, dim3(kBinFoldThreads), 0, s, nullptr, e1, 0, A, p, B.S, part);
@@ -2817,7 +2852,7 @@ static hipError_t launch_binned(const int32_t *pts, int64_t n, Extent p, int2 *p
       hipLaunchKernelGGL(k_bin_fold, gf, dim3(kBinFoldThreads), 0, s, A, p, B.S, part);
     if (r + 1 < B.rounds)
       hipLaunchKernelGGL(k_bin_merge, dim3((unsigned)(((int64_t)p + 255) / 256)), dim3(256), 0, s, part, B.S,
-                         r > 0 ? 1 : 0, p, qs, F);
+                         r > 0 ? 1 : 0, p, qs, F, B.segcap > 0 ? cover : nullptr);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

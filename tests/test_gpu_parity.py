@@ -168,6 +168,26 @@ def test_sampled_filter_orders(hp, order):
     _run_both(hp, torch.from_numpy(a), p, f"sampled-{order}", strategies=(5, 6, 2), split=False)
 
 
+@pytest.mark.parametrize("kind,n,p,seed", [
+    ("disc", 4_200_000, 16_384, 61),     # 256 points a column: the second round's kept points fit their buffer
+    ("uniform", 700_000, 20_000, 62),    # 35 a column: most pass the filter, the round bins the whole range
+    ("gaussian", 3_000_001, 30_000, 63), # odd count: the kept list ends in a single point
+])
+def test_binned_second_round_compaction(hp, kind, n, p, seed):
+    """The binned reduce's second round, whether its filtered points fit the
+    compaction buffer or not, against the oracle; also with the points
+    starting 8 bytes past a 16-byte boundary (a lone first point)."""
+    base = synth.cloud(kind, n + 1, p, seed)
+    for label, pts in (("aligned", base[:n].contiguous()), ("unaligned", base[1:])):
+        want = _oracle(pts.contiguous().numpy(), p)
+        dev = base.cuda()[:n] if label == "aligned" else base.cuda()[1:]
+        hp.set_strategy(6)
+        try:
+            _compare(hp.run(dev, p), want, f"binned-{kind}-{n}-{p}/{label}")
+        finally:
+            hp.set_strategy(0)
+
+
 @pytest.mark.parametrize("strategy", [5, 6])
 @pytest.mark.parametrize("where", [100, 1_500_000])
 def test_sampled_range_error(hp, where, strategy):
