@@ -172,6 +172,7 @@ def test_sampled_filter_orders(hp, order):
     ("disc", 4_200_000, 16_384, 61),     # 256 points a column: the second round's kept points fit their buffer
     ("uniform", 700_000, 20_000, 62),    # 35 a column: most pass the filter, the round bins the whole range
     ("gaussian", 3_000_001, 30_000, 63), # odd count: the kept list ends in a single point
+    ("disc", 12_800_001, 50_000, 64),    # 256 points a column, odd count
 ])
 def test_binned_second_round_compaction(hp, kind, n, p, seed):
     """The binned reduce's second round, whether its filtered points fit the
@@ -186,6 +187,25 @@ def test_binned_second_round_compaction(hp, kind, n, p, seed):
             _compare(hp.run(dev, p), want, f"binned-{kind}-{n}-{p}/{label}")
         finally:
             hp.set_strategy(0)
+
+
+@pytest.mark.parametrize("order", ["inside_first", "outside_first", "columns_late"])
+def test_binned_dense_orders(hp, order):
+    """The binned reduce at 256 points a column (the second round compacted)
+    when the first round is unrepresentative: only interior rows, only
+    extreme rows, or whole columns that appear only in the second round."""
+    p = 50_000
+    a = synth.cloud("disc", 12_800_000, p, 65).numpy()
+    c = (p + 1) / 2.0
+    if order == "inside_first":
+        key = np.abs(a[:, 1] - c)
+    elif order == "outside_first":
+        key = -np.abs(a[:, 1] - c)
+    else:
+        key = (a[:, 0] % 97 == 0).astype(np.int64)
+    a = np.ascontiguousarray(a[np.argsort(key, kind="stable")])
+    print(f"[case] binned at 256 points a column, {order}", flush=True)
+    _run_both(hp, torch.from_numpy(a), p, f"binned-dense-{order}", strategies=(6,), split=False)
 
 
 @pytest.mark.parametrize("strategy", [5, 6])
