@@ -758,14 +758,15 @@ __global__ __launch_bounds__(kBinFoldThreads) void k_bin_fold(BinArgs B, Extent 
   for (int c = tid; c < ncol; c += kBinFoldThreads) out[c] = sL[c];
 }
 
-// Between rounds: the running L (array S_ of part; absent in the first
-// round) and the S_ partial arrays folded into array S_, the overflow flag of
-// the next round's k_bin_compact cleared, and the filter of the next round: per group of 64 columns (one wave), the largest lo
-// rounded up and the smallest hi rounded down to multiples of 2^qs in y - 1
-// (8 bits each), or a range that holds nothing when a column of the group is
-// empty or the lo bound does not fit 8 bits.
-__global__ __launch_bounds__(256) void k_bin_merge(int2 *__restrict__ part, int32_t S_, int32_t has_prev, Extent p,
-                                                   int32_t qs, uint16_t *__restrict__ F,
+// Between rounds: the S_ partial arrays of the round just folded and the
+// running L (array `at` of part; absent after the first round) folded into
+// array `at`; the overflow flag of the next round's k_bin_compact cleared;
+// and the filter of the next round: per group of 64 columns (one wave), the
+// largest lo rounded up and the smallest hi rounded down to multiples of
+// 2^qs in y - 1 (8 bits each), or a range that holds nothing when a column
+// of the group is empty or the lo bound does not fit 8 bits.
+__global__ __launch_bounds__(256) void k_bin_merge(int2 *__restrict__ part, int32_t S_, int32_t has_prev, int32_t at,
+                                                   Extent p, int32_t qs, uint16_t *__restrict__ F,
                                                    int32_t *__restrict__ cover) {
   const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (c == 0 && cover) *cover = 0;   // the next round's k_bin_compact starts with no overflow
@@ -789,11 +790,11 @@ __global__ __launch_bounds__(256) void k_bin_merge(int2 *__restrict__ part, int3
       L.y = max(L.y, b.y);
     }
     if (has_prev) {
-      const int2 b = part[(size_t)S_ * p + c];
+      const int2 b = part[(size_t)at * p + c];
       L.x = min(L.x, b.x);
       L.y = max(L.y, b.y);
     }
-    part[(size_t)S_ * p + c] = L;
+    part[(size_t)at * p + c] = L;   // every array of this column was read above
   }
   const bool inside = c < p;
   bool empty = inside && L.x > L.y;

@@ -2395,7 +2395,7 @@ struct Plan1 {
 // binning workgroup may need: its points of the larger round over the page
 // size, plus one partly filled page per window.
 struct BinPlan {
-  int G, S, nw, pages, rounds;
+  int G, S, S2, nw, pages, rounds;   // S (S2): partial arrays of the first (second) round
   int64_t split;   // points of the first round
   int64_t segcap;  // points a workgroup's compaction segment holds (0: no compaction)
 };
@@ -2416,6 +2416,10 @@ static bool bin_compact_off() {
 
 constexpr int64_t kBinRoundsMinPerCol = 32;
 
+// Partial arrays of the second round at most: it folds far fewer entries
+// than the first, and every array costs the finish a read of 8p bytes.
+constexpr int kBinS2 = 2;
+
 // Points per binning workgroup and round at most, so that a stream's page
 // index fits the 16 bits the page records give it.
 constexpr int64_t kBinMaxPerWg = (int64_t)1 << 25;
@@ -2430,6 +2434,7 @@ static BinPlan bin_plan(int64_t n, int32_t p) {
   const int64_t ntiles = (nv + kBinTileV - 1) / kBinTileV;
   B.G = (int)std::max<int64_t>(device_info().cus, (m + kBinMaxPerWg - 1) / kBinMaxPerWg);
   B.S = (int)std::max<int64_t>(1, std::min<int64_t>(B.G, 2048 / B.nw));
+  B.S2 = std::min(B.S, kBinS2);
   const int64_t tpw = (ntiles + B.G - 1) / B.G;
   const int64_t per_wg = tpw * 2 * (int64_t)kBinTileV + 2;
   B.pages = (int)((per_wg + kBinPage - 1) / kBinPage + B.nw + 1);
@@ -2441,9 +2446,12 @@ static BinPlan bin_plan(int64_t n, int32_t p) {
   return B;
 }
 
-// Partial arrays of the binned reduce: S per round, plus the running L when
-// there are two rounds.
-static int bin_partials(const BinPlan &B) { return B.S + (B.rounds > 1 ? 1 : 0); }
+// Partial arrays the finish folds: the last round's, plus the running L
+// (array S2) when there are two rounds.
+static int bin_partials(const BinPlan &B) { return B.rounds > 1 ? B.S2 + 1 : B.S; }
+// Partial arrays held: the first round writes S of them, and the running L
+// sits at index S2.
+static int bin_part_storage(const BinPlan &B) { return B.rounds > 1 ? std::max(B.S, B.S2 + 1) : B.S; }
 
 // Device bytes of the binned reduce's pages and tables.
 struct BinLayout {
@@ -2587,8 +2595,8 @@ static Plan1 choose(int64_t n, int32_t p, bool allow_binned = true, int32_t q = 
 static int64_t part_pairs_for(const Plan1 &P, int64_t n, int32_t p, int32_t q = 0) {
   // the binned reduce writes pairs; the other partials pack into half a pair
   // when the rows allow
+  if (P.strategy == HP_STRATEGY_BINNED) return (int64_t)bin_part_storage(bin_plan(n, p)) * p;
   const int64_t entries = (int64_t)partial_count(P, n, p) * p;
-  if (P.strategy == HP_STRATEGY_BINNED) return entries;
   return partial_packs(q > 0 ? q : p) ? (entries + 1) / 2 : entries;
 }
 
@@ -2642,7 +2650,7 @@ static size_t ws_bytes_for(int64_t n, int32_t p, bool with_bins = true, int32_t 
   size_t bins = 0;
   if (with_bins && (int64_t)p <= kBinPMax && (int64_t)q <= kBinPMax) {
     const BinPlan B = bin_plan(n, p);
-    part = std::max<int64_t>(part, (int64_t)bin_partials(B) * p);
+    part = std::max<int64_t>(part, (int64_t)bin_part_storage(B) * p);
     bins = bin_layout(B).total;
   }
   return std::max(sparse, make_layout(p, p, part, T, bins).total);
@@ -2845,14 +2853,15 @@ static hipError_t launch_binned(const int32_t *pts, int64_t n, Extent p, int2 *p
     else
       hipLaunchKernelGGL(k_bin, dim3(B.G), dim3(kBinThreads), lds, s, pr, b - a, p, Fr, nf, qs, A, err, org, Rr, cp,
                          (const int64_t *)ccount, B.segcap, (const int32_t *)cover);
-    const dim3 gf((unsigned)(B.nw * B.S));
+    const int Sr = r == 0 ? B.S : B.S2;   // this round's partial arrays
+    const dim3 gf((unsigned)(B.nw * Sr));
     if (r + 1 == B.rounds && e1)
-      hipExtLaunchKernelGGL(k_bin_fold, gf, dim3(kBinFoldThreads), 0, s, nullptr, e1, 0, A, p, B.S, part);
+      hipExtLaunchKernelGGL(k_bin_fold, gf, dim3(kBinFoldThreads), 0, s, nullptr, e1, 0, A, p, Sr, part);
     else
-      hipLaunchKernelGGL(k_bin_fold, gf, dim3(kBinFoldThreads), 0, s, A, p, B.S, part);
-    if (r + 1 < B.rounds)
-      hipLaunchKernelGGL(k_bin_merge, dim3((unsigned)(((int64_t)p + 255) / 256)), dim3(256), 0, s, part, B.S,
-                         r > 0 ? 1 : 0, p, qs, F, B.segcap > 0 ? cover : nullptr);
+      hipLaunchKernelGGL(k_bin_fold, gf, dim3(kBinFoldThreads), 0, s, A, p, Sr, part);
+    if (r + 1 < B.rounds)   // the running L goes to array S2, which the next round's fold leaves alone
+      hipLaunchKernelGGL(k_bin_merge, dim3((unsigned)(((int64_t)p + 255) / 256)), dim3(256), 0, s, part, Sr,
+                         r > 0 ? 1 : 0, B.S2, p, qs, F, B.segcap > 0 ? cover : nullptr);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
