@@ -136,6 +136,9 @@ def bench_single(args, torch, hp, synth):
     # the last step's outputs against the oracle (outside the timed region)
     got = hp.collect(buf)
     host = pts.cpu()
+    # the cloud's bytes as the oracle and the kernels read them, so that a
+    # rerun elsewhere can tell whether it saw the same input
+    input_sha = hashlib.sha256(host.numpy().tobytes()).hexdigest()[:16]
     want = oracle.precondition_and_hull(host.numpy(), p)
     parity = (got["status"] == 0 and got["k"] == want["k"]
               and np.array_equal(got["x"], want["x"]) and np.array_equal(got["clo"], want["clo"])
@@ -160,7 +163,8 @@ def bench_single(args, torch, hp, synth):
         "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": args.workload, "kind": w["kind"], "n": n, "p": p, "seed": w["seed"],
-                   "input_copies": ncopies, "reduce_strategy": strategy, "parity_vs_oracle": bool(parity),
+                   "input_copies": ncopies, "input_sha256": input_sha, "reduce_strategy": strategy,
+                   "parity_vs_oracle": bool(parity),
                    "k": got["k"], "s": got["s"], "h": got["h"]},
         "roofline": {"bound": "hbm",
                      "kernel": "reduce (Algorithm 1): " + REDUCE_KERNELS.get(strategy, f"k_reduce ({strategy})"),
