@@ -177,11 +177,9 @@ __global__ __launch_bounds__(kBitsBlock) void k_bits_write(const uint64_t *__res
     total += s_wave[i];
   }
   const int32_t base = (int32_t)(w * 64 + 1);
-  while (v) {  // Table I: pos = ctz(v), then clear that bit
-    const int pos = __builtin_ctzll(v);
-    s_out[local++] = base + pos;
-    v ^= 1ull << pos;
-  }
+  // the set bits in ascending order (Table I's order): the position of the
+  // lowest one, then that bit cleared (v & (v - 1))
+  for (; v != 0; v &= v - 1) s_out[local++] = base + __builtin_ctzll(v);
   __syncthreads();
   const int64_t off = blockoff[blockIdx.x];
   // the run cols[off .. off + n), n = total clipped to cap: 4-byte stores
