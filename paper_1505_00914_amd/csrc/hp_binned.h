@@ -47,6 +47,7 @@ constexpr int kBinWorkers = kBinThreads - 64;       // lanes that hold points
 constexpr int kBinVpt = 4;                          // 16-byte vectors per point lane per tile
 constexpr int kBinTileV = kBinWorkers * kBinVpt;    // vectors per tile (7680 points)
 constexpr int kBinFilterShift = 6;                  // 64 columns per filter group
+constexpr int kCpFilterShift = 5;                   // 32 columns per group of the compaction's filter
 constexpr int kBinFoldThreads = 256;
 // blocks one tile can complete: its 8192 points (2 more in the tile of the
 // odd points) plus every window's carry of fewer than kBinBlk entries
@@ -556,7 +557,8 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const int32_t *__restrict__
 // the points of its share of [pts, pts + 2n) (a contiguous range of 16-byte
 // vectors; workgroup 0 also takes the point before the aligned body and the
 // odd last point), moved by the origin, each tested against the filter F
-// (nf words, bounds in steps of 2^qs) as in bin_rank.  Every point that
+// (nf words, one per 32 columns: a finer filter than bin_rank's, which the
+// LDS of this kernel has room for; bounds in steps of 2^qs).  Every point that
 // passes, or lies outside the box (which the binning pass then reports), is
 // written to segment g of out (segcap points), back to back in an arbitrary
 // order; count[g] receives the number kept.  A workgroup that keeps more than
@@ -567,7 +569,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(const int32_t *__restrict__
 constexpr int kCpThreads = 1024;
 constexpr int kCpVpt = 4;                          // 16-byte vectors per lane and step
 constexpr int kCpStepV = kCpThreads * kCpVpt;      // 8192 points per step
-constexpr int kCpFilterMax = (int)(kBinPMax >> kBinFilterShift);
+constexpr int kCpFilterMax = (int)(kBinPMax >> kCpFilterShift);
 
 __global__ __launch_bounds__(kCpThreads) void k_bin_compact(const int32_t *__restrict__ pts, int64_t n, Extent p,
                                                             const uint16_t *__restrict__ F, int32_t nf, int32_t qs,
@@ -582,7 +584,7 @@ __global__ __launch_bounds__(kCpThreads) void k_bin_compact(const int32_t *__res
   auto keep = [&](int x, int y) -> bool {
     const unsigned xi = (unsigned)(x - 1), yi = (unsigned)(y - 1);
     if (!((xi < (unsigned)p.p) & (yi < (unsigned)p.q))) return true;
-    const unsigned f = sF[xi >> kBinFilterShift];
+    const unsigned f = sF[xi >> kCpFilterShift];
     return (yi < ((f & 0xFFu) << qs)) | (yi > ((f >> 8) << qs));
   };
   int2 *const seg = out + (size_t)g * (size_t)segcap;
@@ -640,7 +642,7 @@ __global__ __launch_bounds__(kCpThreads) void k_bin_compact(const int32_t *__res
     for (int j = 0; j < PP; ++j) {
       const unsigned xi = (unsigned)(xs[j] - 1), yi = (unsigned)(ys[j] - 1);
       ok[j] = (xi < (unsigned)p.p) & (yi < (unsigned)p.q);
-      f[j] = sF[ok[j] ? (xi >> kBinFilterShift) : 0u];
+      f[j] = sF[ok[j] ? (xi >> kCpFilterShift) : 0u];
     }
     unsigned km = 0;   // bit j: point j of the lane is kept
 #pragma unroll
@@ -761,13 +763,14 @@ __global__ __launch_bounds__(kBinFoldThreads) void k_bin_fold(BinArgs B, Extent 
 // Between rounds: the S_ partial arrays of the round just folded and the
 // running L (array `at` of part; absent after the first round) folded into
 // array `at`; the overflow flag of the next round's k_bin_compact cleared;
-// and the filter of the next round: per group of 64 columns (one wave), the
-// largest lo rounded up and the smallest hi rounded down to multiples of
-// 2^qs in y - 1 (8 bits each), or a range that holds nothing when a column
-// of the group is empty or the lo bound does not fit 8 bits.
+// and the filters of the next round: per group of 64 columns (one wave; F,
+// for k_bin) and of 32 columns (F32, for k_bin_compact), the largest lo
+// rounded up and the smallest hi rounded down to multiples of 2^qs in y - 1
+// (8 bits each), or a range that holds nothing when a column of the group is
+// empty or the lo bound does not fit 8 bits.
 __global__ __launch_bounds__(256) void k_bin_merge(int2 *__restrict__ part, int32_t S_, int32_t has_prev, int32_t at,
                                                    Extent p, int32_t qs, uint16_t *__restrict__ F,
-                                                   int32_t *__restrict__ cover) {
+                                                   uint16_t *__restrict__ F32, int32_t *__restrict__ cover) {
   const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (c == 0 && cover) *cover = 0;   // the next round's k_bin_compact starts with no overflow
   const int lane = threadIdx.x & (kWave - 1);
@@ -797,25 +800,29 @@ __global__ __launch_bounds__(256) void k_bin_merge(int2 *__restrict__ part, int3
     part[(size_t)at * p + c] = L;   // every array of this column was read above
   }
   const bool inside = c < p;
-  bool empty = inside && L.x > L.y;
+  const unsigned long long em = __ballot(inside && L.x > L.y);   // empty columns of the wave
+  // lo bound rounded up and hi bound rounded down, never outwards; a group
+  // with an empty column, or whose lo bound does not fit 8 bits, drops
+  // nothing (lo bound 255 << qs, hi bound 0)
+  auto word = [&](int mlo, int mhi, bool empty) -> uint16_t {
+    if (empty) return 0xFFu;
+    const unsigned qlo = ((unsigned)(mlo - 1) + (1u << qs) - 1) >> qs;
+    const unsigned qhi = (unsigned)(mhi - 1) >> qs;
+    return qlo <= 0xFFu ? (uint16_t)(qlo | (min(qhi, 0xFFu) << 8)) : (uint16_t)0xFFu;
+  };
   int mlo = inside ? L.x : INT_MIN, mhi = inside ? L.y : INT_MAX;
 #pragma unroll
-  for (int d = kWave / 2; d > 0; d >>= 1) {
+  for (int d = kWave / 4; d > 0; d >>= 1) {   // each half wave: 32 columns
     mlo = max(mlo, __shfl_xor(mlo, d, kWave));
     mhi = min(mhi, __shfl_xor(mhi, d, kWave));
   }
-  empty = __any(empty);
+  const int64_t g32 = c >> kCpFilterShift;
+  if (F32 && (lane & 31) == 0 && (g32 << kCpFilterShift) < p)
+    F32[g32] = word(mlo, mhi, ((em >> (lane & 32)) & 0xFFFFFFFFull) != 0);
+  mlo = max(mlo, __shfl_xor(mlo, kWave / 2, kWave));
+  mhi = min(mhi, __shfl_xor(mhi, kWave / 2, kWave));
   const int64_t grp = c >> kBinFilterShift;
-  if (lane == 0 && (grp << kBinFilterShift) < p) {
-    uint16_t word = 0xFFu;   // lo bound 255 << qs, hi bound 0: nothing is dropped
-    if (!empty) {
-      // lo bound rounded up and hi bound rounded down, never outwards
-      const unsigned qlo = ((unsigned)(mlo - 1) + (1u << qs) - 1) >> qs;
-      const unsigned qhi = (unsigned)(mhi - 1) >> qs;
-      if (qlo <= 0xFFu) word = (uint16_t)(qlo | (min(qhi, 0xFFu) << 8));
-    }
-    F[grp] = word;
-  }
+  if (lane == 0 && (grp << kBinFilterShift) < p) F[grp] = word(mlo, mhi, em != 0);
 }
 
 }  // namespace hp

@@ -2365,7 +2365,9 @@ static Layout make_layout(int64_t positions, int32_t p, int64_t part_pairs, cons
   Y.tree = o;     o = align_up(o + sizeof(int32_t) * (size_t)T.nodes);
   Y.wg_err = o;   o = align_up(o + sizeof(int32_t) * (size_t)kMaxGrid);
   Y.wg_cnt = o;   o = align_up(o + sizeof(int32_t) * (size_t)kMaxGrid);
-  Y.filt = o;     o = align_up(o + sizeof(int2) * (size_t)((p > 0 ? (int64_t)p + 63 : 0) / 64));
+  // the sampled filter's pairs, or the binned reduce's 16-bit words per 64
+  // columns (rounded up to 8 words) followed by its words per 32 columns
+  Y.filt = o;     o = align_up(o + sizeof(int2) * (size_t)((p > 0 ? (int64_t)p + 63 : 0) / 64) + 16);
   Y.slab_k = o;   o = align_up(o + sizeof(int32_t) * (size_t)T.size[1]);
   Y.slab_s = o;   o = align_up(o + sizeof(int32_t) * (size_t)T.size[1]);
   Y.slab_off = o; o = align_up(o + sizeof(int32_t) * (size_t)T.size[1]);
@@ -2833,7 +2835,11 @@ static hipError_t launch_binned(const int32_t *pts, int64_t n, Extent p, int2 *p
   int2 *cpts = reinterpret_cast<int2 *>(bins + Z.cpts);
   int64_t *ccount = reinterpret_cast<int64_t *>(bins + Z.ccount);
   int32_t *cover = reinterpret_cast<int32_t *>(bins + Z.cover);
-  if (B.segcap > 0 && nf > kCpFilterMax) return hipErrorInvalidValue;
+  // the compaction's 32-column filter follows the 64-column one in the
+  // filter region (8 bytes per 64 columns)
+  const int nf32 = (int)(((int64_t)p + (1 << kCpFilterShift) - 1) >> kCpFilterShift);
+  uint16_t *F32 = B.segcap > 0 ? F + ((nf + 7) & ~7) : nullptr;
+  if (B.segcap > 0 && nf32 > kCpFilterMax) return hipErrorInvalidValue;
   for (int r = 0; r < B.rounds; ++r) {
     const int64_t a = r == 0 ? 0 : B.split, b = r == 0 ? B.split : n;
     ResetArgs Rr = R;
@@ -2844,7 +2850,7 @@ static hipError_t launch_binned(const int32_t *pts, int64_t n, Extent p, int2 *p
     int32_t *err = wg_err + (size_t)r * B.G;
     const bool compact = r > 0 && B.segcap > 0;
     if (compact)   // the points the filter keeps, a segment per binning workgroup
-      hipLaunchKernelGGL(k_bin_compact, dim3(B.G), dim3(kCpThreads), 0, s, pr, b - a, p, F, nf, qs, org, cpts,
+      hipLaunchKernelGGL(k_bin_compact, dim3(B.G), dim3(kCpThreads), 0, s, pr, b - a, p, F32, nf32, qs, org, cpts,
                          B.segcap, ccount, cover);
     const int2 *cp = compact ? cpts : nullptr;
     if (r == 0 && e0)
@@ -2861,7 +2867,7 @@ static hipError_t launch_binned(const int32_t *pts, int64_t n, Extent p, int2 *p
       hipLaunchKernelGGL(k_bin_fold, gf, dim3(kBinFoldThreads), 0, s, A, p, Sr, part);
     if (r + 1 < B.rounds)   // the running L goes to array S2, which the next round's fold leaves alone
       hipLaunchKernelGGL(k_bin_merge, dim3((unsigned)(((int64_t)p + 255) / 256)), dim3(256), 0, s, part, Sr,
-                         r > 0 ? 1 : 0, B.S2, p, qs, F, B.segcap > 0 ? cover : nullptr);
+                         r > 0 ? 1 : 0, B.S2, p, qs, F, F32, B.segcap > 0 ? cover : nullptr);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
