@@ -352,10 +352,11 @@ def bench_serve(args, torch, hp, synth) -> dict:
     admission) from page-locked host memory, and (b) as a baseline,
     first-in first-out, one request at a time with the plain single-cloud
     launch sequence, both on the full trace (args.serve_rate per second for
-    args.serve_seconds); then both again, on a shorter trace
-    (args.serve_device_seconds), with the points already in device memory, at
-    the same rate and at args.serve_stress_rate.  Latency = the time the
-    result is in host memory minus the scheduled arrival time."""
+    args.serve_seconds); then both again on the same trace with the points
+    already in device memory, and on a shorter one (args.serve_device_seconds)
+    at args.serve_stress_rate.  Latency = the time the result is in host
+    memory minus the scheduled arrival time; the factors are FIFO's p50 and
+    p99 over the server's."""
     import threading
 
     import numpy as np
@@ -517,18 +518,25 @@ def bench_serve(args, torch, hp, synth) -> dict:
            "budget_gib": args.serve_budget, "max_batch": args.serve_max_batch}
     res["server_host_points"] = run_server(False, arrivals, picks)
     res["fifo_percloud_host_points"] = run_fifo(False, arrivals, picks)
-    # points already in device memory, on a shorter trace at the same rate
-    # and at a higher one
-    if args.serve_device_seconds > 0:
-        a_dev, p_dev = trace(args.serve_rate, args.serve_device_seconds)
-        res["device_trace_seconds"] = args.serve_device_seconds
-        res["server_device_points"] = run_server(True, a_dev, p_dev)
-        res["fifo_percloud_device_points"] = run_fifo(True, a_dev, p_dev)
-        if args.serve_stress_rate > 0:
-            a_st, p_st = trace(args.serve_stress_rate, args.serve_device_seconds)
-            res["stress_rate"] = args.serve_stress_rate
-            res["stress_server_device_points"] = run_server(True, a_st, p_st)
-            res["stress_fifo_percloud_device_points"] = run_fifo(True, a_st, p_st)
+    # the same trace with the points already in device memory
+    res["server_device_points"] = run_server(True, arrivals, picks)
+    res["fifo_percloud_device_points"] = run_fifo(True, arrivals, picks)
+
+    def factor(srv: dict, fifo: dict) -> dict:
+        return {"p50": round(fifo["p50_ms"] / srv["p50_ms"], 2), "p99": round(fifo["p99_ms"] / srv["p99_ms"], 2)}
+
+    # FIFO's latency over the server's (above 1: the server is faster)
+    res["fifo_over_server_host_points"] = factor(res["server_host_points"], res["fifo_percloud_host_points"])
+    res["fifo_over_server_device_points"] = factor(res["server_device_points"], res["fifo_percloud_device_points"])
+    # a shorter trace at a higher rate, device-resident points
+    if args.serve_device_seconds > 0 and args.serve_stress_rate > 0:
+        a_st, p_st = trace(args.serve_stress_rate, args.serve_device_seconds)
+        res["stress_rate"] = args.serve_stress_rate
+        res["stress_trace_seconds"] = args.serve_device_seconds
+        res["stress_server_device_points"] = run_server(True, a_st, p_st)
+        res["stress_fifo_percloud_device_points"] = run_fifo(True, a_st, p_st)
+        res["fifo_over_server_stress"] = factor(res["stress_server_device_points"],
+                                                res["stress_fifo_percloud_device_points"])
     return res
 
 
@@ -880,7 +888,7 @@ def main(argv=None):
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="length of the host-memory trace")
     ap.add_argument("--serve-device-seconds", type=float, default=10.0,
-                    help="length of the device-memory traces (0 skips them)")
+                    help="length of the trace at the stress rate, device-resident points (0 skips it)")
     ap.add_argument("--serve-pool", type=int, default=32)
     ap.add_argument("--serve-budget", type=int, default=8, help="device arena, GiB")
     ap.add_argument("--serve-max-batch", type=int, default=64)
