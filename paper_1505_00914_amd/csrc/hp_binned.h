@@ -684,10 +684,10 @@ __global__ __launch_bounds__(kCpThreads) void k_bin_compact(const int32_t *__res
 // LDS, then writes that window of partial array s (pairs).  Every workgroup
 // writes its window, so the S partial arrays cover every column.  The pages
 // to fold are listed in LDS first (kBinFoldList at a time: page id and
-// entry count), then read eight pages per step, each lane taking one
+// entry count), then read sixteen pages per step, each lane taking one
 // 16-byte vector (four entries) of every page.
 constexpr int kBinFoldList = 1024;
-constexpr int kBinFoldStep = 8;
+constexpr int kBinFoldStep = 16;
 
 __global__ __launch_bounds__(kBinFoldThreads) void k_bin_fold(BinArgs B, Extent p, int32_t S_,
                                                               int2 *__restrict__ part) {
