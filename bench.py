@@ -36,8 +36,8 @@ REDUCE_SOURCES = ["paper_1505_00914_amd/csrc/hp_reduce.h", "paper_1505_00914_amd
                   "paper_1505_00914_amd/csrc/hp_device.h", "paper_1505_00914_amd/csrc/hp_binned.h"]
 STRATEGY_NAMES = {1: "lds", 2: "global", 3: "lds_partial", 4: "window", 5: "sampled", 6: "binned", 7: "sparse"}
 REDUCE_KERNELS = {
-    "binned": "k_bin, k_bin_fold (per round) and k_bin_merge between the rounds: the reduce from the first "
-              "kernel's start to the last kernel's end",
+    "binned": "k_bin and k_bin_fold per round, k_bin_merge between the rounds and k_bin_compact before the "
+              "second round's k_bin: the reduce from the first kernel's start to the last kernel's end",
     "sampled": "k_reduce_global on the sample, k_filter_build, k_reduce_filtered",
 }
 
