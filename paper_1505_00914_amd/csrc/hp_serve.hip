@@ -211,13 +211,15 @@ hipEvent_t pool_event(hp_server *S, Slot &sl) {
 }
 
 // Copies and launches for the requests in `take` (blocks already
-// allocated).  Runs without the lock, on the scheduler thread.  The small
-// requests' points and the work tables are copied first and computed in one
-// batched launch sequence; each large request then waits only for its own
-// points and runs the single-cloud sequence.  Every request's outputs are
-// copied back right behind its own kernels, and its event recorded, so it
-// completes independently of the rest of the batch.  Reorders `take` into
-// event order.
+// allocated), all on the slot's stream.  Runs without the lock, on the
+// thread that launches the slot (the scheduler, or a submitting thread that
+// found the server idle).  The small requests' points and the work tables
+// are copied first and computed in one batched launch sequence; the other
+// requests follow one by one with the single-cloud sequence.  Every
+// request's outputs are copied back right behind its own kernels and an
+// event is recorded after them (none after the slot's last request, which
+// completes when the stream is idle), so it completes independently of the
+// rest of the batch.  Reorders `take` into completion order.
 hipError_t issue(hp_server *S, Slot &sl, std::vector<RequestPtr> &take) {
   std::stable_partition(take.begin(), take.end(), [](const RequestPtr &r) { return !r->single; });
   size_t small = 0;
