@@ -744,11 +744,14 @@ __global__ __launch_bounds__(kBinFoldThreads) void k_bin_fold(BinArgs B, Extent 
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
             if (4 * tid + k < cnt[r]) {
+              // atomics whose results are not used (no return, no wait):
+              // testing the column first made every entry wait for an LDS
+              // round trip, since an atomic on one entry may change the
+              // column the next one reads
               const int c = (int)(ev[k] >> kBinYBits);
               const int y = (int)(ev[k] & ((1u << kBinYBits) - 1)) + 1;
-              const int2 cur = sL[c];
-              if (y < cur.x) atomicMin(&sL[c].x, y);
-              if (y > cur.y) atomicMax(&sL[c].y, y);
+              atomicMin(&sL[c].x, y);
+              atomicMax(&sL[c].y, y);
             }
           }
         }
