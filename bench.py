@@ -32,8 +32,11 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 # sources of the single-cloud reduce kernel (the counter summary names their hash)
+# the reduce kernels and the host code that plans their launches (grid
+# shapes and partial-array counts change the traffic as much as the kernels)
 REDUCE_SOURCES = ["paper_1505_00914_amd/csrc/hp_reduce.h", "paper_1505_00914_amd/csrc/hp_kernels.h",
-                  "paper_1505_00914_amd/csrc/hp_device.h", "paper_1505_00914_amd/csrc/hp_binned.h"]
+                  "paper_1505_00914_amd/csrc/hp_device.h", "paper_1505_00914_amd/csrc/hp_binned.h",
+                  "paper_1505_00914_amd/csrc/hp_single.hip"]
 STRATEGY_NAMES = {1: "lds", 2: "global", 3: "lds_partial", 4: "window", 5: "sampled", 6: "binned", 7: "sparse"}
 REDUCE_KERNELS = {
     "binned": "k_bin and k_bin_fold per round, k_bin_merge between the rounds and k_bin_compact before the "

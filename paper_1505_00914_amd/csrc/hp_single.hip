@@ -2420,7 +2420,11 @@ constexpr int64_t kBinRoundsMinPerCol = 32;
 
 // Partial arrays of the second round at most: it folds far fewer entries
 // than the first, and every array costs the finish a read of 8p bytes.
-constexpr int kBinS2 = 2;
+constexpr int kBinS2 = 3;
+// Fold workgroups per CU and round (nw windows x S slices): each holds a
+// window's L and its page lists in 40 KB of LDS.  More slices fold fewer
+// entries each but write more partial arrays for the merge to read back.
+constexpr int kBinFoldPerCu = 3;
 
 // Points per binning workgroup and round at most, so that a stream's page
 // index fits the 16 bits the page records give it.
@@ -2435,7 +2439,7 @@ static BinPlan bin_plan(int64_t n, int32_t p) {
   const int64_t nv = m / 2 + 1;
   const int64_t ntiles = (nv + kBinTileV - 1) / kBinTileV;
   B.G = (int)std::max<int64_t>(device_info().cus, (m + kBinMaxPerWg - 1) / kBinMaxPerWg);
-  B.S = (int)std::max<int64_t>(1, std::min<int64_t>(B.G, 2048 / B.nw));
+  B.S = (int)std::max<int64_t>(1, std::min<int64_t>(B.G, (int64_t)kBinFoldPerCu * device_info().cus / B.nw));
   B.S2 = std::min(B.S, kBinS2);
   const int64_t tpw = (ntiles + B.G - 1) / B.G;
   const int64_t per_wg = tpw * 2 * (int64_t)kBinTileV + 2;
