@@ -2891,7 +2891,10 @@ static void hull_buffers(HullArgs &H, const TreeShape &T, int64_t positions, cha
   H.positions = (int32_t)positions;
 }
 
-constexpr int kHullTestWgs = 1024;  // test workgroups per node level, about
+// Test workgroups per node level, about.  Each stages every sibling's hull,
+// so more of them repeat that work: on the 2^20-column disc (256 nodes under
+// 4 parents) 512 took the step 13 us below 1024, and 256 matched 512.
+constexpr int kHullTestWgs = 512;
 constexpr int kHullMaxSplit = 64;   // test workgroups per child, at most
 
 static hipError_t launch_hull_levels(const TreeShape &T, int64_t positions, char *w, const Layout &Y,
