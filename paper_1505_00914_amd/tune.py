@@ -28,7 +28,7 @@ from . import synth
 
 # regimes tuned by default: (log2 n, log2 p, point distribution)
 REGIMES = [
-    (17, 10, "uniform"), (20, 10, "uniform"), (20, 12, "uniform"), (23, 12, "ellipsoids"),
+    (16, 10, "uniform"), (17, 10, "uniform"), (20, 10, "uniform"), (20, 12, "uniform"), (23, 12, "ellipsoids"),
     (23, 10, "uniform"), (23, 14, "uniform"), (26, 12, "gaussian"), (26, 14, "uniform"),
     (20, 14, "uniform"), (23, 16, "uniform"), (26, 16, "uniform"), (26, 20, "disc"),
     (28, 12, "gaussian"), (28, 20, "disc"),
