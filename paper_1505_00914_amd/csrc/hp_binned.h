@@ -48,7 +48,7 @@ constexpr int kBinVpt = 4;                          // 16-byte vectors per point
 constexpr int kBinTileV = kBinWorkers * kBinVpt;    // vectors per tile (7680 points)
 constexpr int kBinFilterShift = 6;                  // 64 columns per filter group
 constexpr int kCpFilterShift = 5;                   // 32 columns per group of the compaction's filter
-constexpr int kBinFoldThreads = 256;
+constexpr int kBinFoldThreads = 512;
 // blocks one tile can complete: its 8192 points (2 more in the tile of the
 // odd points) plus every window's carry of fewer than kBinBlk entries
 constexpr int kBinMaxBlocks = ((2 * kBinTileV + 2) + kBinNwMax * (kBinBlk - 1)) / kBinBlk + 2;
@@ -65,9 +65,9 @@ struct BinArgs {
   int32_t G;          // binning workgroups
 };
 
-// Exclusive scan of counts packed 16 bits apiece into a uint64, over threads
-// 0..255 (four waves).  Every thread of the workgroup calls it (the others
-// pass 0 and ignore the result); tmp holds one partial sum per wave.
+// Exclusive scan over the WAVES waves of the workgroup, every thread of
+// which calls it; tmp holds one partial sum per wave.
+template <int WAVES>
 __device__ __forceinline__ unsigned long long bin_scan3(unsigned long long v, unsigned long long *tmp,
                                                         unsigned long long *total) {
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
@@ -81,7 +81,7 @@ __device__ __forceinline__ unsigned long long bin_scan3(unsigned long long v, un
   __syncthreads();
   unsigned long long off = 0, all = 0;
 #pragma unroll
-  for (int j = 0; j < kBinNwMax / kWave; ++j) {
+  for (int j = 0; j < WAVES; ++j) {
     if (j < wv) off += tmp[j];
     all += tmp[j];
   }
@@ -684,8 +684,9 @@ __global__ __launch_bounds__(kCpThreads) void k_bin_compact(const int32_t *__res
 // LDS, then writes that window of partial array s (pairs).  Every workgroup
 // writes its window, so the S partial arrays cover every column.  The pages
 // to fold are listed in LDS first (kBinFoldList at a time: page id and
-// entry count), then read sixteen pages per step, each lane taking one
-// 16-byte vector (four entries) of every page.
+// entry count), then read sixteen pages per step: each half of the
+// workgroup takes every other page, each lane one 16-byte vector (four
+// entries) of its half's pages.
 constexpr int kBinFoldList = 1024;
 constexpr int kBinFoldStep = 16;
 
@@ -698,6 +699,13 @@ __global__ __launch_bounds__(kBinFoldThreads) void k_bin_fold(BinArgs B, Extent 
   const int tid = threadIdx.x;
   const int w = blockIdx.x / S_, s = blockIdx.x % S_;
   const int nw = B.nw;
+  // a page is 256 vectors of 16 bytes: the workgroup's halves take
+  // alternate pages of a step, kFoldPer pages per lane
+  constexpr int kFoldLanes = kBinPage / 4;
+  constexpr int kFoldHalves = kBinFoldThreads / kFoldLanes;
+  constexpr int kFoldPer = kBinFoldStep / kFoldHalves;
+  static_assert(kFoldPer * kFoldHalves == kBinFoldStep, "whole pages per lane and step");
+  const int half = tid / kFoldLanes, lt = tid % kFoldLanes;
   const int64_t c0 = (int64_t)w * kBinWc;
   const int ncol = (int)min<int64_t>(kBinWc, (int64_t)p - c0);
   for (int c = tid; c < kBinWc; c += kBinFoldThreads) sL[c] = make_int2(p.q + 1, -1);
@@ -712,7 +720,7 @@ __global__ __launch_bounds__(kBinFoldThreads) void k_bin_fold(BinArgs B, Extent 
       ent = B.E[(size_t)g * nw + w];
     }
     unsigned long long total;
-    const int ex = (int)bin_scan3((unsigned long long)np, tmp, &total);
+    const int ex = (int)bin_scan3<kBinFoldThreads / kWave>((unsigned long long)np, tmp, &total);
     const int npages = (int)total;
     for (int qb = 0; qb < npages; qb += kBinFoldList) {
       __syncthreads();   // the previous list is no longer read
@@ -728,22 +736,22 @@ __global__ __launch_bounds__(kBinFoldThreads) void k_bin_fold(BinArgs B, Extent 
       __syncthreads();
       const int nq = min(kBinFoldList, npages - qb);
       for (int q0 = 0; q0 < nq; q0 += kBinFoldStep) {
-        uint4 e[kBinFoldStep];
-        int cnt[kBinFoldStep];
+        uint4 e[kFoldPer];
+        int cnt[kFoldPer];
 #pragma unroll
-        for (int r = 0; r < kBinFoldStep; ++r) {
-          const int qq = q0 + r;
+        for (int r = 0; r < kFoldPer; ++r) {
+          const int qq = q0 + r * kFoldHalves + half;
           cnt[r] = qq < nq ? lcnt[qq] : 0;
           e[r] = make_uint4(0, 0, 0, 0);
-          if (4 * tid < cnt[r])
-            e[r] = *reinterpret_cast<const uint4 *>(B.pool + (size_t)lpid[qq] * kBinPage + 4 * tid);
+          if (4 * lt < cnt[r])
+            e[r] = *reinterpret_cast<const uint4 *>(B.pool + (size_t)lpid[qq] * kBinPage + 4 * lt);
         }
 #pragma unroll
-        for (int r = 0; r < kBinFoldStep; ++r) {
+        for (int r = 0; r < kFoldPer; ++r) {
           const uint32_t ev[4] = {e[r].x, e[r].y, e[r].z, e[r].w};
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
-            if (4 * tid + k < cnt[r]) {
+            if (4 * lt + k < cnt[r]) {
               // atomics whose results are not used (no return, no wait):
               // testing the column first made every entry wait for an LDS
               // round trip, since an atomic on one entry may change the
